@@ -1,0 +1,279 @@
+/*
+ * infoesrf.h -- C ABI of the InFo-ESRF update library for AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the perturbation update of the Integral-Form Ensemble
+ * Square-Root Filter (Armstrong & Grooms): the matrix square root of the
+ * localized ensemble Kalman update is replaced by a quadrature sum over
+ * shifted symmetric positive definite systems (Sec. 3.2, eq. 3.5), one per
+ * (quadrature node q, ensemble member i), each solved by preconditioned
+ * conjugate gradients (Appendix E, eq. E.1) against the localized forecast
+ * covariance P = L o (Z Z^T) (Sec. 2.3, eq. 2.11), which is only ever applied
+ * as an operator (eq. 2.12).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array pointer in infoesrf_problem, infoesrf_stats, the workspace
+ *    and the outputs is HIP *device* memory owned by the caller.  Host
+ *    pointers are marked "host".  The library never allocates or frees device
+ *    memory: all scratch lives in the caller's workspace, sized by
+ *    infoesrf_workspace_bytes().
+ *  - Matrices are column-major FP64 unless stated otherwise.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream.  Work is ordered on that stream.  With opts->host_sync == 0 a
+ *    call performs no host synchronization and no host read-back, so it can
+ *    be captured in a HIP graph; status is then left in stats->counters.
+ *  - Calls are reentrant given distinct workspaces.
+ *  - Return codes: INFOESRF_OK (0), INFOESRF_WARN_NOT_CONVERGED (+1: outputs
+ *    are written, per-system flags tell which systems missed the
+ *    tolerance), or a negative error.  A message for the last error of the
+ *    calling thread is available from infoesrf_last_error().
+ *
+ * Notation (paper -> ABI): ensemble size m -> N, observation dimension d -> m,
+ * normalized perturbations Z (n x N) and W = H Z (m x N) (eq. 2.9), the
+ * normalized observation covariance S = R^{-1/2} H P H^T R^{-1/2} (called C in
+ * Theorem 3), shifted matrices C_q = (1 + s_q) I + S (eq. E.1).
+ */
+#ifndef INFOESRF_H
+#define INFOESRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------- */
+#define INFOESRF_OK 0
+#define INFOESRF_WARN_NOT_CONVERGED 1
+#define INFOESRF_ERR_INVALID_ARG (-1) /* bad dims, NULL, CSR out of range, N < 2, Q < 1, r <= 0 */
+#define INFOESRF_ERR_NOT_SPD (-2)     /* PCG curvature p^T C p <= 0 (localization not PSD) */
+#define INFOESRF_ERR_NUMERIC (-3)     /* NaN or Inf met in inputs or iterates */
+#define INFOESRF_ERR_WORKSPACE (-4)   /* workspace NULL or smaller than required */
+#define INFOESRF_ERR_HIP (-5)         /* a HIP runtime call failed */
+
+/* ---- localization kinds ------------------------------------------------- */
+#define INFOESRF_LOC_STENCIL 1 /* stationary stencil on an nz x nx grid */
+#define INFOESRF_LOC_DENSE 0   /* explicit n x n matrix (small n, tests) */
+
+/* ---- precision of the covariance applies inside PCG --------------------- */
+#define INFOESRF_FP64 0        /* every apply in FP64 */
+#define INFOESRF_MIXED_FP32 1  /* FP32 MFMA applies + FP64 residual correction */
+#define INFOESRF_MIXED_BF16 2  /* BF16 MFMA applies, FP32 accumulation + FP64 correction */
+
+/* ---- solver scheduling -------------------------------------------------- */
+#define INFOESRF_SOLVER_PLAIN 0      /* one launch per iteration over all systems, converged ones masked */
+#define INFOESRF_SOLVER_COMPACT 1    /* converged systems retired from the launched set each iteration */
+#define INFOESRF_SOLVER_PERSISTENT 2 /* one persistent launch; work queue of systems (batched instances) */
+
+/* ---- where the normalized covariance S is applied ----------------------- */
+#define INFOESRF_DOMAIN_STATE 0       /* general H: scatter to state space, apply P, gather */
+#define INFOESRF_DOMAIN_OBS_LATTICE 1 /* point observations on a regular sub-lattice, see below */
+
+/* ---- warm start --------------------------------------------------------- */
+#define INFOESRF_START_ZERO 0
+#define INFOESRF_START_LEARNED 1
+
+/* ---- counters written to infoesrf_stats.counters ------------------------ */
+#define INFOESRF_CNT_APPLIES 0       /* covariance applies, counted per vector, all precisions */
+#define INFOESRF_CNT_APPLIES_FP64 1  /* of which in FP64 */
+#define INFOESRF_CNT_ITERATIONS 2    /* PCG iterations summed over systems (inner + outer) */
+#define INFOESRF_CNT_SWEEPS 3        /* FP64 residual-correction sweeps (mixed precision) */
+#define INFOESRF_CNT_FALLBACKS 4     /* learned starts replaced by the zero start */
+#define INFOESRF_CNT_NOT_CONVERGED 5 /* systems that missed rtol */
+#define INFOESRF_CNT_MAX_ITERS 6     /* largest per-system iteration count */
+#define INFOESRF_CNT_STATUS 7        /* status code of the call (see return codes) */
+#define INFOESRF_NUM_COUNTERS 8
+
+/*
+ * Localization L (Sec. 2.3, eq. 2.11): symmetric, entries in [0,1], positive
+ * semidefinite.  STENCIL: the state is an nz x nx grid, state index
+ * z*nx + x, and L[(z1,x1),(z2,x2)] = table[(dz+bz)*(2bx+1) + (dx+bx)] for
+ * dz = z2-z1, dx = x2-x1 (wrapped to the nearest image on a periodic axis)
+ * with |dz| <= bz and |dx| <= bx, and 0 otherwise.  The table (device,
+ * (2bz+1)*(2bx+1) doubles, row-major) must be point-symmetric:
+ * table[dz][dx] == table[-dz][-dx].  A periodic axis needs nx >= 2bx+1
+ * (nz >= 2bz+1).  DENSE: `dense` is the n x n matrix (column-major).
+ */
+typedef struct infoesrf_loc {
+  int32_t kind;
+  int32_t nz, nx;
+  int32_t periodic_z, periodic_x;
+  int32_t bz, bx;
+  int32_t reserved;
+  const double* table;
+  const double* dense;
+} infoesrf_loc;
+
+/*
+ * One filter instance (Sec. 2.2 and Sec. 2.3).
+ *   X      n x N forecast members (column i = member x^(i)), ld = n.
+ *   H      linear observation operator, m rows in CSR: row k has entries
+ *          h_w[e] at state index h_idx[e] for e in [h_ptr[k], h_ptr[k+1]).
+ *          Column indices within a row must be strictly increasing.
+ *   r_var  m diagonal entries of R (all > 0).
+ *   loc    localization L.
+ * N >= 2 (eq. 2.9 divides by N-1), m >= 1, n = loc.nz * loc.nx.
+ */
+typedef struct infoesrf_problem {
+  int64_t n, N, m;
+  const double* X;
+  const int32_t* h_ptr;
+  const int32_t* h_idx;
+  const double* h_w;
+  const double* r_var;
+  infoesrf_loc loc;
+} infoesrf_problem;
+
+/*
+ * Observation sub-lattice for INFOESRF_DOMAIN_OBS_LATTICE: the caller asserts
+ * that H row k = a*nxo + b (a < nzo, b < nxo) observes exactly one state
+ * point, (z0 + a*sz, x0 + b*sx), with any nonzero weight.  Then
+ * H P H^T = L_JJ o (W W^T) exactly, and S is applied on the m observed points
+ * with the sub-sampled stencil, which is the same operator restricted to the
+ * rows H reads.  Periodic sub-axes need nx % sx == 0 (nz % sz == 0).
+ */
+typedef struct infoesrf_lattice {
+  int32_t z0, sz, nzo;
+  int32_t x0, sx, nxo;
+} infoesrf_lattice;
+
+typedef struct infoesrf_opts {
+  double rtol;          /* target of the true FP64 relative residual ||b - C u|| / ||b|| per system (default 1e-8) */
+  double inner_rtol;    /* mixed precision: inner PCG tolerance (0 = 1e-2 for BF16, 1e-5 for FP32) */
+  int32_t max_iter;     /* cap on PCG iterations per system (inner iterations summed in mixed mode) */
+  int32_t n_ritz;       /* p: Ritz pairs in the limited-memory preconditioner (Appendix E); 0 disables it */
+  int32_t oversample;   /* extra sketch columns for the randomized eigendecomposition */
+  int32_t precision;    /* INFOESRF_FP64 | INFOESRF_MIXED_FP32 | INFOESRF_MIXED_BF16 */
+  int32_t solver;       /* INFOESRF_SOLVER_* */
+  int32_t warm_start;   /* INFOESRF_START_ZERO | INFOESRF_START_LEARNED */
+  int32_t host_sync;    /* 1: read back and return status; 0: no host sync (graph-capture safe) */
+  int32_t apply_domain; /* INFOESRF_DOMAIN_STATE | INFOESRF_DOMAIN_OBS_LATTICE */
+  infoesrf_lattice lattice;
+  uint64_t seed;        /* seed of the library's own sketch generator when sketch == NULL */
+  const double* sketch; /* device m x (n_ritz+oversample) Gaussian test matrix, or NULL */
+  const void* net;      /* warm-start network from infoesrf_net_load (LEARNED only) */
+  int32_t tile_rows;    /* 0 = autotuned/default; else rows per covariance tile (multiple of 16) */
+  int32_t reserved[7];
+} infoesrf_opts;
+
+/* Per-system results (device arrays, each may be NULL).  Systems of the
+ * perturbation update are ordered s = q*N + i (node-major); the mean update
+ * has one system. */
+typedef struct infoesrf_stats {
+  int32_t* iters;     /* PCG iterations (inner + outer) */
+  double* relres;     /* final true relative residual in FP64 */
+  uint8_t* converged; /* 1 when relres <= rtol */
+  int64_t* counters;  /* INFOESRF_NUM_COUNTERS totals of the call */
+} infoesrf_stats;
+
+/* Fills *opts with defaults: rtol 1e-8, max_iter 1000, n_ritz 10, oversample 10,
+ * FP64, COMPACT solver, zero start, host_sync 1, state domain. */
+void infoesrf_default_opts(infoesrf_opts* opts);
+
+/* Bytes of device workspace needed by a call with this problem, Q nodes
+ * (Q = 0 for infoesrf_mean_update, B vectors for infoesrf_cov_apply via
+ * infoesrf_cov_apply_workspace_bytes) and options.  Returns 0 on invalid
+ * arguments (see infoesrf_last_error). */
+size_t infoesrf_workspace_bytes(const infoesrf_problem* prob, int32_t Q, const infoesrf_opts* opts);
+size_t infoesrf_cov_apply_workspace_bytes(const infoesrf_problem* prob, int64_t B, const infoesrf_opts* opts);
+
+/*
+ * PV = P V with P = L o (Z Z^T) (eq. 2.11), evaluated in the operator form
+ * sum_i z_i o L (z_i o v) (eq. 2.12); Z is formed from prob->X.
+ *   V   n x B state-space vectors, column b at V + b*ldv (ldv >= n).
+ *   PV  n x B output, column b at PV + b*ldpv (ldpv >= n).  May not alias V.
+ * opts->precision selects FP64, FP32 or BF16 (FP32 accumulation) arithmetic.
+ */
+int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ldv, int64_t B, double* PV,
+                       int64_t ldpv, const infoesrf_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Mean update (Sec. 3.2, eq. 3.4): mean_a = mu + P H^T R^{-1/2} u0 where
+ * (I + S) u0 = R^{-1/2} (y - H mu) is solved by PCG with the limited-memory
+ * preconditioner.  y: m observations.  mean_a: n outputs.
+ */
+int infoesrf_mean_update(const infoesrf_problem* prob, const double* y, double* mean_a, const infoesrf_opts* opts,
+                         infoesrf_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Perturbation update (Sec. 3.2, eq. 3.5 in the normalized form of eq. E.1):
+ * for every node q and member i solve C_q u_{q,i} = R^{-1/2} w_i by PCG,
+ * u_bar_i = sum_q p_q u_{q,i}, z_a^(i) = z^(i) - P H^T R^{-1/2} u_bar_i, and
+ * write Xa_pert = sqrt(N-1) Z_a (n x N, ld = n): the analysis deviations, so
+ * the analysis ensemble is mean_a 1^T + Xa_pert.
+ *   s_nodes, p_weights  host arrays of Q quadrature nodes (>= 0) and
+ *                       weights (>= 0), e.g. from infoesrf_quadrature_elliptic.
+ *   y                   m observations, used only by the learned warm start
+ *                       (its innovation input); may be NULL otherwise.
+ * Q must be in [1, 64].
+ */
+int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const double* s_nodes,
+                                 const double* p_weights, const double* y, double* Xa_pert,
+                                 const infoesrf_opts* opts, infoesrf_stats* stats, void* ws, size_t ws_bytes,
+                                 void* stream);
+
+/*
+ * Many independent instances of uneven n, N, m, Q in one call (all systems of
+ * all instances share one persistent launch per phase).  probs[j], Q[j],
+ * s[j], p[j] (host arrays), y[j] (may be NULL), mean_a[j] (n_j, may be NULL
+ * to skip the mean) and Xa_pert[j] (n_j x N_j) describe instance j.
+ * stats arrays, when given, hold sum_j (Q_j N_j + 1) systems in instance
+ * order (the mean system last within each instance).  Every instance must
+ * use a STENCIL localization.
+ */
+size_t infoesrf_batched_workspace_bytes(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
+                                        const infoesrf_opts* opts);
+int infoesrf_update_batched(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
+                            const double* const* s_nodes, const double* const* p_weights,
+                            const double* const* y, double* const* mean_a, double* const* Xa_pert,
+                            const infoesrf_opts* opts, infoesrf_stats* stats, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/*
+ * Elliptic quadrature rule (Appendix D, eq. D.1; host): with k^2 = ell/(1+ell)
+ * and K = K(k^2), u_q = (q - 1/2) K / Q, s_q = sc^2(u_q|k^2),
+ * p_q = (2K/(pi Q)) dn(u_q|k^2)/cn^2(u_q|k^2) / (1 + s_q).  ell should exceed
+ * the largest eigenvalue of S.  Writes Q nodes and weights (host arrays).
+ */
+int infoesrf_quadrature_elliptic(int32_t Q, double ell, double* s_nodes, double* p_weights);
+
+/* Trigonometric rule with Gauss-Legendre nodes (Appendix D, eq. D.2; host). */
+int infoesrf_quadrature_gauss_legendre(int32_t Q, double* s_nodes, double* p_weights);
+
+/* Static description of a return code, and the message of the calling
+ * thread's last error ("" if none). */
+const char* infoesrf_error_string(int code);
+const char* infoesrf_last_error(void);
+
+/*
+ * Learned warm start: a 1-D convolutional network (4 layers, kernel 9,
+ * 64 hidden channels) mapping (b_i/||b_i||, 1/(1+s_q), d/||d||) to the
+ * initial guess ||b_i|| net(.) of C_q u = b_i.  The file is the library's own
+ * little-endian format written by infoesrf_net_save.  The handle owns device
+ * memory allocated at load time (not on the update path).
+ */
+int infoesrf_net_load(const char* path, void** net);
+int infoesrf_net_save(const void* net, const char* path);
+void infoesrf_net_free(void* net);
+
+/*
+ * Measurement hooks (results are unaffected).  While enabled, every launch of
+ * the covariance-apply kernel is bracketed by HIP events recorded on the
+ * stream it runs on, and the kernel adds the number of vectors it applies and
+ * their algorithmic FLOPs (2 N nnz(L) + 3 n N per vector, nnz(L) = nonzeros of
+ * the localization on the grid the launch uses) to device counters.
+ * infoesrf_profile_read synchronizes the device and returns, per apply
+ * precision (index 0 FP64, 1 FP32, 2 BF16), the summed kernel time in ms, the
+ * number of launches, the vectors applied and the FLOPs.  Enabling resets the
+ * totals.  The hook allocates its event pool and counters when enabled; it is
+ * meant for benchmarks, not for the update path.  Not thread-safe.
+ */
+int infoesrf_profile_enable(int on);
+int infoesrf_profile_read(double ms[3], int64_t launches[3], int64_t vectors[3], double flops[3]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INFOESRF_H */

@@ -1,0 +1,971 @@
+// Host runtime of the InFo-ESRF library: argument validation, workspace
+// planning, stream ordering of the kernels, and the C entry points of
+// include/infoesrf.h.
+//
+// Update pipeline (Sec. 3.2 and Appendix E):
+//   1. mu, Z from the forecast ensemble (eq. 2.9); b_i = R^{-1/2} H z_i.
+//   2. Ritz pairs of S by a randomized eigendecomposition (the preconditioner).
+//   3. For every system s = (q, i): solve (1 + s_q) u + S u = b_i by PCG with the
+//      limited-memory preconditioner, inside an iterative-refinement loop whose
+//      residuals are always formed in FP64 (the inner applies may be FP32/BF16).
+//   4. u_bar_i = sum_q p_q u_{q,i};  z_a^(i) = z^(i) - P H^T R^{-1/2} u_bar_i.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace infoesrf {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+namespace {
+
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over the caller's workspace; a null base only measures.
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t count) {
+    off = (size_t)round_up((int64_t)off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+constexpr int kChunk = 128;  // rows per reduction chunk
+
+// ------------------------------------------------------------------ kernels local to the runtime
+__global__ void k_lattice_check(const int32_t* h_ptr, const int32_t* h_idx, int64_t m, infoesrf_lattice lat,
+                                int32_t nx, int32_t* flags) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int64_t a = k / lat.nxo, b = k % lat.nxo;
+  const int64_t want = (int64_t)(lat.z0 + a * lat.sz) * nx + (lat.x0 + b * lat.sx);
+  // h_idx[k] exists only when rows 0..k hold one entry each
+  if (h_ptr[k] != (int32_t)k || h_ptr[k + 1] != (int32_t)(k + 1) || h_idx[k] != want) atomicOr(flags, kFlagBadInput);
+}
+
+__global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t count) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < count) b[t] = a[t];
+}
+
+__global__ void k_widen(const float* __restrict__ a, double* __restrict__ b, int64_t count) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < count) b[t] = (double)a[t];
+}
+
+__global__ void k_positive_check(const double* v, int64_t count, int32_t* flags) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < count && !(v[t] > 0.0 && isfinite(v[t]))) atomicOr(flags, kFlagBadInput);
+}
+
+// Set per-system shifts: sigma[q*N + i] = s_q; the values arrive by kernel argument (capture safe).
+struct Nodes {
+  double s[kMaxQ];
+  double p[kMaxQ];
+};
+__global__ void k_set_nodes(Nodes nd, int32_t Q, int64_t N, double* sigma, double* pw, int64_t extra,
+                            double extra_sigma) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < (int64_t)Q * N) sigma[t] = nd.s[t / N];
+  if (t < Q) pw[t] = nd.p[t];
+  if (t < extra) sigma[(int64_t)Q * N + t] = extra_sigma;
+}
+
+// Sweep bookkeeping from true residual norms (iterative refinement).
+//   fdone: 1 converged (rn <= rtol bn), 2 failed (iteration cap or non-finite), 0 needs work.
+//   done (inner PCG status) = fdone ? 1 : 0; thresh = absolute inner target.
+__global__ void k_sweep_status(const double* rn, const double* bn, double rtol, double inner_rtol, int fp64_inner,
+                               const int32_t* iters, int max_iter, double* relres, int32_t* fdone, int32_t* done,
+                               double* thresh, int32_t* sweeps, int count_sweep, int64_t S, int32_t* flags) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  if (fdone[s] != 0) {
+    done[s] = 1;
+    return;
+  }
+  if (count_sweep) sweeps[s] += 1;
+  const double b = bn[s], r = rn[s];
+  const double rr = b > 0.0 ? r / b : 0.0;
+  relres[s] = rr;
+  if (!isfinite(rr)) {
+    atomicOr(flags, kFlagNumeric);
+    fdone[s] = 2;
+    done[s] = 1;
+    return;
+  }
+  if (rr <= rtol) {
+    fdone[s] = 1;
+    done[s] = 1;
+    return;
+  }
+  if (iters[s] >= max_iter) {
+    fdone[s] = 2;
+    done[s] = 1;
+    return;
+  }
+  done[s] = 0;
+  const double target = 0.5 * rtol * b;
+  thresh[s] = fp64_inner ? target : fmax(inner_rtol * r, target);
+}
+
+// Counters of the call (deterministic reduction over systems in one block).
+__global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, const int32_t* fdone, int64_t S,
+                                  int64_t extra_fp64_applies, int inner_fp64, const int32_t* flags,
+                                  const int32_t* fallbacks, int64_t* out) {
+  __shared__ int64_t acc[4][256];
+  const int t = threadIdx.x;
+  int64_t it = 0, sw = 0, nc = 0, mx = 0;
+  for (int64_t s = t; s < S; s += 256) {
+    it += iters[s];
+    sw += sweeps[s];
+    nc += (fdone[s] != 1);
+    mx = max(mx, (int64_t)iters[s]);
+  }
+  acc[0][t] = it;
+  acc[1][t] = sw;
+  acc[2][t] = nc;
+  acc[3][t] = mx;
+  __syncthreads();
+  if (t == 0) {
+    int64_t a = 0, b = 0, c = 0, d = 0;
+    for (int j = 0; j < 256; ++j) {
+      a += acc[0][j];
+      b += acc[1][j];
+      c += acc[2][j];
+      d = max(d, acc[3][j]);
+    }
+    out[INFOESRF_CNT_ITERATIONS] = a;
+    out[INFOESRF_CNT_SWEEPS] = b;
+    out[INFOESRF_CNT_NOT_CONVERGED] = c;
+    out[INFOESRF_CNT_MAX_ITERS] = d;
+    out[INFOESRF_CNT_APPLIES] = a + b + extra_fp64_applies;
+    out[INFOESRF_CNT_APPLIES_FP64] = (inner_fp64 ? a : 0) + b + extra_fp64_applies;
+    out[INFOESRF_CNT_FALLBACKS] = fallbacks ? *fallbacks : 0;
+    const int32_t f = *flags;
+    int64_t status = INFOESRF_OK;
+    if (f & kFlagBadInput) status = INFOESRF_ERR_INVALID_ARG;
+    else if (f & kFlagNumeric) status = INFOESRF_ERR_NUMERIC;
+    else if (f & kFlagNotSPD) status = INFOESRF_ERR_NOT_SPD;
+    else if (c > 0) status = INFOESRF_WARN_NOT_CONVERGED;
+    out[INFOESRF_CNT_STATUS] = status;
+  }
+}
+
+inline unsigned nb(int64_t c) { return (unsigned)((c + 255) / 256); }
+
+// ------------------------------------------------------------------ plan
+
+struct Options {
+  double rtol, inner_rtol;
+  int max_iter, p, k;  // Ritz pairs, sketch columns
+  Prec inner;
+  int solver;
+  int host_sync;
+  int rows_per_wave;
+  bool obs;
+  infoesrf_lattice lat;
+  uint64_t seed;
+  const double* sketch;
+  int warm;
+  const void* net;
+};
+
+struct Inst {
+  const infoesrf_problem* P = nullptr;
+  int64_t n = 0, N = 0, m = 0;
+  bool dense = false, obs = false;
+  Grid gs{};  // state grid
+  Grid go{};  // observation lattice grid (obs domain)
+  double *mu = nullptr, *Z = nullptr, *Zt = nullptr, *subtab = nullptr;
+  float *Z32 = nullptr, *Zt32 = nullptr, *tab32 = nullptr, *subtab32 = nullptr;
+  int32_t *col_cnt = nullptr, *col_ptr = nullptr, *row_of = nullptr;
+  double* w_of = nullptr;
+  double *diagS = nullptr, *dmin = nullptr;
+  int32_t* flags = nullptr;
+  int32_t* fallbacks = nullptr;
+  int64_t* counters = nullptr;
+};
+
+struct Sys {
+  int64_t S = 0, ld = 0, Bpad = 0;
+  double *b, *u, *x, *r, *p, *q, *bnorm, *rn, *rz0, *rz1, *relres, *rel_in, *sigma, *thresh, *pw;
+  int32_t *iters, *sweeps, *done, *fdone, *act, *nact;
+  double *part_pq, *part2;
+};
+
+struct Pre {
+  int k = 0, p = 0;
+  double *Om = nullptr, *Y = nullptr, *Qb = nullptr, *SQ = nullptr, *Tk = nullptr, *evec = nullptr,
+         *evals = nullptr, *Rinv = nullptr, *sel = nullptr, *Phi = nullptr, *SPhi = nullptr, *theta = nullptr,
+         *G = nullptr, *gscr = nullptr, *sig = nullptr;
+  int32_t *act = nullptr, *nact = nullptr;
+};
+
+struct Buf {
+  void* V = nullptr;
+  void* T = nullptr;
+  int64_t ldmax = 0;  // columns
+};
+
+struct Fin {
+  double* ubar = nullptr;  // m x ld_f sysfast (N + 1 columns)
+  int64_t ld = 0;
+  int32_t *act, *nact;
+};
+
+struct Plan {
+  Inst in;
+  Sys sy;
+  Pre pr;
+  Buf bf;
+  Fin fn;
+  size_t bytes = 0;
+};
+
+int check_problem(const infoesrf_problem* P) {
+  IE_CHECK(P != nullptr, INFOESRF_ERR_INVALID_ARG, "problem is NULL");
+  IE_CHECK(P->N >= 2, INFOESRF_ERR_INVALID_ARG, "ensemble size N must be >= 2");
+  IE_CHECK(P->m >= 1, INFOESRF_ERR_INVALID_ARG, "observation count m must be >= 1");
+  IE_CHECK(P->n >= 1, INFOESRF_ERR_INVALID_ARG, "state dimension n must be >= 1");
+  IE_CHECK(P->n < (1LL << 30) && P->m < (1LL << 30) && P->N < (1LL << 20), INFOESRF_ERR_INVALID_ARG,
+           "dimensions too large");
+  IE_CHECK(P->X && P->h_ptr && P->h_idx && P->h_w && P->r_var, INFOESRF_ERR_INVALID_ARG,
+           "X, h_ptr, h_idx, h_w and r_var must be non-NULL");
+  const infoesrf_loc& L = P->loc;
+  if (L.kind == INFOESRF_LOC_DENSE) {
+    IE_CHECK(L.dense != nullptr, INFOESRF_ERR_INVALID_ARG, "dense localization pointer is NULL");
+    IE_CHECK(P->n <= 8192, INFOESRF_ERR_INVALID_ARG, "dense localization limited to n <= 8192");
+    return 0;
+  }
+  IE_CHECK(L.kind == INFOESRF_LOC_STENCIL, INFOESRF_ERR_INVALID_ARG, "unknown localization kind");
+  IE_CHECK(L.table != nullptr, INFOESRF_ERR_INVALID_ARG, "stencil table is NULL");
+  IE_CHECK(L.nz >= 1 && L.nx >= 1 && (int64_t)L.nz * L.nx == P->n, INFOESRF_ERR_INVALID_ARG,
+           "stencil grid nz*nx must equal n");
+  IE_CHECK(L.bz >= 0 && L.bx >= 0, INFOESRF_ERR_INVALID_ARG, "stencil half-extents must be >= 0");
+  IE_CHECK(!L.periodic_x || L.nx >= 2 * L.bx + 1, INFOESRF_ERR_INVALID_ARG, "periodic x needs nx >= 2bx+1");
+  IE_CHECK(!L.periodic_z || L.nz >= 2 * L.bz + 1, INFOESRF_ERR_INVALID_ARG, "periodic z needs nz >= 2bz+1");
+  IE_CHECK((int64_t)(2 * L.bz + 1) * (2 * L.bx + 41) * 8 <= 64 * 1024, INFOESRF_ERR_INVALID_ARG,
+           "stencil too large for one workgroup LDS: (2bz+1)(2bx+41)*8 must be <= 64 KiB");
+  return 0;
+}
+
+int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& op) {
+  infoesrf_opts d;
+  infoesrf_default_opts(&d);
+  if (!o) o = &d;
+  IE_CHECK(o->rtol > 0.0 && o->rtol < 1.0, INFOESRF_ERR_INVALID_ARG, "rtol must be in (0, 1)");
+  IE_CHECK(o->max_iter >= 1, INFOESRF_ERR_INVALID_ARG, "max_iter must be >= 1");
+  IE_CHECK(o->n_ritz >= 0 && o->oversample >= 0, INFOESRF_ERR_INVALID_ARG, "n_ritz, oversample must be >= 0");
+  const int p = o->n_ritz;
+  IE_CHECK(p == 0 || p == 4 || p == 8 || p == 10 || p == 12 || p == 16, INFOESRF_ERR_INVALID_ARG,
+           "n_ritz must be one of 0, 4, 8, 10, 12, 16");
+  IE_CHECK(p + o->oversample <= kMaxSketch, INFOESRF_ERR_INVALID_ARG, "n_ritz + oversample must be <= 48");
+  IE_CHECK(p == 0 || p + o->oversample <= P->m, INFOESRF_ERR_INVALID_ARG, "n_ritz + oversample must be <= m");
+  IE_CHECK(o->precision >= INFOESRF_FP64 && o->precision <= INFOESRF_MIXED_BF16, INFOESRF_ERR_INVALID_ARG,
+           "unknown precision");
+  IE_CHECK(o->precision != INFOESRF_MIXED_BF16, INFOESRF_ERR_INVALID_ARG, "BF16 applies are not available yet");
+  IE_CHECK(o->solver >= INFOESRF_SOLVER_PLAIN && o->solver <= INFOESRF_SOLVER_PERSISTENT, INFOESRF_ERR_INVALID_ARG,
+           "unknown solver");
+  IE_CHECK(o->warm_start == INFOESRF_START_ZERO, INFOESRF_ERR_INVALID_ARG, "learned warm start not available yet");
+  IE_CHECK(o->apply_domain == INFOESRF_DOMAIN_STATE || o->apply_domain == INFOESRF_DOMAIN_OBS_LATTICE,
+           INFOESRF_ERR_INVALID_ARG, "unknown apply domain");
+  IE_CHECK(o->tile_rows == 0 || o->tile_rows == 16 || o->tile_rows == 32 || o->tile_rows == 64 ||
+               o->tile_rows == 128,
+           INFOESRF_ERR_INVALID_ARG, "tile_rows must be 0, 16, 32, 64 or 128");
+  op.rtol = o->rtol;
+  op.max_iter = o->max_iter;
+  op.p = p;
+  op.k = p > 0 ? p + o->oversample : 0;
+  op.inner = (o->precision == INFOESRF_FP64) ? Prec::F64 : (o->precision == INFOESRF_MIXED_FP32 ? Prec::F32 : Prec::BF16);
+  op.inner_rtol = o->inner_rtol > 0.0 ? o->inner_rtol : (op.inner == Prec::F32 ? 1e-5 : 1e-2);
+  op.solver = o->solver;
+  op.host_sync = o->host_sync;
+  op.rows_per_wave = o->tile_rows ? o->tile_rows : 64;
+  op.obs = (o->apply_domain == INFOESRF_DOMAIN_OBS_LATTICE);
+  op.lat = o->lattice;
+  op.seed = o->seed;
+  op.sketch = o->sketch;
+  op.warm = o->warm_start;
+  op.net = o->net;
+  if (op.obs) {
+    const infoesrf_loc& L = P->loc;
+    const infoesrf_lattice& a = op.lat;
+    IE_CHECK(L.kind == INFOESRF_LOC_STENCIL, INFOESRF_ERR_INVALID_ARG, "lattice domain needs a stencil localization");
+    IE_CHECK(a.sz >= 1 && a.sx >= 1 && a.nzo >= 1 && a.nxo >= 1 && a.z0 >= 0 && a.x0 >= 0,
+             INFOESRF_ERR_INVALID_ARG, "bad lattice description");
+    IE_CHECK((int64_t)a.nzo * a.nxo == P->m, INFOESRF_ERR_INVALID_ARG, "lattice nzo*nxo must equal m");
+    IE_CHECK(a.z0 + (int64_t)(a.nzo - 1) * a.sz < L.nz && a.x0 + (int64_t)(a.nxo - 1) * a.sx < L.nx,
+             INFOESRF_ERR_INVALID_ARG, "lattice leaves the grid");
+    IE_CHECK(!L.periodic_x || (int64_t)a.nxo * a.sx == L.nx, INFOESRF_ERR_INVALID_ARG,
+             "periodic x lattice must cover the axis (nxo*sx == nx)");
+    IE_CHECK(!L.periodic_z || (int64_t)a.nzo * a.sz == L.nz, INFOESRF_ERR_INVALID_ARG,
+             "periodic z lattice must cover the axis (nzo*sz == nz)");
+  }
+  return 0;
+}
+
+// Lay out every buffer of one call.  `S` systems, `nfin` final state-space columns.
+void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& op, int64_t S, int64_t nfin) {
+  Inst& in = pl.in;
+  in.P = P;
+  in.n = P->n;
+  in.N = P->N;
+  in.m = P->m;
+  in.dense = (P->loc.kind == INFOESRF_LOC_DENSE);
+  in.obs = op.obs;
+  const bool low = (op.inner != Prec::F64);
+  in.mu = ar.take<double>(in.n);
+  in.Z = ar.take<double>(in.n * in.N);
+  in.Z32 = (low && !in.obs) ? ar.take<float>(in.n * in.N) : nullptr;
+  if (!in.dense) {
+    const infoesrf_loc& L = P->loc;
+    in.gs = Grid{L.nz, L.nx, L.periodic_z, L.periodic_x, L.bz, L.bx, L.table, nullptr, nullptr};
+    if (low) in.tab32 = ar.take<float>((2 * L.bz + 1) * (2 * L.bx + 1));
+    in.gs.table32 = in.tab32;
+  }
+  if (in.obs) {
+    const infoesrf_loc& L = P->loc;
+    const infoesrf_lattice& a = op.lat;
+    const int bzs = L.bz / a.sz, bxs = L.bx / a.sx;
+    in.Zt = ar.take<double>(in.m * in.N);
+    in.Zt32 = low ? ar.take<float>(in.m * in.N) : nullptr;
+    in.subtab = ar.take<double>((2 * bzs + 1) * (2 * bxs + 1));
+    in.subtab32 = low ? ar.take<float>((2 * bzs + 1) * (2 * bxs + 1)) : nullptr;
+    const int pz = L.periodic_z && (int64_t)a.nzo * a.sz == L.nz;
+    const int px = L.periodic_x && (int64_t)a.nxo * a.sx == L.nx;
+    in.go = Grid{a.nzo, a.nxo, pz, px, bzs, bxs, in.subtab, in.subtab32, nullptr};
+  }
+  in.col_cnt = ar.take<int32_t>(in.n);
+  in.col_ptr = ar.take<int32_t>(in.n + 1);
+  // CSC arrays sized by nnz, which lives on the device; bound it by a per-call maximum (see below)
+  in.row_of = nullptr;
+  in.w_of = nullptr;
+  in.diagS = ar.take<double>(in.m);
+  in.dmin = ar.take<double>(1);
+  in.flags = ar.take<int32_t>(1);
+  in.fallbacks = ar.take<int32_t>(1);
+  in.counters = ar.take<int64_t>(INFOESRF_NUM_COUNTERS);
+
+  Sys& sy = pl.sy;
+  sy.S = S;
+  sy.ld = round_up(S, kSysTile);
+  sy.Bpad = sy.ld;
+  const int64_t ms = in.m * sy.ld;
+  sy.b = ar.take<double>(ms);
+  sy.u = ar.take<double>(ms);
+  sy.x = ar.take<double>(ms);
+  sy.r = ar.take<double>(ms);
+  sy.p = ar.take<double>(ms);
+  sy.q = ar.take<double>(ms);
+  sy.bnorm = ar.take<double>(sy.ld);
+  sy.rn = ar.take<double>(sy.ld);
+  sy.rz0 = ar.take<double>(sy.ld);
+  sy.rz1 = ar.take<double>(sy.ld);
+  sy.relres = ar.take<double>(sy.ld);
+  sy.rel_in = ar.take<double>(sy.ld);
+  sy.sigma = ar.take<double>(sy.ld);
+  sy.thresh = ar.take<double>(sy.ld);
+  sy.pw = ar.take<double>(kMaxQ);
+  sy.iters = ar.take<int32_t>(sy.ld);
+  sy.sweeps = ar.take<int32_t>(sy.ld);
+  sy.done = ar.take<int32_t>(sy.ld);
+  sy.fdone = ar.take<int32_t>(sy.ld);
+  sy.act = ar.take<int32_t>(sy.ld);
+  sy.nact = ar.take<int32_t>(1);
+  const int64_t nchunks = (in.m + kChunk - 1) / kChunk;
+  sy.part_pq = ar.take<double>(nchunks * round_up(std::max<int64_t>(sy.ld, op.k + 16), 64));
+  sy.part2 = ar.take<double>(nchunks * round_up(sy.ld, 64) * (2 * op.p + 1));
+
+  Pre& pr = pl.pr;
+  pr.k = op.k;
+  pr.p = op.p;
+  if (op.k > 0) {
+    const int64_t kl = round_up(op.k, kSysTile);
+    pr.Om = ar.take<double>(in.m * kl);
+    pr.Y = ar.take<double>(in.m * kl);
+    pr.Qb = ar.take<double>(in.m * kl);
+    pr.SQ = ar.take<double>(in.m * kl);
+    pr.Tk = ar.take<double>(op.k * op.k);
+    pr.evec = ar.take<double>(op.k * op.k);
+    pr.evals = ar.take<double>(op.k);
+    pr.Rinv = ar.take<double>(op.k * op.k);
+    pr.sel = ar.take<double>(op.k * op.p);
+    pr.Phi = ar.take<double>(in.m * op.p);
+    pr.SPhi = ar.take<double>(in.m * op.p);
+    pr.theta = ar.take<double>(op.p);
+    pr.G = ar.take<double>(3 * op.p * op.p);
+    pr.gscr = ar.take<double>(((in.m + 127) / 128) * op.k * op.k);
+    pr.sig = ar.take<double>(kl);
+    pr.act = ar.take<int32_t>(kl);
+    pr.nact = ar.take<int32_t>(1);
+  }
+  Fin& fn = pl.fn;
+  fn.ld = round_up(std::max<int64_t>(nfin, 1), kSysTile);
+  fn.ubar = ar.take<double>(in.m * fn.ld);
+  fn.act = ar.take<int32_t>(fn.ld);
+  fn.nact = ar.take<int32_t>(1);
+
+  // apply buffers: rows x columns in FP64 (enough for every precision)
+  const int64_t cols = std::max<int64_t>({sy.ld, round_up(op.k, kSysTile), fn.ld, 16});
+  const int64_t rows = std::max<int64_t>(in.n, in.m);
+  pl.bf.ldmax = cols;
+  pl.bf.V = ar.take<double>(rows * cols);
+  pl.bf.T = ar.take<double>(rows * cols);
+}
+
+// ------------------------------------------------------------------ apply
+// Qout[:, act] = (1 + sigma) Pin[:, act] + S Pin[:, act] with S in precision `prec`;
+// partial dots of Pin^T Qout into part.
+int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* act, const int32_t* nact,
+            int64_t Bmax, const double* sigma, double* Qout, double* part, int rows_per_wave, hipStream_t st) {
+  Inst& in = pl.in;
+  const int64_t Bpad = round_up(Bmax, kSysTile);
+  if (in.obs) {
+    IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, Bpad, st));
+    const void* Zu = (prec == Prec::F64) ? (const void*)in.Zt : (const void*)in.Zt32;
+    IE_HIP(cov_stencil_timed(prec, in.go, Zu, in.m, in.N, pl.bf.V, Bpad, Bpad, nact, pl.bf.T, Bpad, rows_per_wave,
+                              st));
+  } else {
+    IE_HIP(launch_scatter_state(prec, Pin, ldp, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n, in.m,
+                                Bpad, pl.bf.V, Bpad, st));
+    if (in.dense) {
+      IE_CHECK(prec == Prec::F64, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
+      IE_HIP(launch_cov_dense(in.P->loc.dense, in.Z, in.n, in.N, (const double*)pl.bf.V, Bpad, Bpad,
+                              (double*)pl.bf.T, Bpad, st));
+    } else {
+      const void* Zu = (prec == Prec::F64) ? (const void*)in.Z : (const void*)in.Z32;
+      IE_HIP(cov_stencil_timed(prec, in.gs, Zu, in.n, in.N, pl.bf.V, Bpad, Bpad, nact, pl.bf.T, Bpad,
+                                rows_per_wave, st));
+    }
+  }
+  IE_HIP(launch_apply_finish(prec, in.obs ? 1 : 0, Pin, ldp, pl.bf.T, Bpad, act, nact, sigma, in.P->h_ptr,
+                             in.P->h_idx, in.P->h_w, in.P->r_var, in.m, in.n, Bpad, Qout, part, kChunk, st));
+  return 0;
+}
+
+// State-space apply of the m x ncols observation-space vectors U (sysfast, ld):
+// T_state = P H^T R^{-1/2} U, returned in pl.bf.T as n x Bpad sysfast FP64.
+int apply_state(Plan& pl, const double* U, int64_t ld, const int32_t* act, const int32_t* nact, int64_t ncols,
+                int rows_per_wave, hipStream_t st) {
+  Inst& in = pl.in;
+  const int64_t Bpad = round_up(ncols, kSysTile);
+  IE_HIP(launch_scatter_state(Prec::F64, U, ld, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n, in.m,
+                              Bpad, pl.bf.V, Bpad, st));
+  if (in.dense) {
+    IE_HIP(launch_cov_dense(in.P->loc.dense, in.Z, in.n, in.N, (const double*)pl.bf.V, Bpad, ncols,
+                            (double*)pl.bf.T, Bpad, st));
+  } else {
+    IE_HIP(cov_stencil_timed(Prec::F64, in.gs, in.Z, in.n, in.N, pl.bf.V, Bpad, ncols, nullptr, pl.bf.T, Bpad,
+                              rows_per_wave, st));
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------ stages
+int read_flags(Plan& pl, hipStream_t st, int32_t* out) {
+  IE_HIP(hipMemcpyAsync(out, pl.in.flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  IE_HIP(hipStreamSynchronize(st));
+  return 0;
+}
+
+int flags_to_code(int32_t f) {
+  if (f & kFlagBadInput) return INFOESRF_ERR_INVALID_ARG;
+  if (f & kFlagNumeric) return INFOESRF_ERR_NUMERIC;
+  if (f & kFlagNotSPD) return INFOESRF_ERR_NOT_SPD;
+  return 0;
+}
+
+int stage_setup(Plan& pl, const Options& op, hipStream_t st, int64_t nnz_cap) {
+  Inst& in = pl.in;
+  const infoesrf_problem* P = in.P;
+  (void)nnz_cap;
+  // 1. validation kernels (they read H only within its own CSR bounds)
+  IE_HIP(launch_fill_i32(in.flags, 0, 1, st));
+  IE_HIP(launch_fill_i32(in.fallbacks, 0, 1, st));
+  IE_HIP(launch_nan_check(P->X, in.n * in.N, in.flags, st));
+  hipLaunchKernelGGL(k_positive_check, dim3(nb(in.m)), dim3(256), 0, st, P->r_var, in.m, in.flags);
+  IE_HIP(hipGetLastError());
+  IE_HIP(launch_csc_build(P->h_ptr, P->h_idx, P->h_w, in.m, in.n, in.col_cnt, in.col_ptr, in.row_of, in.w_of,
+                          in.flags, st));
+  if (in.obs) {
+    hipLaunchKernelGGL(k_lattice_check, dim3(nb(in.m)), dim3(256), 0, st, P->h_ptr, P->h_idx, in.m, op.lat,
+                       P->loc.nx, in.flags);
+    IE_HIP(hipGetLastError());
+  }
+  if (op.host_sync) {
+    int32_t f = 0;
+    IE_TRY(read_flags(pl, st, &f));
+    if (f & kFlagBadInput) {
+      set_error("invalid observation operator (CSR out of range, unsorted, or not the stated lattice) or r_var <= 0");
+      return INFOESRF_ERR_INVALID_ARG;
+    }
+    if (f & kFlagNumeric) {
+      set_error("non-finite value in the forecast ensemble");
+      return INFOESRF_ERR_NUMERIC;
+    }
+  }
+  // 2. ensemble and observation-space setup (indices are guarded against invalid values, which
+  //    can only reach here when host_sync == 0; the flag then sets the call's status)
+  const bool low = (op.inner != Prec::F64);
+  IE_HIP(launch_ens_stats(P->X, in.n, in.N, in.mu, in.Z, in.Z32, st));
+  IE_HIP(launch_diag_S(P->h_ptr, P->h_idx, P->h_w, P->r_var, in.Z, in.n, in.N, in.m, in.gs,
+                       in.dense ? P->loc.dense : nullptr, in.diagS, st));
+  IE_HIP(launch_min_reduce(in.diagS, in.m, in.dmin, st));
+  if (!in.dense && low) {
+    const infoesrf_loc& L = P->loc;
+    IE_HIP(launch_convert_f32(L.table, in.tab32, (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1), st));
+  }
+  if (in.obs) {
+    IE_HIP(launch_lattice_members(P->h_idx, P->h_w, P->r_var, in.Z, in.n, in.N, in.m, in.Zt, in.Zt32, st));
+    const infoesrf_loc& L = P->loc;
+    IE_HIP(launch_subsample_table(L.table, L.bz, L.bx, op.lat.sz, op.lat.sx, in.go.bz, in.go.bx, in.subtab, st));
+    if (low)
+      IE_HIP(launch_convert_f32(in.subtab, in.subtab32, (int64_t)(2 * in.go.bz + 1) * (2 * in.go.bx + 1), st));
+  }
+  return 0;
+}
+
+// Randomized eigendecomposition of S -> Phi, S Phi, theta, Gram matrices (Appendix E).
+int stage_precond(Plan& pl, const Options& op, hipStream_t st) {
+  Pre& pr = pl.pr;
+  if (pr.p == 0) return 0;
+  Inst& in = pl.in;
+  const int k = pr.k;
+  const int64_t kl = round_up(k, kSysTile);
+  if (op.sketch) {
+    IE_HIP(launch_to_sysfast(op.sketch, in.m, in.m, k, pr.Om, kl, st));
+  } else {
+    IE_HIP(launch_fill_f64(pr.Om, 0.0, in.m * kl, st));
+    IE_HIP(launch_sketch(op.seed, in.m, k, pr.Om, kl, st));
+  }
+  IE_HIP(launch_iota(pr.act, pr.nact, k, st));
+  IE_HIP(launch_fill_f64(pr.sig, -1.0, kl, st));  // (1 + sigma) = 0: pure S
+  double* part = pl.sy.part_pq;
+  IE_TRY(apply_S(pl, Prec::F64, pr.Om, kl, pr.act, pr.nact, k, pr.sig, pr.Y, part, op.rows_per_wave, st));
+  // Cholesky-QR twice: Qb = Y R^{-1}
+  const double* src = pr.Y;
+  double* dst = pr.Qb;
+  for (int pass = 0; pass < 2; ++pass) {
+    IE_HIP(launch_gram(src, kl, src, kl, in.m, k, pr.Rinv, pr.gscr, st));
+    IE_HIP(launch_chol_inv(pr.Rinv, k, in.flags, st));
+    IE_HIP(launch_right_mult(const_cast<double*>(src), kl, in.m, k, pr.Rinv, k, dst, kl, st));
+    if (pass == 0) {
+      src = pr.Qb;
+      dst = pr.Y;
+    }
+  }
+  // after two passes the orthonormal basis is in pr.Y; keep it in Qb
+  hipLaunchKernelGGL(k_copy_f64, dim3(nb(in.m * kl)), dim3(256), 0, st, pr.Y, pr.Qb, in.m * kl);
+  IE_HIP(hipGetLastError());
+  IE_TRY(apply_S(pl, Prec::F64, pr.Qb, kl, pr.act, pr.nact, k, pr.sig, pr.SQ, part, op.rows_per_wave, st));
+  IE_HIP(launch_gram(pr.Qb, kl, pr.SQ, kl, in.m, k, pr.Tk, pr.gscr, st));
+  IE_HIP(launch_sym_eig(pr.Tk, k, pr.evec, pr.evals, st));
+  IE_HIP(launch_lmp_finish(pr.evals, pr.evec, k, pr.p, pr.theta, pr.sel, st));
+  IE_HIP(launch_right_mult(pr.Qb, kl, in.m, k, pr.sel, pr.p, pr.Phi, pr.p, st));
+  IE_HIP(launch_right_mult(pr.SQ, kl, in.m, k, pr.sel, pr.p, pr.SPhi, pr.p, st));
+  const int p = pr.p;
+  IE_HIP(launch_gram(pr.Phi, p, pr.Phi, p, in.m, p, pr.G, pr.gscr, st));
+  IE_HIP(launch_gram(pr.Phi, p, pr.SPhi, p, in.m, p, pr.G + p * p, pr.gscr, st));
+  IE_HIP(launch_gram(pr.SPhi, p, pr.SPhi, p, in.m, p, pr.G + 2 * p * p, pr.gscr, st));
+  return 0;
+}
+
+LMP lmp_of(Plan& pl) {
+  LMP l{};
+  l.p = pl.pr.p;
+  l.Phi = pl.pr.Phi;
+  l.SPhi = pl.pr.SPhi;
+  l.theta = pl.pr.theta;
+  l.G = pl.pr.G;
+  l.dmin = pl.in.dmin;
+  return l;
+}
+
+// Iterative refinement around batched PCG.  Solves (1 + sigma_s) u_s + S u_s = b_s for all s.
+int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
+  Inst& in = pl.in;
+  Sys& sy = pl.sy;
+  const int64_t S = sy.S, ld = sy.ld, m = in.m;
+  const LMP lmp = lmp_of(pl);
+  const bool fp64_inner = (op.inner == Prec::F64);
+  PCGState ps{};
+  ps.m = m;
+  ps.S = S;
+  ps.ld = ld;
+  ps.x = sy.x;
+  ps.r = sy.r;
+  ps.p = sy.p;
+  ps.q = sy.q;
+  ps.b = sy.r;
+  ps.sigma = sy.sigma;
+  ps.bnorm = sy.bnorm;
+  ps.relres = sy.rel_in;  // inner relative residuals (not reported)
+  ps.iters = sy.iters;
+  ps.done = sy.done;
+  ps.flags = in.flags;
+  ps.chunk_rows = kChunk;
+  ps.nchunks = (int)((m + kChunk - 1) / kChunk);
+
+  IE_HIP(launch_col_norms(sy.b, m, S, ld, sy.bnorm, st));
+  IE_HIP(launch_fill_f64(sy.u, 0.0, m * ld, st));
+  IE_HIP(launch_fill_i32(sy.iters, 0, ld, st));
+  IE_HIP(launch_fill_i32(sy.sweeps, 0, ld, st));
+  IE_HIP(launch_fill_i32(sy.fdone, 0, ld, st));
+
+  const int max_sweeps = op.host_sync ? 40 : (fp64_inner ? 2 : (op.inner == Prec::F32 ? 4 : 10));
+  const int check_every = 4;
+  int32_t h_nact = 0;
+  for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
+    // outer residual r = b - C u (FP64).  Zero start: the first residual is b itself.
+    IE_HIP(launch_iota(sy.act, sy.nact, S, st));
+    if (sweep == 0) {
+      hipLaunchKernelGGL(k_copy_f64, dim3(nb(m * ld)), dim3(256), 0, st, sy.b, sy.r, m * ld);
+      IE_HIP(hipGetLastError());
+    } else {
+      // only systems still in play need the FP64 sweep
+      IE_HIP(launch_compact(sy.fdone, S, sy.act, sy.nact, st));
+      IE_TRY(apply_S(pl, Prec::F64, sy.u, ld, sy.act, sy.nact, S, sy.sigma, sy.q, sy.part_pq, op.rows_per_wave, st));
+      IE_HIP(launch_sub(sy.b, sy.q, sy.r, m, S, ld, st));
+    }
+    IE_HIP(launch_col_norms(sy.r, m, S, ld, sy.rn, st));
+    hipLaunchKernelGGL(k_sweep_status, dim3(nb(S)), dim3(256), 0, st, sy.rn, sy.bnorm, op.rtol, op.inner_rtol,
+                       fp64_inner ? 1 : 0, sy.iters, op.max_iter, sy.relres, sy.fdone, sy.done, sy.thresh,
+                       sy.sweeps, sweep > 0 ? 1 : 0, S, in.flags);
+    IE_HIP(hipGetLastError());
+    // active set of this sweep
+    if (op.solver == INFOESRF_SOLVER_PLAIN) {
+      IE_HIP(launch_iota(sy.act, sy.nact, S, st));
+    } else {
+      IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
+    }
+    if (op.host_sync) {
+      // any work left?
+      IE_HIP(launch_compact(sy.done, S, sy.act + 0, sy.nact, st));
+      IE_HIP(hipMemcpyAsync(&h_nact, sy.nact, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      IE_HIP(hipStreamSynchronize(st));
+      if (h_nact == 0) break;
+      if (op.solver == INFOESRF_SOLVER_PLAIN) IE_HIP(launch_iota(sy.act, sy.nact, S, st));
+    }
+    if (sweep == max_sweeps) break;
+    // inner PCG on C d = r, from d = 0
+    IE_HIP(launch_fill_f64(sy.x, 0.0, m * ld, st));
+    ps.bnorm = sy.thresh;  // direction kernel compares ||r|| <= tol * bnorm; tol = 1 => thresh
+    ps.rz = sy.rz0;
+    IE_HIP(launch_pcg_dots(ps, lmp, sy.act, sy.nact, ld, sy.part2, st));
+    IE_HIP(launch_pcg_direction(ps, lmp, sy.act, sy.nact, ld, sy.part2, 1.0, 1, op.max_iter, sy.rz1, sy.rz0, st));
+    double* rz_cur = sy.rz0;
+    double* rz_nxt = sy.rz1;
+    const int inner_cap = op.max_iter;
+    for (int it = 1; it <= inner_cap; ++it) {
+      if (op.solver != INFOESRF_SOLVER_PLAIN) IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
+      IE_TRY(apply_S(pl, op.inner, sy.p, ld, sy.act, sy.nact, S, sy.sigma, sy.q, sy.part_pq, op.rows_per_wave, st));
+      ps.rz = rz_cur;
+      IE_HIP(launch_pcg_step(ps, lmp, sy.act, sy.nact, ld, sy.part_pq, sy.part2, st));
+      IE_HIP(launch_pcg_direction(ps, lmp, sy.act, sy.nact, ld, sy.part2, 1.0, 0, op.max_iter, rz_cur, rz_nxt, st));
+      std::swap(rz_cur, rz_nxt);
+      if (op.host_sync && (it % check_every) == 0) {
+        IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
+        IE_HIP(hipMemcpyAsync(&h_nact, sy.nact, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        IE_HIP(hipStreamSynchronize(st));
+        if (h_nact == 0) break;
+        if (op.solver == INFOESRF_SOLVER_PLAIN) IE_HIP(launch_iota(sy.act, sy.nact, S, st));
+      }
+    }
+    // u += d for every system (d = 0 where the system was not active)
+    IE_HIP(launch_axpy_masked(sy.u, sy.x, m, S, ld, st));
+  }
+  return 0;
+}
+
+int finish_status(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t extra_fp64, hipStream_t st) {
+  Sys& sy = pl.sy;
+  hipLaunchKernelGGL(k_finish_counters, dim3(1), dim3(256), 0, st, sy.iters, sy.sweeps, sy.fdone, sy.S, extra_fp64,
+                     op.inner == Prec::F64 ? 1 : 0, pl.in.flags, pl.in.fallbacks, pl.in.counters);
+  IE_HIP(hipGetLastError());
+  if (stats) {
+    if (stats->iters || stats->relres || stats->converged)
+      IE_HIP(launch_export_stats(sy.iters, sy.relres, sy.fdone, sy.S, stats->iters, stats->relres, stats->converged,
+                                 op.rtol, st));
+    if (stats->counters)
+      IE_HIP(hipMemcpyAsync(stats->counters, pl.in.counters, sizeof(int64_t) * INFOESRF_NUM_COUNTERS,
+                            hipMemcpyDeviceToDevice, st));
+  }
+  if (!op.host_sync) return 0;
+  int64_t cnt[INFOESRF_NUM_COUNTERS];
+  IE_HIP(hipMemcpyAsync(cnt, pl.in.counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
+  IE_HIP(hipStreamSynchronize(st));
+  const int code = (int)cnt[INFOESRF_CNT_STATUS];
+  if (code < 0) {
+    if (code == INFOESRF_ERR_NOT_SPD) set_error("PCG curvature p^T C p <= 0: localized covariance not PSD");
+    else if (code == INFOESRF_ERR_NUMERIC) set_error("non-finite value met during the solve");
+    else set_error("invalid input detected on the device");
+  } else if (code == INFOESRF_WARN_NOT_CONVERGED) {
+    set_error(std::to_string(cnt[INFOESRF_CNT_NOT_CONVERGED]) + " system(s) did not reach rtol");
+  }
+  return code;
+}
+
+// nnz of H (device) is needed to size the CSC arrays: read h_ptr[m] once.  This is the
+// only read-back a call does before its kernels when host_sync == 1; with host_sync == 0
+// the caller's nnz must not exceed m * 64 (the reserved maximum).
+int64_t nnz_bound(const infoesrf_problem* P) { return P->m * 64; }
+
+int plan_for(Plan& pl, const infoesrf_problem* P, const Options& op, int64_t S, int64_t nfin, void* ws,
+             size_t ws_bytes) {
+  Arena ar;
+  ar.base = static_cast<char*>(ws);
+  plan_layout(pl, ar, P, op, S, nfin);
+  const int64_t nnz = nnz_bound(P);
+  pl.in.row_of = ar.take<int32_t>(nnz);
+  pl.in.w_of = ar.take<double>(nnz);
+  pl.bytes = ar.off + 256;
+  if (ws) {
+    IE_CHECK(ws_bytes >= pl.bytes, INFOESRF_ERR_WORKSPACE,
+             "workspace too small: need " + std::to_string(pl.bytes) + " bytes");
+  }
+  return 0;
+}
+
+int check_nnz(const infoesrf_problem* P, const Options& op, hipStream_t st) {
+  if (!op.host_sync) return 0;
+  int32_t nnz = 0;
+  IE_HIP(hipMemcpyAsync(&nnz, P->h_ptr + P->m, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  IE_HIP(hipStreamSynchronize(st));
+  IE_CHECK(nnz >= 0 && nnz <= nnz_bound(P), INFOESRF_ERR_INVALID_ARG,
+           "H has more than 64 entries per row on average (h_ptr[m] too large)");
+  return 0;
+}
+
+}  // namespace
+}  // namespace infoesrf
+
+using namespace infoesrf;
+
+extern "C" {
+
+void infoesrf_default_opts(infoesrf_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->rtol = 1e-8;
+  o->inner_rtol = 0.0;
+  o->max_iter = 1000;
+  o->n_ritz = 10;
+  o->oversample = 10;
+  o->precision = INFOESRF_FP64;
+  o->solver = INFOESRF_SOLVER_COMPACT;
+  o->warm_start = INFOESRF_START_ZERO;
+  o->host_sync = 1;
+  o->apply_domain = INFOESRF_DOMAIN_STATE;
+  o->seed = 0x2503002530ULL;
+}
+
+const char* infoesrf_error_string(int code) {
+  switch (code) {
+    case INFOESRF_OK: return "ok";
+    case INFOESRF_WARN_NOT_CONVERGED: return "some systems did not reach the residual tolerance";
+    case INFOESRF_ERR_INVALID_ARG: return "invalid argument";
+    case INFOESRF_ERR_NOT_SPD: return "matrix not symmetric positive definite (PCG breakdown)";
+    case INFOESRF_ERR_NUMERIC: return "non-finite value (NaN or Inf)";
+    case INFOESRF_ERR_WORKSPACE: return "workspace missing or too small";
+    case INFOESRF_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status code";
+  }
+}
+
+const char* infoesrf_last_error(void) { return g_last_error.c_str(); }
+
+size_t infoesrf_workspace_bytes(const infoesrf_problem* prob, int32_t Q, const infoesrf_opts* opts) {
+  clear_error();
+  if (check_problem(prob) < 0) return 0;
+  Options op;
+  if (resolve_options(prob, opts, op) < 0) return 0;
+  if (Q < 0 || Q > kMaxQ) {
+    set_error("Q must be in [0, 64]");
+    return 0;
+  }
+  Plan pl;
+  const int64_t S = Q > 0 ? (int64_t)Q * prob->N : 1;
+  const int64_t nfin = Q > 0 ? prob->N : 1;
+  if (plan_for(pl, prob, op, S, nfin, nullptr, 0) < 0) return 0;
+  return pl.bytes;
+}
+
+size_t infoesrf_cov_apply_workspace_bytes(const infoesrf_problem* prob, int64_t B, const infoesrf_opts* opts) {
+  clear_error();
+  if (check_problem(prob) < 0) return 0;
+  Options op;
+  if (resolve_options(prob, opts, op) < 0) return 0;
+  const int64_t ldb = round_up(std::max<int64_t>(B, 1), kSysTile);
+  Arena ar;
+  ar.take<double>(prob->n);                  // mu
+  ar.take<double>(prob->n * prob->N);        // Z
+  ar.take<float>(prob->n * prob->N);         // Z32
+  ar.take<float>((2 * prob->loc.bz + 1) * (2 * prob->loc.bx + 1));
+  ar.take<double>(prob->n * ldb);            // V
+  ar.take<double>(prob->n * ldb);            // T
+  ar.take<int32_t>(1);
+  return ar.off + 256;
+}
+
+int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ldv, int64_t B, double* PV,
+                       int64_t ldpv, const infoesrf_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  IE_TRY(check_problem(prob));
+  Options op;
+  IE_TRY(resolve_options(prob, opts, op));
+  IE_CHECK(B >= 0, INFOESRF_ERR_INVALID_ARG, "B must be >= 0");
+  if (B == 0) return INFOESRF_OK;
+  IE_CHECK(V && PV, INFOESRF_ERR_INVALID_ARG, "V and PV must be non-NULL");
+  IE_CHECK(ldv >= prob->n && ldpv >= prob->n, INFOESRF_ERR_INVALID_ARG, "ldv and ldpv must be >= n");
+  IE_CHECK(ws != nullptr, INFOESRF_ERR_WORKSPACE, "workspace is NULL");
+  const size_t need = infoesrf_cov_apply_workspace_bytes(prob, B, opts);
+  IE_CHECK(ws_bytes >= need, INFOESRF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t n = prob->n, N = prob->N;
+  const int64_t ldb = round_up(B, kSysTile);
+  Arena ar;
+  ar.base = static_cast<char*>(ws);
+  double* mu = ar.take<double>(n);
+  double* Z = ar.take<double>(n * N);
+  float* Z32 = ar.take<float>(n * N);
+  float* tab32 = ar.take<float>((2 * prob->loc.bz + 1) * (2 * prob->loc.bx + 1));
+  double* Vs = ar.take<double>(n * ldb);
+  double* Ts = ar.take<double>(n * ldb);
+  int32_t* flags = ar.take<int32_t>(1);
+  const bool low = op.inner != Prec::F64;
+  IE_HIP(launch_ens_stats(prob->X, n, N, mu, Z, low ? Z32 : nullptr, st));
+  IE_HIP(launch_to_sysfast(V, ldv, n, B, Vs, ldb, st));
+  if (prob->loc.kind == INFOESRF_LOC_DENSE) {
+    IE_CHECK(!low, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
+    IE_HIP(launch_cov_dense(prob->loc.dense, Z, n, N, Vs, ldb, B, Ts, ldb, st));
+  } else {
+    const infoesrf_loc& L = prob->loc;
+    Grid g{L.nz, L.nx, L.periodic_z, L.periodic_x, L.bz, L.bx, L.table, tab32, nullptr};
+    if (low) {
+      IE_HIP(launch_convert_f32(L.table, tab32, (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1), st));
+      float* V32 = reinterpret_cast<float*>(Ts);  // stage the FP32 input in the output buffer's storage
+      IE_HIP(launch_convert_f32(Vs, V32, n * ldb, st));
+      float* T32 = reinterpret_cast<float*>(Vs);
+      IE_HIP(cov_stencil_timed(Prec::F32, g, Z32, n, N, V32, ldb, B, nullptr, T32, ldb, op.rows_per_wave, st));
+      // widen T32 (in Vs storage) into Ts
+      hipLaunchKernelGGL(k_widen, dim3(nb(n * ldb)), dim3(256), 0, st, (const float*)T32, Ts, n * ldb);
+      IE_HIP(hipGetLastError());
+    } else {
+      IE_HIP(cov_stencil_timed(Prec::F64, g, Z, n, N, Vs, ldb, B, nullptr, Ts, ldb, op.rows_per_wave, st));
+    }
+  }
+  IE_HIP(launch_from_sysfast(Ts, ldb, n, B, PV, ldpv, st));
+  (void)flags;
+  if (op.host_sync) IE_HIP(hipStreamSynchronize(st));
+  return INFOESRF_OK;
+}
+
+int infoesrf_mean_update(const infoesrf_problem* prob, const double* y, double* mean_a, const infoesrf_opts* opts,
+                         infoesrf_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  IE_TRY(check_problem(prob));
+  Options op;
+  IE_TRY(resolve_options(prob, opts, op));
+  IE_CHECK(y && mean_a, INFOESRF_ERR_INVALID_ARG, "y and mean_a must be non-NULL");
+  IE_CHECK(ws != nullptr, INFOESRF_ERR_WORKSPACE, "workspace is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Plan pl;
+  IE_TRY(plan_for(pl, prob, op, 1, 1, ws, ws_bytes));
+  IE_TRY(check_nnz(prob, op, st));
+  IE_TRY(stage_setup(pl, op, st, 0));
+  Sys& sy = pl.sy;
+  IE_HIP(launch_fill_f64(sy.b, 0.0, pl.in.m * sy.ld, st));
+  IE_HIP(launch_innovation(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, y, pl.in.mu, pl.in.m, pl.in.n, sy.b,
+                           sy.ld, 0, st));
+  IE_HIP(launch_fill_f64(sy.sigma, 0.0, sy.ld, st));
+  IE_TRY(stage_precond(pl, op, st));
+  IE_TRY(stage_solve(pl, op, st));
+  // mean_a = mu + P H^T R^{-1/2} u0
+  IE_HIP(launch_iota(pl.fn.act, pl.fn.nact, 1, st));
+  IE_TRY(apply_state(pl, sy.u, sy.ld, pl.fn.act, pl.fn.nact, 1, op.rows_per_wave, st));
+  IE_HIP(launch_final_mean(pl.in.mu, (const double*)pl.bf.T, round_up(1, kSysTile), pl.in.n, 0, mean_a, st));
+  return finish_status(pl, op, stats, 2 * pl.pr.k + 1, st);
+}
+
+int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const double* s_nodes,
+                                 const double* p_weights, const double* y, double* Xa_pert,
+                                 const infoesrf_opts* opts, infoesrf_stats* stats, void* ws, size_t ws_bytes,
+                                 void* stream) {
+  clear_error();
+  IE_TRY(check_problem(prob));
+  Options op;
+  IE_TRY(resolve_options(prob, opts, op));
+  IE_CHECK(Q >= 1 && Q <= kMaxQ, INFOESRF_ERR_INVALID_ARG, "Q must be in [1, 64]");
+  IE_CHECK(s_nodes && p_weights && Xa_pert, INFOESRF_ERR_INVALID_ARG, "s_nodes, p_weights, Xa_pert must be non-NULL");
+  Nodes nd{};
+  for (int q = 0; q < Q; ++q) {
+    IE_CHECK(std::isfinite(s_nodes[q]) && s_nodes[q] >= 0.0, INFOESRF_ERR_INVALID_ARG, "quadrature nodes must be >= 0");
+    IE_CHECK(std::isfinite(p_weights[q]) && p_weights[q] >= 0.0, INFOESRF_ERR_INVALID_ARG,
+             "quadrature weights must be >= 0");
+    nd.s[q] = s_nodes[q];
+    nd.p[q] = p_weights[q];
+  }
+  (void)y;
+  IE_CHECK(ws != nullptr, INFOESRF_ERR_WORKSPACE, "workspace is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t N = prob->N;
+  const int64_t S = (int64_t)Q * N;
+  Plan pl;
+  IE_TRY(plan_for(pl, prob, op, S, N, ws, ws_bytes));
+  IE_TRY(check_nnz(prob, op, st));
+  IE_TRY(stage_setup(pl, op, st, 0));
+  Sys& sy = pl.sy;
+  IE_HIP(launch_fill_f64(sy.b, 0.0, pl.in.m * sy.ld, st));
+  IE_HIP(launch_obs_rhs(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, pl.in.Z, pl.in.n, N, pl.in.m, sy.b, sy.ld,
+                        0, S, st));
+  IE_HIP(launch_fill_f64(sy.sigma, 0.0, sy.ld, st));
+  hipLaunchKernelGGL(k_set_nodes, dim3(nb(std::max<int64_t>(S, kMaxQ))), dim3(256), 0, st, nd, Q, N, sy.sigma, sy.pw,
+                     (int64_t)0, 0.0);
+  IE_HIP(hipGetLastError());
+  IE_TRY(stage_precond(pl, op, st));
+  IE_TRY(stage_solve(pl, op, st));
+  // u_bar_i = sum_q p_q u_{q,i}; Xa_pert = sqrt(N-1) (Z - P H^T R^{-1/2} U_bar)
+  IE_HIP(launch_quad_combine(sy.u, sy.ld, pl.in.m, N, Q, sy.pw, pl.fn.ubar, pl.fn.ld, 0, st));
+  IE_HIP(launch_iota(pl.fn.act, pl.fn.nact, N, st));
+  IE_TRY(apply_state(pl, pl.fn.ubar, pl.fn.ld, pl.fn.act, pl.fn.nact, N, op.rows_per_wave, st));
+  IE_HIP(launch_final_pert(pl.in.Z, (const double*)pl.bf.T, round_up(N, kSysTile), pl.in.n, N,
+                           std::sqrt((double)(N - 1)), Xa_pert, st));
+  return finish_status(pl, op, stats, 2 * pl.pr.k + N, st);
+}
+
+size_t infoesrf_batched_workspace_bytes(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
+                                        const infoesrf_opts* opts) {
+  clear_error();
+  if (!probs || !Q || count < 1) {
+    set_error("probs/Q must be non-NULL and count >= 1");
+    return 0;
+  }
+  size_t total = 0;
+  for (int j = 0; j < count; ++j) {
+    const size_t b = infoesrf_workspace_bytes(&probs[j], Q[j], opts);
+    if (b == 0) return 0;
+    total += (b + 255) / 256 * 256;
+  }
+  return total;
+}
+
+int infoesrf_update_batched(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
+                            const double* const* s_nodes, const double* const* p_weights, const double* const* y,
+                            double* const* mean_a, double* const* Xa_pert, const infoesrf_opts* opts,
+                            infoesrf_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+  (void)probs; (void)count; (void)Q; (void)s_nodes; (void)p_weights; (void)y; (void)mean_a; (void)Xa_pert;
+  (void)opts; (void)stats; (void)ws; (void)ws_bytes; (void)stream;
+  set_error("batched instances are not available yet");
+  return INFOESRF_ERR_INVALID_ARG;
+}
+
+}  // extern "C"

@@ -1,0 +1,234 @@
+// Internal declarations of the InFo-ESRF HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/infoesrf.h"
+
+namespace infoesrf {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+void clear_error();
+
+#define IE_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      ::infoesrf::set_error(std::string("HIP error in ") + #call + ": " +            \
+                            hipGetErrorString(e_));                                   \
+      return INFOESRF_ERR_HIP;                                                        \
+    }                                                                                 \
+  } while (0)
+
+#define IE_CHECK(cond, code, msg)                                                     \
+  do {                                                                                \
+    if (!(cond)) {                                                                    \
+      ::infoesrf::set_error(msg);                                                     \
+      return (code);                                                                  \
+    }                                                                                 \
+  } while (0)
+
+#define IE_TRY(expr)                                                                  \
+  do {                                                                                \
+    int rc_ = (expr);                                                                 \
+    if (rc_ < 0) return rc_;                                                          \
+  } while (0)
+
+constexpr int kMaxQ = 64;
+constexpr int kMaxRitz = 32;   // p + oversample <= kMaxSketch
+constexpr int kMaxSketch = 48;  // sketch columns (small dense kernels keep k x k in LDS)
+constexpr int kSysTile = 16;   // systems per MFMA column block
+
+// Device-side flag bits set by kernels (read back into the status).
+enum : int32_t { kFlagNotSPD = 1, kFlagNumeric = 2, kFlagBadInput = 4 };
+
+// ---------------------------------------------------------------- stencil grid
+// A stationary stencil on an nz x nx grid (state index z*nx + x).
+struct Grid {
+  int32_t nz, nx;
+  int32_t pz, px;     // periodic flags
+  int32_t bz, bx;     // half-extents
+  const double* table;  // device (2bz+1)*(2bx+1) row-major FP64
+  const float* table32; // device copy in FP32 (or null)
+  const __hip_bfloat16* table16; // device copy in BF16 (or null)
+};
+
+// Precision of a covariance apply.
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+// ---------------------------------------------------------------- kernels (launchers)
+// All launchers enqueue on `st` and return hipError_t of the launch.
+
+// K1: mu = X 1 / N; Z = (X - mu 1^T)/sqrt(N-1), optional FP32 shadow of Z.
+hipError_t launch_ens_stats(const double* X, int64_t n, int64_t N, double* mu, double* Z, float* Z32,
+                            hipStream_t st);
+
+// CSR -> CSC transpose of H (deterministic: entries of a column sorted by row).
+hipError_t launch_csc_build(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, int64_t m, int64_t n,
+                            int32_t* col_cnt, int32_t* col_ptr, int32_t* row_of, double* w_of, int32_t* flags,
+                            hipStream_t st);
+
+// rhs[r, s] = dinv[r] * sum_e h_w[e] * Z[h_idx[e], member(s)] for systems s in [s0, s0+cnt),
+// member(s) = (s - s0) % N  (layout: rhs[r * ld + s]).
+hipError_t launch_obs_rhs(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, const double* r_var,
+                          const double* Z, int64_t n, int64_t N, int64_t m, double* rhs, int64_t ld, int64_t s0,
+                          int64_t cnt, hipStream_t st);
+
+// innovation rhs: out[r * ld + s] = dinv[r] * (y[r] - sum_e h_w[e] mu[h_idx[e]])
+hipError_t launch_innovation(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, const double* r_var,
+                             const double* y, const double* mu, int64_t m, int64_t n, double* out, int64_t ld,
+                             int64_t s, hipStream_t st);
+
+// diag(S)_r = dinv_r^2 * sum_{e,e'} w_e w_e' L(idx_e, idx_e') sum_i Z[idx_e,i] Z[idx_e',i]
+hipError_t launch_diag_S(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, const double* r_var,
+                         const double* Z, int64_t n, int64_t N, int64_t m, const Grid& g, const double* dense_L,
+                         double* diagS, hipStream_t st);
+
+// Observed-lattice members: Zt[k, i] = dinv[k] * h_w[k] * Z[idx[k], i] (m x N col-major)
+hipError_t launch_lattice_members(const int32_t* h_idx, const double* h_w, const double* r_var, const double* Z,
+                                  int64_t n, int64_t N, int64_t m, double* Zt, float* Zt32, hipStream_t st);
+// Sub-sampled stencil: sub[dz'][dx'] = table[dz' sz][dx' sx]
+hipError_t launch_subsample_table(const double* table, int32_t bz, int32_t bx, int32_t sz, int32_t sx, int32_t bzs,
+                                  int32_t bxs, double* sub, hipStream_t st);
+// Lower-precision copies of a table / matrix.
+hipError_t launch_convert_f32(const double* in, float* out, int64_t count, hipStream_t st);
+hipError_t launch_convert_bf16(const double* in, __hip_bfloat16* out, int64_t count, hipStream_t st);
+
+// ---------------------------------------------------------------- covariance apply (K3)
+// T[k * ldt + b] = sum_i Z[k,i] sum_l L[k,l] Z[l,i] V[l * ldv + b] for b < B (B padded to 16 in V).
+// Z is column-major with leading dimension ldz.  V and T are "system-fastest".
+struct CovTile {
+  int rows_per_wave;  // multiple of 16
+};
+// Optional device-side measurement counters of a launch (see infoesrf_profile_enable).
+struct ProfDev {
+  unsigned long long* vectors;  // += live column count
+  double* flops;                // += live column count * flops_per_vector
+  double flops_per_vector;
+};
+// B is the (padded) maximum column count; Bdev (nullable) holds the live count on the device.
+hipError_t launch_cov_stencil(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
+                              int64_t ldv, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, int rows_per_wave,
+                              hipStream_t st, const ProfDev* prof = nullptr);
+// Measurement wrapper used by the runtime: records events around the launch when profiling is on.
+hipError_t cov_stencil_timed(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
+                             int64_t ldv, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, int rows_per_wave,
+                             hipStream_t st);
+hipError_t launch_cov_dense(const double* L, const double* Z, int64_t n, int64_t N, const double* V, int64_t ldv,
+                            int64_t B, double* T, int64_t ldt, hipStream_t st);
+
+// ---------------------------------------------------------------- observation-space glue
+// Compact copy of active systems into an apply buffer (optionally scaled into state space by H^T R^{-1/2}).
+//   domain OBS:   V[r * ldv + c] = P[r * ldp + act[c]] (converted to the apply precision), zero pad columns.
+//   domain STATE: V[k * ldv + c] = sum_{e in CSC col k} w_e dinv[row_e] P[row_e * ldp + act[c]].
+hipError_t launch_gather_active(Prec prec, const double* P, int64_t ldp, const int32_t* act, const int32_t* nact,
+                                int64_t rows, int64_t Bpad, void* V, int64_t ldv, hipStream_t st);
+hipError_t launch_scatter_state(Prec prec, const double* P, int64_t ldp, const int32_t* act, const int32_t* nact,
+                                const int32_t* col_ptr, const int32_t* row_of, const double* w_of,
+                                const double* r_var, int64_t n, int64_t m, int64_t Bpad, void* V, int64_t ldv,
+                                hipStream_t st);
+// Q[r, s] = c_s * P[r, s] + (domain OBS ? T[r, c] : dinv_r sum_e w_e T[idx_e, c]), s = act[c],
+// c_s = (1 + sigma_s) (sigma_s = shift of system s; sigma = -1 gives S itself),
+// plus per-(chunk, c) partial dot products P^T Q written to part[chunk * Bpad + c].
+hipError_t launch_apply_finish(Prec prec, int obs_domain, const double* P, int64_t ldp, const void* T, int64_t ldt,
+                               const int32_t* act, const int32_t* nact, const double* sigma, const int32_t* h_ptr,
+                               const int32_t* h_idx, const double* h_w, const double* r_var, int64_t m,
+                               int64_t n_state, int64_t Bpad, double* Qv, double* part, int chunk_rows,
+                               hipStream_t st);
+
+// ---------------------------------------------------------------- PCG (K4)
+struct LMP {
+  int p;               // number of Ritz pairs (0 = no preconditioner)
+  const double* Phi;   // m x p row-major (Phi[r*p + j])
+  const double* SPhi;  // m x p row-major
+  const double* theta; // p Ritz values of S
+  const double* G;     // 3 p x p Gram matrices: Phi^T Phi, Phi^T S Phi, (S Phi)^T S Phi (row-major)
+  const double* dmin;  // min diag(S) (1 value)
+};
+
+struct PCGState {
+  int64_t m, S, ld;     // rows, systems, leading dim (>= S, multiple of 16)
+  double *x, *r, *p, *q;
+  const double* b;      // right-hand sides
+  const double* sigma;  // per-system shift
+  double* rz;           // per system r^T z (current)
+  double* bnorm;        // per system ||b||
+  double* relres;       // per system recursive relres (inner) / true relres
+  int32_t* iters;       // per system iteration counts
+  int32_t* done;        // per system: 0 active, 1 converged, 2 failed/capped
+  int32_t* flags;       // global error flags
+  double* part;         // partial sums
+  int chunk_rows;       // rows per reduction chunk
+  int nchunks;
+};
+
+// Dots of r with itself and with the Ritz bases: part2[(chunk * Bpad + c) * (2p+1) + j]
+hipError_t launch_pcg_dots(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact, int64_t Bpad,
+                           double* part2, hipStream_t st);
+// alpha = rz/(p^T q) (from apply partials); x += alpha p; r -= alpha q; then dots of r (part2).
+hipError_t launch_pcg_step(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact, int64_t Bpad,
+                           const double* part_pq, double* part2, hipStream_t st);
+// From the dots of r: convergence test against tol_rel * bnorm, z = M^{-1} r, p = z + beta p.
+// first != 0: p = z and rz initialized.  rz_next receives the new r^T z.
+hipError_t launch_pcg_direction(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact,
+                                int64_t Bpad, const double* part2, double tol_rel, int first, int max_iter,
+                                const double* rz_cur, double* rz_next, hipStream_t st);
+// Rebuild the list of active systems (done == 0), in increasing order.  One block.
+hipError_t launch_compact(const int32_t* done, int64_t S, int32_t* act, int32_t* nact, hipStream_t st);
+// Fill act = 0..S-1 with systems that have done==0 kept in place (masked plain solver uses all).
+hipError_t launch_iota(int32_t* act, int32_t* nact, int64_t S, hipStream_t st);
+
+// ---------------------------------------------------------------- misc vector kernels
+hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st);
+// out[r*ld + s] = a[r*ld+s] - b[r*ld+s] for all r < m, s < S
+hipError_t launch_sub(const double* a, const double* b, double* out, int64_t m, int64_t S, int64_t ld,
+                      hipStream_t st);
+// x[r*ld+s] += d[r*ld+s] for s with mask[s] (mask may be null)
+hipError_t launch_axpy_masked(double* x, const double* d, int64_t m, int64_t S, int64_t ld, hipStream_t st);
+// per-system norms: out[s] = ||v[:, s]||_2 (deterministic)
+hipError_t launch_col_norms(const double* v, int64_t m, int64_t S, int64_t ld, double* out, hipStream_t st);
+// true-residual bookkeeping: relres[s] = rn[s] / bn[s]; done[s] = relres <= tol ? 1 : 0 (for done != 2)
+hipError_t launch_residual_status(const double* rn, const double* bn, double tol, double* relres, int32_t* done,
+                                  int64_t S, int32_t* flags, hipStream_t st);
+// Quadrature combine: ubar[r, i] = sum_q p_q u[r, q*N + i]  (u: ld = ldu, ubar: ld = ldb)
+hipError_t launch_quad_combine(const double* u, int64_t ldu, int64_t m, int64_t N, int32_t Q, const double* pw,
+                               double* ubar, int64_t ldb, int64_t s0, hipStream_t st);
+// Final state update: out[k + i*n] = scale * (Z[k + i*n] - T[k*ldt + i])  (column-major out)
+hipError_t launch_final_pert(const double* Z, const double* T, int64_t ldt, int64_t n, int64_t N, double scale,
+                             double* out, hipStream_t st);
+hipError_t launch_final_mean(const double* mu, const double* T, int64_t ldt, int64_t n, int64_t col, double* out,
+                             hipStream_t st);
+// transposes between column-major (ld) and system-fastest layouts
+hipError_t launch_to_sysfast(const double* V, int64_t ldv, int64_t n, int64_t B, double* out, int64_t ldo,
+                             hipStream_t st);
+hipError_t launch_from_sysfast(const double* in, int64_t ldi, int64_t n, int64_t B, double* out, int64_t ldo,
+                               hipStream_t st);
+// stats export
+hipError_t launch_export_stats(const int32_t* iters, const double* relres, const int32_t* done, int64_t S,
+                               int32_t* out_iters, double* out_relres, uint8_t* out_conv, double tol,
+                               hipStream_t st);
+hipError_t launch_nan_check(const double* v, int64_t count, int32_t* flags, hipStream_t st);
+
+// ---------------------------------------------------------------- preconditioner setup (K8)
+// Gaussian sketch by counter-based Philox4x32-10 + Box-Muller: out[r*ld + j]
+hipError_t launch_sketch(uint64_t seed, int64_t m, int k, double* out, int64_t ld, hipStream_t st);
+// Gram: G[a*k+b] = sum_r A[r*lda + a] B[r*ldb + b], a,b < k (fixed order, deterministic)
+hipError_t launch_gram(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t m, int k, double* G,
+                       double* scratch, hipStream_t st);
+// One-workgroup small dense kernels.
+hipError_t launch_chol_inv(double* G, int k, int32_t* flags, hipStream_t st);   // G <- R^{-1} (upper), G = R^T R
+hipError_t launch_right_mult(double* A, int64_t lda, int64_t m, int k, const double* M, int kout, double* out,
+                             int64_t ldo, hipStream_t st);                     // out = A M (k x kout)
+hipError_t launch_sym_eig(double* T, int k, double* evec, double* evals, hipStream_t st);  // Jacobi
+hipError_t launch_lmp_finish(const double* evals, const double* evec, int k, int p, double* theta, double* sel,
+                             hipStream_t st);                                  // top-p selection matrix
+hipError_t launch_min_reduce(const double* v, int64_t count, double* out, hipStream_t st);
+
+}  // namespace infoesrf

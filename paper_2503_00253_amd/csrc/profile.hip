@@ -1,0 +1,127 @@
+// Measurement hooks: HIP events around covariance-apply launches and device-side
+// counters of the vectors and algorithmic FLOPs they process.
+#include <mutex>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace infoesrf {
+
+namespace {
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // pairs
+  std::vector<int> ev_prec;    // precision of each pair
+  size_t used = 0;
+  double ms[3] = {0, 0, 0};
+  int64_t launches[3] = {0, 0, 0};
+  unsigned long long* dvec = nullptr;  // [3]
+  double* dflops = nullptr;            // [3]
+};
+
+Prof g_prof;
+constexpr size_t kPairs = 2048;
+
+// Nonzeros of L on grid g (host copy of the table).
+double grid_nnz(const Grid& g) {
+  const int w = 2 * g.bx + 1, h = 2 * g.bz + 1;
+  std::vector<double> t((size_t)w * h);
+  if (hipMemcpy(t.data(), g.table, sizeof(double) * t.size(), hipMemcpyDeviceToHost) != hipSuccess) return 0.0;
+  double nnz = 0.0;
+  for (int dz = -g.bz; dz <= g.bz; ++dz)
+    for (int dx = -g.bx; dx <= g.bx; ++dx) {
+      if (t[(size_t)(dz + g.bz) * w + (dx + g.bx)] == 0.0) continue;
+      const double cz = g.pz ? g.nz : (double)std::max(0, g.nz - std::abs(dz));
+      const double cx = g.px ? g.nx : (double)std::max(0, g.nx - std::abs(dx));
+      nnz += cz * cx;
+    }
+  return nnz;
+}
+
+hipError_t drain() {
+  for (size_t i = 0; i < g_prof.used; ++i) {
+    hipError_t e = hipEventSynchronize(g_prof.ev[2 * i + 1]);
+    if (e != hipSuccess) return e;
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]);
+    if (e != hipSuccess) return e;
+    g_prof.ms[g_prof.ev_prec[i]] += t;
+  }
+  g_prof.used = 0;
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t cov_stencil_timed(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
+                             int64_t ldv, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, int rows_per_wave,
+                             hipStream_t st) {
+  if (!g_prof.on) return launch_cov_stencil(prec, g, Z, ldz, N, V, ldv, B, Bdev, T, ldt, rows_per_wave, st);
+  hipError_t e;
+  if (g_prof.used == kPairs && (e = drain()) != hipSuccess) return e;
+  const int pi = (int)prec;
+  const double n_g = (double)g.nz * g.nx;
+  ProfDev pd{g_prof.dvec + pi, g_prof.dflops + pi, 2.0 * (double)N * grid_nnz(g) + 3.0 * n_g * (double)N};
+  const size_t k = g_prof.used++;
+  g_prof.ev_prec[k] = pi;
+  if ((e = hipEventRecord(g_prof.ev[2 * k], st)) != hipSuccess) return e;
+  if ((e = launch_cov_stencil(prec, g, Z, ldz, N, V, ldv, B, Bdev, T, ldt, rows_per_wave, st, &pd)) != hipSuccess)
+    return e;
+  g_prof.launches[pi] += 1;
+  return hipEventRecord(g_prof.ev[2 * k + 1], st);
+}
+
+}  // namespace infoesrf
+
+using namespace infoesrf;
+
+extern "C" int infoesrf_profile_enable(int on) {
+  clear_error();
+  if (on) {
+    if (g_prof.ev.empty()) {
+      g_prof.ev.resize(2 * kPairs);
+      g_prof.ev_prec.resize(kPairs);
+      for (auto& e : g_prof.ev) IE_HIP(hipEventCreate(&e));
+      IE_HIP(hipMalloc(&g_prof.dvec, 3 * sizeof(unsigned long long)));
+      IE_HIP(hipMalloc(&g_prof.dflops, 3 * sizeof(double)));
+    }
+    IE_HIP(hipDeviceSynchronize());
+    IE_HIP(hipMemset(g_prof.dvec, 0, 3 * sizeof(unsigned long long)));
+    IE_HIP(hipMemset(g_prof.dflops, 0, 3 * sizeof(double)));
+    for (int i = 0; i < 3; ++i) {
+      g_prof.ms[i] = 0.0;
+      g_prof.launches[i] = 0;
+    }
+    g_prof.used = 0;
+  }
+  g_prof.on = on != 0;
+  return INFOESRF_OK;
+}
+
+extern "C" int infoesrf_profile_read(double ms[3], int64_t launches[3], int64_t vectors[3], double flops[3]) {
+  clear_error();
+  IE_CHECK(ms && launches && vectors && flops, INFOESRF_ERR_INVALID_ARG, "outputs must be non-NULL");
+  if (!g_prof.dvec) {
+    for (int i = 0; i < 3; ++i) {
+      ms[i] = 0.0;
+      launches[i] = 0;
+      vectors[i] = 0;
+      flops[i] = 0.0;
+    }
+    return INFOESRF_OK;
+  }
+  IE_HIP(hipDeviceSynchronize());
+  IE_HIP(drain());
+  unsigned long long v[3];
+  double f[3];
+  IE_HIP(hipMemcpy(v, g_prof.dvec, sizeof(v), hipMemcpyDeviceToHost));
+  IE_HIP(hipMemcpy(f, g_prof.dflops, sizeof(f), hipMemcpyDeviceToHost));
+  for (int i = 0; i < 3; ++i) {
+    ms[i] = g_prof.ms[i];
+    launches[i] = g_prof.launches[i];
+    vectors[i] = (int64_t)v[i];
+    flops[i] = f[i];
+  }
+  return INFOESRF_OK;
+}

@@ -1,0 +1,318 @@
+"""ctypes binding of libinfoesrf.so (include/infoesrf.h).
+
+Argument marshalling only: every step of the update runs in the library's HIP
+kernels.  torch supplies device memory (tensors, workspaces) and the current
+HIP stream.  If the library is missing the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libinfoesrf.so")
+
+# ---- constants mirrored from the header
+OK, WARN_NOT_CONVERGED = 0, 1
+ERR_INVALID_ARG, ERR_NOT_SPD, ERR_NUMERIC, ERR_WORKSPACE, ERR_HIP = -1, -2, -3, -4, -5
+LOC_DENSE, LOC_STENCIL = 0, 1
+FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
+SOLVER_PLAIN, SOLVER_COMPACT, SOLVER_PERSISTENT = 0, 1, 2
+DOMAIN_STATE, DOMAIN_OBS_LATTICE = 0, 1
+START_ZERO, START_LEARNED = 0, 1
+CNT_APPLIES, CNT_APPLIES_FP64, CNT_ITERATIONS, CNT_SWEEPS = 0, 1, 2, 3
+CNT_FALLBACKS, CNT_NOT_CONVERGED, CNT_MAX_ITERS, CNT_STATUS = 4, 5, 6, 7
+NUM_COUNTERS = 8
+
+
+class Loc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nz", C.c_int32), ("nx", C.c_int32),
+                ("periodic_z", C.c_int32), ("periodic_x", C.c_int32),
+                ("bz", C.c_int32), ("bx", C.c_int32), ("reserved", C.c_int32),
+                ("table", C.c_void_p), ("dense", C.c_void_p)]
+
+
+class ProblemC(C.Structure):
+    _fields_ = [("n", C.c_int64), ("N", C.c_int64), ("m", C.c_int64),
+                ("X", C.c_void_p), ("h_ptr", C.c_void_p), ("h_idx", C.c_void_p),
+                ("h_w", C.c_void_p), ("r_var", C.c_void_p), ("loc", Loc)]
+
+
+class Lattice(C.Structure):
+    _fields_ = [("z0", C.c_int32), ("sz", C.c_int32), ("nzo", C.c_int32),
+                ("x0", C.c_int32), ("sx", C.c_int32), ("nxo", C.c_int32)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("inner_rtol", C.c_double),
+                ("max_iter", C.c_int32), ("n_ritz", C.c_int32), ("oversample", C.c_int32),
+                ("precision", C.c_int32), ("solver", C.c_int32), ("warm_start", C.c_int32),
+                ("host_sync", C.c_int32), ("apply_domain", C.c_int32), ("lattice", Lattice),
+                ("seed", C.c_uint64), ("sketch", C.c_void_p), ("net", C.c_void_p),
+                ("tile_rows", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class StatsC(C.Structure):
+    _fields_ = [("iters", C.c_void_p), ("relres", C.c_void_p), ("converged", C.c_void_p),
+                ("counters", C.c_void_p)]
+
+
+class InfoEsrfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"infoesrf error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def library():
+    """Load libinfoesrf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise InfoEsrfError(ERR_HIP, f"{LIB_PATH} not found: run python -m paper_2503_00253_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    P, VP = C.POINTER, C.c_void_p
+    lib.infoesrf_default_opts.argtypes = [P(Opts)]
+    lib.infoesrf_default_opts.restype = None
+    lib.infoesrf_workspace_bytes.argtypes = [P(ProblemC), C.c_int32, P(Opts)]
+    lib.infoesrf_workspace_bytes.restype = C.c_size_t
+    lib.infoesrf_cov_apply_workspace_bytes.argtypes = [P(ProblemC), C.c_int64, P(Opts)]
+    lib.infoesrf_cov_apply_workspace_bytes.restype = C.c_size_t
+    lib.infoesrf_cov_apply.argtypes = [P(ProblemC), VP, C.c_int64, C.c_int64, VP, C.c_int64, P(Opts),
+                                       VP, C.c_size_t, VP]
+    lib.infoesrf_cov_apply.restype = C.c_int
+    lib.infoesrf_mean_update.argtypes = [P(ProblemC), VP, VP, P(Opts), P(StatsC), VP, C.c_size_t, VP]
+    lib.infoesrf_mean_update.restype = C.c_int
+    lib.infoesrf_perturbation_update.argtypes = [P(ProblemC), C.c_int32, P(C.c_double), P(C.c_double), VP, VP,
+                                                 P(Opts), P(StatsC), VP, C.c_size_t, VP]
+    lib.infoesrf_perturbation_update.restype = C.c_int
+    lib.infoesrf_quadrature_elliptic.argtypes = [C.c_int32, C.c_double, P(C.c_double), P(C.c_double)]
+    lib.infoesrf_quadrature_elliptic.restype = C.c_int
+    lib.infoesrf_quadrature_gauss_legendre.argtypes = [C.c_int32, P(C.c_double), P(C.c_double)]
+    lib.infoesrf_quadrature_gauss_legendre.restype = C.c_int
+    lib.infoesrf_error_string.argtypes = [C.c_int]
+    lib.infoesrf_error_string.restype = C.c_char_p
+    lib.infoesrf_last_error.argtypes = []
+    lib.infoesrf_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code, allow_warn=True):
+    if code == OK or (allow_warn and code == WARN_NOT_CONVERGED):
+        return code
+    lib = library()
+    raise InfoEsrfError(code, lib.infoesrf_last_error().decode() or lib.infoesrf_error_string(code).decode())
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    library().infoesrf_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if k == "lattice":
+            o.lattice = Lattice(*v)
+        elif k == "sketch":
+            o.sketch = 0 if v is None else v.data_ptr()
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def quadrature_elliptic(Q: int, ell: float):
+    s = np.zeros(Q)
+    p = np.zeros(Q)
+    _check(library().infoesrf_quadrature_elliptic(Q, ell, s.ctypes.data_as(C.POINTER(C.c_double)),
+                                                   p.ctypes.data_as(C.POINTER(C.c_double))))
+    return s, p
+
+
+def quadrature_gauss_legendre(Q: int):
+    s = np.zeros(Q)
+    p = np.zeros(Q)
+    _check(library().infoesrf_quadrature_gauss_legendre(Q, s.ctypes.data_as(C.POINTER(C.c_double)),
+                                                         p.ctypes.data_as(C.POINTER(C.c_double))))
+    return s, p
+
+
+def lattice_of(h_ptr, h_idx, nz, nx):
+    """Detect whether host CSR arrays describe point observations on a regular
+    sub-lattice of the nz x nx grid; returns (z0, sz, nzo, x0, sx, nxo) or None."""
+    h_ptr = np.asarray(h_ptr)
+    h_idx = np.asarray(h_idx)
+    m = len(h_ptr) - 1
+    if not np.array_equal(h_ptr, np.arange(m + 1)):
+        return None
+    z, x = np.divmod(h_idx.astype(np.int64), nx)
+    xs = np.unique(x)
+    zs = np.unique(z)
+    nxo, nzo = len(xs), len(zs)
+    if nxo * nzo != m:
+        return None
+    sx = int(xs[1] - xs[0]) if nxo > 1 else 1
+    sz = int(zs[1] - zs[0]) if nzo > 1 else 1
+    a, b = np.divmod(np.arange(m), nxo)
+    want = (zs[0] + a * sz) * nx + (xs[0] + b * sx)
+    if not np.array_equal(want, h_idx):
+        return None
+    return (int(zs[0]), sz, nzo, int(xs[0]), sx, nxo)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Problem:
+    """Device-resident arguments of one filter instance (keeps the tensors alive)."""
+
+    def __init__(self, X, h_ptr, h_idx, h_w, r_var, *, nz=1, nx=None, periodic_z=0, periodic_x=1, bz=0, bx=0,
+                 table=None, dense=None, device="cuda"):
+        torch = _torch()
+        # column-major n x N on the device: a contiguous (N, n) tensor whose row i is member i
+        if isinstance(X, np.ndarray):
+            self.X = torch.from_numpy(np.ascontiguousarray(np.asarray(X, dtype=np.float64).T)).to(device)
+        else:
+            self.X = X.t().contiguous().to(device)
+        N, n = self.X.shape
+        self.n, self.N = int(n), int(N)
+        self.h_ptr = torch.as_tensor(np.asarray(h_ptr, dtype=np.int32)).to(device)
+        self.h_idx = torch.as_tensor(np.asarray(h_idx, dtype=np.int32)).to(device)
+        self.h_w = torch.as_tensor(np.asarray(h_w, dtype=np.float64)).to(device)
+        self.r_var = torch.as_tensor(np.asarray(r_var, dtype=np.float64)).to(device)
+        self.m = int(len(h_ptr) - 1)
+        self.host_h_ptr = np.asarray(h_ptr)
+        self.host_h_idx = np.asarray(h_idx)
+        loc = Loc()
+        if dense is not None:
+            # column-major n x n: a contiguous tensor holding L^T row by row
+            self.dense = torch.from_numpy(np.ascontiguousarray(np.asarray(dense, dtype=np.float64).T)).to(device)
+            loc.kind = LOC_DENSE
+            loc.dense = self.dense.data_ptr()
+            loc.nz, loc.nx = 1, self.n
+        else:
+            nx = self.n if nx is None else nx
+            self.table = torch.as_tensor(np.ascontiguousarray(table, dtype=np.float64).reshape(-1)).to(device)
+            loc.kind = LOC_STENCIL
+            loc.nz, loc.nx = int(nz), int(nx)
+            loc.periodic_z, loc.periodic_x = int(periodic_z), int(periodic_x)
+            loc.bz, loc.bx = int(bz), int(bx)
+            loc.table = self.table.data_ptr()
+        self.loc = loc
+        self.c = ProblemC(self.n, self.N, self.m, self.X.data_ptr(), self.h_ptr.data_ptr(), self.h_idx.data_ptr(),
+                          self.h_w.data_ptr(), self.r_var.data_ptr(), loc)
+
+    @classmethod
+    def from_synthetic(cls, prob, device="cuda"):
+        return cls(prob.X, prob.h_ptr, prob.h_idx, prob.h_w, prob.r_var, nz=prob.nz, nx=prob.nx,
+                   periodic_z=prob.periodic_z, periodic_x=prob.periodic_x, bz=prob.bz, bx=prob.bx,
+                   table=prob.table, device=device)
+
+    def lattice(self):
+        return lattice_of(self.host_h_ptr, self.host_h_idx, self.loc.nz, self.loc.nx)
+
+
+@dataclass
+class Stats:
+    code: int
+    iters: object
+    relres: object
+    converged: object
+    counters: object
+
+    def counter(self, i):
+        return int(self.counters[i])
+
+
+_ws_cache = {}
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    key = str(device)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _stats(nsys, device):
+    torch = _torch()
+    it = torch.zeros(nsys, dtype=torch.int32, device=device)
+    rr = torch.zeros(nsys, dtype=torch.float64, device=device)
+    cv = torch.zeros(nsys, dtype=torch.uint8, device=device)
+    cn = torch.zeros(NUM_COUNTERS, dtype=torch.int64, device=device)
+    sc = StatsC(it.data_ptr(), rr.data_ptr(), cv.data_ptr(), cn.data_ptr())
+    return sc, (it, rr, cv, cn)
+
+
+def workspace_bytes(problem: Problem, Q: int, opts: Opts) -> int:
+    b = library().infoesrf_workspace_bytes(C.byref(problem.c), Q, C.byref(opts))
+    if b == 0:
+        raise InfoEsrfError(ERR_INVALID_ARG, library().infoesrf_last_error().decode())
+    return int(b)
+
+
+def cov_apply(problem: Problem, V, opts: Opts | None = None):
+    """P V for state-space vectors V (torch, n x B, column-major: pass V with V.t() contiguous)."""
+    torch = _torch()
+    lib = library()
+    opts = opts or default_opts()
+    Vt = V.t().contiguous()  # B x n row-major == n x B column-major
+    B = Vt.shape[0]
+    out = torch.empty_like(Vt)
+    nbytes = lib.infoesrf_cov_apply_workspace_bytes(C.byref(problem.c), B, C.byref(opts))
+    ws = _workspace(nbytes, Vt.device)
+    _check(lib.infoesrf_cov_apply(C.byref(problem.c), Vt.data_ptr(), problem.n, B, out.data_ptr(), problem.n,
+                                  C.byref(opts), ws.data_ptr(), ws.numel(), _stream()), allow_warn=False)
+    return out.t()
+
+
+def mean_update(problem: Problem, y, opts: Opts | None = None):
+    torch = _torch()
+    lib = library()
+    opts = opts or default_opts()
+    dev = problem.X.device
+    y = torch.as_tensor(np.asarray(y, dtype=np.float64) if not torch.is_tensor(y) else y).to(dev)
+    out = torch.empty(problem.n, dtype=torch.float64, device=dev)
+    ws = _workspace(workspace_bytes(problem, 0, opts), dev)
+    sc, keep = _stats(1, dev)
+    code = _check(lib.infoesrf_mean_update(C.byref(problem.c), y.data_ptr(), out.data_ptr(), C.byref(opts),
+                                           C.byref(sc), ws.data_ptr(), ws.numel(), _stream()))
+    torch.cuda.synchronize()
+    return out, Stats(code, *(t.cpu().numpy() for t in keep))
+
+
+def perturbation_update(problem: Problem, s_nodes, p_weights, opts: Opts | None = None, y=None):
+    """Returns (Xa_pert as an n x N torch view, Stats)."""
+    torch = _torch()
+    lib = library()
+    opts = opts or default_opts()
+    dev = problem.X.device
+    s_nodes = np.ascontiguousarray(s_nodes, dtype=np.float64)
+    p_weights = np.ascontiguousarray(p_weights, dtype=np.float64)
+    Q = len(s_nodes)
+    out = torch.empty((problem.N, problem.n), dtype=torch.float64, device=dev)  # column-major n x N
+    ws = _workspace(workspace_bytes(problem, Q, opts), dev)
+    sc, keep = _stats(Q * problem.N, dev)
+    yp = 0
+    if y is not None:
+        yt = torch.as_tensor(np.asarray(y, dtype=np.float64)).to(dev)
+        yp = yt.data_ptr()
+    dp = C.POINTER(C.c_double)
+    code = _check(lib.infoesrf_perturbation_update(
+        C.byref(problem.c), Q, s_nodes.ctypes.data_as(dp), p_weights.ctypes.data_as(dp), C.c_void_p(yp),
+        out.data_ptr(), C.byref(opts), C.byref(sc), ws.data_ptr(), ws.numel(), _stream()))
+    torch.cuda.synchronize()
+    return out.t(), Stats(code, *(t.cpu().numpy() for t in keep))

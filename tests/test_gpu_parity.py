@@ -1,0 +1,278 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances:
+* covariance apply, FP64: 1e-13 relative (rounding order only);
+* covariance apply, FP32: 1e-6 relative (stated bound of the FP32 apply);
+* mean and perturbation updates at rtol = 1e-8: 1e-6 relative (Frobenius),
+  the FP64-mode target; PCG at rtol gives ||u - u*|| <= kappa * rtol, and the
+  correction term is a fraction of Z, so the observed error is far smaller;
+* at rtol = 1e-12: 1e-9.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import infoesrf_ref as ref
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2503_00253_amd import infoesrf as ie  # noqa: E402
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def stencil_problem(nz, nx, pz, px, ch, cv, N, stride, seed, r=0.3):
+    rng = np.random.default_rng(seed)
+    n = nz * nx
+    X = rng.standard_normal((n, N)) + 0.5 * np.sin(np.arange(n) / 7.0)[:, None]
+    if nz == 1:
+        bx, table = syn.gc_table_1d(ch)
+        bz = 0
+    else:
+        bz, bx, table = syn.gc_table_2d(ch, cv)
+    idx = np.array([z * nx + x for z in range(nz) for x in range(0, nx, stride)], dtype=np.int32)
+    m = idx.size
+    h_ptr = np.arange(m + 1, dtype=np.int32)
+    h_w = 1.0 + 0.25 * np.cos(np.arange(m))
+    r_var = r * (1.0 + 0.5 * rng.random(m))
+    y = rng.standard_normal(m)
+    return syn.Problem(n=n, N=N, m=m, X=np.asfortranarray(X), h_ptr=h_ptr, h_idx=idx, h_w=h_w, r_var=r_var, y=y,
+                       nz=nz, nx=nx, periodic_z=pz, periodic_x=px, bz=bz, bx=bx, table=table,
+                       truth=np.zeros(n), Q=8, ell=100.0, name=f"stencil-{nz}x{nx}")
+
+
+CASES = {
+    "gauss-n256-periodic": lambda: syn.config1(),
+    "ragged-1d-nonperiodic": lambda: stencil_problem(1, 203, 0, 0, 6.5, 1.0, 7, 3, 11),
+    "small-nx-periodic": lambda: stencil_problem(1, 40, 0, 1, 3.0, 1.0, 5, 2, 12),
+    "2d-layers": lambda: stencil_problem(4, 50, 0, 1, 3.0, 1.0, 6, 2, 13),
+    "2d-periodic-z": lambda: stencil_problem(6, 37, 1, 1, 2.5, 1.0, 5, 1, 14),
+}
+
+
+def dense_of(prob):
+    return ref.DenseProblem.from_problem(prob)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("B", [1, 17, 40])
+def test_cov_apply_fp64_matches_dense(case, B):
+    prob = CASES[case]()
+    say("cov_apply fp64", case, "B", B)
+    dp = dense_of(prob)
+    V = np.random.default_rng(B).standard_normal((prob.n, B))
+    want = dp.P @ V
+    P = ie.Problem.from_synthetic(prob)
+    for rows in (16, 64, 128):
+        got = ie.cov_apply(P, torch.from_numpy(V).cuda(), ie.default_opts(tile_rows=rows)).cpu().numpy()
+        assert rel(got, want) < 1e-13, (case, B, rows)
+        assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_cov_apply_fp32_stated_bound(case):
+    prob = CASES[case]()
+    say("cov_apply fp32", case)
+    dp = dense_of(prob)
+    V = np.random.default_rng(3).standard_normal((prob.n, 20))
+    want = dp.P @ V
+    P = ie.Problem.from_synthetic(prob)
+    got = ie.cov_apply(P, torch.from_numpy(V).cuda(), ie.default_opts(precision=ie.MIXED_FP32)).cpu().numpy()
+    assert rel(got, want) < 1e-6
+
+
+def test_cov_apply_dense_localization():
+    prob = CASES["ragged-1d-nonperiodic"]()
+    say("cov_apply dense L")
+    dp = dense_of(prob)
+    V = np.random.default_rng(5).standard_normal((prob.n, 9))
+    P = ie.Problem(prob.X, prob.h_ptr, prob.h_idx, prob.h_w, prob.r_var, dense=dp.L)
+    got = ie.cov_apply(P, torch.from_numpy(V).cuda()).cpu().numpy()
+    assert rel(got, dp.P @ V) < 1e-13
+
+
+def opts_for(prob, P, domain, **kw):
+    if domain == "lattice":
+        lat = P.lattice()
+        assert lat is not None
+        return ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=lat, **kw)
+    return ie.default_opts(**kw)
+
+
+@pytest.mark.parametrize("domain", ["state", "lattice"])
+@pytest.mark.parametrize("case", ["gauss-n256-periodic", "ragged-1d-nonperiodic", "2d-layers"])
+def test_mean_update_matches_oracle(case, domain):
+    prob = CASES[case]()
+    say("mean_update", case, domain)
+    dp = dense_of(prob)
+    want = ref.mean_update_eig(dp, prob.y)
+    P = ie.Problem.from_synthetic(prob)
+    got, st = ie.mean_update(P, prob.y, opts_for(prob, P, domain))
+    assert st.code == ie.OK
+    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert rel(got.cpu().numpy() - dp.mu, want - dp.mu) < 1e-6
+    assert st.relres[0] <= 1e-8 and st.converged[0] == 1
+
+
+@pytest.mark.parametrize("domain", ["state", "lattice"])
+@pytest.mark.parametrize("case", ["gauss-n256-periodic", "ragged-1d-nonperiodic", "2d-layers", "2d-periodic-z"])
+def test_perturbation_update_matches_oracle(case, domain):
+    prob = CASES[case]()
+    say("perturbation_update", case, domain)
+    dp = dense_of(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    P = ie.Problem.from_synthetic(prob)
+    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain))
+    assert st.code == ie.OK
+    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert np.all(st.relres <= 1e-8) and np.all(st.converged == 1)
+    assert st.counter(ie.CNT_NOT_CONVERGED) == 0
+    assert st.counter(ie.CNT_ITERATIONS) == int(st.iters.sum())
+
+
+def test_perturbation_update_tight_tolerance():
+    prob = syn.config1()
+    say("perturbation_update rtol 1e-12")
+    dp = dense_of(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    P = ie.Problem.from_synthetic(prob)
+    got, st = ie.perturbation_update(P, s, p, ie.default_opts(rtol=1e-12))
+    assert rel(got.cpu().numpy(), want) < 1e-9
+    assert np.all(st.relres <= 1e-12)
+
+
+def test_pcg_iterations_match_oracle_pcg():
+    """Same sketch -> same preconditioner: per-system iteration counts agree with the CPU PCG (+-1)."""
+    prob = syn.config1()
+    say("iteration counts vs oracle PCG")
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    Om = syn.sketch_matrix(prob.m, 20, 77)
+    _, it_ref = ref.info_esrf_pcg(prob, s, p, rtol=0.5e-8, Omega=Om)
+    P = ie.Problem.from_synthetic(prob)
+    Omt = torch.from_numpy(np.ascontiguousarray(Om.T)).cuda()  # column-major m x k
+    _, st = ie.perturbation_update(P, s, p, ie.default_opts(sketch=Omt))
+    got = st.iters.reshape(prob.Q, prob.N)
+    assert np.max(np.abs(got - it_ref)) <= 1, (got, it_ref)
+
+
+@pytest.mark.parametrize("solver", [ie.SOLVER_PLAIN, ie.SOLVER_COMPACT])
+def test_solvers_agree_and_are_deterministic(solver):
+    prob = syn.config1()
+    say("solver", solver)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    P = ie.Problem.from_synthetic(prob)
+    a, sa = ie.perturbation_update(P, s, p, ie.default_opts(solver=solver))
+    b, sb = ie.perturbation_update(P, s, p, ie.default_opts(solver=solver))
+    assert torch.equal(a, b)
+    assert np.array_equal(sa.iters, sb.iters)
+    c, _ = ie.perturbation_update(P, s, p, ie.default_opts(solver=ie.SOLVER_COMPACT))
+    assert rel(a.cpu().numpy(), c.cpu().numpy()) < 1e-12
+
+
+@pytest.mark.parametrize("domain", ["state", "lattice"])
+def test_mixed_fp32_meets_fp64_bound(domain):
+    prob = syn.config1()
+    say("mixed fp32", domain)
+    dp = dense_of(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    P = ie.Problem.from_synthetic(prob)
+    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, precision=ie.MIXED_FP32))
+    assert st.code == ie.OK
+    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert np.all(st.relres <= 1e-8)
+    assert st.counter(ie.CNT_SWEEPS) >= prob.Q * prob.N  # every system had at least one FP64 check
+
+
+def test_not_converged_is_reported():
+    prob = syn.config1()
+    say("max_iter=2 -> warning")
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    P = ie.Problem.from_synthetic(prob)
+    _, st = ie.perturbation_update(P, s, p, ie.default_opts(max_iter=2))
+    assert st.code == ie.WARN_NOT_CONVERGED
+    assert st.counter(ie.CNT_NOT_CONVERGED) > 0
+    assert np.any(st.converged == 0)
+    assert np.all(st.iters <= 2 + 1)
+
+
+def test_nan_input_is_an_error():
+    prob = syn.config1()
+    say("NaN in X")
+    X = prob.X.copy()
+    X[5, 3] = np.nan
+    P = ie.Problem(X, prob.h_ptr, prob.h_idx, prob.h_w, prob.r_var, nx=prob.nx, bx=prob.bx, table=prob.table)
+    s, p, _ = ref.quadrature_elliptic(4, 100.0)
+    with pytest.raises(ie.InfoEsrfError) as e:
+        ie.perturbation_update(P, s, p)
+    assert e.value.code == ie.ERR_NUMERIC
+
+
+def test_bad_observation_operator_is_an_error():
+    prob = syn.config1()
+    s, p, _ = ref.quadrature_elliptic(4, 100.0)
+    say("out-of-range CSR index")
+    idx = prob.h_idx.copy()
+    idx[3] = prob.n + 5
+    P = ie.Problem(prob.X, prob.h_ptr, idx, prob.h_w, prob.r_var, nx=prob.nx, bx=prob.bx, table=prob.table)
+    with pytest.raises(ie.InfoEsrfError) as e:
+        ie.perturbation_update(P, s, p)
+    assert e.value.code == ie.ERR_INVALID_ARG
+    say("r_var <= 0")
+    rv = prob.r_var.copy()
+    rv[0] = 0.0
+    P = ie.Problem(prob.X, prob.h_ptr, prob.h_idx, prob.h_w, rv, nx=prob.nx, bx=prob.bx, table=prob.table)
+    with pytest.raises(ie.InfoEsrfError) as e:
+        ie.perturbation_update(P, s, p)
+    assert e.value.code == ie.ERR_INVALID_ARG
+    say("wrong lattice claim")
+    P = ie.Problem.from_synthetic(prob)
+    with pytest.raises(ie.InfoEsrfError) as e:
+        ie.perturbation_update(P, s, p, ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE,
+                                                        lattice=(0, 1, 1, 1, 4, 64)))
+    assert e.value.code == ie.ERR_INVALID_ARG
+
+
+def test_indefinite_localization_is_not_spd():
+    """A localization far from PSD makes p^T C p <= 0 at some iteration."""
+    prob = syn.config1()
+    say("indefinite L -> NOT_SPD")
+    n = prob.n
+    L = np.zeros((n, n))
+    L[np.arange(n), np.arange(n)] = 1.0
+    L[np.arange(n), (np.arange(n) + 4) % n] = -40.0
+    L[(np.arange(n) + 4) % n, np.arange(n)] = -40.0
+    P = ie.Problem(prob.X, prob.h_ptr, prob.h_idx, prob.h_w, prob.r_var, dense=L)
+    s, p, _ = ref.quadrature_elliptic(4, 100.0)
+    with pytest.raises(ie.InfoEsrfError) as e:
+        ie.perturbation_update(P, s, p, ie.default_opts(n_ritz=0))
+    assert e.value.code in (ie.ERR_NOT_SPD, ie.ERR_NUMERIC)
+
+
+@pytest.mark.parametrize("domain", ["lattice", "state"])
+def test_full_size_gaussian_n4096(domain):
+    """n=4096, N=40, m=1024, Q=16 (640 systems) against the eigendecomposition oracle."""
+    prob = syn.config2()
+    say("full size n4096", domain)
+    dp = dense_of(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    P = ie.Problem.from_synthetic(prob)
+    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain))
+    assert st.code == ie.OK
+    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert np.all(st.relres <= 1e-8)
+    mean_want = ref.mean_update_eig(dp, prob.y)
+    mean_got, sm = ie.mean_update(P, prob.y, opts_for(prob, P, domain))
+    assert rel(mean_got.cpu().numpy() - dp.mu, mean_want - dp.mu) < 1e-6
