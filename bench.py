@@ -1,0 +1,170 @@
+#!/usr/bin/env python
+"""Benchmark of the InFo-ESRF perturbation update on one MI355X.
+
+One step = one call of infoesrf_perturbation_update on the n=4096 Gaussian
+workload (N=40 members, m=1024 point observations, Q=16 elliptic nodes: 640
+shifted SPD systems solved to a true FP64 relative residual of 1e-8),
+including ensemble statistics, preconditioner setup, all PCG solves, the
+quadrature combine and the final state-space apply.  Inputs are resident in
+HBM before the timed region.
+
+Printed: one JSON line with the solve rate, the roofline position of the
+dominant kernel (the covariance apply, timed live with HIP events on its
+stream), the rate of plain GPU PCG (FP64, state-space applies, masked
+systems, no compaction) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0}   # MI355X dense matrix peaks: FP64, FP32, BF16
+PREC_NAME = {0: "fp64", 1: "fp32", 2: "bf16"}
+DTYPE = {0: "f64", 1: "f32/f64", 2: "bf16/f64"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp32")
+    ap.add_argument("--domain", choices=["state", "lattice"], default="lattice")
+    ap.add_argument("--solver", choices=["plain", "compact"], default="compact")
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-members", type=int, default=1)
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def traffic_record(src_path):
+    """HBM traffic per launch from a committed rocprofv3 counter summary, if the kernel is unchanged."""
+    path = os.path.join(ROOT, "profiles", "cov_apply_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(src_path, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synthetic as syn
+    from paper_2503_00253_amd import infoesrf as ie
+
+    prec = {"fp64": ie.FP64, "fp32": ie.MIXED_FP32, "bf16": ie.MIXED_BF16}[a.precision]
+    prob = syn.config2()
+    log("workload", prob.name, "precision", a.precision, "domain", a.domain, "solver", a.solver)
+    P = ie.Problem.from_synthetic(prob)
+    s, p = ie.quadrature_elliptic(prob.Q, prob.ell)
+    kw = dict(precision=prec, solver=ie.SOLVER_PLAIN if a.solver == "plain" else ie.SOLVER_COMPACT)
+    if a.domain == "lattice":
+        kw.update(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=P.lattice())
+    opts = ie.default_opts(**kw)
+    run = ie.PerturbationRunner(P, s, p, opts)
+    systems = prob.Q * prob.N
+
+    for w in range(a.warmup):
+        code = run.run()
+        torch.cuda.synchronize()
+        log("warmup", w, "code", code)
+    st = run.stats(code)
+    log("iterations: total", int(st.iters.sum()), "max", int(st.iters.max()), "mean", float(st.iters.mean()),
+        "sweeps", st.counter(ie.CNT_SWEEPS), "not converged", st.counter(ie.CNT_NOT_CONVERGED))
+
+    ie.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        code = run.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, launches, vectors, flops = ie.profile_read()
+    ie.profile_enable(False)
+    st = run.stats(code)
+    assert st.counter(ie.CNT_NOT_CONVERGED) == 0, "systems missed rtol"
+    ms_step = (t1 - t0) * 1e3 / a.steps
+    value = systems * a.steps / (t1 - t0)
+    log(f"{value:.1f} solves/s, {ms_step:.3f} ms/step")
+
+    dom = max(range(3), key=lambda i: ms[i])
+    achieved = flops[dom] / (ms[dom] * 1e-3) / 1e12 if ms[dom] > 0 else 0.0
+    avg_ms = ms[dom] / max(launches[dom], 1)
+    src = os.path.join(ROOT, "paper_2503_00253_amd", "csrc", "cov_apply.hip")
+    tr = traffic_record(src)
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dom], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS[dom], 4),
+            "traffic": (tr or {}).get("bytes_per_launch"),
+            "kernel": f"k_cov_stencil<{PREC_NAME[dom]}>", "launches": launches[dom],
+            "avg_launch_ms": round(avg_ms, 4), "vectors": vectors[dom],
+            "flops_per_launch": flops[dom] / max(launches[dom], 1),
+            "flops_per_vector": flops[dom] / max(vectors[dom], 1)}
+    log("roofline", roof)
+
+    out = {"metric": "shifted SPD solves/s at rel-res 1e-8", "value": round(value, 2), "unit": "solves/s",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec],
+           "data": "synthetic",
+           "config": {"workload": prob.name, "n": prob.n, "N": prob.N, "m": prob.m, "Q": prob.Q,
+                      "systems_per_step": systems, "rtol": 1e-8, "precision": a.precision,
+                      "apply_domain": a.domain, "solver": a.solver, "n_ritz": 10},
+           "iterations": {"total": int(st.iters.sum()), "max": int(st.iters.max()),
+                          "fp64_sweeps": st.counter(ie.CNT_SWEEPS)},
+           "roofline": roof}
+
+    if not a.no_plain:
+        popts = ie.default_opts(precision=ie.FP64, solver=ie.SOLVER_PLAIN)
+        prun = ie.PerturbationRunner(P, s, p, popts)
+        prun.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.plain_steps):
+            prun.run()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pv = systems * a.plain_steps / (t1 - t0)
+        diff = float((run.result() - prun.result()).norm() / prun.result().norm())
+        out["plain_gpu_pcg"] = {"value": round(pv, 2), "unit": "solves/s", "steps": a.plain_steps,
+                                "speedup": round(value / pv, 3), "rel_diff_vs_plain": diff}
+        log("plain GPU PCG", pv, "speedup", value / pv, "diff", diff)
+
+    if not a.no_cpu_baseline:
+        from oracle import infoesrf_ref as ref
+        members = list(range(a.cpu_members))
+        s0, p0, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+        Om = syn.sketch_matrix(prob.m, 20, 1)
+        t0 = time.perf_counter()
+        _, it = ref.info_esrf_pcg(prob, s0, p0, rtol=1e-8, Omega=Om, members=members)
+        t1 = time.perf_counter()
+        nsys = len(members) * prob.Q
+        out["cpu_baseline"] = {"value": round(nsys / (t1 - t0), 4), "unit": "solves/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{nsys} systems ({len(members)} member x {prob.Q} nodes) of the same "
+                                         f"workload incl. preconditioner setup, matrix-free FP64 PCG, "
+                                         f"{int(it.sum())} iterations, {t1 - t0:.1f} s; SciPy sparse apply "
+                                         f"(single-threaded)"}
+        log("cpu baseline", out["cpu_baseline"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

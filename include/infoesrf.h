@@ -153,7 +153,8 @@ typedef struct infoesrf_opts {
   uint64_t seed;        /* seed of the library's own sketch generator when sketch == NULL */
   const double* sketch; /* device m x (n_ritz+oversample) Gaussian test matrix, or NULL */
   const void* net;      /* warm-start network from infoesrf_net_load (LEARNED only) */
-  int32_t tile_rows;    /* 0 = autotuned/default; else rows per covariance tile (multiple of 16) */
+  int32_t tile_rows;    /* covariance-apply tile variant: 0 = default; 16, 32, 64, 128 select blocks of
+                           16x32, 32x32, 64x16, 64x32 (rows x systems) */
   int32_t reserved[7];
 } infoesrf_opts;
 

@@ -289,7 +289,7 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   op.inner_rtol = o->inner_rtol > 0.0 ? o->inner_rtol : (op.inner == Prec::F32 ? 1e-5 : 1e-2);
   op.solver = o->solver;
   op.host_sync = o->host_sync;
-  op.rows_per_wave = o->tile_rows ? o->tile_rows : 64;
+  op.rows_per_wave = o->tile_rows;  // 0: chosen per launch from the batch size
   op.obs = (o->apply_domain == INFOESRF_DOMAIN_OBS_LATTICE);
   op.lat = o->lattice;
   op.seed = o->seed;
@@ -423,6 +423,13 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
 }
 
 // ------------------------------------------------------------------ apply
+// Tile variant of a covariance launch: the caller's choice, else a rule from the
+// measured sweep on MI355X (large batches: 32 rows x 32 systems per block; small
+// batches: 16 x 32, which doubles the number of blocks).
+int tile_for(int requested, int64_t B) {
+  if (requested) return requested;
+  return B >= 128 ? 32 : 16;
+}
 // Qout[:, act] = (1 + sigma) Pin[:, act] + S Pin[:, act] with S in precision `prec`;
 // partial dots of Pin^T Qout into part.
 int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* act, const int32_t* nact,
@@ -432,8 +439,8 @@ int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* 
   if (in.obs) {
     IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, Bpad, st));
     const void* Zu = (prec == Prec::F64) ? (const void*)in.Zt : (const void*)in.Zt32;
-    IE_HIP(cov_stencil_timed(prec, in.go, Zu, in.m, in.N, pl.bf.V, Bpad, Bpad, nact, pl.bf.T, Bpad, rows_per_wave,
-                              st));
+    IE_HIP(cov_stencil_timed(prec, in.go, Zu, in.m, in.N, pl.bf.V, Bpad, Bpad, nact, pl.bf.T, Bpad,
+                             tile_for(rows_per_wave, Bmax), st));
   } else {
     IE_HIP(launch_scatter_state(prec, Pin, ldp, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n, in.m,
                                 Bpad, pl.bf.V, Bpad, st));
@@ -444,7 +451,7 @@ int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* 
     } else {
       const void* Zu = (prec == Prec::F64) ? (const void*)in.Z : (const void*)in.Z32;
       IE_HIP(cov_stencil_timed(prec, in.gs, Zu, in.n, in.N, pl.bf.V, Bpad, Bpad, nact, pl.bf.T, Bpad,
-                                rows_per_wave, st));
+                               tile_for(rows_per_wave, Bmax), st));
     }
   }
   IE_HIP(launch_apply_finish(prec, in.obs ? 1 : 0, Pin, ldp, pl.bf.T, Bpad, act, nact, sigma, in.P->h_ptr,
@@ -465,7 +472,7 @@ int apply_state(Plan& pl, const double* U, int64_t ld, const int32_t* act, const
                             (double*)pl.bf.T, Bpad, st));
   } else {
     IE_HIP(cov_stencil_timed(Prec::F64, in.gs, in.Z, in.n, in.N, pl.bf.V, Bpad, ncols, nullptr, pl.bf.T, Bpad,
-                              rows_per_wave, st));
+                             tile_for(rows_per_wave, ncols), st));
   }
   return 0;
 }
@@ -855,12 +862,13 @@ int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ld
       float* V32 = reinterpret_cast<float*>(Ts);  // stage the FP32 input in the output buffer's storage
       IE_HIP(launch_convert_f32(Vs, V32, n * ldb, st));
       float* T32 = reinterpret_cast<float*>(Vs);
-      IE_HIP(cov_stencil_timed(Prec::F32, g, Z32, n, N, V32, ldb, B, nullptr, T32, ldb, op.rows_per_wave, st));
+      IE_HIP(cov_stencil_timed(Prec::F32, g, Z32, n, N, V32, ldb, B, nullptr, T32, ldb, tile_for(op.rows_per_wave, B),
+                               st));
       // widen T32 (in Vs storage) into Ts
       hipLaunchKernelGGL(k_widen, dim3(nb(n * ldb)), dim3(256), 0, st, (const float*)T32, Ts, n * ldb);
       IE_HIP(hipGetLastError());
     } else {
-      IE_HIP(cov_stencil_timed(Prec::F64, g, Z, n, N, Vs, ldb, B, nullptr, Ts, ldb, op.rows_per_wave, st));
+      IE_HIP(cov_stencil_timed(Prec::F64, g, Z, n, N, Vs, ldb, B, nullptr, Ts, ldb, tile_for(op.rows_per_wave, B), st));
     }
   }
   IE_HIP(launch_from_sysfast(Ts, ldb, n, B, PV, ldpv, st));

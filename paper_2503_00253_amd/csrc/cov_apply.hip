@@ -71,128 +71,206 @@ __device__ inline int wrap_mod(int a, int n) {
   return r < 0 ? r + n : r;
 }
 
-template <typename T, int RB>
+// LDS row padding of the staged V window (64 bytes) so the four K rows a
+// wavefront reads in one step fall on different banks.
+template <typename T>
+constexpr int vpad() { return 64 / (int)sizeof(T); }
+
+// Block tile: TM = 16 RB output rows of one layer, NS = 16 SB systems.  The
+// four wavefronts of a block split the members (wave w takes members
+// j = w, w+4, ...) and each accumulates the whole TM x NS tile; a final
+// cross-wave reduction in LDS sums the four partial tiles.  V and Z are staged
+// in LDS one K-chunk (KC rows of the K-window) and one member chunk (MC
+// members) at a time, so the LDS footprint does not grow with the stencil.
+template <typename T, int RB, int SB>
 __global__ __launch_bounds__(256) void k_cov_stencil(Grid g, const T* __restrict__ Z, int64_t ldz, int N,
                                                      const T* __restrict__ V, int64_t ldv, int B,
                                                      const int32_t* __restrict__ Bdev, T* __restrict__ Tout,
-                                                     int64_t ldt, int tiles_per_layer, int ntiles,
+                                                     int64_t ldt, int tiles_per_layer, int KC, int MC,
                                                      ProfDev prof) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int TM = 16 * RB;
+  constexpr int NS = 16 * SB;
+  constexpr int VS = NS + vpad<T>();
   if (Bdev) B = *Bdev;  // active-system count produced on the device
   if (prof.vectors && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
     atomicAdd(prof.vectors, (unsigned long long)B);
     atomicAdd(prof.flops, (double)B * prof.flops_per_vector);
   }
-  if ((int)blockIdx.y * 16 >= B) return;
-  typedef typename Mfma<T>::acc_t acc_t;
-  constexpr int TM = 16 * RB;
-  extern __shared__ unsigned char smem_raw[];
-  T* tab = reinterpret_cast<T*>(smem_raw);
+  const int b0 = blockIdx.y * NS;
+  if (b0 >= B) return;
 
+  extern __shared__ unsigned char smem_raw[];
   const int bx = g.bx, bz = g.bz;
-  const int tw = 2 * bx + 1 + 2 * kPad;  // padded table row width
+  const int tw = 2 * bx + 1 + 2 * kPad;
+  T* tab = reinterpret_cast<T*>(smem_raw);
+  T* Vw = tab + (2 * bz + 1) * tw;  // KC x VS
+  T* Zw = Vw + KC * VS;             // MC x KC
+  T* Zr = Zw + MC * KC;             // MC x TM
+
   const T* gtab = table_ptr<T>(g);
   for (int t = threadIdx.x; t < (2 * bz + 1) * tw; t += blockDim.x) {
     const int row = t / tw, c = t % tw - kPad;
     tab[t] = (c >= 0 && c <= 2 * bx) ? gtab[row * (2 * bx + 1) + c] : T(0);
   }
-  __syncthreads();
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int tile = blockIdx.x * 4 + wave;
-  if (tile >= ntiles) return;
+  const int tile = blockIdx.x;
   const int z = tile / tiles_per_layer;
   const int x0 = (tile % tiles_per_layer) * TM;
   const int nx = g.nx, nz = g.nz;
-  const int b = blockIdx.y * 16 + (lane & 15);  // this lane's B column (< padded B)
-  const int lrow = lane & 15;                   // A operand row within a row block
-  const int lk = lane >> 4;                     // operand k within a K step
-
-  acc_t acc[RB];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb) acc[rb] = acc_t{0, 0, 0, 0};
-
+  const int lrow = lane & 15;
+  const int lk = lane >> 4;
   const int KW = TM + 2 * bx;
-  const int nK = (KW + 3) / 4;
 
-  for (int dz = -bz; dz <= bz; ++dz) {
-    int zz = z + dz;
-    if (g.pz) {
-      zz = wrap_mod(zz, nz);
-    } else if (zz < 0 || zz >= nz) {
-      continue;
+  acc_t acc[RB][SB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) acc[rb][sb] = acc_t{0, 0, 0, 0};
+
+  for (int m0 = 0; m0 < N; m0 += MC) {
+    const int mcn = min(MC, N - m0);
+    __syncthreads();
+    // output-row scales z_i[r] of this member chunk (layer z)
+    for (int t = threadIdx.x; t < MC * TM; t += blockDim.x) {
+      const int j = t / TM, r = t % TM;
+      const int xr = x0 + r;
+      Zr[t] = (j < mcn && xr < nx) ? Z[(int64_t)(m0 + j) * ldz + (int64_t)z * nx + xr] : T(0);
     }
-    const T* trow = tab + (dz + bz) * tw + kPad;
-    const int64_t lay = (int64_t)zz * nx;
-    for (int i = 0; i < N; ++i) {
-      const T* zc = Z + (int64_t)i * ldz;
-      T zr[RB];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int xr = x0 + 16 * rb + lrow;
-        zr[rb] = (xr < nx) ? zc[(int64_t)z * nx + xr] : T(0);
+    for (int dz = -bz; dz <= bz; ++dz) {
+      int zz = z + dz;
+      if (g.pz) {
+        zz = wrap_mod(zz, nz);
+      } else if (zz < 0 || zz >= nz) {
+        continue;
       }
-      // one-step software prefetch of the B operand
-      auto load_b = [&](int kk) -> T {
-        const int kl = 4 * kk + lk;
-        int kx = x0 - bx + kl;
-        if (g.px) {
-          kx = wrap_mod(kx, nx);
-        } else if (kx < 0 || kx >= nx) {
-          return T(0);
+      const T* trow = tab + (dz + bz) * tw + kPad;
+      const int64_t lay = (int64_t)zz * nx;
+      for (int k0 = 0; k0 < KW; k0 += KC) {
+        __syncthreads();
+        // stage V rows k0..k0+KC of the K-window (systems b0..b0+NS) and the matching Z rows
+        for (int t = threadIdx.x; t < KC * NS; t += blockDim.x) {
+          const int kl = t / NS, c = t % NS;
+          const int kw = k0 + kl;
+          int kx = x0 - bx + kw;
+          bool ok = kw < KW && b0 + c < ldv;  // columns past the buffer width are not read
+          if (g.px) kx = wrap_mod(kx, nx);
+          else ok = ok && kx >= 0 && kx < nx;
+          Vw[kl * VS + c] = ok ? V[(lay + kx) * ldv + b0 + c] : T(0);
         }
-        if (kl >= KW) return T(0);
-        const int64_t kidx = lay + kx;
-        return zc[kidx] * V[kidx * ldv + b];
-      };
-      T bnext = load_b(0);
-      for (int kk = 0; kk < nK; ++kk) {
-        const T bval = bnext;
-        if (kk + 1 < nK) bnext = load_b(kk + 1);
+        for (int t = threadIdx.x; t < MC * KC; t += blockDim.x) {
+          const int j = t / KC, kl = t % KC;
+          const int kw = k0 + kl;
+          int kx = x0 - bx + kw;
+          bool ok = kw < KW && j < mcn;
+          if (g.px) kx = wrap_mod(kx, nx);
+          else ok = ok && kx >= 0 && kx < nx;
+          Zw[t] = ok ? Z[(int64_t)(m0 + j) * ldz + lay + kx] : T(0);
+        }
+        __syncthreads();
+        const int kk0 = k0 >> 2;
+        const int nkk = KC >> 2;
+        for (int j = wave; j < mcn; j += 4) {
+          T zr[RB];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const int base = 4 * kk - 16 * rb;
-          if (base + 3 >= 0 && base - 15 <= 2 * bx) {
-            const T a = zr[rb] * trow[base + lk - lrow];
-            acc[rb] = Mfma<T>::step(a, bval, acc[rb]);
+          for (int rb = 0; rb < RB; ++rb) zr[rb] = Zr[j * TM + 16 * rb + lrow];
+          const T* zk_row = Zw + j * KC;
+          for (int kl4 = 0; kl4 < nkk; ++kl4) {
+            const int kl = 4 * kl4 + lk;
+            const T zk = zk_row[kl];
+            T bv[SB];
+#pragma unroll
+            for (int sb = 0; sb < SB; ++sb) bv[sb] = zk * Vw[kl * VS + 16 * sb + lrow];
+            const int kk = kk0 + kl4;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+              const int base = 4 * kk - 16 * rb;
+              if (base + 3 >= 0 && base - 15 <= 2 * bx) {
+                const T a = zr[rb] * trow[base + lk - lrow];
+#pragma unroll
+                for (int sb = 0; sb < SB; ++sb) acc[rb][sb] = Mfma<T>::step(a, bv[sb], acc[rb][sb]);
+              }
+            }
           }
         }
       }
     }
   }
 
-  if (b >= B) return;
+  // cross-wave reduction of the four partial tiles
+  __syncthreads();
+  T* red = Vw;  // reuse: needs 4 * 64 * RB * SB * 4 values (checked by the launcher)
+  constexpr int PER = RB * SB * 4;
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) {
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[((wave * PER) + (rb * SB + sb) * 4 + v) * 64 + lane] = acc[rb][sb][v];
+  __syncthreads();
+  // each wave writes a quarter of the tile's fragments
+  for (int f = wave; f < RB * SB; f += 4) {
+    const int rb = f / SB, sb = f % SB;
+    const int b = b0 + 16 * sb + (lane & 15);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
+      T s = T(0);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) s += red[((w * PER) + f * 4 + v) * 64 + lane];
       const int x = x0 + 16 * rb + Mfma<T>::out_row(lane, v);
-      if (x < nx) Tout[((int64_t)z * nx + x) * ldt + b] = acc[rb][v];
+      if (x < nx && b < B) Tout[((int64_t)z * nx + x) * ldt + b] = s;
     }
   }
 }
 
-template <typename T, int RB>
+template <typename T, int RB, int SB>
+size_t smem_bytes(const Grid& g, int KC, int MC) {
+  constexpr int TM = 16 * RB, NS = 16 * SB, VS = NS + vpad<T>();
+  const size_t stage = (size_t)KC * VS + (size_t)MC * KC + (size_t)MC * TM;
+  const size_t red = (size_t)4 * 64 * RB * SB * 4;
+  return sizeof(T) * ((size_t)(2 * g.bz + 1) * (2 * g.bx + 1 + 2 * kPad) + (stage > red ? stage : red));
+}
+
+template <typename T, int RB, int SB>
 hipError_t launch_typed(const Grid& g, const T* Z, int64_t ldz, int64_t N, const T* V, int64_t ldv, int64_t B,
                         const int32_t* Bdev, T* Tout, int64_t ldt, hipStream_t st, const ProfDev& prof) {
-  constexpr int TM = 16 * RB;
+  constexpr int TM = 16 * RB, NS = 16 * SB;
   const int tiles_per_layer = (g.nx + TM - 1) / TM;
   const int ntiles = tiles_per_layer * g.nz;
-  const size_t smem = sizeof(T) * (size_t)(2 * g.bz + 1) * (2 * g.bx + 1 + 2 * kPad);
-  dim3 grid((ntiles + 3) / 4, (unsigned)((B + 15) / 16));
-  hipLaunchKernelGGL((k_cov_stencil<T, RB>), grid, dim3(256), smem, st, g, Z, ldz, (int)N, V, ldv, (int)B, Bdev,
-                     Tout, ldt, tiles_per_layer, ntiles, prof);
+  const int KW = TM + 2 * g.bx;
+  // K-chunks: the window split into equal chunks of at most 128 rows (multiples of 4)
+  const int nch = (KW + 127) / 128;
+  int KC = ((KW + nch - 1) / nch + 3) / 4 * 4;
+  int MC = ((int)N + 3) / 4 * 4;
+  const size_t budget = 72 * 1024;
+  while (MC > 4 && smem_bytes<T, RB, SB>(g, KC, MC) > budget) MC -= 4;
+  while (KC > 16 && smem_bytes<T, RB, SB>(g, KC, MC) > budget) KC -= 16;
+  const size_t smem = smem_bytes<T, RB, SB>(g, KC, MC);
+  if (smem > 150 * 1024) return hipErrorInvalidValue;
+  static bool attr_set = false;  // once per instantiation: allow more than 64 KiB of dynamic LDS
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cov_stencil<T, RB, SB>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  dim3 grid(ntiles, (unsigned)((B + NS - 1) / NS));
+  hipLaunchKernelGGL((k_cov_stencil<T, RB, SB>), grid, dim3(256), smem, st, g, Z, ldz, (int)N, V, ldv, (int)B, Bdev,
+                     Tout, ldt, tiles_per_layer, KC, MC, prof);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_rb(int rows_per_wave, const Grid& g, const T* Z, int64_t ldz, int64_t N, const T* V, int64_t ldv,
                      int64_t B, const int32_t* Bdev, T* Tout, int64_t ldt, hipStream_t st, const ProfDev& pf) {
+  // rows_per_wave selects the tile: 16 -> 16 rows x 32 systems, 32 -> 32 x 32, 64 -> 64 x 16
   switch (rows_per_wave) {
-    case 16: return launch_typed<T, 1>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
-    case 32: return launch_typed<T, 2>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
-    case 64: return launch_typed<T, 4>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
-    case 128: return launch_typed<T, 8>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
+    case 16: return launch_typed<T, 1, 2>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
+    case 32: return launch_typed<T, 2, 2>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
+    case 64: return launch_typed<T, 4, 1>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
+    case 128: return launch_typed<T, 4, 2>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
     default: return hipErrorInvalidValue;
   }
 }

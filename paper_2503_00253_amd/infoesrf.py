@@ -316,3 +316,53 @@ def perturbation_update(problem: Problem, s_nodes, p_weights, opts: Opts | None 
         out.data_ptr(), C.byref(opts), C.byref(sc), ws.data_ptr(), ws.numel(), _stream()))
     torch.cuda.synchronize()
     return out.t(), Stats(code, *(t.cpu().numpy() for t in keep))
+
+
+class PerturbationRunner:
+    """Preallocated perturbation update: run() only enqueues the C call (no allocation)."""
+
+    def __init__(self, problem: Problem, s_nodes, p_weights, opts: Opts):
+        torch = _torch()
+        self.lib = library()
+        self.problem = problem
+        self.opts = opts
+        self.s = np.ascontiguousarray(s_nodes, dtype=np.float64)
+        self.p = np.ascontiguousarray(p_weights, dtype=np.float64)
+        self.Q = len(self.s)
+        dev = problem.X.device
+        self.out = torch.empty((problem.N, problem.n), dtype=torch.float64, device=dev)
+        nbytes = workspace_bytes(problem, self.Q, opts)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.sc, self.keep = _stats(self.Q * problem.N, dev)
+        dp = C.POINTER(C.c_double)
+        self._sp = self.s.ctypes.data_as(dp)
+        self._pp = self.p.ctypes.data_as(dp)
+
+    def run(self):
+        return _check(self.lib.infoesrf_perturbation_update(
+            C.byref(self.problem.c), self.Q, self._sp, self._pp, None, self.out.data_ptr(), C.byref(self.opts),
+            C.byref(self.sc), self.ws.data_ptr(), self.ws.numel(), _stream()))
+
+    def result(self):
+        return self.out.t()
+
+    def stats(self, code=0):
+        return Stats(code, *(t.cpu().numpy() for t in self.keep))
+
+
+def profile_enable(on: bool):
+    lib = library()
+    lib.infoesrf_profile_enable.argtypes = [C.c_int]
+    lib.infoesrf_profile_enable.restype = C.c_int
+    _check(lib.infoesrf_profile_enable(1 if on else 0), allow_warn=False)
+
+
+def profile_read():
+    """Per precision (FP64, FP32, BF16): kernel ms, launches, vectors, FLOPs of the covariance apply."""
+    lib = library()
+    D3, I3 = C.c_double * 3, C.c_int64 * 3
+    lib.infoesrf_profile_read.argtypes = [D3, I3, I3, D3]
+    lib.infoesrf_profile_read.restype = C.c_int
+    ms, la, ve, fl = D3(), I3(), I3(), D3()
+    _check(lib.infoesrf_profile_read(ms, la, ve, fl), allow_warn=False)
+    return list(ms), list(la), list(ve), list(fl)
