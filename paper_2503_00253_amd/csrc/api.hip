@@ -198,8 +198,8 @@ struct Inst {
 struct Sys {
   int64_t S = 0, ld = 0, Bpad = 0;
   double *b, *u, *x, *r, *p, *q, *bnorm, *rn, *rz0, *rz1, *relres, *rel_in, *sigma, *thresh, *pw;
-  int32_t *iters, *sweeps, *done, *fdone, *act, *nact;
-  double *part_pq, *part2;
+  int32_t *iters, *sweeps, *done, *fdone, *act, *nact, *act2, *nact2, *tile_cnt, *glob_cnt;
+  double *part_pq, *part2, *alpha, *coef;
 };
 
 struct Pre {
@@ -381,9 +381,17 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   sy.fdone = ar.take<int32_t>(sy.ld);
   sy.act = ar.take<int32_t>(sy.ld);
   sy.nact = ar.take<int32_t>(1);
+  sy.act2 = ar.take<int32_t>(sy.ld);
+  sy.nact2 = ar.take<int32_t>(1);
+  sy.tile_cnt = ar.take<int32_t>(round_up(std::max<int64_t>(sy.ld, op.k + 16), 16) / 16 + 16);
+  sy.glob_cnt = ar.take<int32_t>(1);
+  sy.alpha = ar.take<double>(sy.ld);
+  sy.coef = ar.take<double>(sy.ld * (2 * op.p + 1));
   const int64_t nchunks = (in.m + kChunk - 1) / kChunk;
   sy.part_pq = ar.take<double>(nchunks * round_up(std::max<int64_t>(sy.ld, op.k + 16), 64));
-  sy.part2 = ar.take<double>(nchunks * round_up(sy.ld, 64) * (2 * op.p + 1));
+  // PCG partial dots (nchunks x ld x (2p+1)) and the column-norm partials (ceil(m/64) x ld) share this buffer
+  sy.part2 = ar.take<double>(std::max<int64_t>(nchunks * round_up(sy.ld, 64) * (2 * op.p + 1),
+                                               ((in.m + 63) / 64) * sy.ld));
 
   Pre& pr = pl.pr;
   pr.k = op.k;
@@ -433,13 +441,17 @@ int tile_for(int requested, int64_t B) {
 // Qout[:, act] = (1 + sigma) Pin[:, act] + S Pin[:, act] with S in precision `prec`;
 // partial dots of Pin^T Qout into part.
 int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* act, const int32_t* nact,
-            int64_t Bmax, const double* sigma, double* Qout, double* part, int rows_per_wave, hipStream_t st) {
+            int64_t Bmax, const double* sigma, double* Qout, double* part, int rows_per_wave, hipStream_t st,
+            const AlphaOut* alpha = nullptr, int64_t v_ready_ld = 0) {
   Inst& in = pl.in;
   const int64_t Bpad = round_up(Bmax, kSysTile);
   if (in.obs) {
-    IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, Bpad, st));
+    // v_ready_ld > 0: the caller already wrote Pin's active columns into the apply buffer with that
+    // leading dimension (the PCG direction kernel does)
+    const int64_t ldv = v_ready_ld > 0 ? v_ready_ld : Bpad;
+    if (v_ready_ld <= 0) IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, Bpad, st));
     const void* Zu = (prec == Prec::F64) ? (const void*)in.Zt : (const void*)in.Zt32;
-    IE_HIP(cov_stencil_timed(prec, in.go, Zu, in.m, in.N, pl.bf.V, Bpad, Bpad, nact, pl.bf.T, Bpad,
+    IE_HIP(cov_stencil_timed(prec, in.go, Zu, in.m, in.N, pl.bf.V, ldv, Bpad, nact, pl.bf.T, Bpad,
                              tile_for(rows_per_wave, Bmax), st));
   } else {
     IE_HIP(launch_scatter_state(prec, Pin, ldp, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n, in.m,
@@ -455,7 +467,7 @@ int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* 
     }
   }
   IE_HIP(launch_apply_finish(prec, in.obs ? 1 : 0, Pin, ldp, pl.bf.T, Bpad, act, nact, sigma, in.P->h_ptr,
-                             in.P->h_idx, in.P->h_w, in.P->r_var, in.m, in.n, Bpad, Qout, part, kChunk, st));
+                             in.P->h_idx, in.P->h_w, in.P->r_var, in.m, in.n, Bpad, Qout, part, kChunk, alpha, st));
   return 0;
 }
 
@@ -598,6 +610,8 @@ LMP lmp_of(Plan& pl) {
 }
 
 // Iterative refinement around batched PCG.  Solves (1 + sigma_s) u_s + S u_s = b_s for all s.
+// Outer sweeps form the true residual r = b - C u in FP64; the inner PCG (apply precision
+// op.inner) solves C d = r to the per-system target and u += d.
 int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   Inst& in = pl.in;
   Sys& sy = pl.sy;
@@ -612,17 +626,27 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   ps.r = sy.r;
   ps.p = sy.p;
   ps.q = sy.q;
-  ps.b = sy.r;
   ps.sigma = sy.sigma;
+  ps.rz = sy.rz0;
+  ps.alpha = sy.alpha;
+  ps.coef = sy.coef;
+  ps.thresh = sy.thresh;
   ps.bnorm = sy.bnorm;
-  ps.relres = sy.rel_in;  // inner relative residuals (not reported)
+  ps.relres = sy.rel_in;
   ps.iters = sy.iters;
   ps.done = sy.done;
   ps.flags = in.flags;
+  ps.tile_cnt = sy.tile_cnt;
+  ps.glob_cnt = sy.glob_cnt;
+  ps.part = sy.part2;
   ps.chunk_rows = kChunk;
   ps.nchunks = (int)((m + kChunk - 1) / kChunk);
+  ps.max_iter = op.max_iter;
+  AlphaOut ao{sy.rz0, sy.alpha, sy.done, in.flags, sy.tile_cnt};
 
-  IE_HIP(launch_col_norms(sy.b, m, S, ld, sy.bnorm, st));
+  IE_HIP(launch_fill_i32(sy.tile_cnt, 0, round_up(std::max<int64_t>(ld, pl.pr.k + 16), 16) / 16 + 16, st));
+  IE_HIP(launch_fill_i32(sy.glob_cnt, 0, 1, st));
+  IE_HIP(launch_col_norms(sy.b, m, S, ld, sy.bnorm, sy.part2, st));
   IE_HIP(launch_fill_f64(sy.u, 0.0, m * ld, st));
   IE_HIP(launch_fill_i32(sy.iters, 0, ld, st));
   IE_HIP(launch_fill_i32(sy.sweeps, 0, ld, st));
@@ -630,61 +654,52 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
 
   const int max_sweeps = op.host_sync ? 40 : (fp64_inner ? 2 : (op.inner == Prec::F32 ? 4 : 10));
   const int check_every = 4;
-  int32_t h_nact = 0;
+  const bool plain = (op.solver == INFOESRF_SOLVER_PLAIN);
+  void* Vbuf = in.obs ? pl.bf.V : nullptr;
+  int32_t h_nact = (int32_t)S;
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
     // outer residual r = b - C u (FP64).  Zero start: the first residual is b itself.
-    IE_HIP(launch_iota(sy.act, sy.nact, S, st));
     if (sweep == 0) {
       hipLaunchKernelGGL(k_copy_f64, dim3(nb(m * ld)), dim3(256), 0, st, sy.b, sy.r, m * ld);
       IE_HIP(hipGetLastError());
     } else {
-      // only systems still in play need the FP64 sweep
       IE_HIP(launch_compact(sy.fdone, S, sy.act, sy.nact, st));
       IE_TRY(apply_S(pl, Prec::F64, sy.u, ld, sy.act, sy.nact, S, sy.sigma, sy.q, sy.part_pq, op.rows_per_wave, st));
       IE_HIP(launch_sub(sy.b, sy.q, sy.r, m, S, ld, st));
     }
-    IE_HIP(launch_col_norms(sy.r, m, S, ld, sy.rn, st));
+    IE_HIP(launch_col_norms(sy.r, m, S, ld, sy.rn, sy.part2, st));
     hipLaunchKernelGGL(k_sweep_status, dim3(nb(S)), dim3(256), 0, st, sy.rn, sy.bnorm, op.rtol, op.inner_rtol,
                        fp64_inner ? 1 : 0, sy.iters, op.max_iter, sy.relres, sy.fdone, sy.done, sy.thresh,
                        sy.sweeps, sweep > 0 ? 1 : 0, S, in.flags);
     IE_HIP(hipGetLastError());
-    // active set of this sweep
-    if (op.solver == INFOESRF_SOLVER_PLAIN) {
-      IE_HIP(launch_iota(sy.act, sy.nact, S, st));
-    } else {
-      IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
-    }
+    IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
     if (op.host_sync) {
-      // any work left?
-      IE_HIP(launch_compact(sy.done, S, sy.act + 0, sy.nact, st));
       IE_HIP(hipMemcpyAsync(&h_nact, sy.nact, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       IE_HIP(hipStreamSynchronize(st));
       if (h_nact == 0) break;
-      if (op.solver == INFOESRF_SOLVER_PLAIN) IE_HIP(launch_iota(sy.act, sy.nact, S, st));
     }
     if (sweep == max_sweeps) break;
-    // inner PCG on C d = r, from d = 0
+    // inner PCG on C d = r from d = 0
     IE_HIP(launch_fill_f64(sy.x, 0.0, m * ld, st));
-    ps.bnorm = sy.thresh;  // direction kernel compares ||r|| <= tol * bnorm; tol = 1 => thresh
-    ps.rz = sy.rz0;
-    IE_HIP(launch_pcg_dots(ps, lmp, sy.act, sy.nact, ld, sy.part2, st));
-    IE_HIP(launch_pcg_direction(ps, lmp, sy.act, sy.nact, ld, sy.part2, 1.0, 1, op.max_iter, sy.rz1, sy.rz0, st));
-    double* rz_cur = sy.rz0;
-    double* rz_nxt = sy.rz1;
-    const int inner_cap = op.max_iter;
-    for (int it = 1; it <= inner_cap; ++it) {
-      if (op.solver != INFOESRF_SOLVER_PLAIN) IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
-      IE_TRY(apply_S(pl, op.inner, sy.p, ld, sy.act, sy.nact, S, sy.sigma, sy.q, sy.part_pq, op.rows_per_wave, st));
-      ps.rz = rz_cur;
-      IE_HIP(launch_pcg_step(ps, lmp, sy.act, sy.nact, ld, sy.part_pq, sy.part2, st));
-      IE_HIP(launch_pcg_direction(ps, lmp, sy.act, sy.nact, ld, sy.part2, 1.0, 0, op.max_iter, rz_cur, rz_nxt, st));
-      std::swap(rz_cur, rz_nxt);
+    int32_t *act_c = sy.act, *nact_c = sy.nact, *act_n = sy.act2, *nact_n = sy.nact2;
+    int64_t hint = plain ? S : (int64_t)h_nact;  // upper bound of the live count on the device
+    IE_HIP(launch_pcg_step(ps, lmp, 0, act_c, nact_c, act_n, nact_n, round_up(hint, kSysTile), 1.0, st));
+    std::swap(act_c, act_n);
+    std::swap(nact_c, nact_n);
+    IE_HIP(launch_pcg_direction(op.inner, ps, lmp, 1, act_c, nact_c, round_up(hint, kSysTile), Vbuf, ld, st));
+    for (int it = 1; it <= op.max_iter; ++it) {
+      const int64_t bp = round_up(hint, kSysTile);
+      IE_TRY(apply_S(pl, op.inner, sy.p, ld, act_c, nact_c, bp, sy.sigma, sy.q, sy.part_pq, op.rows_per_wave, st,
+                     &ao, /*v_ready_ld=*/ld));
+      IE_HIP(launch_pcg_step(ps, lmp, 1, act_c, nact_c, act_n, nact_n, bp, 1.0, st));
+      std::swap(act_c, act_n);
+      std::swap(nact_c, nact_n);
+      IE_HIP(launch_pcg_direction(op.inner, ps, lmp, 0, act_c, nact_c, bp, Vbuf, ld, st));
       if (op.host_sync && (it % check_every) == 0) {
-        IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
-        IE_HIP(hipMemcpyAsync(&h_nact, sy.nact, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        IE_HIP(hipMemcpyAsync(&h_nact, nact_c, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         IE_HIP(hipStreamSynchronize(st));
         if (h_nact == 0) break;
-        if (op.solver == INFOESRF_SOLVER_PLAIN) IE_HIP(launch_iota(sy.act, sy.nact, S, st));
+        if (!plain) hint = h_nact;
       }
     }
     // u += d for every system (d = 0 where the system was not active)

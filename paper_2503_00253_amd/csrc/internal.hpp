@@ -133,6 +133,15 @@ hipError_t launch_scatter_state(Prec prec, const double* P, int64_t ldp, const i
                                 const int32_t* col_ptr, const int32_t* row_of, const double* w_of,
                                 const double* r_var, int64_t n, int64_t m, int64_t Bpad, void* V, int64_t ldv,
                                 hipStream_t st);
+// With an AlphaOut the last block of each column tile also forms alpha_s = rz_s / p^T q for the
+// listed systems (retiring any whose curvature is not positive).
+struct AlphaOut {
+  const double* rz;
+  double* alpha;
+  int32_t* done;
+  int32_t* flags;
+  int32_t* tile_cnt;  // zero on entry; left zero
+};
 // Q[r, s] = c_s * P[r, s] + (domain OBS ? T[r, c] : dinv_r sum_e w_e T[idx_e, c]), s = act[c],
 // c_s = (1 + sigma_s) (sigma_s = shift of system s; sigma = -1 gives S itself),
 // plus per-(chunk, c) partial dot products P^T Q written to part[chunk * Bpad + c].
@@ -140,7 +149,7 @@ hipError_t launch_apply_finish(Prec prec, int obs_domain, const double* P, int64
                                const int32_t* act, const int32_t* nact, const double* sigma, const int32_t* h_ptr,
                                const int32_t* h_idx, const double* h_w, const double* r_var, int64_t m,
                                int64_t n_state, int64_t Bpad, double* Qv, double* part, int chunk_rows,
-                               hipStream_t st);
+                               const AlphaOut* alpha, hipStream_t st);
 
 // ---------------------------------------------------------------- PCG (K4)
 struct LMP {
@@ -153,35 +162,35 @@ struct LMP {
 };
 
 struct PCGState {
-  int64_t m, S, ld;     // rows, systems, leading dim (>= S, multiple of 16)
-  double *x, *r, *p, *q;
-  const double* b;      // right-hand sides
-  const double* sigma;  // per-system shift
-  double* rz;           // per system r^T z (current)
-  double* bnorm;        // per system ||b||
-  double* relres;       // per system recursive relres (inner) / true relres
-  int32_t* iters;       // per system iteration counts
-  int32_t* done;        // per system: 0 active, 1 converged, 2 failed/capped
-  int32_t* flags;       // global error flags
-  double* part;         // partial sums
-  int chunk_rows;       // rows per reduction chunk
+  int64_t m, S, ld;      // rows, systems, leading dim (>= S, multiple of 16)
+  double *x, *r, *p, *q; // iterate, residual, direction, C p
+  const double* sigma;   // per-system shift
+  double* rz;            // per system r^T z
+  double* alpha;         // per system step length
+  double* coef;          // per system (2p+1): c1, gamma, beta
+  double* thresh;        // per system absolute residual target
+  double* bnorm;         // per system ||b|| (for relres)
+  double* relres;        // per system recursive relative residual
+  int32_t* iters;        // per system iteration counts
+  int32_t* done;         // per system: 0 active, 1 converged, 2 failed/capped
+  int32_t* flags;        // global error flags
+  int32_t* tile_cnt;     // arrival counters per column tile (zero on entry, left zero)
+  int32_t* glob_cnt;     // arrival counter of column tiles (zero on entry, left zero)
+  double* part;          // partial sums, nchunks x Bpad x (2p+1)
+  int chunk_rows;        // rows per reduction chunk
   int nchunks;
+  int max_iter;
 };
 
-// Dots of r with itself and with the Ritz bases: part2[(chunk * Bpad + c) * (2p+1) + j]
-hipError_t launch_pcg_dots(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact, int64_t Bpad,
-                           double* part2, hipStream_t st);
-// alpha = rz/(p^T q) (from apply partials); x += alpha p; r -= alpha q; then dots of r (part2).
-hipError_t launch_pcg_step(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact, int64_t Bpad,
-                           const double* part_pq, double* part2, hipStream_t st);
-// From the dots of r: convergence test against tol_rel * bnorm, z = M^{-1} r, p = z + beta p.
-// first != 0: p = z and rz initialized.  rz_next receives the new r^T z.
-hipError_t launch_pcg_direction(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact,
-                                int64_t Bpad, const double* part2, double tol_rel, int first, int max_iter,
-                                const double* rz_cur, double* rz_next, hipStream_t st);
+// mode 0: dots of r; mode 1: x += alpha p, r -= alpha q, then dots.  Converged systems are
+// retired (done), and the systems still active are listed in act_out/nact_out.
+hipError_t launch_pcg_step(const PCGState& s, const LMP& lmp, int mode, const int32_t* act, const int32_t* nact,
+                           int32_t* act_out, int32_t* nact_out, int64_t Bpad, double tol_rel, hipStream_t st);
+// p = z + beta p (first: p = z) for the listed systems; V (nullable) receives p in the apply precision.
+hipError_t launch_pcg_direction(Prec vprec, const PCGState& s, const LMP& lmp, int first, const int32_t* act,
+                                const int32_t* nact, int64_t Bpad, void* V, int64_t ldv, hipStream_t st);
 // Rebuild the list of active systems (done == 0), in increasing order.  One block.
 hipError_t launch_compact(const int32_t* done, int64_t S, int32_t* act, int32_t* nact, hipStream_t st);
-// Fill act = 0..S-1 with systems that have done==0 kept in place (masked plain solver uses all).
 hipError_t launch_iota(int32_t* act, int32_t* nact, int64_t S, hipStream_t st);
 
 // ---------------------------------------------------------------- misc vector kernels
@@ -192,8 +201,9 @@ hipError_t launch_sub(const double* a, const double* b, double* out, int64_t m, 
                       hipStream_t st);
 // x[r*ld+s] += d[r*ld+s] for s with mask[s] (mask may be null)
 hipError_t launch_axpy_masked(double* x, const double* d, int64_t m, int64_t S, int64_t ld, hipStream_t st);
-// per-system norms: out[s] = ||v[:, s]||_2 (deterministic)
-hipError_t launch_col_norms(const double* v, int64_t m, int64_t S, int64_t ld, double* out, hipStream_t st);
+// per-system norms: out[s] = ||v[:, s]||_2 (deterministic); scratch holds ceil(m/64) * S doubles
+hipError_t launch_col_norms(const double* v, int64_t m, int64_t S, int64_t ld, double* out, double* scratch,
+                            hipStream_t st);
 // true-residual bookkeeping: relres[s] = rn[s] / bn[s]; done[s] = relres <= tol ? 1 : 0 (for done != 2)
 hipError_t launch_residual_status(const double* rn, const double* bn, double tol, double* relres, int32_t* done,
                                   int64_t S, int32_t* flags, hipStream_t st);

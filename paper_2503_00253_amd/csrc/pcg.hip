@@ -30,6 +30,27 @@ __device__ inline int32_t load_nact(const int32_t* nact, int64_t fallback) {
 
 // --------------------------------------------------------------- apply glue
 
+// Block arrival count of a column tile; true in the last block to arrive (which resets the counter).
+// One agent-scope release per block (thread 0, after the block's barrier) and one acquire in the
+// last block: on gfx950 each agent-scope fence is an L2 writeback/invalidate, because the L2s of
+// the eight XCDs are not coherent with each other, so fences are kept to one per block.
+__device__ inline bool last_arrival_apply(int32_t* cnt, int total, int* s_flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const int prev = atomicAdd(cnt, 1);
+    const int last = (prev == total - 1);
+    if (last) {
+      atomicExch(cnt, 0);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    *s_flag = last;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
 template <typename TV>
 __device__ inline TV to_prec(double v);
 template <>
@@ -70,6 +91,8 @@ __global__ void k_scatter_state(const double* __restrict__ P, int64_t ldp, const
 }
 
 // q = (1 + sigma_s) p + S p, with S p = T (obs domain) or R^{-1/2} H T (state domain); partial p^T q.
+// With an AlphaOut, the last block of each column tile also forms alpha_s = rz_s / p^T q
+// (and retires systems whose curvature is not positive).
 template <typename TT>
 __global__ __launch_bounds__(256) void k_apply_finish(int obs_domain, const double* __restrict__ P, int64_t ldp,
                                                       const TT* __restrict__ T, int64_t ldt,
@@ -81,10 +104,11 @@ __global__ __launch_bounds__(256) void k_apply_finish(int obs_domain, const doub
                                                       const double* __restrict__ h_w,
                                                       const double* __restrict__ r_var, int64_t m,
                                                       int64_t n_state, int64_t Bpad, double* __restrict__ Qv,
-                                                      double* __restrict__ part, int chunk_rows) {
-  __shared__ double red[kLanes][kSys];
-  const int cl = threadIdx.x % kSys, lane_r = threadIdx.x / kSys;
-  const int64_t c = blockIdx.y * (int64_t)kSys + cl;
+                                                      double* __restrict__ part, int chunk_rows, AlphaOut ao) {
+  __shared__ double red[16][16];
+  __shared__ int s_flag;
+  const int cl = threadIdx.x % 16, lane_r = threadIdx.x / 16;
+  const int64_t c = blockIdx.y * (int64_t)16 + cl;
   const int32_t na = load_nact(nact, Bpad);
   const int64_t r0 = blockIdx.x * (int64_t)chunk_rows;
   const int64_t r1 = min<int64_t>(m, r0 + chunk_rows);
@@ -92,7 +116,7 @@ __global__ __launch_bounds__(256) void k_apply_finish(int obs_domain, const doub
   if (c < na) {
     const int32_t s = act[c];
     const double coef = 1.0 + sigma[s];
-    for (int64_t r = r0 + lane_r; r < r1; r += kLanes) {
+    for (int64_t r = r0 + lane_r; r < r1; r += 16) {
       double sp;
       if (obs_domain) {
         sp = (double)T[r * ldt + c];
@@ -113,199 +137,270 @@ __global__ __launch_bounds__(256) void k_apply_finish(int obs_domain, const doub
   red[lane_r][cl] = dot;
   __syncthreads();
   if (lane_r == 0 && c < na) {
-    double s = red[0][cl];
-    for (int j = 1; j < kLanes; ++j) s += red[j][cl];
-    part[blockIdx.x * Bpad + c] = s;
+    double t = red[0][cl];
+    for (int j = 1; j < 16; ++j) t += red[j][cl];
+    part[blockIdx.x * Bpad + c] = t;
+  }
+  if (!ao.alpha) return;
+  if (!last_arrival_apply(ao.tile_cnt + blockIdx.y, gridDim.x, &s_flag)) return;
+  if (threadIdx.x < 16 && c < na) {
+    const int32_t s = act[c];
+    if (ao.done[s] == 0) {
+      double pq = 0.0;
+      for (int k = 0; k < (int)gridDim.x; ++k) pq += part[k * Bpad + c];  // after the fence of last_arrival
+      if (!(pq > 0.0) || !isfinite(pq)) {
+        atomicOr(ao.flags, isfinite(pq) ? kFlagNotSPD : kFlagNumeric);
+        ao.done[s] = 2;
+        ao.alpha[s] = 0.0;
+      } else {
+        ao.alpha[s] = ao.rz[s] / pq;
+      }
+    }
   }
 }
 
 // --------------------------------------------------------------- PCG kernels
+//
+// Thread layout of the reduction kernels: a block holds 16 systems (columns of
+// the active list) x 16 row lanes and covers `chunk_rows` rows.  Partial sums
+// of a (chunk, system) are written once; the last block of each column tile to
+// finish (counted with a device-scope atomic after a fence) reduces the
+// partials of its 16 systems over all chunks in chunk order.  No block waits
+// for another, and the summation order is fixed.
 
-// Accumulate r^T r, Phi^T r, (S Phi)^T r of the rows of this block's chunk for system s.
-template <int P>
-__device__ inline void chunk_dots(const PCGState& st, const LMP& lmp, int32_t s, int64_t r0, int64_t r1, int lane_r,
-                                  double* acc) {
-#pragma unroll
-  for (int j = 0; j < 2 * P + 1; ++j) acc[j] = 0.0;
-  for (int64_t r = r0 + lane_r; r < r1; r += kLanes) {
-    const double rv = st.r[r * st.ld + s];
-    acc[0] += rv * rv;
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      acc[1 + j] += lmp.Phi[r * P + j] * rv;
-      acc[1 + P + j] += lmp.SPhi[r * P + j] * rv;
-    }
-  }
+constexpr int kCS = 16;   // systems per block
+constexpr int kRL = 16;   // row lanes per block
+
+// Values written by other blocks of the same kernel are read only after last_arrival(), whose
+// agent-scope acquire invalidates this CU's L1 and the XCD's L2 lines, so plain loads see them.
+__device__ inline double vload(const double* p) { return *p; }
+__device__ inline int32_t vload_i32(const int32_t* p) { return *p; }
+
+__device__ inline bool last_arrival(int32_t* cnt, int total, int* s_flag) {
+  return last_arrival_apply(cnt, total, s_flag);
 }
 
+// LMP coefficients of one system from the dots of r (Appendix E preconditioner):
+//   c1 = Theta^{-1} Phi^T r, c2 = Theta^{-1} [(C Phi)^T r - (C Phi)^T (C Phi) c1],
+//   z = r - S Phi c1 - Phi gamma, gamma = (1 + sigma - beta_L) c1 + c2, r^T z.
 template <int P>
-__device__ inline void reduce_store(double* acc, double (*red)[kSys], int cl, int lane_r, bool ok, double* part2,
-                                    int64_t base) {
-  // red: [kLanes][kSys] reused per component (fixed order)
-  for (int j = 0; j < 2 * P + 1; ++j) {
-    red[lane_r][cl] = acc[j];
-    __syncthreads();
-    if (lane_r == 0 && ok) {
-      double s = red[0][cl];
-      for (int t = 1; t < kLanes; ++t) s += red[t][cl];
-      part2[base * (2 * P + 1) + j] = s;
-    }
-    __syncthreads();
+__device__ inline double lmp_coefficients(const LMP& lmp, double sig1, const double* d, double* c1, double* gam) {
+  double rz = d[0];
+  if (P == 0) return rz;
+  const double beta_l = sig1 + *lmp.dmin;
+  const double* Gpp = lmp.G;
+  const double* Gps = lmp.G + P * P;
+  const double* Gss = lmp.G + 2 * P * P;
+  for (int j = 0; j < P; ++j) c1[j] = d[1 + j] / (sig1 + lmp.theta[j]);
+  for (int j = 0; j < P; ++j) {
+    double mc = 0.0;
+    for (int l = 0; l < P; ++l)
+      mc += (Gss[j * P + l] + sig1 * (Gps[j * P + l] + Gps[l * P + j]) + sig1 * sig1 * Gpp[j * P + l]) * c1[l];
+    const double c2 = (d[1 + P + j] + sig1 * d[1 + j] - mc) / (sig1 + lmp.theta[j]);
+    gam[j] = (sig1 - beta_l) * c1[j] + c2;
   }
+  for (int j = 0; j < P; ++j) rz -= d[1 + P + j] * c1[j] + d[1 + j] * gam[j];
+  return rz;
 }
 
+// mode 0: dots of r only (start of a solve); mode 1: alpha step on x and r, then dots.
+// The last block per column tile turns the dots into per-system coefficients
+// (coef[s*W + 0..P) = c1, [P..2P) = gamma, [2P] = beta), the convergence status and
+// r^T z; the last of those blocks writes the next active list (act_out, nact_out).
 template <int P>
-__global__ __launch_bounds__(256) void k_pcg_dots(PCGState st, LMP lmp, const int32_t* __restrict__ act,
-                                                  const int32_t* __restrict__ nact, int64_t Bpad,
-                                                  double* __restrict__ part2) {
-  __shared__ double red[kLanes][kSys];
-  const int cl = threadIdx.x % kSys, lane_r = threadIdx.x / kSys;
-  const int64_t c = blockIdx.y * (int64_t)kSys + cl;
-  const int32_t na = load_nact(nact, Bpad);
+__global__ __launch_bounds__(256) void k_pcg_step(PCGState st, LMP lmp, int mode, const int32_t* __restrict__ act,
+                                                  const int32_t* __restrict__ nact, int32_t* __restrict__ act_out,
+                                                  int32_t* __restrict__ nact_out, int64_t Bpad, double tol_rel) {
+  constexpr int W = 2 * P + 1;
+  extern __shared__ double sm[];  // kRL * kCS * W doubles, reused for the final sums
+  __shared__ int s_flag;
+  __shared__ int32_t s_cnt[256];
+  const int cl = threadIdx.x % kCS, lr = threadIdx.x / kCS;
+  const int64_t c = blockIdx.y * (int64_t)kCS + cl;
+  const int32_t na = *nact;
   const int64_t r0 = blockIdx.x * (int64_t)st.chunk_rows;
   const int64_t r1 = min<int64_t>(st.m, r0 + st.chunk_rows);
-  double acc[2 * P + 1];
-  bool ok = false;
-  if (c < na) {
-    const int32_t s = act[c];
-    ok = (st.done[s] == 0);
-    if (ok) {
-      chunk_dots<P>(st, lmp, s, r0, r1, lane_r, acc);
-    }
-  }
-  if (!ok) {
+  double acc[W];
 #pragma unroll
-    for (int j = 0; j < 2 * P + 1; ++j) acc[j] = 0.0;
-  }
-  reduce_store<P>(acc, red, cl, lane_r, ok, part2, blockIdx.x * Bpad + c);
-}
-
-template <int P>
-__global__ __launch_bounds__(256) void k_pcg_step(PCGState st, LMP lmp, const int32_t* __restrict__ act,
-                                                  const int32_t* __restrict__ nact, int64_t Bpad,
-                                                  const double* __restrict__ part_pq, double* __restrict__ part2) {
-  __shared__ double red[kLanes][kSys];
-  const int cl = threadIdx.x % kSys, lane_r = threadIdx.x / kSys;
-  const int64_t c = blockIdx.y * (int64_t)kSys + cl;
-  const int32_t na = load_nact(nact, Bpad);
-  const int64_t r0 = blockIdx.x * (int64_t)st.chunk_rows;
-  const int64_t r1 = min<int64_t>(st.m, r0 + st.chunk_rows);
-  double acc[2 * P + 1];
+  for (int j = 0; j < W; ++j) acc[j] = 0.0;
+  int32_t s = -1;
   bool ok = false;
   if (c < na) {
-    const int32_t s = act[c];
+    s = act[c];
     ok = (st.done[s] == 0);
-    if (ok) {
-      double pq = 0.0;
-      for (int k = 0; k < st.nchunks; ++k) pq += part_pq[k * Bpad + c];
-      const double rz = st.rz[s];
-      if (!(pq > 0.0) || !isfinite(pq)) {
-        // curvature breakdown: every chunk of this system sees the same pq and stops; the
-        // first chunk retires the system and raises the flag
-        if (blockIdx.x == 0 && lane_r == 0) {
-          atomicOr(st.flags, isfinite(pq) ? kFlagNotSPD : kFlagNumeric);
-          st.done[s] = 2;
-        }
-        ok = false;
-      } else {
-        const double alpha = rz / pq;
-        for (int64_t r = r0 + lane_r; r < r1; r += kLanes) {
-          const int64_t e = r * st.ld + s;
-          st.x[e] += alpha * st.p[e];
-          st.r[e] -= alpha * st.q[e];
-        }
-        chunk_dots<P>(st, lmp, s, r0, r1, lane_r, acc);
+  }
+  // Ritz-basis rows of this chunk, shared by the block's 16 systems
+  double* sphi = sm;                        // chunk_rows x 2P (Phi row, then S Phi row)
+  for (int o = threadIdx.x; o < (int)(r1 - r0) * 2 * P; o += blockDim.x) {
+    const int rl = o / (2 * P), j = o % (2 * P);
+    sphi[o] = (j < P) ? lmp.Phi[(r0 + rl) * P + j] : lmp.SPhi[(r0 + rl) * P + (j - P)];
+  }
+  __syncthreads();
+  if (ok) {
+    const double alpha = mode ? st.alpha[s] : 0.0;
+    for (int64_t r = r0 + lr; r < r1; r += kRL) {
+      const int64_t e = r * st.ld + s;
+      double rv = st.r[e];
+      if (mode) {
+        st.x[e] += alpha * st.p[e];
+        rv -= alpha * st.q[e];
+        st.r[e] = rv;
+      }
+      acc[0] += rv * rv;
+      const double* row = sphi + (r - r0) * 2 * P;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        acc[1 + j] += row[j] * rv;
+        acc[1 + P + j] += row[P + j] * rv;
       }
     }
   }
-  if (!ok) {
+  __syncthreads();  // sphi is reused below
+  // block reduction over the 16 row lanes (fixed order)
 #pragma unroll
-    for (int j = 0; j < 2 * P + 1; ++j) acc[j] = 0.0;
+  for (int j = 0; j < W; ++j) sm[(j * kRL + lr) * kCS + cl] = acc[j];
+  __syncthreads();
+  for (int o = threadIdx.x; o < W * kCS; o += blockDim.x) {
+    const int j = o / kCS, cc = o % kCS;
+    const int64_t col = blockIdx.y * (int64_t)kCS + cc;
+    double t = 0.0;
+    for (int l = 0; l < kRL; ++l) t += sm[(j * kRL + l) * kCS + cc];
+    if (col < na) st.part[(blockIdx.x * Bpad + col) * W + j] = t;
   }
-  reduce_store<P>(acc, red, cl, lane_r, ok, part2, blockIdx.x * Bpad + c);
+  if (!last_arrival(st.tile_cnt + blockIdx.y, gridDim.x, &s_flag)) return;
+
+  // ---- last block of this column tile: reduce over chunks, per-system scalars
+  __shared__ double sG[3 * 16 * 16 + 16];
+  __shared__ double sc1[kCS][16];
+  for (int o = threadIdx.x; o < 3 * P * P; o += blockDim.x) sG[o] = lmp.G[o];
+  if (threadIdx.x < P) sG[3 * P * P + threadIdx.x] = lmp.theta[threadIdx.x];
+  for (int o = threadIdx.x; o < W * kCS; o += blockDim.x) {
+    const int j = o / kCS, cc = o % kCS;
+    const int64_t col = blockIdx.y * (int64_t)kCS + cc;
+    double t = 0.0;
+    if (col < na)
+      for (int k = 0; k < (int)gridDim.x; ++k) t += vload(&st.part[(k * Bpad + col) * W + j]);
+    sm[j * kCS + cc] = t;
+  }
+  __syncthreads();
+  // one system per column (cc), its P coefficient indices spread over the 16 lanes (jj)
+  const int cc = threadIdx.x % kCS, jj = threadIdx.x / kCS;
+  const int64_t col = blockIdx.y * (int64_t)kCS + cc;
+  int32_t sy = -1;
+  int state = 0;  // 0 skip, 1 converged, 2 non-finite, 3 continue
+  double sig1 = 1.0;
+  if (col < na) {
+    sy = act[col];
+    if (st.done[sy] == 0) {
+      const double rr = sm[cc];
+      sig1 = 1.0 + st.sigma[sy];
+      state = !isfinite(rr) ? 2 : (sqrt(rr) <= tol_rel * st.thresh[sy] ? 1 : 3);
+    }
+  }
+  const double* sth = sG + 3 * P * P;
+  if (state == 3 && jj < P) sc1[cc][jj] = sm[(1 + jj) * kCS + cc] / (sig1 + sth[jj]);
+  __syncthreads();
+  double* cf = (sy >= 0) ? st.coef + (int64_t)sy * W : nullptr;
+  if (state == 3 && jj < P) {
+    // (C Phi)^T (C Phi) = Gss + sig1 (Gps + Gps^T) + sig1^2 Gpp, applied to c1
+    const double* Gpp = sG;
+    const double* Gps = sG + P * P;
+    const double* Gss = sG + 2 * P * P;
+    double mc = 0.0;
+    for (int l = 0; l < P; ++l)
+      mc += (Gss[jj * P + l] + sig1 * (Gps[jj * P + l] + Gps[l * P + jj]) + sig1 * sig1 * Gpp[jj * P + l]) *
+            sc1[cc][l];
+    const double c2 = (sm[(1 + P + jj) * kCS + cc] + sig1 * sm[(1 + jj) * kCS + cc] - mc) / (sig1 + sth[jj]);
+    const double beta_l = sig1 + *lmp.dmin;
+    const double g = (sig1 - beta_l) * sc1[cc][jj] + c2;
+    cf[jj] = sc1[cc][jj];
+    cf[P + jj] = g;
+    // the products of r^T z, summed below in index order
+    sm[(W + jj) * kCS + cc] = sm[(1 + P + jj) * kCS + cc] * sc1[cc][jj] + sm[(1 + jj) * kCS + cc] * g;
+  }
+  __syncthreads();
+  if (state != 0 && jj == 0) {
+    const double rr = sm[cc];
+    const double bn = st.bnorm[sy];
+    const int it = st.iters[sy] + mode;
+    st.iters[sy] = it;
+    st.relres[sy] = bn > 0.0 ? sqrt(rr) / bn : 0.0;
+    if (state == 2) {
+      atomicOr(st.flags, kFlagNumeric);
+      st.done[sy] = 2;
+    } else if (state == 1) {
+      st.done[sy] = 1;
+    } else {
+      double rz = rr;
+      for (int j = 0; j < P; ++j) rz -= sm[(W + j) * kCS + cc];
+      cf[2 * P] = mode ? rz / st.rz[sy] : 0.0;
+      st.rz[sy] = rz;
+      if (!(rz > 0.0)) {
+        atomicOr(st.flags, isfinite(rz) ? kFlagNotSPD : kFlagNumeric);
+        st.done[sy] = 2;
+      } else if (it >= st.max_iter) {
+        st.done[sy] = 2;
+      }
+    }
+  }
+  if (!last_arrival(st.glob_cnt, gridDim.y, &s_flag)) return;
+
+  // ---- last block overall: next active list, in the order of the current one
+  const int per = (na + 255) / 256;
+  const int a = threadIdx.x * per, b = min(na, a + per);
+  int32_t keep = 0;
+  for (int i = a; i < b; ++i) keep += (vload_i32(&st.done[act[i]]) == 0);
+  s_cnt[threadIdx.x] = keep;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t run = 0;
+    for (int i = 0; i < 256; ++i) {
+      const int32_t v = s_cnt[i];
+      s_cnt[i] = run;
+      run += v;
+    }
+    *nact_out = run;
+  }
+  __syncthreads();
+  int32_t pos = s_cnt[threadIdx.x];
+  for (int i = a; i < b; ++i) {
+    const int32_t sy = act[i];
+    if (vload_i32(&st.done[sy]) == 0) act_out[pos++] = sy;
+  }
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void k_pcg_direction(PCGState st, LMP lmp, const int32_t* __restrict__ act,
-                                                       const int32_t* __restrict__ nact, int64_t Bpad,
-                                                       const double* __restrict__ part2, double tol_rel, int first,
-                                                       int max_iter, const double* __restrict__ rz_cur,
-                                                       double* __restrict__ rz_next) {
-  const int cl = threadIdx.x % kSys, lane_r = threadIdx.x / kSys;
-  const int64_t c = blockIdx.y * (int64_t)kSys + cl;
-  const int32_t na = load_nact(nact, Bpad);
+// p = z + beta p with z = r - S Phi c1 - Phi gamma for the systems of the (new) active list;
+// optionally also writes p into the apply buffer V (column c of the list, apply precision).
+template <int P, typename TV>
+__global__ __launch_bounds__(256) void k_pcg_direction(PCGState st, LMP lmp, int first,
+                                                       const int32_t* __restrict__ act,
+                                                       const int32_t* __restrict__ nact, TV* __restrict__ V,
+                                                       int64_t ldv) {
+  constexpr int W = 2 * P + 1;
+  __shared__ double cf[kCS][W];
+  const int cl = threadIdx.x % kCS, lr = threadIdx.x / kCS;
+  const int64_t c = blockIdx.y * (int64_t)kCS + cl;
+  const int32_t na = *nact;
+  if (blockIdx.y * (int64_t)kCS >= na) return;
+  for (int o = threadIdx.x; o < kCS * W; o += blockDim.x) {
+    const int cc = o / W, j = o % W;
+    const int64_t col = blockIdx.y * (int64_t)kCS + cc;
+    cf[cc][j] = (col < na) ? st.coef[(int64_t)act[col] * W + j] : 0.0;
+  }
+  __syncthreads();
   if (c >= na) return;
   const int32_t s = act[c];
-  if (st.done[s] != 0) return;
-  const bool writer = (blockIdx.x == 0 && lane_r == 0);
-  // reduce the dots of r over chunks (fixed order)
-  double d[2 * P + 1];
-#pragma unroll
-  for (int j = 0; j < 2 * P + 1; ++j) d[j] = 0.0;
-  for (int k = 0; k < st.nchunks; ++k) {
-    const double* src = part2 + (k * Bpad + c) * (2 * P + 1);
-#pragma unroll
-    for (int j = 0; j < 2 * P + 1; ++j) d[j] += src[j];
-  }
-  const double rr = d[0];
-  const double rn = sqrt(rr);
-  const double bn = st.bnorm[s];
-  const int it = st.iters[s] + (first ? 0 : 1);
-  if (!isfinite(rr)) {
-    if (writer) {
-      atomicOr(st.flags, kFlagNumeric);
-      st.done[s] = 2;
-      st.iters[s] = it;
-    }
-    return;
-  }
-  if (rn <= tol_rel * bn) {
-    if (writer) {
-      st.done[s] = 1;
-      st.iters[s] = it;
-      st.relres[s] = bn > 0.0 ? rn / bn : 0.0;
-    }
-    return;
-  }
-  const double sig1 = 1.0 + st.sigma[s];
-  double c1[P > 0 ? P : 1], gam[P > 0 ? P : 1];
-  double rz = rr;
-  if (P > 0) {
-    const double beta_l = sig1 + *lmp.dmin;
-    const double* Gpp = lmp.G;
-    const double* Gps = lmp.G + P * P;
-    const double* Gss = lmp.G + 2 * P * P;
-#pragma unroll
-    for (int j = 0; j < P; ++j) c1[j] = d[1 + j] / (sig1 + lmp.theta[j]);
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      // (C Phi)^T (C Phi) = Gss + sig1 (Gps + Gps^T) + sig1^2 Gpp
-      double mc = 0.0;
-#pragma unroll
-      for (int l = 0; l < P; ++l)
-        mc += (Gss[j * P + l] + sig1 * (Gps[j * P + l] + Gps[l * P + j]) + sig1 * sig1 * Gpp[j * P + l]) * c1[l];
-      const double c2 = (d[1 + P + j] + sig1 * d[1 + j] - mc) / (sig1 + lmp.theta[j]);
-      gam[j] = (sig1 - beta_l) * c1[j] + c2;
-    }
-#pragma unroll
-    for (int j = 0; j < P; ++j) rz -= d[1 + P + j] * c1[j] + d[1 + j] * gam[j];
-  }
-  const double beta = first ? 0.0 : rz / rz_cur[s];
+  const double beta = cf[cl][2 * P];
   const int64_t r0 = blockIdx.x * (int64_t)st.chunk_rows;
   const int64_t r1 = min<int64_t>(st.m, r0 + st.chunk_rows);
-  for (int64_t r = r0 + lane_r; r < r1; r += kLanes) {
+  for (int64_t r = r0 + lr; r < r1; r += kRL) {
     const int64_t e = r * st.ld + s;
     double z = st.r[e];
 #pragma unroll
-    for (int j = 0; j < P; ++j) z -= lmp.SPhi[r * P + j] * c1[j] + lmp.Phi[r * P + j] * gam[j];
-    st.p[e] = first ? z : z + beta * st.p[e];
-  }
-  if (writer) {
-    rz_next[s] = rz;
-    st.iters[s] = it;
-    st.relres[s] = bn > 0.0 ? rn / bn : 0.0;
-    if (!(rz > 0.0)) atomicOr(st.flags, isfinite(rz) ? kFlagNotSPD : kFlagNumeric);
-    if (it >= max_iter) st.done[s] = 2;
+    for (int j = 0; j < P; ++j) z -= lmp.SPhi[r * P + j] * cf[cl][j] + lmp.Phi[r * P + j] * cf[cl][P + j];
+    const double pn = first ? z : z + beta * st.p[e];
+    st.p[e] = pn;
+    if (V) V[r * ldv + c] = to_prec<TV>(pn);
   }
 }
 
@@ -361,24 +456,34 @@ __global__ void k_axpy(double* x, const double* d, int64_t m, int64_t S, int64_t
   const int64_t e = (t / S) * ld + t % S;
   x[e] += d[e];
 }
-// per-system 2-norm, one block of 256 per 64 systems; fixed order
-__global__ void k_col_norms(const double* __restrict__ v, int64_t m, int64_t S, int64_t ld, double* __restrict__ out) {
-  __shared__ double red[kLanes][kSys];
-  const int cl = threadIdx.x % kSys, lane_r = threadIdx.x / kSys;
-  const int64_t s = blockIdx.x * (int64_t)kSys + cl;
+// per-system 2-norm in two passes: partial sums of row chunks (16 systems x 16 row lanes per
+// block), then one thread per system adds the chunks in order.
+__global__ void k_col_norms_part(const double* __restrict__ v, int64_t m, int64_t S, int64_t ld, int chunk_rows,
+                                 double* __restrict__ part) {
+  __shared__ double red[16][16];
+  const int cl = threadIdx.x % 16, lr = threadIdx.x / 16;
+  const int64_t s = blockIdx.y * (int64_t)16 + cl;
+  const int64_t r0 = blockIdx.x * (int64_t)chunk_rows, r1 = min<int64_t>(m, r0 + chunk_rows);
   double acc = 0.0;
   if (s < S)
-    for (int64_t r = lane_r; r < m; r += kLanes) {
+    for (int64_t r = r0 + lr; r < r1; r += 16) {
       const double x = v[r * ld + s];
       acc += x * x;
     }
-  red[lane_r][cl] = acc;
+  red[lr][cl] = acc;
   __syncthreads();
-  if (lane_r == 0 && s < S) {
+  if (lr == 0 && s < S) {
     double t = red[0][cl];
-    for (int j = 1; j < kLanes; ++j) t += red[j][cl];
-    out[s] = sqrt(t);
+    for (int j = 1; j < 16; ++j) t += red[j][cl];
+    part[blockIdx.x * S + s] = t;
   }
+}
+__global__ void k_col_norms_fin(const double* __restrict__ part, int nchunks, int64_t S, double* __restrict__ out) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  double t = 0.0;
+  for (int k = 0; k < nchunks; ++k) t += part[k * S + s];
+  out[s] = sqrt(t);
 }
 __global__ void k_residual_status(const double* rn, const double* bn, double tol, double* relres, int32_t* done,
                                   int64_t S, int32_t* flags) {
@@ -444,26 +549,32 @@ __global__ void k_nan_check(const double* v, int64_t count, int32_t* flags) {
 inline unsigned nb(int64_t count) { return (unsigned)((count + 255) / 256); }
 
 template <int P>
-hipError_t dispatch_dots(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact, int64_t Bpad,
-                         double* part2, hipStream_t st) {
-  dim3 grid(s.nchunks, (unsigned)((Bpad + kSys - 1) / kSys));
-  hipLaunchKernelGGL(k_pcg_dots<P>, grid, dim3(256), 0, st, s, lmp, act, nact, Bpad, part2);
+hipError_t dispatch_step(const PCGState& s, const LMP& lmp, int mode, const int32_t* act, const int32_t* nact,
+                         int32_t* act_out, int32_t* nact_out, int64_t Bpad, double tol, hipStream_t st) {
+  constexpr int W = 2 * P + 1;
+  size_t smem = sizeof(double) * (size_t)kCS * (kRL * W > W + P ? kRL * W : W + P);
+  const size_t stage = sizeof(double) * (size_t)s.chunk_rows * 2 * P;  // Ritz rows of one chunk
+  if (stage > smem) smem = stage;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pcg_step<P>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  dim3 grid(s.nchunks, (unsigned)((Bpad + kCS - 1) / kCS));
+  hipLaunchKernelGGL(k_pcg_step<P>, grid, dim3(256), smem, st, s, lmp, mode, act, nact, act_out, nact_out, Bpad, tol);
   return hipGetLastError();
 }
 template <int P>
-hipError_t dispatch_step(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact, int64_t Bpad,
-                         const double* part_pq, double* part2, hipStream_t st) {
-  dim3 grid(s.nchunks, (unsigned)((Bpad + kSys - 1) / kSys));
-  hipLaunchKernelGGL(k_pcg_step<P>, grid, dim3(256), 0, st, s, lmp, act, nact, Bpad, part_pq, part2);
-  return hipGetLastError();
-}
-template <int P>
-hipError_t dispatch_dir(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact, int64_t Bpad,
-                        const double* part2, double tol, int first, int max_iter, const double* rz_cur,
-                        double* rz_next, hipStream_t st) {
-  dim3 grid(s.nchunks, (unsigned)((Bpad + kSys - 1) / kSys));
-  hipLaunchKernelGGL(k_pcg_direction<P>, grid, dim3(256), 0, st, s, lmp, act, nact, Bpad, part2, tol, first,
-                     max_iter, rz_cur, rz_next);
+hipError_t dispatch_dir(Prec vp, const PCGState& s, const LMP& lmp, int first, const int32_t* act,
+                        const int32_t* nact, int64_t Bpad, void* V, int64_t ldv, hipStream_t st) {
+  dim3 grid(s.nchunks, (unsigned)((Bpad + kCS - 1) / kCS));
+  if (vp == Prec::F64)
+    hipLaunchKernelGGL((k_pcg_direction<P, double>), grid, dim3(256), 0, st, s, lmp, first, act, nact, (double*)V,
+                       ldv);
+  else
+    hipLaunchKernelGGL((k_pcg_direction<P, float>), grid, dim3(256), 0, st, s, lmp, first, act, nact, (float*)V, ldv);
   return hipGetLastError();
 }
 
@@ -508,36 +619,29 @@ hipError_t launch_apply_finish(Prec prec, int obs_domain, const double* P, int64
                                const int32_t* act, const int32_t* nact, const double* sigma, const int32_t* h_ptr,
                                const int32_t* h_idx, const double* h_w, const double* r_var, int64_t m,
                                int64_t n_state, int64_t Bpad, double* Qv, double* part, int chunk_rows,
-                               hipStream_t st) {
+                               const AlphaOut* alpha, hipStream_t st) {
   const int nchunks = (int)((m + chunk_rows - 1) / chunk_rows);
-  dim3 grid(nchunks, (unsigned)((Bpad + kSys - 1) / kSys));
+  dim3 grid(nchunks, (unsigned)((Bpad + 15) / 16));
+  const AlphaOut ao = alpha ? *alpha : AlphaOut{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (prec == Prec::F64)
     hipLaunchKernelGGL(k_apply_finish<double>, grid, dim3(256), 0, st, obs_domain, P, ldp, (const double*)T, ldt,
-                       act, nact, sigma, h_ptr, h_idx, h_w, r_var, m, n_state, Bpad, Qv, part, chunk_rows);
+                       act, nact, sigma, h_ptr, h_idx, h_w, r_var, m, n_state, Bpad, Qv, part, chunk_rows, ao);
   else
     hipLaunchKernelGGL(k_apply_finish<float>, grid, dim3(256), 0, st, obs_domain, P, ldp, (const float*)T, ldt, act,
-                       nact, sigma, h_ptr, h_idx, h_w, r_var, m, n_state, Bpad, Qv, part, chunk_rows);
+                       nact, sigma, h_ptr, h_idx, h_w, r_var, m, n_state, Bpad, Qv, part, chunk_rows, ao);
   return hipGetLastError();
 }
 
-hipError_t launch_pcg_dots(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact, int64_t Bpad,
-                           double* part2, hipStream_t st) {
-#define IE_CALL(P) dispatch_dots<P>(s, lmp, act, nact, Bpad, part2, st)
+hipError_t launch_pcg_step(const PCGState& s, const LMP& lmp, int mode, const int32_t* act, const int32_t* nact,
+                           int32_t* act_out, int32_t* nact_out, int64_t Bpad, double tol_rel, hipStream_t st) {
+#define IE_CALL(P) dispatch_step<P>(s, lmp, mode, act, nact, act_out, nact_out, Bpad, tol_rel, st)
   IE_P_SWITCH(lmp.p, IE_CALL)
 #undef IE_CALL
 }
 
-hipError_t launch_pcg_step(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact, int64_t Bpad,
-                           const double* part_pq, double* part2, hipStream_t st) {
-#define IE_CALL(P) dispatch_step<P>(s, lmp, act, nact, Bpad, part_pq, part2, st)
-  IE_P_SWITCH(lmp.p, IE_CALL)
-#undef IE_CALL
-}
-
-hipError_t launch_pcg_direction(const PCGState& s, const LMP& lmp, const int32_t* act, const int32_t* nact,
-                                int64_t Bpad, const double* part2, double tol_rel, int first, int max_iter,
-                                const double* rz_cur, double* rz_next, hipStream_t st) {
-#define IE_CALL(P) dispatch_dir<P>(s, lmp, act, nact, Bpad, part2, tol_rel, first, max_iter, rz_cur, rz_next, st)
+hipError_t launch_pcg_direction(Prec vprec, const PCGState& s, const LMP& lmp, int first, const int32_t* act,
+                                const int32_t* nact, int64_t Bpad, void* V, int64_t ldv, hipStream_t st) {
+#define IE_CALL(P) dispatch_dir<P>(vprec, s, lmp, first, act, nact, Bpad, V, ldv, st)
   IE_P_SWITCH(lmp.p, IE_CALL)
 #undef IE_CALL
 }
@@ -569,8 +673,15 @@ hipError_t launch_axpy_masked(double* x, const double* d, int64_t m, int64_t S, 
   hipLaunchKernelGGL(k_axpy, dim3(nb(m * S)), dim3(256), 0, st, x, d, m, S, ld);
   return hipGetLastError();
 }
-hipError_t launch_col_norms(const double* v, int64_t m, int64_t S, int64_t ld, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_col_norms, dim3((unsigned)((S + kSys - 1) / kSys)), dim3(256), 0, st, v, m, S, ld, out);
+hipError_t launch_col_norms(const double* v, int64_t m, int64_t S, int64_t ld, double* out, double* scratch,
+                            hipStream_t st) {
+  const int chunk = 64;
+  const int nchunks = (int)((m + chunk - 1) / chunk);
+  hipLaunchKernelGGL(k_col_norms_part, dim3(nchunks, (unsigned)((S + 15) / 16)), dim3(256), 0, st, v, m, S, ld, chunk,
+                     scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_norms_fin, dim3(nb(S)), dim3(256), 0, st, scratch, nchunks, S, out);
   return hipGetLastError();
 }
 hipError_t launch_residual_status(const double* rn, const double* bn, double tol, double* relres, int32_t* done,

@@ -124,67 +124,98 @@ __global__ void k_right_mult(const double* __restrict__ A, int64_t lda, int64_t 
   out[r * ldo + j] = acc;
 }
 
-// Cyclic Jacobi eigendecomposition of a small symmetric matrix on one workgroup.
-// T (k x k row-major) is destroyed; evec[a*k + j] = component a of eigenvector j.
+// Jacobi eigendecomposition of a small symmetric matrix on one workgroup with the
+// round-robin (tournament) ordering: each step rotates k/2 disjoint index pairs at
+// once, k-1 steps make a sweep in which every pair is visited once.
+// T (k x k row-major) is read; evec[a*k + j] = component a of eigenvector j.
 __global__ void k_sym_eig(double* T, int k, double* evec, double* evals) {
   __shared__ double A[kMaxSketch * kMaxSketch];
   __shared__ double Vv[kMaxSketch * kMaxSketch];
-  __shared__ double cs[2];
-  __shared__ double offn;
+  __shared__ double cs_c[kMaxSketch / 2], cs_s[kMaxSketch / 2];
+  __shared__ int pp[kMaxSketch / 2], qq[kMaxSketch / 2];
+  __shared__ double red_off[256], red_dia[256];
   const int t = threadIdx.x;
+  const int ke = k + (k & 1);  // even number of players; index k (if odd) is a dummy
+  const int half = ke / 2;
   for (int e = t; e < k * k; e += blockDim.x) {
     A[e] = 0.5 * (T[e] + T[(e % k) * k + e / k]);
     Vv[e] = (e / k == e % k) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    if (t == 0) {
-      double s = 0.0, d = 0.0;
-      for (int a = 0; a < k; ++a)
-        for (int b = 0; b < k; ++b) {
-          if (a != b) s += A[a * k + b] * A[a * k + b];
-          else d += A[a * k + b] * A[a * k + b];
-        }
-      offn = (s <= 1e-30 * d) ? 0.0 : s;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = t; e < k * k; e += blockDim.x) {
+      const double v = A[e] * A[e];
+      if (e / k == e % k) dia += v;
+      else off += v;
     }
+    red_off[t] = off;
+    red_dia[t] = dia;
     __syncthreads();
-    if (offn == 0.0) break;
-    for (int p = 0; p < k - 1; ++p)
-      for (int q = p + 1; q < k; ++q) {
-        if (t == 0) {
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) {
+        red_off[t] += red_off[t + w];
+        red_dia[t] += red_dia[t + w];
+      }
+      __syncthreads();
+    }
+    const bool conv = red_off[0] <= 1e-30 * red_dia[0];
+    __syncthreads();
+    if (conv) break;
+    for (int step = 0; step < ke - 1; ++step) {
+      if (t < half) {
+        // players: slot 0 fixed, slots 1..ke-1 rotate by `step`
+        auto player = [&](int slot) { return slot == 0 ? 0 : 1 + (slot - 1 + step) % (ke - 1); };
+        int p = player(t), q = player(ke - 1 - t);
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
+        double c = 1.0, sn = 0.0;
+        if (q < k) {
           const double apq = A[p * k + q];
-          double c = 1.0, s = 0.0;
           if (apq != 0.0) {
             const double tau = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
             const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + tt * tt);
-            s = tt * c;
-          }
-          cs[0] = c;
-          cs[1] = s;
-        }
-        __syncthreads();
-        const double c = cs[0], s = cs[1];
-        if (s != 0.0) {
-          // rows p, q
-          for (int j = t; j < k; j += blockDim.x) {
-            const double ap = A[p * k + j], aq = A[q * k + j];
-            A[p * k + j] = c * ap - s * aq;
-            A[q * k + j] = s * ap + c * aq;
-          }
-          __syncthreads();
-          // columns p, q and eigenvectors
-          for (int j = t; j < k; j += blockDim.x) {
-            const double ap = A[j * k + p], aq = A[j * k + q];
-            A[j * k + p] = c * ap - s * aq;
-            A[j * k + q] = s * ap + c * aq;
-            const double vp = Vv[j * k + p], vq = Vv[j * k + q];
-            Vv[j * k + p] = c * vp - s * vq;
-            Vv[j * k + q] = s * vp + c * vq;
+            sn = tt * c;
           }
         }
-        __syncthreads();
+        pp[t] = p;
+        qq[t] = (q < k) ? q : p;
+        cs_c[t] = c;
+        cs_s[t] = (q < k) ? sn : 0.0;
       }
+      __syncthreads();
+      // rows p, q of every pair
+      for (int e = t; e < half * k; e += blockDim.x) {
+        const int i = e / k, j = e % k;
+        const double sn = cs_s[i];
+        if (sn == 0.0) continue;
+        const int p = pp[i], q = qq[i];
+        const double c = cs_c[i];
+        const double ap = A[p * k + j], aq = A[q * k + j];
+        A[p * k + j] = c * ap - sn * aq;
+        A[q * k + j] = sn * ap + c * aq;
+      }
+      __syncthreads();
+      // columns p, q of every pair, and the eigenvector columns
+      for (int e = t; e < half * k; e += blockDim.x) {
+        const int i = e / k, j = e % k;
+        const double sn = cs_s[i];
+        if (sn == 0.0) continue;
+        const int p = pp[i], q = qq[i];
+        const double c = cs_c[i];
+        const double ap = A[j * k + p], aq = A[j * k + q];
+        A[j * k + p] = c * ap - sn * aq;
+        A[j * k + q] = sn * ap + c * aq;
+        const double vp = Vv[j * k + p], vq = Vv[j * k + q];
+        Vv[j * k + p] = c * vp - sn * vq;
+        Vv[j * k + q] = sn * vp + c * vq;
+      }
+      __syncthreads();
+    }
   }
   for (int e = t; e < k * k; e += blockDim.x) evec[e] = Vv[e];
   for (int j = t; j < k; j += blockDim.x) evals[j] = A[j * k + j];
@@ -257,7 +288,7 @@ hipError_t launch_right_mult(double* A, int64_t lda, int64_t m, int k, const dou
 }
 
 hipError_t launch_sym_eig(double* T, int k, double* evec, double* evals, hipStream_t st) {
-  hipLaunchKernelGGL(k_sym_eig, dim3(1), dim3(64), 0, st, T, k, evec, evals);
+  hipLaunchKernelGGL(k_sym_eig, dim3(1), dim3(256), 0, st, T, k, evec, evals);
   return hipGetLastError();
 }
 
