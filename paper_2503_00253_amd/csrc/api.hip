@@ -62,6 +62,15 @@ __global__ void k_widen(const float* __restrict__ a, double* __restrict__ b, int
   if (t < count) b[t] = (double)a[t];
 }
 
+// column-major FP64 (ld) -> system-major BF16 (ldk >= n, zero padded)
+__global__ void k_to_bf16_cols(const double* __restrict__ V, int64_t ldv, int64_t n, int64_t ldk, int64_t B,
+                               __hip_bfloat16* __restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ldk * B) return;
+  const int64_t k = t % ldk, b = t / ldk;
+  out[t] = __float2bfloat16(k < n ? (float)V[k + b * ldv] : 0.f);
+}
+
 __global__ void k_positive_check(const double* v, int64_t count, int32_t* flags) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t < count && !(v[t] > 0.0 && isfinite(v[t]))) atomicOr(flags, kFlagBadInput);
@@ -272,7 +281,6 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   IE_CHECK(p == 0 || p + o->oversample <= P->m, INFOESRF_ERR_INVALID_ARG, "n_ritz + oversample must be <= m");
   IE_CHECK(o->precision >= INFOESRF_FP64 && o->precision <= INFOESRF_MIXED_BF16, INFOESRF_ERR_INVALID_ARG,
            "unknown precision");
-  IE_CHECK(o->precision != INFOESRF_MIXED_BF16, INFOESRF_ERR_INVALID_ARG, "BF16 applies are not available yet");
   IE_CHECK(o->solver >= INFOESRF_SOLVER_PLAIN && o->solver <= INFOESRF_SOLVER_PERSISTENT, INFOESRF_ERR_INVALID_ARG,
            "unknown solver");
   IE_CHECK(o->warm_start == INFOESRF_START_ZERO, INFOESRF_ERR_INVALID_ARG, "learned warm start not available yet");
@@ -438,6 +446,12 @@ int tile_for(int requested, int64_t B) {
   if (requested) return requested;
   return B >= 128 ? 32 : 16;
 }
+// BF16 blocks: 16 rows x 128 / 64 / 32 systems by batch size
+int tile_for_bf16(int requested, int64_t B) {
+  if (requested) return requested;
+  return B >= 384 ? 128 : (B >= 96 ? 64 : 16);
+}
+inline int64_t bf16_ld(int64_t rows) { return round_up(rows, 8); }
 // Qout[:, act] = (1 + sigma) Pin[:, act] + S Pin[:, act] with S in precision `prec`;
 // partial dots of Pin^T Qout into part.
 int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* act, const int32_t* nact,
@@ -448,15 +462,27 @@ int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* 
   if (in.obs) {
     // v_ready_ld > 0: the caller already wrote Pin's active columns into the apply buffer with that
     // leading dimension (the PCG direction kernel does)
-    const int64_t ldv = v_ready_ld > 0 ? v_ready_ld : Bpad;
-    if (v_ready_ld <= 0) IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, Bpad, st));
-    const void* Zu = (prec == Prec::F64) ? (const void*)in.Zt : (const void*)in.Zt32;
-    IE_HIP(cov_stencil_timed(prec, in.go, Zu, in.m, in.N, pl.bf.V, ldv, Bpad, nact, pl.bf.T, Bpad,
-                             tile_for(rows_per_wave, Bmax), st));
+    if (prec == Prec::BF16) {
+      const int64_t ldk = bf16_ld(in.m);
+      if (v_ready_ld <= 0) IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, ldk, st));
+      IE_HIP(cov_bf16_timed(in.go, in.Zt32, in.m, in.N, (const __hip_bfloat16*)pl.bf.V, ldk, pl.bf.ldmax, Bpad, nact,
+                            (float*)pl.bf.T, Bpad, tile_for_bf16(rows_per_wave, Bmax), st));
+    } else {
+      const int64_t ldv = v_ready_ld > 0 ? v_ready_ld : Bpad;
+      if (v_ready_ld <= 0) IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, Bpad, st));
+      const void* Zu = (prec == Prec::F64) ? (const void*)in.Zt : (const void*)in.Zt32;
+      IE_HIP(cov_stencil_timed(prec, in.go, Zu, in.m, in.N, pl.bf.V, ldv, Bpad, nact, pl.bf.T, Bpad,
+                               tile_for(rows_per_wave, Bmax), st));
+    }
   } else {
+    const int64_t ldvs = (prec == Prec::BF16) ? bf16_ld(in.n) : Bpad;
     IE_HIP(launch_scatter_state(prec, Pin, ldp, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n, in.m,
-                                Bpad, pl.bf.V, Bpad, st));
-    if (in.dense) {
+                                Bpad, pl.bf.V, ldvs, st));
+    if (prec == Prec::BF16) {
+      IE_CHECK(!in.dense, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
+      IE_HIP(cov_bf16_timed(in.gs, in.Z32, in.n, in.N, (const __hip_bfloat16*)pl.bf.V, ldvs, pl.bf.ldmax, Bpad, nact,
+                            (float*)pl.bf.T, Bpad, tile_for_bf16(rows_per_wave, Bmax), st));
+    } else if (in.dense) {
       IE_CHECK(prec == Prec::F64, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
       IE_HIP(launch_cov_dense(in.P->loc.dense, in.Z, in.n, in.N, (const double*)pl.bf.V, Bpad, Bpad,
                               (double*)pl.bf.T, Bpad, st));
@@ -656,6 +682,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   const int check_every = 4;
   const bool plain = (op.solver == INFOESRF_SOLVER_PLAIN);
   void* Vbuf = in.obs ? pl.bf.V : nullptr;
+  const int64_t vld = (op.inner == Prec::BF16) ? bf16_ld(m) : ld;  // apply-buffer leading dimension
   int32_t h_nact = (int32_t)S;
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
     // outer residual r = b - C u (FP64).  Zero start: the first residual is b itself.
@@ -686,15 +713,15 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
     IE_HIP(launch_pcg_step(ps, lmp, 0, act_c, nact_c, act_n, nact_n, round_up(hint, kSysTile), 1.0, st));
     std::swap(act_c, act_n);
     std::swap(nact_c, nact_n);
-    IE_HIP(launch_pcg_direction(op.inner, ps, lmp, 1, act_c, nact_c, round_up(hint, kSysTile), Vbuf, ld, st));
+    IE_HIP(launch_pcg_direction(op.inner, ps, lmp, 1, act_c, nact_c, round_up(hint, kSysTile), Vbuf, vld, st));
     for (int it = 1; it <= op.max_iter; ++it) {
       const int64_t bp = round_up(hint, kSysTile);
       IE_TRY(apply_S(pl, op.inner, sy.p, ld, act_c, nact_c, bp, sy.sigma, sy.q, sy.part_pq, op.rows_per_wave, st,
-                     &ao, /*v_ready_ld=*/ld));
+                     &ao, /*v_ready_ld=*/vld));
       IE_HIP(launch_pcg_step(ps, lmp, 1, act_c, nact_c, act_n, nact_n, bp, 1.0, st));
       std::swap(act_c, act_n);
       std::swap(nact_c, nact_n);
-      IE_HIP(launch_pcg_direction(op.inner, ps, lmp, 0, act_c, nact_c, bp, Vbuf, ld, st));
+      IE_HIP(launch_pcg_direction(op.inner, ps, lmp, 0, act_c, nact_c, bp, Vbuf, vld, st));
       if (op.host_sync && (it % check_every) == 0) {
         IE_HIP(hipMemcpyAsync(&h_nact, nact_c, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         IE_HIP(hipStreamSynchronize(st));
@@ -872,7 +899,18 @@ int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ld
   } else {
     const infoesrf_loc& L = prob->loc;
     Grid g{L.nz, L.nx, L.periodic_z, L.periodic_x, L.bz, L.bx, L.table, tab32, nullptr};
-    if (low) {
+    if (op.inner == Prec::BF16) {
+      IE_HIP(launch_convert_f32(L.table, tab32, (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1), st));
+      // V is column-major n x B: already system-major; convert to BF16 (ld n) in Ts storage
+      __hip_bfloat16* V16 = reinterpret_cast<__hip_bfloat16*>(Ts);
+      const int64_t ldk = bf16_ld(n);
+      hipLaunchKernelGGL(k_to_bf16_cols, dim3(nb(ldk * B)), dim3(256), 0, st, V, ldv, n, ldk, B, V16);
+      IE_HIP(hipGetLastError());
+      float* T32 = reinterpret_cast<float*>(Vs);
+      IE_HIP(cov_bf16_timed(g, Z32, n, N, V16, ldk, B, B, nullptr, T32, ldb, tile_for_bf16(op.rows_per_wave, B), st));
+      hipLaunchKernelGGL(k_widen, dim3(nb(n * ldb)), dim3(256), 0, st, (const float*)T32, Ts, n * ldb);
+      IE_HIP(hipGetLastError());
+    } else if (low) {
       IE_HIP(launch_convert_f32(L.table, tab32, (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1), st));
       float* V32 = reinterpret_cast<float*>(Ts);  // stage the FP32 input in the output buffer's storage
       IE_HIP(launch_convert_f32(Vs, V32, n * ldb, st));

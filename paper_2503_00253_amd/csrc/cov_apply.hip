@@ -275,6 +275,205 @@ hipError_t launch_rb(int rows_per_wave, const Grid& g, const T* Z, int64_t ldz, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 variant (FP32 accumulation).  The member-dependent factor goes into the A
+// operand, A_i[r, k] = L[r, k] z_i[k] (rounded to BF16 once per fragment), and the
+// B operand is the member-independent BF16 copy of V, so the B fragments are staged
+// once per block and reused by every member:
+//   T_i = A_i V (MFMA, FP32 accumulate),   out[r, b] += z_i[r] T_i[r, b]  (FP32 epilogue).
+// V is stored system-major (column b contiguous in k) so a lane's eight consecutive
+// k of one fragment are one aligned 16-byte LDS read.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+constexpr int kPadB = 48;  // a band-overlapping 16x32 fragment reads up to 46 entries past the band
+
+template <int RB, int SB>
+__global__ __launch_bounds__(256) void k_cov_bf16(Grid g, const float* __restrict__ Z, int64_t ldz, int N,
+                                                  const __hip_bfloat16* __restrict__ V, int64_t ldk, int64_t vcols,
+                                                  int B, const int32_t* __restrict__ Bdev, float* __restrict__ Tout,
+                                                  int64_t ldt, int tiles_per_layer, int KWs, int MC, ProfDev prof) {
+  constexpr int TM = 16 * RB;
+  constexpr int NS = 16 * SB;
+  if (Bdev) B = *Bdev;
+  if (prof.vectors && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    atomicAdd(prof.vectors, (unsigned long long)B);
+    atomicAdd(prof.flops, (double)B * prof.flops_per_vector);
+  }
+  const int b0 = blockIdx.y * NS;
+  if (b0 >= B) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int bx = g.bx, bz = g.bz, nl = 2 * bz + 1;
+  const int tw = 2 * bx + 1 + 2 * kPadB;
+  float* tab = reinterpret_cast<float*>(smem_raw);                    // nl x tw
+  const int tab_sz = (nl * tw + 3) / 4 * 4;
+  __hip_bfloat16* Vs = reinterpret_cast<__hip_bfloat16*>(tab + tab_sz);  // nl x NS x KWs
+  float* Zw = reinterpret_cast<float*>(Vs + (size_t)nl * NS * KWs);     // nl x MC x KWs
+  float* Zr = Zw + (size_t)nl * MC * KWs;                               // MC x TM
+  const int tile = blockIdx.x;
+  const int z = tile / tiles_per_layer;
+  const int x0 = (tile % tiles_per_layer) * TM;
+  const int nx = g.nx, nz = g.nz;
+  const int KW = TM + 2 * bx;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lrow = lane & 15, lk = lane >> 4;
+
+  for (int t = threadIdx.x; t < nl * tw; t += blockDim.x) {
+    const int row = t / tw, c = t % tw - kPadB;
+    tab[t] = (c >= 0 && c <= 2 * bx) ? g.table32[row * (2 * bx + 1) + c] : 0.f;
+  }
+  // member-independent B operand: BF16 V window of every stencil layer
+  for (int t = threadIdx.x; t < nl * NS * KWs; t += blockDim.x) {
+    const int kw = t % KWs, bl = (t / KWs) % NS, li = t / (KWs * NS);
+    int zz = z + li - bz;
+    bool ok = kw < KW && (b0 + bl) < vcols;
+    if (g.pz) zz = wrap_mod(zz, nz);
+    else ok = ok && zz >= 0 && zz < nz;
+    int kx = x0 - bx + kw;
+    if (g.px) kx = wrap_mod(kx, nx);
+    else ok = ok && kx >= 0 && kx < nx;
+    Vs[t] = ok ? V[(int64_t)(b0 + bl) * ldk + (int64_t)zz * nx + kx] : __float2bfloat16(0.f);
+  }
+
+  f4v out[RB][SB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) out[rb][sb] = f4v{0.f, 0.f, 0.f, 0.f};
+  const int nK = KWs / 32;
+
+  for (int m0 = 0; m0 < N; m0 += MC) {
+    const int mcn = min(MC, N - m0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nl * MC * KWs; t += blockDim.x) {
+      const int kw = t % KWs, j = (t / KWs) % MC, li = t / (KWs * MC);
+      int zz = z + li - bz;
+      bool ok = kw < KW && j < mcn;
+      if (g.pz) zz = wrap_mod(zz, nz);
+      else ok = ok && zz >= 0 && zz < nz;
+      int kx = x0 - bx + kw;
+      if (g.px) kx = wrap_mod(kx, nx);
+      else ok = ok && kx >= 0 && kx < nx;
+      Zw[t] = ok ? Z[(int64_t)(m0 + j) * ldz + (int64_t)zz * nx + kx] : 0.f;
+    }
+    for (int t = threadIdx.x; t < MC * TM; t += blockDim.x) {
+      const int j = t / TM, r = t % TM;
+      Zr[t] = (j < mcn && x0 + r < nx) ? Z[(int64_t)(m0 + j) * ldz + (int64_t)z * nx + x0 + r] : 0.f;
+    }
+    __syncthreads();
+    for (int j = wave; j < mcn; j += 4) {
+      f4v acc[RB][SB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) acc[rb][sb] = f4v{0.f, 0.f, 0.f, 0.f};
+      for (int li = 0; li < nl; ++li) {
+        const int zz = z + li - bz;
+        if (!g.pz && (zz < 0 || zz >= nz)) continue;
+        const float* trow = tab + li * tw + kPadB;
+        const float* zrow = Zw + ((size_t)li * MC + j) * KWs;
+        const __hip_bfloat16* vrow = Vs + (size_t)li * NS * KWs;
+        for (int kk = 0; kk < nK; ++kk) {
+          const int kb = 32 * kk + 8 * lk;
+          const f4v za = *reinterpret_cast<const f4v*>(zrow + kb);
+          const f4v zb = *reinterpret_cast<const f4v*>(zrow + kb + 4);
+          bf8 bv[SB];
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb)
+            bv[sb] = *reinterpret_cast<const bf8*>(vrow + (size_t)(16 * sb + lrow) * KWs + kb);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            const int base = 32 * kk - 16 * rb;
+            if (base + 31 >= 0 && base - 15 <= 2 * bx) {
+              const int d0 = base + 8 * lk - lrow;
+              bf8 a;
+              a[0] = (__bf16)(trow[d0 + 0] * za[0]);
+              a[1] = (__bf16)(trow[d0 + 1] * za[1]);
+              a[2] = (__bf16)(trow[d0 + 2] * za[2]);
+              a[3] = (__bf16)(trow[d0 + 3] * za[3]);
+              a[4] = (__bf16)(trow[d0 + 4] * zb[0]);
+              a[5] = (__bf16)(trow[d0 + 5] * zb[1]);
+              a[6] = (__bf16)(trow[d0 + 6] * zb[2]);
+              a[7] = (__bf16)(trow[d0 + 7] * zb[3]);
+#pragma unroll
+              for (int sb = 0; sb < SB; ++sb)
+                acc[rb][sb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv[sb], acc[rb][sb], 0, 0, 0);
+            }
+          }
+        }
+      }
+      // epilogue: out[r, b] += z_j[r] T_j[r, b]; D register v of lane l is row 4(l/16) + v
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float zr = Zr[j * TM + 16 * rb + 4 * lk + v];
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) out[rb][sb][v] += zr * acc[rb][sb][v];
+        }
+    }
+  }
+
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(smem_raw);
+  constexpr int PER = RB * SB * 4;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[((wave * PER) + (rb * SB + sb) * 4 + v) * 64 + lane] = out[rb][sb][v];
+  __syncthreads();
+  for (int f = wave; f < RB * SB; f += 4) {
+    const int rb = f / SB, sb = f % SB;
+    const int b = b0 + 16 * sb + lrow;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float sacc = 0.f;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) sacc += red[((w * PER) + f * 4 + v) * 64 + lane];
+      const int x = x0 + 16 * rb + 4 * lk + v;
+      if (x < nx && b < B) Tout[((int64_t)z * nx + x) * ldt + b] = sacc;
+    }
+  }
+}
+
+template <int RB, int SB>
+size_t smem_bf16(const Grid& g, int KWs, int MC) {
+  constexpr int TM = 16 * RB, NS = 16 * SB;
+  const int nl = 2 * g.bz + 1;
+  const size_t tab = (size_t)((nl * (2 * g.bx + 1 + 2 * kPadB) + 3) / 4 * 4) * 4;
+  const size_t stage = tab + (size_t)nl * NS * KWs * 2 + (size_t)nl * MC * KWs * 4 + (size_t)MC * TM * 4;
+  const size_t red = (size_t)4 * 64 * RB * SB * 4 * 4;
+  return stage > red ? stage : red;
+}
+
+template <int RB, int SB>
+hipError_t launch_bf16_typed(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
+                             int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt,
+                             hipStream_t st, const ProfDev& prof) {
+  constexpr int TM = 16 * RB, NS = 16 * SB;
+  const int tiles_per_layer = (g.nx + TM - 1) / TM;
+  const int ntiles = tiles_per_layer * g.nz;
+  const int KWs = (TM + 2 * g.bx + 31) / 32 * 32;
+  int MC = ((int)N + 3) / 4 * 4;
+  const size_t budget = 96 * 1024;
+  while (MC > 4 && smem_bf16<RB, SB>(g, KWs, MC) > budget) MC -= 4;
+  const size_t smem = smem_bf16<RB, SB>(g, KWs, MC);
+  if (smem > 150 * 1024) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cov_bf16<RB, SB>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  dim3 grid(ntiles, (unsigned)((B + NS - 1) / NS));
+  hipLaunchKernelGGL((k_cov_bf16<RB, SB>), grid, dim3(256), smem, st, g, Z, ldz, (int)N, V, ldk, vcols, (int)B, Bdev,
+                     T, ldt, tiles_per_layer, KWs, MC, prof);
+  return hipGetLastError();
+}
+
 // Dense L (small n, tests): T[r, b] = sum_i z_i[r] sum_k L[r,k] z_i[k] V[k,b]; one thread per (r, b).
 __global__ void k_cov_dense(const double* __restrict__ L, const double* __restrict__ Z, int64_t n, int64_t N,
                             const double* __restrict__ V, int64_t ldv, int64_t B, double* __restrict__ T,
@@ -305,6 +504,20 @@ hipError_t launch_cov_stencil(Prec prec, const Grid& g, const void* Z, int64_t l
     case Prec::F32:
       return launch_rb<float>(rows_per_wave, g, (const float*)Z, ldz, N, (const float*)V, ldv, B, Bdev, (float*)T,
                               ldt, st, pf);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_cov_bf16(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
+                           int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt, int tile,
+                           hipStream_t st, const ProfDev* prof) {
+  if (B <= 0) return hipSuccess;
+  const ProfDev pf = prof ? *prof : ProfDev{nullptr, nullptr, 0.0};
+  switch (tile) {
+    case 16: return launch_bf16_typed<1, 2>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf);
+    case 32: return launch_bf16_typed<2, 2>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf);
+    case 64: return launch_bf16_typed<1, 4>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf);
+    case 128: return launch_bf16_typed<1, 8>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf);
     default: return hipErrorInvalidValue;
   }
 }

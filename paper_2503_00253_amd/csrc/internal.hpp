@@ -116,6 +116,15 @@ struct ProfDev {
 hipError_t launch_cov_stencil(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
                               int64_t ldv, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, int rows_per_wave,
                               hipStream_t st, const ProfDev* prof = nullptr);
+// BF16 apply (FP32 accumulation): Z (FP32, column-major, ldz), V system-major BF16
+// (column b at V + b*ldk, vcols columns allocated), T FP32 system-fastest.  tile selects
+// 16 x 32, 32 x 32, 16 x 64 or 16 x 128 (rows x systems) blocks.
+hipError_t launch_cov_bf16(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
+                           int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt, int tile,
+                           hipStream_t st, const ProfDev* prof = nullptr);
+hipError_t cov_bf16_timed(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
+                          int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt, int tile,
+                          hipStream_t st);
 // Measurement wrapper used by the runtime: records events around the launch when profiling is on.
 hipError_t cov_stencil_timed(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
                              int64_t ldv, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, int rows_per_wave,
@@ -125,6 +134,8 @@ hipError_t launch_cov_dense(const double* L, const double* Z, int64_t n, int64_t
 
 // ---------------------------------------------------------------- observation-space glue
 // Compact copy of active systems into an apply buffer (optionally scaled into state space by H^T R^{-1/2}).
+// FP64/FP32 buffers are system-fastest (element (r, c) at r*ldv + c); BF16 buffers are system-major
+// (element (r, c) at c*ldv + r).
 //   domain OBS:   V[r * ldv + c] = P[r * ldp + act[c]] (converted to the apply precision), zero pad columns.
 //   domain STATE: V[k * ldv + c] = sum_{e in CSC col k} w_e dinv[row_e] P[row_e * ldp + act[c]].
 hipError_t launch_gather_active(Prec prec, const double* P, int64_t ldp, const int32_t* act, const int32_t* nact,

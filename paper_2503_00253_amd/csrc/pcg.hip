@@ -57,6 +57,19 @@ template <>
 __device__ inline double to_prec<double>(double v) { return v; }
 template <>
 __device__ inline float to_prec<float>(double v) { return (float)v; }
+template <>
+__device__ inline __hip_bfloat16 to_prec<__hip_bfloat16>(double v) { return __float2bfloat16((float)v); }
+
+// Index of (row r, column c) in an apply buffer: system-fastest (FP64/FP32 applies) or
+// system-major (BF16 applies, column c contiguous in r).
+template <typename TV>
+__device__ inline int64_t vidx(int64_t r, int64_t c, int64_t ld) {
+  return r * ld + c;
+}
+template <>
+__device__ inline int64_t vidx<__hip_bfloat16>(int64_t r, int64_t c, int64_t ld) {
+  return c * ld + r;
+}
 
 template <typename TV>
 __global__ void k_gather_active(const double* __restrict__ P, int64_t ldp, const int32_t* __restrict__ act,
@@ -66,7 +79,7 @@ __global__ void k_gather_active(const double* __restrict__ P, int64_t ldp, const
   if (t >= rows * Bpad) return;
   const int64_t r = t / Bpad, c = t % Bpad;
   const int32_t na = load_nact(nact, Bpad);
-  V[r * ldv + c] = (c < na) ? to_prec<TV>(P[r * ldp + act[c]]) : TV(0);
+  V[vidx<TV>(r, c, ldv)] = to_prec<TV>((c < na) ? P[r * ldp + act[c]] : 0.0);
 }
 
 template <typename TV>
@@ -87,7 +100,7 @@ __global__ void k_scatter_state(const double* __restrict__ P, int64_t ldp, const
       if (r >= 0 && r < m) acc += w_of[e] / sqrt(r_var[r]) * P[r * ldp + s];
     }
   }
-  V[k * ldv + c] = to_prec<TV>(acc);
+  V[vidx<TV>(k, c, ldv)] = to_prec<TV>(acc);
 }
 
 // q = (1 + sigma_s) p + S p, with S p = T (obs domain) or R^{-1/2} H T (state domain); partial p^T q.
@@ -400,7 +413,7 @@ __global__ __launch_bounds__(256) void k_pcg_direction(PCGState st, LMP lmp, int
     for (int j = 0; j < P; ++j) z -= lmp.SPhi[r * P + j] * cf[cl][j] + lmp.Phi[r * P + j] * cf[cl][P + j];
     const double pn = first ? z : z + beta * st.p[e];
     st.p[e] = pn;
-    if (V) V[r * ldv + c] = to_prec<TV>(pn);
+    if (V) V[vidx<TV>(r, c, ldv)] = to_prec<TV>(pn);
   }
 }
 
@@ -573,8 +586,11 @@ hipError_t dispatch_dir(Prec vp, const PCGState& s, const LMP& lmp, int first, c
   if (vp == Prec::F64)
     hipLaunchKernelGGL((k_pcg_direction<P, double>), grid, dim3(256), 0, st, s, lmp, first, act, nact, (double*)V,
                        ldv);
-  else
+  else if (vp == Prec::F32)
     hipLaunchKernelGGL((k_pcg_direction<P, float>), grid, dim3(256), 0, st, s, lmp, first, act, nact, (float*)V, ldv);
+  else
+    hipLaunchKernelGGL((k_pcg_direction<P, __hip_bfloat16>), grid, dim3(256), 0, st, s, lmp, first, act, nact,
+                       (__hip_bfloat16*)V, ldv);
   return hipGetLastError();
 }
 
@@ -596,9 +612,12 @@ hipError_t launch_gather_active(Prec prec, const double* P, int64_t ldp, const i
   if (prec == Prec::F64)
     hipLaunchKernelGGL(k_gather_active<double>, dim3(nb(rows * Bpad)), dim3(256), 0, st, P, ldp, act, nact, rows,
                        Bpad, (double*)V, ldv);
-  else
+  else if (prec == Prec::F32)
     hipLaunchKernelGGL(k_gather_active<float>, dim3(nb(rows * Bpad)), dim3(256), 0, st, P, ldp, act, nact, rows,
                        Bpad, (float*)V, ldv);
+  else
+    hipLaunchKernelGGL(k_gather_active<__hip_bfloat16>, dim3(nb(rows * Bpad)), dim3(256), 0, st, P, ldp, act, nact,
+                       rows, Bpad, (__hip_bfloat16*)V, ldv);
   return hipGetLastError();
 }
 
@@ -609,9 +628,12 @@ hipError_t launch_scatter_state(Prec prec, const double* P, int64_t ldp, const i
   if (prec == Prec::F64)
     hipLaunchKernelGGL(k_scatter_state<double>, dim3(nb(n * Bpad)), dim3(256), 0, st, P, ldp, act, nact, col_ptr,
                        row_of, w_of, r_var, n, m, Bpad, (double*)V, ldv);
-  else
+  else if (prec == Prec::F32)
     hipLaunchKernelGGL(k_scatter_state<float>, dim3(nb(n * Bpad)), dim3(256), 0, st, P, ldp, act, nact, col_ptr,
                        row_of, w_of, r_var, n, m, Bpad, (float*)V, ldv);
+  else
+    hipLaunchKernelGGL(k_scatter_state<__hip_bfloat16>, dim3(nb(n * Bpad)), dim3(256), 0, st, P, ldp, act, nact,
+                       col_ptr, row_of, w_of, r_var, n, m, Bpad, (__hip_bfloat16*)V, ldv);
   return hipGetLastError();
 }
 

@@ -72,6 +72,23 @@ hipError_t cov_stencil_timed(Prec prec, const Grid& g, const void* Z, int64_t ld
   return hipEventRecord(g_prof.ev[2 * k + 1], st);
 }
 
+hipError_t cov_bf16_timed(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
+                          int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt, int tile,
+                          hipStream_t st) {
+  if (!g_prof.on) return launch_cov_bf16(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, tile, st);
+  hipError_t e;
+  if (g_prof.used == kPairs && (e = drain()) != hipSuccess) return e;
+  const int pi = 2;
+  const double n_g = (double)g.nz * g.nx;
+  ProfDev pd{g_prof.dvec + pi, g_prof.dflops + pi, 2.0 * (double)N * grid_nnz(g) + 3.0 * n_g * (double)N};
+  const size_t k = g_prof.used++;
+  g_prof.ev_prec[k] = pi;
+  if ((e = hipEventRecord(g_prof.ev[2 * k], st)) != hipSuccess) return e;
+  if ((e = launch_cov_bf16(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, tile, st, &pd)) != hipSuccess) return e;
+  g_prof.launches[pi] += 1;
+  return hipEventRecord(g_prof.ev[2 * k + 1], st);
+}
+
 }  // namespace infoesrf
 
 using namespace infoesrf;

@@ -276,3 +276,46 @@ def test_full_size_gaussian_n4096(domain):
     mean_want = ref.mean_update_eig(dp, prob.y)
     mean_got, sm = ie.mean_update(P, prob.y, opts_for(prob, P, domain))
     assert rel(mean_got.cpu().numpy() - dp.mu, mean_want - dp.mu) < 1e-6
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_cov_apply_bf16_stated_bound(case):
+    """BF16 operands, FP32 accumulation: stated bound 1e-2 relative."""
+    prob = CASES[case]()
+    say("cov_apply bf16", case)
+    dp = dense_of(prob)
+    V = np.random.default_rng(4).standard_normal((prob.n, 37))
+    want = dp.P @ V
+    P = ie.Problem.from_synthetic(prob)
+    for tile in (16, 32, 64, 128):
+        got = ie.cov_apply(P, torch.from_numpy(V).cuda(),
+                           ie.default_opts(precision=ie.MIXED_BF16, tile_rows=tile)).cpu().numpy()
+        assert rel(got, want) < 1e-2, (case, tile, rel(got, want))
+
+
+@pytest.mark.parametrize("domain", ["state", "lattice"])
+@pytest.mark.parametrize("case", ["gauss-n256-periodic", "2d-layers"])
+def test_mixed_bf16_meets_fp64_bound(case, domain):
+    prob = CASES[case]()
+    say("mixed bf16", case, domain)
+    dp = dense_of(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    P = ie.Problem.from_synthetic(prob)
+    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, precision=ie.MIXED_BF16))
+    assert st.code == ie.OK
+    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert np.all(st.relres <= 1e-8)
+    assert st.counter(ie.CNT_SWEEPS) >= prob.Q * prob.N
+
+
+def test_mixed_bf16_full_size_lattice():
+    prob = syn.config2()
+    say("mixed bf16 n4096 lattice")
+    dp = dense_of(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    P = ie.Problem.from_synthetic(prob)
+    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, "lattice", precision=ie.MIXED_BF16))
+    assert st.code == ie.OK and np.all(st.relres <= 1e-8)
+    assert rel(got.cpu().numpy(), want) < 1e-6
