@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -60,6 +61,22 @@ __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b,
 __global__ void k_widen(const float* __restrict__ a, double* __restrict__ b, int64_t count) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t < count) b[t] = (double)a[t];
+}
+
+// out[c * ldo + r] = in[c * ldi + r] converted (r < rows); rows <= r < ldo are zeroed when pad != 0
+// and left untouched otherwise (the caller's padding)
+template <typename Tin, typename Tout>
+__global__ void k_convert_cols(const Tin* __restrict__ in, int64_t ldi, int64_t rows, int64_t cols,
+                               Tout* __restrict__ out, int64_t ldo, int pad) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ldo * cols) return;
+  const int64_t c = t / ldo, r = t % ldo;
+  if (r >= rows && !pad) return;
+  const float zero = 0.f;
+  if constexpr (std::is_same<Tout, __hip_bfloat16>::value)
+    out[t] = __float2bfloat16(r < rows ? (float)in[c * ldi + r] : zero);
+  else
+    out[t] = (Tout)(r < rows ? in[c * ldi + r] : (Tin)0);
 }
 
 // column-major FP64 (ld) -> system-major BF16 (ldk >= n, zero padded)
@@ -204,11 +221,14 @@ struct Inst {
   int64_t* counters = nullptr;
 };
 
+// Solver state: observation-space vectors are system-major, system s at s * ldm.
 struct Sys {
-  int64_t S = 0, ld = 0, Bpad = 0;
-  double *b, *u, *x, *r, *p, *q, *bnorm, *rn, *rz0, *rz1, *relres, *rel_in, *sigma, *thresh, *pw;
-  int32_t *iters, *sweeps, *done, *fdone, *act, *nact, *act2, *nact2, *tile_cnt, *glob_cnt;
-  double *part_pq, *part2, *alpha, *coef;
+  int64_t S = 0, ldm = 0, Spad = 0;
+  double *b = nullptr, *u = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+  double *bnorm = nullptr, *rn = nullptr, *rz = nullptr, *relres = nullptr, *rel_in = nullptr, *sigma = nullptr,
+         *thresh = nullptr, *pw = nullptr;
+  int32_t *iters = nullptr, *sweeps = nullptr, *done = nullptr, *fdone = nullptr;
+  int32_t *act = nullptr, *nact = nullptr, *act2 = nullptr, *nact2 = nullptr;
 };
 
 struct Pre {
@@ -219,16 +239,16 @@ struct Pre {
   int32_t *act = nullptr, *nact = nullptr;
 };
 
+// Apply buffers (input V, output T), system-major with leading dimension round_up(rows, 64).
 struct Buf {
   void* V = nullptr;
   void* T = nullptr;
-  int64_t ldmax = 0;  // columns
+  int64_t cols = 0;  // columns allocated
 };
 
 struct Fin {
-  double* ubar = nullptr;  // m x ld_f sysfast (N + 1 columns)
-  int64_t ld = 0;
-  int32_t *act, *nact;
+  double* ubar = nullptr;  // system-major, N (or 1) columns of ldm
+  int32_t *act = nullptr, *nact = nullptr;
 };
 
 struct Plan {
@@ -240,13 +260,15 @@ struct Plan {
   size_t bytes = 0;
 };
 
+inline int64_t ld64(int64_t rows) { return round_up(rows, 64); }
+
 int check_problem(const infoesrf_problem* P) {
   IE_CHECK(P != nullptr, INFOESRF_ERR_INVALID_ARG, "problem is NULL");
   IE_CHECK(P->N >= 2, INFOESRF_ERR_INVALID_ARG, "ensemble size N must be >= 2");
   IE_CHECK(P->m >= 1, INFOESRF_ERR_INVALID_ARG, "observation count m must be >= 1");
   IE_CHECK(P->n >= 1, INFOESRF_ERR_INVALID_ARG, "state dimension n must be >= 1");
-  IE_CHECK(P->n < (1LL << 30) && P->m < (1LL << 30) && P->N < (1LL << 20), INFOESRF_ERR_INVALID_ARG,
-           "dimensions too large");
+  IE_CHECK(P->n < (1LL << 30) && P->N < (1LL << 20), INFOESRF_ERR_INVALID_ARG, "dimensions too large");
+  IE_CHECK(P->m <= 4096, INFOESRF_ERR_INVALID_ARG, "m must be <= 4096 (one workgroup holds a system's vectors)");
   IE_CHECK(P->X && P->h_ptr && P->h_idx && P->h_w && P->r_var, INFOESRF_ERR_INVALID_ARG,
            "X, h_ptr, h_idx, h_w and r_var must be non-NULL");
   const infoesrf_loc& L = P->loc;
@@ -354,9 +376,6 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   }
   in.col_cnt = ar.take<int32_t>(in.n);
   in.col_ptr = ar.take<int32_t>(in.n + 1);
-  // CSC arrays sized by nnz, which lives on the device; bound it by a per-call maximum (see below)
-  in.row_of = nullptr;
-  in.w_of = nullptr;
   in.diagS = ar.take<double>(in.m);
   in.dmin = ar.take<double>(1);
   in.flags = ar.take<int32_t>(1);
@@ -365,51 +384,41 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
 
   Sys& sy = pl.sy;
   sy.S = S;
-  sy.ld = round_up(S, kSysTile);
-  sy.Bpad = sy.ld;
-  const int64_t ms = in.m * sy.ld;
+  sy.ldm = ld64(in.m);
+  sy.Spad = round_up(S, kSysTile);
+  const int64_t ms = sy.ldm * sy.Spad;
   sy.b = ar.take<double>(ms);
   sy.u = ar.take<double>(ms);
   sy.x = ar.take<double>(ms);
   sy.r = ar.take<double>(ms);
   sy.p = ar.take<double>(ms);
   sy.q = ar.take<double>(ms);
-  sy.bnorm = ar.take<double>(sy.ld);
-  sy.rn = ar.take<double>(sy.ld);
-  sy.rz0 = ar.take<double>(sy.ld);
-  sy.rz1 = ar.take<double>(sy.ld);
-  sy.relres = ar.take<double>(sy.ld);
-  sy.rel_in = ar.take<double>(sy.ld);
-  sy.sigma = ar.take<double>(sy.ld);
-  sy.thresh = ar.take<double>(sy.ld);
+  sy.bnorm = ar.take<double>(sy.Spad);
+  sy.rn = ar.take<double>(sy.Spad);
+  sy.rz = ar.take<double>(sy.Spad);
+  sy.relres = ar.take<double>(sy.Spad);
+  sy.rel_in = ar.take<double>(sy.Spad);
+  sy.sigma = ar.take<double>(sy.Spad);
+  sy.thresh = ar.take<double>(sy.Spad);
   sy.pw = ar.take<double>(kMaxQ);
-  sy.iters = ar.take<int32_t>(sy.ld);
-  sy.sweeps = ar.take<int32_t>(sy.ld);
-  sy.done = ar.take<int32_t>(sy.ld);
-  sy.fdone = ar.take<int32_t>(sy.ld);
-  sy.act = ar.take<int32_t>(sy.ld);
+  sy.iters = ar.take<int32_t>(sy.Spad);
+  sy.sweeps = ar.take<int32_t>(sy.Spad);
+  sy.done = ar.take<int32_t>(sy.Spad);
+  sy.fdone = ar.take<int32_t>(sy.Spad);
+  sy.act = ar.take<int32_t>(sy.Spad);
   sy.nact = ar.take<int32_t>(1);
-  sy.act2 = ar.take<int32_t>(sy.ld);
+  sy.act2 = ar.take<int32_t>(sy.Spad);
   sy.nact2 = ar.take<int32_t>(1);
-  sy.tile_cnt = ar.take<int32_t>(round_up(std::max<int64_t>(sy.ld, op.k + 16), 16) / 16 + 16);
-  sy.glob_cnt = ar.take<int32_t>(1);
-  sy.alpha = ar.take<double>(sy.ld);
-  sy.coef = ar.take<double>(sy.ld * (2 * op.p + 1));
-  const int64_t nchunks = (in.m + kChunk - 1) / kChunk;
-  sy.part_pq = ar.take<double>(nchunks * round_up(std::max<int64_t>(sy.ld, op.k + 16), 64));
-  // PCG partial dots (nchunks x ld x (2p+1)) and the column-norm partials (ceil(m/64) x ld) share this buffer
-  sy.part2 = ar.take<double>(std::max<int64_t>(nchunks * round_up(sy.ld, 64) * (2 * op.p + 1),
-                                               ((in.m + 63) / 64) * sy.ld));
 
   Pre& pr = pl.pr;
   pr.k = op.k;
   pr.p = op.p;
   if (op.k > 0) {
     const int64_t kl = round_up(op.k, kSysTile);
-    pr.Om = ar.take<double>(in.m * kl);
-    pr.Y = ar.take<double>(in.m * kl);
-    pr.Qb = ar.take<double>(in.m * kl);
-    pr.SQ = ar.take<double>(in.m * kl);
+    pr.Om = ar.take<double>(sy.ldm * kl);
+    pr.Y = ar.take<double>(sy.ldm * kl);
+    pr.Qb = ar.take<double>(sy.ldm * kl);
+    pr.SQ = ar.take<double>(sy.ldm * kl);
     pr.Tk = ar.take<double>(op.k * op.k);
     pr.evec = ar.take<double>(op.k * op.k);
     pr.evals = ar.take<double>(op.k);
@@ -425,15 +434,15 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
     pr.nact = ar.take<int32_t>(1);
   }
   Fin& fn = pl.fn;
-  fn.ld = round_up(std::max<int64_t>(nfin, 1), kSysTile);
-  fn.ubar = ar.take<double>(in.m * fn.ld);
-  fn.act = ar.take<int32_t>(fn.ld);
+  const int64_t nf = round_up(std::max<int64_t>(nfin, 1), kSysTile);
+  fn.ubar = ar.take<double>(sy.ldm * nf);
+  fn.act = ar.take<int32_t>(nf);
   fn.nact = ar.take<int32_t>(1);
 
   // apply buffers: rows x columns in FP64 (enough for every precision)
-  const int64_t cols = std::max<int64_t>({sy.ld, round_up(op.k, kSysTile), fn.ld, 16});
-  const int64_t rows = std::max<int64_t>(in.n, in.m);
-  pl.bf.ldmax = cols;
+  const int64_t cols = std::max<int64_t>({sy.Spad, round_up(op.k, kSysTile), nf, 16});
+  const int64_t rows = std::max<int64_t>(ld64(in.n), ld64(in.m));
+  pl.bf.cols = cols;
   pl.bf.V = ar.take<double>(rows * cols);
   pl.bf.T = ar.take<double>(rows * cols);
 }
@@ -451,66 +460,66 @@ int tile_for_bf16(int requested, int64_t B) {
   if (requested) return requested;
   return B >= 384 ? 128 : (B >= 96 ? 64 : 16);
 }
-inline int64_t bf16_ld(int64_t rows) { return round_up(rows, 8); }
-// Qout[:, act] = (1 + sigma) Pin[:, act] + S Pin[:, act] with S in precision `prec`;
-// partial dots of Pin^T Qout into part.
+
+// T = S-part of the apply for the listed columns of Pin (system-major, ldp); when Qout is given,
+// Qout[:, s] = (1 + sigma_s) Pin[:, s] + S Pin[:, s] as well.  v_ready: the observation-domain
+// apply buffer already holds the listed columns (written by the fused PCG kernel).  zero_counter
+// (nullable) is set to 0 on the stream before the apply finishes; the stencil kernels do it
+// themselves, which saves a launch per PCG iteration.
 int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* act, const int32_t* nact,
-            int64_t Bmax, const double* sigma, double* Qout, double* part, int rows_per_wave, hipStream_t st,
-            const AlphaOut* alpha = nullptr, int64_t v_ready_ld = 0) {
+            int64_t Bmax, const double* sigma, double* Qout, int rows_per_wave, hipStream_t st,
+            bool v_ready = false, int32_t* zero_counter = nullptr) {
   Inst& in = pl.in;
   const int64_t Bpad = round_up(Bmax, kSysTile);
+  const int64_t rows = in.obs ? in.m : in.n;
+  const int64_t ldr = ld64(rows);
   if (in.obs) {
-    // v_ready_ld > 0: the caller already wrote Pin's active columns into the apply buffer with that
-    // leading dimension (the PCG direction kernel does)
-    if (prec == Prec::BF16) {
-      const int64_t ldk = bf16_ld(in.m);
-      if (v_ready_ld <= 0) IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, ldk, st));
-      IE_HIP(cov_bf16_timed(in.go, in.Zt32, in.m, in.N, (const __hip_bfloat16*)pl.bf.V, ldk, pl.bf.ldmax, Bpad, nact,
-                            (float*)pl.bf.T, Bpad, tile_for_bf16(rows_per_wave, Bmax), st));
-    } else {
-      const int64_t ldv = v_ready_ld > 0 ? v_ready_ld : Bpad;
-      if (v_ready_ld <= 0) IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, Bpad, st));
-      const void* Zu = (prec == Prec::F64) ? (const void*)in.Zt : (const void*)in.Zt32;
-      IE_HIP(cov_stencil_timed(prec, in.go, Zu, in.m, in.N, pl.bf.V, ldv, Bpad, nact, pl.bf.T, Bpad,
-                               tile_for(rows_per_wave, Bmax), st));
-    }
+    if (!v_ready) IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, ldr, st));
   } else {
-    const int64_t ldvs = (prec == Prec::BF16) ? bf16_ld(in.n) : Bpad;
     IE_HIP(launch_scatter_state(prec, Pin, ldp, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n, in.m,
-                                Bpad, pl.bf.V, ldvs, st));
-    if (prec == Prec::BF16) {
-      IE_CHECK(!in.dense, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
-      IE_HIP(cov_bf16_timed(in.gs, in.Z32, in.n, in.N, (const __hip_bfloat16*)pl.bf.V, ldvs, pl.bf.ldmax, Bpad, nact,
-                            (float*)pl.bf.T, Bpad, tile_for_bf16(rows_per_wave, Bmax), st));
-    } else if (in.dense) {
-      IE_CHECK(prec == Prec::F64, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
-      IE_HIP(launch_cov_dense(in.P->loc.dense, in.Z, in.n, in.N, (const double*)pl.bf.V, Bpad, Bpad,
-                              (double*)pl.bf.T, Bpad, st));
-    } else {
-      const void* Zu = (prec == Prec::F64) ? (const void*)in.Z : (const void*)in.Z32;
-      IE_HIP(cov_stencil_timed(prec, in.gs, Zu, in.n, in.N, pl.bf.V, Bpad, Bpad, nact, pl.bf.T, Bpad,
-                               tile_for(rows_per_wave, Bmax), st));
-    }
+                                Bpad, pl.bf.V, ldr, st));
   }
-  IE_HIP(launch_apply_finish(prec, in.obs ? 1 : 0, Pin, ldp, pl.bf.T, Bpad, act, nact, sigma, in.P->h_ptr,
-                             in.P->h_idx, in.P->h_w, in.P->r_var, in.m, in.n, Bpad, Qout, part, kChunk, alpha, st));
+  const Grid& g = in.obs ? in.go : in.gs;
+  if (Bpad == 0 || in.dense) {
+    if (zero_counter) IE_HIP(launch_fill_i32(zero_counter, 0, 1, st));
+    zero_counter = nullptr;
+  }
+  if (prec == Prec::BF16) {
+    IE_CHECK(!in.dense, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
+    const float* Zu = in.obs ? in.Zt32 : in.Z32;
+    IE_HIP(cov_bf16_timed(g, Zu, rows, in.N, (const __hip_bfloat16*)pl.bf.V, ldr, pl.bf.cols, Bpad, nact,
+                          (float*)pl.bf.T, ldr, tile_for_bf16(rows_per_wave, Bmax), st, zero_counter));
+  } else if (in.dense) {
+    IE_CHECK(prec == Prec::F64, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
+    IE_HIP(launch_cov_dense(in.P->loc.dense, in.Z, in.n, in.N, (const double*)pl.bf.V, ldr, Bpad, (double*)pl.bf.T,
+                            ldr, st));
+  } else {
+    const void* Zu = (prec == Prec::F64) ? (in.obs ? (const void*)in.Zt : (const void*)in.Z)
+                                         : (in.obs ? (const void*)in.Zt32 : (const void*)in.Z32);
+    IE_HIP(cov_stencil_timed(prec, g, Zu, rows, in.N, pl.bf.V, ldr, pl.bf.cols, Bpad, nact, pl.bf.T, ldr,
+                             tile_for(rows_per_wave, Bmax), st, zero_counter));
+  }
+  if (Qout)
+    IE_HIP(launch_apply_finish(prec, in.obs ? 1 : 0, Pin, ldp, pl.bf.T, ldr, act, nact, sigma, in.P->h_ptr,
+                               in.P->h_idx, in.P->h_w, in.P->r_var, in.m, in.n, Bpad, Qout, st));
   return 0;
 }
 
-// State-space apply of the m x ncols observation-space vectors U (sysfast, ld):
-// T_state = P H^T R^{-1/2} U, returned in pl.bf.T as n x Bpad sysfast FP64.
+// State-space apply of observation-space columns U (system-major, ld):
+// T_state = P H^T R^{-1/2} U, returned in pl.bf.T (system-major FP64, leading dimension ld64(n)).
 int apply_state(Plan& pl, const double* U, int64_t ld, const int32_t* act, const int32_t* nact, int64_t ncols,
                 int rows_per_wave, hipStream_t st) {
   Inst& in = pl.in;
   const int64_t Bpad = round_up(ncols, kSysTile);
+  const int64_t ldr = ld64(in.n);
   IE_HIP(launch_scatter_state(Prec::F64, U, ld, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n, in.m,
-                              Bpad, pl.bf.V, Bpad, st));
+                              Bpad, pl.bf.V, ldr, st));
   if (in.dense) {
-    IE_HIP(launch_cov_dense(in.P->loc.dense, in.Z, in.n, in.N, (const double*)pl.bf.V, Bpad, ncols,
-                            (double*)pl.bf.T, Bpad, st));
+    IE_HIP(launch_cov_dense(in.P->loc.dense, in.Z, in.n, in.N, (const double*)pl.bf.V, ldr, ncols,
+                            (double*)pl.bf.T, ldr, st));
   } else {
-    IE_HIP(cov_stencil_timed(Prec::F64, in.gs, in.Z, in.n, in.N, pl.bf.V, Bpad, ncols, nullptr, pl.bf.T, Bpad,
-                             tile_for(rows_per_wave, ncols), st));
+    IE_HIP(cov_stencil_timed(Prec::F64, in.gs, in.Z, in.n, in.N, pl.bf.V, ldr, pl.bf.cols, ncols, nullptr, pl.bf.T,
+                             ldr, tile_for(rows_per_wave, ncols), st));
   }
   return 0;
 }
@@ -522,17 +531,9 @@ int read_flags(Plan& pl, hipStream_t st, int32_t* out) {
   return 0;
 }
 
-int flags_to_code(int32_t f) {
-  if (f & kFlagBadInput) return INFOESRF_ERR_INVALID_ARG;
-  if (f & kFlagNumeric) return INFOESRF_ERR_NUMERIC;
-  if (f & kFlagNotSPD) return INFOESRF_ERR_NOT_SPD;
-  return 0;
-}
-
-int stage_setup(Plan& pl, const Options& op, hipStream_t st, int64_t nnz_cap) {
+int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
   Inst& in = pl.in;
   const infoesrf_problem* P = in.P;
-  (void)nnz_cap;
   // 1. validation kernels (they read H only within its own CSR bounds)
   IE_HIP(launch_fill_i32(in.flags, 0, 1, st));
   IE_HIP(launch_fill_i32(in.fallbacks, 0, 1, st));
@@ -585,44 +586,107 @@ int stage_precond(Plan& pl, const Options& op, hipStream_t st) {
   if (pr.p == 0) return 0;
   Inst& in = pl.in;
   const int k = pr.k;
-  const int64_t kl = round_up(k, kSysTile);
+  const int64_t ldm = pl.sy.ldm;
   if (op.sketch) {
-    IE_HIP(launch_to_sysfast(op.sketch, in.m, in.m, k, pr.Om, kl, st));
+    IE_HIP(launch_copy_cols(op.sketch, in.m, in.m, k, pr.Om, ldm, st));
   } else {
-    IE_HIP(launch_fill_f64(pr.Om, 0.0, in.m * kl, st));
-    IE_HIP(launch_sketch(op.seed, in.m, k, pr.Om, kl, st));
+    IE_HIP(launch_fill_f64(pr.Om, 0.0, ldm * k, st));
+    IE_HIP(launch_sketch(op.seed, in.m, k, pr.Om, ldm, st));
   }
   IE_HIP(launch_iota(pr.act, pr.nact, k, st));
-  IE_HIP(launch_fill_f64(pr.sig, -1.0, kl, st));  // (1 + sigma) = 0: pure S
-  double* part = pl.sy.part_pq;
-  IE_TRY(apply_S(pl, Prec::F64, pr.Om, kl, pr.act, pr.nact, k, pr.sig, pr.Y, part, op.rows_per_wave, st));
+  IE_HIP(launch_fill_f64(pr.sig, -1.0, round_up(k, kSysTile), st));  // (1 + sigma) = 0: pure S
+  IE_TRY(apply_S(pl, Prec::F64, pr.Om, ldm, pr.act, pr.nact, k, pr.sig, pr.Y, op.rows_per_wave, st));
   // Cholesky-QR twice: Qb = Y R^{-1}
-  const double* src = pr.Y;
-  double* dst = pr.Qb;
-  for (int pass = 0; pass < 2; ++pass) {
-    IE_HIP(launch_gram(src, kl, src, kl, in.m, k, pr.Rinv, pr.gscr, st));
-    IE_HIP(launch_chol_inv(pr.Rinv, k, in.flags, st));
-    IE_HIP(launch_right_mult(const_cast<double*>(src), kl, in.m, k, pr.Rinv, k, dst, kl, st));
-    if (pass == 0) {
-      src = pr.Qb;
-      dst = pr.Y;
-    }
-  }
-  // after two passes the orthonormal basis is in pr.Y; keep it in Qb
-  hipLaunchKernelGGL(k_copy_f64, dim3(nb(in.m * kl)), dim3(256), 0, st, pr.Y, pr.Qb, in.m * kl);
-  IE_HIP(hipGetLastError());
-  IE_TRY(apply_S(pl, Prec::F64, pr.Qb, kl, pr.act, pr.nact, k, pr.sig, pr.SQ, part, op.rows_per_wave, st));
-  IE_HIP(launch_gram(pr.Qb, kl, pr.SQ, kl, in.m, k, pr.Tk, pr.gscr, st));
+  const Strided Ys{pr.Y, 1, ldm}, Qs{pr.Qb, 1, ldm};
+  IE_HIP(launch_gram(Ys, Ys, in.m, k, pr.Rinv, pr.gscr, st));
+  IE_HIP(launch_chol_inv(pr.Rinv, k, in.flags, st));
+  IE_HIP(launch_right_mult(Ys, in.m, k, pr.Rinv, k, pr.Qb, 1, ldm, st));
+  IE_HIP(launch_gram(Qs, Qs, in.m, k, pr.Rinv, pr.gscr, st));
+  IE_HIP(launch_chol_inv(pr.Rinv, k, in.flags, st));
+  IE_HIP(launch_right_mult(Qs, in.m, k, pr.Rinv, k, pr.Y, 1, ldm, st));
+  IE_HIP(launch_copy_cols(pr.Y, ldm, ldm, k, pr.Qb, ldm, st));
+  IE_TRY(apply_S(pl, Prec::F64, pr.Qb, ldm, pr.act, pr.nact, k, pr.sig, pr.SQ, op.rows_per_wave, st));
+  const Strided SQs{pr.SQ, 1, ldm};
+  IE_HIP(launch_gram(Qs, SQs, in.m, k, pr.Tk, pr.gscr, st));
   IE_HIP(launch_sym_eig(pr.Tk, k, pr.evec, pr.evals, st));
   IE_HIP(launch_lmp_finish(pr.evals, pr.evec, k, pr.p, pr.theta, pr.sel, st));
-  IE_HIP(launch_right_mult(pr.Qb, kl, in.m, k, pr.sel, pr.p, pr.Phi, pr.p, st));
-  IE_HIP(launch_right_mult(pr.SQ, kl, in.m, k, pr.sel, pr.p, pr.SPhi, pr.p, st));
   const int p = pr.p;
-  IE_HIP(launch_gram(pr.Phi, p, pr.Phi, p, in.m, p, pr.G, pr.gscr, st));
-  IE_HIP(launch_gram(pr.Phi, p, pr.SPhi, p, in.m, p, pr.G + p * p, pr.gscr, st));
-  IE_HIP(launch_gram(pr.SPhi, p, pr.SPhi, p, in.m, p, pr.G + 2 * p * p, pr.gscr, st));
+  IE_HIP(launch_right_mult(Qs, in.m, k, pr.sel, p, pr.Phi, p, 1, st));    // row-major m x p
+  IE_HIP(launch_right_mult(SQs, in.m, k, pr.sel, p, pr.SPhi, p, 1, st));
+  const Strided Ph{pr.Phi, p, 1}, SPh{pr.SPhi, p, 1};
+  IE_HIP(launch_gram(Ph, Ph, in.m, p, pr.G, pr.gscr, st));
+  IE_HIP(launch_gram(Ph, SPh, in.m, p, pr.G + p * p, pr.gscr, st));
+  IE_HIP(launch_gram(SPh, SPh, in.m, p, pr.G + 2 * p * p, pr.gscr, st));
   return 0;
 }
+
+// Non-blocking convergence poll.  The host copies the device's live-system count into pinned
+// memory behind an event every few iterations and reads it once the event has completed, so the
+// stream never drains while the host waits.  At most kDepth copies are in flight; when that many
+// are pending the host waits for the oldest, which bounds how far launches run ahead of the
+// device (iterations enqueued after convergence find an empty list and return at once).
+class LivePoll {
+ public:
+  static constexpr int kDepth = 2;
+  ~LivePoll() {
+    // copies still in flight target the thread's pinned words: let them land first
+    for (int i = 0; i < pending_; ++i) (void)hipEventSynchronize(ev_[(head_ + i) % kDepth]);
+    for (auto& e : ev_)
+      if (e) (void)hipEventDestroy(e);
+  }
+  int init() {
+    words_ = pinned_words();
+    IE_CHECK(words_ != nullptr, INFOESRF_ERR_HIP, "pinned host allocation failed");
+    for (auto& e : ev_) IE_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return 0;
+  }
+  // Enqueue a copy of *count; blocks for the oldest copy when kDepth are in flight.
+  // Returns 1 (and sets *value) when a copy has been read, 0 when none has, <0 on error.
+  int post(const int32_t* count, hipStream_t st, int32_t* value) {
+    int got = 0;
+    if (pending_ == kDepth) {
+      const int slot = head_ % kDepth;
+      IE_HIP(hipEventSynchronize(ev_[slot]));
+      *value = words_[slot];
+      ++head_;
+      --pending_;
+      got = 1;
+    }
+    const int slot = (head_ + pending_) % kDepth;
+    IE_HIP(hipMemcpyAsync(&words_[slot], count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    IE_HIP(hipEventRecord(ev_[slot], st));
+    ++pending_;
+    return got;
+  }
+  // Read every copy that has already landed, without blocking.
+  int drain(int32_t* value) {
+    int got = 0;
+    while (pending_ > 0) {
+      const int slot = head_ % kDepth;
+      const hipError_t e = hipEventQuery(ev_[slot]);
+      if (e == hipErrorNotReady) break;
+      IE_HIP(e);
+      *value = words_[slot];
+      ++head_;
+      --pending_;
+      got = 1;
+    }
+    return got;
+  }
+
+ private:
+  // One pinned block per host thread, kept for the thread's lifetime (calls on one thread are
+  // sequential; calls on different threads do not share it).
+  static int32_t* pinned_words() {
+    static thread_local int32_t* words = nullptr;
+    if (!words && hipHostMalloc((void**)&words, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+      words = nullptr;
+    return words;
+  }
+  int32_t* words_ = nullptr;
+  hipEvent_t ev_[kDepth] = {};
+  int head_ = 0, pending_ = 0;
+};
 
 LMP lmp_of(Plan& pl) {
   LMP l{};
@@ -637,100 +701,106 @@ LMP lmp_of(Plan& pl) {
 
 // Iterative refinement around batched PCG.  Solves (1 + sigma_s) u_s + S u_s = b_s for all s.
 // Outer sweeps form the true residual r = b - C u in FP64; the inner PCG (apply precision
-// op.inner) solves C d = r to the per-system target and u += d.
+// op.inner) solves C d = r to the per-system target and u += d.  One inner iteration is two
+// launches: the covariance apply on the active columns, and the fused PCG kernel.
 int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   Inst& in = pl.in;
   Sys& sy = pl.sy;
-  const int64_t S = sy.S, ld = sy.ld, m = in.m;
+  const int64_t S = sy.S, ldm = sy.ldm, m = in.m;
+  const int64_t flat = S * ldm;
   const LMP lmp = lmp_of(pl);
   const bool fp64_inner = (op.inner == Prec::F64);
   PCGState ps{};
   ps.m = m;
   ps.S = S;
-  ps.ld = ld;
+  ps.ld = ldm;
   ps.x = sy.x;
   ps.r = sy.r;
   ps.p = sy.p;
-  ps.q = sy.q;
   ps.sigma = sy.sigma;
-  ps.rz = sy.rz0;
-  ps.alpha = sy.alpha;
-  ps.coef = sy.coef;
+  ps.rz = sy.rz;
   ps.thresh = sy.thresh;
   ps.bnorm = sy.bnorm;
   ps.relres = sy.rel_in;
   ps.iters = sy.iters;
   ps.done = sy.done;
   ps.flags = in.flags;
-  ps.tile_cnt = sy.tile_cnt;
-  ps.glob_cnt = sy.glob_cnt;
-  ps.part = sy.part2;
-  ps.chunk_rows = kChunk;
-  ps.nchunks = (int)((m + kChunk - 1) / kChunk);
   ps.max_iter = op.max_iter;
-  AlphaOut ao{sy.rz0, sy.alpha, sy.done, in.flags, sy.tile_cnt};
 
-  IE_HIP(launch_fill_i32(sy.tile_cnt, 0, round_up(std::max<int64_t>(ld, pl.pr.k + 16), 16) / 16 + 16, st));
-  IE_HIP(launch_fill_i32(sy.glob_cnt, 0, 1, st));
-  IE_HIP(launch_col_norms(sy.b, m, S, ld, sy.bnorm, sy.part2, st));
-  IE_HIP(launch_fill_f64(sy.u, 0.0, m * ld, st));
-  IE_HIP(launch_fill_i32(sy.iters, 0, ld, st));
-  IE_HIP(launch_fill_i32(sy.sweeps, 0, ld, st));
-  IE_HIP(launch_fill_i32(sy.fdone, 0, ld, st));
+  IE_HIP(launch_col_norms(sy.b, m, S, ldm, sy.bnorm, st));
+  IE_HIP(launch_fill_f64(sy.u, 0.0, flat, st));
+  IE_HIP(launch_fill_i32(sy.iters, 0, sy.Spad, st));
+  IE_HIP(launch_fill_i32(sy.sweeps, 0, sy.Spad, st));
+  IE_HIP(launch_fill_i32(sy.fdone, 0, sy.Spad, st));
 
   const int max_sweeps = op.host_sync ? 40 : (fp64_inner ? 2 : (op.inner == Prec::F32 ? 4 : 10));
   const int check_every = 4;
   const bool plain = (op.solver == INFOESRF_SOLVER_PLAIN);
   void* Vbuf = in.obs ? pl.bf.V : nullptr;
-  const int64_t vld = (op.inner == Prec::BF16) ? bf16_ld(m) : ld;  // apply-buffer leading dimension
+  const int64_t ldr = ld64(in.obs ? in.m : in.n);
   int32_t h_nact = (int32_t)S;
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
     // outer residual r = b - C u (FP64).  Zero start: the first residual is b itself.
     if (sweep == 0) {
-      hipLaunchKernelGGL(k_copy_f64, dim3(nb(m * ld)), dim3(256), 0, st, sy.b, sy.r, m * ld);
+      hipLaunchKernelGGL(k_copy_f64, dim3(nb(flat)), dim3(256), 0, st, sy.b, sy.r, flat);
       IE_HIP(hipGetLastError());
     } else {
       IE_HIP(launch_compact(sy.fdone, S, sy.act, sy.nact, st));
-      IE_TRY(apply_S(pl, Prec::F64, sy.u, ld, sy.act, sy.nact, S, sy.sigma, sy.q, sy.part_pq, op.rows_per_wave, st));
-      IE_HIP(launch_sub(sy.b, sy.q, sy.r, m, S, ld, st));
+      IE_TRY(apply_S(pl, Prec::F64, sy.u, ldm, sy.act, sy.nact, S, sy.sigma, sy.q, op.rows_per_wave, st));
+      IE_HIP(launch_sub(sy.b, sy.q, sy.r, flat, st));
     }
-    IE_HIP(launch_col_norms(sy.r, m, S, ld, sy.rn, sy.part2, st));
+    IE_HIP(launch_col_norms(sy.r, m, S, ldm, sy.rn, st));
     hipLaunchKernelGGL(k_sweep_status, dim3(nb(S)), dim3(256), 0, st, sy.rn, sy.bnorm, op.rtol, op.inner_rtol,
                        fp64_inner ? 1 : 0, sy.iters, op.max_iter, sy.relres, sy.fdone, sy.done, sy.thresh,
                        sy.sweeps, sweep > 0 ? 1 : 0, S, in.flags);
     IE_HIP(hipGetLastError());
-    IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
+    if (plain) IE_HIP(launch_iota(sy.act, sy.nact, S, st));
+    else IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
     if (op.host_sync) {
-      IE_HIP(hipMemcpyAsync(&h_nact, sy.nact, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      IE_HIP(launch_compact(sy.done, S, sy.act2, sy.nact2, st));
+      IE_HIP(hipMemcpyAsync(&h_nact, sy.nact2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       IE_HIP(hipStreamSynchronize(st));
       if (h_nact == 0) break;
     }
     if (sweep == max_sweeps) break;
     // inner PCG on C d = r from d = 0
-    IE_HIP(launch_fill_f64(sy.x, 0.0, m * ld, st));
+    IE_HIP(launch_fill_f64(sy.x, 0.0, flat, st));
     int32_t *act_c = sy.act, *nact_c = sy.nact, *act_n = sy.act2, *nact_n = sy.nact2;
     int64_t hint = plain ? S : (int64_t)h_nact;  // upper bound of the live count on the device
-    IE_HIP(launch_pcg_step(ps, lmp, 0, act_c, nact_c, act_n, nact_n, round_up(hint, kSysTile), 1.0, st));
+    IE_HIP(launch_fill_i32(nact_n, 0, 1, st));
+    IE_HIP(launch_pcg_fused(op.inner, ps, lmp, 0, in.obs ? 1 : 0, plain ? 1 : 0, nullptr, ldr, act_c, nact_c, act_n,
+                            nact_n, round_up(hint, kSysTile), Vbuf, ldr, in.P->h_ptr, in.P->h_idx, in.P->h_w,
+                            in.P->r_var, in.n, st));
     std::swap(act_c, act_n);
     std::swap(nact_c, nact_n);
-    IE_HIP(launch_pcg_direction(op.inner, ps, lmp, 1, act_c, nact_c, round_up(hint, kSysTile), Vbuf, vld, st));
+    LivePoll poll;
+    if (op.host_sync) IE_TRY(poll.init());
     for (int it = 1; it <= op.max_iter; ++it) {
       const int64_t bp = round_up(hint, kSysTile);
-      IE_TRY(apply_S(pl, op.inner, sy.p, ld, act_c, nact_c, bp, sy.sigma, sy.q, sy.part_pq, op.rows_per_wave, st,
-                     &ao, /*v_ready_ld=*/vld));
-      IE_HIP(launch_pcg_step(ps, lmp, 1, act_c, nact_c, act_n, nact_n, bp, 1.0, st));
+      // the apply also clears the list counter that the fused kernel fills
+      IE_TRY(apply_S(pl, op.inner, sy.p, ldm, act_c, nact_c, bp, sy.sigma, nullptr, op.rows_per_wave, st,
+                     /*v_ready=*/in.obs, nact_n));
+      IE_HIP(launch_pcg_fused(op.inner, ps, lmp, 1, in.obs ? 1 : 0, plain ? 1 : 0, pl.bf.T, ldr, act_c, nact_c, act_n,
+                              nact_n, bp, Vbuf, ldr, in.P->h_ptr, in.P->h_idx, in.P->h_w, in.P->r_var, in.n, st));
       std::swap(act_c, act_n);
       std::swap(nact_c, nact_n);
-      IE_HIP(launch_pcg_direction(op.inner, ps, lmp, 0, act_c, nact_c, bp, Vbuf, vld, st));
-      if (op.host_sync && (it % check_every) == 0) {
-        IE_HIP(hipMemcpyAsync(&h_nact, nact_c, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        IE_HIP(hipStreamSynchronize(st));
-        if (h_nact == 0) break;
-        if (!plain) hint = h_nact;
+      if (op.host_sync) {
+        // counts only shrink, so any earlier count bounds the current one
+        int32_t seen = 0;
+        int got = poll.drain(&seen);
+        IE_TRY(got);
+        if (!got && (it % check_every) == 0) {
+          got = poll.post(nact_c, st, &seen);
+          IE_TRY(got);
+        }
+        if (got) {
+          if (seen == 0) break;
+          if (!plain) hint = seen;
+        }
       }
     }
     // u += d for every system (d = 0 where the system was not active)
-    IE_HIP(launch_axpy_masked(sy.u, sy.x, m, S, ld, st));
+    IE_HIP(launch_axpy(sy.u, sy.x, flat, st));
   }
   return 0;
 }
@@ -763,9 +833,8 @@ int finish_status(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t ex
   return code;
 }
 
-// nnz of H (device) is needed to size the CSC arrays: read h_ptr[m] once.  This is the
-// only read-back a call does before its kernels when host_sync == 1; with host_sync == 0
-// the caller's nnz must not exceed m * 64 (the reserved maximum).
+// nnz of H (device) sizes the CSC arrays: the reserved maximum is 64 entries per row on average;
+// with host_sync == 1 h_ptr[m] is read and checked against it.
 int64_t nnz_bound(const infoesrf_problem* P) { return P->m * 64; }
 
 int plan_for(Plan& pl, const infoesrf_problem* P, const Options& op, int64_t S, int64_t nfin, void* ws,
@@ -853,15 +922,15 @@ size_t infoesrf_cov_apply_workspace_bytes(const infoesrf_problem* prob, int64_t 
   if (check_problem(prob) < 0) return 0;
   Options op;
   if (resolve_options(prob, opts, op) < 0) return 0;
-  const int64_t ldb = round_up(std::max<int64_t>(B, 1), kSysTile);
+  const int64_t cols = std::max<int64_t>(B, 1);
+  const int64_t ldr = ld64(prob->n);
   Arena ar;
   ar.take<double>(prob->n);                  // mu
   ar.take<double>(prob->n * prob->N);        // Z
   ar.take<float>(prob->n * prob->N);         // Z32
   ar.take<float>((2 * prob->loc.bz + 1) * (2 * prob->loc.bx + 1));
-  ar.take<double>(prob->n * ldb);            // V
-  ar.take<double>(prob->n * ldb);            // T
-  ar.take<int32_t>(1);
+  ar.take<float>(ldr * cols);                // low-precision V
+  ar.take<float>(ldr * cols);                // FP32 T
   return ar.off + 256;
 }
 
@@ -880,52 +949,49 @@ int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ld
   IE_CHECK(ws_bytes >= need, INFOESRF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t n = prob->n, N = prob->N;
-  const int64_t ldb = round_up(B, kSysTile);
+  const int64_t ldr = ld64(n);
   Arena ar;
   ar.base = static_cast<char*>(ws);
   double* mu = ar.take<double>(n);
   double* Z = ar.take<double>(n * N);
   float* Z32 = ar.take<float>(n * N);
   float* tab32 = ar.take<float>((2 * prob->loc.bz + 1) * (2 * prob->loc.bx + 1));
-  double* Vs = ar.take<double>(n * ldb);
-  double* Ts = ar.take<double>(n * ldb);
-  int32_t* flags = ar.take<int32_t>(1);
+  void* Vlow = ar.take<float>(ldr * B);
+  float* T32 = ar.take<float>(ldr * B);
   const bool low = op.inner != Prec::F64;
   IE_HIP(launch_ens_stats(prob->X, n, N, mu, Z, low ? Z32 : nullptr, st));
-  IE_HIP(launch_to_sysfast(V, ldv, n, B, Vs, ldb, st));
   if (prob->loc.kind == INFOESRF_LOC_DENSE) {
     IE_CHECK(!low, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
-    IE_HIP(launch_cov_dense(prob->loc.dense, Z, n, N, Vs, ldb, B, Ts, ldb, st));
+    IE_HIP(launch_cov_dense(prob->loc.dense, Z, n, N, V, ldv, B, PV, ldpv, st));
   } else {
     const infoesrf_loc& L = prob->loc;
     Grid g{L.nz, L.nx, L.periodic_z, L.periodic_x, L.bz, L.bx, L.table, tab32, nullptr};
-    if (op.inner == Prec::BF16) {
-      IE_HIP(launch_convert_f32(L.table, tab32, (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1), st));
-      // V is column-major n x B: already system-major; convert to BF16 (ld n) in Ts storage
-      __hip_bfloat16* V16 = reinterpret_cast<__hip_bfloat16*>(Ts);
-      const int64_t ldk = bf16_ld(n);
-      hipLaunchKernelGGL(k_to_bf16_cols, dim3(nb(ldk * B)), dim3(256), 0, st, V, ldv, n, ldk, B, V16);
-      IE_HIP(hipGetLastError());
-      float* T32 = reinterpret_cast<float*>(Vs);
-      IE_HIP(cov_bf16_timed(g, Z32, n, N, V16, ldk, B, B, nullptr, T32, ldb, tile_for_bf16(op.rows_per_wave, B), st));
-      hipLaunchKernelGGL(k_widen, dim3(nb(n * ldb)), dim3(256), 0, st, (const float*)T32, Ts, n * ldb);
-      IE_HIP(hipGetLastError());
-    } else if (low) {
-      IE_HIP(launch_convert_f32(L.table, tab32, (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1), st));
-      float* V32 = reinterpret_cast<float*>(Ts);  // stage the FP32 input in the output buffer's storage
-      IE_HIP(launch_convert_f32(Vs, V32, n * ldb, st));
-      float* T32 = reinterpret_cast<float*>(Vs);
-      IE_HIP(cov_stencil_timed(Prec::F32, g, Z32, n, N, V32, ldb, B, nullptr, T32, ldb, tile_for(op.rows_per_wave, B),
-                               st));
-      // widen T32 (in Vs storage) into Ts
-      hipLaunchKernelGGL(k_widen, dim3(nb(n * ldb)), dim3(256), 0, st, (const float*)T32, Ts, n * ldb);
-      IE_HIP(hipGetLastError());
+    if (!low) {
+      // column-major V and PV are system-major apply buffers already
+      IE_HIP(cov_stencil_timed(Prec::F64, g, Z, n, N, V, ldv, B, B, nullptr, PV, ldpv,
+                               tile_for(op.rows_per_wave, B), st));
     } else {
-      IE_HIP(cov_stencil_timed(Prec::F64, g, Z, n, N, Vs, ldb, B, nullptr, Ts, ldb, tile_for(op.rows_per_wave, B), st));
+      IE_HIP(launch_convert_f32(L.table, tab32, (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1), st));
+      if (op.inner == Prec::BF16) {
+        __hip_bfloat16* V16 = static_cast<__hip_bfloat16*>(Vlow);
+        hipLaunchKernelGGL((k_convert_cols<double, __hip_bfloat16>), dim3(nb(ldr * B)), dim3(256), 0, st, V, ldv, n,
+                           B, V16, ldr, 1);
+        IE_HIP(hipGetLastError());
+        IE_HIP(cov_bf16_timed(g, Z32, n, N, V16, ldr, B, B, nullptr, T32, ldr, tile_for_bf16(op.rows_per_wave, B),
+                              st));
+      } else {
+        float* V32 = static_cast<float*>(Vlow);
+        hipLaunchKernelGGL((k_convert_cols<double, float>), dim3(nb(ldr * B)), dim3(256), 0, st, V, ldv, n, B, V32,
+                           ldr, 1);
+        IE_HIP(hipGetLastError());
+        IE_HIP(cov_stencil_timed(Prec::F32, g, Z32, n, N, V32, ldr, B, B, nullptr, T32, ldr,
+                                 tile_for(op.rows_per_wave, B), st));
+      }
+      hipLaunchKernelGGL((k_convert_cols<float, double>), dim3(nb(ldpv * B)), dim3(256), 0, st, T32, ldr, n, B, PV,
+                         ldpv, 0);
+      IE_HIP(hipGetLastError());
     }
   }
-  IE_HIP(launch_from_sysfast(Ts, ldb, n, B, PV, ldpv, st));
-  (void)flags;
   if (op.host_sync) IE_HIP(hipStreamSynchronize(st));
   return INFOESRF_OK;
 }
@@ -942,18 +1008,18 @@ int infoesrf_mean_update(const infoesrf_problem* prob, const double* y, double* 
   Plan pl;
   IE_TRY(plan_for(pl, prob, op, 1, 1, ws, ws_bytes));
   IE_TRY(check_nnz(prob, op, st));
-  IE_TRY(stage_setup(pl, op, st, 0));
+  IE_TRY(stage_setup(pl, op, st));
   Sys& sy = pl.sy;
-  IE_HIP(launch_fill_f64(sy.b, 0.0, pl.in.m * sy.ld, st));
+  IE_HIP(launch_fill_f64(sy.b, 0.0, sy.ldm * sy.Spad, st));
   IE_HIP(launch_innovation(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, y, pl.in.mu, pl.in.m, pl.in.n, sy.b,
-                           sy.ld, 0, st));
-  IE_HIP(launch_fill_f64(sy.sigma, 0.0, sy.ld, st));
+                           sy.ldm, 0, st));
+  IE_HIP(launch_fill_f64(sy.sigma, 0.0, sy.Spad, st));
   IE_TRY(stage_precond(pl, op, st));
   IE_TRY(stage_solve(pl, op, st));
   // mean_a = mu + P H^T R^{-1/2} u0
   IE_HIP(launch_iota(pl.fn.act, pl.fn.nact, 1, st));
-  IE_TRY(apply_state(pl, sy.u, sy.ld, pl.fn.act, pl.fn.nact, 1, op.rows_per_wave, st));
-  IE_HIP(launch_final_mean(pl.in.mu, (const double*)pl.bf.T, round_up(1, kSysTile), pl.in.n, 0, mean_a, st));
+  IE_TRY(apply_state(pl, sy.u, sy.ldm, pl.fn.act, pl.fn.nact, 1, op.rows_per_wave, st));
+  IE_HIP(launch_final_mean(pl.in.mu, (const double*)pl.bf.T, ld64(pl.in.n), pl.in.n, 0, mean_a, st));
   return finish_status(pl, op, stats, 2 * pl.pr.k + 1, st);
 }
 
@@ -983,23 +1049,23 @@ int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const 
   Plan pl;
   IE_TRY(plan_for(pl, prob, op, S, N, ws, ws_bytes));
   IE_TRY(check_nnz(prob, op, st));
-  IE_TRY(stage_setup(pl, op, st, 0));
+  IE_TRY(stage_setup(pl, op, st));
   Sys& sy = pl.sy;
-  IE_HIP(launch_fill_f64(sy.b, 0.0, pl.in.m * sy.ld, st));
-  IE_HIP(launch_obs_rhs(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, pl.in.Z, pl.in.n, N, pl.in.m, sy.b, sy.ld,
+  IE_HIP(launch_fill_f64(sy.b, 0.0, sy.ldm * sy.Spad, st));
+  IE_HIP(launch_obs_rhs(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, pl.in.Z, pl.in.n, N, pl.in.m, sy.b, sy.ldm,
                         0, S, st));
-  IE_HIP(launch_fill_f64(sy.sigma, 0.0, sy.ld, st));
+  IE_HIP(launch_fill_f64(sy.sigma, 0.0, sy.Spad, st));
   hipLaunchKernelGGL(k_set_nodes, dim3(nb(std::max<int64_t>(S, kMaxQ))), dim3(256), 0, st, nd, Q, N, sy.sigma, sy.pw,
                      (int64_t)0, 0.0);
   IE_HIP(hipGetLastError());
   IE_TRY(stage_precond(pl, op, st));
   IE_TRY(stage_solve(pl, op, st));
   // u_bar_i = sum_q p_q u_{q,i}; Xa_pert = sqrt(N-1) (Z - P H^T R^{-1/2} U_bar)
-  IE_HIP(launch_quad_combine(sy.u, sy.ld, pl.in.m, N, Q, sy.pw, pl.fn.ubar, pl.fn.ld, 0, st));
+  IE_HIP(launch_quad_combine(sy.u, sy.ldm, pl.in.m, N, Q, sy.pw, pl.fn.ubar, sy.ldm, 0, st));
   IE_HIP(launch_iota(pl.fn.act, pl.fn.nact, N, st));
-  IE_TRY(apply_state(pl, pl.fn.ubar, pl.fn.ld, pl.fn.act, pl.fn.nact, N, op.rows_per_wave, st));
-  IE_HIP(launch_final_pert(pl.in.Z, (const double*)pl.bf.T, round_up(N, kSysTile), pl.in.n, N,
-                           std::sqrt((double)(N - 1)), Xa_pert, st));
+  IE_TRY(apply_state(pl, pl.fn.ubar, sy.ldm, pl.fn.act, pl.fn.nact, N, op.rows_per_wave, st));
+  IE_HIP(launch_final_pert(pl.in.Z, (const double*)pl.bf.T, ld64(pl.in.n), pl.in.n, N, std::sqrt((double)(N - 1)),
+                           Xa_pert, st));
   return finish_status(pl, op, stats, 2 * pl.pr.k + N, st);
 }
 

@@ -84,18 +84,21 @@ constexpr int vpad() { return 64 / (int)sizeof(T); }
 // members) at a time, so the LDS footprint does not grow with the stencil.
 template <typename T, int RB, int SB>
 __global__ __launch_bounds__(256) void k_cov_stencil(Grid g, const T* __restrict__ Z, int64_t ldz, int N,
-                                                     const T* __restrict__ V, int64_t ldv, int B,
+                                                     const T* __restrict__ V, int64_t ldv, int64_t vcols, int B,
                                                      const int32_t* __restrict__ Bdev, T* __restrict__ Tout,
                                                      int64_t ldt, int tiles_per_layer, int KC, int MC,
-                                                     ProfDev prof) {
+                                                     ProfDev prof, int32_t* __restrict__ zero_counter) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int TM = 16 * RB;
   constexpr int NS = 16 * SB;
   constexpr int VS = NS + vpad<T>();
   if (Bdev) B = *Bdev;  // active-system count produced on the device
-  if (prof.vectors && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    atomicAdd(prof.vectors, (unsigned long long)B);
-    atomicAdd(prof.flops, (double)B * prof.flops_per_vector);
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (zero_counter) *zero_counter = 0;  // list counter of the next PCG step (nobody reads it now)
+    if (prof.vectors) {
+      atomicAdd(prof.vectors, (unsigned long long)B);
+      atomicAdd(prof.flops, (double)B * prof.flops_per_vector);
+    }
   }
   const int b0 = blockIdx.y * NS;
   if (b0 >= B) return;
@@ -107,6 +110,7 @@ __global__ __launch_bounds__(256) void k_cov_stencil(Grid g, const T* __restrict
   T* Vw = tab + (2 * bz + 1) * tw;  // KC x VS
   T* Zw = Vw + KC * VS;             // MC x KC
   T* Zr = Zw + MC * KC;             // MC x TM
+  int* kxs = reinterpret_cast<int*>(Zr + MC * TM);  // KC: wrapped x of each chunk row, -1 outside
 
   const T* gtab = table_ptr<T>(g);
   for (int t = threadIdx.x; t < (2 * bz + 1) * tw; t += blockDim.x) {
@@ -150,24 +154,33 @@ __global__ __launch_bounds__(256) void k_cov_stencil(Grid g, const T* __restrict
       const int64_t lay = (int64_t)zz * nx;
       for (int k0 = 0; k0 < KW; k0 += KC) {
         __syncthreads();
-        // stage V rows k0..k0+KC of the K-window (systems b0..b0+NS) and the matching Z rows
-        for (int t = threadIdx.x; t < KC * NS; t += blockDim.x) {
-          const int kl = t / NS, c = t % NS;
+        for (int kl = threadIdx.x; kl < KC; kl += blockDim.x) {
           const int kw = k0 + kl;
           int kx = x0 - bx + kw;
-          bool ok = kw < KW && b0 + c < ldv;  // columns past the buffer width are not read
+          bool ok = kw < KW;
           if (g.px) kx = wrap_mod(kx, nx);
           else ok = ok && kx >= 0 && kx < nx;
-          Vw[kl * VS + c] = ok ? V[(lay + kx) * ldv + b0 + c] : T(0);
+          kxs[kl] = ok ? kx : -1;
         }
-        for (int t = threadIdx.x; t < MC * KC; t += blockDim.x) {
-          const int j = t / KC, kl = t % KC;
-          const int kw = k0 + kl;
-          int kx = x0 - bx + kw;
-          bool ok = kw < KW && j < mcn;
-          if (g.px) kx = wrap_mod(kx, nx);
-          else ok = ok && kx >= 0 && kx < nx;
-          Zw[t] = ok ? Z[(int64_t)(m0 + j) * ldz + lay + kx] : T(0);
+        __syncthreads();
+        // stage V rows k0..k0+KC of the K-window (systems b0..b0+NS; V is system-major, so the
+        // lanes of a wavefront read consecutive k of one column) and the matching Z rows
+        const int lw = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int c = wv; c < NS; c += 4) {
+          const bool colok = b0 + c < vcols;  // columns past the buffer width are not read
+          const T* vcol = V + (int64_t)(b0 + c) * ldv + lay;
+          for (int kl = lw; kl < KC; kl += 64) {
+            const int kx = kxs[kl];
+            Vw[kl * VS + c] = (colok && kx >= 0) ? vcol[kx] : T(0);
+          }
+        }
+        for (int j = wv; j < MC; j += 4) {
+          const bool jok = j < mcn;
+          const T* zcol = Z + (int64_t)(m0 + (jok ? j : 0)) * ldz + lay;
+          for (int kl = lw; kl < KC; kl += 64) {
+            const int kx = kxs[kl];
+            Zw[j * KC + kl] = (jok && kx >= 0) ? zcol[kx] : T(0);
+          }
         }
         __syncthreads();
         const int kk0 = k0 >> 2;
@@ -220,7 +233,7 @@ __global__ __launch_bounds__(256) void k_cov_stencil(Grid g, const T* __restrict
 #pragma unroll
       for (int w = 0; w < 4; ++w) s += red[((w * PER) + f * 4 + v) * 64 + lane];
       const int x = x0 + 16 * rb + Mfma<T>::out_row(lane, v);
-      if (x < nx && b < B) Tout[((int64_t)z * nx + x) * ldt + b] = s;
+      if (x < nx && b < B) Tout[(int64_t)b * ldt + (int64_t)z * nx + x] = s;
     }
   }
 }
@@ -228,14 +241,16 @@ __global__ __launch_bounds__(256) void k_cov_stencil(Grid g, const T* __restrict
 template <typename T, int RB, int SB>
 size_t smem_bytes(const Grid& g, int KC, int MC) {
   constexpr int TM = 16 * RB, NS = 16 * SB, VS = NS + vpad<T>();
-  const size_t stage = (size_t)KC * VS + (size_t)MC * KC + (size_t)MC * TM;
+  const size_t stage = (size_t)KC * VS + (size_t)MC * KC + (size_t)MC * TM +
+                       ((size_t)KC * sizeof(int) + sizeof(T) - 1) / sizeof(T);
   const size_t red = (size_t)4 * 64 * RB * SB * 4;
   return sizeof(T) * ((size_t)(2 * g.bz + 1) * (2 * g.bx + 1 + 2 * kPad) + (stage > red ? stage : red));
 }
 
 template <typename T, int RB, int SB>
-hipError_t launch_typed(const Grid& g, const T* Z, int64_t ldz, int64_t N, const T* V, int64_t ldv, int64_t B,
-                        const int32_t* Bdev, T* Tout, int64_t ldt, hipStream_t st, const ProfDev& prof) {
+hipError_t launch_typed(const Grid& g, const T* Z, int64_t ldz, int64_t N, const T* V, int64_t ldv, int64_t vcols,
+                        int64_t B, const int32_t* Bdev, T* Tout, int64_t ldt, hipStream_t st, const ProfDev& prof,
+                        int32_t* zero_counter) {
   constexpr int TM = 16 * RB, NS = 16 * SB;
   const int tiles_per_layer = (g.nx + TM - 1) / TM;
   const int ntiles = tiles_per_layer * g.nz;
@@ -257,20 +272,21 @@ hipError_t launch_typed(const Grid& g, const T* Z, int64_t ldz, int64_t N, const
     attr_set = true;
   }
   dim3 grid(ntiles, (unsigned)((B + NS - 1) / NS));
-  hipLaunchKernelGGL((k_cov_stencil<T, RB, SB>), grid, dim3(256), smem, st, g, Z, ldz, (int)N, V, ldv, (int)B, Bdev,
-                     Tout, ldt, tiles_per_layer, KC, MC, prof);
+  hipLaunchKernelGGL((k_cov_stencil<T, RB, SB>), grid, dim3(256), smem, st, g, Z, ldz, (int)N, V, ldv, vcols, (int)B,
+                     Bdev, Tout, ldt, tiles_per_layer, KC, MC, prof, zero_counter);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_rb(int rows_per_wave, const Grid& g, const T* Z, int64_t ldz, int64_t N, const T* V, int64_t ldv,
-                     int64_t B, const int32_t* Bdev, T* Tout, int64_t ldt, hipStream_t st, const ProfDev& pf) {
-  // rows_per_wave selects the tile: 16 -> 16 rows x 32 systems, 32 -> 32 x 32, 64 -> 64 x 16
+                     int64_t vcols, int64_t B, const int32_t* Bdev, T* Tout, int64_t ldt, hipStream_t st,
+                     const ProfDev& pf, int32_t* zc) {
+  // rows_per_wave selects the tile: 16 -> 16 rows x 32 systems, 32 -> 32 x 32, 64 -> 64 x 16, 128 -> 64 x 32
   switch (rows_per_wave) {
-    case 16: return launch_typed<T, 1, 2>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
-    case 32: return launch_typed<T, 2, 2>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
-    case 64: return launch_typed<T, 4, 1>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
-    case 128: return launch_typed<T, 4, 2>(g, Z, ldz, N, V, ldv, B, Bdev, Tout, ldt, st, pf);
+    case 16: return launch_typed<T, 1, 2>(g, Z, ldz, N, V, ldv, vcols, B, Bdev, Tout, ldt, st, pf, zc);
+    case 32: return launch_typed<T, 2, 2>(g, Z, ldz, N, V, ldv, vcols, B, Bdev, Tout, ldt, st, pf, zc);
+    case 64: return launch_typed<T, 4, 1>(g, Z, ldz, N, V, ldv, vcols, B, Bdev, Tout, ldt, st, pf, zc);
+    case 128: return launch_typed<T, 4, 2>(g, Z, ldz, N, V, ldv, vcols, B, Bdev, Tout, ldt, st, pf, zc);
     default: return hipErrorInvalidValue;
   }
 }
@@ -292,13 +308,17 @@ template <int RB, int SB>
 __global__ __launch_bounds__(256) void k_cov_bf16(Grid g, const float* __restrict__ Z, int64_t ldz, int N,
                                                   const __hip_bfloat16* __restrict__ V, int64_t ldk, int64_t vcols,
                                                   int B, const int32_t* __restrict__ Bdev, float* __restrict__ Tout,
-                                                  int64_t ldt, int tiles_per_layer, int KWs, int MC, ProfDev prof) {
+                                                  int64_t ldt, int tiles_per_layer, int KWs, int MC, ProfDev prof,
+                                                  int32_t* __restrict__ zero_counter) {
   constexpr int TM = 16 * RB;
   constexpr int NS = 16 * SB;
   if (Bdev) B = *Bdev;
-  if (prof.vectors && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    atomicAdd(prof.vectors, (unsigned long long)B);
-    atomicAdd(prof.flops, (double)B * prof.flops_per_vector);
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (zero_counter) *zero_counter = 0;  // list counter of the next PCG step (nobody reads it now)
+    if (prof.vectors) {
+      atomicAdd(prof.vectors, (unsigned long long)B);
+      atomicAdd(prof.flops, (double)B * prof.flops_per_vector);
+    }
   }
   const int b0 = blockIdx.y * NS;
   if (b0 >= B) return;
@@ -310,6 +330,7 @@ __global__ __launch_bounds__(256) void k_cov_bf16(Grid g, const float* __restric
   __hip_bfloat16* Vs = reinterpret_cast<__hip_bfloat16*>(tab + tab_sz);  // nl x NS x KWs
   float* Zw = reinterpret_cast<float*>(Vs + (size_t)nl * NS * KWs);     // nl x MC x KWs
   float* Zr = Zw + (size_t)nl * MC * KWs;                               // MC x TM
+  int* kxs = reinterpret_cast<int*>(Zr + MC * TM);                      // nl x KWs: source index, -1 outside
   const int tile = blockIdx.x;
   const int z = tile / tiles_per_layer;
   const int x0 = (tile % tiles_per_layer) * TM;
@@ -322,17 +343,30 @@ __global__ __launch_bounds__(256) void k_cov_bf16(Grid g, const float* __restric
     const int row = t / tw, c = t % tw - kPadB;
     tab[t] = (c >= 0 && c <= 2 * bx) ? g.table32[row * (2 * bx + 1) + c] : 0.f;
   }
-  // member-independent B operand: BF16 V window of every stencil layer
-  for (int t = threadIdx.x; t < nl * NS * KWs; t += blockDim.x) {
-    const int kw = t % KWs, bl = (t / KWs) % NS, li = t / (KWs * NS);
-    int zz = z + li - bz;
-    bool ok = kw < KW && (b0 + bl) < vcols;
-    if (g.pz) zz = wrap_mod(zz, nz);
-    else ok = ok && zz >= 0 && zz < nz;
-    int kx = x0 - bx + kw;
-    if (g.px) kx = wrap_mod(kx, nx);
-    else ok = ok && kx >= 0 && kx < nx;
-    Vs[t] = ok ? V[(int64_t)(b0 + bl) * ldk + (int64_t)zz * nx + kx] : __float2bfloat16(0.f);
+  // source state index (layer offset + wrapped x) of every window position of every stencil layer
+  for (int li = 0; li < nl; ++li)
+    for (int kw = threadIdx.x; kw < KWs; kw += blockDim.x) {
+      int zz = z + li - bz;
+      bool ok = kw < KW;
+      if (g.pz) zz = wrap_mod(zz, nz);
+      else ok = ok && zz >= 0 && zz < nz;
+      int kx = x0 - bx + kw;
+      if (g.px) kx = wrap_mod(kx, nx);
+      else ok = ok && kx >= 0 && kx < nx;
+      kxs[li * KWs + kw] = ok ? zz * nx + kx : -1;
+    }
+  __syncthreads();
+  // member-independent B operand: BF16 V window of every stencil layer (a wavefront per column)
+  for (int r = wave; r < nl * NS; r += 4) {
+    const int li = r / NS, bl = r % NS;
+    const bool colok = (b0 + bl) < vcols;
+    const __hip_bfloat16* vcol = V + (int64_t)(b0 + bl) * ldk;
+    const int* ks = kxs + li * KWs;
+    __hip_bfloat16* dst = Vs + (size_t)r * KWs;
+    for (int kw = lane; kw < KWs; kw += 64) {
+      const int k = ks[kw];
+      dst[kw] = (colok && k >= 0) ? vcol[k] : __float2bfloat16(0.f);
+    }
   }
 
   f4v out[RB][SB];
@@ -345,16 +379,16 @@ __global__ __launch_bounds__(256) void k_cov_bf16(Grid g, const float* __restric
   for (int m0 = 0; m0 < N; m0 += MC) {
     const int mcn = min(MC, N - m0);
     __syncthreads();
-    for (int t = threadIdx.x; t < nl * MC * KWs; t += blockDim.x) {
-      const int kw = t % KWs, j = (t / KWs) % MC, li = t / (KWs * MC);
-      int zz = z + li - bz;
-      bool ok = kw < KW && j < mcn;
-      if (g.pz) zz = wrap_mod(zz, nz);
-      else ok = ok && zz >= 0 && zz < nz;
-      int kx = x0 - bx + kw;
-      if (g.px) kx = wrap_mod(kx, nx);
-      else ok = ok && kx >= 0 && kx < nx;
-      Zw[t] = ok ? Z[(int64_t)(m0 + j) * ldz + (int64_t)zz * nx + kx] : 0.f;
+    for (int r = wave; r < nl * MC; r += 4) {
+      const int li = r / MC, j = r % MC;
+      const bool jok = j < mcn;
+      const float* zcol = Z + (int64_t)(m0 + (jok ? j : 0)) * ldz;
+      const int* ks = kxs + li * KWs;
+      float* dst = Zw + (size_t)r * KWs;
+      for (int kw = lane; kw < KWs; kw += 64) {
+        const int k = ks[kw];
+        dst[kw] = (jok && k >= 0) ? zcol[k] : 0.f;
+      }
     }
     for (int t = threadIdx.x; t < MC * TM; t += blockDim.x) {
       const int j = t / TM, r = t % TM;
@@ -433,7 +467,7 @@ __global__ __launch_bounds__(256) void k_cov_bf16(Grid g, const float* __restric
 #pragma unroll
       for (int w = 0; w < 4; ++w) sacc += red[((w * PER) + f * 4 + v) * 64 + lane];
       const int x = x0 + 16 * rb + 4 * lk + v;
-      if (x < nx && b < B) Tout[((int64_t)z * nx + x) * ldt + b] = sacc;
+      if (x < nx && b < B) Tout[(int64_t)b * ldt + (int64_t)z * nx + x] = sacc;
     }
   }
 }
@@ -443,7 +477,8 @@ size_t smem_bf16(const Grid& g, int KWs, int MC) {
   constexpr int TM = 16 * RB, NS = 16 * SB;
   const int nl = 2 * g.bz + 1;
   const size_t tab = (size_t)((nl * (2 * g.bx + 1 + 2 * kPadB) + 3) / 4 * 4) * 4;
-  const size_t stage = tab + (size_t)nl * NS * KWs * 2 + (size_t)nl * MC * KWs * 4 + (size_t)MC * TM * 4;
+  const size_t stage = tab + (size_t)nl * NS * KWs * 2 + (size_t)nl * MC * KWs * 4 + (size_t)MC * TM * 4 +
+                       (size_t)nl * KWs * 4;
   const size_t red = (size_t)4 * 64 * RB * SB * 4 * 4;
   return stage > red ? stage : red;
 }
@@ -451,7 +486,7 @@ size_t smem_bf16(const Grid& g, int KWs, int MC) {
 template <int RB, int SB>
 hipError_t launch_bf16_typed(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
                              int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt,
-                             hipStream_t st, const ProfDev& prof) {
+                             hipStream_t st, const ProfDev& prof, int32_t* zero_counter) {
   constexpr int TM = 16 * RB, NS = 16 * SB;
   const int tiles_per_layer = (g.nx + TM - 1) / TM;
   const int ntiles = tiles_per_layer * g.nz;
@@ -470,11 +505,12 @@ hipError_t launch_bf16_typed(const Grid& g, const float* Z, int64_t ldz, int64_t
   }
   dim3 grid(ntiles, (unsigned)((B + NS - 1) / NS));
   hipLaunchKernelGGL((k_cov_bf16<RB, SB>), grid, dim3(256), smem, st, g, Z, ldz, (int)N, V, ldk, vcols, (int)B, Bdev,
-                     T, ldt, tiles_per_layer, KWs, MC, prof);
+                     T, ldt, tiles_per_layer, KWs, MC, prof, zero_counter);
   return hipGetLastError();
 }
 
-// Dense L (small n, tests): T[r, b] = sum_i z_i[r] sum_k L[r,k] z_i[k] V[k,b]; one thread per (r, b).
+// Dense L (small n, tests): T[r, b] = sum_i z_i[r] sum_k L[r,k] z_i[k] V[k,b]; one thread per (r, b);
+// V and T system-major.
 __global__ void k_cov_dense(const double* __restrict__ L, const double* __restrict__ Z, int64_t n, int64_t N,
                             const double* __restrict__ V, int64_t ldv, int64_t B, double* __restrict__ T,
                             int64_t ldt) {
@@ -484,40 +520,40 @@ __global__ void k_cov_dense(const double* __restrict__ L, const double* __restri
   double acc = 0.0;
   for (int64_t i = 0; i < N; ++i) {
     double inner = 0.0;
-    for (int64_t k = 0; k < n; ++k) inner += L[r + k * n] * Z[k + i * n] * V[k * ldv + b];
+    for (int64_t k = 0; k < n; ++k) inner += L[r + k * n] * Z[k + i * n] * V[b * ldv + k];
     acc += Z[r + i * n] * inner;
   }
-  T[r * ldt + b] = acc;
+  T[b * ldt + r] = acc;
 }
 
 }  // namespace
 
 hipError_t launch_cov_stencil(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
-                              int64_t ldv, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, int rows_per_wave,
-                              hipStream_t st, const ProfDev* prof) {
+                              int64_t ldv, int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt,
+                              int rows_per_wave, hipStream_t st, const ProfDev* prof, int32_t* zero_counter) {
   if (B <= 0) return hipSuccess;
   const ProfDev pf = prof ? *prof : ProfDev{nullptr, nullptr, 0.0};
   switch (prec) {
     case Prec::F64:
-      return launch_rb<double>(rows_per_wave, g, (const double*)Z, ldz, N, (const double*)V, ldv, B, Bdev,
-                               (double*)T, ldt, st, pf);
+      return launch_rb<double>(rows_per_wave, g, (const double*)Z, ldz, N, (const double*)V, ldv, vcols, B, Bdev,
+                               (double*)T, ldt, st, pf, zero_counter);
     case Prec::F32:
-      return launch_rb<float>(rows_per_wave, g, (const float*)Z, ldz, N, (const float*)V, ldv, B, Bdev, (float*)T,
-                              ldt, st, pf);
+      return launch_rb<float>(rows_per_wave, g, (const float*)Z, ldz, N, (const float*)V, ldv, vcols, B, Bdev,
+                              (float*)T, ldt, st, pf, zero_counter);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_cov_bf16(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
                            int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt, int tile,
-                           hipStream_t st, const ProfDev* prof) {
+                           hipStream_t st, const ProfDev* prof, int32_t* zc) {
   if (B <= 0) return hipSuccess;
   const ProfDev pf = prof ? *prof : ProfDev{nullptr, nullptr, 0.0};
   switch (tile) {
-    case 16: return launch_bf16_typed<1, 2>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf);
-    case 32: return launch_bf16_typed<2, 2>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf);
-    case 64: return launch_bf16_typed<1, 4>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf);
-    case 128: return launch_bf16_typed<1, 8>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf);
+    case 16: return launch_bf16_typed<1, 2>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf, zc);
+    case 32: return launch_bf16_typed<2, 2>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf, zc);
+    case 64: return launch_bf16_typed<1, 4>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf, zc);
+    case 128: return launch_bf16_typed<1, 8>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf, zc);
     default: return hipErrorInvalidValue;
   }
 }

@@ -114,21 +114,21 @@ __global__ void k_csc_sort(const int32_t* __restrict__ col_ptr, int64_t n, int32
   }
 }
 
-// rhs[r, s] = dinv_r * sum_e w_e Z[idx_e, i], i = (s - s0) % N
+// rhs[s * ld + r] = dinv_r * sum_e w_e Z[idx_e, i], i = (s - s0) % N
 __global__ void k_obs_rhs(const int32_t* __restrict__ h_ptr, const int32_t* __restrict__ h_idx,
                           const double* __restrict__ h_w, const double* __restrict__ r_var,
                           const double* __restrict__ Z, int64_t n, int64_t N, int64_t m, double* __restrict__ rhs,
                           int64_t ld, int64_t s0, int64_t cnt) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= m * cnt) return;
-  const int64_t r = t / cnt, c = t % cnt;
+  const int64_t c = t / m, r = t % m;
   const int64_t i = c % N;
   double acc = 0.0;
   for (int32_t e = h_ptr[r]; e < h_ptr[r + 1]; ++e) {
     const int32_t j = h_idx[e];
     if (j >= 0 && j < n) acc += h_w[e] * Z[j + i * n];  // invalid indices are flagged elsewhere
   }
-  rhs[r * ld + s0 + c] = acc / sqrt(r_var[r]);
+  rhs[(s0 + c) * ld + r] = acc / sqrt(r_var[r]);
 }
 
 __global__ void k_innovation(const int32_t* __restrict__ h_ptr, const int32_t* __restrict__ h_idx,
@@ -142,7 +142,7 @@ __global__ void k_innovation(const int32_t* __restrict__ h_ptr, const int32_t* _
     const int32_t j = h_idx[e];
     if (j >= 0 && j < n) hm += h_w[e] * mu[j];
   }
-  out[r * ld + s] = (y[r] - hm) / sqrt(r_var[r]);
+  out[s * ld + r] = (y[r] - hm) / sqrt(r_var[r]);
 }
 
 __device__ inline int32_t wrap_offset(int32_t d, int32_t len, int32_t periodic) {

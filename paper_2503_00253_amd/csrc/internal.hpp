@@ -74,13 +74,13 @@ hipError_t launch_csc_build(const int32_t* h_ptr, const int32_t* h_idx, const do
                             int32_t* col_cnt, int32_t* col_ptr, int32_t* row_of, double* w_of, int32_t* flags,
                             hipStream_t st);
 
-// rhs[r, s] = dinv[r] * sum_e h_w[e] * Z[h_idx[e], member(s)] for systems s in [s0, s0+cnt),
-// member(s) = (s - s0) % N  (layout: rhs[r * ld + s]).
+// rhs[s * ld + r] = dinv[r] * sum_e h_w[e] * Z[h_idx[e], member(s)] for systems s in [s0, s0+cnt),
+// member(s) = (s - s0) % N.
 hipError_t launch_obs_rhs(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, const double* r_var,
                           const double* Z, int64_t n, int64_t N, int64_t m, double* rhs, int64_t ld, int64_t s0,
                           int64_t cnt, hipStream_t st);
 
-// innovation rhs: out[r * ld + s] = dinv[r] * (y[r] - sum_e h_w[e] mu[h_idx[e]])
+// innovation rhs: out[s * ld + r] = dinv[r] * (y[r] - sum_e h_w[e] mu[h_idx[e]])
 hipError_t launch_innovation(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, const double* r_var,
                              const double* y, const double* mu, int64_t m, int64_t n, double* out, int64_t ld,
                              int64_t s, hipStream_t st);
@@ -101,8 +101,10 @@ hipError_t launch_convert_f32(const double* in, float* out, int64_t count, hipSt
 hipError_t launch_convert_bf16(const double* in, __hip_bfloat16* out, int64_t count, hipStream_t st);
 
 // ---------------------------------------------------------------- covariance apply (K3)
-// T[k * ldt + b] = sum_i Z[k,i] sum_l L[k,l] Z[l,i] V[l * ldv + b] for b < B (B padded to 16 in V).
-// Z is column-major with leading dimension ldz.  V and T are "system-fastest".
+// Layout convention of the whole solver: every family of vectors (PCG state, apply inputs V
+// and outputs T) is system-major: element (row r, system/column c) at c * ld + r.
+// T[b * ldt + k] = sum_i Z[k,i] sum_l L[k,l] Z[l,i] V[b * ldv + l] for b < B.
+// Z is column-major with leading dimension ldz; vcols = columns allocated in V.
 struct CovTile {
   int rows_per_wave;  // multiple of 16
 };
@@ -113,54 +115,43 @@ struct ProfDev {
   double flops_per_vector;
 };
 // B is the (padded) maximum column count; Bdev (nullable) holds the live count on the device.
+// zero_counter (nullable) is set to 0 by the launch (the next PCG step's list counter).
 hipError_t launch_cov_stencil(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
-                              int64_t ldv, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, int rows_per_wave,
-                              hipStream_t st, const ProfDev* prof = nullptr);
+                              int64_t ldv, int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt,
+                              int rows_per_wave, hipStream_t st, const ProfDev* prof = nullptr,
+                              int32_t* zero_counter = nullptr);
 // BF16 apply (FP32 accumulation): Z (FP32, column-major, ldz), V system-major BF16
 // (column b at V + b*ldk, vcols columns allocated), T FP32 system-fastest.  tile selects
 // 16 x 32, 32 x 32, 16 x 64 or 16 x 128 (rows x systems) blocks.
 hipError_t launch_cov_bf16(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
                            int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt, int tile,
-                           hipStream_t st, const ProfDev* prof = nullptr);
+                           hipStream_t st, const ProfDev* prof = nullptr, int32_t* zero_counter = nullptr);
 hipError_t cov_bf16_timed(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
                           int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt, int tile,
-                          hipStream_t st);
+                          hipStream_t st, int32_t* zero_counter = nullptr);
 // Measurement wrapper used by the runtime: records events around the launch when profiling is on.
 hipError_t cov_stencil_timed(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
-                             int64_t ldv, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, int rows_per_wave,
-                             hipStream_t st);
+                             int64_t ldv, int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt,
+                             int rows_per_wave, hipStream_t st, int32_t* zero_counter = nullptr);
 hipError_t launch_cov_dense(const double* L, const double* Z, int64_t n, int64_t N, const double* V, int64_t ldv,
                             int64_t B, double* T, int64_t ldt, hipStream_t st);
 
 // ---------------------------------------------------------------- observation-space glue
-// Compact copy of active systems into an apply buffer (optionally scaled into state space by H^T R^{-1/2}).
-// FP64/FP32 buffers are system-fastest (element (r, c) at r*ldv + c); BF16 buffers are system-major
-// (element (r, c) at c*ldv + r).
-//   domain OBS:   V[r * ldv + c] = P[r * ldp + act[c]] (converted to the apply precision), zero pad columns.
-//   domain STATE: V[k * ldv + c] = sum_{e in CSC col k} w_e dinv[row_e] P[row_e * ldp + act[c]].
+// Active-system lists: act[c] = system of apply column c, *nact = live count (device).
+// gather (observation domain): V[c * ldv + r] = P[act[c] * ldp + r] in the apply precision.
 hipError_t launch_gather_active(Prec prec, const double* P, int64_t ldp, const int32_t* act, const int32_t* nact,
-                                int64_t rows, int64_t Bpad, void* V, int64_t ldv, hipStream_t st);
+                                int64_t rows, int64_t Bmax, void* V, int64_t ldv, hipStream_t st);
+// scatter (state domain): V[c * ldv + k] = sum_{e in CSC col k} w_e r^{-1/2}_{row_e} P[act[c] * ldp + row_e].
 hipError_t launch_scatter_state(Prec prec, const double* P, int64_t ldp, const int32_t* act, const int32_t* nact,
                                 const int32_t* col_ptr, const int32_t* row_of, const double* w_of,
-                                const double* r_var, int64_t n, int64_t m, int64_t Bpad, void* V, int64_t ldv,
+                                const double* r_var, int64_t n, int64_t m, int64_t Bmax, void* V, int64_t ldv,
                                 hipStream_t st);
-// With an AlphaOut the last block of each column tile also forms alpha_s = rz_s / p^T q for the
-// listed systems (retiring any whose curvature is not positive).
-struct AlphaOut {
-  const double* rz;
-  double* alpha;
-  int32_t* done;
-  int32_t* flags;
-  int32_t* tile_cnt;  // zero on entry; left zero
-};
-// Q[r, s] = c_s * P[r, s] + (domain OBS ? T[r, c] : dinv_r sum_e w_e T[idx_e, c]), s = act[c],
-// c_s = (1 + sigma_s) (sigma_s = shift of system s; sigma = -1 gives S itself),
-// plus per-(chunk, c) partial dot products P^T Q written to part[chunk * Bpad + c].
+// Q[s * ldp + r] = (1 + sigma_s) P[s * ldp + r] + (obs ? T[c * ldt + r] : r_r^{-1/2} sum_e w_e T[c * ldt + idx_e]),
+// s = act[c] (sigma = -1 gives S itself).  T is FP64 for FP64 applies, FP32 otherwise.
 hipError_t launch_apply_finish(Prec prec, int obs_domain, const double* P, int64_t ldp, const void* T, int64_t ldt,
                                const int32_t* act, const int32_t* nact, const double* sigma, const int32_t* h_ptr,
                                const int32_t* h_idx, const double* h_w, const double* r_var, int64_t m,
-                               int64_t n_state, int64_t Bpad, double* Qv, double* part, int chunk_rows,
-                               const AlphaOut* alpha, hipStream_t st);
+                               int64_t n_state, int64_t Bmax, double* Qv, hipStream_t st);
 
 // ---------------------------------------------------------------- PCG (K4)
 struct LMP {
@@ -173,33 +164,29 @@ struct LMP {
 };
 
 struct PCGState {
-  int64_t m, S, ld;      // rows, systems, leading dim (>= S, multiple of 16)
-  double *x, *r, *p, *q; // iterate, residual, direction, C p
+  int64_t m, S, ld;      // rows, systems, leading dimension (system s at s * ld)
+  double *x, *r, *p;     // iterate, residual, search direction
   const double* sigma;   // per-system shift
   double* rz;            // per system r^T z
-  double* alpha;         // per system step length
-  double* coef;          // per system (2p+1): c1, gamma, beta
   double* thresh;        // per system absolute residual target
   double* bnorm;         // per system ||b|| (for relres)
   double* relres;        // per system recursive relative residual
   int32_t* iters;        // per system iteration counts
   int32_t* done;         // per system: 0 active, 1 converged, 2 failed/capped
   int32_t* flags;        // global error flags
-  int32_t* tile_cnt;     // arrival counters per column tile (zero on entry, left zero)
-  int32_t* glob_cnt;     // arrival counter of column tiles (zero on entry, left zero)
-  double* part;          // partial sums, nchunks x Bpad x (2p+1)
-  int chunk_rows;        // rows per reduction chunk
-  int nchunks;
   int max_iter;
 };
 
-// mode 0: dots of r; mode 1: x += alpha p, r -= alpha q, then dots.  Converged systems are
-// retired (done), and the systems still active are listed in act_out/nact_out.
-hipError_t launch_pcg_step(const PCGState& s, const LMP& lmp, int mode, const int32_t* act, const int32_t* nact,
-                           int32_t* act_out, int32_t* nact_out, int64_t Bpad, double tol_rel, hipStream_t st);
-// p = z + beta p (first: p = z) for the listed systems; V (nullable) receives p in the apply precision.
-hipError_t launch_pcg_direction(Prec vprec, const PCGState& s, const LMP& lmp, int first, const int32_t* act,
-                                const int32_t* nact, int64_t Bpad, void* V, int64_t ldv, hipStream_t st);
+// One PCG iteration for every system of the list (one workgroup per system), after the apply.
+// mode 0 starts a solve (dots of r, p = z); mode 1 takes the step from T = S p.  Systems still
+// active are appended to act_out (*nact_out must be zero on entry) and their new p is written to
+// V (apply precision, observation domain; nullable).  plain != 0 keeps retired systems in the
+// list (masked solver).  m <= 4096.
+hipError_t launch_pcg_fused(Prec prec, const PCGState& s, const LMP& lmp, int mode, int obs_domain, int plain,
+                            const void* T, int64_t ldt, const int32_t* act, const int32_t* nact, int32_t* act_out,
+                            int32_t* nact_out, int64_t Bmax, void* V, int64_t ldv, const int32_t* h_ptr,
+                            const int32_t* h_idx, const double* h_w, const double* r_var, int64_t n_state,
+                            hipStream_t st);
 // Rebuild the list of active systems (done == 0), in increasing order.  One block.
 hipError_t launch_compact(const int32_t* done, int64_t S, int32_t* act, int32_t* nact, hipStream_t st);
 hipError_t launch_iota(int32_t* act, int32_t* nact, int64_t S, hipStream_t st);
@@ -207,46 +194,43 @@ hipError_t launch_iota(int32_t* act, int32_t* nact, int64_t S, hipStream_t st);
 // ---------------------------------------------------------------- misc vector kernels
 hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st);
-// out[r*ld + s] = a[r*ld+s] - b[r*ld+s] for all r < m, s < S
-hipError_t launch_sub(const double* a, const double* b, double* out, int64_t m, int64_t S, int64_t ld,
-                      hipStream_t st);
-// x[r*ld+s] += d[r*ld+s] for s with mask[s] (mask may be null)
-hipError_t launch_axpy_masked(double* x, const double* d, int64_t m, int64_t S, int64_t ld, hipStream_t st);
-// per-system norms: out[s] = ||v[:, s]||_2 (deterministic); scratch holds ceil(m/64) * S doubles
-hipError_t launch_col_norms(const double* v, int64_t m, int64_t S, int64_t ld, double* out, double* scratch,
-                            hipStream_t st);
-// true-residual bookkeeping: relres[s] = rn[s] / bn[s]; done[s] = relres <= tol ? 1 : 0 (for done != 2)
+hipError_t launch_sub(const double* a, const double* b, double* out, int64_t count, hipStream_t st);  // out = a - b
+hipError_t launch_axpy(double* x, const double* d, int64_t count, hipStream_t st);                  // x += d
+// out[s] = ||v[s*ld : s*ld + m]||_2, one workgroup per system (deterministic)
+hipError_t launch_col_norms(const double* v, int64_t m, int64_t S, int64_t ld, double* out, hipStream_t st);
 hipError_t launch_residual_status(const double* rn, const double* bn, double tol, double* relres, int32_t* done,
                                   int64_t S, int32_t* flags, hipStream_t st);
-// Quadrature combine: ubar[r, i] = sum_q p_q u[r, q*N + i]  (u: ld = ldu, ubar: ld = ldb)
+// Quadrature combine: ubar[i * ldb + r] = sum_q p_q u[(s0 + q N + i) * ldu + r]
 hipError_t launch_quad_combine(const double* u, int64_t ldu, int64_t m, int64_t N, int32_t Q, const double* pw,
                                double* ubar, int64_t ldb, int64_t s0, hipStream_t st);
-// Final state update: out[k + i*n] = scale * (Z[k + i*n] - T[k*ldt + i])  (column-major out)
+// Final state update: out[k + i*n] = scale * (Z[k + i*n] - T[i*ldt + k])  (column-major out)
 hipError_t launch_final_pert(const double* Z, const double* T, int64_t ldt, int64_t n, int64_t N, double scale,
                              double* out, hipStream_t st);
 hipError_t launch_final_mean(const double* mu, const double* T, int64_t ldt, int64_t n, int64_t col, double* out,
                              hipStream_t st);
-// transposes between column-major (ld) and system-fastest layouts
-hipError_t launch_to_sysfast(const double* V, int64_t ldv, int64_t n, int64_t B, double* out, int64_t ldo,
-                             hipStream_t st);
-hipError_t launch_from_sysfast(const double* in, int64_t ldi, int64_t n, int64_t B, double* out, int64_t ldo,
-                               hipStream_t st);
-// stats export
+// dst[c*ldd + r] = src[c*lds + r] for r < rows, zero for rows <= r < ldd
+hipError_t launch_copy_cols(const double* src, int64_t lds, int64_t rows, int64_t cols, double* dst, int64_t ldd,
+                            hipStream_t st);
 hipError_t launch_export_stats(const int32_t* iters, const double* relres, const int32_t* done, int64_t S,
                                int32_t* out_iters, double* out_relres, uint8_t* out_conv, double tol,
                                hipStream_t st);
 hipError_t launch_nan_check(const double* v, int64_t count, int32_t* flags, hipStream_t st);
 
 // ---------------------------------------------------------------- preconditioner setup (K8)
-// Gaussian sketch by counter-based Philox4x32-10 + Box-Muller: out[r*ld + j]
+// A strided m x k operand: element (r, a) at ptr[r * rs + a * cs].
+struct Strided {
+  const double* ptr;
+  int64_t rs, cs;
+};
+// Gaussian sketch by counter-based Philox4x32-10 + Box-Muller: out[j*ld + r] (system-major)
 hipError_t launch_sketch(uint64_t seed, int64_t m, int k, double* out, int64_t ld, hipStream_t st);
-// Gram: G[a*k+b] = sum_r A[r*lda + a] B[r*ldb + b], a,b < k (fixed order, deterministic)
-hipError_t launch_gram(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t m, int k, double* G,
-                       double* scratch, hipStream_t st);
+// Gram: G[a*k+b] = sum_r A(r, a) B(r, b), a,b < k (fixed order, deterministic)
+hipError_t launch_gram(Strided A, Strided B, int64_t m, int k, double* G, double* scratch, hipStream_t st);
 // One-workgroup small dense kernels.
 hipError_t launch_chol_inv(double* G, int k, int32_t* flags, hipStream_t st);   // G <- R^{-1} (upper), G = R^T R
-hipError_t launch_right_mult(double* A, int64_t lda, int64_t m, int k, const double* M, int kout, double* out,
-                             int64_t ldo, hipStream_t st);                     // out = A M (k x kout)
+// out(r, j) = sum_a A(r, a) M[a*kout + j], out(r, j) at out[r*ors + j*ocs]
+hipError_t launch_right_mult(Strided A, int64_t m, int k, const double* M, int kout, double* out, int64_t ors,
+                             int64_t ocs, hipStream_t st);
 hipError_t launch_sym_eig(double* T, int k, double* evec, double* evals, hipStream_t st);  // Jacobi
 hipError_t launch_lmp_finish(const double* evals, const double* evec, int k, int p, double* theta, double* sel,
                              hipStream_t st);                                  // top-p selection matrix

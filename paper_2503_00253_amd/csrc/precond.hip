@@ -45,19 +45,18 @@ __global__ void k_sketch(uint64_t seed, int64_t m, int k, double* __restrict__ o
   const double u1 = ((double)((((uint64_t)c[0]) << 21) ^ (uint64_t)(c[1] >> 11)) + 1.0) * 0x1p-53;
   const double u2 = ((double)((((uint64_t)c[2]) << 21) ^ (uint64_t)(c[3] >> 11)) + 0.5) * 0x1p-53;
   const double g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-  const int64_t r = t / k, j = t % k;
-  out[r * ld + j] = g;
+  const int64_t j = t / m, r = t % m;
+  out[j * ld + r] = g;
 }
 
 // partial Gram over a row chunk: scratch[chunk][a*k+b]
-__global__ void k_gram_partial(const double* __restrict__ A, int64_t lda, const double* __restrict__ B, int64_t ldb,
-                               int64_t m, int k, int chunk_rows, double* __restrict__ scratch) {
+__global__ void k_gram_partial(Strided A, Strided B, int64_t m, int k, int chunk_rows, double* __restrict__ scratch) {
   const int64_t r0 = blockIdx.x * (int64_t)chunk_rows;
   const int64_t r1 = min<int64_t>(m, r0 + chunk_rows);
   for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
     const int a = t / k, b = t % k;
     double acc = 0.0;
-    for (int64_t r = r0; r < r1; ++r) acc += A[r * lda + a] * B[r * ldb + b];
+    for (int64_t r = r0; r < r1; ++r) acc += A.ptr[r * A.rs + a * A.cs] * B.ptr[r * B.rs + b * B.cs];
     scratch[blockIdx.x * (int64_t)k * k + t] = acc;
   }
 }
@@ -112,16 +111,16 @@ __global__ void k_chol_inv(double* G, int k, int32_t* flags) {
   if (t == 0 && bad) atomicOr(flags, kFlagNumeric);
 }
 
-// out[r*ldo + j] = sum_a A[r*lda + a] M[a*kout + j]
-__global__ void k_right_mult(const double* __restrict__ A, int64_t lda, int64_t m, int k,
-                             const double* __restrict__ M, int kout, double* __restrict__ out, int64_t ldo) {
+// out(r, j) = sum_a A(r, a) M[a*kout + j]
+__global__ void k_right_mult(Strided A, int64_t m, int k, const double* __restrict__ M, int kout,
+                             double* __restrict__ out, int64_t ors, int64_t ocs) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= m * kout) return;
-  const int64_t r = t / kout;
-  const int j = (int)(t % kout);
+  const int64_t r = t % m;
+  const int j = (int)(t / m);
   double acc = 0.0;
-  for (int a = 0; a < k; ++a) acc += A[r * lda + a] * M[a * kout + j];
-  out[r * ldo + j] = acc;
+  for (int a = 0; a < k; ++a) acc += A.ptr[r * A.rs + a * A.cs] * M[a * kout + j];
+  out[r * ors + j * ocs] = acc;
 }
 
 // Jacobi eigendecomposition of a small symmetric matrix on one workgroup with the
@@ -263,11 +262,10 @@ hipError_t launch_sketch(uint64_t seed, int64_t m, int k, double* out, int64_t l
   return hipGetLastError();
 }
 
-hipError_t launch_gram(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t m, int k, double* G,
-                       double* scratch, hipStream_t st) {
+hipError_t launch_gram(Strided A, Strided B, int64_t m, int k, double* G, double* scratch, hipStream_t st) {
   const int chunk = 128;
   const int nchunks = (int)((m + chunk - 1) / chunk);
-  hipLaunchKernelGGL(k_gram_partial, dim3(nchunks), dim3(256), 0, st, A, lda, B, ldb, m, k, chunk, scratch);
+  hipLaunchKernelGGL(k_gram_partial, dim3(nchunks), dim3(256), 0, st, A, B, m, k, chunk, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gram_reduce, dim3((k * k + 255) / 256), dim3(256), 0, st, scratch, nchunks, k, G);
@@ -279,11 +277,11 @@ hipError_t launch_chol_inv(double* G, int k, int32_t* flags, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_right_mult(double* A, int64_t lda, int64_t m, int k, const double* M, int kout, double* out,
-                             int64_t ldo, hipStream_t st) {
+hipError_t launch_right_mult(Strided A, int64_t m, int k, const double* M, int kout, double* out, int64_t ors,
+                             int64_t ocs, hipStream_t st) {
   const int64_t cnt = m * kout;
-  hipLaunchKernelGGL(k_right_mult, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, A, lda, m, k, M, kout,
-                     out, ldo);
+  hipLaunchKernelGGL(k_right_mult, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, A, m, k, M, kout, out, ors,
+                     ocs);
   return hipGetLastError();
 }
 

@@ -55,9 +55,10 @@ hipError_t drain() {
 }  // namespace
 
 hipError_t cov_stencil_timed(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
-                             int64_t ldv, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, int rows_per_wave,
-                             hipStream_t st) {
-  if (!g_prof.on) return launch_cov_stencil(prec, g, Z, ldz, N, V, ldv, B, Bdev, T, ldt, rows_per_wave, st);
+                             int64_t ldv, int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt,
+                             int rows_per_wave, hipStream_t st, int32_t* zc) {
+  if (!g_prof.on)
+    return launch_cov_stencil(prec, g, Z, ldz, N, V, ldv, vcols, B, Bdev, T, ldt, rows_per_wave, st, nullptr, zc);
   hipError_t e;
   if (g_prof.used == kPairs && (e = drain()) != hipSuccess) return e;
   const int pi = (int)prec;
@@ -66,7 +67,8 @@ hipError_t cov_stencil_timed(Prec prec, const Grid& g, const void* Z, int64_t ld
   const size_t k = g_prof.used++;
   g_prof.ev_prec[k] = pi;
   if ((e = hipEventRecord(g_prof.ev[2 * k], st)) != hipSuccess) return e;
-  if ((e = launch_cov_stencil(prec, g, Z, ldz, N, V, ldv, B, Bdev, T, ldt, rows_per_wave, st, &pd)) != hipSuccess)
+  if ((e = launch_cov_stencil(prec, g, Z, ldz, N, V, ldv, vcols, B, Bdev, T, ldt, rows_per_wave, st, &pd, zc)) !=
+      hipSuccess)
     return e;
   g_prof.launches[pi] += 1;
   return hipEventRecord(g_prof.ev[2 * k + 1], st);
@@ -74,8 +76,8 @@ hipError_t cov_stencil_timed(Prec prec, const Grid& g, const void* Z, int64_t ld
 
 hipError_t cov_bf16_timed(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
                           int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt, int tile,
-                          hipStream_t st) {
-  if (!g_prof.on) return launch_cov_bf16(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, tile, st);
+                          hipStream_t st, int32_t* zc) {
+  if (!g_prof.on) return launch_cov_bf16(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, tile, st, nullptr, zc);
   hipError_t e;
   if (g_prof.used == kPairs && (e = drain()) != hipSuccess) return e;
   const int pi = 2;
@@ -84,7 +86,7 @@ hipError_t cov_bf16_timed(const Grid& g, const float* Z, int64_t ldz, int64_t N,
   const size_t k = g_prof.used++;
   g_prof.ev_prec[k] = pi;
   if ((e = hipEventRecord(g_prof.ev[2 * k], st)) != hipSuccess) return e;
-  if ((e = launch_cov_bf16(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, tile, st, &pd)) != hipSuccess) return e;
+  if ((e = launch_cov_bf16(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, tile, st, &pd, zc)) != hipSuccess) return e;
   g_prof.launches[pi] += 1;
   return hipEventRecord(g_prof.ev[2 * k + 1], st);
 }
