@@ -33,13 +33,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp32")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="bf16")
     ap.add_argument("--domain", choices=["state", "lattice"], default="lattice")
     ap.add_argument("--solver", choices=["plain", "compact"], default="compact")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-members", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device copy before the timed region (scale for HBM counters)")
     return ap.parse_args()
 
 
@@ -62,8 +64,8 @@ def traffic_record(src_path):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
+                          "(sharding by ensemble member is designed but not implemented)"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -82,14 +84,21 @@ def main():
     opts = ie.default_opts(**kw)
     run = ie.PerturbationRunner(P, s, p, opts)
     systems = prob.Q * prob.N
+    if a.copy_calibration:
+        src_buf = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst_buf = torch.empty_like(src_buf)
+        dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
+        del src_buf, dst_buf
 
     for w in range(a.warmup):
         code = run.run()
         torch.cuda.synchronize()
         log("warmup", w, "code", code)
-    st = run.stats(code)
-    log("iterations: total", int(st.iters.sum()), "max", int(st.iters.max()), "mean", float(st.iters.mean()),
-        "sweeps", st.counter(ie.CNT_SWEEPS), "not converged", st.counter(ie.CNT_NOT_CONVERGED))
+        st = run.stats(code)
+        log("iterations: total", int(st.iters.sum()), "max", int(st.iters.max()), "mean", float(st.iters.mean()),
+            "sweeps", st.counter(ie.CNT_SWEEPS), "not converged", st.counter(ie.CNT_NOT_CONVERGED))
 
     ie.profile_enable(True)
     torch.cuda.synchronize()
@@ -114,7 +123,7 @@ def main():
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dom], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_TFLOPS[dom], 4),
             "traffic": (tr or {}).get("bytes_per_launch"),
-            "kernel": f"k_cov_stencil<{PREC_NAME[dom]}>", "launches": launches[dom],
+            "kernel": "k_cov_bf16" if dom == 2 else f"k_cov_stencil<{PREC_NAME[dom]}>", "launches": launches[dom],
             "avg_launch_ms": round(avg_ms, 4), "vectors": vectors[dom],
             "flops_per_launch": flops[dom] / max(launches[dom], 1),
             "flops_per_vector": flops[dom] / max(vectors[dom], 1)}
@@ -148,20 +157,23 @@ def main():
         log("plain GPU PCG", pv, "speedup", value / pv, "diff", diff)
 
     if not a.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
         from oracle import infoesrf_ref as ref
         members = list(range(a.cpu_members))
         s0, p0, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
         Om = syn.sketch_matrix(prob.m, 20, 1)
-        t0 = time.perf_counter()
-        _, it = ref.info_esrf_pcg(prob, s0, p0, rtol=1e-8, Omega=Om, members=members)
-        t1 = time.perf_counter()
+        with threadpool_limits(limits=1):   # the oracle as it stands, on one host core
+            t0 = time.perf_counter()
+            _, it = ref.info_esrf_pcg(prob, s0, p0, rtol=1e-8, Omega=Om, members=members)
+            t1 = time.perf_counter()
         nsys = len(members) * prob.Q
         out["cpu_baseline"] = {"value": round(nsys / (t1 - t0), 4), "unit": "solves/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"{nsys} systems ({len(members)} member x {prob.Q} nodes) of the same "
-                                         f"workload incl. preconditioner setup, matrix-free FP64 PCG, "
-                                         f"{int(it.sum())} iterations, {t1 - t0:.1f} s; SciPy sparse apply "
-                                         f"(single-threaded)"}
+                                         f"workload incl. preconditioner setup, matrix-free FP64 PCG "
+                                         f"in the state space, {int(it.sum())} iterations, {t1 - t0:.1f} s; "
+                                         f"SciPy sparse apply, BLAS limited to 1 thread"}
         log("cpu baseline", out["cpu_baseline"])
     print(json.dumps(out), flush=True)
 

@@ -406,9 +406,9 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   sy.done = ar.take<int32_t>(sy.Spad);
   sy.fdone = ar.take<int32_t>(sy.Spad);
   sy.act = ar.take<int32_t>(sy.Spad);
-  sy.nact = ar.take<int32_t>(1);
+  sy.nact = ar.take<int32_t>(2);  // list length, live count
   sy.act2 = ar.take<int32_t>(sy.Spad);
-  sy.nact2 = ar.take<int32_t>(1);
+  sy.nact2 = ar.take<int32_t>(2);
 
   Pre& pr = pl.pr;
   pr.k = op.k;
@@ -481,7 +481,7 @@ int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* 
   }
   const Grid& g = in.obs ? in.go : in.gs;
   if (Bpad == 0 || in.dense) {
-    if (zero_counter) IE_HIP(launch_fill_i32(zero_counter, 0, 1, st));
+    if (zero_counter) IE_HIP(launch_fill_i32(zero_counter, 0, 2, st));
     zero_counter = nullptr;
   }
   if (prec == Prec::BF16) {
@@ -767,7 +767,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
     IE_HIP(launch_fill_f64(sy.x, 0.0, flat, st));
     int32_t *act_c = sy.act, *nact_c = sy.nact, *act_n = sy.act2, *nact_n = sy.nact2;
     int64_t hint = plain ? S : (int64_t)h_nact;  // upper bound of the live count on the device
-    IE_HIP(launch_fill_i32(nact_n, 0, 1, st));
+    IE_HIP(launch_fill_i32(nact_n, 0, 2, st));
     IE_HIP(launch_pcg_fused(op.inner, ps, lmp, 0, in.obs ? 1 : 0, plain ? 1 : 0, nullptr, ldr, act_c, nact_c, act_n,
                             nact_n, round_up(hint, kSysTile), Vbuf, ldr, in.P->h_ptr, in.P->h_idx, in.P->h_w,
                             in.P->r_var, in.n, st));
@@ -790,12 +790,12 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
         int got = poll.drain(&seen);
         IE_TRY(got);
         if (!got && (it % check_every) == 0) {
-          got = poll.post(nact_c, st, &seen);
+          got = poll.post(nact_c + 1, st, &seen);  // live count (the masked list keeps every system)
           IE_TRY(got);
         }
         if (got) {
           if (seen == 0) break;
-          if (!plain) hint = seen;
+          if (!plain) hint = seen;  // compacted lists hold exactly the live systems
         }
       }
     }

@@ -94,7 +94,10 @@ __global__ __launch_bounds__(256) void k_cov_stencil(Grid g, const T* __restrict
   constexpr int VS = NS + vpad<T>();
   if (Bdev) B = *Bdev;  // active-system count produced on the device
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    if (zero_counter) *zero_counter = 0;  // list counter of the next PCG step (nobody reads it now)
+    if (zero_counter) {  // list and live counters of the next PCG step (nobody reads them now)
+      zero_counter[0] = 0;
+      zero_counter[1] = 0;
+    }
     if (prof.vectors) {
       atomicAdd(prof.vectors, (unsigned long long)B);
       atomicAdd(prof.flops, (double)B * prof.flops_per_vector);
@@ -314,7 +317,10 @@ __global__ __launch_bounds__(256) void k_cov_bf16(Grid g, const float* __restric
   constexpr int NS = 16 * SB;
   if (Bdev) B = *Bdev;
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-    if (zero_counter) *zero_counter = 0;  // list counter of the next PCG step (nobody reads it now)
+    if (zero_counter) {  // list and live counters of the next PCG step (nobody reads them now)
+      zero_counter[0] = 0;
+      zero_counter[1] = 0;
+    }
     if (prof.vectors) {
       atomicAdd(prof.vectors, (unsigned long long)B);
       atomicAdd(prof.flops, (double)B * prof.flops_per_vector);

@@ -115,7 +115,8 @@ struct ProfDev {
   double flops_per_vector;
 };
 // B is the (padded) maximum column count; Bdev (nullable) holds the live count on the device.
-// zero_counter (nullable) is set to 0 by the launch (the next PCG step's list counter).
+// zero_counter (nullable): two int32 counters set to 0 by the launch (the next PCG step's list and
+// live counts).
 hipError_t launch_cov_stencil(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
                               int64_t ldv, int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt,
                               int rows_per_wave, hipStream_t st, const ProfDev* prof = nullptr,

@@ -144,10 +144,12 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
   const int64_t base = (int64_t)s * st.ld;
   const int tid = threadIdx.x;
 
-  // claim a slot in the next list (appended in any order) and write the next apply input
+  // claim a slot in the next list (appended in any order) and write the next apply input;
+  // nact_out[0] counts the list, nact_out[1] the systems still iterating (pv != nullptr)
   auto append = [&](const double* pv) {
     if (tid == 0) {
       const int slot = atomicAdd(nact_out, 1);
+      if (pv) atomicAdd(nact_out + 1, 1);
       act_out[slot] = s;
       s_slot = slot;
     }
