@@ -215,21 +215,36 @@ int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const 
                                  void* stream);
 
 /*
- * Many independent instances of uneven n, N, m, Q in one call (all systems of
- * all instances share one persistent launch per phase).  probs[j], Q[j],
- * s[j], p[j] (host arrays), y[j] (may be NULL), mean_a[j] (n_j, may be NULL
- * to skip the mean) and Xa_pert[j] (n_j x N_j) describe instance j.
- * stats arrays, when given, hold sum_j (Q_j N_j + 1) systems in instance
- * order (the mean system last within each instance).  Every instance must
- * use a STENCIL localization.
+ * Many independent filter instances of uneven n, N, m, Q in one call (the
+ * uneven batch of Section 3.2's remark that the solves parallelize across
+ * members and nodes, extended across instances).  Instance j is probs[j]
+ * with Q[j] nodes s_nodes[j], p_weights[j] (host arrays), observations y[j]
+ * (device, may be NULL unless its mean is wanted), mean_a[j] (device, n_j; the
+ * mean update of eq. 3.4 is skipped when mean_a or mean_a[j] is NULL) and
+ * Xa_pert[j] (device, n_j x N_j, as in infoesrf_perturbation_update).
+ *   lattices  host array of count observed lattices, read only when
+ *             opts->apply_domain is INFOESRF_DOMAIN_OBS_LATTICE (instance j
+ *             then uses lattices[j] in place of opts->lattice); else NULL.
+ *   stats     per-system arrays hold sum_j (Q_j N_j + 1) entries in instance
+ *             order (node-major systems, then the mean system); counters are
+ *             the totals over all instances, the status the most severe one.
+ *   ws        one workspace of infoesrf_batched_workspace_bytes() bytes,
+ *             split into one slice per instance.
+ * Instances run largest first on a pool of library-owned streams (default
+ * priority) that fork from and join back into `stream`.  With host_sync 1 the
+ * return code is the most severe instance code and the message names the
+ * first failing instance; with host_sync 0 every launch is issued from the
+ * calling thread and the status is left in stats->counters (this call is
+ * not meant for HIP graph capture; the single-instance calls are).
+ * Validation of every instance precedes any device work.
  */
 size_t infoesrf_batched_workspace_bytes(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
-                                        const infoesrf_opts* opts);
+                                        const infoesrf_opts* opts, const infoesrf_lattice* lattices);
 int infoesrf_update_batched(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
                             const double* const* s_nodes, const double* const* p_weights,
                             const double* const* y, double* const* mean_a, double* const* Xa_pert,
-                            const infoesrf_opts* opts, infoesrf_stats* stats, void* ws, size_t ws_bytes,
-                            void* stream);
+                            const infoesrf_opts* opts, const infoesrf_lattice* lattices, infoesrf_stats* stats,
+                            void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Elliptic quadrature rule (Appendix D, eq. D.1; host): with k^2 = ell/(1+ell)

@@ -7,6 +7,9 @@ ctypes binding with the same entry-point names.  Build the library with
 """
 from .infoesrf import (  # noqa: F401
     LIB_PATH,
+    BatchedRunner,
+    PerturbationRunner,
+    batched_workspace_bytes,
     InfoEsrfError,
     Problem,
     Stats,

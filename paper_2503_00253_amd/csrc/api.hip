@@ -10,8 +10,15 @@
 //      residuals are always formed in FP64 (the inner applies may be FP32/BF16).
 //   4. u_bar_i = sum_q p_q u_{q,i};  z_a^(i) = z^(i) - P H^T R^{-1/2} u_bar_i.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <functional>
+#include <mutex>
+#include <numeric>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -261,6 +268,8 @@ struct Plan {
 };
 
 inline int64_t ld64(int64_t rows) { return round_up(rows, 64); }
+// Room reserved for the CSC copy of H: 64 entries per row on average.
+inline int64_t nnz_bound(const infoesrf_problem* P) { return P->m * 64; }
 
 int check_problem(const infoesrf_problem* P) {
   IE_CHECK(P != nullptr, INFOESRF_ERR_INVALID_ARG, "problem is NULL");
@@ -540,8 +549,8 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
   IE_HIP(launch_nan_check(P->X, in.n * in.N, in.flags, st));
   hipLaunchKernelGGL(k_positive_check, dim3(nb(in.m)), dim3(256), 0, st, P->r_var, in.m, in.flags);
   IE_HIP(hipGetLastError());
-  IE_HIP(launch_csc_build(P->h_ptr, P->h_idx, P->h_w, in.m, in.n, in.col_cnt, in.col_ptr, in.row_of, in.w_of,
-                          in.flags, st));
+  IE_HIP(launch_csc_build(P->h_ptr, P->h_idx, P->h_w, in.m, in.n, nnz_bound(P), in.col_cnt, in.col_ptr, in.row_of,
+                          in.w_of, in.flags, st));
   if (in.obs) {
     hipLaunchKernelGGL(k_lattice_check, dim3(nb(in.m)), dim3(256), 0, st, P->h_ptr, P->h_idx, in.m, op.lat,
                        P->loc.nx, in.flags);
@@ -835,7 +844,6 @@ int finish_status(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t ex
 
 // nnz of H (device) sizes the CSC arrays: the reserved maximum is 64 entries per row on average;
 // with host_sync == 1 h_ptr[m] is read and checked against it.
-int64_t nnz_bound(const infoesrf_problem* P) { return P->m * 64; }
 
 int plan_for(Plan& pl, const infoesrf_problem* P, const Options& op, int64_t S, int64_t nfin, void* ws,
              size_t ws_bytes) {
@@ -862,6 +870,96 @@ int check_nnz(const infoesrf_problem* P, const Options& op, hipStream_t st) {
            "H has more than 64 entries per row on average (h_ptr[m] too large)");
   return 0;
 }
+
+// ------------------------------------------------------------------ batched instances
+// Sum of per-call counter blocks (k blocks of INFOESRF_NUM_COUNTERS); the status is the most
+// severe one: any error (the most negative), else the largest warning.
+__global__ void k_sum_counters(const int64_t* __restrict__ blocks, int k, int64_t* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= INFOESRF_NUM_COUNTERS) return;
+  int64_t acc = 0, worst_err = 0, worst_warn = 0;
+  for (int j = 0; j < k; ++j) {
+    const int64_t v = blocks[(int64_t)j * INFOESRF_NUM_COUNTERS + c];
+    if (c == INFOESRF_CNT_MAX_ITERS) acc = max(acc, v);
+    else if (c == INFOESRF_CNT_STATUS) {
+      worst_err = min(worst_err, v);
+      worst_warn = max(worst_warn, v);
+    } else acc += v;
+  }
+  out[c] = (c == INFOESRF_CNT_STATUS) ? (worst_err < 0 ? worst_err : worst_warn) : acc;
+}
+
+// Host worker pool for batched instances: created on first use, kept for the life of the
+// process (its threads are detached and end with it).  Each worker owns one non-blocking stream
+// per device, so instances on different workers overlap on the GPU.
+class WorkerPool {
+ public:
+  static constexpr int kWorkers = 4;
+  static WorkerPool& get() {
+    static WorkerPool* pool = new WorkerPool();  // intentionally never destroyed
+    return *pool;
+  }
+  // Runs every task on the workers and returns when all have finished.
+  void run(std::vector<std::function<void()>>& tasks) {
+    struct Latch {
+      std::mutex mu;
+      std::condition_variable cv;
+      size_t left;
+    } latch;
+    latch.left = tasks.size();
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      for (auto& t : tasks)
+        q_.push_back([&t, &latch] {
+          t();
+          std::lock_guard<std::mutex> l2(latch.mu);
+          if (--latch.left == 0) latch.cv.notify_all();
+        });
+    }
+    cv_.notify_all();
+    std::unique_lock<std::mutex> lk(latch.mu);
+    latch.cv.wait(lk, [&] { return latch.left == 0; });
+  }
+  // Stream idx (< kWorkers) of the calling thread on device dev, created on first use and kept
+  // for the thread's lifetime (default priority, non-blocking).
+  static hipError_t worker_stream(int dev, int idx, hipStream_t* out) {
+    static thread_local std::vector<hipStream_t> streams;
+    const size_t k = (size_t)dev * kWorkers + idx;
+    if (streams.size() <= k) streams.resize(k + 1, nullptr);
+    if (!streams[k]) {
+      const hipError_t e = hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        streams[k] = nullptr;
+        return e;
+      }
+    }
+    *out = streams[k];
+    return hipSuccess;
+  }
+
+ private:
+  WorkerPool() {
+    for (int i = 0; i < kWorkers; ++i) std::thread([this] { loop(); }).detach();
+  }
+  void loop() {
+    for (;;) {
+      std::function<void()> job;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return !q_.empty(); });
+        job = std::move(q_.front());
+        q_.pop_front();
+      }
+      job();
+    }
+  }
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<std::function<void()>> q_;
+};
+
+// Workspace of one instance: room for its perturbation update and (if asked) its mean update.
+size_t instance_ws_bytes(const infoesrf_problem* P, int32_t Q, bool mean, const infoesrf_opts* opts);
 
 }  // namespace
 }  // namespace infoesrf
@@ -1070,29 +1168,230 @@ int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const 
 }
 
 size_t infoesrf_batched_workspace_bytes(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
-                                        const infoesrf_opts* opts) {
+                                        const infoesrf_opts* opts, const infoesrf_lattice* lattices) {
   clear_error();
   if (!probs || !Q || count < 1) {
     set_error("probs/Q must be non-NULL and count >= 1");
     return 0;
   }
+  infoesrf_opts o;
+  if (opts) o = *opts;
+  else infoesrf_default_opts(&o);
+  if (o.apply_domain == INFOESRF_DOMAIN_OBS_LATTICE && !lattices) {
+    set_error("the observed-lattice domain needs lattices[count]");
+    return 0;
+  }
   size_t total = 0;
   for (int j = 0; j < count; ++j) {
-    const size_t b = infoesrf_workspace_bytes(&probs[j], Q[j], opts);
-    if (b == 0) return 0;
+    if (o.apply_domain == INFOESRF_DOMAIN_OBS_LATTICE) o.lattice = lattices[j];
+    const size_t b = instance_ws_bytes(&probs[j], Q[j], true, &o);
+    if (b == 0) {
+      set_error("instance " + std::to_string(j) + ": " + g_last_error);
+      return 0;
+    }
     total += (b + 255) / 256 * 256;
   }
+  // two counter blocks per instance (perturbation and mean calls)
+  total += (size_t)2 * count * INFOESRF_NUM_COUNTERS * sizeof(int64_t) + 256;
   return total;
 }
 
 int infoesrf_update_batched(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
                             const double* const* s_nodes, const double* const* p_weights, const double* const* y,
                             double* const* mean_a, double* const* Xa_pert, const infoesrf_opts* opts,
-                            infoesrf_stats* stats, void* ws, size_t ws_bytes, void* stream) {
-  (void)probs; (void)count; (void)Q; (void)s_nodes; (void)p_weights; (void)y; (void)mean_a; (void)Xa_pert;
-  (void)opts; (void)stats; (void)ws; (void)ws_bytes; (void)stream;
-  set_error("batched instances are not available yet");
-  return INFOESRF_ERR_INVALID_ARG;
+                            const infoesrf_lattice* lattices, infoesrf_stats* stats, void* ws, size_t ws_bytes,
+                            void* stream) {
+  clear_error();
+  IE_CHECK(probs && Q && s_nodes && p_weights && Xa_pert && count >= 1, INFOESRF_ERR_INVALID_ARG,
+           "probs, Q, s_nodes, p_weights, Xa_pert must be non-NULL and count >= 1");
+  IE_CHECK(ws != nullptr, INFOESRF_ERR_WORKSPACE, "workspace is NULL");
+  infoesrf_opts o;
+  if (opts) o = *opts;
+  else infoesrf_default_opts(&o);
+  const bool per_lattice = o.apply_domain == INFOESRF_DOMAIN_OBS_LATTICE;
+  IE_CHECK(!per_lattice || lattices, INFOESRF_ERR_INVALID_ARG, "the observed-lattice domain needs lattices[count]");
+  std::vector<infoesrf_opts> oj(count, o);
+  if (per_lattice)
+    for (int j = 0; j < count; ++j) oj[j].lattice = lattices[j];
+  // per-instance workspace slices and system offsets (validates every instance first)
+  std::vector<size_t> off(count + 1, 0);
+  std::vector<int64_t> sys_off(count + 1, 0);
+  for (int j = 0; j < count; ++j) {
+    const bool want_mean = mean_a && mean_a[j];
+    IE_CHECK(!want_mean || (y && y[j]), INFOESRF_ERR_INVALID_ARG,
+             "instance " + std::to_string(j) + ": the mean update needs y");
+    IE_CHECK(Xa_pert[j] && s_nodes[j] && p_weights[j], INFOESRF_ERR_INVALID_ARG,
+             "instance " + std::to_string(j) + ": s_nodes, p_weights and Xa_pert must be non-NULL");
+    const size_t b = instance_ws_bytes(&probs[j], Q[j], want_mean, &oj[j]);
+    if (b == 0) {
+      set_error("instance " + std::to_string(j) + ": " + g_last_error);
+      return INFOESRF_ERR_INVALID_ARG;
+    }
+    off[j + 1] = off[j] + (b + 255) / 256 * 256;
+    sys_off[j + 1] = sys_off[j] + (int64_t)Q[j] * probs[j].N + 1;
+  }
+  const size_t cnt_bytes = (size_t)2 * count * INFOESRF_NUM_COUNTERS * sizeof(int64_t);
+  const size_t need = off[count] + cnt_bytes + 256;
+  IE_CHECK(ws_bytes >= need, INFOESRF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  char* base = static_cast<char*>(ws);
+  int64_t* cnt = reinterpret_cast<int64_t*>(base + off[count]);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  IE_HIP(hipGetDevice(&dev));
+  // blocks of instances that fail before launching anything, or skip the mean, must read zero
+  IE_HIP(launch_fill_i32(reinterpret_cast<int32_t*>(cnt), 0, (int64_t)4 * count * INFOESRF_NUM_COUNTERS, st));
+
+  // largest instances first: cost ~ systems x observations x members x stencil width
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  auto cost = [&](int j) {
+    const infoesrf_problem& P = probs[j];
+    return (double)Q[j] * P.N * (double)P.m * P.N * (2.0 * P.loc.bx + 1) * (2.0 * P.loc.bz + 1);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+
+  hipEvent_t fork = nullptr;
+  IE_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  std::vector<hipEvent_t> done(count, nullptr);
+  std::vector<int> codes(count, 0);
+  std::vector<std::string> msgs(count);
+  auto cleanup = [&] {
+    for (auto e : done)
+      if (e) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(fork);
+  };
+  for (int j = 0; j < count; ++j) {
+    if (hipEventCreateWithFlags(&done[j], hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      set_error("hipEventCreate failed");
+      return INFOESRF_ERR_HIP;
+    }
+  }
+  if (hipEventRecord(fork, st) != hipSuccess) {
+    cleanup();
+    set_error("hipEventRecord failed");
+    return INFOESRF_ERR_HIP;
+  }
+
+  // one instance: mean update (optional) then perturbation update, on stream ss
+  auto run_one = [&](int j, hipStream_t ss) {
+    int code = 0;
+    if (hipStreamWaitEvent(ss, fork, 0) != hipSuccess) {
+      codes[j] = INFOESRF_ERR_HIP;
+      msgs[j] = "hipStreamWaitEvent failed";
+      return;
+    }
+    void* wsj = base + off[j];
+    const size_t wsb = off[j + 1] - off[j];
+    infoesrf_stats sj{};
+    const int64_t S = (int64_t)Q[j] * probs[j].N;
+    if (stats) {
+      sj.iters = stats->iters ? stats->iters + sys_off[j] : nullptr;
+      sj.relres = stats->relres ? stats->relres + sys_off[j] : nullptr;
+      sj.converged = stats->converged ? stats->converged + sys_off[j] : nullptr;
+    }
+    sj.counters = cnt + (int64_t)(2 * j) * INFOESRF_NUM_COUNTERS;
+    code = infoesrf_perturbation_update(&probs[j], Q[j], s_nodes[j], p_weights[j], y ? y[j] : nullptr, Xa_pert[j],
+                                        &oj[j], &sj, wsj, wsb, ss);
+    if (code >= 0 && mean_a && mean_a[j]) {
+      infoesrf_stats sm{};
+      if (stats) {
+        sm.iters = stats->iters ? stats->iters + sys_off[j] + S : nullptr;
+        sm.relres = stats->relres ? stats->relres + sys_off[j] + S : nullptr;
+        sm.converged = stats->converged ? stats->converged + sys_off[j] + S : nullptr;
+      }
+      sm.counters = cnt + (int64_t)(2 * j + 1) * INFOESRF_NUM_COUNTERS;
+      const int cm = infoesrf_mean_update(&probs[j], y[j], mean_a[j], &oj[j], &sm, wsj, wsb, ss);
+      code = (cm < 0) ? cm : std::max(code, cm);
+    }
+    codes[j] = code;
+    if (code < 0) msgs[j] = g_last_error;
+    if (hipEventRecord(done[j], ss) != hipSuccess && codes[j] >= 0) {
+      codes[j] = INFOESRF_ERR_HIP;
+      msgs[j] = "hipEventRecord failed";
+    }
+  };
+
+  if (o.host_sync) {
+    // every worker takes the next-largest instance from a shared cursor
+    std::atomic<int> cursor{0};
+    std::vector<std::function<void()>> tasks;
+    const int nw = std::min<int>(WorkerPool::kWorkers, count);
+    for (int w = 0; w < nw; ++w)
+      tasks.emplace_back([&, dev] {
+        hipStream_t ss = nullptr;
+        hipError_t e = hipSetDevice(dev);
+        if (e == hipSuccess) e = WorkerPool::worker_stream(dev, 0, &ss);
+        for (int k = cursor.fetch_add(1); k < count; k = cursor.fetch_add(1)) {
+          const int j = order[k];
+          if (e != hipSuccess) {
+            codes[j] = INFOESRF_ERR_HIP;
+            msgs[j] = "worker device or stream set-up failed";
+            (void)hipEventRecord(done[j], st);  // nothing ran: the join must not wait on it
+            continue;
+          }
+          run_one(j, ss);
+        }
+      });
+    WorkerPool::get().run(tasks);
+  } else {
+    // no host synchronization: every launch is issued from this thread, over this thread's
+    // kWorkers streams in turn, so the call returns as soon as the work is enqueued
+    for (int k = 0; k < count; ++k) {
+      const int j = order[k];
+      hipStream_t ss = nullptr;
+      if (WorkerPool::worker_stream(dev, k % WorkerPool::kWorkers, &ss) != hipSuccess) {
+        codes[j] = INFOESRF_ERR_HIP;
+        msgs[j] = "stream creation failed";
+        (void)hipEventRecord(done[j], st);
+        continue;
+      }
+      run_one(j, ss);
+    }
+  }
+  int worst_err = 0, worst_warn = 0, first_bad = -1;
+  for (int j = 0; j < count; ++j) {
+    if (codes[j] < worst_err) {
+      worst_err = codes[j];
+      first_bad = j;
+    }
+    worst_warn = std::max(worst_warn, codes[j]);
+  }
+  // join: the caller's stream waits for every instance
+  for (int j = 0; j < count; ++j) {
+    if (hipStreamWaitEvent(st, done[j], 0) != hipSuccess) {
+      cleanup();
+      set_error("hipStreamWaitEvent failed");
+      return INFOESRF_ERR_HIP;
+    }
+  }
+  if (stats && stats->counters) {
+    hipLaunchKernelGGL(k_sum_counters, dim3(1), dim3(64), 0, st, cnt, 2 * count, stats->counters);
+    if (hipGetLastError() != hipSuccess) {
+      cleanup();
+      set_error("counter reduction launch failed");
+      return INFOESRF_ERR_HIP;
+    }
+  }
+  cleanup();
+  if (worst_err < 0) {
+    set_error("instance " + std::to_string(first_bad) + ": " + msgs[first_bad]);
+    return worst_err;
+  }
+  return worst_warn;
 }
 
 }  // extern "C"
+
+namespace infoesrf {
+namespace {
+size_t instance_ws_bytes(const infoesrf_problem* P, int32_t Q, bool mean, const infoesrf_opts* opts) {
+  const size_t bp = infoesrf_workspace_bytes(P, Q, opts);
+  if (bp == 0) return 0;
+  if (!mean) return bp;
+  const size_t bm = infoesrf_workspace_bytes(P, 0, opts);
+  if (bm == 0) return 0;
+  return std::max(bp, bm);
+}
+}  // namespace
+}  // namespace infoesrf

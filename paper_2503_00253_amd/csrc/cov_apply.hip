@@ -21,6 +21,7 @@
 // consecutive row tiles.  Row blocks skip K steps that lie outside their band,
 // so the padded MFMA work per row block is (16 + 2bx + 3) / (2bx + 1) of the
 // band's.
+#include <atomic>
 #include "internal.hpp"
 
 namespace infoesrf {
@@ -267,12 +268,12 @@ hipError_t launch_typed(const Grid& g, const T* Z, int64_t ldz, int64_t N, const
   while (KC > 16 && smem_bytes<T, RB, SB>(g, KC, MC) > budget) KC -= 16;
   const size_t smem = smem_bytes<T, RB, SB>(g, KC, MC);
   if (smem > 150 * 1024) return hipErrorInvalidValue;
-  static bool attr_set = false;  // once per instantiation: allow more than 64 KiB of dynamic LDS
-  if (!attr_set) {
+  static std::atomic<bool> attr_set{false};  // once per instantiation: allow more than 64 KiB of dynamic LDS
+  if (!attr_set.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cov_stencil<T, RB, SB>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    attr_set.store(true, std::memory_order_release);
   }
   dim3 grid(ntiles, (unsigned)((B + NS - 1) / NS));
   hipLaunchKernelGGL((k_cov_stencil<T, RB, SB>), grid, dim3(256), smem, st, g, Z, ldz, (int)N, V, ldv, vcols, (int)B,
@@ -502,12 +503,12 @@ hipError_t launch_bf16_typed(const Grid& g, const float* Z, int64_t ldz, int64_t
   while (MC > 4 && smem_bf16<RB, SB>(g, KWs, MC) > budget) MC -= 4;
   const size_t smem = smem_bf16<RB, SB>(g, KWs, MC);
   if (smem > 150 * 1024) return hipErrorInvalidValue;
-  static bool attr = false;
-  if (!attr) {
+  static std::atomic<bool> attr{false};  // concurrent first calls set the same attribute twice: harmless
+  if (!attr.load(std::memory_order_acquire)) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cov_bf16<RB, SB>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     if (e != hipSuccess) return e;
-    attr = true;
+    attr.store(true, std::memory_order_release);
   }
   dim3 grid(ntiles, (unsigned)((B + NS - 1) / NS));
   hipLaunchKernelGGL((k_cov_bf16<RB, SB>), grid, dim3(256), smem, st, g, Z, ldz, (int)N, V, ldk, vcols, (int)B, Bdev,

@@ -31,13 +31,14 @@ __global__ void k_ens_stats(const double* __restrict__ X, int64_t n, int64_t N, 
   }
 }
 
-// Column counts of H (one thread per CSR entry); also validates indices.
+// Column counts of H (one thread per CSR row); also validates indices and that the entry count
+// fits the cap entries the CSC copy has room for.
 __global__ void k_csc_count(const int32_t* __restrict__ h_ptr, const int32_t* __restrict__ h_idx, int64_t m,
-                            int64_t n, int32_t* __restrict__ cnt, int32_t* __restrict__ flags) {
+                            int64_t n, int64_t cap, int32_t* __restrict__ cnt, int32_t* __restrict__ flags) {
   int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= m) return;
   const int32_t e0 = h_ptr[r], e1 = h_ptr[r + 1];
-  if (e1 < e0 || e0 < 0 || e1 > h_ptr[m] || (r == 0 && e0 != 0)) {
+  if (e1 < e0 || e0 < 0 || e1 > h_ptr[m] || (int64_t)h_ptr[m] > cap || (r == 0 && e0 != 0)) {
     atomicOr(flags, kFlagBadInput);
     return;
   }
@@ -227,11 +228,12 @@ hipError_t launch_ens_stats(const double* X, int64_t n, int64_t N, double* mu, d
 }
 
 hipError_t launch_csc_build(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, int64_t m, int64_t n,
-                            int32_t* col_cnt, int32_t* col_ptr, int32_t* row_of, double* w_of, int32_t* flags,
-                            hipStream_t st) {
+                            int64_t cap, int32_t* col_cnt, int32_t* col_ptr, int32_t* row_of, double* w_of,
+                            int32_t* flags, hipStream_t st) {
   hipError_t e;
   if ((e = launch_fill_i32(col_cnt, 0, n, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_csc_count, dim3(blocks_for(m)), dim3(kBlock), 0, st, h_ptr, h_idx, m, n, col_cnt, flags);
+  hipLaunchKernelGGL(k_csc_count, dim3(blocks_for(m)), dim3(kBlock), 0, st, h_ptr, h_idx, m, n, cap, col_cnt,
+                     flags);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_scan_one_block, dim3(1), dim3(kBlock), 0, st, col_cnt, n, col_ptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;

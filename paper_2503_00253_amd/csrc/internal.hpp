@@ -70,9 +70,10 @@ hipError_t launch_ens_stats(const double* X, int64_t n, int64_t N, double* mu, d
                             hipStream_t st);
 
 // CSR -> CSC transpose of H (deterministic: entries of a column sorted by row).
+// cap: entries row_of / w_of can hold; h_ptr[m] > cap raises the bad-input flag and nothing is written.
 hipError_t launch_csc_build(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, int64_t m, int64_t n,
-                            int32_t* col_cnt, int32_t* col_ptr, int32_t* row_of, double* w_of, int32_t* flags,
-                            hipStream_t st);
+                            int64_t cap, int32_t* col_cnt, int32_t* col_ptr, int32_t* row_of, double* w_of,
+                            int32_t* flags, hipStream_t st);
 
 // rhs[s * ld + r] = dinv[r] * sum_e h_w[e] * Z[h_idx[e], member(s)] for systems s in [s0, s0+cnt),
 // member(s) = (s - s0) % N.

@@ -92,6 +92,12 @@ def library():
     lib.infoesrf_perturbation_update.argtypes = [P(ProblemC), C.c_int32, P(C.c_double), P(C.c_double), VP, VP,
                                                  P(Opts), P(StatsC), VP, C.c_size_t, VP]
     lib.infoesrf_perturbation_update.restype = C.c_int
+    lib.infoesrf_batched_workspace_bytes.argtypes = [P(ProblemC), C.c_int32, P(C.c_int32), P(Opts), P(Lattice)]
+    lib.infoesrf_batched_workspace_bytes.restype = C.c_size_t
+    PD = P(C.c_double)
+    lib.infoesrf_update_batched.argtypes = [P(ProblemC), C.c_int32, P(C.c_int32), P(PD), P(PD), P(VP), P(VP),
+                                            P(VP), P(Opts), P(Lattice), P(StatsC), VP, C.c_size_t, VP]
+    lib.infoesrf_update_batched.restype = C.c_int
     lib.infoesrf_quadrature_elliptic.argtypes = [C.c_int32, C.c_double, P(C.c_double), P(C.c_double)]
     lib.infoesrf_quadrature_elliptic.restype = C.c_int
     lib.infoesrf_quadrature_gauss_legendre.argtypes = [C.c_int32, P(C.c_double), P(C.c_double)]
@@ -316,6 +322,70 @@ def perturbation_update(problem: Problem, s_nodes, p_weights, opts: Opts | None 
         out.data_ptr(), C.byref(opts), C.byref(sc), ws.data_ptr(), ws.numel(), _stream()))
     torch.cuda.synchronize()
     return out.t(), Stats(code, *(t.cpu().numpy() for t in keep))
+
+
+def batched_workspace_bytes(problems, Qs, opts: Opts, lattices=None) -> int:
+    arr = (ProblemC * len(problems))(*[pb.c for pb in problems])
+    qa = (C.c_int32 * len(Qs))(*Qs)
+    lat = None
+    if lattices is not None:
+        lat = lattices if isinstance(lattices, C.Array) else (Lattice * len(lattices))(*[Lattice(*t) for t in lattices])
+    b = library().infoesrf_batched_workspace_bytes(arr, len(problems), qa, C.byref(opts), lat)
+    if b == 0:
+        raise InfoEsrfError(ERR_INVALID_ARG, library().infoesrf_last_error().decode())
+    return int(b)
+
+
+class BatchedRunner:
+    """Many independent instances in one infoesrf_update_batched call (buffers preallocated).
+
+    problems: list of Problem; nodes: list of (s, p) host arrays; ys: list of observation
+    vectors (needed when means are wanted).  run() only enqueues the call.
+    """
+
+    def __init__(self, problems, nodes, opts: Opts, ys=None, want_mean=True, lattices=None):
+        torch = _torch()
+        self.lib = library()
+        self.problems = list(problems)
+        self.opts = opts
+        k = len(self.problems)
+        dev = self.problems[0].X.device
+        self.s = [np.ascontiguousarray(sn, dtype=np.float64) for sn, _ in nodes]
+        self.p = [np.ascontiguousarray(pw, dtype=np.float64) for _, pw in nodes]
+        self.Qs = [len(x) for x in self.s]
+        self.outs = [torch.empty((pb.N, pb.n), dtype=torch.float64, device=dev) for pb in self.problems]
+        self.means = [torch.empty(pb.n, dtype=torch.float64, device=dev) for pb in self.problems] if want_mean \
+            else None
+        self.ys = None
+        if ys is not None:
+            self.ys = [torch.as_tensor(np.asarray(y, dtype=np.float64)).to(dev) if not torch.is_tensor(y)
+                       else y.to(dev, torch.float64) for y in ys]
+        self.nsys = sum(q * pb.N + 1 for q, pb in zip(self.Qs, self.problems))
+        self.sc, self.keep = _stats(self.nsys, dev)
+        self._probs = (ProblemC * k)(*[pb.c for pb in self.problems])
+        self._qa = (C.c_int32 * k)(*self.Qs)
+        PD = C.POINTER(C.c_double)
+        self._sp = (PD * k)(*[x.ctypes.data_as(PD) for x in self.s])
+        self._pp = (PD * k)(*[x.ctypes.data_as(PD) for x in self.p])
+        self._yp = (C.c_void_p * k)(*[y.data_ptr() for y in self.ys]) if self.ys is not None else None
+        self._mp = (C.c_void_p * k)(*[mm.data_ptr() for mm in self.means]) if self.means is not None else None
+        self._xp = (C.c_void_p * k)(*[o.data_ptr() for o in self.outs])
+        self._lat = (Lattice * k)(*[Lattice(*t) for t in lattices]) if lattices is not None else None
+        nbytes = batched_workspace_bytes(self.problems, self.Qs, opts, self._lat)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+    def run(self):
+        return _check(self.lib.infoesrf_update_batched(
+            self._probs, len(self.problems), self._qa, self._sp, self._pp, self._yp, self._mp, self._xp,
+            C.byref(self.opts), self._lat, C.byref(self.sc), self.ws.data_ptr(), self.ws.numel(), _stream()))
+
+    def results(self):
+        """(list of n_j x N_j analysis deviations, list of analysis means or None)."""
+        return [o.t() for o in self.outs], self.means
+
+    def stats(self, code=0):
+        """Per-system arrays over all instances (instance order, node-major, the mean system last)."""
+        return Stats(code, *(t.cpu().numpy() for t in self.keep))
 
 
 class PerturbationRunner:

@@ -130,3 +130,57 @@ def test_workspace_monotone_in_Q_and_N():
     a = lib.infoesrf_workspace_bytes(C.byref(fake_problem(N=8)), 8, C.byref(o))
     b = lib.infoesrf_workspace_bytes(C.byref(fake_problem(N=16)), 8, C.byref(o))
     assert b > a
+
+
+def _batched_args(probs, Qs, with_mean=False):
+    k = len(probs)
+    PD = C.POINTER(C.c_double)
+    nodes = [np.ones(q) for q in Qs]
+    arr = (ie.ProblemC * k)(*probs)
+    qa = (C.c_int32 * k)(*Qs)
+    sp = (PD * k)(*[x.ctypes.data_as(PD) for x in nodes])
+    outs = (C.c_void_p * k)(*([0x1000] * k))
+    means = (C.c_void_p * k)(*([0x1000] * k)) if with_mean else None
+    return arr, qa, sp, outs, means, nodes
+
+
+def test_batched_workspace_is_sum_of_instances():
+    lib = ie.library()
+    o = ie.default_opts()
+    probs = [fake_problem(n=64, N=8), fake_problem(n=128, N=4, m=40), fake_problem(n=64, N=16)]
+    Qs = [4, 8, 2]
+    arr, qa, *_ = _batched_args(probs, Qs)
+    total = lib.infoesrf_batched_workspace_bytes(arr, 3, qa, C.byref(o), None)
+    expect = 0
+    for p, q in zip(probs, Qs):
+        b = max(lib.infoesrf_workspace_bytes(C.byref(p), q, C.byref(o)),
+                lib.infoesrf_workspace_bytes(C.byref(p), 0, C.byref(o)))
+        expect += (b + 255) // 256 * 256
+    expect += 2 * 3 * ie.NUM_COUNTERS * 8 + 256
+    assert total == expect
+
+
+def test_batched_validation_before_device_access():
+    lib = ie.library()
+    o = ie.default_opts()
+    bad = fake_problem()
+    bad.N = 1
+    probs = [fake_problem(), bad]
+    arr, qa, sp, outs, means, keep = _batched_args(probs, [4, 4])
+    assert lib.infoesrf_batched_workspace_bytes(arr, 2, qa, C.byref(o), None) == 0
+    assert "instance 1" in lib.infoesrf_last_error().decode()
+    rc = lib.infoesrf_update_batched(arr, 2, qa, sp, sp, None, None, outs, C.byref(o), None, None, C.c_void_p(0x1000),
+                                     1 << 30, None)
+    assert rc == ie.ERR_INVALID_ARG and "instance 1" in lib.infoesrf_last_error().decode()
+    # means without observations
+    arr, qa, sp, outs, means, keep = _batched_args([fake_problem(), fake_problem()], [4, 4], with_mean=True)
+    rc = lib.infoesrf_update_batched(arr, 2, qa, sp, sp, None, means, outs, C.byref(o), None, None, C.c_void_p(0x1000),
+                                     1 << 30, None)
+    assert rc == ie.ERR_INVALID_ARG and "needs y" in lib.infoesrf_last_error().decode()
+    # workspace too small, empty batch
+    rc = lib.infoesrf_update_batched(arr, 2, qa, sp, sp, None, None, outs, C.byref(o), None, None, C.c_void_p(0x1000),
+                                     64, None)
+    assert rc == ie.ERR_WORKSPACE
+    rc = lib.infoesrf_update_batched(arr, 0, qa, sp, sp, None, None, outs, C.byref(o), None, None, C.c_void_p(0x1000),
+                                     1 << 30, None)
+    assert rc == ie.ERR_INVALID_ARG

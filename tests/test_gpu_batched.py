@@ -1,0 +1,157 @@
+"""Batched instances (infoesrf_update_batched) through the C ABI.
+
+Every instance of a batch must give exactly the bits of the same instance run
+alone: instances share no arithmetic, each keeps its own workspace slice, and
+the per-system work does not depend on which stream or host thread issued it.
+One instance is also checked against the FP64 oracle (1e-6, the FP64-mode
+bound at rtol 1e-8).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import infoesrf_ref as ref
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2503_00253_amd import infoesrf as ie  # noqa: E402
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def layered_problem(seed):
+    """4 x 50 layered grid, every 2nd site of every layer observed."""
+    rng = np.random.default_rng(seed)
+    nz, nx, N = 4, 50, 6
+    n = nz * nx
+    X = rng.standard_normal((n, N)) + 0.5 * np.sin(np.arange(n) / 7.0)[:, None]
+    bz, bx, table = syn.gc_table_2d(3.0, 1.0)
+    idx = np.array([z * nx + x for z in range(nz) for x in range(0, nx, 2)], dtype=np.int32)
+    m = idx.size
+    return syn.Problem(n=n, N=N, m=m, X=np.asfortranarray(X), h_ptr=np.arange(m + 1, dtype=np.int32), h_idx=idx,
+                       h_w=1.0 + 0.25 * np.cos(np.arange(m)), r_var=0.3 * (1.0 + 0.5 * rng.random(m)),
+                       y=rng.standard_normal(m), nz=nz, nx=nx, periodic_z=0, periodic_x=1, bz=bz, bx=bx,
+                       table=table, truth=np.zeros(n), Q=5, ell=100.0, name="layered-4x50")
+
+
+def batch():
+    return [
+        syn.gaussian_problem(512, 16, 20.0, 12.0, 4, 0.25, 6, 100.0, 101, name="g512"),
+        syn.config1(),
+        layered_problem(13),
+        syn.gaussian_problem(1024, 12, 40.0, 30.0, 4, 0.5, 5, 1000.0, 103, name="g1024"),
+        syn.gaussian_problem(256, 8, 10.0, 20.0, 4, 0.25, 3, 100.0, 102, name="g256"),
+    ]
+
+
+def run_single(P, prob, s, p, opts):
+    Xa, st = ie.perturbation_update(P, s, p, opts)
+    mu, sm = ie.mean_update(P, prob.y, opts)
+    return Xa.cpu().numpy(), mu.cpu().numpy(), st, sm
+
+
+def make_opts(domain, precision, P=None, **kw):
+    if domain == "lattice":
+        kw.update(apply_domain=ie.DOMAIN_OBS_LATTICE)
+        if P is not None:
+            kw.update(lattice=P.lattice())
+    return ie.default_opts(precision=precision, **kw)
+
+
+@pytest.mark.parametrize("domain,precision", [("state", ie.FP64), ("lattice", ie.MIXED_BF16),
+                                              ("lattice", ie.MIXED_FP32)])
+def test_batched_equals_single_instances(domain, precision):
+    probs = batch()
+    Ps = [ie.Problem.from_synthetic(pr) for pr in probs]
+    nodes = [ie.quadrature_elliptic(pr.Q, pr.ell) for pr in probs]
+    lats = [P.lattice() for P in Ps] if domain == "lattice" else None
+    say("batched", domain, precision, [pr.name for pr in probs])
+    runner = ie.BatchedRunner(Ps, nodes, make_opts(domain, precision), ys=[pr.y for pr in probs], lattices=lats)
+    code = runner.run()
+    torch.cuda.synchronize()
+    assert code == ie.OK
+    Xs, mus = runner.results()
+    st = runner.stats(code)
+    off = 0
+    totals = np.zeros(ie.NUM_COUNTERS, dtype=np.int64)
+    for j, (pr, P, (s, p)) in enumerate(zip(probs, Ps, nodes)):
+        say("single", j, pr.name)
+        Xa, mu, s1, sm = run_single(P, pr, s, p, make_opts(domain, precision, P))
+        assert np.array_equal(Xs[j].cpu().numpy(), Xa), (j, pr.name)
+        assert np.array_equal(mus[j].cpu().numpy(), mu), (j, pr.name)
+        S = len(s) * pr.N
+        assert np.array_equal(st.iters[off:off + S], s1.iters)
+        assert np.array_equal(st.relres[off:off + S], s1.relres)
+        assert st.iters[off + S] == sm.iters[0] and st.relres[off + S] == sm.relres[0]
+        totals += s1.counters + sm.counters
+        off += S + 1
+    assert off == len(st.iters)
+    assert st.converged.all()
+    for c in (ie.CNT_APPLIES, ie.CNT_ITERATIONS, ie.CNT_SWEEPS, ie.CNT_NOT_CONVERGED):
+        assert st.counter(c) == totals[c], c
+    assert st.counter(ie.CNT_STATUS) == 0
+
+
+def test_batched_instance_matches_oracle():
+    probs = batch()
+    Ps = [ie.Problem.from_synthetic(pr) for pr in probs]
+    nodes = [ie.quadrature_elliptic(pr.Q, pr.ell) for pr in probs]
+    say("batched vs oracle")
+    runner = ie.BatchedRunner(Ps, nodes, ie.default_opts(), ys=[pr.y for pr in probs])
+    runner.run()
+    torch.cuda.synchronize()
+    Xs, mus = runner.results()
+    for j in (1, 2):
+        pr = probs[j]
+        dp = ref.DenseProblem.from_problem(pr)
+        s0, p0, _ = ref.quadrature_elliptic(pr.Q, pr.ell)
+        want = np.sqrt(pr.N - 1) * ref.perturbation_update_quadrature(dp, s0, p0)
+        got = Xs[j].cpu().numpy()
+        assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-6, pr.name
+        mwant = ref.mean_update_cholesky(dp, pr.y)
+        assert np.linalg.norm(mus[j].cpu().numpy() - mwant) / np.linalg.norm(mwant) < 1e-6
+
+
+def test_batched_without_host_sync_matches():
+    probs = batch()
+    Ps = [ie.Problem.from_synthetic(pr) for pr in probs]
+    nodes = [ie.quadrature_elliptic(pr.Q, pr.ell) for pr in probs]
+    lats = [P.lattice() for P in Ps]
+    say("batched host_sync 0")
+    base = ie.BatchedRunner(Ps, nodes, make_opts("lattice", ie.MIXED_BF16, max_iter=200),
+                            ys=[pr.y for pr in probs], lattices=lats)
+    base.run()
+    torch.cuda.synchronize()
+    nosync = ie.BatchedRunner(Ps, nodes, make_opts("lattice", ie.MIXED_BF16, max_iter=200, host_sync=0),
+                              ys=[pr.y for pr in probs], lattices=lats)
+    assert nosync.run() == ie.OK
+    torch.cuda.synchronize()
+    st = nosync.stats()
+    assert st.counter(ie.CNT_STATUS) == 0 and st.counter(ie.CNT_NOT_CONVERGED) == 0
+    (xa, ma), (xb, mb) = base.results(), nosync.results()
+    for j in range(len(probs)):
+        assert np.array_equal(xa[j].cpu().numpy(), xb[j].cpu().numpy()), j
+        assert np.array_equal(ma[j].cpu().numpy(), mb[j].cpu().numpy()), j
+
+
+def test_batched_reports_failing_instance():
+    probs = batch()
+    probs[3].r_var = probs[3].r_var.copy()
+    probs[3].r_var[7] = -1.0   # detected on the device by the input checks
+    Ps = [ie.Problem.from_synthetic(pr) for pr in probs]
+    nodes = [ie.quadrature_elliptic(pr.Q, pr.ell) for pr in probs]
+    say("batched failing instance")
+    runner = ie.BatchedRunner(Ps, nodes, ie.default_opts(), ys=[pr.y for pr in probs])
+    with pytest.raises(ie.InfoEsrfError) as e:
+        runner.run()
+    torch.cuda.synchronize()
+    assert e.value.code == ie.ERR_INVALID_ARG and "instance 3" in str(e.value)
+    Xs, _ = runner.results()
+    # the other instances are still solved
+    Xa, _ = ie.perturbation_update(Ps[0], *nodes[0], ie.default_opts())
+    assert np.array_equal(Xs[0].cpu().numpy(), Xa.cpu().numpy())
