@@ -9,8 +9,9 @@ quadrature combine and the final state-space apply.  Inputs are resident in
 HBM before the timed region.
 
 Printed: one JSON line with the solve rate, the roofline position of the
-dominant kernel (the covariance apply, timed live with HIP events on its
-stream), the rate of plain GPU PCG (FP64, state-space applies, masked
+dominant kernel (the instrumented kernel with the most time: a covariance
+apply or the fused PCG step, timed live with HIP events on its stream), the
+rate of plain GPU PCG (FP64, operator-form state-space applies, masked
 systems, no compaction) and the CPU oracle timed on a bounded sample.
 """
 import argparse
@@ -24,8 +25,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0}   # MI355X dense matrix peaks: FP64, FP32, BF16
-PREC_NAME = {0: "fp64", 1: "fp32", 2: "bf16"}
+PEAK_HBM_GBS = 8000.0                            # MI355X HBM3E
 DTYPE = {0: "f64", 1: "f32/f64", 2: "bf16/f64"}
+# profile slots of the covariance applies: (kernel, bound, MFMA peak key)
+SLOTS = {0: ("k_cov_stencil<fp64>", "mfma", 0), 1: ("k_cov_stencil<fp32>", "mfma", 1),
+         2: ("k_cov_bf16", "mfma", 2), 3: ("k_band_apply<fp64>", "hbm", None),
+         4: ("k_band_apply<fp32>", "hbm", None), 5: ("k_pcg_fused", "hbm", None)}
+SRC = {0: "cov_apply.hip", 1: "cov_apply.hip", 2: "cov_apply.hip", 3: "band.hip", 4: "band.hip", 5: "pcg.hip"}
 
 
 def parse():
@@ -33,9 +39,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="bf16")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64")
     ap.add_argument("--domain", choices=["state", "lattice"], default="lattice")
     ap.add_argument("--solver", choices=["plain", "compact"], default="compact")
+    ap.add_argument("--form", choices=["auto", "operator", "band"], default="auto",
+                    help="covariance form: explicit band of P, or the operator form sum_i z_i o L(z_i o v)")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -52,16 +60,18 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def traffic_record(src_path):
-    """HBM traffic per launch from a committed rocprofv3 counter summary, if the kernel is unchanged."""
-    path = os.path.join(ROOT, "profiles", "cov_apply_traffic.json")
+def traffic_record(src_path, kernel):
+    """HBM traffic per launch of `kernel` from the committed rocprofv3 counter summary
+    (profiles/traffic.json, one record per kernel family), if its source is unchanged since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    sha = hashlib.sha256(open(src_path, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    recs = json.load(open(path))
+    rec = recs.get(kernel.split("<")[0])
+    if not rec:
         return None
-    return rec
+    sha = hashlib.sha256(open(src_path, "rb").read()).hexdigest()
+    return rec if rec.get("source_sha256") == sha else None
 
 
 def main():
@@ -83,7 +93,8 @@ def main():
     log("workload", prob.name, "precision", a.precision, "domain", a.domain, "solver", a.solver)
     P = ie.Problem.from_synthetic(prob)
     s, p = ie.quadrature_elliptic(prob.Q, prob.ell)
-    kw = dict(precision=prec, solver=ie.SOLVER_PLAIN if a.solver == "plain" else ie.SOLVER_COMPACT)
+    kw = dict(precision=prec, solver=ie.SOLVER_PLAIN if a.solver == "plain" else ie.SOLVER_COMPACT,
+              cov_form={"auto": ie.COV_AUTO, "operator": ie.COV_OPERATOR, "band": ie.COV_BAND}[a.form])
     if a.domain == "lattice":
         kw.update(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=P.lattice())
     opts = ie.default_opts(**kw)
@@ -105,14 +116,22 @@ def main():
         log("iterations: total", int(st.iters.sum()), "max", int(st.iters.max()), "mean", float(st.iters.mean()),
             "sweeps", st.counter(ie.CNT_SWEEPS), "not converged", st.counter(ie.CNT_NOT_CONVERGED))
 
+    # one profiled step finds the dominant kernel; the timed steps then carry events around that
+    # kernel only, so the measurement perturbs the timeline as little as possible
     ie.profile_enable(True)
+    run.run()
+    torch.cuda.synchronize()
+    ms0 = ie.profile_read()[0]
+    dom = max(range(len(ms0)), key=lambda i: ms0[i])
+    ie.profile_enable(True)
+    ie.profile_select([dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
         code = run.run()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms, launches, vectors, flops = ie.profile_read()
+    ms, launches, vectors, flops, nbytes = ie.profile_read()   # one entry per profile slot
     ie.profile_enable(False)
     st = run.stats(code)
     assert st.counter(ie.CNT_NOT_CONVERGED) == 0, "systems missed rtol"
@@ -120,19 +139,28 @@ def main():
     value = systems * a.steps / (t1 - t0)
     log(f"{value:.1f} solves/s, {ms_step:.3f} ms/step")
 
-    dom = max(range(3), key=lambda i: ms[i])
-    achieved = flops[dom] / (ms[dom] * 1e-3) / 1e12 if ms[dom] > 0 else 0.0
+    kname, bound, pk = SLOTS[dom]
+    secs = ms[dom] * 1e-3
     avg_ms = ms[dom] / max(launches[dom], 1)
-    src = os.path.join(ROOT, "paper_2503_00253_amd", "csrc", "cov_apply.hip")
-    tr = traffic_record(src)
-    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dom], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_TFLOPS[dom], 4),
+    src = os.path.join(ROOT, "paper_2503_00253_amd", "csrc", SRC[dom])
+    tr = traffic_record(src, kname)
+    if bound == "mfma":
+        achieved = flops[dom] / secs / 1e12 if secs > 0 else 0.0
+        peak, unit = PEAK_TFLOPS[pk], "TFLOP/s"
+    else:
+        achieved = nbytes[dom] / secs / 1e9 if secs > 0 else 0.0
+        peak, unit = PEAK_HBM_GBS, "GB/s"
+    roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4),
             "traffic": (tr or {}).get("bytes_per_launch"),
-            "kernel": "k_cov_bf16" if dom == 2 else f"k_cov_stencil<{PREC_NAME[dom]}>", "launches": launches[dom],
-            "avg_launch_ms": round(avg_ms, 4), "vectors": vectors[dom],
+            "kernel": kname, "launches": launches[dom], "avg_launch_ms": round(avg_ms, 4), "vectors": vectors[dom],
             "flops_per_launch": flops[dom] / max(launches[dom], 1),
-            "flops_per_vector": flops[dom] / max(vectors[dom], 1)}
+            "flops_per_vector": flops[dom] / max(vectors[dom], 1),
+            "bytes_per_launch": nbytes[dom] / max(launches[dom], 1),
+            "time_share": round(ms[dom] / (ms_step * a.steps), 4)}
     log("roofline", roof)
+    log("profile slots ms", [round(x, 3) for x in ms], "launches", launches)
+    roof["first_step_ms_by_kernel"] = {SLOTS[i][0]: round(ms0[i], 3) for i in range(len(ms0)) if ms0[i] > 0}
 
     out = {"metric": "shifted SPD solves/s at rel-res 1e-8", "value": round(value, 2), "unit": "solves/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
@@ -140,13 +168,14 @@ def main():
            "data": "synthetic",
            "config": {"workload": prob.name, "n": prob.n, "N": prob.N, "m": prob.m, "Q": prob.Q,
                       "systems_per_step": systems, "rtol": 1e-8, "precision": a.precision,
-                      "apply_domain": a.domain, "solver": a.solver, "n_ritz": 10},
+                      "apply_domain": a.domain, "solver": a.solver, "cov_form": a.form, "n_ritz": 10},
            "iterations": {"total": int(st.iters.sum()), "max": int(st.iters.max()),
                           "fp64_sweeps": st.counter(ie.CNT_SWEEPS)},
            "roofline": roof}
 
     if not a.no_plain:
-        popts = ie.default_opts(precision=ie.FP64, solver=ie.SOLVER_PLAIN)
+        # the plain baseline: FP64 operator-form applies in the state space, masked systems
+        popts = ie.default_opts(precision=ie.FP64, solver=ie.SOLVER_PLAIN, cov_form=ie.COV_OPERATOR)
         prun = ie.PerturbationRunner(P, s, p, popts)
         prun.run()
         torch.cuda.synchronize()
@@ -194,7 +223,8 @@ def bench_batched(a, prec):
     Ps = [ie.Problem.from_synthetic(pr) for pr in probs]
     nodes = [ie.quadrature_elliptic(pr.Q, pr.ell) for pr in probs]
     systems = sum(pr.Q * pr.N for pr in probs)
-    kw = dict(precision=prec, solver=ie.SOLVER_PLAIN if a.solver == "plain" else ie.SOLVER_COMPACT)
+    kw = dict(precision=prec, solver=ie.SOLVER_PLAIN if a.solver == "plain" else ie.SOLVER_COMPACT,
+              cov_form={"auto": ie.COV_AUTO, "operator": ie.COV_OPERATOR, "band": ie.COV_BAND}[a.form])
     lats = None
     if a.domain == "lattice":
         kw.update(apply_domain=ie.DOMAIN_OBS_LATTICE)

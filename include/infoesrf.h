@@ -52,6 +52,19 @@ extern "C" {
 #define INFOESRF_ERR_WORKSPACE (-4)   /* workspace NULL or smaller than required */
 #define INFOESRF_ERR_HIP (-5)         /* a HIP runtime call failed */
 
+/* ---- form of the covariance apply (Sec. 2.3) ------------------------------
+ * OPERATOR: sum_i z_i o L (z_i o v) (eq. 2.12), 2 N nnz(L) flops per vector,
+ *           no storage beyond Z; the only form for BF16 and dense L.
+ * BAND:     P = L o (Z Z^T) built once per call as an explicit band with the
+ *           stencil's sparsity ((2bz+1)(2bx+1) entries per row, FP64, plus an
+ *           FP32 copy for MIXED_FP32), then applied as a banded product,
+ *           2 nnz(L) flops per vector.  Same result up to rounding.
+ * AUTO:     BAND for a stencil localization in FP64 or MIXED_FP32 when the
+ *           band needs at most 2 GiB, else OPERATOR. */
+#define INFOESRF_COV_AUTO 0
+#define INFOESRF_COV_OPERATOR 1
+#define INFOESRF_COV_BAND 2
+
 /* ---- localization kinds ------------------------------------------------- */
 #define INFOESRF_LOC_STENCIL 1 /* stationary stencil on an nz x nx grid */
 #define INFOESRF_LOC_DENSE 0   /* explicit n x n matrix (small n, tests) */
@@ -153,9 +166,10 @@ typedef struct infoesrf_opts {
   uint64_t seed;        /* seed of the library's own sketch generator when sketch == NULL */
   const double* sketch; /* device m x (n_ritz+oversample) Gaussian test matrix, or NULL */
   const void* net;      /* warm-start network from infoesrf_net_load (LEARNED only) */
-  int32_t tile_rows;    /* covariance-apply tile variant: 0 = default; 16, 32, 64, 128 select blocks of
+  int32_t tile_rows;    /* operator-form tile variant: 0 = default; 16, 32, 64, 128 select blocks of
                            16x32, 32x32, 64x16, 64x32 (rows x systems) */
-  int32_t reserved[7];
+  int32_t cov_form;     /* INFOESRF_COV_AUTO | INFOESRF_COV_OPERATOR | INFOESRF_COV_BAND */
+  int32_t reserved[6];
 } infoesrf_opts;
 
 /* Per-system results (device arrays, each may be NULL).  Systems of the
@@ -275,18 +289,32 @@ void infoesrf_net_free(void* net);
 
 /*
  * Measurement hooks (results are unaffected).  While enabled, every launch of
- * the covariance-apply kernel is bracketed by HIP events recorded on the
- * stream it runs on, and the kernel adds the number of vectors it applies and
- * their algorithmic FLOPs (2 N nnz(L) + 3 n N per vector, nnz(L) = nonzeros of
- * the localization on the grid the launch uses) to device counters.
- * infoesrf_profile_read synchronizes the device and returns, per apply
- * precision (index 0 FP64, 1 FP32, 2 BF16), the summed kernel time in ms, the
- * number of launches, the vectors applied and the FLOPs.  Enabling resets the
- * totals.  The hook allocates its event pool and counters when enabled; it is
- * meant for benchmarks, not for the update path.  Not thread-safe.
+ * a covariance-apply kernel is bracketed by HIP events recorded on the stream
+ * it runs on, and the kernel adds the number of vectors it applies and their
+ * algorithmic FLOPs to device counters: 2 N nnz(L) + 3 n N per vector in
+ * operator form, 2 nnz(L) in band form (nnz(L) = nonzeros of the localization
+ * on the grid the launch uses, n its rows).  Algorithmic bytes are counted as
+ * well: per vector one read of its input column and one write of its output
+ * column; per launch one read of the band (band form) or of Z (operator form).
+ * infoesrf_profile_read synchronizes the device and returns, per slot
+ * (INFOESRF_PROF_*), the summed kernel time in ms, the launches, the vectors
+ * applied, the FLOPs and the bytes.  Enabling resets the totals.  The hook
+ * allocates its event pool and counters when enabled; it is meant for
+ * benchmarks, not for the update path.  Launches from several threads are
+ * serialized by a lock while it is on.
  */
+#define INFOESRF_PROF_OP_FP64 0
+#define INFOESRF_PROF_OP_FP32 1
+#define INFOESRF_PROF_OP_BF16 2
+#define INFOESRF_PROF_BAND_FP64 3
+#define INFOESRF_PROF_BAND_FP32 4
+#define INFOESRF_PROF_PCG 5 /* the fused PCG step: vectors = live systems, bytes per system 6-8 m-vector passes */
+#define INFOESRF_PROF_SLOTS 6
 int infoesrf_profile_enable(int on);
-int infoesrf_profile_read(double ms[3], int64_t launches[3], int64_t vectors[3], double flops[3]);
+/* Restricts the hook to the slots whose bit (1 << slot) is set in mask (all slots after enabling);
+ * launches of other slots then run without events.  Fewer event pairs perturb the timeline less. */
+int infoesrf_profile_select(uint32_t mask);
+int infoesrf_profile_read(double ms[6], int64_t launches[6], int64_t vectors[6], double flops[6], double bytes[6]);
 
 #ifdef __cplusplus
 }

@@ -210,6 +210,7 @@ struct Options {
   const double* sketch;
   int warm;
   const void* net;
+  bool band;  // covariance applies through the explicit band of P
 };
 
 struct Inst {
@@ -226,6 +227,10 @@ struct Inst {
   int32_t* flags = nullptr;
   int32_t* fallbacks = nullptr;
   int64_t* counters = nullptr;
+  // explicit bands of P (band form): state grid, and observed lattice (obs domain); FP64 and,
+  // for MIXED_FP32 inner applies in that domain, an FP32 copy
+  bool band = false;
+  void *bandS = nullptr, *bandS32 = nullptr, *bandO = nullptr, *bandO32 = nullptr;
 };
 
 // Solver state: observation-space vectors are system-major, system s at s * ldm.
@@ -320,6 +325,18 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   IE_CHECK(o->tile_rows == 0 || o->tile_rows == 16 || o->tile_rows == 32 || o->tile_rows == 64 ||
                o->tile_rows == 128,
            INFOESRF_ERR_INVALID_ARG, "tile_rows must be 0, 16, 32, 64 or 128");
+  IE_CHECK(o->cov_form >= INFOESRF_COV_AUTO && o->cov_form <= INFOESRF_COV_BAND, INFOESRF_ERR_INVALID_ARG,
+           "unknown cov_form");
+  {
+    const bool stencil = P->loc.kind == INFOESRF_LOC_STENCIL;
+    const bool prec_ok = o->precision != INFOESRF_MIXED_BF16;
+    IE_CHECK(o->cov_form != INFOESRF_COV_BAND || (stencil && prec_ok), INFOESRF_ERR_INVALID_ARG,
+             "the band form needs a stencil localization and FP64 or MIXED_FP32");
+    const double planes = stencil ? (double)(2 * P->loc.bz + 1) * (2 * P->loc.bx + 1) : 0.0;
+    const double bytes = planes * (double)round_up(P->n, 64) * 12.0;  // FP64 + FP32 copies, state grid
+    op.band = o->cov_form == INFOESRF_COV_BAND ||
+              (o->cov_form == INFOESRF_COV_AUTO && stencil && prec_ok && bytes <= 2.0 * (1ull << 30));
+  }
   op.rtol = o->rtol;
   op.max_iter = o->max_iter;
   op.p = p;
@@ -361,7 +378,9 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   in.m = P->m;
   in.dense = (P->loc.kind == INFOESRF_LOC_DENSE);
   in.obs = op.obs;
-  const bool low = (op.inner != Prec::F64);
+  in.band = op.band;
+  // the operator form in a low precision needs FP32 copies of Z and the stencil
+  const bool low = (op.inner != Prec::F64) && !op.band;
   in.mu = ar.take<double>(in.n);
   in.Z = ar.take<double>(in.n * in.N);
   in.Z32 = (low && !in.obs) ? ar.take<float>(in.n * in.N) : nullptr;
@@ -382,6 +401,18 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
     const int pz = L.periodic_z && (int64_t)a.nzo * a.sz == L.nz;
     const int px = L.periodic_x && (int64_t)a.nxo * a.sx == L.nx;
     in.go = Grid{a.nzo, a.nxo, pz, px, bzs, bxs, in.subtab, in.subtab32, nullptr};
+  }
+  if (in.band) {
+    const infoesrf_loc& L = P->loc;
+    const bool f32 = op.inner == Prec::F32;
+    const int64_t ps = (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1) * ld64(in.n);
+    in.bandS = ar.take<double>(ps);
+    in.bandS32 = (f32 && !in.obs) ? ar.take<float>(ps) : nullptr;
+    if (in.obs) {
+      const int64_t po = (int64_t)(2 * in.go.bz + 1) * (2 * in.go.bx + 1) * ld64(in.m);
+      in.bandO = ar.take<double>(po);
+      in.bandO32 = f32 ? ar.take<float>(po) : nullptr;
+    }
   }
   in.col_cnt = ar.take<int32_t>(in.n);
   in.col_ptr = ar.take<int32_t>(in.n + 1);
@@ -433,8 +464,8 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
     pr.evals = ar.take<double>(op.k);
     pr.Rinv = ar.take<double>(op.k * op.k);
     pr.sel = ar.take<double>(op.k * op.p);
-    pr.Phi = ar.take<double>(in.m * op.p);
-    pr.SPhi = ar.take<double>(in.m * op.p);
+    pr.Phi = ar.take<double>(sy.ldm * op.p);
+    pr.SPhi = ar.take<double>(sy.ldm * op.p);
     pr.theta = ar.take<double>(op.p);
     pr.G = ar.take<double>(3 * op.p * op.p);
     pr.gscr = ar.take<double>(((in.m + 127) / 128) * op.k * op.k);
@@ -493,7 +524,12 @@ int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* 
     if (zero_counter) IE_HIP(launch_fill_i32(zero_counter, 0, 2, st));
     zero_counter = nullptr;
   }
-  if (prec == Prec::BF16) {
+  if (in.band) {
+    IE_CHECK(prec != Prec::BF16, INFOESRF_ERR_INVALID_ARG, "the band form has no BF16 apply");
+    const void* band = in.obs ? (prec == Prec::F64 ? in.bandO : in.bandO32)
+                              : (prec == Prec::F64 ? in.bandS : in.bandS32);
+    IE_HIP(cov_band_timed(prec, g, band, ldr, pl.bf.V, ldr, pl.bf.cols, Bpad, nact, pl.bf.T, ldr, st, zero_counter));
+  } else if (prec == Prec::BF16) {
     IE_CHECK(!in.dense, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
     const float* Zu = in.obs ? in.Zt32 : in.Z32;
     IE_HIP(cov_bf16_timed(g, Zu, rows, in.N, (const __hip_bfloat16*)pl.bf.V, ldr, pl.bf.cols, Bpad, nact,
@@ -523,7 +559,10 @@ int apply_state(Plan& pl, const double* U, int64_t ld, const int32_t* act, const
   const int64_t ldr = ld64(in.n);
   IE_HIP(launch_scatter_state(Prec::F64, U, ld, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n, in.m,
                               Bpad, pl.bf.V, ldr, st));
-  if (in.dense) {
+  if (in.band) {
+    IE_HIP(cov_band_timed(Prec::F64, in.gs, in.bandS, ldr, pl.bf.V, ldr, pl.bf.cols, ncols, nullptr, pl.bf.T, ldr,
+                          st));
+  } else if (in.dense) {
     IE_HIP(launch_cov_dense(in.P->loc.dense, in.Z, in.n, in.N, (const double*)pl.bf.V, ldr, ncols,
                             (double*)pl.bf.T, ldr, st));
   } else {
@@ -570,21 +609,35 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
   }
   // 2. ensemble and observation-space setup (indices are guarded against invalid values, which
   //    can only reach here when host_sync == 0; the flag then sets the call's status)
-  const bool low = (op.inner != Prec::F64);
+  // FP32 copies of Z and of the stencil exist only for the operator form in a low precision
+  // (plan_layout allocates them under the same condition)
+  const bool low = (op.inner != Prec::F64) && !in.band;
   IE_HIP(launch_ens_stats(P->X, in.n, in.N, in.mu, in.Z, in.Z32, st));
   IE_HIP(launch_diag_S(P->h_ptr, P->h_idx, P->h_w, P->r_var, in.Z, in.n, in.N, in.m, in.gs,
                        in.dense ? P->loc.dense : nullptr, in.diagS, st));
   IE_HIP(launch_min_reduce(in.diagS, in.m, in.dmin, st));
   if (!in.dense && low) {
     const infoesrf_loc& L = P->loc;
+    IE_CHECK(in.tab32 != nullptr, INFOESRF_ERR_HIP, "internal: FP32 stencil copy not allocated");
     IE_HIP(launch_convert_f32(L.table, in.tab32, (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1), st));
   }
   if (in.obs) {
     IE_HIP(launch_lattice_members(P->h_idx, P->h_w, P->r_var, in.Z, in.n, in.N, in.m, in.Zt, in.Zt32, st));
     const infoesrf_loc& L = P->loc;
     IE_HIP(launch_subsample_table(L.table, L.bz, L.bx, op.lat.sz, op.lat.sx, in.go.bz, in.go.bx, in.subtab, st));
-    if (low)
+    if (low) {
+      IE_CHECK(in.subtab32 != nullptr, INFOESRF_ERR_HIP, "internal: FP32 lattice stencil not allocated");
       IE_HIP(launch_convert_f32(in.subtab, in.subtab32, (int64_t)(2 * in.go.bz + 1) * (2 * in.go.bx + 1), st));
+    }
+  }
+  // 3. explicit bands of P (band form): one pass over the members each
+  if (in.band) {
+    IE_HIP(launch_band_build(Prec::F64, in.gs, in.Z, in.n, in.N, in.bandS, ld64(in.n), st));
+    if (in.bandS32) IE_HIP(launch_band_build(Prec::F32, in.gs, in.Z, in.n, in.N, in.bandS32, ld64(in.n), st));
+    if (in.obs) {
+      IE_HIP(launch_band_build(Prec::F64, in.go, in.Zt, in.m, in.N, in.bandO, ld64(in.m), st));
+      if (in.bandO32) IE_HIP(launch_band_build(Prec::F32, in.go, in.Zt, in.m, in.N, in.bandO32, ld64(in.m), st));
+    }
   }
   return 0;
 }
@@ -620,9 +673,9 @@ int stage_precond(Plan& pl, const Options& op, hipStream_t st) {
   IE_HIP(launch_sym_eig(pr.Tk, k, pr.evec, pr.evals, st));
   IE_HIP(launch_lmp_finish(pr.evals, pr.evec, k, pr.p, pr.theta, pr.sel, st));
   const int p = pr.p;
-  IE_HIP(launch_right_mult(Qs, in.m, k, pr.sel, p, pr.Phi, p, 1, st));    // row-major m x p
-  IE_HIP(launch_right_mult(SQs, in.m, k, pr.sel, p, pr.SPhi, p, 1, st));
-  const Strided Ph{pr.Phi, p, 1}, SPh{pr.SPhi, p, 1};
+  IE_HIP(launch_right_mult(Qs, in.m, k, pr.sel, p, pr.Phi, 1, ldm, st));  // column-major m x p, ld = ldm
+  IE_HIP(launch_right_mult(SQs, in.m, k, pr.sel, p, pr.SPhi, 1, ldm, st));
+  const Strided Ph{pr.Phi, 1, ldm}, SPh{pr.SPhi, 1, ldm};
   IE_HIP(launch_gram(Ph, Ph, in.m, p, pr.G, pr.gscr, st));
   IE_HIP(launch_gram(Ph, SPh, in.m, p, pr.G + p * p, pr.gscr, st));
   IE_HIP(launch_gram(SPh, SPh, in.m, p, pr.G + 2 * p * p, pr.gscr, st));
@@ -702,6 +755,7 @@ LMP lmp_of(Plan& pl) {
   l.p = pl.pr.p;
   l.Phi = pl.pr.Phi;
   l.SPhi = pl.pr.SPhi;
+  l.ld = pl.sy.ldm;
   l.theta = pl.pr.theta;
   l.G = pl.pr.G;
   l.dmin = pl.in.dmin;
@@ -777,7 +831,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
     int32_t *act_c = sy.act, *nact_c = sy.nact, *act_n = sy.act2, *nact_n = sy.nact2;
     int64_t hint = plain ? S : (int64_t)h_nact;  // upper bound of the live count on the device
     IE_HIP(launch_fill_i32(nact_n, 0, 2, st));
-    IE_HIP(launch_pcg_fused(op.inner, ps, lmp, 0, in.obs ? 1 : 0, plain ? 1 : 0, nullptr, ldr, act_c, nact_c, act_n,
+    IE_HIP(pcg_fused_timed(op.inner, ps, lmp, 0, in.obs ? 1 : 0, plain ? 1 : 0, nullptr, ldr, act_c, nact_c, act_n,
                             nact_n, round_up(hint, kSysTile), Vbuf, ldr, in.P->h_ptr, in.P->h_idx, in.P->h_w,
                             in.P->r_var, in.n, st));
     std::swap(act_c, act_n);
@@ -789,7 +843,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
       // the apply also clears the list counter that the fused kernel fills
       IE_TRY(apply_S(pl, op.inner, sy.p, ldm, act_c, nact_c, bp, sy.sigma, nullptr, op.rows_per_wave, st,
                      /*v_ready=*/in.obs, nact_n));
-      IE_HIP(launch_pcg_fused(op.inner, ps, lmp, 1, in.obs ? 1 : 0, plain ? 1 : 0, pl.bf.T, ldr, act_c, nact_c, act_n,
+      IE_HIP(pcg_fused_timed(op.inner, ps, lmp, 1, in.obs ? 1 : 0, plain ? 1 : 0, pl.bf.T, ldr, act_c, nact_c, act_n,
                               nact_n, bp, Vbuf, ldr, in.P->h_ptr, in.P->h_idx, in.P->h_w, in.P->r_var, in.n, st));
       std::swap(act_c, act_n);
       std::swap(nact_c, nact_n);
@@ -799,7 +853,9 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
         int got = poll.drain(&seen);
         IE_TRY(got);
         if (!got && (it % check_every) == 0) {
-          got = poll.post(nact_c + 1, st, &seen);  // live count (the masked list keeps every system)
+          // live count: the compacted list holds exactly the live systems; the masked list
+          // keeps every system and counts the live ones separately
+          got = poll.post(plain ? nact_c + 1 : nact_c, st, &seen);
           IE_TRY(got);
         }
         if (got) {
@@ -1029,6 +1085,7 @@ size_t infoesrf_cov_apply_workspace_bytes(const infoesrf_problem* prob, int64_t 
   ar.take<float>((2 * prob->loc.bz + 1) * (2 * prob->loc.bx + 1));
   ar.take<float>(ldr * cols);                // low-precision V
   ar.take<float>(ldr * cols);                // FP32 T
+  if (op.band) ar.take<double>((int64_t)(2 * prob->loc.bz + 1) * (2 * prob->loc.bx + 1) * ldr);  // band
   return ar.off + 256;
 }
 
@@ -1056,9 +1113,27 @@ int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ld
   float* tab32 = ar.take<float>((2 * prob->loc.bz + 1) * (2 * prob->loc.bx + 1));
   void* Vlow = ar.take<float>(ldr * B);
   float* T32 = ar.take<float>(ldr * B);
+  void* band = op.band ? ar.take<double>((int64_t)(2 * prob->loc.bz + 1) * (2 * prob->loc.bx + 1) * ldr) : nullptr;
   const bool low = op.inner != Prec::F64;
   IE_HIP(launch_ens_stats(prob->X, n, N, mu, Z, low ? Z32 : nullptr, st));
-  if (prob->loc.kind == INFOESRF_LOC_DENSE) {
+  if (op.band) {
+    const infoesrf_loc& L = prob->loc;
+    const Grid g{L.nz, L.nx, L.periodic_z, L.periodic_x, L.bz, L.bx, L.table, nullptr, nullptr};
+    // the FP32 band fits in the FP64 band's storage
+    IE_HIP(launch_band_build(op.inner, g, Z, n, N, band, ldr, st));
+    if (!low) {
+      IE_HIP(cov_band_timed(Prec::F64, g, band, ldr, V, ldv, B, B, nullptr, PV, ldpv, st));
+    } else {
+      float* V32 = static_cast<float*>(Vlow);
+      hipLaunchKernelGGL((k_convert_cols<double, float>), dim3(nb(ldr * B)), dim3(256), 0, st, V, ldv, n, B, V32,
+                         ldr, 1);
+      IE_HIP(hipGetLastError());
+      IE_HIP(cov_band_timed(Prec::F32, g, band, ldr, V32, ldr, B, B, nullptr, T32, ldr, st));
+      hipLaunchKernelGGL((k_convert_cols<float, double>), dim3(nb(ldpv * B)), dim3(256), 0, st, T32, ldr, n, B, PV,
+                         ldpv, 0);
+      IE_HIP(hipGetLastError());
+    }
+  } else if (prob->loc.kind == INFOESRF_LOC_DENSE) {
     IE_CHECK(!low, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
     IE_HIP(launch_cov_dense(prob->loc.dense, Z, n, N, V, ldv, B, PV, ldpv, st));
   } else {

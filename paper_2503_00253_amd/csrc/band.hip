@@ -1,0 +1,229 @@
+// Localized covariance held as an explicit band (Sec. 2.3, eq. 2.11).
+//
+// P = L o (Z Z^T) has the sparsity of the stationary stencil L: row r couples only to the
+// (2bz+1)(2bx+1) grid neighbours r + (dz, dx).  Its entries
+//
+//   band[j, r] = L(dz, dx) * sum_i Z[r, i] Z[r + (dz, dx), i],   j = (dz + bz)(2bx + 1) + (dx + bx)
+//
+// cost one pass over the members (N fused multiply-adds per entry, done once per update), after
+// which an apply is a banded product, 2 nnz(L) flops per vector instead of the 2 N nnz(L) of the
+// operator form sum_i z_i o L (z_i o v) (eq. 2.12).  The operator form stays the path for grids
+// whose band does not fit in memory; both give P V up to rounding.
+//
+// Layout: band[j * ldb + r] (one plane per stencil offset, rows contiguous, so the lanes of a
+// wavefront read consecutive rows of one plane).  Entries whose neighbour falls off a
+// non-periodic grid are 0.
+#include <atomic>
+
+#include "internal.hpp"
+
+namespace infoesrf {
+
+namespace {
+
+__device__ inline int wrap_idx(int a, int n) {
+  a %= n;
+  return a < 0 ? a + n : a;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_band_build(Grid g, const double* __restrict__ Z, int64_t ldz, int N,
+                                                    T* __restrict__ band, int64_t ldb) {
+  const int rows = g.nz * g.nx;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (r >= rows) return;
+  const int w = 2 * g.bx + 1;
+  const int dz = j / w - g.bz, dx = j % w - g.bx;
+  const int z = r / g.nx, x = r % g.nx;
+  int zz = z + dz, xx = x + dx;
+  bool ok = true;
+  if (g.pz) zz = wrap_idx(zz, g.nz);
+  else ok = ok && zz >= 0 && zz < g.nz;
+  if (g.px) xx = wrap_idx(xx, g.nx);
+  else ok = ok && xx >= 0 && xx < g.nx;
+  double v = 0.0;
+  const double l = g.table[j];
+  if (ok && l != 0.0) {
+    const int64_t c = (int64_t)zz * g.nx + xx;
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s = fma(Z[(int64_t)i * ldz + r], Z[(int64_t)i * ldz + c], s);
+    v = l * s;
+  }
+  band[(int64_t)j * ldb + r] = (T)v;
+}
+
+// T[:, b] = band * V[:, b] for the listed columns b < B (B from Bdev when given).
+// Block: TX = 64 consecutive x of one layer (one lane each) x NSB systems (the four waves take
+// systems w, w + 4, ...).  For each stencil layer the block stages the V window
+// [x0 - bx, x0 + 64 + bx) of its systems in LDS; every lane then runs over the 2bx + 1 offsets,
+// loading each band entry once (eight at a time, so the loads overlap) and using it for its
+// NSB / 4 systems.
+template <typename T, int NSB>
+__global__ __launch_bounds__(256) void k_band_apply(Grid g, const T* __restrict__ band, int64_t ldb,
+                                                    const T* __restrict__ V, int64_t ldv, int64_t vcols, int B,
+                                                    const int32_t* __restrict__ Bdev, T* __restrict__ Tout,
+                                                    int64_t ldt, int tiles_per_layer, ProfDev prof,
+                                                    int32_t* __restrict__ zero_counter) {
+  constexpr int TX = 64;
+  constexpr int PER = NSB / 4;
+  if (Bdev) B = *Bdev;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (zero_counter) {  // list and live counters of the next PCG step (nobody reads them now)
+      zero_counter[0] = 0;
+      zero_counter[1] = 0;
+    }
+    if (prof.vectors) {
+      atomicAdd(prof.vectors, (unsigned long long)B);
+      atomicAdd(prof.flops, (double)B * prof.flops_per_vector);
+      atomicAdd(prof.bytes, (double)B * prof.bytes_per_vector);
+    }
+  }
+  const int b0 = blockIdx.y * NSB;
+  if (b0 >= B) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  T* Vw = reinterpret_cast<T*>(smem_raw);  // NSB x WX
+  const int nx = g.nx, nz = g.nz, bx = g.bx, bz = g.bz;
+  const int WX = TX + 2 * bx;
+  const int tile = blockIdx.x;
+  const int z = tile / tiles_per_layer;
+  const int x0 = (tile % tiles_per_layer) * TX;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x = x0 + lane;
+  const bool row_ok = x < nx;
+  const int64_t r = (int64_t)z * nx + x;
+  const int w = 2 * bx + 1;
+
+  T acc[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) acc[k] = T(0);
+
+  for (int li = 0; li < 2 * bz + 1; ++li) {
+    int zz = z + li - bz;
+    if (g.pz) zz = wrap_idx(zz, nz);
+    else if (zz < 0 || zz >= nz) continue;  // uniform over the block
+    __syncthreads();
+    // each lane stages window positions t = lane, lane + 64, ... of the wave's PER columns; the
+    // PER loads of one position are independent, so they are in flight together
+    const T* vbase = V + (int64_t)zz * nx;
+    for (int t = lane; t < WX; t += 64) {
+      int kx = x0 - bx + t;
+      bool ok = true;
+      if (g.px) kx = wrap_idx(kx, nx);
+      else ok = kx >= 0 && kx < nx;
+      T v[PER];
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int c = wave + 4 * k;
+        v[k] = (ok && b0 + c < vcols) ? vbase[(int64_t)(b0 + c) * ldv + kx] : T(0);  // no column past vcols
+      }
+#pragma unroll
+      for (int k = 0; k < PER; ++k) Vw[(wave + 4 * k) * WX + t] = v[k];
+    }
+    __syncthreads();
+    if (row_ok) {
+      const T* bp = band + (int64_t)(li * w) * ldb + r;
+      const T* vw = Vw + wave * WX + lane;
+      int d = 0;
+      for (; d + 8 <= w; d += 8) {
+        T bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bv[u] = bp[(int64_t)(d + u) * ldb];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int k = 0; k < PER; ++k) acc[k] = fma(bv[u], vw[4 * k * WX + d + u], acc[k]);
+      }
+      for (; d < w; ++d) {
+        const T bv = bp[(int64_t)d * ldb];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) acc[k] = fma(bv, vw[4 * k * WX + d], acc[k]);
+      }
+    }
+  }
+  if (row_ok) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int b = b0 + wave + 4 * k;
+      if (b < B) Tout[(int64_t)b * ldt + r] = acc[k];
+    }
+  }
+}
+
+template <typename T, int NSB>
+hipError_t band_apply_typed(const Grid& g, const T* band, int64_t ldb, const T* V, int64_t ldv, int64_t vcols,
+                            int64_t B, const int32_t* Bdev, T* Tout, int64_t ldt, hipStream_t st, const ProfDev& pf,
+                            int32_t* zc) {
+  constexpr int TX = 64;
+  const int tiles_per_layer = (g.nx + TX - 1) / TX;
+  const size_t smem = sizeof(T) * (size_t)NSB * (TX + 2 * g.bx);
+  if (smem > 150 * 1024) return hipErrorInvalidValue;
+  static std::atomic<bool> attr{false};  // concurrent first calls set the same attribute twice: harmless
+  if (smem > 64 * 1024 && !attr.load(std::memory_order_acquire)) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_band_apply<T, NSB>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    if (e != hipSuccess) return e;
+    attr.store(true, std::memory_order_release);
+  }
+  dim3 grid((unsigned)(tiles_per_layer * g.nz), (unsigned)((B + NSB - 1) / NSB));
+  hipLaunchKernelGGL((k_band_apply<T, NSB>), grid, dim3(256), smem, st, g, band, ldb, V, ldv, vcols, (int)B, Bdev,
+                     Tout, ldt, tiles_per_layer, pf, zc);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+static int band_systems_per_block(const Grid& g, size_t elem, int64_t B) {
+  // widest system block whose V window stays within 48 KiB of LDS (four blocks per CU), and no
+  // wider than the batch needs
+  for (int nsb : {64, 32, 16}) {
+    if ((size_t)nsb * (64 + 2 * g.bx) * elem <= 48 * 1024 && (nsb <= 16 || B > nsb / 2)) return nsb;
+  }
+  return 8;
+}
+
+hipError_t launch_band_build(Prec prec, const Grid& g, const double* Z, int64_t ldz, int64_t N, void* band,
+                             int64_t ldb, hipStream_t st) {
+  const int rows = g.nz * g.nx;
+  const int nb = (2 * g.bz + 1) * (2 * g.bx + 1);
+  if (!band || !Z || !g.table) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((rows + 255) / 256), (unsigned)nb);
+  if (prec == Prec::F64)
+    hipLaunchKernelGGL((k_band_build<double>), grid, dim3(256), 0, st, g, Z, ldz, (int)N, (double*)band, ldb);
+  else
+    hipLaunchKernelGGL((k_band_build<float>), grid, dim3(256), 0, st, g, Z, ldz, (int)N, (float*)band, ldb);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_apply(Prec prec, const Grid& g, const void* band, int64_t ldb, const void* V, int64_t ldv,
+                             int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, hipStream_t st,
+                             const ProfDev* prof, int32_t* zc) {
+  if (B <= 0) return hipSuccess;
+  if (!band || !V || !T) return hipErrorInvalidValue;
+  const ProfDev pf = prof ? *prof : ProfDev{};
+  if (prec == Prec::F64) {
+    const double* b = (const double*)band;
+    const double* v = (const double*)V;
+    double* t = (double*)T;
+    switch (band_systems_per_block(g, sizeof(double), B)) {
+      case 64: return band_apply_typed<double, 64>(g, b, ldb, v, ldv, vcols, B, Bdev, t, ldt, st, pf, zc);
+      case 32: return band_apply_typed<double, 32>(g, b, ldb, v, ldv, vcols, B, Bdev, t, ldt, st, pf, zc);
+      case 16: return band_apply_typed<double, 16>(g, b, ldb, v, ldv, vcols, B, Bdev, t, ldt, st, pf, zc);
+      default: return band_apply_typed<double, 8>(g, b, ldb, v, ldv, vcols, B, Bdev, t, ldt, st, pf, zc);
+    }
+  }
+  if (prec == Prec::F32) {
+    const float* b = (const float*)band;
+    const float* v = (const float*)V;
+    float* t = (float*)T;
+    switch (band_systems_per_block(g, sizeof(float), B)) {
+      case 64: return band_apply_typed<float, 64>(g, b, ldb, v, ldv, vcols, B, Bdev, t, ldt, st, pf, zc);
+      case 32: return band_apply_typed<float, 32>(g, b, ldb, v, ldv, vcols, B, Bdev, t, ldt, st, pf, zc);
+      case 16: return band_apply_typed<float, 16>(g, b, ldb, v, ldv, vcols, B, Bdev, t, ldt, st, pf, zc);
+      default: return band_apply_typed<float, 8>(g, b, ldb, v, ldv, vcols, B, Bdev, t, ldt, st, pf, zc);
+    }
+  }
+  return hipErrorInvalidValue;  // the band form has FP64 and FP32 entries only
+}
+
+}  // namespace infoesrf

@@ -102,6 +102,7 @@ __global__ __launch_bounds__(256) void k_cov_stencil(Grid g, const T* __restrict
     if (prof.vectors) {
       atomicAdd(prof.vectors, (unsigned long long)B);
       atomicAdd(prof.flops, (double)B * prof.flops_per_vector);
+      atomicAdd(prof.bytes, (double)B * prof.bytes_per_vector);
     }
   }
   const int b0 = blockIdx.y * NS;
@@ -325,6 +326,7 @@ __global__ __launch_bounds__(256) void k_cov_bf16(Grid g, const float* __restric
     if (prof.vectors) {
       atomicAdd(prof.vectors, (unsigned long long)B);
       atomicAdd(prof.flops, (double)B * prof.flops_per_vector);
+      atomicAdd(prof.bytes, (double)B * prof.bytes_per_vector);
     }
   }
   const int b0 = blockIdx.y * NS;
@@ -539,7 +541,8 @@ hipError_t launch_cov_stencil(Prec prec, const Grid& g, const void* Z, int64_t l
                               int64_t ldv, int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt,
                               int rows_per_wave, hipStream_t st, const ProfDev* prof, int32_t* zero_counter) {
   if (B <= 0) return hipSuccess;
-  const ProfDev pf = prof ? *prof : ProfDev{nullptr, nullptr, 0.0};
+  if (!Z || !V || !T || (prec == Prec::F64 ? !g.table : !g.table32)) return hipErrorInvalidValue;
+  const ProfDev pf = prof ? *prof : ProfDev{};
   switch (prec) {
     case Prec::F64:
       return launch_rb<double>(rows_per_wave, g, (const double*)Z, ldz, N, (const double*)V, ldv, vcols, B, Bdev,
@@ -555,7 +558,8 @@ hipError_t launch_cov_bf16(const Grid& g, const float* Z, int64_t ldz, int64_t N
                            int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt, int tile,
                            hipStream_t st, const ProfDev* prof, int32_t* zc) {
   if (B <= 0) return hipSuccess;
-  const ProfDev pf = prof ? *prof : ProfDev{nullptr, nullptr, 0.0};
+  if (!Z || !V || !T || !g.table32) return hipErrorInvalidValue;
+  const ProfDev pf = prof ? *prof : ProfDev{};
   switch (tile) {
     case 16: return launch_bf16_typed<1, 2>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf, zc);
     case 32: return launch_bf16_typed<2, 2>(g, Z, ldz, N, V, ldk, vcols, B, Bdev, T, ldt, st, pf, zc);

@@ -285,11 +285,13 @@ hipError_t launch_subsample_table(const double* table, int32_t bz, int32_t bx, i
 }
 
 hipError_t launch_convert_f32(const double* in, float* out, int64_t count, hipStream_t st) {
+  if (count > 0 && (!in || !out)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_convert_f32, dim3(blocks_for(count)), dim3(kBlock), 0, st, in, out, count);
   return hipGetLastError();
 }
 
 hipError_t launch_convert_bf16(const double* in, __hip_bfloat16* out, int64_t count, hipStream_t st) {
+  if (count > 0 && (!in || !out)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_convert_bf16, dim3(blocks_for(count)), dim3(kBlock), 0, st, in, out, count);
   return hipGetLastError();
 }

@@ -114,6 +114,8 @@ struct ProfDev {
   unsigned long long* vectors;  // += live column count
   double* flops;                // += live column count * flops_per_vector
   double flops_per_vector;
+  double* bytes;                // += live column count * bytes_per_vector
+  double bytes_per_vector;
 };
 // B is the (padded) maximum column count; Bdev (nullable) holds the live count on the device.
 // zero_counter (nullable): two int32 counters set to 0 by the launch (the next PCG step's list and
@@ -131,6 +133,19 @@ hipError_t launch_cov_bf16(const Grid& g, const float* Z, int64_t ldz, int64_t N
 hipError_t cov_bf16_timed(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
                           int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt, int tile,
                           hipStream_t st, int32_t* zero_counter = nullptr);
+// Explicit band of P = L o (Z Z^T) on grid g (band.hip): band[j * ldb + r] for the
+// (2bz+1)(2bx+1) stencil offsets j, FP64 or FP32 entries computed in FP64 from Z (FP64,
+// column-major, ldz).
+hipError_t launch_band_build(Prec prec, const Grid& g, const double* Z, int64_t ldz, int64_t N, void* band,
+                             int64_t ldb, hipStream_t st);
+// T[:, b] = band V[:, b] for the listed columns b < B (Bdev: live count on the device), system-major
+// V (ldv, vcols columns allocated) and T (ldt); FP64 or FP32.  zero_counter as for the operator form.
+hipError_t launch_band_apply(Prec prec, const Grid& g, const void* band, int64_t ldb, const void* V, int64_t ldv,
+                             int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, hipStream_t st,
+                             const ProfDev* prof = nullptr, int32_t* zero_counter = nullptr);
+hipError_t cov_band_timed(Prec prec, const Grid& g, const void* band, int64_t ldb, const void* V, int64_t ldv,
+                          int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, hipStream_t st,
+                          int32_t* zero_counter = nullptr);
 // Measurement wrapper used by the runtime: records events around the launch when profiling is on.
 hipError_t cov_stencil_timed(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
                              int64_t ldv, int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt,
@@ -158,8 +173,9 @@ hipError_t launch_apply_finish(Prec prec, int obs_domain, const double* P, int64
 // ---------------------------------------------------------------- PCG (K4)
 struct LMP {
   int p;               // number of Ritz pairs (0 = no preconditioner)
-  const double* Phi;   // m x p row-major (Phi[r*p + j])
-  const double* SPhi;  // m x p row-major
+  const double* Phi;   // m x p column-major (Phi[j*ld + r]): a wavefront reads 64 consecutive rows
+  const double* SPhi;  // m x p column-major, same ld
+  int64_t ld;          // leading dimension of Phi and SPhi
   const double* theta; // p Ritz values of S
   const double* G;     // 3 p x p Gram matrices: Phi^T Phi, Phi^T S Phi, (S Phi)^T S Phi (row-major)
   const double* dmin;  // min diag(S) (1 value)
@@ -177,6 +193,7 @@ struct PCGState {
   int32_t* done;         // per system: 0 active, 1 converged, 2 failed/capped
   int32_t* flags;        // global error flags
   int max_iter;
+  ProfDev prof;          // measurement counters (vectors = live systems of each launch), or empty
 };
 
 // One PCG iteration for every system of the list (one workgroup per system), after the apply.
@@ -189,6 +206,14 @@ hipError_t launch_pcg_fused(Prec prec, const PCGState& s, const LMP& lmp, int mo
                             int32_t* nact_out, int64_t Bmax, void* V, int64_t ldv, const int32_t* h_ptr,
                             const int32_t* h_idx, const double* h_w, const double* r_var, int64_t n_state,
                             hipStream_t st);
+// The fused PCG step with the measurement hook (profile slot INFOESRF_PROF_PCG); arguments as
+// launch_pcg_fused.
+hipError_t pcg_fused_timed(Prec prec, const PCGState& s, const LMP& lmp, int mode, int obs_domain, int plain,
+                           const void* T, int64_t ldt, const int32_t* act, const int32_t* nact, int32_t* act_out,
+                           int32_t* nact_out, int64_t Bmax, void* V, int64_t ldv, const int32_t* h_ptr,
+                           const int32_t* h_idx, const double* h_w, const double* r_var, int64_t n_state,
+                           hipStream_t st);
+
 // Rebuild the list of active systems (done == 0), in increasing order.  One block.
 hipError_t launch_compact(const int32_t* done, int64_t S, int32_t* act, int32_t* nact, hipStream_t st);
 hipError_t launch_iota(int32_t* act, int32_t* nact, int64_t S, hipStream_t st);

@@ -124,6 +124,25 @@ __device__ inline void block_sum(const double* v, double (*sred)[4], double* out
   __syncthreads();
 }
 
+// The same sums (same order) written once to LDS: out_lds[j] for j < W, read back by every lane.
+template <int W>
+__device__ inline void block_sum_lds(const double* v, double (*sred)[4], double* out_lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    double x = v[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) sred[j][wave] = x;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < W) {
+    const int j = threadIdx.x;
+    out_lds[j] = ((sred[j][0] + sred[j][1]) + sred[j][2]) + sred[j][3];
+  }
+  __syncthreads();
+}
+
 template <int P, int RPT, typename TT, typename TV>
 __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mode, int obs_domain, int plain,
                                                    const TT* __restrict__ T, int64_t ldt,
@@ -136,23 +155,39 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
   __shared__ double sred[W][4];
   __shared__ double sG[3 * 16 * 16 + 16];
   __shared__ double scoef[2 * 16 + 2];
+  __shared__ double sdot[W];  // the reduced dots (broadcast reads; lanes index them by thread id)
   __shared__ int s_slot;
   const int c = blockIdx.x;
-  if (c >= *nact) return;
+  const int tid = threadIdx.x;
+  // The kernel is a chain of dependent steps per system, so every load that does not depend on
+  // an earlier result is issued in the same round trip: (1) the list entry with the list length
+  // (c < grid <= list capacity); (2) everything the system needs; (3) Phi, S Phi for the dots;
+  // (4) Phi, S Phi again for the preconditioned residual.
+  const int na = *nact;
   const int32_t s = act[c];
+  if (st.prof.vectors && c == 0 && tid == 0) {
+    atomicAdd(st.prof.vectors, (unsigned long long)na);
+    atomicAdd(st.prof.flops, (double)na * st.prof.flops_per_vector);
+    atomicAdd(st.prof.bytes, (double)na * st.prof.bytes_per_vector);
+  }
+  if (c >= na) return;
   const int64_t m = st.m;
   const int64_t base = (int64_t)s * st.ld;
-  const int tid = threadIdx.x;
 
-  // claim a slot in the next list (appended in any order) and write the next apply input;
-  // nact_out[0] counts the list, nact_out[1] the systems still iterating (pv != nullptr)
-  auto append = [&](const double* pv) {
+  // Next list: a system claims a slot (appended in any order) and writes its next apply input
+  // there.  nact_out[0] counts the list; in the masked solver, where retired systems stay in the
+  // list, nact_out[1] counts the systems still iterating (the compacted list holds only those).
+  // A live system claims its slot as soon as it knows it continues, so the atomic's round trip
+  // overlaps the preconditioner arithmetic.
+  auto claim = [&](bool live) {
     if (tid == 0) {
       const int slot = atomicAdd(nact_out, 1);
-      if (pv) atomicAdd(nact_out + 1, 1);
+      if (live && plain) atomicAdd(nact_out + 1, 1);
       act_out[slot] = s;
       s_slot = slot;
     }
+  };
+  auto write_v = [&](const double* pv) {
     __syncthreads();
     if (V) {
       TV* col = V + (int64_t)s_slot * ldv;
@@ -163,19 +198,38 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       }
     }
   };
+  auto append = [&](const double* pv) {
+    claim(pv != nullptr);
+    write_v(pv);
+  };
 
-  if (st.done[s] != 0) {  // only reachable in the masked (plain) solver
-    if (plain) append(nullptr);
-    return;
-  }
-  double rv[RPT], pv[RPT];
+  // (2) per-system scalars and vectors, and the preconditioner's small matrices into LDS
+  const int32_t dn = st.done[s];
+  const double sig1 = 1.0 + st.sigma[s];
+  const double rz_old = st.rz[s];
+  const int it = st.iters[s] + mode;
+  const double bn = st.bnorm[s];
+  const double thresh = st.thresh[s];
+  double rv[RPT], pv[RPT], xv[RPT], sv[RPT];
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int64_t r = tid + 256 * j;
-    rv[j] = (r < m) ? st.r[base + r] : 0.0;
-    pv[j] = (r < m) ? st.p[base + r] : 0.0;
+    const bool ok = r < m;
+    rv[j] = ok ? st.r[base + r] : 0.0;
+    pv[j] = ok ? st.p[base + r] : 0.0;
+    xv[j] = (ok && mode == 1) ? st.x[base + r] : 0.0;
+    sv[j] = (ok && mode == 1 && obs_domain) ? (double)T[(int64_t)c * ldt + r] : 0.0;
   }
-  const double sig1 = 1.0 + st.sigma[s];
+  if (P > 0) {
+    for (int o = tid; o < 3 * P * P; o += blockDim.x) sG[o] = lmp.G[o];
+    if (tid < P) sG[3 * P * P + tid] = lmp.theta[tid];
+  }
+  const double dmin = (P > 0) ? *lmp.dmin : 0.0;
+
+  if (dn != 0) {  // only reachable in the masked solver, or for a slot that broke down
+    if (plain) append(nullptr);
+    return;
+  }
   if (mode == 1) {
     double qv[RPT];
     double pq = 0.0;
@@ -184,7 +238,9 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       const int64_t r = tid + 256 * j;
       qv[j] = 0.0;
       if (r < m) {
-        qv[j] = sig1 * pv[j] + s_times<TT>(obs_domain, T, ldt, c, r, h_ptr, h_idx, h_w, r_var, n_state);
+        const double sp =
+            obs_domain ? sv[j] : s_times<TT>(obs_domain, T, ldt, c, r, h_ptr, h_idx, h_w, r_var, n_state);
+        qv[j] = sig1 * pv[j] + sp;
         pq += pv[j] * qv[j];
       }
     }
@@ -198,19 +254,20 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       if (plain) append(nullptr);
       return;
     }
-    const double alpha = st.rz[s] / tot;
+    const double alpha = rz_old / tot;
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       const int64_t r = tid + 256 * j;
       if (r < m) {
-        st.x[base + r] += alpha * pv[j];
+        st.x[base + r] = xv[j] + alpha * pv[j];
         rv[j] -= alpha * qv[j];
         st.r[base + r] = rv[j];
       }
     }
   }
-  // dots of r: r^T r, Phi^T r, (S Phi)^T r
-  double acc[W], d[W];
+  // (3) dots of r: r^T r, Phi^T r, (S Phi)^T r
+  double acc[W];
+  const double* d = sdot;
 #pragma unroll
   for (int j = 0; j < W; ++j) acc[j] = 0.0;
 #pragma unroll
@@ -220,16 +277,13 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       acc[0] += rv[j] * rv[j];
 #pragma unroll
       for (int l = 0; l < P; ++l) {
-        acc[1 + l] += lmp.Phi[r * P + l] * rv[j];
-        acc[1 + P + l] += lmp.SPhi[r * P + l] * rv[j];
+        acc[1 + l] += lmp.Phi[l * lmp.ld + r] * rv[j];
+        acc[1 + P + l] += lmp.SPhi[l * lmp.ld + r] * rv[j];
       }
     }
   }
-  block_sum<W>(acc, sred, d);
+  block_sum_lds<W>(acc, sred, sdot);  // also orders the LDS writes of sG above
   const double rn = sqrt(d[0]);
-  const int it = st.iters[s] + mode;
-  const double bn = st.bnorm[s];
-  const double rz_old = st.rz[s];
   if (tid == 0) {
     st.iters[s] = it;
     st.relres[s] = bn > 0.0 ? rn / bn : 0.0;
@@ -242,22 +296,25 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
     if (plain) append(nullptr);
     return;
   }
-  if (rn <= st.thresh[s]) {
+  if (rn <= thresh) {
     if (tid == 0) st.done[s] = 1;
     if (plain) append(nullptr);
     return;
   }
+  if (it >= st.max_iter) {
+    if (tid == 0) st.done[s] = 2;
+    if (plain) append(nullptr);
+    return;
+  }
+  claim(true);
   // limited-memory preconditioner coefficients (Appendix E), with Theta = diag(1 + sigma + theta_j):
   //   c1 = Theta^{-1} Phi^T r,  c2 = Theta^{-1} [(C Phi)^T r - (C Phi)^T (C Phi) c1],
   //   gamma = (1 + sigma - beta_L) c1 + c2,  z = r - S Phi c1 - Phi gamma,
   //   r^T z = r^T r - ((S Phi)^T r) . c1 - (Phi^T r) . gamma.
   double rz = d[0];
   if (P > 0) {
-    for (int o = tid; o < 3 * P * P; o += blockDim.x) sG[o] = lmp.G[o];
-    if (tid < P) sG[3 * P * P + tid] = lmp.theta[tid];
-    __syncthreads();
     const double* sth = sG + 3 * P * P;
-    if (tid < P) scoef[tid] = d[1 + tid] / (sig1 + sth[tid]);
+    if (tid < P) scoef[tid] = sdot[1 + tid] / (sig1 + sth[tid]);
     __syncthreads();
     if (tid < P) {
       const double* Gpp = sG;
@@ -267,8 +324,8 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       for (int l = 0; l < P; ++l)
         mc += (Gss[tid * P + l] + sig1 * (Gps[tid * P + l] + Gps[l * P + tid]) + sig1 * sig1 * Gpp[tid * P + l]) *
               scoef[l];
-      const double c2 = (d[1 + P + tid] + sig1 * d[1 + tid] - mc) / (sig1 + sth[tid]);
-      const double beta_l = sig1 + *lmp.dmin;
+      const double c2 = (sdot[1 + P + tid] + sig1 * sdot[1 + tid] - mc) / (sig1 + sth[tid]);
+      const double beta_l = sig1 + dmin;
       scoef[P + tid] = (sig1 - beta_l) * scoef[tid] + c2;
     }
     __syncthreads();
@@ -280,28 +337,24 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       atomicOr(st.flags, isfinite(rz) ? kFlagNotSPD : kFlagNumeric);
       st.done[s] = 2;
     }
-    if (plain) append(nullptr);
+    write_v(nullptr);  // the slot is claimed: a zero direction, skipped next step (done != 0)
     return;
   }
-  if (it >= st.max_iter) {
-    if (tid == 0) st.done[s] = 2;
-    if (plain) append(nullptr);
-    return;
-  }
-  __syncthreads();  // every wavefront has read st.rz[s] (rz_old) before it is replaced
-  if (tid == 0) st.rz[s] = rz;
+  if (tid == 0) st.rz[s] = rz;  // rz_old was read into registers at the start
+  // (4) the preconditioned residual and the next direction
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int64_t r = tid + 256 * j;
     if (r < m) {
       double z = rv[j];
 #pragma unroll
-      for (int l = 0; l < P; ++l) z -= lmp.SPhi[r * P + l] * scoef[l] + lmp.Phi[r * P + l] * scoef[P + l];
+      for (int l = 0; l < P; ++l)
+        z -= lmp.SPhi[l * lmp.ld + r] * scoef[l] + lmp.Phi[l * lmp.ld + r] * scoef[P + l];
       pv[j] = mode ? z + beta * pv[j] : z;
       st.p[base + r] = pv[j];
     }
   }
-  append(pv);
+  write_v(pv);
 }
 
 // --------------------------------------------------------------- list and vector kernels

@@ -23,6 +23,9 @@ FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 SOLVER_PLAIN, SOLVER_COMPACT, SOLVER_PERSISTENT = 0, 1, 2
 DOMAIN_STATE, DOMAIN_OBS_LATTICE = 0, 1
 START_ZERO, START_LEARNED = 0, 1
+COV_AUTO, COV_OPERATOR, COV_BAND = 0, 1, 2
+PROF_OP_FP64, PROF_OP_FP32, PROF_OP_BF16, PROF_BAND_FP64, PROF_BAND_FP32, PROF_PCG = 0, 1, 2, 3, 4, 5
+PROF_SLOTS = 6
 CNT_APPLIES, CNT_APPLIES_FP64, CNT_ITERATIONS, CNT_SWEEPS = 0, 1, 2, 3
 CNT_FALLBACKS, CNT_NOT_CONVERGED, CNT_MAX_ITERS, CNT_STATUS = 4, 5, 6, 7
 NUM_COUNTERS = 8
@@ -52,7 +55,7 @@ class Opts(C.Structure):
                 ("precision", C.c_int32), ("solver", C.c_int32), ("warm_start", C.c_int32),
                 ("host_sync", C.c_int32), ("apply_domain", C.c_int32), ("lattice", Lattice),
                 ("seed", C.c_uint64), ("sketch", C.c_void_p), ("net", C.c_void_p),
-                ("tile_rows", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("tile_rows", C.c_int32), ("cov_form", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class StatsC(C.Structure):
@@ -427,12 +430,24 @@ def profile_enable(on: bool):
     _check(lib.infoesrf_profile_enable(1 if on else 0), allow_warn=False)
 
 
-def profile_read():
-    """Per precision (FP64, FP32, BF16): kernel ms, launches, vectors, FLOPs of the covariance apply."""
+def profile_select(slots):
+    """Measure only the listed profile slots (PROF_*) until the next profile_enable."""
     lib = library()
-    D3, I3 = C.c_double * 3, C.c_int64 * 3
-    lib.infoesrf_profile_read.argtypes = [D3, I3, I3, D3]
+    lib.infoesrf_profile_select.argtypes = [C.c_uint32]
+    lib.infoesrf_profile_select.restype = C.c_int
+    mask = 0
+    for s in slots:
+        mask |= 1 << int(s)
+    _check(lib.infoesrf_profile_select(mask), allow_warn=False)
+
+
+def profile_read():
+    """Per slot (PROF_*: operator FP64/FP32/BF16, band FP64/FP32): kernel ms, launches, vectors,
+    algorithmic FLOPs and algorithmic bytes of the covariance applies."""
+    lib = library()
+    D, I = C.c_double * PROF_SLOTS, C.c_int64 * PROF_SLOTS
+    lib.infoesrf_profile_read.argtypes = [D, I, I, D, D]
     lib.infoesrf_profile_read.restype = C.c_int
-    ms, la, ve, fl = D3(), I3(), I3(), D3()
-    _check(lib.infoesrf_profile_read(ms, la, ve, fl), allow_warn=False)
-    return list(ms), list(la), list(ve), list(fl)
+    ms, la, ve, fl, by = D(), I(), I(), D(), D()
+    _check(lib.infoesrf_profile_read(ms, la, ve, fl, by), allow_warn=False)
+    return list(ms), list(la), list(ve), list(fl), list(by)

@@ -102,7 +102,8 @@ def test_option_and_node_validation():
     p = fake_problem()
     dp = C.POINTER(C.c_double)
     s = np.ones(4)
-    for kw in (dict(rtol=0.0), dict(max_iter=0), dict(n_ritz=7), dict(precision=9), dict(tile_rows=48)):
+    for kw in (dict(rtol=0.0), dict(max_iter=0), dict(n_ritz=7), dict(precision=9), dict(tile_rows=48),
+               dict(cov_form=5), dict(cov_form=ie.COV_BAND, precision=ie.MIXED_BF16)):
         o = ie.default_opts(**kw)
         assert lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(o)) == 0
     o = ie.default_opts()
@@ -184,3 +185,15 @@ def test_batched_validation_before_device_access():
     rc = lib.infoesrf_update_batched(arr, 0, qa, sp, sp, None, None, outs, C.byref(o), None, None, C.c_void_p(0x1000),
                                      1 << 30, None)
     assert rc == ie.ERR_INVALID_ARG
+
+
+def test_band_form_workspace():
+    """The band form adds (2bz+1)(2bx+1) planes of round_up(n, 64) doubles (state grid)."""
+    lib = ie.library()
+    p = fake_problem(n=64, N=8, bx=3)
+    op = lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(ie.default_opts(cov_form=ie.COV_OPERATOR)))
+    bd = lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(ie.default_opts(cov_form=ie.COV_BAND)))
+    assert bd - op >= 7 * 64 * 8
+    d = fake_problem(kind=ie.LOC_DENSE)
+    assert lib.infoesrf_workspace_bytes(C.byref(d), 4, C.byref(ie.default_opts(cov_form=ie.COV_BAND))) == 0
+    assert "band form" in lib.infoesrf_last_error().decode()

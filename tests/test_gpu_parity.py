@@ -72,9 +72,10 @@ def test_cov_apply_fp64_matches_dense(case, B):
     V = np.random.default_rng(B).standard_normal((prob.n, B))
     want = dp.P @ V
     P = ie.Problem.from_synthetic(prob)
-    for rows in (16, 64, 128):
-        got = ie.cov_apply(P, torch.from_numpy(V).cuda(), ie.default_opts(tile_rows=rows)).cpu().numpy()
-        assert rel(got, want) < 1e-13, (case, B, rows)
+    variants = [dict(cov_form=ie.COV_OPERATOR, tile_rows=r) for r in (16, 64, 128)] + [dict(cov_form=ie.COV_BAND)]
+    for kw in variants:
+        got = ie.cov_apply(P, torch.from_numpy(V).cuda(), ie.default_opts(**kw)).cpu().numpy()
+        assert rel(got, want) < 1e-13, (case, B, kw)
         assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
 
 
@@ -86,8 +87,10 @@ def test_cov_apply_fp32_stated_bound(case):
     V = np.random.default_rng(3).standard_normal((prob.n, 20))
     want = dp.P @ V
     P = ie.Problem.from_synthetic(prob)
-    got = ie.cov_apply(P, torch.from_numpy(V).cuda(), ie.default_opts(precision=ie.MIXED_FP32)).cpu().numpy()
-    assert rel(got, want) < 1e-6
+    for form in (ie.COV_OPERATOR, ie.COV_BAND):
+        got = ie.cov_apply(P, torch.from_numpy(V).cuda(),
+                           ie.default_opts(precision=ie.MIXED_FP32, cov_form=form)).cpu().numpy()
+        assert rel(got, want) < 1e-6, form
 
 
 def test_cov_apply_dense_localization():
@@ -100,7 +103,12 @@ def test_cov_apply_dense_localization():
     assert rel(got, dp.P @ V) < 1e-13
 
 
-def opts_for(prob, P, domain, **kw):
+FORMS = {"operator": ie.COV_OPERATOR, "band": ie.COV_BAND}
+
+
+def opts_for(prob, P, domain, form=None, **kw):
+    if form is not None:
+        kw["cov_form"] = FORMS[form]
     if domain == "lattice":
         lat = P.lattice()
         assert lat is not None
@@ -108,31 +116,33 @@ def opts_for(prob, P, domain, **kw):
     return ie.default_opts(**kw)
 
 
+@pytest.mark.parametrize("form", ["operator", "band"])
 @pytest.mark.parametrize("domain", ["state", "lattice"])
 @pytest.mark.parametrize("case", ["gauss-n256-periodic", "ragged-1d-nonperiodic", "2d-layers"])
-def test_mean_update_matches_oracle(case, domain):
+def test_mean_update_matches_oracle(case, domain, form):
     prob = CASES[case]()
-    say("mean_update", case, domain)
+    say("mean_update", case, domain, form)
     dp = dense_of(prob)
     want = ref.mean_update_eig(dp, prob.y)
     P = ie.Problem.from_synthetic(prob)
-    got, st = ie.mean_update(P, prob.y, opts_for(prob, P, domain))
+    got, st = ie.mean_update(P, prob.y, opts_for(prob, P, domain, form))
     assert st.code == ie.OK
     assert rel(got.cpu().numpy(), want) < 1e-6
     assert rel(got.cpu().numpy() - dp.mu, want - dp.mu) < 1e-6
     assert st.relres[0] <= 1e-8 and st.converged[0] == 1
 
 
+@pytest.mark.parametrize("form", ["operator", "band"])
 @pytest.mark.parametrize("domain", ["state", "lattice"])
 @pytest.mark.parametrize("case", ["gauss-n256-periodic", "ragged-1d-nonperiodic", "2d-layers", "2d-periodic-z"])
-def test_perturbation_update_matches_oracle(case, domain):
+def test_perturbation_update_matches_oracle(case, domain, form):
     prob = CASES[case]()
-    say("perturbation_update", case, domain)
+    say("perturbation_update", case, domain, form)
     dp = dense_of(prob)
     s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
     want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
     P = ie.Problem.from_synthetic(prob)
-    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain))
+    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, form))
     assert st.code == ie.OK
     assert rel(got.cpu().numpy(), want) < 1e-6
     assert np.all(st.relres <= 1e-8) and np.all(st.converged == 1)
@@ -180,15 +190,16 @@ def test_solvers_agree_and_are_deterministic(solver):
     assert rel(a.cpu().numpy(), c.cpu().numpy()) < 1e-12
 
 
+@pytest.mark.parametrize("form", ["operator", "band"])
 @pytest.mark.parametrize("domain", ["state", "lattice"])
-def test_mixed_fp32_meets_fp64_bound(domain):
+def test_mixed_fp32_meets_fp64_bound(domain, form):
     prob = syn.config1()
-    say("mixed fp32", domain)
+    say("mixed fp32", domain, form)
     dp = dense_of(prob)
     s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
     want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
     P = ie.Problem.from_synthetic(prob)
-    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, precision=ie.MIXED_FP32))
+    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, form, precision=ie.MIXED_FP32))
     assert st.code == ie.OK
     assert rel(got.cpu().numpy(), want) < 1e-6
     assert np.all(st.relres <= 1e-8)
@@ -260,21 +271,22 @@ def test_indefinite_localization_is_not_spd():
     assert e.value.code in (ie.ERR_NOT_SPD, ie.ERR_NUMERIC)
 
 
+@pytest.mark.parametrize("form", ["operator", "band"])
 @pytest.mark.parametrize("domain", ["lattice", "state"])
-def test_full_size_gaussian_n4096(domain):
+def test_full_size_gaussian_n4096(domain, form):
     """n=4096, N=40, m=1024, Q=16 (640 systems) against the eigendecomposition oracle."""
     prob = syn.config2()
-    say("full size n4096", domain)
+    say("full size n4096", domain, form)
     dp = dense_of(prob)
     s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
     want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
     P = ie.Problem.from_synthetic(prob)
-    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain))
+    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, form))
     assert st.code == ie.OK
     assert rel(got.cpu().numpy(), want) < 1e-6
     assert np.all(st.relres <= 1e-8)
     mean_want = ref.mean_update_eig(dp, prob.y)
-    mean_got, sm = ie.mean_update(P, prob.y, opts_for(prob, P, domain))
+    mean_got, sm = ie.mean_update(P, prob.y, opts_for(prob, P, domain, form))
     assert rel(mean_got.cpu().numpy() - dp.mu, mean_want - dp.mu) < 1e-6
 
 
@@ -319,3 +331,18 @@ def test_mixed_bf16_full_size_lattice():
     got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, "lattice", precision=ie.MIXED_BF16))
     assert st.code == ie.OK and np.all(st.relres <= 1e-8)
     assert rel(got.cpu().numpy(), want) < 1e-6
+
+
+def test_band_form_options():
+    """The band form takes FP64 and FP32 only; BF16 asks for the operator form."""
+    prob = syn.config1()
+    say("band form option checks")
+    P = ie.Problem.from_synthetic(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    with pytest.raises(ie.InfoEsrfError) as e:
+        ie.perturbation_update(P, s, p, ie.default_opts(precision=ie.MIXED_BF16, cov_form=ie.COV_BAND))
+    assert e.value.code == ie.ERR_INVALID_ARG
+    # AUTO with BF16 runs the operator form; the FP64 forms agree to rounding
+    a, _ = ie.perturbation_update(P, s, p, ie.default_opts(cov_form=ie.COV_OPERATOR))
+    b, _ = ie.perturbation_update(P, s, p, ie.default_opts(cov_form=ie.COV_BAND))
+    assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-9
