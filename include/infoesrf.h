@@ -277,15 +277,59 @@ const char* infoesrf_error_string(int code);
 const char* infoesrf_last_error(void);
 
 /*
- * Learned warm start: a 1-D convolutional network (4 layers, kernel 9,
- * 64 hidden channels) mapping (b_i/||b_i||, 1/(1+s_q), d/||d||) to the
- * initial guess ||b_i|| net(.) of C_q u = b_i.  The file is the library's own
- * little-endian format written by infoesrf_net_save.  The handle owns device
- * memory allocated at load time (not on the update path).
+ * Learned warm start (an extension of the method; the paper starts every
+ * system from zero).  A 1-D convolutional network over the m observation rows
+ * (3 -> H -> H -> H -> 1 channels, odd kernel width K <= 15, "same" zero
+ * padding, GELU after the first three layers, FP32 parameters) maps the
+ * features of system (q, i)
+ *     channel 0: b_i / ||b_i||,  channel 1: 1 / (1 + s_q),  channel 2: d / ||d||,
+ *     with d = R^{-1/2} (y - H mu) (eq. E.1 and Sec. 3.2),
+ * to u0 = ||b_i|| net(.), the initial guess of C_q u = b_i.  With
+ * warm_start = INFOESRF_START_LEARNED and opts->net set, the perturbation
+ * update (which then needs y) starts every system from u0; a system whose u0
+ * is not finite starts from zero and counters[FALLBACKS] counts it.  The mean
+ * system always starts from zero.
+ *
+ * Handles own device memory (parameters, Adam moments, a gradient buffer),
+ * allocated by create/load and released by free; never on the update path.
+ * File: little-endian "IENET001", 5 int32 (4, 3, H, K, 1), then the FP32
+ * parameters W1 (H x 3 x K) b1 (H) W2 (H x H x K) b2 W3 b3 W4 (1 x H x K) b4 (1).
+ *
+ * Batches: X is B x 3 x m, Y and targets T are B x m, FP32 row-contiguous
+ * device arrays; workspaces from infoesrf_net_workspace_bytes (training != 0
+ * keeps every activation for the backward pass).  The loss is the batch mean
+ * of ||Y_b - T_b|| / ||T_b|| (T = u* / ||b|| for exact solutions u*), written
+ * to the device float *loss; gradients have the parameter layout; a training
+ * step is one Adam update (beta1 0.9, beta2 0.999, eps 1e-8).
  */
+int infoesrf_net_create(int32_t hidden, int32_t kernel, uint64_t seed, void** net);
 int infoesrf_net_load(const char* path, void** net);
 int infoesrf_net_save(const void* net, const char* path);
 void infoesrf_net_free(void* net);
+int64_t infoesrf_net_param_count(const void* net);
+int infoesrf_net_get_params(const void* net, float* host);        /* host array of param_count */
+int infoesrf_net_set_params(void* net, const float* host);        /* also resets the Adam state */
+size_t infoesrf_net_workspace_bytes(const void* net, int64_t B, int64_t m, int32_t training);
+int infoesrf_net_forward(const void* net, const float* X, int64_t B, int64_t m, float* Y, void* ws,
+                         size_t ws_bytes, void* stream);
+int infoesrf_net_gradients(const void* net, const float* X, const float* T, int64_t B, int64_t m,
+                           float* grads, float* loss, void* ws, size_t ws_bytes, void* stream);
+int infoesrf_net_train_step(void* net, const float* X, const float* T, int64_t B, int64_t m, float lr,
+                            float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Training pairs for the warm start: solves the Q N systems of the
+ * perturbation update exactly as infoesrf_perturbation_update does (same
+ * options; warm_start must be ZERO) and writes, for system s = q N + i,
+ * X[s] (3 x m) the network features above and T[s] (m) = u*_s / ||b_s||, the
+ * converged solution scaled like the network output.  X: Q N x 3 x m FP32,
+ * T: Q N x m FP32 (device).  y: the m observations (device).  Workspace:
+ * infoesrf_workspace_bytes(prob, Q, opts).
+ */
+int infoesrf_warmstart_pairs(const infoesrf_problem* prob, int32_t Q, const double* s_nodes,
+                             const double* p_weights, const double* y, float* X, float* T,
+                             const infoesrf_opts* opts, infoesrf_stats* stats, void* ws, size_t ws_bytes,
+                             void* stream);
 
 /*
  * Measurement hooks (results are unaffected).  While enabled, every launch of

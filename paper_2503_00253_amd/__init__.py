@@ -8,6 +8,8 @@ ctypes binding with the same entry-point names.  Build the library with
 from .infoesrf import (  # noqa: F401
     LIB_PATH,
     BatchedRunner,
+    Net,
+    warmstart_pairs,
     PerturbationRunner,
     batched_workspace_bytes,
     InfoEsrfError,

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "net.hpp"
 
 namespace infoesrf {
 
@@ -116,6 +117,50 @@ __global__ void k_set_nodes(Nodes nd, int32_t Q, int64_t N, double* sigma, doubl
 // Sweep bookkeeping from true residual norms (iterative refinement).
 //   fdone: 1 converged (rn <= rtol bn), 2 failed (iteration cap or non-finite), 0 needs work.
 //   done (inner PCG status) = fdone ? 1 : 0; thresh = absolute inner target.
+// Network features of systems s0 .. s0 + cnt (see infoesrf.h): X[(s - s0), 0..2, r] from the
+// right-hand sides b (system-major, ld), the shifts sigma and the innovation d (norm *dn).
+__global__ void k_net_features(const double* __restrict__ b, int64_t ld, const double* __restrict__ bn,
+                               const double* __restrict__ sigma, const double* __restrict__ d,
+                               const double* __restrict__ dn, int64_t m, int64_t s0, int64_t cnt,
+                               float* __restrict__ X) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= cnt * m) return;
+  const int64_t j = t / m, r = t % m, s = s0 + j;
+  const double nb = bn[s], nd = *dn;
+  float* x = X + j * 3 * m;
+  x[r] = nb > 0.0 ? (float)(b[s * ld + r] / nb) : 0.f;
+  x[m + r] = (float)(1.0 / (1.0 + sigma[s]));
+  x[2 * m + r] = nd > 0.0 ? (float)(d[r] / nd) : 0.f;
+}
+
+// u_s = ||b_s|| Y_s for systems s0 .. s0 + cnt (one block each); a system whose prediction is not
+// finite starts from zero and is counted in *fallbacks.
+__global__ __launch_bounds__(256) void k_warm_init(const float* __restrict__ Y, const double* __restrict__ bn,
+                                                   int64_t m, int64_t s0, double* __restrict__ u, int64_t ld,
+                                                   int32_t* __restrict__ fallbacks) {
+  __shared__ int bad;
+  const int64_t s = s0 + blockIdx.x;
+  const float* y = Y + (int64_t)blockIdx.x * m;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int64_t r = threadIdx.x; r < m; r += 256)
+    if (!isfinite(y[r])) bad = 1;
+  __syncthreads();
+  const double nb = bn[s];
+  for (int64_t r = threadIdx.x; r < m; r += 256) u[s * ld + r] = bad ? 0.0 : nb * (double)y[r];
+  if (bad && threadIdx.x == 0) atomicAdd(fallbacks, 1);
+}
+
+// Training targets T[s, r] = u_s[r] / ||b_s|| (FP32).
+__global__ void k_net_targets(const double* __restrict__ u, int64_t ld, const double* __restrict__ bn, int64_t m,
+                              int64_t S, float* __restrict__ T) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= S * m) return;
+  const int64_t s = t / m, r = t % m;
+  const double nb = bn[s];
+  T[t] = nb > 0.0 ? (float)(u[s * ld + r] / nb) : 0.f;
+}
+
 __global__ void k_sweep_status(const double* rn, const double* bn, double rtol, double inner_rtol, int fp64_inner,
                                const int32_t* iters, int max_iter, double* relres, int32_t* fdone, int32_t* done,
                                double* thresh, int32_t* sweeps, int count_sweep, int64_t S, int32_t* flags) {
@@ -231,6 +276,15 @@ struct Inst {
   // for MIXED_FP32 inner applies in that domain, an FP32 copy
   bool band = false;
   void *bandS = nullptr, *bandS32 = nullptr, *bandO = nullptr, *bandO32 = nullptr;
+  // learned warm start: innovation d = R^{-1/2}(y - H mu) and its norm, network buffers for a
+  // chunk of systems (features, outputs, the network's own workspace)
+  const double* y = nullptr;
+  double *d = nullptr, *dnorm = nullptr;
+  const Net* net = nullptr;
+  int64_t wchunk = 0;
+  float *wX = nullptr, *wY = nullptr;
+  void* wnet = nullptr;
+  size_t wnet_bytes = 0;
 };
 
 // Solver state: observation-space vectors are system-major, system s at s * ldm.
@@ -319,7 +373,10 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
            "unknown precision");
   IE_CHECK(o->solver >= INFOESRF_SOLVER_PLAIN && o->solver <= INFOESRF_SOLVER_PERSISTENT, INFOESRF_ERR_INVALID_ARG,
            "unknown solver");
-  IE_CHECK(o->warm_start == INFOESRF_START_ZERO, INFOESRF_ERR_INVALID_ARG, "learned warm start not available yet");
+  IE_CHECK(o->warm_start == INFOESRF_START_ZERO || o->warm_start == INFOESRF_START_LEARNED, INFOESRF_ERR_INVALID_ARG,
+           "unknown warm_start");
+  IE_CHECK(o->warm_start != INFOESRF_START_LEARNED || o->net != nullptr, INFOESRF_ERR_INVALID_ARG,
+           "the learned warm start needs opts->net");
   IE_CHECK(o->apply_domain == INFOESRF_DOMAIN_STATE || o->apply_domain == INFOESRF_DOMAIN_OBS_LATTICE,
            INFOESRF_ERR_INVALID_ARG, "unknown apply domain");
   IE_CHECK(o->tile_rows == 0 || o->tile_rows == 16 || o->tile_rows == 32 || o->tile_rows == 64 ||
@@ -421,6 +478,16 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   in.flags = ar.take<int32_t>(1);
   in.fallbacks = ar.take<int32_t>(1);
   in.counters = ar.take<int64_t>(INFOESRF_NUM_COUNTERS);
+  in.d = ar.take<double>(in.m);
+  in.dnorm = ar.take<double>(1);
+  if (op.warm == INFOESRF_START_LEARNED && S > 1) {
+    in.net = static_cast<const Net*>(op.net);
+    in.wchunk = std::min<int64_t>(S, 128);
+    in.wX = ar.take<float>(in.wchunk * 3 * in.m);
+    in.wY = ar.take<float>(in.wchunk * in.m);
+    in.wnet_bytes = net_ws_bytes(*in.net, in.wchunk, in.m, false);
+    in.wnet = ar.take<char>((int64_t)in.wnet_bytes);
+  }
 
   Sys& sy = pl.sy;
   sy.S = S;
@@ -750,6 +817,27 @@ class LivePoll {
   int head_ = 0, pending_ = 0;
 };
 
+// Learned warm start: u = ||b|| net(b/||b||, 1/(1+sigma), d/||d||) for every system, in chunks of
+// in.wchunk systems (non-finite predictions fall back to zero).  Needs sy.bnorm.
+int stage_warm(Plan& pl, hipStream_t st) {
+  Inst& in = pl.in;
+  Sys& sy = pl.sy;
+  const infoesrf_problem* P = in.P;
+  IE_HIP(launch_innovation(P->h_ptr, P->h_idx, P->h_w, P->r_var, in.y, in.mu, in.m, in.n, in.d, sy.ldm, 0, st));
+  IE_HIP(launch_col_norms(in.d, in.m, 1, sy.ldm, in.dnorm, st));
+  for (int64_t s0 = 0; s0 < sy.S; s0 += in.wchunk) {
+    const int64_t cnt = std::min<int64_t>(in.wchunk, sy.S - s0);
+    hipLaunchKernelGGL(k_net_features, dim3(nb(cnt * in.m)), dim3(256), 0, st, sy.b, sy.ldm, sy.bnorm, sy.sigma,
+                       in.d, in.dnorm, in.m, s0, cnt, in.wX);
+    IE_HIP(hipGetLastError());
+    IE_TRY(net_forward(*in.net, in.wX, cnt, in.m, in.wY, in.wnet, in.wnet_bytes, st));
+    hipLaunchKernelGGL(k_warm_init, dim3((unsigned)cnt), dim3(256), 0, st, in.wY, sy.bnorm, in.m, s0, sy.u, sy.ldm,
+                       in.fallbacks);
+    IE_HIP(hipGetLastError());
+  }
+  return 0;
+}
+
 LMP lmp_of(Plan& pl) {
   LMP l{};
   l.p = pl.pr.p;
@@ -792,6 +880,8 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
 
   IE_HIP(launch_col_norms(sy.b, m, S, ldm, sy.bnorm, st));
   IE_HIP(launch_fill_f64(sy.u, 0.0, flat, st));
+  const bool warm = in.net != nullptr;
+  if (warm) IE_TRY(stage_warm(pl, st));
   IE_HIP(launch_fill_i32(sy.iters, 0, sy.Spad, st));
   IE_HIP(launch_fill_i32(sy.sweeps, 0, sy.Spad, st));
   IE_HIP(launch_fill_i32(sy.fdone, 0, sy.Spad, st));
@@ -804,7 +894,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   int32_t h_nact = (int32_t)S;
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
     // outer residual r = b - C u (FP64).  Zero start: the first residual is b itself.
-    if (sweep == 0) {
+    if (sweep == 0 && !warm) {
       hipLaunchKernelGGL(k_copy_f64, dim3(nb(flat)), dim3(256), 0, st, sy.b, sy.r, flat);
       IE_HIP(hipGetLastError());
     } else {
@@ -815,7 +905,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
     IE_HIP(launch_col_norms(sy.r, m, S, ldm, sy.rn, st));
     hipLaunchKernelGGL(k_sweep_status, dim3(nb(S)), dim3(256), 0, st, sy.rn, sy.bnorm, op.rtol, op.inner_rtol,
                        fp64_inner ? 1 : 0, sy.iters, op.max_iter, sy.relres, sy.fdone, sy.done, sy.thresh,
-                       sy.sweeps, sweep > 0 ? 1 : 0, S, in.flags);
+                       sy.sweeps, (sweep > 0 || warm) ? 1 : 0, S, in.flags);
     IE_HIP(hipGetLastError());
     if (plain) IE_HIP(launch_iota(sy.act, sy.nact, S, st));
     else IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
@@ -1017,6 +1107,45 @@ class WorkerPool {
 // Workspace of one instance: room for its perturbation update and (if asked) its mean update.
 size_t instance_ws_bytes(const infoesrf_problem* P, int32_t Q, bool mean, const infoesrf_opts* opts);
 
+// Everything of the perturbation update up to the converged solutions u (Sec. 3.2, eq. E.1):
+// validation, set-up, right-hand sides, nodes, preconditioner and the solves.
+int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_nodes, const double* p_weights,
+                       const double* y, const infoesrf_opts* opts, Plan& pl, Options& op, void* ws,
+                       size_t ws_bytes, hipStream_t st) {
+  IE_TRY(check_problem(prob));
+  IE_TRY(resolve_options(prob, opts, op));
+  IE_CHECK(Q >= 1 && Q <= kMaxQ, INFOESRF_ERR_INVALID_ARG, "Q must be in [1, 64]");
+  IE_CHECK(s_nodes && p_weights, INFOESRF_ERR_INVALID_ARG, "s_nodes and p_weights must be non-NULL");
+  IE_CHECK(op.warm != INFOESRF_START_LEARNED || y != nullptr, INFOESRF_ERR_INVALID_ARG,
+           "the learned warm start needs y (its innovation input)");
+  Nodes nd{};
+  for (int q = 0; q < Q; ++q) {
+    IE_CHECK(std::isfinite(s_nodes[q]) && s_nodes[q] >= 0.0, INFOESRF_ERR_INVALID_ARG, "quadrature nodes must be >= 0");
+    IE_CHECK(std::isfinite(p_weights[q]) && p_weights[q] >= 0.0, INFOESRF_ERR_INVALID_ARG,
+             "quadrature weights must be >= 0");
+    nd.s[q] = s_nodes[q];
+    nd.p[q] = p_weights[q];
+  }
+  IE_CHECK(ws != nullptr, INFOESRF_ERR_WORKSPACE, "workspace is NULL");
+  const int64_t N = prob->N;
+  const int64_t S = (int64_t)Q * N;
+  IE_TRY(plan_for(pl, prob, op, S, N, ws, ws_bytes));
+  pl.in.y = y;
+  IE_TRY(check_nnz(prob, op, st));
+  IE_TRY(stage_setup(pl, op, st));
+  Sys& sy = pl.sy;
+  IE_HIP(launch_fill_f64(sy.b, 0.0, sy.ldm * sy.Spad, st));
+  IE_HIP(launch_obs_rhs(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, pl.in.Z, pl.in.n, N, pl.in.m, sy.b, sy.ldm,
+                        0, S, st));
+  IE_HIP(launch_fill_f64(sy.sigma, 0.0, sy.Spad, st));
+  hipLaunchKernelGGL(k_set_nodes, dim3(nb(std::max<int64_t>(S, kMaxQ))), dim3(256), 0, st, nd, Q, N, sy.sigma, sy.pw,
+                     (int64_t)0, 0.0);
+  IE_HIP(hipGetLastError());
+  IE_TRY(stage_precond(pl, op, st));
+  IE_TRY(stage_solve(pl, op, st));
+  return 0;
+}
+
 }  // namespace
 }  // namespace infoesrf
 
@@ -1201,38 +1330,13 @@ int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const 
                                  const infoesrf_opts* opts, infoesrf_stats* stats, void* ws, size_t ws_bytes,
                                  void* stream) {
   clear_error();
-  IE_TRY(check_problem(prob));
-  Options op;
-  IE_TRY(resolve_options(prob, opts, op));
-  IE_CHECK(Q >= 1 && Q <= kMaxQ, INFOESRF_ERR_INVALID_ARG, "Q must be in [1, 64]");
-  IE_CHECK(s_nodes && p_weights && Xa_pert, INFOESRF_ERR_INVALID_ARG, "s_nodes, p_weights, Xa_pert must be non-NULL");
-  Nodes nd{};
-  for (int q = 0; q < Q; ++q) {
-    IE_CHECK(std::isfinite(s_nodes[q]) && s_nodes[q] >= 0.0, INFOESRF_ERR_INVALID_ARG, "quadrature nodes must be >= 0");
-    IE_CHECK(std::isfinite(p_weights[q]) && p_weights[q] >= 0.0, INFOESRF_ERR_INVALID_ARG,
-             "quadrature weights must be >= 0");
-    nd.s[q] = s_nodes[q];
-    nd.p[q] = p_weights[q];
-  }
-  (void)y;
-  IE_CHECK(ws != nullptr, INFOESRF_ERR_WORKSPACE, "workspace is NULL");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const int64_t N = prob->N;
-  const int64_t S = (int64_t)Q * N;
+  IE_CHECK(Xa_pert, INFOESRF_ERR_INVALID_ARG, "Xa_pert must be non-NULL");
   Plan pl;
-  IE_TRY(plan_for(pl, prob, op, S, N, ws, ws_bytes));
-  IE_TRY(check_nnz(prob, op, st));
-  IE_TRY(stage_setup(pl, op, st));
+  Options op;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  IE_TRY(perturbation_solve(prob, Q, s_nodes, p_weights, y, opts, pl, op, ws, ws_bytes, st));
   Sys& sy = pl.sy;
-  IE_HIP(launch_fill_f64(sy.b, 0.0, sy.ldm * sy.Spad, st));
-  IE_HIP(launch_obs_rhs(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, pl.in.Z, pl.in.n, N, pl.in.m, sy.b, sy.ldm,
-                        0, S, st));
-  IE_HIP(launch_fill_f64(sy.sigma, 0.0, sy.Spad, st));
-  hipLaunchKernelGGL(k_set_nodes, dim3(nb(std::max<int64_t>(S, kMaxQ))), dim3(256), 0, st, nd, Q, N, sy.sigma, sy.pw,
-                     (int64_t)0, 0.0);
-  IE_HIP(hipGetLastError());
-  IE_TRY(stage_precond(pl, op, st));
-  IE_TRY(stage_solve(pl, op, st));
+  const int64_t N = prob->N;
   // u_bar_i = sum_q p_q u_{q,i}; Xa_pert = sqrt(N-1) (Z - P H^T R^{-1/2} U_bar)
   IE_HIP(launch_quad_combine(sy.u, sy.ldm, pl.in.m, N, Q, sy.pw, pl.fn.ubar, sy.ldm, 0, st));
   IE_HIP(launch_iota(pl.fn.act, pl.fn.nact, N, st));
@@ -1240,6 +1344,31 @@ int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const 
   IE_HIP(launch_final_pert(pl.in.Z, (const double*)pl.bf.T, ld64(pl.in.n), pl.in.n, N, std::sqrt((double)(N - 1)),
                            Xa_pert, st));
   return finish_status(pl, op, stats, 2 * pl.pr.k + N, st);
+}
+
+int infoesrf_warmstart_pairs(const infoesrf_problem* prob, int32_t Q, const double* s_nodes,
+                             const double* p_weights, const double* y, float* X, float* T,
+                             const infoesrf_opts* opts, infoesrf_stats* stats, void* ws, size_t ws_bytes,
+                             void* stream) {
+  clear_error();
+  IE_CHECK(X && T && y, INFOESRF_ERR_INVALID_ARG, "X, T and y must be non-NULL");
+  IE_CHECK(!opts || opts->warm_start == INFOESRF_START_ZERO, INFOESRF_ERR_INVALID_ARG,
+           "training pairs are solved from the zero start");
+  Plan pl;
+  Options op;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  IE_TRY(perturbation_solve(prob, Q, s_nodes, p_weights, y, opts, pl, op, ws, ws_bytes, st));
+  Inst& in = pl.in;
+  Sys& sy = pl.sy;
+  IE_HIP(launch_innovation(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, y, in.mu, in.m, in.n, in.d, sy.ldm, 0,
+                           st));
+  IE_HIP(launch_col_norms(in.d, in.m, 1, sy.ldm, in.dnorm, st));
+  hipLaunchKernelGGL(k_net_features, dim3(nb(sy.S * in.m)), dim3(256), 0, st, sy.b, sy.ldm, sy.bnorm, sy.sigma, in.d,
+                     in.dnorm, in.m, (int64_t)0, sy.S, X);
+  IE_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_net_targets, dim3(nb(sy.S * in.m)), dim3(256), 0, st, sy.u, sy.ldm, sy.bnorm, in.m, sy.S, T);
+  IE_HIP(hipGetLastError());
+  return finish_status(pl, op, stats, 2 * pl.pr.k, st);
 }
 
 size_t infoesrf_batched_workspace_bytes(const infoesrf_problem* probs, int32_t count, const int32_t* Q,

@@ -1,0 +1,271 @@
+// Kernels of the warm-start network (a 1-D convolutional net over the m observation rows; the
+// method's extension for initial guesses of the shifted systems, Appendix E, eq. E.1).
+//
+// Layout: activations of a batch are (B, C, m) row-contiguous, element (b, c, x) at
+// (b * C + c) * m + x.  Weights (Cout, Cin, K) row-contiguous, K odd, "same" zero padding:
+//
+//   y[b, o, x] = bias[o] + sum_c sum_k W[o, c, k] a[b, c, x + k - K/2].
+//
+// All arithmetic is FP32 (accumulation in FP32, reductions in a fixed order).
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace infoesrf {
+
+namespace {
+
+constexpr int kTX = 64;    // positions per block (one per lane)
+constexpr int kCIC = 16;   // input channels staged per chunk
+
+__device__ inline float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_grad_f(float z) {
+  const float Phi = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+  const float phi = 0.39894228040143268f * expf(-0.5f * z * z);
+  return Phi + z * phi;
+}
+
+// Direct correlation.  Block: 64 positions (lanes) x 4 * CPW output channels (CPW per wave).
+// Input window and weight chunk in LDS; weights are read as wave-uniform broadcasts.
+template <int CPW>
+__global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ in, int Cin, const float* __restrict__ W,
+                                                  const float* __restrict__ bias, int Cout, int K, int m,
+                                                  float* __restrict__ pre, float* __restrict__ act, int gelu) {
+  extern __shared__ float sm[];
+  const int h = K / 2;
+  const int WX = kTX + K - 1;
+  float* win = sm;                      // kCIC x WX
+  float* wts = sm + kCIC * WX;          // (4 CPW) x kCIC x K
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int x0 = blockIdx.x * kTX;
+  const int o0 = blockIdx.y * 4 * CPW;
+  const int64_t b = blockIdx.z;
+  const float* inb = in + b * (int64_t)Cin * m;
+  float acc[CPW];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) acc[j] = 0.f;
+  for (int c0 = 0; c0 < Cin; c0 += kCIC) {
+    const int cc = min(kCIC, Cin - c0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kCIC * WX; t += 256) {
+      const int ci = t / WX, u = t % WX;
+      const int x = x0 - h + u;
+      win[t] = (ci < cc && x >= 0 && x < m) ? inb[(int64_t)(c0 + ci) * m + x] : 0.f;
+    }
+    for (int t = threadIdx.x; t < 4 * CPW * kCIC * K; t += 256) {
+      const int o = t / (kCIC * K), rem = t % (kCIC * K), ci = rem / K, k = rem % K;
+      wts[t] = (o0 + o < Cout && ci < cc) ? W[((int64_t)(o0 + o) * Cin + c0 + ci) * K + k] : 0.f;
+    }
+    __syncthreads();
+    for (int ci = 0; ci < cc; ++ci)
+      for (int k = 0; k < K; ++k) {
+        const float v = win[ci * WX + lane + k];
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) acc[j] = fmaf(wts[((wave * CPW + j) * kCIC + ci) * K + k], v, acc[j]);
+      }
+  }
+  const int x = x0 + lane;
+  if (x >= m) return;
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int o = o0 + wave * CPW + j;
+    if (o >= Cout) continue;
+    const float z = acc[j] + (bias ? bias[o] : 0.f);
+    const int64_t at = (b * Cout + o) * (int64_t)m + x;
+    if (pre) pre[at] = z;
+    act[at] = gelu ? gelu_f(z) : z;
+  }
+}
+
+// Weight gradient of one layer: gW[o, c, k] = sum_{b, x} g[b, o, x] a[b, c, x + k - K/2] and
+// gb[o] = sum_{b, x} g[b, o, x].  Block (o, c-group of 8): threads stride over (b, x) and keep
+// 8 K partial sums; then a fixed-order reduction (wave shuffles, then the four waves).
+__global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ a, int Cin, const float* __restrict__ g,
+                                                    int Cout, int K, int m, int64_t B, float* __restrict__ gW,
+                                                    float* __restrict__ gb) {
+  constexpr int CG = 8;
+  constexpr int KMAX = 15;
+  __shared__ float red[4][CG * KMAX + 1];
+  const int o = blockIdx.x;
+  const int c0 = blockIdx.y * CG;
+  const int h = K / 2;
+  float acc[CG * KMAX + 1];
+#pragma unroll
+  for (int j = 0; j < CG * KMAX + 1; ++j) acc[j] = 0.f;
+  const int64_t total = B * (int64_t)m;
+  for (int64_t p = threadIdx.x; p < total; p += 256) {
+    const int64_t b = p / m;
+    const int x = (int)(p % m);
+    const float gv = g[(b * Cout + o) * (int64_t)m + x];
+    acc[CG * KMAX] += gv;
+#pragma unroll
+    for (int cj = 0; cj < CG; ++cj) {
+      const int c = c0 + cj;
+      if (c >= Cin) break;
+      const float* ar = a + (b * Cin + c) * (int64_t)m;
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k >= K) break;
+        const int xs = x + k - h;
+        if (xs >= 0 && xs < m) acc[cj * KMAX + k] = fmaf(gv, ar[xs], acc[cj * KMAX + k]);
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < CG * KMAX + 1; ++j) {
+    float v = acc[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wave][j] = v;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < CG * KMAX + 1; j += 256) {
+    const float v = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+    if (j == CG * KMAX) {
+      if (blockIdx.y == 0) gb[o] = v;
+    } else {
+      const int cj = j / KMAX, k = j % KMAX;
+      if (c0 + cj < Cin && k < K) gW[((int64_t)o * Cin + c0 + cj) * K + k] = v;
+    }
+  }
+}
+
+// W' (Cin, Cout, K) with W'[c, o, k] = W[o, c, K - 1 - k]: the input gradient of a "same"
+// correlation is the correlation of the output gradient with W'.
+__global__ void k_flip_transpose(const float* __restrict__ W, int Cout, int Cin, int K, float* __restrict__ Wt) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)Cout * Cin * K;
+  if (t >= n) return;
+  const int k = (int)(t % K);
+  const int64_t oc = t / K;
+  const int o = (int)(oc / Cin), c = (int)(oc % Cin);
+  Wt[((int64_t)c * Cout + o) * K + (K - 1 - k)] = W[t];
+}
+
+// g *= GELU'(z) elementwise.
+__global__ void k_gelu_bwd(float* __restrict__ g, const float* __restrict__ z, int64_t n) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) g[t] *= gelu_grad_f(z[t]);
+}
+
+// Relative L2 loss per sample: per[b] = ||y_b - t_b|| / ||t_b||, and the gradient
+// gy_b = (y_b - t_b) / (||y_b - t_b|| ||t_b|| B).  One block per sample.
+__global__ __launch_bounds__(256) void k_rel_l2(const float* __restrict__ y, const float* __restrict__ t, int m,
+                                                int64_t B, float* __restrict__ gy, float* __restrict__ per) {
+  __shared__ float sd[4], st[4];
+  const int64_t b = blockIdx.x;
+  float dd = 0.f, tt = 0.f;
+  for (int x = threadIdx.x; x < m; x += 256) {
+    const float d = y[b * m + x] - t[b * m + x];
+    dd = fmaf(d, d, dd);
+    tt = fmaf(t[b * m + x], t[b * m + x], tt);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    dd += __shfl_xor(dd, off, 64);
+    tt += __shfl_xor(tt, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sd[wave] = dd;
+    st[wave] = tt;
+  }
+  __syncthreads();
+  const float dn = sqrtf(((sd[0] + sd[1]) + sd[2]) + sd[3]);
+  const float tn = sqrtf(((st[0] + st[1]) + st[2]) + st[3]);
+  const float scale = (dn > 0.f && tn > 0.f) ? 1.0f / (dn * tn * (float)B) : 0.f;
+  for (int x = threadIdx.x; x < m; x += 256) gy[b * m + x] = (y[b * m + x] - t[b * m + x]) * scale;
+  if (threadIdx.x == 0) per[b] = tn > 0.f ? dn / tn : 0.f;
+}
+
+// mean of B values in one block (fixed order)
+__global__ void k_mean(const float* __restrict__ v, int64_t B, float* __restrict__ out) {
+  __shared__ float s[256];
+  float a = 0.f;
+  for (int64_t i = threadIdx.x; i < B; i += 256) a += v[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float tot = 0.f;
+    for (int i = 0; i < 256; ++i) tot += s[i];
+    *out = tot / (float)B;
+  }
+}
+
+// Adam (Kingma & Ba, Algorithm 1); c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t).
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ mo,
+                       float* __restrict__ ve, int64_t n, float lr, float beta1, float beta2, float eps, float c1,
+                       float c2) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const float gi = g[t];
+  const float m1 = beta1 * mo[t] + (1.f - beta1) * gi;
+  const float v1 = beta2 * ve[t] + (1.f - beta2) * gi * gi;
+  mo[t] = m1;
+  ve[t] = v1;
+  p[t] -= lr * (m1 * c1) / (sqrtf(v1 * c2) + eps);
+}
+
+}  // namespace
+
+static unsigned nb1(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+size_t net_conv_smem(int K, int CPW) { return sizeof(float) * ((size_t)kCIC * (kTX + K - 1) + 4 * CPW * kCIC * K); }
+
+hipError_t launch_conv_fwd(const float* in, int Cin, const float* W, const float* bias, int Cout, int K, int m,
+                           int64_t B, float* pre, float* act, int gelu, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  if (!in || !W || !act || K < 1 || K > 15 || (K % 2) == 0) return hipErrorInvalidValue;
+  const unsigned gx = (unsigned)((m + kTX - 1) / kTX);
+  if (Cout >= 16) {
+    constexpr int CPW = 4;
+    dim3 grid(gx, (unsigned)((Cout + 4 * CPW - 1) / (4 * CPW)), (unsigned)B);
+    hipLaunchKernelGGL((k_conv_fwd<CPW>), grid, dim3(256), net_conv_smem(K, CPW), st, in, Cin, W, bias, Cout, K, m,
+                       pre, act, gelu);
+  } else {
+    constexpr int CPW = 1;
+    dim3 grid(gx, (unsigned)((Cout + 3) / 4), (unsigned)B);
+    hipLaunchKernelGGL((k_conv_fwd<CPW>), grid, dim3(256), net_conv_smem(K, CPW), st, in, Cin, W, bias, Cout, K, m,
+                       pre, act, gelu);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_conv_wgrad(const float* a, int Cin, const float* g, int Cout, int K, int m, int64_t B, float* gW,
+                             float* gb, hipStream_t st) {
+  if (K < 1 || K > 15) return hipErrorInvalidValue;
+  dim3 grid((unsigned)Cout, (unsigned)((Cin + 7) / 8));
+  hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(256), 0, st, a, Cin, g, Cout, K, m, B, gW, gb);
+  return hipGetLastError();
+}
+
+hipError_t launch_flip_transpose(const float* W, int Cout, int Cin, int K, float* Wt, hipStream_t st) {
+  const int64_t n = (int64_t)Cout * Cin * K;
+  hipLaunchKernelGGL(k_flip_transpose, dim3(nb1(n)), dim3(256), 0, st, W, Cout, Cin, K, Wt);
+  return hipGetLastError();
+}
+
+hipError_t launch_gelu_bwd(float* g, const float* z, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_gelu_bwd, dim3(nb1(n)), dim3(256), 0, st, g, z, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_rel_l2(const float* y, const float* t, int m, int64_t B, float* gy, float* per, float* mean,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_rel_l2, dim3((unsigned)B), dim3(256), 0, st, y, t, m, B, gy, per);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, per, B, mean);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* mo, float* ve, int64_t n, float lr, int64_t t,
+                       hipStream_t st) {
+  const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+  const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, (double)t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, (double)t)));
+  hipLaunchKernelGGL(k_adam, dim3(nb1(n)), dim3(256), 0, st, p, g, mo, ve, n, lr, beta1, beta2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace infoesrf

@@ -101,6 +101,32 @@ def library():
     lib.infoesrf_update_batched.argtypes = [P(ProblemC), C.c_int32, P(C.c_int32), P(PD), P(PD), P(VP), P(VP),
                                             P(VP), P(Opts), P(Lattice), P(StatsC), VP, C.c_size_t, VP]
     lib.infoesrf_update_batched.restype = C.c_int
+    FP = P(C.c_float)
+    lib.infoesrf_net_create.argtypes = [C.c_int32, C.c_int32, C.c_uint64, P(VP)]
+    lib.infoesrf_net_create.restype = C.c_int
+    lib.infoesrf_net_load.argtypes = [C.c_char_p, P(VP)]
+    lib.infoesrf_net_load.restype = C.c_int
+    lib.infoesrf_net_save.argtypes = [VP, C.c_char_p]
+    lib.infoesrf_net_save.restype = C.c_int
+    lib.infoesrf_net_free.argtypes = [VP]
+    lib.infoesrf_net_free.restype = None
+    lib.infoesrf_net_param_count.argtypes = [VP]
+    lib.infoesrf_net_param_count.restype = C.c_int64
+    lib.infoesrf_net_get_params.argtypes = [VP, FP]
+    lib.infoesrf_net_get_params.restype = C.c_int
+    lib.infoesrf_net_set_params.argtypes = [VP, FP]
+    lib.infoesrf_net_set_params.restype = C.c_int
+    lib.infoesrf_net_workspace_bytes.argtypes = [VP, C.c_int64, C.c_int64, C.c_int32]
+    lib.infoesrf_net_workspace_bytes.restype = C.c_size_t
+    lib.infoesrf_net_forward.argtypes = [VP, VP, C.c_int64, C.c_int64, VP, VP, C.c_size_t, VP]
+    lib.infoesrf_net_forward.restype = C.c_int
+    lib.infoesrf_net_gradients.argtypes = [VP, VP, VP, C.c_int64, C.c_int64, VP, VP, VP, C.c_size_t, VP]
+    lib.infoesrf_net_gradients.restype = C.c_int
+    lib.infoesrf_net_train_step.argtypes = [VP, VP, VP, C.c_int64, C.c_int64, C.c_float, VP, VP, C.c_size_t, VP]
+    lib.infoesrf_net_train_step.restype = C.c_int
+    lib.infoesrf_warmstart_pairs.argtypes = [P(ProblemC), C.c_int32, P(C.c_double), P(C.c_double), VP, VP, VP,
+                                             P(Opts), P(StatsC), VP, C.c_size_t, VP]
+    lib.infoesrf_warmstart_pairs.restype = C.c_int
     lib.infoesrf_quadrature_elliptic.argtypes = [C.c_int32, C.c_double, P(C.c_double), P(C.c_double)]
     lib.infoesrf_quadrature_elliptic.restype = C.c_int
     lib.infoesrf_quadrature_gauss_legendre.argtypes = [C.c_int32, P(C.c_double), P(C.c_double)]
@@ -128,6 +154,8 @@ def default_opts(**kw) -> Opts:
             o.lattice = Lattice(*v)
         elif k == "sketch":
             o.sketch = 0 if v is None else v.data_ptr()
+        elif k == "net":
+            o.net = None if v is None else (v.h.value if isinstance(v, Net) else v)
         else:
             setattr(o, k, v)
     return o
@@ -391,12 +419,130 @@ class BatchedRunner:
         return Stats(code, *(t.cpu().numpy() for t in self.keep))
 
 
+class Net:
+    """Warm-start network handle (device parameters, Adam state); see infoesrf_net_* in the header."""
+
+    def __init__(self, handle):
+        self.h = C.c_void_p(handle) if not isinstance(handle, C.c_void_p) else handle
+        self._ws = {}
+
+    @classmethod
+    def create(cls, hidden=64, kernel=9, seed=0):
+        h = C.c_void_p()
+        _check(library().infoesrf_net_create(hidden, kernel, seed, C.byref(h)), allow_warn=False)
+        return cls(h)
+
+    @classmethod
+    def load(cls, path):
+        h = C.c_void_p()
+        _check(library().infoesrf_net_load(str(path).encode(), C.byref(h)), allow_warn=False)
+        return cls(h)
+
+    def save(self, path):
+        _check(library().infoesrf_net_save(self.h, str(path).encode()), allow_warn=False)
+
+    def free(self):
+        if self.h:
+            library().infoesrf_net_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def param_count(self):
+        return int(library().infoesrf_net_param_count(self.h))
+
+    def params(self):
+        out = np.zeros(self.param_count, dtype=np.float32)
+        _check(library().infoesrf_net_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float))), allow_warn=False)
+        return out
+
+    def set_params(self, values):
+        v = np.ascontiguousarray(values, dtype=np.float32)
+        assert v.size == self.param_count
+        _check(library().infoesrf_net_set_params(self.h, v.ctypes.data_as(C.POINTER(C.c_float))), allow_warn=False)
+
+    def _workspace(self, B, m, training):
+        torch = _torch()
+        key = (B, m, bool(training))
+        if key not in self._ws:
+            nbytes = library().infoesrf_net_workspace_bytes(self.h, B, m, 1 if training else 0)
+            if nbytes == 0:
+                raise InfoEsrfError(ERR_INVALID_ARG, library().infoesrf_last_error().decode())
+            self._ws = {key: torch.empty(nbytes, dtype=torch.uint8, device="cuda")}
+        return self._ws[key]
+
+    def forward(self, X):
+        """X: (B, 3, m) float32 CUDA tensor -> (B, m)."""
+        torch = _torch()
+        X = X.contiguous()
+        B, _, m = X.shape
+        Y = torch.empty((B, m), dtype=torch.float32, device=X.device)
+        ws = self._workspace(B, m, False)
+        _check(library().infoesrf_net_forward(self.h, X.data_ptr(), B, m, Y.data_ptr(), ws.data_ptr(), ws.numel(),
+                                              _stream()), allow_warn=False)
+        return Y
+
+    def gradients(self, X, T):
+        """(gradient in the parameter layout, loss) of the mean relative L2 loss."""
+        torch = _torch()
+        X, T = X.contiguous(), T.contiguous()
+        B, _, m = X.shape
+        g = torch.empty(self.param_count, dtype=torch.float32, device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        ws = self._workspace(B, m, True)
+        _check(library().infoesrf_net_gradients(self.h, X.data_ptr(), T.data_ptr(), B, m, g.data_ptr(),
+                                                loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream()),
+               allow_warn=False)
+        return g, loss
+
+    def train_step(self, X, T, lr):
+        """One Adam step; returns the batch loss before the step (device tensor)."""
+        torch = _torch()
+        B, _, m = X.shape
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        ws = self._workspace(B, m, True)
+        _check(library().infoesrf_net_train_step(self.h, X.data_ptr(), T.data_ptr(), B, m, float(lr),
+                                                 loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream()),
+               allow_warn=False)
+        return loss
+
+
+def warmstart_pairs(problem: Problem, s_nodes, p_weights, y, opts: Opts | None = None):
+    """Training pairs (X (QN, 3, m), T (QN, m), Stats) of the perturbation update's systems."""
+    torch = _torch()
+    lib = library()
+    opts = opts or default_opts()
+    dev = problem.X.device
+    s_nodes = np.ascontiguousarray(s_nodes, dtype=np.float64)
+    p_weights = np.ascontiguousarray(p_weights, dtype=np.float64)
+    Q = len(s_nodes)
+    S = Q * problem.N
+    X = torch.empty((S, 3, problem.m), dtype=torch.float32, device=dev)
+    T = torch.empty((S, problem.m), dtype=torch.float32, device=dev)
+    yt = torch.as_tensor(np.asarray(y, dtype=np.float64)).to(dev)
+    ws = _workspace(workspace_bytes(problem, Q, opts), dev)
+    sc, keep = _stats(S, dev)
+    dp = C.POINTER(C.c_double)
+    code = _check(lib.infoesrf_warmstart_pairs(C.byref(problem.c), Q, s_nodes.ctypes.data_as(dp),
+                                               p_weights.ctypes.data_as(dp), yt.data_ptr(), X.data_ptr(),
+                                               T.data_ptr(), C.byref(opts), C.byref(sc), ws.data_ptr(), ws.numel(),
+                                               _stream()))
+    torch.cuda.synchronize()
+    return X, T, Stats(code, *(t.cpu().numpy() for t in keep))
+
+
 class PerturbationRunner:
     """Preallocated perturbation update: run() only enqueues the C call (no allocation)."""
 
-    def __init__(self, problem: Problem, s_nodes, p_weights, opts: Opts):
+    def __init__(self, problem: Problem, s_nodes, p_weights, opts: Opts, y=None):
         torch = _torch()
         self.lib = library()
+        self.y = None if y is None else torch.as_tensor(np.asarray(y, dtype=np.float64)).to(problem.X.device)
         self.problem = problem
         self.opts = opts
         self.s = np.ascontiguousarray(s_nodes, dtype=np.float64)
@@ -413,7 +559,8 @@ class PerturbationRunner:
 
     def run(self):
         return _check(self.lib.infoesrf_perturbation_update(
-            C.byref(self.problem.c), self.Q, self._sp, self._pp, None, self.out.data_ptr(), C.byref(self.opts),
+            C.byref(self.problem.c), self.Q, self._sp, self._pp,
+            None if self.y is None else C.c_void_p(self.y.data_ptr()), self.out.data_ptr(), C.byref(self.opts),
             C.byref(self.sc), self.ws.data_ptr(), self.ws.numel(), _stream()))
 
     def result(self):

@@ -103,7 +103,8 @@ def test_option_and_node_validation():
     dp = C.POINTER(C.c_double)
     s = np.ones(4)
     for kw in (dict(rtol=0.0), dict(max_iter=0), dict(n_ritz=7), dict(precision=9), dict(tile_rows=48),
-               dict(cov_form=5), dict(cov_form=ie.COV_BAND, precision=ie.MIXED_BF16)):
+               dict(cov_form=5), dict(cov_form=ie.COV_BAND, precision=ie.MIXED_BF16), dict(warm_start=1),
+               dict(warm_start=3)):
         o = ie.default_opts(**kw)
         assert lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(o)) == 0
     o = ie.default_opts()
@@ -197,3 +198,27 @@ def test_band_form_workspace():
     d = fake_problem(kind=ie.LOC_DENSE)
     assert lib.infoesrf_workspace_bytes(C.byref(d), 4, C.byref(ie.default_opts(cov_form=ie.COV_BAND))) == 0
     assert "band form" in lib.infoesrf_last_error().decode()
+
+
+def test_net_argument_validation(tmp_path):
+    """Network entry points reject bad arguments before any device allocation."""
+    lib = ie.library()
+    h = C.c_void_p()
+    assert lib.infoesrf_net_create(0, 9, 1, C.byref(h)) == ie.ERR_INVALID_ARG
+    assert lib.infoesrf_net_create(64, 8, 1, C.byref(h)) == ie.ERR_INVALID_ARG
+    assert lib.infoesrf_net_create(64, 17, 1, C.byref(h)) == ie.ERR_INVALID_ARG
+    assert lib.infoesrf_net_param_count(None) == 0
+    assert lib.infoesrf_net_workspace_bytes(None, 4, 100, 0) == 0
+    bad = tmp_path / "bad.ienet"
+    bad.write_bytes(b"NOTANET!" + b"\0" * 40)
+    assert lib.infoesrf_net_load(str(bad).encode(), C.byref(h)) == ie.ERR_INVALID_ARG
+    assert "not a warm-start network" in lib.infoesrf_last_error().decode()
+    assert lib.infoesrf_net_load(str(tmp_path / "missing").encode(), C.byref(h)) == ie.ERR_INVALID_ARG
+    # the learned start needs the observations
+    p = fake_problem()
+    s = np.ones(4)
+    dp = C.POINTER(C.c_double)
+    o = ie.default_opts(warm_start=ie.START_LEARNED, net=0x1000)
+    rc = lib.infoesrf_perturbation_update(C.byref(p), 4, s.ctypes.data_as(dp), s.ctypes.data_as(dp), None,
+                                          C.c_void_p(0x1000), C.byref(o), None, C.c_void_p(0x1000), 1 << 30, None)
+    assert rc == ie.ERR_INVALID_ARG and "needs y" in lib.infoesrf_last_error().decode()
