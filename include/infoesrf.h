@@ -219,8 +219,8 @@ int infoesrf_mean_update(const infoesrf_problem* prob, const double* y, double* 
  * the analysis ensemble is mean_a 1^T + Xa_pert.
  *   s_nodes, p_weights  host arrays of Q quadrature nodes (>= 0) and
  *                       weights (>= 0), e.g. from infoesrf_quadrature_elliptic.
- *   y                   m observations, used only by the learned warm start
- *                       (its innovation input); may be NULL otherwise.
+ *   y                   m observations; not used by the perturbation update
+ *                       (kept for callers that pass them), may be NULL.
  * Q must be in [1, 64].
  */
 int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const double* s_nodes,
@@ -281,14 +281,17 @@ const char* infoesrf_last_error(void);
  * system from zero).  A 1-D convolutional network over the m observation rows
  * (3 -> H -> H -> H -> 1 channels, odd kernel width K <= 15, "same" zero
  * padding, GELU after the first three layers, FP32 parameters) maps the
- * features of system (q, i)
- *     channel 0: b_i / ||b_i||,  channel 1: 1 / (1 + s_q),  channel 2: d / ||d||,
- *     with d = R^{-1/2} (y - H mu) (eq. E.1 and Sec. 3.2),
- * to u0 = ||b_i|| net(.), the initial guess of C_q u = b_i.  With
+ * features of system (q, i), with bh = sqrt(m) b_i / ||b_i|| and
+ * c = 1 / (1 + s_q),
+ *     channel 0: bh c,  channel 1: bh c^2,  channel 2: c
+ * (the first two are the leading terms of the Neumann series of C_q^{-1} b,
+ * eq. E.1) to u0 = (||b_i|| / sqrt(m)) net(.), the initial guess of
+ * C_q u = b_i.  A created network's output layer is zero (it predicts the
+ * zero start until trained).  With
  * warm_start = INFOESRF_START_LEARNED and opts->net set, the perturbation
- * update (which then needs y) starts every system from u0; a system whose u0
- * is not finite starts from zero and counters[FALLBACKS] counts it.  The mean
- * system always starts from zero.
+ * update starts every system from u0; a system whose u0 is not finite starts
+ * from zero and counters[FALLBACKS] counts it.  The mean system always starts
+ * from zero.
  *
  * Handles own device memory (parameters, Adam moments, a gradient buffer),
  * allocated by create/load and released by free; never on the update path.
@@ -298,7 +301,7 @@ const char* infoesrf_last_error(void);
  * Batches: X is B x 3 x m, Y and targets T are B x m, FP32 row-contiguous
  * device arrays; workspaces from infoesrf_net_workspace_bytes (training != 0
  * keeps every activation for the backward pass).  The loss is the batch mean
- * of ||Y_b - T_b|| / ||T_b|| (T = u* / ||b|| for exact solutions u*), written
+ * of ||Y_b - T_b|| / ||T_b|| (T = sqrt(m) u* / ||b|| for exact solutions u*), written
  * to the device float *loss; gradients have the parameter layout; a training
  * step is one Adam update (beta1 0.9, beta2 0.999, eps 1e-8).
  */
@@ -321,10 +324,10 @@ int infoesrf_net_train_step(void* net, const float* X, const float* T, int64_t B
  * Training pairs for the warm start: solves the Q N systems of the
  * perturbation update exactly as infoesrf_perturbation_update does (same
  * options; warm_start must be ZERO) and writes, for system s = q N + i,
- * X[s] (3 x m) the network features above and T[s] (m) = u*_s / ||b_s||, the
+ * X[s] (3 x m) the network features above and T[s] (m) = sqrt(m) u*_s / ||b_s||, the
  * converged solution scaled like the network output.  X: Q N x 3 x m FP32,
- * T: Q N x m FP32 (device).  y: the m observations (device).  Workspace:
- * infoesrf_workspace_bytes(prob, Q, opts).
+ * T: Q N x m FP32 (device).  y may be NULL (the systems do not depend on it).
+ * Workspace: infoesrf_workspace_bytes(prob, Q, opts).
  */
 int infoesrf_warmstart_pairs(const infoesrf_problem* prob, int32_t Q, const double* s_nodes,
                              const double* p_weights, const double* y, float* X, float* T,

@@ -2,10 +2,15 @@
 
 The warm start extends the method (it is not in the paper): a small 1-D
 convolutional network predicts the initial guess of each shifted system
-C_q u = b_i (Appendix E, eq. E.1) from three input channels over the m
-observation rows -- the right-hand side b_i/||b_i||, the shift feature
-1/(1+s_q) and the normalized innovation d/||d||, d = R^{-1/2}(y - H mu) --
-and the prediction is u0 = ||b_i|| net(.), so u0 scales with b_i.
+C_q u = b_i (Appendix E, eq. E.1), C_q = (1 + s_q) I + S, from three input
+channels over the m observation rows, with bh = sqrt(m) b_i/||b_i|| (unit
+root-mean-square entries):
+    bh/(1+s_q), bh/(1+s_q)^2 and 1/(1+s_q),
+the first two being the leading terms of the Neumann series
+u = sum_k (-S)^k b / (1+s)^(k+1) (so a network that acts as a convolution
+like S reproduces its first-order truncation), and the prediction is
+u0 = (||b_i|| / sqrt(m)) net(.), so u0 scales with b_i.  Training targets are
+u* sqrt(m) / ||b_i||.
 
 Its arithmetic is standard and is written out here from the definitions:
   * cross-correlation with zero "same" padding:
@@ -104,22 +109,30 @@ def backward(params, cache, gout):
     return grads
 
 
-def features(b, s, d):
-    """Network input (B, 3, m) of systems with right-hand sides b (B, m), shifts s (B,), innovation d (m,)."""
+def features(b, s):
+    """Network input (B, 3, m) of systems with right-hand sides b (B, m) and shifts s (B,)."""
     b = np.atleast_2d(np.asarray(b, dtype=np.float64))
     B, m = b.shape
+    bh = np.sqrt(m) * b / np.linalg.norm(b, axis=1)[:, None]
+    c = 1.0 / (1.0 + np.asarray(s, dtype=np.float64))
     X = np.empty((B, 3, m))
-    X[:, 0, :] = b / np.linalg.norm(b, axis=1)[:, None]
-    X[:, 1, :] = (1.0 / (1.0 + np.asarray(s, dtype=np.float64)))[:, None]
-    X[:, 2, :] = (np.asarray(d) / np.linalg.norm(d))[None, :]
+    X[:, 0, :] = bh * c[:, None]
+    X[:, 1, :] = bh * (c * c)[:, None]
+    X[:, 2, :] = c[:, None]
     return X
 
 
-def predict(params, b, s, d):
-    """Warm starts u0 = ||b|| net(features) (B, m)."""
+def predict(params, b, s):
+    """Warm starts u0 = (||b|| / sqrt(m)) net(features) (B, m)."""
     b = np.atleast_2d(np.asarray(b, dtype=np.float64))
-    Y, _ = forward(params, features(b, s, d))
-    return np.linalg.norm(b, axis=1)[:, None] * Y[:, 0, :]
+    Y, _ = forward(params, features(b, s))
+    return (np.linalg.norm(b, axis=1) / np.sqrt(b.shape[1]))[:, None] * Y[:, 0, :]
+
+
+def targets(u, b):
+    """Training targets u* sqrt(m) / ||b|| (B, m) of exact solutions u (B, m)."""
+    b = np.atleast_2d(np.asarray(b, dtype=np.float64))
+    return np.sqrt(b.shape[1]) * np.atleast_2d(u) / np.linalg.norm(b, axis=1)[:, None]
 
 
 def loss_rel_l2(Y, T):

@@ -117,24 +117,26 @@ __global__ void k_set_nodes(Nodes nd, int32_t Q, int64_t N, double* sigma, doubl
 // Sweep bookkeeping from true residual norms (iterative refinement).
 //   fdone: 1 converged (rn <= rtol bn), 2 failed (iteration cap or non-finite), 0 needs work.
 //   done (inner PCG status) = fdone ? 1 : 0; thresh = absolute inner target.
-// Network features of systems s0 .. s0 + cnt (see infoesrf.h): X[(s - s0), 0..2, r] from the
-// right-hand sides b (system-major, ld), the shifts sigma and the innovation d (norm *dn).
+// Network features of systems s0 .. s0 + cnt (see infoesrf.h): with bh = sqrt(m) b_s / ||b_s||
+// and c = 1 / (1 + sigma_s), X[(s - s0)] = (bh c, bh c^2, c), the first two being the leading
+// terms of the Neumann series of C_q^{-1} b.  b system-major (ld).
 __global__ void k_net_features(const double* __restrict__ b, int64_t ld, const double* __restrict__ bn,
-                               const double* __restrict__ sigma, const double* __restrict__ d,
-                               const double* __restrict__ dn, int64_t m, int64_t s0, int64_t cnt,
+                               const double* __restrict__ sigma, int64_t m, int64_t s0, int64_t cnt,
                                float* __restrict__ X) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= cnt * m) return;
   const int64_t j = t / m, r = t % m, s = s0 + j;
-  const double nb = bn[s], nd = *dn;
+  const double nb = bn[s];
+  const double c = 1.0 / (1.0 + sigma[s]);
+  const double bh = nb > 0.0 ? sqrt((double)m) * b[s * ld + r] / nb : 0.0;
   float* x = X + j * 3 * m;
-  x[r] = nb > 0.0 ? (float)(b[s * ld + r] / nb) : 0.f;
-  x[m + r] = (float)(1.0 / (1.0 + sigma[s]));
-  x[2 * m + r] = nd > 0.0 ? (float)(d[r] / nd) : 0.f;
+  x[r] = (float)(bh * c);
+  x[m + r] = (float)(bh * c * c);
+  x[2 * m + r] = (float)c;
 }
 
-// u_s = ||b_s|| Y_s for systems s0 .. s0 + cnt (one block each); a system whose prediction is not
-// finite starts from zero and is counted in *fallbacks.
+// u_s = (||b_s|| / sqrt(m)) Y_s for systems s0 .. s0 + cnt (one block each); a system whose
+// prediction is not finite starts from zero and is counted in *fallbacks.
 __global__ __launch_bounds__(256) void k_warm_init(const float* __restrict__ Y, const double* __restrict__ bn,
                                                    int64_t m, int64_t s0, double* __restrict__ u, int64_t ld,
                                                    int32_t* __restrict__ fallbacks) {
@@ -146,19 +148,19 @@ __global__ __launch_bounds__(256) void k_warm_init(const float* __restrict__ Y, 
   for (int64_t r = threadIdx.x; r < m; r += 256)
     if (!isfinite(y[r])) bad = 1;
   __syncthreads();
-  const double nb = bn[s];
-  for (int64_t r = threadIdx.x; r < m; r += 256) u[s * ld + r] = bad ? 0.0 : nb * (double)y[r];
+  const double sc = bn[s] / sqrt((double)m);
+  for (int64_t r = threadIdx.x; r < m; r += 256) u[s * ld + r] = bad ? 0.0 : sc * (double)y[r];
   if (bad && threadIdx.x == 0) atomicAdd(fallbacks, 1);
 }
 
-// Training targets T[s, r] = u_s[r] / ||b_s|| (FP32).
+// Training targets T[s, r] = sqrt(m) u_s[r] / ||b_s|| (FP32).
 __global__ void k_net_targets(const double* __restrict__ u, int64_t ld, const double* __restrict__ bn, int64_t m,
                               int64_t S, float* __restrict__ T) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= S * m) return;
   const int64_t s = t / m, r = t % m;
   const double nb = bn[s];
-  T[t] = nb > 0.0 ? (float)(u[s * ld + r] / nb) : 0.f;
+  T[t] = nb > 0.0 ? (float)(sqrt((double)m) * u[s * ld + r] / nb) : 0.f;
 }
 
 __global__ void k_sweep_status(const double* rn, const double* bn, double rtol, double inner_rtol, int fp64_inner,
@@ -276,10 +278,8 @@ struct Inst {
   // for MIXED_FP32 inner applies in that domain, an FP32 copy
   bool band = false;
   void *bandS = nullptr, *bandS32 = nullptr, *bandO = nullptr, *bandO32 = nullptr;
-  // learned warm start: innovation d = R^{-1/2}(y - H mu) and its norm, network buffers for a
-  // chunk of systems (features, outputs, the network's own workspace)
-  const double* y = nullptr;
-  double *d = nullptr, *dnorm = nullptr;
+  // learned warm start: network buffers for a chunk of systems (features, outputs, the network's
+  // own workspace)
   const Net* net = nullptr;
   int64_t wchunk = 0;
   float *wX = nullptr, *wY = nullptr;
@@ -478,8 +478,6 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   in.flags = ar.take<int32_t>(1);
   in.fallbacks = ar.take<int32_t>(1);
   in.counters = ar.take<int64_t>(INFOESRF_NUM_COUNTERS);
-  in.d = ar.take<double>(in.m);
-  in.dnorm = ar.take<double>(1);
   if (op.warm == INFOESRF_START_LEARNED && S > 1) {
     in.net = static_cast<const Net*>(op.net);
     in.wchunk = std::min<int64_t>(S, 128);
@@ -817,18 +815,15 @@ class LivePoll {
   int head_ = 0, pending_ = 0;
 };
 
-// Learned warm start: u = ||b|| net(b/||b||, 1/(1+sigma), d/||d||) for every system, in chunks of
+// Learned warm start: u = ||b|| net(features of b and sigma) for every system, in chunks of
 // in.wchunk systems (non-finite predictions fall back to zero).  Needs sy.bnorm.
 int stage_warm(Plan& pl, hipStream_t st) {
   Inst& in = pl.in;
   Sys& sy = pl.sy;
-  const infoesrf_problem* P = in.P;
-  IE_HIP(launch_innovation(P->h_ptr, P->h_idx, P->h_w, P->r_var, in.y, in.mu, in.m, in.n, in.d, sy.ldm, 0, st));
-  IE_HIP(launch_col_norms(in.d, in.m, 1, sy.ldm, in.dnorm, st));
   for (int64_t s0 = 0; s0 < sy.S; s0 += in.wchunk) {
     const int64_t cnt = std::min<int64_t>(in.wchunk, sy.S - s0);
     hipLaunchKernelGGL(k_net_features, dim3(nb(cnt * in.m)), dim3(256), 0, st, sy.b, sy.ldm, sy.bnorm, sy.sigma,
-                       in.d, in.dnorm, in.m, s0, cnt, in.wX);
+                       in.m, s0, cnt, in.wX);
     IE_HIP(hipGetLastError());
     IE_TRY(net_forward(*in.net, in.wX, cnt, in.m, in.wY, in.wnet, in.wnet_bytes, st));
     hipLaunchKernelGGL(k_warm_init, dim3((unsigned)cnt), dim3(256), 0, st, in.wY, sy.bnorm, in.m, s0, sy.u, sy.ldm,
@@ -1116,8 +1111,6 @@ int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_
   IE_TRY(resolve_options(prob, opts, op));
   IE_CHECK(Q >= 1 && Q <= kMaxQ, INFOESRF_ERR_INVALID_ARG, "Q must be in [1, 64]");
   IE_CHECK(s_nodes && p_weights, INFOESRF_ERR_INVALID_ARG, "s_nodes and p_weights must be non-NULL");
-  IE_CHECK(op.warm != INFOESRF_START_LEARNED || y != nullptr, INFOESRF_ERR_INVALID_ARG,
-           "the learned warm start needs y (its innovation input)");
   Nodes nd{};
   for (int q = 0; q < Q; ++q) {
     IE_CHECK(std::isfinite(s_nodes[q]) && s_nodes[q] >= 0.0, INFOESRF_ERR_INVALID_ARG, "quadrature nodes must be >= 0");
@@ -1129,8 +1122,8 @@ int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_
   IE_CHECK(ws != nullptr, INFOESRF_ERR_WORKSPACE, "workspace is NULL");
   const int64_t N = prob->N;
   const int64_t S = (int64_t)Q * N;
+  (void)y;  // the observations do not enter the shifted systems' solutions
   IE_TRY(plan_for(pl, prob, op, S, N, ws, ws_bytes));
-  pl.in.y = y;
   IE_TRY(check_nnz(prob, op, st));
   IE_TRY(stage_setup(pl, op, st));
   Sys& sy = pl.sy;
@@ -1351,7 +1344,7 @@ int infoesrf_warmstart_pairs(const infoesrf_problem* prob, int32_t Q, const doub
                              const infoesrf_opts* opts, infoesrf_stats* stats, void* ws, size_t ws_bytes,
                              void* stream) {
   clear_error();
-  IE_CHECK(X && T && y, INFOESRF_ERR_INVALID_ARG, "X, T and y must be non-NULL");
+  IE_CHECK(X && T, INFOESRF_ERR_INVALID_ARG, "X and T must be non-NULL");
   IE_CHECK(!opts || opts->warm_start == INFOESRF_START_ZERO, INFOESRF_ERR_INVALID_ARG,
            "training pairs are solved from the zero start");
   Plan pl;
@@ -1360,11 +1353,8 @@ int infoesrf_warmstart_pairs(const infoesrf_problem* prob, int32_t Q, const doub
   IE_TRY(perturbation_solve(prob, Q, s_nodes, p_weights, y, opts, pl, op, ws, ws_bytes, st));
   Inst& in = pl.in;
   Sys& sy = pl.sy;
-  IE_HIP(launch_innovation(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, y, in.mu, in.m, in.n, in.d, sy.ldm, 0,
-                           st));
-  IE_HIP(launch_col_norms(in.d, in.m, 1, sy.ldm, in.dnorm, st));
-  hipLaunchKernelGGL(k_net_features, dim3(nb(sy.S * in.m)), dim3(256), 0, st, sy.b, sy.ldm, sy.bnorm, sy.sigma, in.d,
-                     in.dnorm, in.m, (int64_t)0, sy.S, X);
+  hipLaunchKernelGGL(k_net_features, dim3(nb(sy.S * in.m)), dim3(256), 0, st, sy.b, sy.ldm, sy.bnorm, sy.sigma,
+                     in.m, (int64_t)0, sy.S, X);
   IE_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_net_targets, dim3(nb(sy.S * in.m)), dim3(256), 0, st, sy.u, sy.ldm, sy.bnorm, in.m, sy.S, T);
   IE_HIP(hipGetLastError());

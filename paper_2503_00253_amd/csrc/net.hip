@@ -176,9 +176,10 @@ extern "C" int infoesrf_net_create(int32_t hidden, int32_t kernel, uint64_t seed
   h->K = kernel;
   h->count = net_param_count(hidden, kernel);
   std::vector<float> host((size_t)h->count, 0.f);
-  // uniform(-a, a) weights with a = sqrt(6 / (Cin K)), zero biases
+  // uniform(-a, a) weights with a = sqrt(6 / (Cin K)), zero biases; the output layer starts at
+  // zero, so an untrained network predicts the zero start
   uint64_t ctr = seed * 0x100000001B3ULL;
-  for (int l = 0; l < 4; ++l) {
+  for (int l = 0; l < 3; ++l) {
     int64_t wo, bo;
     int ci, co;
     net_layer(*h, l, &wo, &bo, &ci, &co);

@@ -512,7 +512,7 @@ class Net:
         return loss
 
 
-def warmstart_pairs(problem: Problem, s_nodes, p_weights, y, opts: Opts | None = None):
+def warmstart_pairs(problem: Problem, s_nodes, p_weights, y=None, opts: Opts | None = None):
     """Training pairs (X (QN, 3, m), T (QN, m), Stats) of the perturbation update's systems."""
     torch = _torch()
     lib = library()
@@ -524,12 +524,15 @@ def warmstart_pairs(problem: Problem, s_nodes, p_weights, y, opts: Opts | None =
     S = Q * problem.N
     X = torch.empty((S, 3, problem.m), dtype=torch.float32, device=dev)
     T = torch.empty((S, problem.m), dtype=torch.float32, device=dev)
-    yt = torch.as_tensor(np.asarray(y, dtype=np.float64)).to(dev)
+    yp = 0
+    if y is not None:
+        yt = torch.as_tensor(np.asarray(y, dtype=np.float64)).to(dev)
+        yp = yt.data_ptr()
     ws = _workspace(workspace_bytes(problem, Q, opts), dev)
     sc, keep = _stats(S, dev)
     dp = C.POINTER(C.c_double)
     code = _check(lib.infoesrf_warmstart_pairs(C.byref(problem.c), Q, s_nodes.ctypes.data_as(dp),
-                                               p_weights.ctypes.data_as(dp), yt.data_ptr(), X.data_ptr(),
+                                               p_weights.ctypes.data_as(dp), C.c_void_p(yp), X.data_ptr(),
                                                T.data_ptr(), C.byref(opts), C.byref(sc), ws.data_ptr(), ws.numel(),
                                                _stream()))
     torch.cuda.synchronize()

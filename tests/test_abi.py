@@ -214,11 +214,8 @@ def test_net_argument_validation(tmp_path):
     assert lib.infoesrf_net_load(str(bad).encode(), C.byref(h)) == ie.ERR_INVALID_ARG
     assert "not a warm-start network" in lib.infoesrf_last_error().decode()
     assert lib.infoesrf_net_load(str(tmp_path / "missing").encode(), C.byref(h)) == ie.ERR_INVALID_ARG
-    # the learned start needs the observations
+    # the learned start needs a network
     p = fake_problem()
-    s = np.ones(4)
-    dp = C.POINTER(C.c_double)
-    o = ie.default_opts(warm_start=ie.START_LEARNED, net=0x1000)
-    rc = lib.infoesrf_perturbation_update(C.byref(p), 4, s.ctypes.data_as(dp), s.ctypes.data_as(dp), None,
-                                          C.c_void_p(0x1000), C.byref(o), None, C.c_void_p(0x1000), 1 << 30, None)
-    assert rc == ie.ERR_INVALID_ARG and "needs y" in lib.infoesrf_last_error().decode()
+    o = ie.default_opts(warm_start=ie.START_LEARNED)
+    assert lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(o)) == 0
+    assert "needs opts->net" in lib.infoesrf_last_error().decode()

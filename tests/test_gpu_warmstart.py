@@ -125,11 +125,10 @@ def test_training_pairs_match_oracle():
     # b_i = R^{-1/2} w_i for every node, node-major; exact u* per node from the spectral form
     B = np.tile(dp.B.T, (prob.Q, 1))
     sig = np.repeat(s, prob.N)
-    d = dp.dinv * (prob.y - dp.H @ dp.mu)
-    want_X = wr.features(B, sig, d)
+    want_X = wr.features(B, sig)
     assert rel(X.cpu().numpy(), want_X) < 1e-6
     U = np.concatenate([dp.spectral(lambda lam, sq=sq: 1.0 / (1.0 + sq + lam), dp.B).T for sq in s])
-    want_T = U / np.linalg.norm(B, axis=1)[:, None]
+    want_T = wr.targets(U, B)
     assert rel(T.cpu().numpy(), want_T) < 1e-6
 
 

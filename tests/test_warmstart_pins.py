@@ -88,10 +88,22 @@ def test_prediction_scales_with_rhs():
     params = wr.init_params(channels=(3, 8, 8, 8, 1), K=9, seed=6)
     b = rng.standard_normal((4, 30))
     s = np.array([0.0, 1.5, 10.0, 100.0])
-    d = rng.standard_normal(30)
-    u1 = wr.predict(params, b, s, d)
-    u2 = wr.predict(params, 7.5 * b, s, d)
+    u1 = wr.predict(params, b, s)
+    u2 = wr.predict(params, 7.5 * b, s)
     assert np.allclose(u2, 7.5 * u1, rtol=1e-13, atol=0)
+
+
+def test_neumann_features_solve_the_unlocalized_limit():
+    """With S = 0 the first feature times ||b|| is the exact solution b / (1 + s)."""
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal((3, 20))
+    s = np.array([0.5, 3.0, 40.0])
+    X = wr.features(b, s)
+    scale = (np.linalg.norm(b, axis=1) / np.sqrt(b.shape[1]))[:, None]
+    assert np.allclose(scale * X[:, 0, :], b / (1 + s)[:, None], rtol=1e-14)
+    assert np.allclose(X[:, 1, :] * (1 + s)[:, None], X[:, 0, :], rtol=1e-14)
+    # the exact solution's target is the first feature when S = 0
+    assert np.allclose(wr.targets(b / (1 + s)[:, None], b), X[:, 0, :], rtol=1e-14)
 
 
 def test_loss_zero_at_target():
