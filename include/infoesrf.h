@@ -335,6 +335,32 @@ int infoesrf_warmstart_pairs(const infoesrf_problem* prob, int32_t Q, const doub
                              void* stream);
 
 /*
+ * Cycled assimilation around the update (the experiment of Sec. 5).
+ *
+ * infoesrf_l96_forecast: advances the k columns of X (n = nz nx rows each,
+ * column c at X + c ld, state index layer * nx + site, device FP64) by `steps`
+ * classical RK4 steps of length dt of the coupled multi-layer Lorenz-96 model
+ * (Sec. 5.1, eq. 5.1): periodic sites, forcing[j] per layer (device, nz
+ * values), coupling gamma between adjacent layers, no exchange through the
+ * top and bottom layers.  n <= 8192 (a column is integrated on chip).
+ *
+ * infoesrf_observe: y = H x + noise for one state x (device n), noise (device
+ * m, may be NULL), H the problem's CSR rows.
+ *
+ * infoesrf_rtps_assemble: analysis members Xout[:, i] = mean_a + f o Xa'[:, i]
+ * with the relaxation-to-prior-spread factor f_k = 1 + alpha (s_f - s_a)/s_a
+ * per state variable (Whitaker & Hamill; Sec. 5.3 uses alpha = 0.01), s_f the
+ * standard deviation of the forecast members Xf (n x N, ldf), s_a that of the
+ * analysis deviations Xa' (n x N, lda, e.g. the output of
+ * infoesrf_perturbation_update); f_k = 1 where s_a = 0.  Xout may alias Xf.
+ */
+int infoesrf_l96_forecast(double* X, int64_t ld, int64_t k, int32_t nz, int32_t nx, const double* forcing,
+                          double gamma, double dt, int32_t steps, void* stream);
+int infoesrf_observe(const infoesrf_problem* prob, const double* x, const double* noise, double* y, void* stream);
+int infoesrf_rtps_assemble(const double* Xf, int64_t ldf, const double* mean_a, const double* Xa_pert, int64_t lda,
+                           int64_t n, int64_t N, double alpha, double* Xout, int64_t ldo, void* stream);
+
+/*
  * Measurement hooks (results are unaffected).  While enabled, every launch of
  * a covariance-apply kernel is bracketed by HIP events recorded on the stream
  * it runs on, and the kernel adds the number of vectors it applies and their

@@ -127,6 +127,14 @@ def library():
     lib.infoesrf_warmstart_pairs.argtypes = [P(ProblemC), C.c_int32, P(C.c_double), P(C.c_double), VP, VP, VP,
                                              P(Opts), P(StatsC), VP, C.c_size_t, VP]
     lib.infoesrf_warmstart_pairs.restype = C.c_int
+    lib.infoesrf_l96_forecast.argtypes = [VP, C.c_int64, C.c_int64, C.c_int32, C.c_int32, VP, C.c_double,
+                                          C.c_double, C.c_int32, VP]
+    lib.infoesrf_l96_forecast.restype = C.c_int
+    lib.infoesrf_observe.argtypes = [P(ProblemC), VP, VP, VP, VP]
+    lib.infoesrf_observe.restype = C.c_int
+    lib.infoesrf_rtps_assemble.argtypes = [VP, C.c_int64, VP, VP, C.c_int64, C.c_int64, C.c_int64, C.c_double, VP,
+                                           C.c_int64, VP]
+    lib.infoesrf_rtps_assemble.restype = C.c_int
     lib.infoesrf_quadrature_elliptic.argtypes = [C.c_int32, C.c_double, P(C.c_double), P(C.c_double)]
     lib.infoesrf_quadrature_elliptic.restype = C.c_int
     lib.infoesrf_quadrature_gauss_legendre.argtypes = [C.c_int32, P(C.c_double), P(C.c_double)]
@@ -537,6 +545,29 @@ def warmstart_pairs(problem: Problem, s_nodes, p_weights, y=None, opts: Opts | N
                                                _stream()))
     torch.cuda.synchronize()
     return X, T, Stats(code, *(t.cpu().numpy() for t in keep))
+
+
+def l96_forecast(X, nz, nx, forcing, gamma, dt, steps):
+    """Advance the rows of X (k, n) (each row one state, i.e. a column-major n x k array) in place."""
+    k, n = X.shape
+    _check(library().infoesrf_l96_forecast(X.data_ptr(), n, k, nz, nx, forcing.data_ptr(), float(gamma), float(dt),
+                                           int(steps), _stream()), allow_warn=False)
+    return X
+
+
+def observe(problem: Problem, x, noise, y):
+    """y = H x + noise (device vectors; noise may be None)."""
+    _check(library().infoesrf_observe(C.byref(problem.c), x.data_ptr(), None if noise is None else noise.data_ptr(),
+                                      y.data_ptr(), _stream()), allow_warn=False)
+    return y
+
+
+def rtps_assemble(Xf, mean_a, Xa, alpha, out):
+    """Analysis members out (N, n) = mean_a + RTPS-relaxed deviations Xa (N, n); Xf the forecast members."""
+    N, n = Xf.shape
+    _check(library().infoesrf_rtps_assemble(Xf.data_ptr(), n, mean_a.data_ptr(), Xa.data_ptr(), n, n, N,
+                                            float(alpha), out.data_ptr(), n, _stream()), allow_warn=False)
+    return out
 
 
 class PerturbationRunner:
