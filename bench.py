@@ -53,6 +53,8 @@ def parse():
                          "batch of 64 independent instances in one batched call; lorenz-cycle: cycled "
                          "assimilation of the 8 x 480 multi-layer Lorenz-96 model (steps = cycles)")
     ap.add_argument("--graph", action="store_true", help="lorenz-cycle: replay a HIP graph of one cycle")
+    ap.add_argument("--no-autotune", action="store_true", help="use the built-in block-shape rules")
+    ap.add_argument("--n-ritz", type=int, default=10, help="Ritz pairs of the limited-memory preconditioner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy before the timed region (scale for HBM counters)")
     return ap.parse_args()
@@ -98,10 +100,14 @@ def main():
     P = ie.Problem.from_synthetic(prob)
     s, p = ie.quadrature_elliptic(prob.Q, prob.ell)
     kw = dict(precision=prec, solver=ie.SOLVER_PLAIN if a.solver == "plain" else ie.SOLVER_COMPACT,
-              cov_form={"auto": ie.COV_AUTO, "operator": ie.COV_OPERATOR, "band": ie.COV_BAND}[a.form])
+              cov_form={"auto": ie.COV_AUTO, "operator": ie.COV_OPERATOR, "band": ie.COV_BAND}[a.form],
+              n_ritz=a.n_ritz)
     if a.domain == "lattice":
         kw.update(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=P.lattice())
     opts = ie.default_opts(**kw)
+    # block shapes measured on this problem (outside the timed region)
+    tuned = ie.autotune(P, prob.Q, opts) if not a.no_autotune else []
+    log("autotune", tuned)
     run = ie.PerturbationRunner(P, s, p, opts)
     systems = prob.Q * prob.N
     if a.copy_calibration:
@@ -172,7 +178,8 @@ def main():
            "data": "synthetic",
            "config": {"workload": prob.name, "n": prob.n, "N": prob.N, "m": prob.m, "Q": prob.Q,
                       "systems_per_step": systems, "rtol": 1e-8, "precision": a.precision,
-                      "apply_domain": a.domain, "solver": a.solver, "cov_form": a.form, "n_ritz": 10},
+                      "apply_domain": a.domain, "solver": a.solver, "cov_form": a.form, "n_ritz": a.n_ritz,
+                      "autotuned": [list(t) for t in tuned]},
            "iterations": {"total": int(st.iters.sum()), "max": int(st.iters.max()),
                           "fp64_sweeps": st.counter(ie.CNT_SWEEPS)},
            "roofline": roof}

@@ -335,6 +335,27 @@ int infoesrf_warmstart_pairs(const infoesrf_problem* prob, int32_t Q, const doub
                              void* stream);
 
 /*
+ * Autotuner of the covariance apply's block shape (process-wide).  For the
+ * apply the solve of (prob, Q, opts) would run -- its form, domain and inner
+ * precision, plus the FP64 apply of the residual sweeps -- times every block
+ * shape (band form: 8/16/32/64 systems per block; operator form: tiles 16, 32,
+ * 64, 128) with HIP events at three batch sizes (the Q N systems, a quarter
+ * and a sixteenth of them), and records the fastest per batch-size bucket
+ * (>= 256, 64..255, < 64 systems) for grids of this shape.  Later applies on
+ * such grids use the recorded choice unless opts->tile_rows forces one.  The
+ * band form's results do not depend on the choice (each output keeps its
+ * summation order); the operator form's do by rounding only.  Synchronizes
+ * the stream.  Workspace: infoesrf_workspace_bytes(prob, Q, opts).
+ *   report  host int32[24] or NULL: per measured (precision, batch) the
+ *           precision, the batch size, the chosen shape and the microseconds
+ *           per launch.
+ * infoesrf_autotune_reset forgets every recorded choice.
+ */
+int infoesrf_autotune(const infoesrf_problem* prob, int32_t Q, const infoesrf_opts* opts, void* ws, size_t ws_bytes,
+                      void* stream, int32_t* report);
+void infoesrf_autotune_reset(void);
+
+/*
  * Cycled assimilation around the update (the experiment of Sec. 5).
  *
  * infoesrf_l96_forecast: advances the k columns of X (n = nz nx rows each,

@@ -556,13 +556,20 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
 // Tile variant of a covariance launch: the caller's choice, else a rule from the
 // measured sweep on MI355X (large batches: 32 rows x 32 systems per block; small
 // batches: 16 x 32, which doubles the number of blocks).
-int tile_for(int requested, int64_t B) {
+TuneKey op_key(int form, Prec p, const Grid& g, int64_t N) {
+  return TuneKey{form, (int)p, g.nz, g.nx, g.bz, g.bx, (int)N};
+}
+int tile_for(int requested, int64_t B, const TuneKey& k) {
   if (requested) return requested;
+  const int t = tuned_choice(k, B);  // a measured choice (infoesrf_autotune), if any
+  if (t == 16 || t == 32 || t == 64 || t == 128) return t;
   return B >= 128 ? 32 : 16;
 }
 // BF16 blocks: 16 rows x 128 / 64 / 32 systems by batch size
-int tile_for_bf16(int requested, int64_t B) {
+int tile_for_bf16(int requested, int64_t B, const TuneKey& k) {
   if (requested) return requested;
+  const int t = tuned_choice(k, B);
+  if (t == 16 || t == 32 || t == 64 || t == 128) return t;
   return B >= 384 ? 128 : (B >= 96 ? 64 : 16);
 }
 
@@ -598,7 +605,8 @@ int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* 
     IE_CHECK(!in.dense, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
     const float* Zu = in.obs ? in.Zt32 : in.Z32;
     IE_HIP(cov_bf16_timed(g, Zu, rows, in.N, (const __hip_bfloat16*)pl.bf.V, ldr, pl.bf.cols, Bpad, nact,
-                          (float*)pl.bf.T, ldr, tile_for_bf16(rows_per_wave, Bmax), st, zero_counter));
+                          (float*)pl.bf.T, ldr, tile_for_bf16(rows_per_wave, Bmax, op_key(2, prec, g, in.N)), st,
+                          zero_counter));
   } else if (in.dense) {
     IE_CHECK(prec == Prec::F64, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
     IE_HIP(launch_cov_dense(in.P->loc.dense, in.Z, in.n, in.N, (const double*)pl.bf.V, ldr, Bpad, (double*)pl.bf.T,
@@ -607,7 +615,7 @@ int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* 
     const void* Zu = (prec == Prec::F64) ? (in.obs ? (const void*)in.Zt : (const void*)in.Z)
                                          : (in.obs ? (const void*)in.Zt32 : (const void*)in.Z32);
     IE_HIP(cov_stencil_timed(prec, g, Zu, rows, in.N, pl.bf.V, ldr, pl.bf.cols, Bpad, nact, pl.bf.T, ldr,
-                             tile_for(rows_per_wave, Bmax), st, zero_counter));
+                             tile_for(rows_per_wave, Bmax, op_key(1, prec, g, in.N)), st, zero_counter));
   }
   if (Qout)
     IE_HIP(launch_apply_finish(prec, in.obs ? 1 : 0, Pin, ldp, pl.bf.T, ldr, act, nact, sigma, in.P->h_ptr,
@@ -632,7 +640,7 @@ int apply_state(Plan& pl, const double* U, int64_t ld, const int32_t* act, const
                             (double*)pl.bf.T, ldr, st));
   } else {
     IE_HIP(cov_stencil_timed(Prec::F64, in.gs, in.Z, in.n, in.N, pl.bf.V, ldr, pl.bf.cols, ncols, nullptr, pl.bf.T,
-                             ldr, tile_for(rows_per_wave, ncols), st));
+                             ldr, tile_for(rows_per_wave, ncols, op_key(1, Prec::F64, in.gs, in.N)), st));
   }
   return 0;
 }
@@ -1264,7 +1272,7 @@ int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ld
     if (!low) {
       // column-major V and PV are system-major apply buffers already
       IE_HIP(cov_stencil_timed(Prec::F64, g, Z, n, N, V, ldv, B, B, nullptr, PV, ldpv,
-                               tile_for(op.rows_per_wave, B), st));
+                               tile_for(op.rows_per_wave, B, op_key(1, Prec::F64, g, N)), st));
     } else {
       IE_HIP(launch_convert_f32(L.table, tab32, (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1), st));
       if (op.inner == Prec::BF16) {
@@ -1272,7 +1280,7 @@ int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ld
         hipLaunchKernelGGL((k_convert_cols<double, __hip_bfloat16>), dim3(nb(ldr * B)), dim3(256), 0, st, V, ldv, n,
                            B, V16, ldr, 1);
         IE_HIP(hipGetLastError());
-        IE_HIP(cov_bf16_timed(g, Z32, n, N, V16, ldr, B, B, nullptr, T32, ldr, tile_for_bf16(op.rows_per_wave, B),
+        IE_HIP(cov_bf16_timed(g, Z32, n, N, V16, ldr, B, B, nullptr, T32, ldr, tile_for_bf16(op.rows_per_wave, B, op_key(2, Prec::BF16, g, N)),
                               st));
       } else {
         float* V32 = static_cast<float*>(Vlow);
@@ -1280,7 +1288,7 @@ int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ld
                            ldr, 1);
         IE_HIP(hipGetLastError());
         IE_HIP(cov_stencil_timed(Prec::F32, g, Z32, n, N, V32, ldr, B, B, nullptr, T32, ldr,
-                                 tile_for(op.rows_per_wave, B), st));
+                                 tile_for(op.rows_per_wave, B, op_key(1, Prec::F64, g, N)), st));
       }
       hipLaunchKernelGGL((k_convert_cols<float, double>), dim3(nb(ldpv * B)), dim3(256), 0, st, T32, ldr, n, B, PV,
                          ldpv, 0);
@@ -1338,6 +1346,112 @@ int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const 
                            Xa_pert, st));
   return finish_status(pl, op, stats, 2 * pl.pr.k + N, st);
 }
+
+int infoesrf_autotune(const infoesrf_problem* prob, int32_t Q, const infoesrf_opts* opts, void* ws,
+                      size_t ws_bytes, void* stream, int32_t* report) {
+  clear_error();
+  IE_TRY(check_problem(prob));
+  Options op;
+  IE_TRY(resolve_options(prob, opts, op));
+  IE_CHECK(Q >= 0 && Q <= kMaxQ, INFOESRF_ERR_INVALID_ARG, "Q must be in [0, 64]");
+  IE_CHECK(ws != nullptr, INFOESRF_ERR_WORKSPACE, "workspace is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t S = Q > 0 ? (int64_t)Q * prob->N : 1;
+  Plan pl;
+  IE_TRY(plan_for(pl, prob, op, S, Q > 0 ? prob->N : 1, ws, ws_bytes));
+  op.host_sync = 1;  // the tuner reads timings on the host
+  IE_TRY(check_nnz(prob, op, st));
+  IE_TRY(stage_setup(pl, op, st));
+  Inst& in = pl.in;
+  IE_CHECK(!in.dense, INFOESRF_ERR_INVALID_ARG, "dense localization has nothing to tune");
+  const Grid& g = in.obs ? in.go : in.gs;
+  const int64_t rows = in.obs ? in.m : in.n;
+  const int64_t ldr = ld64(rows);
+  const int64_t cols = pl.bf.cols;
+  IE_HIP(launch_fill_f64((double*)pl.bf.V, 1.0, ldr * cols, st));
+  // the inner precision's apply, and the FP64 apply of the residual sweeps when they differ
+  std::vector<Prec> precs{op.inner};
+  if (op.inner != Prec::F64) precs.push_back(Prec::F64);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  IE_HIP(hipEventCreate(&e0));
+  IE_HIP(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  int rep = 0;
+  for (Prec prec : precs) {
+    const bool band = in.band;
+    const int form = band ? 0 : (prec == Prec::BF16 ? 2 : 1);
+    const TuneKey key = band ? TuneKey{0, prec == Prec::F64 ? 0 : 1, g.nz, g.nx, g.bz, g.bx, 0}
+                             : op_key(form, prec, g, in.N);
+    const size_t es = prec == Prec::F64 ? 8 : 4;
+    std::vector<int> cands;
+    if (band) {
+      for (int c : {8, 16, 32, 64})
+        if ((size_t)c * (64 + 2 * g.bx) * es <= 150 * 1024) cands.push_back(c);
+    } else {
+      cands = {16, 32, 64, 128};
+    }
+    const void* bandp = in.obs ? (prec == Prec::F64 ? in.bandO : in.bandO32) : (prec == Prec::F64 ? in.bandS : in.bandS32);
+    const void* Zu = (prec == Prec::F64) ? (in.obs ? (const void*)in.Zt : (const void*)in.Z)
+                                         : (in.obs ? (const void*)in.Zt32 : (const void*)in.Z32);
+    auto launch = [&](int64_t B) -> hipError_t {
+      if (band) return launch_band_apply(prec, g, bandp, ldr, pl.bf.V, ldr, cols, B, nullptr, pl.bf.T, ldr, st);
+      if (prec == Prec::BF16)
+        return launch_cov_bf16(g, (const float*)Zu, rows, in.N, (const __hip_bfloat16*)pl.bf.V, ldr, cols, B, nullptr,
+                               (float*)pl.bf.T, ldr, g_force_choice, st);
+      return launch_cov_stencil(prec, g, Zu, rows, in.N, pl.bf.V, ldr, cols, B, nullptr, pl.bf.T, ldr, g_force_choice,
+                                st);
+    };
+    bool seen[kTuneBuckets] = {false, false, false};
+    for (int64_t div : {1, 4, 16}) {
+      const int64_t B = std::min<int64_t>(cols, std::max<int64_t>(16, round_up(S / div, 16)));
+      const int bucket = tune_bucket(B);
+      if (seen[bucket]) continue;
+      seen[bucket] = true;
+      int best = 0;
+      float best_ms = 0.f;
+      for (int c : cands) {
+        g_force_choice = c;
+        hipError_t e = launch(B);  // warm-up (also sets kernel attributes)
+        for (int r = 0; r < 5 && e == hipSuccess; ++r) {
+          if (r == 1) e = hipEventRecord(e0, st);
+          if (e == hipSuccess) e = launch(B);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        g_force_choice = 0;
+        if (e == hipErrorInvalidValue) {
+          (void)hipGetLastError();  // a candidate that does not fit: skip it
+          continue;
+        }
+        IE_HIP(e);
+        float ms = 0.f;
+        IE_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ms /= 4.f;
+        if (best == 0 || ms < best_ms) {
+          best = c;
+          best_ms = ms;
+        }
+      }
+      if (best) set_tuned(key, bucket, best);
+      if (report && rep < 2 * kTuneBuckets) {
+        report[4 * rep + 0] = (int32_t)prec;
+        report[4 * rep + 1] = (int32_t)B;
+        report[4 * rep + 2] = best;
+        report[4 * rep + 3] = (int32_t)(best_ms * 1000.f);  // microseconds per launch
+        ++rep;
+      }
+    }
+  }
+  return INFOESRF_OK;
+}
+
+void infoesrf_autotune_reset(void) { tune_reset(); }
 
 int infoesrf_warmstart_pairs(const infoesrf_problem* prob, int32_t Q, const double* s_nodes,
                              const double* p_weights, const double* y, float* X, float* T,

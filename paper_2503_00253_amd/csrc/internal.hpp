@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <array>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -133,6 +134,19 @@ hipError_t launch_cov_bf16(const Grid& g, const float* Z, int64_t ldz, int64_t N
 hipError_t cov_bf16_timed(const Grid& g, const float* Z, int64_t ldz, int64_t N, const __hip_bfloat16* V,
                           int64_t ldk, int64_t vcols, int64_t B, const int32_t* Bdev, float* T, int64_t ldt, int tile,
                           hipStream_t st, int32_t* zero_counter = nullptr);
+// Measured block shapes (tune.hip).  form: 0 band apply (choice = systems per block 8/16/32/64),
+// 1 operator form FP64/FP32 (choice = tile 16/32/64/128), 2 operator form BF16 (tile).  prec:
+// element type of the apply.  A choice of 0 means "not measured: use the built-in rule".
+constexpr int kTuneBuckets = 3;  // batch sizes >= 256, 64..255, < 64
+struct TuneKey {
+  int form, prec, nz, nx, bz, bx, N;
+};
+extern thread_local int g_force_choice;  // nonzero while the tuner times a candidate
+int tune_bucket(int64_t B);
+int tuned_choice(const TuneKey& k, int64_t B);
+void set_tuned(const TuneKey& k, int bucket, int choice);
+void tune_reset();
+
 // Explicit band of P = L o (Z Z^T) on grid g (band.hip): band[j * ldb + r] for the
 // (2bz+1)(2bx+1) stencil offsets j, FP64 or FP32 entries computed in FP64 from Z (FP64,
 // column-major, ldz).

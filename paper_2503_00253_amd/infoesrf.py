@@ -135,6 +135,10 @@ def library():
     lib.infoesrf_rtps_assemble.argtypes = [VP, C.c_int64, VP, VP, C.c_int64, C.c_int64, C.c_int64, C.c_double, VP,
                                            C.c_int64, VP]
     lib.infoesrf_rtps_assemble.restype = C.c_int
+    lib.infoesrf_autotune.argtypes = [P(ProblemC), C.c_int32, P(Opts), VP, C.c_size_t, VP, P(C.c_int32)]
+    lib.infoesrf_autotune.restype = C.c_int
+    lib.infoesrf_autotune_reset.argtypes = []
+    lib.infoesrf_autotune_reset.restype = None
     lib.infoesrf_quadrature_elliptic.argtypes = [C.c_int32, C.c_double, P(C.c_double), P(C.c_double)]
     lib.infoesrf_quadrature_elliptic.restype = C.c_int
     lib.infoesrf_quadrature_gauss_legendre.argtypes = [C.c_int32, P(C.c_double), P(C.c_double)]
@@ -568,6 +572,23 @@ def rtps_assemble(Xf, mean_a, Xa, alpha, out):
     _check(library().infoesrf_rtps_assemble(Xf.data_ptr(), n, mean_a.data_ptr(), Xa.data_ptr(), n, n, N,
                                             float(alpha), out.data_ptr(), n, _stream()), allow_warn=False)
     return out
+
+
+def autotune(problem: Problem, Q: int, opts: Opts | None = None):
+    """Measure and record the fastest apply block shapes for this problem's grid; returns
+    [(precision, batch, choice, microseconds per launch), ...]."""
+    lib = library()
+    opts = opts or default_opts()
+    dev = problem.X.device
+    ws = _workspace(workspace_bytes(problem, Q, opts), dev)
+    rep = (C.c_int32 * 24)(*([-1] * 24))
+    _check(lib.infoesrf_autotune(C.byref(problem.c), Q, C.byref(opts), ws.data_ptr(), ws.numel(), _stream(), rep),
+           allow_warn=False)
+    return [tuple(rep[4 * i:4 * i + 4]) for i in range(6) if rep[4 * i] >= 0]
+
+
+def autotune_reset():
+    library().infoesrf_autotune_reset()
 
 
 class PerturbationRunner:

@@ -346,3 +346,33 @@ def test_band_form_options():
     a, _ = ie.perturbation_update(P, s, p, ie.default_opts(cov_form=ie.COV_OPERATOR))
     b, _ = ie.perturbation_update(P, s, p, ie.default_opts(cov_form=ie.COV_BAND))
     assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-9
+
+
+def test_autotune_records_choices_and_keeps_results():
+    """The band form's output does not depend on the tuned block shape; the operator form's
+    changes by rounding only; every recorded shape is a valid one."""
+    prob = syn.config2()
+    say("autotune n4096")
+    P = ie.Problem.from_synthetic(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    lat = P.lattice()
+    ie.autotune_reset()
+    for kw in (dict(), dict(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=lat),
+               dict(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=lat, precision=ie.MIXED_FP32)):
+        o = ie.default_opts(**kw)
+        before, _ = ie.perturbation_update(P, s, p, o)
+        rep = ie.autotune(P, prob.Q, o)
+        say("autotune report", kw.get("precision", 0), rep)
+        assert rep and all(r[2] in (8, 16, 32, 64) for r in rep)
+        after, st = ie.perturbation_update(P, s, p, o)
+        assert st.code == ie.OK
+        assert torch.equal(before, after)
+    o = ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=lat, precision=ie.MIXED_BF16)
+    rep = ie.autotune(P, prob.Q, o)
+    say("autotune report bf16", rep)
+    assert rep and all(r[2] in (16, 32, 64, 128) for r in rep)
+    dp = dense_of(prob)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    got, st = ie.perturbation_update(P, s, p, o)
+    assert st.code == ie.OK and rel(got.cpu().numpy(), want) < 1e-6
+    ie.autotune_reset()
