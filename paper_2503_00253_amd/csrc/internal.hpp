@@ -189,6 +189,8 @@ struct LMP {
   int p;               // number of Ritz pairs (0 = no preconditioner)
   const double* Phi;   // m x p column-major (Phi[j*ld + r]): a wavefront reads 64 consecutive rows
   const double* SPhi;  // m x p column-major, same ld
+  const float* Phi32;  // the same vectors in FP32 (Phi and SPhi hold these values exactly)
+  const float* SPhi32;
   int64_t ld;          // leading dimension of Phi and SPhi
   const double* theta; // p Ritz values of S
   const double* G;     // 3 p x p Gram matrices: Phi^T Phi, Phi^T S Phi, (S Phi)^T S Phi (row-major)
@@ -215,6 +217,9 @@ struct PCGState {
 // active are appended to act_out (*nact_out must be zero on entry) and their new p is written to
 // V (apply precision, observation domain; nullable).  plain != 0 keeps retired systems in the
 // list (masked solver).  m <= 4096.
+// Rounds Phi and SPhi (m x p, column-major, ld) to FP32 in place and writes the FP32 copies.
+hipError_t launch_round_ritz(double* Phi, double* SPhi, int64_t m, int p, int64_t ld, float* Phi32, float* SPhi32,
+                             hipStream_t st);
 hipError_t launch_pcg_fused(Prec prec, const PCGState& s, const LMP& lmp, int mode, int obs_domain, int plain,
                             const void* T, int64_t ldt, const int32_t* act, const int32_t* nact, int32_t* act_out,
                             int32_t* nact_out, int64_t Bmax, void* V, int64_t ldv, const int32_t* h_ptr,

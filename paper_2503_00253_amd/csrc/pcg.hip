@@ -265,7 +265,12 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       }
     }
   }
-  // (3) dots of r: r^T r, Phi^T r, (S Phi)^T r
+  // (3) dots of r: r^T r, Phi^T r, (S Phi)^T r.  The Ritz vectors are read in FP32 (the values
+  // the preconditioner's Gram matrices were formed from) and, when they fit, kept in registers
+  // for the preconditioned residual below, so each system reads them once per iteration.
+  constexpr bool kCache = (RPT * P <= 20);
+  constexpr int kC = (kCache && P > 0) ? RPT * P : 1;
+  float ph[kC], sph[kC];
   double acc[W];
   const double* d = sdot;
 #pragma unroll
@@ -277,8 +282,13 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       acc[0] += rv[j] * rv[j];
 #pragma unroll
       for (int l = 0; l < P; ++l) {
-        acc[1 + l] += lmp.Phi[l * lmp.ld + r] * rv[j];
-        acc[1 + P + l] += lmp.SPhi[l * lmp.ld + r] * rv[j];
+        const float a = lmp.Phi32[l * lmp.ld + r], b = lmp.SPhi32[l * lmp.ld + r];
+        if (kCache) {
+          ph[j * P + l] = a;
+          sph[j * P + l] = b;
+        }
+        acc[1 + l] += (double)a * rv[j];
+        acc[1 + P + l] += (double)b * rv[j];
       }
     }
   }
@@ -348,13 +358,28 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
     if (r < m) {
       double z = rv[j];
 #pragma unroll
-      for (int l = 0; l < P; ++l)
-        z -= lmp.SPhi[l * lmp.ld + r] * scoef[l] + lmp.Phi[l * lmp.ld + r] * scoef[P + l];
+      for (int l = 0; l < P; ++l) {
+        const double a = kCache ? (double)ph[j * P + l] : (double)lmp.Phi32[l * lmp.ld + r];
+        const double b = kCache ? (double)sph[j * P + l] : (double)lmp.SPhi32[l * lmp.ld + r];
+        z -= b * scoef[l] + a * scoef[P + l];
+      }
       pv[j] = mode ? z + beta * pv[j] : z;
       st.p[base + r] = pv[j];
     }
   }
   write_v(pv);
+}
+
+__global__ void k_round_ritz(double* __restrict__ Phi, double* __restrict__ SPhi, int64_t m, int p, int64_t ld,
+                             float* __restrict__ Phi32, float* __restrict__ SPhi32) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= m * p) return;
+  const int64_t j = t / m, r = t % m, i = j * ld + r;
+  const float a = (float)Phi[i], b = (float)SPhi[i];
+  Phi32[i] = a;
+  SPhi32[i] = b;
+  Phi[i] = (double)a;
+  SPhi[i] = (double)b;
 }
 
 // --------------------------------------------------------------- list and vector kernels
@@ -527,6 +552,15 @@ hipError_t fused_rows(Prec prec, const PCGState& s, const LMP& lmp, int mode, in
 }
 
 }  // namespace
+
+hipError_t launch_round_ritz(double* Phi, double* SPhi, int64_t m, int p, int64_t ld, float* Phi32, float* SPhi32,
+                             hipStream_t st) {
+  const int64_t n = m * p;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_round_ritz, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Phi, SPhi, m, p, ld, Phi32,
+                     SPhi32);
+  return hipGetLastError();
+}
 
 hipError_t launch_gather_active(Prec prec, const double* P, int64_t ldp, const int32_t* act, const int32_t* nact,
                                 int64_t rows, int64_t Bmax, void* V, int64_t ldv, hipStream_t st) {
