@@ -123,7 +123,8 @@ typedef struct infoesrf_loc {
  *   X      n x N forecast members (column i = member x^(i)), ld = n.
  *   H      linear observation operator, m rows in CSR: row k has entries
  *          h_w[e] at state index h_idx[e] for e in [h_ptr[k], h_ptr[k+1]).
- *          Column indices within a row must be strictly increasing.
+ *          Column indices within a row must be strictly increasing; at most
+ *          max(64 m, 16 n) entries in total; m <= 4096.
  *   r_var  m diagonal entries of R (all > 0).
  *   loc    localization L.
  * N >= 2 (eq. 2.9 divides by N-1), m >= 1, n = loc.nz * loc.nx.
@@ -155,7 +156,8 @@ typedef struct infoesrf_opts {
   double rtol;          /* target of the true FP64 relative residual ||b - C u|| / ||b|| per system (default 1e-8) */
   double inner_rtol;    /* mixed precision: inner PCG tolerance (0 = 1e-2 for BF16, 1e-5 for FP32) */
   int32_t max_iter;     /* cap on PCG iterations per system (inner iterations summed in mixed mode) */
-  int32_t n_ritz;       /* p: Ritz pairs in the limited-memory preconditioner (Appendix E); 0 disables it */
+  int32_t n_ritz;       /* p: Ritz pairs in the limited-memory preconditioner (Appendix E), one of
+                           0 (none), 4, 8, 10, 12, 16, 20; n_ritz + oversample <= min(48, m) */
   int32_t oversample;   /* extra sketch columns for the randomized eigendecomposition */
   int32_t precision;    /* INFOESRF_FP64 | INFOESRF_MIXED_FP32 | INFOESRF_MIXED_BF16 */
   int32_t solver;       /* INFOESRF_SOLVER_* */

@@ -328,8 +328,9 @@ struct Plan {
 };
 
 inline int64_t ld64(int64_t rows) { return round_up(rows, 64); }
-// Room reserved for the CSC copy of H: 64 entries per row on average.
-inline int64_t nnz_bound(const infoesrf_problem* P) { return P->m * 64; }
+// Room reserved for the CSC copy of H: 64 entries per row on average, or 16 per state variable
+// (wide observation channels), whichever is larger.
+inline int64_t nnz_bound(const infoesrf_problem* P) { return std::max<int64_t>(P->m * 64, P->n * 16); }
 
 int check_problem(const infoesrf_problem* P) {
   IE_CHECK(P != nullptr, INFOESRF_ERR_INVALID_ARG, "problem is NULL");
@@ -366,8 +367,8 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   IE_CHECK(o->max_iter >= 1, INFOESRF_ERR_INVALID_ARG, "max_iter must be >= 1");
   IE_CHECK(o->n_ritz >= 0 && o->oversample >= 0, INFOESRF_ERR_INVALID_ARG, "n_ritz, oversample must be >= 0");
   const int p = o->n_ritz;
-  IE_CHECK(p == 0 || p == 4 || p == 8 || p == 10 || p == 12 || p == 16, INFOESRF_ERR_INVALID_ARG,
-           "n_ritz must be one of 0, 4, 8, 10, 12, 16");
+  IE_CHECK(p == 0 || p == 4 || p == 8 || p == 10 || p == 12 || p == 16 || p == 20, INFOESRF_ERR_INVALID_ARG,
+           "n_ritz must be one of 0, 4, 8, 10, 12, 16, 20");
   IE_CHECK(p + o->oversample <= kMaxSketch, INFOESRF_ERR_INVALID_ARG, "n_ritz + oversample must be <= 48");
   IE_CHECK(p == 0 || p + o->oversample <= P->m, INFOESRF_ERR_INVALID_ARG, "n_ritz + oversample must be <= m");
   IE_CHECK(o->precision >= INFOESRF_FP64 && o->precision <= INFOESRF_MIXED_BF16, INFOESRF_ERR_INVALID_ARG,
@@ -1024,7 +1025,7 @@ int check_nnz(const infoesrf_problem* P, const Options& op, hipStream_t st) {
   IE_HIP(hipMemcpyAsync(&nnz, P->h_ptr + P->m, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   IE_HIP(hipStreamSynchronize(st));
   IE_CHECK(nnz >= 0 && nnz <= nnz_bound(P), INFOESRF_ERR_INVALID_ARG,
-           "H has more than 64 entries per row on average (h_ptr[m] too large)");
+           "H has more than max(64 m, 16 n) entries (h_ptr[m] too large)");
   return 0;
 }
 

@@ -153,8 +153,8 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
                                                    const double* __restrict__ r_var, int64_t n_state) {
   constexpr int W = 2 * P + 1;
   __shared__ double sred[W][4];
-  __shared__ double sG[3 * 16 * 16 + 16];
-  __shared__ double scoef[2 * 16 + 2];
+  __shared__ double sG[3 * P * P + P + 1];
+  __shared__ double scoef[2 * P + 2];
   __shared__ double sdot[W];  // the reduced dots (broadcast reads; lanes index them by thread id)
   __shared__ int s_slot;
   const int c = blockIdx.x;
@@ -616,6 +616,7 @@ hipError_t launch_apply_finish(Prec prec, int obs_domain, const double* P, int64
     case 10: return CALL(10);             \
     case 12: return CALL(12);             \
     case 16: return CALL(16);             \
+    case 20: return CALL(20);             \
     default: return hipErrorInvalidValue; \
   }
 

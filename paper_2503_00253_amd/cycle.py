@@ -37,7 +37,8 @@ class CycleRunner:
         self.P = ie.Problem.from_synthetic(prob)
         self.P.X = self.state[:self.N]          # the update reads the live ensemble
         self.P.c.X = self.P.X.data_ptr()
-        self.forcing = torch.full((self.nz,), float(meta["forcing"]), dtype=torch.float64, device=dev)
+        forcing = np.broadcast_to(np.asarray(meta["forcing"], dtype=np.float64), (self.nz,))
+        self.forcing = torch.from_numpy(np.array(forcing)).to(dev)   # per layer
         Q = Q or prob.Q
         ell = ell or prob.ell
         s, p = ie.quadrature_elliptic(Q, ell)

@@ -14,6 +14,9 @@ Lorenz-96 system of Sec. 5):
   N(0, C) with a Gaussian-shaped circulant C, Gaspari--Cohn localization,
   point observations of every ``obs_stride``-th grid point.
 * ``lorenz_problem``: multi-layer Lorenz-96 ensemble (Sec. 5, eq. 5.1).
+* ``experiment1_problem`` / ``experiment2_problem``: the paper's own settings
+  of Sec. 4 (weighted-channel observations of a Gaussian prior) and Sec. 5
+  (vertical channels of the 32 x 40 coupled Lorenz-96 atmosphere).
 """
 from .gaussian import (  # noqa: F401
     Problem,
@@ -29,3 +32,4 @@ from .gaussian import (  # noqa: F401
     sketch_matrix,
 )
 from .lorenz import lorenz_problem, l96_tendency, l96_rk4_step  # noqa: F401
+from .paper import chordal, experiment1_problem, experiment2_forcing, experiment2_problem  # noqa: F401

@@ -152,3 +152,12 @@ def test_graph_captured_cycle_matches_eager():
         graph.replay()
         torch.cuda.synchronize()
     assert torch.equal(g_run.state, want)
+
+
+def test_paper_sec5_cycles_match_oracle():
+    """Section 5's 32 x 40 atmosphere (forcing 8 -> 4 over the layers, coupling 1, 40 members,
+    8 columns x 5 channels): two cycles, each update checked in full."""
+    prob = syn.experiment2_problem()
+    say("cycles paper sec5")
+    assert np.ndim(prob.meta["forcing"]) == 1
+    cycle_checks(prob, cycles=2, Q=8)
