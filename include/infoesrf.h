@@ -65,6 +65,23 @@ extern "C" {
 #define INFOESRF_COV_OPERATOR 1
 #define INFOESRF_COV_BAND 2
 
+/* ---- form of the normalized observation covariance S ---------------------
+ * S = R^{-1/2} H P H^T R^{-1/2} (the matrix of Theorem 3; every shifted system
+ * of Appendix E is (1 + s_q) I + S).
+ * OPERATOR: every PCG apply goes through P (in the form above), in the
+ *           state domain or on the observed lattice.
+ * DENSE:    S is assembled once per call as a dense m x m FP64 matrix (m
+ *           applies of P, symmetrized; plus an FP32 copy for MIXED_FP32) and
+ *           every PCG apply is an m x m product, 2 m^2 flops per vector.
+ *           m <= 16384; not with MIXED_BF16.  Same result up to rounding.
+ * AUTO:     DENSE in FP64 or MIXED_FP32 when m <= 4096, an m x m product costs
+ *           at most half of an apply of P in the working domain, and
+ *           m <= 8 (systems + sketch columns + 16) (forming S takes m applies
+ *           of P); else OPERATOR. */
+#define INFOESRF_S_AUTO 0
+#define INFOESRF_S_OPERATOR 1
+#define INFOESRF_S_DENSE 2
+
 /* ---- localization kinds ------------------------------------------------- */
 #define INFOESRF_LOC_STENCIL 1 /* stationary stencil on an nz x nx grid */
 #define INFOESRF_LOC_DENSE 0   /* explicit n x n matrix (small n, tests) */
@@ -171,7 +188,12 @@ typedef struct infoesrf_opts {
   int32_t tile_rows;    /* operator-form tile variant: 0 = default; 16, 32, 64, 128 select blocks of
                            16x32, 32x32, 64x16, 64x32 (rows x systems) */
   int32_t cov_form;     /* INFOESRF_COV_AUTO | INFOESRF_COV_OPERATOR | INFOESRF_COV_BAND */
-  int32_t reserved[6];
+  int32_t fixed_iters;  /* > 0: every system runs exactly this many PCG iterations (FP64 only; the
+                           experiments of Sec. 4 and Sec. 5 run 2 and 10) and stops earlier only on
+                           an exactly zero residual; reaching the count is not a warning, and
+                           stats->converged still reports relres <= rtol.  0: iterate to rtol. */
+  int32_t s_form;       /* INFOESRF_S_AUTO | INFOESRF_S_OPERATOR | INFOESRF_S_DENSE */
+  int32_t reserved[4];
 } infoesrf_opts;
 
 /* Per-system results (device arrays, each may be NULL).  Systems of the

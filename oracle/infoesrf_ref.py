@@ -438,3 +438,21 @@ def info_esrf_pcg(prob, s, p, rtol=1e-8, n_ritz=10, Omega=None, max_iter=1000,
             Ubar[:, c] += p[q] * u
     Vs = op.H.T @ (op.dinv[:, None] * Ubar)
     return Z[:, members] - op.cov(Vs), iters
+
+
+def info_esrf_mean_pcg(prob, y, rtol=1e-8, n_ritz=10, Omega=None, max_iter=1000):
+    """Matrix-free mean update (Sec. 3.2, eq. 3.4) with PCG on (I + S) u0 = R^{-1/2} d,
+    d = y - H mu, preconditioned as the perturbation systems are (Appendix E at shift 0),
+    then mu_a = mu + P H^T R^{-1/2} u0.  With rtol = 0 the solve runs exactly max_iter
+    iterations (the fixed counts of Sec. 4 and Sec. 5).  Returns (mu_a, iterations).
+    """
+    op = FBOperator(prob)
+    mu, _ = ensemble_stats(prob.X)
+    d = np.asarray(y, dtype=np.float64) - op.H @ mu
+    pre = None
+    if n_ritz > 0:
+        Phi, SPhi, th = randomized_eig(op, Omega, n_ritz)
+        pre = LimitedMemoryPreconditioner(Phi, SPhi, th, op.diag(), 0.0)
+    u0, k, _ = pcg(lambda v: v + op(v), op.dinv * d, pre, rtol, max_iter)
+    v = op.H.T @ (op.dinv * u0)
+    return mu + op.cov(v[:, None])[:, 0], k

@@ -163,9 +163,12 @@ __global__ void k_net_targets(const double* __restrict__ u, int64_t ld, const do
   T[t] = nb > 0.0 ? (float)(sqrt((double)m) * u[s * ld + r] / nb) : 0.f;
 }
 
+//   With a fixed iteration count, reaching it sets fdone = 3 (finished, not a failure) and the
+//   inner target is 0, so the inner PCG stops only at the count or on an exactly zero residual.
 __global__ void k_sweep_status(const double* rn, const double* bn, double rtol, double inner_rtol, int fp64_inner,
-                               const int32_t* iters, int max_iter, double* relres, int32_t* fdone, int32_t* done,
-                               double* thresh, int32_t* sweeps, int count_sweep, int64_t S, int32_t* flags) {
+                               const int32_t* iters, int max_iter, int fixed, double* relres, int32_t* fdone,
+                               int32_t* done, double* thresh, int32_t* sweeps, int count_sweep, int64_t S,
+                               int32_t* flags) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= S) return;
   if (fdone[s] != 0) {
@@ -188,18 +191,18 @@ __global__ void k_sweep_status(const double* rn, const double* bn, double rtol, 
     return;
   }
   if (iters[s] >= max_iter) {
-    fdone[s] = 2;
+    fdone[s] = fixed ? 3 : 2;
     done[s] = 1;
     return;
   }
   done[s] = 0;
   const double target = 0.5 * rtol * b;
-  thresh[s] = fp64_inner ? target : fmax(inner_rtol * r, target);
+  thresh[s] = fixed ? 0.0 : (fp64_inner ? target : fmax(inner_rtol * r, target));
 }
 
 // Counters of the call (deterministic reduction over systems in one block).
 __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, const int32_t* fdone, int64_t S,
-                                  int64_t extra_fp64_applies, int inner_fp64, const int32_t* flags,
+                                  int64_t extra_fp64_applies, int inner_fp64, int fixed, const int32_t* flags,
                                   const int32_t* fallbacks, int64_t* out) {
   __shared__ int64_t acc[4][256];
   const int t = threadIdx.x;
@@ -235,7 +238,7 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
     if (f & kFlagBadInput) status = INFOESRF_ERR_INVALID_ARG;
     else if (f & kFlagNumeric) status = INFOESRF_ERR_NUMERIC;
     else if (f & kFlagNotSPD) status = INFOESRF_ERR_NOT_SPD;
-    else if (c > 0) status = INFOESRF_WARN_NOT_CONVERGED;
+    else if (c > 0 && !fixed) status = INFOESRF_WARN_NOT_CONVERGED;  // a fixed count is what was asked
     out[INFOESRF_CNT_STATUS] = status;
   }
 }
@@ -246,6 +249,7 @@ inline unsigned nb(int64_t c) { return (unsigned)((c + 255) / 256); }
 
 struct Options {
   double rtol, inner_rtol;
+  int fixed;  // > 0: run exactly this many PCG iterations per system
   int max_iter, p, k;  // Ritz pairs, sketch columns
   Prec inner;
   int solver;
@@ -258,12 +262,20 @@ struct Options {
   int warm;
   const void* net;
   bool band;  // covariance applies through the explicit band of P
+  int sform;  // INFOESRF_S_*: requested form of S
 };
 
 struct Inst {
   const infoesrf_problem* P = nullptr;
   int64_t n = 0, N = 0, m = 0;
   bool dense = false, obs = false;
+  // S assembled as a dense m x m matrix (column-major, ld = lds; FP32 copy for FP32 inner applies)
+  bool sd = false;
+  double* Sd = nullptr;
+  float* Sd32 = nullptr;
+  int64_t lds = 0;
+  // the PCG vectors and their applies live in observation space (lattice domain or dense S)
+  bool odom() const { return obs || sd; }
   Grid gs{};  // state grid
   Grid go{};  // observation lattice grid (obs domain)
   double *mu = nullptr, *Z = nullptr, *Zt = nullptr, *subtab = nullptr;
@@ -365,6 +377,9 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   if (!o) o = &d;
   IE_CHECK(o->rtol > 0.0 && o->rtol < 1.0, INFOESRF_ERR_INVALID_ARG, "rtol must be in (0, 1)");
   IE_CHECK(o->max_iter >= 1, INFOESRF_ERR_INVALID_ARG, "max_iter must be >= 1");
+  IE_CHECK(o->fixed_iters >= 0, INFOESRF_ERR_INVALID_ARG, "fixed_iters must be >= 0");
+  IE_CHECK(o->fixed_iters == 0 || o->precision == INFOESRF_FP64, INFOESRF_ERR_INVALID_ARG,
+           "fixed_iters needs precision FP64 (a mixed solve counts inner and outer iterations)");
   IE_CHECK(o->n_ritz >= 0 && o->oversample >= 0, INFOESRF_ERR_INVALID_ARG, "n_ritz, oversample must be >= 0");
   const int p = o->n_ritz;
   IE_CHECK(p == 0 || p == 4 || p == 8 || p == 10 || p == 12 || p == 16 || p == 20, INFOESRF_ERR_INVALID_ARG,
@@ -386,6 +401,10 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
            INFOESRF_ERR_INVALID_ARG, "tile_rows must be 0, 16, 32, 64 or 128");
   IE_CHECK(o->cov_form >= INFOESRF_COV_AUTO && o->cov_form <= INFOESRF_COV_BAND, INFOESRF_ERR_INVALID_ARG,
            "unknown cov_form");
+  IE_CHECK(o->s_form >= INFOESRF_S_AUTO && o->s_form <= INFOESRF_S_DENSE, INFOESRF_ERR_INVALID_ARG,
+           "unknown s_form");
+  IE_CHECK(o->s_form != INFOESRF_S_DENSE || (o->precision != INFOESRF_MIXED_BF16 && P->m <= kDenseSMax),
+           INFOESRF_ERR_INVALID_ARG, "the dense form of S needs FP64 or MIXED_FP32 and m <= 16384");
   {
     const bool stencil = P->loc.kind == INFOESRF_LOC_STENCIL;
     const bool prec_ok = o->precision != INFOESRF_MIXED_BF16;
@@ -397,7 +416,9 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
               (o->cov_form == INFOESRF_COV_AUTO && stencil && prec_ok && bytes <= 2.0 * (1ull << 30));
   }
   op.rtol = o->rtol;
-  op.max_iter = o->max_iter;
+  op.sform = o->s_form;
+  op.fixed = o->fixed_iters;
+  op.max_iter = op.fixed > 0 ? op.fixed : o->max_iter;
   op.p = p;
   op.k = p > 0 ? p + o->oversample : 0;
   op.inner = (o->precision == INFOESRF_FP64) ? Prec::F64 : (o->precision == INFOESRF_MIXED_FP32 ? Prec::F32 : Prec::BF16);
@@ -428,6 +449,33 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   return 0;
 }
 
+// Whether S is assembled as a dense m x m matrix for a call with S systems (INFOESRF_S_AUTO:
+// when a product with it costs at most half of an apply of P in the working domain, counted as
+// rows x stencil points for the band, times N for the operator form, and the m applies that
+// form it are few next to the applies of the solves).
+bool use_dense_s(const infoesrf_problem* P, const Options& op, int64_t S) {
+  if (op.sform == INFOESRF_S_DENSE) return true;
+  if (op.sform == INFOESRF_S_OPERATOR || op.inner == Prec::BF16) return false;
+  const int64_t m = P->m;
+  if (m > kDenseSAuto) return false;
+  double rows, points;
+  if (P->loc.kind == INFOESRF_LOC_STENCIL) {
+    const infoesrf_loc& L = P->loc;
+    if (op.obs) {
+      rows = (double)m;
+      points = (double)(2 * (L.bz / op.lat.sz) + 1) * (2 * (L.bx / op.lat.sx) + 1);
+    } else {
+      rows = (double)P->n;
+      points = (double)(2 * L.bz + 1) * (2 * L.bx + 1);
+    }
+  } else {
+    rows = (double)P->n;
+    points = (double)P->n;
+  }
+  const double per_vector = rows * points * (op.band ? 1.0 : (double)P->N);
+  return 2.0 * (double)m * (double)m <= per_vector && m <= 8 * (S + op.k + 16);
+}
+
 // Lay out every buffer of one call.  `S` systems, `nfin` final state-space columns.
 void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& op, int64_t S, int64_t nfin) {
   Inst& in = pl.in;
@@ -438,8 +486,10 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   in.dense = (P->loc.kind == INFOESRF_LOC_DENSE);
   in.obs = op.obs;
   in.band = op.band;
-  // the operator form in a low precision needs FP32 copies of Z and the stencil
-  const bool low = (op.inner != Prec::F64) && !op.band;
+  in.sd = use_dense_s(P, op, S);
+  // the operator form in a low precision needs FP32 copies of Z and the stencil (with a dense S
+  // every low-precision apply is a product with the FP32 copy of S)
+  const bool low = (op.inner != Prec::F64) && !op.band && !in.sd;
   in.mu = ar.take<double>(in.n);
   in.Z = ar.take<double>(in.n * in.N);
   in.Z32 = (low && !in.obs) ? ar.take<float>(in.n * in.N) : nullptr;
@@ -466,12 +516,17 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
     const bool f32 = op.inner == Prec::F32;
     const int64_t ps = (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1) * ld64(in.n);
     in.bandS = ar.take<double>(ps);
-    in.bandS32 = (f32 && !in.obs) ? ar.take<float>(ps) : nullptr;
+    in.bandS32 = (f32 && !in.obs && !in.sd) ? ar.take<float>(ps) : nullptr;
     if (in.obs) {
       const int64_t po = (int64_t)(2 * in.go.bz + 1) * (2 * in.go.bx + 1) * ld64(in.m);
       in.bandO = ar.take<double>(po);
-      in.bandO32 = f32 ? ar.take<float>(po) : nullptr;
+      in.bandO32 = (f32 && !in.sd) ? ar.take<float>(po) : nullptr;
     }
+  }
+  if (in.sd) {
+    in.lds = ld64(in.m);
+    in.Sd = ar.take<double>(in.lds * in.m);
+    in.Sd32 = (op.inner == Prec::F32) ? ar.take<float>(in.lds * in.m) : nullptr;
   }
   in.col_cnt = ar.take<int32_t>(in.n);
   in.col_ptr = ar.take<int32_t>(in.n + 1);
@@ -582,21 +637,15 @@ int tile_for_bf16(int requested, int64_t B, const TuneKey& k) {
 // apply buffer already holds the listed columns (written by the fused PCG kernel).  zero_counter
 // (nullable) is set to 0 on the stream before the apply finishes; the stencil kernels do it
 // themselves, which saves a launch per PCG iteration.
-int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* act, const int32_t* nact,
-            int64_t Bmax, const double* sigma, double* Qout, int rows_per_wave, hipStream_t st,
-            bool v_ready = false, int32_t* zero_counter = nullptr) {
+// T = P V for the first Bmax (or *nact) columns of the apply buffer V, in the working domain of
+// the covariance (observed lattice or state grid) and the form chosen for P.
+int apply_raw(Plan& pl, Prec prec, int64_t Bmax, const int32_t* nact, int rows_per_wave, hipStream_t st,
+              int32_t* zero_counter) {
   Inst& in = pl.in;
-  const int64_t Bpad = round_up(Bmax, kSysTile);
   const int64_t rows = in.obs ? in.m : in.n;
   const int64_t ldr = ld64(rows);
-  if (in.obs) {
-    if (!v_ready) IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, ldr, st));
-  } else {
-    IE_HIP(launch_scatter_state(prec, Pin, ldp, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n, in.m,
-                                Bpad, pl.bf.V, ldr, st));
-  }
   const Grid& g = in.obs ? in.go : in.gs;
-  if (Bpad == 0 || in.dense) {
+  if (Bmax == 0 || in.dense) {
     if (zero_counter) IE_HIP(launch_fill_i32(zero_counter, 0, 2, st));
     zero_counter = nullptr;
   }
@@ -604,25 +653,78 @@ int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* 
     IE_CHECK(prec != Prec::BF16, INFOESRF_ERR_INVALID_ARG, "the band form has no BF16 apply");
     const void* band = in.obs ? (prec == Prec::F64 ? in.bandO : in.bandO32)
                               : (prec == Prec::F64 ? in.bandS : in.bandS32);
-    IE_HIP(cov_band_timed(prec, g, band, ldr, pl.bf.V, ldr, pl.bf.cols, Bpad, nact, pl.bf.T, ldr, st, zero_counter));
+    IE_HIP(cov_band_timed(prec, g, band, ldr, pl.bf.V, ldr, pl.bf.cols, Bmax, nact, pl.bf.T, ldr, st, zero_counter));
   } else if (prec == Prec::BF16) {
     IE_CHECK(!in.dense, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
     const float* Zu = in.obs ? in.Zt32 : in.Z32;
-    IE_HIP(cov_bf16_timed(g, Zu, rows, in.N, (const __hip_bfloat16*)pl.bf.V, ldr, pl.bf.cols, Bpad, nact,
+    IE_HIP(cov_bf16_timed(g, Zu, rows, in.N, (const __hip_bfloat16*)pl.bf.V, ldr, pl.bf.cols, Bmax, nact,
                           (float*)pl.bf.T, ldr, tile_for_bf16(rows_per_wave, Bmax, op_key(2, prec, g, in.N)), st,
                           zero_counter));
   } else if (in.dense) {
     IE_CHECK(prec == Prec::F64, INFOESRF_ERR_INVALID_ARG, "dense localization supports FP64 only");
-    IE_HIP(launch_cov_dense(in.P->loc.dense, in.Z, in.n, in.N, (const double*)pl.bf.V, ldr, Bpad, (double*)pl.bf.T,
+    IE_HIP(launch_cov_dense(in.P->loc.dense, in.Z, in.n, in.N, (const double*)pl.bf.V, ldr, Bmax, (double*)pl.bf.T,
                             ldr, st));
   } else {
     const void* Zu = (prec == Prec::F64) ? (in.obs ? (const void*)in.Zt : (const void*)in.Z)
                                          : (in.obs ? (const void*)in.Zt32 : (const void*)in.Z32);
-    IE_HIP(cov_stencil_timed(prec, g, Zu, rows, in.N, pl.bf.V, ldr, pl.bf.cols, Bpad, nact, pl.bf.T, ldr,
+    IE_HIP(cov_stencil_timed(prec, g, Zu, rows, in.N, pl.bf.V, ldr, pl.bf.cols, Bmax, nact, pl.bf.T, ldr,
                              tile_for(rows_per_wave, Bmax, op_key(1, prec, g, in.N)), st, zero_counter));
   }
+  return 0;
+}
+
+// S = R^{-1/2} H P H^T R^{-1/2} as a dense m x m matrix: P applied to H^T R^{-1/2} e_k (state
+// domain) or to e_k on the observed lattice (whose members already carry H and R^{-1/2}), a
+// buffer's worth of columns at a time, then symmetrized.
+int build_dense_s(Plan& pl, const Options& op, hipStream_t st) {
+  Inst& in = pl.in;
+  const infoesrf_problem* P = in.P;
+  const int64_t rows = in.obs ? in.m : in.n;
+  const int64_t ldr = ld64(rows);
+  double* V = static_cast<double*>(pl.bf.V);
+  for (int64_t j0 = 0; j0 < in.m; j0 += pl.bf.cols) {
+    const int64_t bc = std::min<int64_t>(pl.bf.cols, in.m - j0);
+    if (in.obs) {
+      IE_HIP(launch_unit_cols(rows, j0, bc, V, ldr, st));
+    } else {
+      IE_HIP(launch_fill_f64(V, 0.0, ldr * bc, st));
+      IE_HIP(launch_scatter_unit_obs(P->h_ptr, P->h_idx, P->h_w, P->r_var, in.n, j0, bc, V, ldr, st));
+    }
+    IE_TRY(apply_raw(pl, Prec::F64, bc, nullptr, op.rows_per_wave, st, nullptr));
+    IE_HIP(launch_gather_s_cols(in.obs ? 1 : 0, static_cast<const double*>(pl.bf.T), ldr, P->h_ptr, P->h_idx,
+                                P->h_w, P->r_var, in.n, in.m, j0, bc, in.Sd, in.lds, st));
+  }
+  IE_HIP(launch_symmetrize(in.Sd, in.m, in.lds, in.Sd32, st));
+  return 0;
+}
+
+// T = S-part of the apply for the listed columns of Pin (system-major, ldp); when Qout is given,
+// Qout[:, s] = (1 + sigma_s) Pin[:, s] + S Pin[:, s] as well.  v_ready: the observation-domain
+// apply buffer already holds the listed columns (written by the fused PCG kernel).  zero_counter
+// (nullable) is set to 0 on the stream before the apply finishes; the covariance kernels do it
+// themselves, which saves a launch per PCG iteration.
+int apply_S(Plan& pl, Prec prec, const double* Pin, int64_t ldp, const int32_t* act, const int32_t* nact,
+            int64_t Bmax, const double* sigma, double* Qout, int rows_per_wave, hipStream_t st,
+            bool v_ready = false, int32_t* zero_counter = nullptr) {
+  Inst& in = pl.in;
+  const int64_t Bpad = round_up(Bmax, kSysTile);
+  const bool od = in.odom();
+  const int64_t ldr = ld64(od ? in.m : in.n);
+  if (od) {
+    if (!v_ready) IE_HIP(launch_gather_active(prec, Pin, ldp, act, nact, in.m, Bpad, pl.bf.V, ldr, st));
+  } else {
+    IE_HIP(launch_scatter_state(prec, Pin, ldp, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n, in.m,
+                                Bpad, pl.bf.V, ldr, st));
+  }
+  if (in.sd) {
+    const void* Sp = (prec == Prec::F64) ? (const void*)in.Sd : (const void*)in.Sd32;
+    IE_CHECK(Sp != nullptr, INFOESRF_ERR_INVALID_ARG, "the dense form of S has no copy in this precision");
+    IE_HIP(launch_dense_s_apply(prec, Sp, in.lds, in.m, pl.bf.V, ldr, nact, Bpad, pl.bf.T, ldr, zero_counter, st));
+  } else {
+    IE_TRY(apply_raw(pl, prec, Bpad, nact, rows_per_wave, st, zero_counter));
+  }
   if (Qout)
-    IE_HIP(launch_apply_finish(prec, in.obs ? 1 : 0, Pin, ldp, pl.bf.T, ldr, act, nact, sigma, in.P->h_ptr,
+    IE_HIP(launch_apply_finish(prec, od ? 1 : 0, Pin, ldp, pl.bf.T, ldr, act, nact, sigma, in.P->h_ptr,
                                in.P->h_idx, in.P->h_w, in.P->r_var, in.m, in.n, Bpad, Qout, st));
   return 0;
 }
@@ -688,7 +790,7 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
   //    can only reach here when host_sync == 0; the flag then sets the call's status)
   // FP32 copies of Z and of the stencil exist only for the operator form in a low precision
   // (plan_layout allocates them under the same condition)
-  const bool low = (op.inner != Prec::F64) && !in.band;
+  const bool low = (op.inner != Prec::F64) && !in.band && !in.sd;
   IE_HIP(launch_ens_stats(P->X, in.n, in.N, in.mu, in.Z, in.Z32, st));
   IE_HIP(launch_diag_S(P->h_ptr, P->h_idx, P->h_w, P->r_var, in.Z, in.n, in.N, in.m, in.gs,
                        in.dense ? P->loc.dense : nullptr, in.diagS, st));
@@ -716,6 +818,8 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
       if (in.bandO32) IE_HIP(launch_band_build(Prec::F32, in.go, in.Zt, in.m, in.N, in.bandO32, ld64(in.m), st));
     }
   }
+  // 4. dense S (m applies of P)
+  if (in.sd) IE_TRY(build_dense_s(pl, op, st));
   return 0;
 }
 
@@ -898,11 +1002,14 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   IE_HIP(launch_fill_i32(sy.sweeps, 0, sy.Spad, st));
   IE_HIP(launch_fill_i32(sy.fdone, 0, sy.Spad, st));
 
-  const int max_sweeps = op.host_sync ? 40 : (fp64_inner ? 2 : (op.inner == Prec::F32 ? 4 : 10));
+  // a fixed iteration count is one FP64 inner solve: the status pass after it finishes every system
+  const int max_sweeps =
+      op.fixed > 0 ? 1 : (op.host_sync ? 40 : (fp64_inner ? 2 : (op.inner == Prec::F32 ? 4 : 10)));
   const int check_every = 4;
   const bool plain = (op.solver == INFOESRF_SOLVER_PLAIN);
-  void* Vbuf = in.obs ? pl.bf.V : nullptr;
-  const int64_t ldr = ld64(in.obs ? in.m : in.n);
+  const bool od = in.odom();
+  void* Vbuf = od ? pl.bf.V : nullptr;
+  const int64_t ldr = ld64(od ? in.m : in.n);
   int32_t h_nact = (int32_t)S;
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
     // outer residual r = b - C u (FP64).  Zero start: the first residual is b itself.
@@ -916,7 +1023,8 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
     }
     IE_HIP(launch_col_norms(sy.r, m, S, ldm, sy.rn, st));
     hipLaunchKernelGGL(k_sweep_status, dim3(nb(S)), dim3(256), 0, st, sy.rn, sy.bnorm, op.rtol, op.inner_rtol,
-                       fp64_inner ? 1 : 0, sy.iters, op.max_iter, sy.relres, sy.fdone, sy.done, sy.thresh,
+                       fp64_inner ? 1 : 0, sy.iters, op.max_iter, op.fixed > 0 ? 1 : 0, sy.relres, sy.fdone,
+                       sy.done, sy.thresh,
                        sy.sweeps, (sweep > 0 || warm) ? 1 : 0, S, in.flags);
     IE_HIP(hipGetLastError());
     if (plain) IE_HIP(launch_iota(sy.act, sy.nact, S, st));
@@ -933,7 +1041,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
     int32_t *act_c = sy.act, *nact_c = sy.nact, *act_n = sy.act2, *nact_n = sy.nact2;
     int64_t hint = plain ? S : (int64_t)h_nact;  // upper bound of the live count on the device
     IE_HIP(launch_fill_i32(nact_n, 0, 2, st));
-    IE_HIP(pcg_fused_timed(op.inner, ps, lmp, 0, in.obs ? 1 : 0, plain ? 1 : 0, nullptr, ldr, act_c, nact_c, act_n,
+    IE_HIP(pcg_fused_timed(op.inner, ps, lmp, 0, od ? 1 : 0, plain ? 1 : 0, nullptr, ldr, act_c, nact_c, act_n,
                             nact_n, round_up(hint, kSysTile), Vbuf, ldr, in.P->h_ptr, in.P->h_idx, in.P->h_w,
                             in.P->r_var, in.n, st));
     std::swap(act_c, act_n);
@@ -944,8 +1052,8 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
       const int64_t bp = round_up(hint, kSysTile);
       // the apply also clears the list counter that the fused kernel fills
       IE_TRY(apply_S(pl, op.inner, sy.p, ldm, act_c, nact_c, bp, sy.sigma, nullptr, op.rows_per_wave, st,
-                     /*v_ready=*/in.obs, nact_n));
-      IE_HIP(pcg_fused_timed(op.inner, ps, lmp, 1, in.obs ? 1 : 0, plain ? 1 : 0, pl.bf.T, ldr, act_c, nact_c, act_n,
+                     /*v_ready=*/od, nact_n));
+      IE_HIP(pcg_fused_timed(op.inner, ps, lmp, 1, od ? 1 : 0, plain ? 1 : 0, pl.bf.T, ldr, act_c, nact_c, act_n,
                               nact_n, bp, Vbuf, ldr, in.P->h_ptr, in.P->h_idx, in.P->h_w, in.P->r_var, in.n, st));
       std::swap(act_c, act_n);
       std::swap(nact_c, nact_n);
@@ -975,7 +1083,8 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
 int finish_status(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t extra_fp64, hipStream_t st) {
   Sys& sy = pl.sy;
   hipLaunchKernelGGL(k_finish_counters, dim3(1), dim3(256), 0, st, sy.iters, sy.sweeps, sy.fdone, sy.S, extra_fp64,
-                     op.inner == Prec::F64 ? 1 : 0, pl.in.flags, pl.in.fallbacks, pl.in.counters);
+                     op.inner == Prec::F64 ? 1 : 0, op.fixed > 0 ? 1 : 0, pl.in.flags, pl.in.fallbacks,
+                     pl.in.counters);
   IE_HIP(hipGetLastError());
   if (stats) {
     if (stats->iters || stats->relres || stats->converged)
@@ -1379,8 +1488,9 @@ int infoesrf_autotune(const infoesrf_problem* prob, int32_t Q, const infoesrf_op
   const int64_t cols = pl.bf.cols;
   IE_HIP(launch_fill_f64((double*)pl.bf.V, 1.0, ldr * cols, st));
   // the inner precision's apply, and the FP64 apply of the residual sweeps when they differ
-  std::vector<Prec> precs{op.inner};
-  if (op.inner != Prec::F64) precs.push_back(Prec::F64);
+  // (with a dense S, applies of P are FP64 only: they form S and the final state-space update)
+  std::vector<Prec> precs{in.sd ? Prec::F64 : op.inner};
+  if (precs[0] != Prec::F64) precs.push_back(Prec::F64);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   IE_HIP(hipEventCreate(&e0));
   IE_HIP(hipEventCreate(&e1));

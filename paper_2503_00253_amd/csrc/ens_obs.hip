@@ -162,27 +162,65 @@ __device__ inline double stencil_value(const Grid& g, int64_t a, int64_t b) {
   return g.table[(dz + g.bz) * (2 * g.bx + 1) + (dx + g.bx)];
 }
 
-__global__ void k_diag_S(const int32_t* __restrict__ h_ptr, const int32_t* __restrict__ h_idx,
-                         const double* __restrict__ h_w, const double* __restrict__ r_var,
-                         const double* __restrict__ Z, int64_t n, int64_t N, int64_t m, Grid g,
-                         const double* __restrict__ dense_L, double* __restrict__ diagS) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= m) return;
+// diag(S)_r = (1 / r_r) sum_{e,f in row r} h_e h_f L(a_e, a_f) sum_i z_i[a_e] z_i[a_f], the scalar
+// beta of the limited-memory preconditioner (Appendix E).  One block per observation: its
+// threads share the row's (e, f) pairs, and the row's entries of Z are staged in LDS a chunk
+// of members at a time (member-major, so a wave's pairs with consecutive f read consecutive
+// words).  Rows longer than the staging buffer read Z from global memory.  Entry indices
+// outside [0, n) are skipped (the CSC build flags them).
+constexpr int kDiagThreads = 256;
+constexpr int kDiagStage = 4096;  // doubles
+
+__global__ __launch_bounds__(kDiagThreads) void k_diag_S(const int32_t* __restrict__ h_ptr,
+                                                         const int32_t* __restrict__ h_idx,
+                                                         const double* __restrict__ h_w,
+                                                         const double* __restrict__ r_var,
+                                                         const double* __restrict__ Z, int64_t n, int64_t N,
+                                                         Grid g, const double* __restrict__ dense_L,
+                                                         double* __restrict__ diagS) {
+  __shared__ double zs[kDiagStage];
+  __shared__ double part[kDiagThreads / 64];
+  const int64_t r = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int32_t e0 = h_ptr[r];
+  const int64_t cnt = h_ptr[r + 1] - e0;
+  const bool staged = cnt <= kDiagStage;
+  const int64_t nc = staged ? max<int64_t>(1, min<int64_t>(N, kDiagStage / max<int64_t>(cnt, 1))) : N;
   double acc = 0.0;
-  for (int32_t e = h_ptr[r]; e < h_ptr[r + 1]; ++e) {
-    const int64_t a = h_idx[e];
-    if (a < 0 || a >= n) continue;  // invalid indices are flagged by the CSC build
-    for (int32_t f = h_ptr[r]; f < h_ptr[r + 1]; ++f) {
-      const int64_t b = h_idx[f];
-      if (b < 0 || b >= n) continue;
+  for (int64_t i0 = 0; i0 < N; i0 += nc) {
+    const int64_t ni = min<int64_t>(nc, N - i0);
+    if (staged) {
+      __syncthreads();  // the previous chunk's reads are done
+      for (int64_t t = tid; t < cnt * ni; t += kDiagThreads) {
+        const int64_t i = t / cnt, e = t - i * cnt;
+        const int64_t a = h_idx[e0 + e];
+        zs[t] = (a >= 0 && a < n) ? Z[a + (i0 + i) * n] : 0.0;
+      }
+      __syncthreads();
+    }
+    for (int64_t q = tid; q < cnt * cnt; q += kDiagThreads) {
+      const int64_t e = q / cnt, f = q - e * cnt;
+      const int64_t a = h_idx[e0 + e], b = h_idx[e0 + f];
+      if (a < 0 || a >= n || b < 0 || b >= n) continue;
       const double l = dense_L ? dense_L[a + b * n] : stencil_value(g, a, b);
       if (l == 0.0) continue;
       double zz = 0.0;
-      for (int64_t i = 0; i < N; ++i) zz += Z[a + i * n] * Z[b + i * n];
-      acc += h_w[e] * h_w[f] * l * zz;
+      if (staged) {
+        for (int64_t i = 0; i < ni; ++i) zz += zs[i * cnt + e] * zs[i * cnt + f];
+      } else {
+        for (int64_t i = 0; i < N; ++i) zz += Z[a + i * n] * Z[b + i * n];
+      }
+      acc += h_w[e0 + e] * h_w[e0 + f] * l * zz;
     }
   }
-  diagS[r] = acc / r_var[r];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((tid & 63) == 0) part[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < kDiagThreads / 64; ++w) tot += part[w];
+    diagS[r] = tot / r_var[r];
+  }
 }
 
 __global__ void k_lattice_members(const int32_t* __restrict__ h_idx, const double* __restrict__ h_w,
@@ -264,7 +302,8 @@ hipError_t launch_innovation(const int32_t* h_ptr, const int32_t* h_idx, const d
 hipError_t launch_diag_S(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, const double* r_var,
                          const double* Z, int64_t n, int64_t N, int64_t m, const Grid& g, const double* dense_L,
                          double* diagS, hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_S, dim3(blocks_for(m)), dim3(kBlock), 0, st, h_ptr, h_idx, h_w, r_var, Z, n, N, m, g,
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diag_S, dim3((unsigned)m), dim3(kDiagThreads), 0, st, h_ptr, h_idx, h_w, r_var, Z, n, N, g,
                      dense_L, diagS);
   return hipGetLastError();
 }

@@ -43,6 +43,8 @@ void clear_error();
 
 constexpr int kMaxQ = 64;
 constexpr int kMaxRitz = 32;   // p + oversample <= kMaxSketch
+constexpr int64_t kDenseSMax = 16384;  // largest m of the dense form of S
+constexpr int64_t kDenseSAuto = 4096;  // largest m the automatic choice assembles
 constexpr int kMaxSketch = 48;  // sketch columns (small dense kernels keep k x k in LDS)
 constexpr int kSysTile = 16;   // systems per MFMA column block
 
@@ -164,6 +166,19 @@ hipError_t cov_band_timed(Prec prec, const Grid& g, const void* band, int64_t ld
 hipError_t cov_stencil_timed(Prec prec, const Grid& g, const void* Z, int64_t ldz, int64_t N, const void* V,
                              int64_t ldv, int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt,
                              int rows_per_wave, hipStream_t st, int32_t* zero_counter = nullptr);
+// Dense S (observation space, assembled once per call): unit columns, H^T R^{-1/2} e_k columns,
+// gathered columns of S, symmetrization (+ FP32 copy), and the batched product T = S V.
+hipError_t launch_unit_cols(int64_t rows, int64_t j0, int64_t bc, double* V, int64_t ldv, hipStream_t st);
+hipError_t launch_scatter_unit_obs(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w,
+                                   const double* r_var, int64_t n, int64_t j0, int64_t bc, double* V, int64_t ldv,
+                                   hipStream_t st);
+hipError_t launch_gather_s_cols(int obs_domain, const double* T, int64_t ldt, const int32_t* h_ptr,
+                                const int32_t* h_idx, const double* h_w, const double* r_var, int64_t n, int64_t m,
+                                int64_t j0, int64_t bc, double* S, int64_t lds, hipStream_t st);
+hipError_t launch_symmetrize(double* S, int64_t m, int64_t lds, float* S32, hipStream_t st);
+hipError_t launch_dense_s_apply(Prec prec, const void* S, int64_t lds, int64_t m, const void* V, int64_t ldv,
+                                const int32_t* nact, int64_t Bmax, void* T, int64_t ldt, int32_t* zero_counter,
+                                hipStream_t st);
 hipError_t launch_cov_dense(const double* L, const double* Z, int64_t n, int64_t N, const double* V, int64_t ldv,
                             int64_t B, double* T, int64_t ldt, hipStream_t st);
 

@@ -24,6 +24,7 @@ SOLVER_PLAIN, SOLVER_COMPACT, SOLVER_PERSISTENT = 0, 1, 2
 DOMAIN_STATE, DOMAIN_OBS_LATTICE = 0, 1
 START_ZERO, START_LEARNED = 0, 1
 COV_AUTO, COV_OPERATOR, COV_BAND = 0, 1, 2
+S_AUTO, S_OPERATOR, S_DENSE = 0, 1, 2
 PROF_OP_FP64, PROF_OP_FP32, PROF_OP_BF16, PROF_BAND_FP64, PROF_BAND_FP32, PROF_PCG = 0, 1, 2, 3, 4, 5
 PROF_SLOTS = 6
 CNT_APPLIES, CNT_APPLIES_FP64, CNT_ITERATIONS, CNT_SWEEPS = 0, 1, 2, 3
@@ -55,7 +56,8 @@ class Opts(C.Structure):
                 ("precision", C.c_int32), ("solver", C.c_int32), ("warm_start", C.c_int32),
                 ("host_sync", C.c_int32), ("apply_domain", C.c_int32), ("lattice", Lattice),
                 ("seed", C.c_uint64), ("sketch", C.c_void_p), ("net", C.c_void_p),
-                ("tile_rows", C.c_int32), ("cov_form", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("tile_rows", C.c_int32), ("cov_form", C.c_int32), ("fixed_iters", C.c_int32),
+                ("s_form", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class StatsC(C.Structure):

@@ -32,4 +32,11 @@ from .gaussian import (  # noqa: F401
     sketch_matrix,
 )
 from .lorenz import lorenz_problem, l96_tendency, l96_rk4_step  # noqa: F401
-from .paper import chordal, experiment1_problem, experiment2_forcing, experiment2_problem  # noqa: F401
+from .paper import (  # noqa: F401
+    chordal,
+    experiment1_prior_row,
+    experiment1_problem,
+    experiment2_forcing,
+    experiment2_noise,
+    experiment2_problem,
+)

@@ -27,13 +27,25 @@ def chordal(d, n):
     return (n / np.pi) * np.sin(np.pi * np.abs(d) / n)
 
 
+def experiment1_prior_row(n: int = 2000, nu: float = 10.0, eta: float = 1e-4):
+    """First row of the circulant prior covariance of Sec. 4 (eq. of Sec. 4.1)."""
+    row = np.exp(-chordal(np.arange(n), n) ** 2 / (2 * nu * nu))
+    row[0] += eta
+    return row
+
+
+def experiment2_noise(cycles: int, m: int = 40, noise_var: float = 0.25, trial: int = 0):
+    """Observation noise of the cycled experiment, one row per cycle."""
+    rng = np.random.Generator(np.random.PCG64(config_seed(13, trial)))
+    return rng.standard_normal((cycles, m)) * np.sqrt(noise_var)
+
+
 def experiment1_problem(trial: int = 0, n: int = 2000, N: int = 20, d_obs: int = 100, nu: float = 10.0,
                         eta: float = 1e-4, b: float = 10.0, L: float = 12.0, Q: int = 8, ell: float = 1000.0):
     seed = config_seed(11, trial)
     rng = np.random.Generator(np.random.PCG64(seed))
     idx = np.arange(n)
-    row = np.exp(-chordal(idx, n) ** 2 / (2 * nu * nu))
-    row[0] += eta
+    row = experiment1_prior_row(n, nu, eta)
     # circulant covariance: eigenvalues are the real DFT of its first row
     lam = np.maximum(np.fft.rfft(row).real, 0.0)
     sq = np.sqrt(lam)
@@ -83,8 +95,8 @@ def experiment2_problem(trial: int = 0, nz: int = 32, nx: int = 40, N: int = 40,
     rng = np.random.Generator(np.random.PCG64(seed))
     n = nz * nx
     F = experiment2_forcing(nz)
-    # 41 independent Gaussian random fields (unit-variance, smoothed along the sites), integrated
-    # to t = 10; the first N are the ensemble, the last the truth
+    # 41 independent Gaussian random fields (white, unit variance, around the forcing of each
+    # layer), integrated to t = 10; the first N are the ensemble, the last the truth
     fields = rng.standard_normal((n, N + 1))
     state = F.repeat(nx)[:, None] + fields
     forcing = F[:, None, None]   # per layer, broadcast over sites and columns

@@ -104,9 +104,11 @@ def test_option_and_node_validation():
     s = np.ones(4)
     for kw in (dict(rtol=0.0), dict(max_iter=0), dict(n_ritz=7), dict(precision=9), dict(tile_rows=48),
                dict(cov_form=5), dict(cov_form=ie.COV_BAND, precision=ie.MIXED_BF16), dict(warm_start=1),
-               dict(warm_start=3)):
+               dict(warm_start=3), dict(fixed_iters=-1), dict(fixed_iters=2, precision=ie.MIXED_FP32), dict(s_form=3),
+               dict(s_form=ie.S_DENSE, precision=ie.MIXED_BF16)):
         o = ie.default_opts(**kw)
         assert lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(o)) == 0
+    assert lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(ie.default_opts(fixed_iters=2))) > 0
     o = ie.default_opts()
     assert lib.infoesrf_perturbation_update(C.byref(p), 0, s.ctypes.data_as(dp), s.ctypes.data_as(dp), None,
                                             C.c_void_p(0x1000), C.byref(o), None, C.c_void_p(0x1000), 1 << 30,
@@ -192,8 +194,9 @@ def test_band_form_workspace():
     """The band form adds (2bz+1)(2bx+1) planes of round_up(n, 64) doubles (state grid)."""
     lib = ie.library()
     p = fake_problem(n=64, N=8, bx=3)
-    op = lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(ie.default_opts(cov_form=ie.COV_OPERATOR)))
-    bd = lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(ie.default_opts(cov_form=ie.COV_BAND)))
+    kw = dict(s_form=ie.S_OPERATOR)
+    op = lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(ie.default_opts(cov_form=ie.COV_OPERATOR, **kw)))
+    bd = lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(ie.default_opts(cov_form=ie.COV_BAND, **kw)))
     assert bd - op >= 7 * 64 * 8
     d = fake_problem(kind=ie.LOC_DENSE)
     assert lib.infoesrf_workspace_bytes(C.byref(d), 4, C.byref(ie.default_opts(cov_form=ie.COV_BAND))) == 0
@@ -219,3 +222,36 @@ def test_net_argument_validation(tmp_path):
     o = ie.default_opts(warm_start=ie.START_LEARNED)
     assert lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(o)) == 0
     assert "needs opts->net" in lib.infoesrf_last_error().decode()
+
+
+def test_dense_s_choice():
+    """The automatic form of S: dense (the m x m matrix is in the workspace) when a product with
+    it costs at most half of an apply of P in the working domain and forming it is cheap next to
+    the solves; explicit choices are honoured."""
+    lib = ie.library()
+
+    def ws(p, Q, **kw):
+        return lib.infoesrf_workspace_bytes(C.byref(p), Q, C.byref(ie.default_opts(**kw)))
+
+    def dense_taken(p, Q, **kw):
+        base = ws(p, Q, s_form=ie.S_OPERATOR, **kw)
+        auto = ws(p, Q, **kw)
+        assert auto in (base, ws(p, Q, s_form=ie.S_DENSE, **kw))
+        return auto > base
+
+    m = 40
+    extra = ws(fake_problem(n=1280, m=m, bx=6), 8, s_form=ie.S_DENSE) - ws(fake_problem(n=1280, m=m, bx=6), 8,
+                                                                           s_form=ie.S_OPERATOR)
+    assert extra >= 8 * m * m
+    # few observations of a large state: dense S (band: 2 m^2 = 3200 <= 1280 * 13)
+    assert dense_taken(fake_problem(n=1280, m=m, bx=6), 8)
+    # as many observations as the band is wide: the band apply is cheaper
+    assert not dense_taken(fake_problem(n=1024, m=1024, bx=40), 16)
+    # the operator form costs N times the band per vector
+    assert dense_taken(fake_problem(n=1024, m=256, bx=40), 16, cov_form=ie.COV_OPERATOR)
+    assert not dense_taken(fake_problem(n=1024, m=256, bx=40), 16, cov_form=ie.COV_BAND)
+    # the mean update (one system) does not assemble a large S for its few iterations
+    assert dense_taken(fake_problem(n=4096, m=200, bx=60), 0)
+    assert not dense_taken(fake_problem(n=4096, m=400, bx=60), 0)
+    # BF16 inner applies never take it
+    assert not dense_taken(fake_problem(n=1280, m=m, bx=6), 8, precision=ie.MIXED_BF16)

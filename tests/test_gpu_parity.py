@@ -103,12 +103,16 @@ def test_cov_apply_dense_localization():
     assert rel(got, dp.P @ V) < 1e-13
 
 
-FORMS = {"operator": ie.COV_OPERATOR, "band": ie.COV_BAND}
+# operator / band: every PCG apply goes through P in that form; dense-s: S assembled once as an
+# m x m matrix (from the band of P when the automatic choice of P's form takes it)
+FORMS = {"operator": dict(cov_form=ie.COV_OPERATOR, s_form=ie.S_OPERATOR),
+         "band": dict(cov_form=ie.COV_BAND, s_form=ie.S_OPERATOR),
+         "dense-s": dict(s_form=ie.S_DENSE)}
 
 
 def opts_for(prob, P, domain, form=None, **kw):
     if form is not None:
-        kw["cov_form"] = FORMS[form]
+        kw.update(FORMS[form])
     if domain == "lattice":
         lat = P.lattice()
         assert lat is not None
@@ -116,7 +120,7 @@ def opts_for(prob, P, domain, form=None, **kw):
     return ie.default_opts(**kw)
 
 
-@pytest.mark.parametrize("form", ["operator", "band"])
+@pytest.mark.parametrize("form", ["operator", "band", "dense-s"])
 @pytest.mark.parametrize("domain", ["state", "lattice"])
 @pytest.mark.parametrize("case", ["gauss-n256-periodic", "ragged-1d-nonperiodic", "2d-layers"])
 def test_mean_update_matches_oracle(case, domain, form):
@@ -132,7 +136,7 @@ def test_mean_update_matches_oracle(case, domain, form):
     assert st.relres[0] <= 1e-8 and st.converged[0] == 1
 
 
-@pytest.mark.parametrize("form", ["operator", "band"])
+@pytest.mark.parametrize("form", ["operator", "band", "dense-s"])
 @pytest.mark.parametrize("domain", ["state", "lattice"])
 @pytest.mark.parametrize("case", ["gauss-n256-periodic", "ragged-1d-nonperiodic", "2d-layers", "2d-periodic-z"])
 def test_perturbation_update_matches_oracle(case, domain, form):
@@ -190,7 +194,7 @@ def test_solvers_agree_and_are_deterministic(solver):
     assert rel(a.cpu().numpy(), c.cpu().numpy()) < 1e-12
 
 
-@pytest.mark.parametrize("form", ["operator", "band"])
+@pytest.mark.parametrize("form", ["operator", "band", "dense-s"])
 @pytest.mark.parametrize("domain", ["state", "lattice"])
 def test_mixed_fp32_meets_fp64_bound(domain, form):
     prob = syn.config1()
@@ -343,9 +347,37 @@ def test_band_form_options():
         ie.perturbation_update(P, s, p, ie.default_opts(precision=ie.MIXED_BF16, cov_form=ie.COV_BAND))
     assert e.value.code == ie.ERR_INVALID_ARG
     # AUTO with BF16 runs the operator form; the FP64 forms agree to rounding
-    a, _ = ie.perturbation_update(P, s, p, ie.default_opts(cov_form=ie.COV_OPERATOR))
-    b, _ = ie.perturbation_update(P, s, p, ie.default_opts(cov_form=ie.COV_BAND))
+    a, _ = ie.perturbation_update(P, s, p, ie.default_opts(cov_form=ie.COV_OPERATOR, s_form=ie.S_OPERATOR))
+    b, _ = ie.perturbation_update(P, s, p, ie.default_opts(cov_form=ie.COV_BAND, s_form=ie.S_OPERATOR))
     assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-9
+
+
+def test_dense_s_options_and_agreement():
+    """The dense form of S: not with BF16; AUTO takes it for few observations of a large state
+    (same result as the per-iteration applies to rounding), and not for the n = 4096 lattice."""
+    prob = syn.config1()
+    say("dense S option checks")
+    P = ie.Problem.from_synthetic(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    with pytest.raises(ie.InfoEsrfError) as e:
+        ie.perturbation_update(P, s, p, ie.default_opts(precision=ie.MIXED_BF16, s_form=ie.S_DENSE))
+    assert e.value.code == ie.ERR_INVALID_ARG
+    a, _ = ie.perturbation_update(P, s, p, ie.default_opts(s_form=ie.S_OPERATOR))
+    b, _ = ie.perturbation_update(P, s, p, ie.default_opts(s_form=ie.S_DENSE))
+    c, _ = ie.perturbation_update(P, s, p, ie.default_opts())
+    assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-9
+    assert rel(b.cpu().numpy(), c.cpu().numpy()) < 1e-9
+    # the workspace holds the m x m matrix exactly when the form is taken
+    Q = prob.Q
+    w_op = ie.workspace_bytes(P, Q, ie.default_opts(s_form=ie.S_OPERATOR))
+    w_d = ie.workspace_bytes(P, Q, ie.default_opts(s_form=ie.S_DENSE))
+    w_auto = ie.workspace_bytes(P, Q, ie.default_opts())
+    assert w_d >= w_op + 8 * prob.m * prob.m and w_auto == w_d
+    big = syn.config2()
+    Pb = ie.Problem.from_synthetic(big)
+    lat = ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=Pb.lattice())
+    lat_op = ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=Pb.lattice(), s_form=ie.S_OPERATOR)
+    assert ie.workspace_bytes(Pb, big.Q, lat) == ie.workspace_bytes(Pb, big.Q, lat_op)
 
 
 def test_autotune_records_choices_and_keeps_results():

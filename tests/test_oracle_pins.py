@@ -305,3 +305,50 @@ def test_matrix_free_update_matches_dense_oracle():
     Zd = ref.perturbation_update_quadrature(dp, s, p)
     assert np.linalg.norm(Za - Zd) < 1e-9 * np.linalg.norm(Zd)
     assert iters.min() >= 1
+
+
+def _galerkin(A, K, b):
+    """The A-orthogonal projection of A^{-1} b onto span(K): CG's optimality over a Krylov space."""
+    c = np.linalg.solve(K.T @ A @ K, K.T @ b)
+    return K @ c
+
+
+@pytest.mark.parametrize("workload", ["config1", "paper-sec4"])
+def test_matrix_free_mean_update_matches_dense(workload):
+    prob = syn.config1() if workload == "config1" else syn.experiment1_problem()
+    dp = ref.DenseProblem.from_problem(prob)
+    Om = syn.sketch_matrix(prob.m, 20, 5)
+    mu_a, k = ref.info_esrf_mean_pcg(prob, prob.y, rtol=1e-12, Omega=Om)
+    want = ref.mean_update_eig(dp, prob.y)
+    assert np.linalg.norm(mu_a - want) < 1e-9 * np.linalg.norm(want - dp.mu)
+    assert k >= 1
+
+
+def test_fixed_count_pcg_is_krylov_galerkin_projection():
+    """k PCG iterations from zero give the A-norm-optimal point of the k-dimensional
+    preconditioned Krylov space span{M b, (M A) M b, ...} (exact arithmetic; checked at k = 1, 2),
+    with M the limited-memory preconditioner (SPD) or the identity."""
+    prob = syn.experiment1_problem()
+    dp = ref.DenseProblem.from_problem(prob)
+    Om = syn.sketch_matrix(prob.m, 30, 8)
+    Phi, SPhi, th = ref.randomized_eig(lambda V: dp.S @ V, Om, 20)
+    b = dp.B[:, 4]
+    for sigma in (0.0, 3.0):
+        A = (1.0 + sigma) * np.eye(prob.m) + dp.S
+        pre = ref.LimitedMemoryPreconditioner(Phi, SPhi, th, np.diag(dp.S), sigma)
+        for M in (None, pre):
+            Mi = (lambda v: v) if M is None else M
+            z0 = Mi(b)
+            K = np.column_stack([z0, Mi(A @ z0)])
+            for k in (1, 2):
+                x, its, _ = ref.pcg(lambda v: A @ v, b, M, rtol=0.0, max_iter=k)
+                want = _galerkin(A, K[:, :k], b)
+                assert its == k
+                assert np.linalg.norm(x - want) < 1e-10 * np.linalg.norm(want)
+    # the one-step mean update is the steepest-descent step along R^{-1/2} d, mapped by P H^T R^{-1/2}
+    mu_a, k = ref.info_esrf_mean_pcg(prob, prob.y, rtol=0.0, n_ritz=0, max_iter=1)
+    d = dp.dinv * (prob.y - dp.H @ dp.mu)
+    A0 = np.eye(prob.m) + dp.S
+    step = (d @ d) / (d @ A0 @ d) * d
+    assert k == 1
+    assert np.linalg.norm(mu_a - dp.mu - dp.gain_apply(step[:, None])[:, 0]) < 1e-10 * np.linalg.norm(mu_a - dp.mu)

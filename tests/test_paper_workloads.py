@@ -52,3 +52,31 @@ def test_sec5_channels_normalized():
         cols = prob.h_idx[prob.h_ptr[k]:prob.h_ptr[k + 1]] % nx
         assert len(set(cols.tolist())) == 1
     assert np.allclose(syn.experiment2_forcing(32)[[0, -1]], [8.0, 4.0])
+
+
+def test_kalman_analysis_variance_matches_dense_formula():
+    """The FFT evaluation of the Sec. 4 score's reference variances against the dense Kalman
+    analysis covariance Sigma - Sigma H^T (H Sigma H^T + R)^{-1} H Sigma."""
+    import scipy.linalg as sla
+
+    from paper_2503_00253_amd import experiments as ex
+
+    prob = syn.experiment1_problem(n=400, d_obs=20)
+    row = syn.experiment1_prior_row(400)
+    Sig = sla.circulant(row)
+    assert np.allclose(Sig, Sig.T)
+    Hd = np.zeros((prob.m, prob.n))
+    for k in range(prob.m):
+        sl = slice(prob.h_ptr[k], prob.h_ptr[k + 1])
+        Hd[k, prob.h_idx[sl]] = prob.h_w[sl]
+    A = Hd @ Sig @ Hd.T + np.diag(prob.r_var)
+    want = np.diag(Sig - Sig @ Hd.T @ np.linalg.solve(A, Hd @ Sig))
+    got = ex.kalman_analysis_variance(prob, row)
+    assert np.allclose(got, want, rtol=1e-10, atol=1e-12)
+    # observations only remove variance; the analysis variance stays positive
+    assert np.all(got < row[0]) and np.all(got > 0)
+    # E^2 of perturbations whose variances are exact is zero, and scales as the square of a bias
+    N = 9
+    pert = np.sqrt(want)[:, None] * np.sqrt((N - 1) / N) * np.ones((1, N))
+    assert ex.variance_error(pert, want) < 1e-24
+    assert np.isclose(ex.variance_error(pert * np.sqrt(1.1), want), 0.01)
