@@ -456,3 +456,146 @@ def info_esrf_mean_pcg(prob, y, rtol=1e-8, n_ritz=10, Omega=None, max_iter=1000)
     u0, k, _ = pcg(lambda v: v + op(v), op.dinv * d, pre, rtol, max_iter)
     v = op.H.T @ (op.dinv * u0)
     return mu + op.cov(v[:, None])[:, 0], k
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.2's alternatives to one PCG process per (q, i)
+# ---------------------------------------------------------------------------
+
+
+def multishift_cg(apply_A, b, shifts, rtol=1e-8, max_iter=1000):
+    """One CG process for A x = b that also solves (A + sigma I) x = b for every sigma >= 0 in
+    `shifts` (Sec. 3.2, first alternative: the Krylov spaces of shifted matrices coincide).
+
+    The shifted residuals stay parallel to the base residual, r_sigma = zeta_sigma r, and the
+    shifted iterates follow from the base CG scalars (alpha_k, beta_k) by the coupled recurrences
+        zeta_{k+1} = zeta_k zeta_{k-1} alpha_{k-1}
+                     / (alpha_k beta_{k-1} (zeta_{k-1} - zeta_k) + zeta_{k-1} alpha_{k-1} (1 + sigma alpha_k)),
+        alpha^sigma_k = alpha_k zeta_{k+1} / zeta_k,  beta^sigma_k = (zeta_{k+1} / zeta_k)^2 beta_k,
+        x^sigma += alpha^sigma_k p^sigma,  p^sigma = zeta_{k+1} r_{k+1} + beta^sigma_k p^sigma,
+    with zeta_{-1} = zeta_0 = 1, alpha_{-1} = 1, beta_{-1} = 0, x^sigma_0 = 0, p^sigma_0 = b.  No
+    preconditioner (a shift-dependent one would break the shared Krylov space).  A shift stops
+    when |zeta| ||r|| <= rtol ||b||; the process stops when every shift has.  With rtol = 0 it runs
+    exactly max_iter iterations.  Returns (X with one column per shift, iterations per shift).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    shifts = np.asarray(shifts, dtype=np.float64)
+    ns = shifts.size
+    X = np.zeros((b.size, ns))
+    its = np.zeros(ns, dtype=np.int64)
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return X, its
+    r = b.copy()
+    p = b.copy()
+    Ps = np.repeat(b[:, None], ns, axis=1)
+    z_prev = np.ones(ns)
+    z = np.ones(ns)
+    alpha_prev, beta_prev = 1.0, 0.0
+    rr = r @ r
+    live = np.ones(ns, dtype=bool)
+    for k in range(1, max_iter + 1):
+        Ap = apply_A(p)
+        alpha = rr / (p @ Ap)
+        r = r - alpha * Ap
+        rr_new = r @ r
+        beta = rr_new / rr
+        for j in np.nonzero(live)[0]:
+            den = alpha * beta_prev * (z_prev[j] - z[j]) + z_prev[j] * alpha_prev * (1.0 + shifts[j] * alpha)
+            z_new = z[j] * z_prev[j] * alpha_prev / den
+            a_j = alpha * z_new / z[j]
+            b_j = (z_new / z[j]) ** 2 * beta
+            X[:, j] += a_j * Ps[:, j]
+            Ps[:, j] = z_new * r + b_j * Ps[:, j]
+            z_prev[j], z[j] = z[j], z_new
+            its[j] = k
+            if abs(z_new) * np.sqrt(rr_new) <= rtol * bnorm:
+                live[j] = False
+        p = r + beta * p
+        alpha_prev, beta_prev, rr = alpha, beta, rr_new
+        if not live.any():
+            break
+    return X, its
+
+
+def info_esrf_multishift(prob, s, p, rtol=1e-8, max_iter=1000):
+    """Perturbation update (Sec. 3.2) with one multi-shift CG process per member: the base
+    system is the smallest shift, C_min = (1 + min s) I + S, and every node is a shift of it.
+    Returns (Za, iterations[q, i])."""
+    op = FBOperator(prob)
+    _, Z = ensemble_stats(prob.X)
+    B = op.dinv[:, None] * (op.H @ Z)
+    s = np.asarray(s, dtype=np.float64)
+    q0 = int(np.argmin(s))
+    base = 1.0 + s[q0]
+    Ubar = np.zeros((prob.m, prob.N))
+    iters = np.zeros((len(s), prob.N), dtype=np.int64)
+    for i in range(prob.N):
+        U, its = multishift_cg(lambda v: base * v + op(v), B[:, i], s - s[q0], rtol, max_iter)
+        Ubar[:, i] = U @ np.asarray(p, dtype=np.float64)
+        iters[:, i] = its
+    Vs = op.H.T @ (op.dinv[:, None] * Ubar)
+    return Z - op.cov(Vs), iters
+
+
+def block_cg(apply_A, B, precond=None, rtol=1e-8, max_iter=1000, drop=1e-12):
+    """Block (P)CG for A X = B over all columns of B together (Sec. 3.2, second alternative;
+    O'Leary's method): each column's iterate is the A-norm-optimal point of the SUM of the
+    columns' (preconditioned) Krylov spaces.
+
+    Every iteration A-orthonormalizes the search block: with G = P^T A P = V diag(lam) V^T,
+    directions whose lam <= drop * max(lam) are dropped (a rank-deficient block loses nothing
+    of its span), Pt = P V lam^{-1/2}, and then
+        X += Pt (Pt^T R),   R -= (A Pt)(Pt^T R),   Zb = M R,   P = Zb - Pt ((A Pt)^T Zb),
+    the last step making the next block A-orthogonal to the current one (the block CG short
+    recurrence).  Stops when every column has ||r_j|| <= rtol ||b_j||; rtol = 0 runs exactly
+    max_iter iterations.  Returns (X, iterations).
+    """
+    B = np.atleast_2d(np.asarray(B, dtype=np.float64).T).T
+    X = np.zeros_like(B)
+    R = B.copy()
+    bn = np.linalg.norm(B, axis=0)
+    Mi = precond if precond is not None else (lambda V: V)
+    P = Mi(R)
+    if np.all(np.linalg.norm(R, axis=0) <= rtol * bn):
+        return X, 0
+    k = 0
+    for k in range(1, max_iter + 1):
+        W = apply_A(P)
+        G = P.T @ W
+        lam, V = np.linalg.eigh(0.5 * (G + G.T))
+        keep = lam > drop * lam.max()
+        T = V[:, keep] / np.sqrt(lam[keep])
+        Pt, Wt = P @ T, W @ T
+        a = Pt.T @ R
+        X = X + Pt @ a
+        R = R - Wt @ a
+        if np.all(np.linalg.norm(R, axis=0) <= rtol * bn):
+            break
+        Zb = Mi(R)
+        P = Zb - Pt @ (Wt.T @ Zb)
+    return X, k
+
+
+def info_esrf_block_cg(prob, s, p, rtol=1e-8, n_ritz=10, Omega=None, max_iter=1000):
+    """Perturbation update (Sec. 3.2) with one block PCG per node q over the N members'
+    right-hand sides, with the node's limited-memory preconditioner (Appendix E).
+    Returns (Za, iterations per node)."""
+    op = FBOperator(prob)
+    _, Z = ensemble_stats(prob.X)
+    B = op.dinv[:, None] * (op.H @ Z)
+    if n_ritz > 0:
+        Phi, SPhi, th = randomized_eig(op, Omega, n_ritz)
+        dS = op.diag()
+    Ubar = np.zeros((prob.m, prob.N))
+    iters = np.zeros(len(s), dtype=np.int64)
+    for q in range(len(s)):
+        pre = None
+        if n_ritz > 0:
+            lmp = LimitedMemoryPreconditioner(Phi, SPhi, th, dS, s[q])
+            pre = lambda V, lmp=lmp: np.column_stack([lmp(V[:, j]) for j in range(V.shape[1])])
+        U, k = block_cg(lambda V, sh=s[q]: (1.0 + sh) * V + op(V), B, pre, rtol, max_iter)
+        Ubar += p[q] * U
+        iters[q] = k
+    Vs = op.H.T @ (op.dinv[:, None] * Ubar)
+    return Z - op.cov(Vs), iters

@@ -352,3 +352,91 @@ def test_fixed_count_pcg_is_krylov_galerkin_projection():
     step = (d @ d) / (d @ A0 @ d) * d
     assert k == 1
     assert np.linalg.norm(mu_a - dp.mu - dp.gain_apply(step[:, None])[:, 0]) < 1e-10 * np.linalg.norm(mu_a - dp.mu)
+
+
+def _krylov(A, v, k):
+    """Orthonormal basis of span{v, A v, ..., A^{k-1} v} (Gram-Schmidt twice per column)."""
+    Q = np.zeros((v.size, 0))
+    w = v.copy()
+    for _ in range(k):
+        for _ in range(2):
+            w = w - Q @ (Q.T @ w)
+        Q = np.column_stack([Q, w / np.linalg.norm(w)])
+        w = A @ Q[:, -1]
+    return Q
+
+
+def test_multishift_cg_iterates_are_shifted_galerkin_projections():
+    """k steps of multi-shift CG give, for every shift, the A_sigma-norm-optimal point of the
+    common Krylov space K_k(A, b) (k = 1..4, exact arithmetic), and converged runs solve every
+    shifted system."""
+    prob = syn.experiment1_problem()
+    dp = ref.DenseProblem.from_problem(prob)
+    base = 1.0 + 0.02
+    A = base * np.eye(prob.m) + dp.S
+    b = dp.B[:, 3]
+    shifts = np.array([0.0, 0.3, 2.0, 40.0, 1e4])
+    for k in (1, 2, 3, 4):
+        X, its = ref.multishift_cg(lambda v: A @ v, b, shifts, rtol=0.0, max_iter=k)
+        K = _krylov(A, b, k)
+        assert np.all(its == k)
+        for j, sg in enumerate(shifts):
+            want = _galerkin(A + sg * np.eye(prob.m), K, b)
+            assert np.linalg.norm(X[:, j] - want) < 1e-10 * np.linalg.norm(want), (k, sg)
+    X, its = ref.multishift_cg(lambda v: A @ v, b, shifts, rtol=1e-12, max_iter=500)
+    for j, sg in enumerate(shifts):
+        want = np.linalg.solve(A + sg * np.eye(prob.m), b)
+        assert np.linalg.norm(X[:, j] - want) < 1e-10 * np.linalg.norm(want)
+    # larger shifts are better conditioned and stop no later; the base runs longest
+    assert np.all(np.diff(its) <= 0) and its[0] == its.max()
+    # one shift of 0 is plain CG
+    x, k0, _ = ref.pcg(lambda v: A @ v, b, None, rtol=1e-12)
+    assert its[0] in (k0 - 1, k0, k0 + 1)
+    assert np.linalg.norm(X[:, 0] - x) < 1e-11 * np.linalg.norm(x)
+
+
+def test_block_cg_iterates_are_block_krylov_galerkin_projections():
+    """k steps of block PCG give, for every column, the A-norm-optimal point of the sum of the
+    columns' preconditioned Krylov spaces span{M B, (M A) M B, ...} (k = 1, 2, 3), with the
+    limited-memory preconditioner and without; converged runs solve every column."""
+    prob = syn.experiment1_problem()
+    dp = ref.DenseProblem.from_problem(prob)
+    A = (1.0 + 0.5) * np.eye(prob.m) + dp.S
+    B = dp.B[:, :6]
+    Om = syn.sketch_matrix(prob.m, 20, 3)
+    Phi, SPhi, th = ref.randomized_eig(lambda V: dp.S @ V, Om, 10)
+    lmp = ref.LimitedMemoryPreconditioner(Phi, SPhi, th, np.diag(dp.S), 0.5)
+    Mblk = lambda V: np.column_stack([lmp(V[:, j]) for j in range(V.shape[1])])
+    for M in (None, Mblk):
+        Mi = (lambda V: V) if M is None else M
+        blocks = [Mi(B)]
+        for k in (1, 2, 3):
+            X, its = ref.block_cg(lambda V: A @ V, B, M, rtol=0.0, max_iter=k)
+            K = np.column_stack(blocks)
+            want = K @ np.linalg.solve(K.T @ A @ K, K.T @ B)
+            assert its == k
+            assert np.linalg.norm(X - want) < 1e-9 * np.linalg.norm(want), (k, M is None)
+            blocks.append(Mi(A @ blocks[-1]))
+        X, its = ref.block_cg(lambda V: A @ V, B, M, rtol=1e-12, max_iter=500)
+        want = np.linalg.solve(A, B)
+        assert np.linalg.norm(X - want) < 1e-10 * np.linalg.norm(want)
+        # the block method needs no more iterations than single-column CG on its hardest column
+        single = max(ref.pcg(lambda v: A @ v, B[:, j], None if M is None else lmp, rtol=1e-12)[1]
+                     for j in range(B.shape[1]))
+        assert its <= single
+
+
+def test_multishift_and_block_updates_match_dense_oracle():
+    prob = syn.config1()
+    dp = ref.DenseProblem.from_problem(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = ref.perturbation_update_quadrature(dp, s, p)
+    Za, it_ms = ref.info_esrf_multishift(prob, s, p, rtol=1e-12)
+    assert np.linalg.norm(Za - want) < 1e-9 * np.linalg.norm(want)
+    q0 = int(np.argmin(s))
+    assert np.all(it_ms[q0] == it_ms.max(axis=0))
+    Om = syn.sketch_matrix(prob.m, 20, 4)
+    Zb, it_b = ref.info_esrf_block_cg(prob, s, p, rtol=1e-12, Omega=Om)
+    assert np.linalg.norm(Zb - want) < 1e-9 * np.linalg.norm(want)
+    _, it_pcg = ref.info_esrf_pcg(prob, s, p, rtol=1e-12, Omega=Om)
+    assert np.all(it_b <= it_pcg.max(axis=1))
