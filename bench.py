@@ -31,6 +31,7 @@ DTYPE = {0: "f64", 1: "f32/f64", 2: "bf16/f64"}
 SLOTS = {0: ("k_cov_stencil<fp64>", "mfma", 0), 1: ("k_cov_stencil<fp32>", "mfma", 1),
          2: ("k_cov_bf16", "mfma", 2), 3: ("k_band_apply<fp64>", "hbm", None),
          4: ("k_band_apply<fp32>", "hbm", None), 5: ("k_pcg_fused", "hbm", None)}
+SOLVERS = {"plain": 0, "compact": 1, "multishift": 3}
 SRC = {0: "cov_apply.hip", 1: "cov_apply.hip", 2: "cov_apply.hip", 3: "band.hip", 4: "band.hip", 5: "pcg.hip"}
 
 
@@ -41,7 +42,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64")
     ap.add_argument("--domain", choices=["state", "lattice"], default="lattice")
-    ap.add_argument("--solver", choices=["plain", "compact"], default="compact")
+    ap.add_argument("--solver", choices=["plain", "compact", "multishift"], default="compact",
+                    help="compact: batched PCG with the limited-memory preconditioner (default); plain: the "
+                         "same with converged systems masked; multishift: one unpreconditioned CG process "
+                         "per member serving every node")
     ap.add_argument("--form", choices=["auto", "operator", "band"], default="auto",
                     help="covariance form: explicit band of P, or the operator form sum_i z_i o L(z_i o v)")
     ap.add_argument("--plain-steps", type=int, default=3)
@@ -102,7 +106,7 @@ def main():
     log("workload", prob.name, "precision", a.precision, "domain", a.domain, "solver", a.solver)
     P = ie.Problem.from_synthetic(prob)
     s, p = ie.quadrature_elliptic(prob.Q, prob.ell)
-    kw = dict(precision=prec, solver=ie.SOLVER_PLAIN if a.solver == "plain" else ie.SOLVER_COMPACT,
+    kw = dict(precision=prec, solver=SOLVERS[a.solver],
               cov_form={"auto": ie.COV_AUTO, "operator": ie.COV_OPERATOR, "band": ie.COV_BAND}[a.form],
               n_ritz=a.n_ritz)
     if a.domain == "lattice":
@@ -245,7 +249,7 @@ def bench_cycle(a, prec):
             raise SystemExit("paper-sec5-cycle runs its fixed iteration count in FP64 (--precision fp64)")
         prob = syn.experiment2_problem()
         noise = syn.experiment2_noise(cycles, prob.m)
-        kw = dict(precision=prec, cov_form=form, n_ritz=a.n_ritz, fixed_iters=10)
+        kw = dict(precision=prec, cov_form=form, n_ritz=a.n_ritz, fixed_iters=10, solver=SOLVERS[a.solver])
         run = CycleRunner(prob, noise=noise, opts=ie.default_opts(**kw), lattice=False)
         name = f"paper-sec5-lorenz96-32x40-N40-m40-Q{run.Q}-fixed10-cycle"
         metric = "shifted SPD solves/s at 10 fixed PCG iterations"
@@ -253,7 +257,8 @@ def bench_cycle(a, prec):
         prob = syn.lorenz_problem()
         noise = np.random.default_rng(4242).standard_normal((cycles, prob.m)) * np.sqrt(prob.r_var[0])
         run = CycleRunner(prob, noise=noise)
-        kw = dict(precision=prec, apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=run.P.lattice(), cov_form=form)
+        kw = dict(precision=prec, apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=run.P.lattice(), cov_form=form,
+                  solver=SOLVERS[a.solver])
         run.opts = ie.default_opts(**kw)
         name = "lorenz96-8x480-N20-m1280-Q12-cycle"
         metric = "shifted SPD solves/s at rel-res 1e-8"
@@ -294,7 +299,8 @@ def bench_cycle(a, prec):
            "data": "synthetic",
            "config": {"workload": name, "n": prob.n, "N": prob.N, "m": prob.m,
                       "Q": run.Q, "systems_per_step": systems, "step": "one forecast-analysis cycle",
-                      "graph": bool(a.graph), "precision": a.precision, "rtps_alpha": run.alpha},
+                      "graph": bool(a.graph), "precision": a.precision, "rtps_alpha": run.alpha,
+                      "solver": a.solver},
            "final_analysis": {"mse": mse, "variance": var},
            "last_cycle_iterations": {"mean": float(sp.iters.mean()), "max": int(sp.iters.max())}}
     log(f"{value:.1f} solves/s, {(t1 - t0) * 1e3 / a.steps:.3f} ms/cycle, mse {mse:.4f} var {var:.4f}")
@@ -312,7 +318,7 @@ def bench_batched(a, prec):
     Ps = [ie.Problem.from_synthetic(pr) for pr in probs]
     nodes = [ie.quadrature_elliptic(pr.Q, pr.ell) for pr in probs]
     systems = sum(pr.Q * pr.N for pr in probs)
-    kw = dict(precision=prec, solver=ie.SOLVER_PLAIN if a.solver == "plain" else ie.SOLVER_COMPACT,
+    kw = dict(precision=prec, solver=SOLVERS[a.solver],
               cov_form={"auto": ie.COV_AUTO, "operator": ie.COV_OPERATOR, "band": ie.COV_BAND}[a.form])
     lats = None
     if a.domain == "lattice":

@@ -95,6 +95,12 @@ extern "C" {
 #define INFOESRF_SOLVER_PLAIN 0      /* one launch per iteration over all systems, converged ones masked */
 #define INFOESRF_SOLVER_COMPACT 1    /* converged systems retired from the launched set each iteration */
 #define INFOESRF_SOLVER_PERSISTENT 2 /* one persistent launch; work queue of systems (batched instances) */
+/* MULTISHIFT (perturbation update; the first alternative of Sec. 3.2): one CG process per
+ * member on the smallest node's system serves every node as a shift of it (shared Krylov
+ * spaces, collinear residuals), one apply of S per member per iteration instead of Q.  It has no
+ * preconditioner (n_ritz is used by the mean update only); FP64 and the zero start only.  FP64
+ * residual sweeps then check every (q, i) system and correct any above rtol with PCG. */
+#define INFOESRF_SOLVER_MULTISHIFT 3
 
 /* ---- where the normalized covariance S is applied ----------------------- */
 #define INFOESRF_DOMAIN_STATE 0       /* general H: scatter to state space, apply P, gather */

@@ -114,6 +114,11 @@ __global__ void k_set_nodes(Nodes nd, int32_t Q, int64_t N, double* sigma, doubl
   if (t < extra) sigma[(int64_t)Q * N + t] = extra_sigma;
 }
 
+__global__ void k_fill_i64(int64_t* p, int64_t v, int64_t count) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < count) p[t] = v;
+}
+
 // Sweep bookkeeping from true residual norms (iterative refinement).
 //   fdone: 1 converged (rn <= rtol bn), 2 failed (iteration cap or non-finite), 0 needs work.
 //   done (inner PCG status) = fdone ? 1 : 0; thresh = absolute inner target.
@@ -201,8 +206,26 @@ __global__ void k_sweep_status(const double* rn, const double* bn, double rtol, 
 }
 
 // Counters of the call (deterministic reduction over systems in one block).
+// Applies saved by a multi-shift process: every member iteration is one apply, while the
+// per-system counts add one per live shift.  adj = sum_i mit[i] - sum_s iters[s] (one block).
+__global__ void k_msc_adjust(const int32_t* iters, int64_t S, const int32_t* mit, int64_t N, int64_t* adj) {
+  __shared__ int64_t acc[256];
+  const int t = threadIdx.x;
+  int64_t a = 0;
+  for (int64_t i = t; i < N; i += 256) a += mit[i];
+  for (int64_t s = t; s < S; s += 256) a -= iters[s];
+  acc[t] = a;
+  __syncthreads();
+  if (t == 0) {
+    int64_t tot = 0;
+    for (int j = 0; j < 256; ++j) tot += acc[j];
+    *adj = tot;
+  }
+}
+
 __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, const int32_t* fdone, int64_t S,
-                                  int64_t extra_fp64_applies, int inner_fp64, int fixed, const int32_t* flags,
+                                  int64_t extra_fp64_applies, const int64_t* adj, int inner_fp64, int fixed,
+                                  const int32_t* flags,
                                   const int32_t* fallbacks, int64_t* out) {
   __shared__ int64_t acc[4][256];
   const int t = threadIdx.x;
@@ -230,8 +253,9 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
     out[INFOESRF_CNT_SWEEPS] = b;
     out[INFOESRF_CNT_NOT_CONVERGED] = c;
     out[INFOESRF_CNT_MAX_ITERS] = d;
-    out[INFOESRF_CNT_APPLIES] = a + b + extra_fp64_applies;
-    out[INFOESRF_CNT_APPLIES_FP64] = (inner_fp64 ? a : 0) + b + extra_fp64_applies;
+    const int64_t ai = a + (adj ? *adj : 0);  // inner applies
+    out[INFOESRF_CNT_APPLIES] = ai + b + extra_fp64_applies;
+    out[INFOESRF_CNT_APPLIES_FP64] = (inner_fp64 ? ai : 0) + b + extra_fp64_applies;
     out[INFOESRF_CNT_FALLBACKS] = fallbacks ? *fallbacks : 0;
     const int32_t f = *flags;
     int64_t status = INFOESRF_OK;
@@ -263,6 +287,7 @@ struct Options {
   const void* net;
   bool band;  // covariance applies through the explicit band of P
   int sform;  // INFOESRF_S_*: requested form of S
+  int msc_q0 = -1;  // multi-shift perturbation solve: the base node (-1: not used)
 };
 
 struct Inst {
@@ -307,6 +332,10 @@ struct Sys {
          *thresh = nullptr, *pw = nullptr;
   int32_t *iters = nullptr, *sweeps = nullptr, *done = nullptr, *fdone = nullptr;
   int32_t *act = nullptr, *nact = nullptr, *act2 = nullptr, *nact2 = nullptr;
+  // multi-shift CG (SOLVER_MULTISHIFT): per-system zeta pair, per-member base scalars
+  double *zeta = nullptr, *zeta_prev = nullptr, *mrr = nullptr, *malpha = nullptr, *mbeta = nullptr;
+  int32_t* mit = nullptr;
+  int64_t* app_adj = nullptr;  // applies counter correction: member iterations replace system iterations
 };
 
 struct Pre {
@@ -388,7 +417,10 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   IE_CHECK(p == 0 || p + o->oversample <= P->m, INFOESRF_ERR_INVALID_ARG, "n_ritz + oversample must be <= m");
   IE_CHECK(o->precision >= INFOESRF_FP64 && o->precision <= INFOESRF_MIXED_BF16, INFOESRF_ERR_INVALID_ARG,
            "unknown precision");
-  IE_CHECK(o->solver >= INFOESRF_SOLVER_PLAIN && o->solver <= INFOESRF_SOLVER_PERSISTENT, INFOESRF_ERR_INVALID_ARG,
+  IE_CHECK(o->solver != INFOESRF_SOLVER_MULTISHIFT ||
+               (o->precision == INFOESRF_FP64 && o->warm_start == INFOESRF_START_ZERO),
+           INFOESRF_ERR_INVALID_ARG, "the multi-shift solver needs precision FP64 and the zero start");
+  IE_CHECK(o->solver >= INFOESRF_SOLVER_PLAIN && o->solver <= INFOESRF_SOLVER_MULTISHIFT, INFOESRF_ERR_INVALID_ARG,
            "unknown solver");
   IE_CHECK(o->warm_start == INFOESRF_START_ZERO || o->warm_start == INFOESRF_START_LEARNED, INFOESRF_ERR_INVALID_ARG,
            "unknown warm_start");
@@ -571,6 +603,16 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   sy.nact = ar.take<int32_t>(2);  // list length, live count
   sy.act2 = ar.take<int32_t>(sy.Spad);
   sy.nact2 = ar.take<int32_t>(2);
+  if (op.solver == INFOESRF_SOLVER_MULTISHIFT) {
+    const int64_t nm = round_up(std::max<int64_t>(in.N, 1), kSysTile);
+    sy.zeta = ar.take<double>(sy.Spad);
+    sy.zeta_prev = ar.take<double>(sy.Spad);
+    sy.mrr = ar.take<double>(nm);
+    sy.malpha = ar.take<double>(nm);
+    sy.mbeta = ar.take<double>(nm);
+    sy.mit = ar.take<int32_t>(nm);
+  }
+  sy.app_adj = ar.take<int64_t>(1);
 
   Pre& pr = pl.pr;
   pr.k = op.k;
@@ -966,6 +1008,78 @@ LMP lmp_of(Plan& pl) {
   return l;
 }
 
+// Multi-shift CG for every member at once (the first sweep of a SOLVER_MULTISHIFT perturbation
+// solve): d_s for all systems s = q N + i into sy.x, from the residuals r = b of the base
+// systems.  One apply of S per live member per iteration, the same polling as the PCG loop.
+int msc_solve(Plan& pl, const Options& op, hipStream_t st) {
+  Inst& in = pl.in;
+  Sys& sy = pl.sy;
+  const int64_t N = in.N;
+  const bool od = in.odom();
+  double* Vbuf = od ? static_cast<double*>(pl.bf.V) : nullptr;
+  const int64_t ldr = ld64(od ? in.m : in.n);
+  MscState ms{};
+  ms.m = in.m;
+  ms.ld = sy.ldm;
+  ms.N = N;
+  ms.Q = (int)(sy.S / N);
+  ms.q0 = op.msc_q0;
+  ms.x = sy.x;
+  ms.r = sy.r;
+  ms.p = sy.p;
+  ms.sigma = sy.sigma;
+  ms.bnorm = sy.bnorm;
+  ms.thresh = sy.thresh;
+  ms.zeta = sy.zeta;
+  ms.zeta_prev = sy.zeta_prev;
+  ms.rr = sy.mrr;
+  ms.alpha_prev = sy.malpha;
+  ms.beta_prev = sy.mbeta;
+  ms.mit = sy.mit;
+  ms.relres = sy.rel_in;
+  ms.iters = sy.iters;
+  ms.done = sy.done;
+  ms.flags = in.flags;
+  ms.max_iter = op.max_iter;
+  const infoesrf_problem* P = in.P;
+  int32_t *act_c = sy.act, *nact_c = sy.nact, *act_n = sy.act2, *nact_n = sy.nact2;
+  IE_HIP(launch_msc_list(act_c, nact_c, op.msc_q0, N, st));
+  IE_HIP(launch_fill_i32(nact_n, 0, 2, st));
+  IE_HIP(launch_msc_step(ms, 0, od ? 1 : 0, nullptr, ldr, act_c, nact_c, act_n, nact_n, N, Vbuf, ldr, P->h_ptr,
+                         P->h_idx, P->h_w, P->r_var, in.n, st));
+  std::swap(act_c, act_n);
+  std::swap(nact_c, nact_n);
+  LivePoll poll;
+  if (op.host_sync) IE_TRY(poll.init());
+  int64_t hint = N;
+  const int check_every = 4;
+  for (int it = 1; it <= op.max_iter; ++it) {
+    const int64_t bp = round_up(hint, kSysTile);
+    IE_TRY(apply_S(pl, Prec::F64, sy.p, sy.ldm, act_c, nact_c, bp, sy.sigma, nullptr, op.rows_per_wave, st,
+                   /*v_ready=*/od, nact_n));
+    IE_HIP(launch_msc_step(ms, 1, od ? 1 : 0, static_cast<const double*>(pl.bf.T), ldr, act_c, nact_c, act_n, nact_n,
+                           bp, Vbuf, ldr, P->h_ptr, P->h_idx, P->h_w, P->r_var, in.n, st));
+    std::swap(act_c, act_n);
+    std::swap(nact_c, nact_n);
+    if (op.host_sync) {
+      int32_t seen = 0;
+      int got = poll.drain(&seen);
+      IE_TRY(got);
+      if (!got && (it % check_every) == 0) {
+        got = poll.post(nact_c, st, &seen);
+        IE_TRY(got);
+      }
+      if (got) {
+        if (seen == 0) break;
+        hint = seen;
+      }
+    }
+  }
+  hipLaunchKernelGGL(k_msc_adjust, dim3(1), dim3(256), 0, st, sy.iters, sy.S, sy.mit, N, sy.app_adj);
+  IE_HIP(hipGetLastError());
+  return 0;
+}
+
 // Iterative refinement around batched PCG.  Solves (1 + sigma_s) u_s + S u_s = b_s for all s.
 // Outer sweeps form the true residual r = b - C u in FP64; the inner PCG (apply precision
 // op.inner) solves C d = r to the per-system target and u += d.  One inner iteration is two
@@ -1001,6 +1115,9 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   IE_HIP(launch_fill_i32(sy.iters, 0, sy.Spad, st));
   IE_HIP(launch_fill_i32(sy.sweeps, 0, sy.Spad, st));
   IE_HIP(launch_fill_i32(sy.fdone, 0, sy.Spad, st));
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, sy.app_adj, (int64_t)0, (int64_t)1);
+  IE_HIP(hipGetLastError());
+  const bool msc = op.msc_q0 >= 0 && !warm;
 
   // a fixed iteration count is one FP64 inner solve: the status pass after it finishes every system
   const int max_sweeps =
@@ -1036,8 +1153,13 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
       if (h_nact == 0) break;
     }
     if (sweep == max_sweeps) break;
-    // inner PCG on C d = r from d = 0
+    // inner solve on C d = r from d = 0: the multi-shift process first when asked, else PCG
     IE_HIP(launch_fill_f64(sy.x, 0.0, flat, st));
+    if (msc && sweep == 0) {
+      IE_TRY(msc_solve(pl, op, st));
+      IE_HIP(launch_axpy(sy.u, sy.x, flat, st));
+      continue;
+    }
     int32_t *act_c = sy.act, *nact_c = sy.nact, *act_n = sy.act2, *nact_n = sy.nact2;
     int64_t hint = plain ? S : (int64_t)h_nact;  // upper bound of the live count on the device
     IE_HIP(launch_fill_i32(nact_n, 0, 2, st));
@@ -1083,7 +1205,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
 int finish_status(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t extra_fp64, hipStream_t st) {
   Sys& sy = pl.sy;
   hipLaunchKernelGGL(k_finish_counters, dim3(1), dim3(256), 0, st, sy.iters, sy.sweeps, sy.fdone, sy.S, extra_fp64,
-                     op.inner == Prec::F64 ? 1 : 0, op.fixed > 0 ? 1 : 0, pl.in.flags, pl.in.fallbacks,
+                     sy.app_adj, op.inner == Prec::F64 ? 1 : 0, op.fixed > 0 ? 1 : 0, pl.in.flags, pl.in.fallbacks,
                      pl.in.counters);
   IE_HIP(hipGetLastError());
   if (stats) {
@@ -1249,6 +1371,16 @@ int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_
   const int64_t N = prob->N;
   const int64_t S = (int64_t)Q * N;
   (void)y;  // the observations do not enter the shifted systems' solutions
+  if (op.solver == INFOESRF_SOLVER_MULTISHIFT) {
+    // the base is the smallest node (the worst conditioned system, which converges last); the
+    // process has no preconditioner, and later correction sweeps use plain PCG
+    int q0 = 0;
+    for (int q = 1; q < Q; ++q)
+      if (nd.s[q] < nd.s[q0]) q0 = q;
+    op.msc_q0 = q0;
+    op.p = 0;
+    op.k = 0;
+  }
   IE_TRY(plan_for(pl, prob, op, S, N, ws, ws_bytes));
   IE_TRY(check_nnz(prob, op, st));
   IE_TRY(stage_setup(pl, op, st));

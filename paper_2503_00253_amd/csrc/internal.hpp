@@ -235,6 +235,31 @@ struct PCGState {
 // Rounds Phi and SPhi (m x p, column-major, ld) to FP32 in place and writes the FP32 copies.
 hipError_t launch_round_ritz(double* Phi, double* SPhi, int64_t m, int p, int64_t ld, float* Phi32, float* SPhi32,
                              hipStream_t st);
+// Multi-shift CG state (systems s = q N + i, system-major columns of ld; per-member scalars).
+struct MscState {
+  int64_t m, ld, N;
+  int Q, q0;                     // nodes and the base (smallest) node
+  double *x, *r, *p;             // every system's iterate and direction; r of the base systems
+  const double* sigma;           // per system node s_q
+  const double* bnorm;           // per system ||b||
+  const double* thresh;          // per system absolute residual target
+  double *zeta, *zeta_prev;      // per system residual ratios to the base residual
+  double *rr, *alpha_prev, *beta_prev;  // per member base CG scalars
+  int32_t* mit;                  // per member iterations taken
+  double* relres;                // per system recursive relative residual
+  int32_t* iters;                // per system iterations
+  int32_t* done;                 // per system: 0 live, 1 converged, 2 capped or failed
+  int32_t* flags;
+  int max_iter;
+};
+hipError_t launch_msc_list(int32_t* act, int32_t* nact, int64_t q0, int64_t N, hipStream_t st);
+// One multi-shift iteration for every member in the list (mode 0 starts), after the apply of S to
+// the base directions (T, slot-major).  Live members are appended to act_out (*nact_out zeroed
+// beforehand) with their next base direction in V (observation domain, nullable).  m <= 4096.
+hipError_t launch_msc_step(const MscState& s, int mode, int obs_domain, const double* T, int64_t ldt,
+                           const int32_t* act, const int32_t* nact, int32_t* act_out, int32_t* nact_out, int64_t Bmax,
+                           double* V, int64_t ldv, const int32_t* h_ptr, const int32_t* h_idx, const double* h_w,
+                           const double* r_var, int64_t n_state, hipStream_t st);
 hipError_t launch_pcg_fused(Prec prec, const PCGState& s, const LMP& lmp, int mode, int obs_domain, int plain,
                             const void* T, int64_t ldt, const int32_t* act, const int32_t* nact, int32_t* act_out,
                             int32_t* nact_out, int64_t Bmax, void* V, int64_t ldv, const int32_t* h_ptr,

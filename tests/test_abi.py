@@ -105,7 +105,8 @@ def test_option_and_node_validation():
     for kw in (dict(rtol=0.0), dict(max_iter=0), dict(n_ritz=7), dict(precision=9), dict(tile_rows=48),
                dict(cov_form=5), dict(cov_form=ie.COV_BAND, precision=ie.MIXED_BF16), dict(warm_start=1),
                dict(warm_start=3), dict(fixed_iters=-1), dict(fixed_iters=2, precision=ie.MIXED_FP32), dict(s_form=3),
-               dict(s_form=ie.S_DENSE, precision=ie.MIXED_BF16)):
+               dict(s_form=ie.S_DENSE, precision=ie.MIXED_BF16), dict(solver=5),
+               dict(solver=ie.SOLVER_MULTISHIFT, precision=ie.MIXED_FP32)):
         o = ie.default_opts(**kw)
         assert lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(o)) == 0
     assert lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(ie.default_opts(fixed_iters=2))) > 0
