@@ -31,7 +31,7 @@ DTYPE = {0: "f64", 1: "f32/f64", 2: "bf16/f64"}
 SLOTS = {0: ("k_cov_stencil<fp64>", "mfma", 0), 1: ("k_cov_stencil<fp32>", "mfma", 1),
          2: ("k_cov_bf16", "mfma", 2), 3: ("k_band_apply<fp64>", "hbm", None),
          4: ("k_band_apply<fp32>", "hbm", None), 5: ("k_pcg_fused", "hbm", None)}
-SOLVERS = {"plain": 0, "compact": 1, "multishift": 3}
+SOLVERS = {"plain": 0, "compact": 1, "multishift": 3, "block": 4}
 SRC = {0: "cov_apply.hip", 1: "cov_apply.hip", 2: "cov_apply.hip", 3: "band.hip", 4: "band.hip", 5: "pcg.hip"}
 
 
@@ -42,10 +42,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64")
     ap.add_argument("--domain", choices=["state", "lattice"], default="lattice")
-    ap.add_argument("--solver", choices=["plain", "compact", "multishift"], default="compact",
+    ap.add_argument("--solver", choices=["plain", "compact", "multishift", "block"], default="compact",
                     help="compact: batched PCG with the limited-memory preconditioner (default); plain: the "
                          "same with converged systems masked; multishift: one unpreconditioned CG process "
-                         "per member serving every node")
+                         "per member serving every node; block: one block PCG per node over the members")
     ap.add_argument("--form", choices=["auto", "operator", "band"], default="auto",
                     help="covariance form: explicit band of P, or the operator form sum_i z_i o L(z_i o v)")
     ap.add_argument("--plain-steps", type=int, default=3)
@@ -259,7 +259,7 @@ def bench_cycle(a, prec):
         run = CycleRunner(prob, noise=noise)
         kw = dict(precision=prec, apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=run.P.lattice(), cov_form=form,
                   solver=SOLVERS[a.solver])
-        run.opts = ie.default_opts(**kw)
+        run.set_opts(ie.default_opts(**kw))
         name = "lorenz96-8x480-N20-m1280-Q12-cycle"
         metric = "shifted SPD solves/s at rel-res 1e-8"
     for _ in range(a.warmup):
@@ -270,7 +270,7 @@ def bench_cycle(a, prec):
         # without host synchronization every launch of the iteration loop is in the graph: cap the
         # loop at twice the largest count the eager warm-up cycles needed
         most = int(max(run.stats()[1].iters.max(), run.stats()[0].iters.max()))
-        run.opts = ie.default_opts(host_sync=0, max_iter=2 * most + 4, **kw)
+        run.set_opts(ie.default_opts(host_sync=0, max_iter=2 * most + 4, **kw))
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         saved = run.state.clone()

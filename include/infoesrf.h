@@ -101,6 +101,12 @@ extern "C" {
  * preconditioner (n_ritz is used by the mean update only); FP64 and the zero start only.  FP64
  * residual sweeps then check every (q, i) system and correct any above rtol with PCG. */
 #define INFOESRF_SOLVER_MULTISHIFT 3
+/* BLOCK (perturbation update; the second alternative of Sec. 3.2): for each node one block PCG
+ * (O'Leary) over the N members' systems, with the node's limited-memory preconditioner: every
+ * member's iterate is optimal over the sum of all members' Krylov spaces, so the block needs
+ * fewer iterations than its slowest member alone, at the cost of N x N products per iteration.
+ * FP64, zero start, N <= 64; FP64 residual sweeps then check and correct as for MULTISHIFT. */
+#define INFOESRF_SOLVER_BLOCK 4
 
 /* ---- where the normalized covariance S is applied ----------------------- */
 #define INFOESRF_DOMAIN_STATE 0       /* general H: scatter to state space, apply P, gather */

@@ -288,6 +288,7 @@ struct Options {
   bool band;  // covariance applies through the explicit band of P
   int sform;  // INFOESRF_S_*: requested form of S
   int msc_q0 = -1;  // multi-shift perturbation solve: the base node (-1: not used)
+  int bcg_Q = 0;    // block perturbation solve: number of nodes (0: not used)
 };
 
 struct Inst {
@@ -336,6 +337,9 @@ struct Sys {
   double *zeta = nullptr, *zeta_prev = nullptr, *mrr = nullptr, *malpha = nullptr, *mbeta = nullptr;
   int32_t* mit = nullptr;
   int64_t* app_adj = nullptr;  // applies counter correction: member iterations replace system iterations
+  // block PCG (SOLVER_BLOCK): W = C P, partial and reduced products, coefficients, node states
+  double *bw = nullptr, *bpart = nullptr, *bred = nullptr, *bcoef = nullptr;
+  int32_t* bdone = nullptr;
 };
 
 struct Pre {
@@ -420,7 +424,10 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   IE_CHECK(o->solver != INFOESRF_SOLVER_MULTISHIFT ||
                (o->precision == INFOESRF_FP64 && o->warm_start == INFOESRF_START_ZERO),
            INFOESRF_ERR_INVALID_ARG, "the multi-shift solver needs precision FP64 and the zero start");
-  IE_CHECK(o->solver >= INFOESRF_SOLVER_PLAIN && o->solver <= INFOESRF_SOLVER_MULTISHIFT, INFOESRF_ERR_INVALID_ARG,
+  IE_CHECK(o->solver != INFOESRF_SOLVER_BLOCK ||
+               (o->precision == INFOESRF_FP64 && o->warm_start == INFOESRF_START_ZERO && P->N <= 64),
+           INFOESRF_ERR_INVALID_ARG, "the block solver needs precision FP64, the zero start and N <= 64");
+  IE_CHECK(o->solver >= INFOESRF_SOLVER_PLAIN && o->solver <= INFOESRF_SOLVER_BLOCK, INFOESRF_ERR_INVALID_ARG,
            "unknown solver");
   IE_CHECK(o->warm_start == INFOESRF_START_ZERO || o->warm_start == INFOESRF_START_LEARNED, INFOESRF_ERR_INVALID_ARG,
            "unknown warm_start");
@@ -613,6 +620,14 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
     sy.mit = ar.take<int32_t>(nm);
   }
   sy.app_adj = ar.take<int64_t>(1);
+  if (op.solver == INFOESRF_SOLVER_BLOCK && S > 1 && S % in.N == 0) {
+    const int Qb = (int)(S / in.N);
+    sy.bw = ar.take<double>(ms);
+    sy.bpart = ar.take<double>(bcg_partial_doubles(in.m, in.N, op.p, Qb));
+    sy.bred = ar.take<double>(bcg_reduced_doubles(in.N, op.p, Qb));
+    sy.bcoef = ar.take<double>(bcg_coef_doubles(in.N, op.p, Qb));
+    sy.bdone = ar.take<int32_t>(Qb);
+  }
 
   Pre& pr = pl.pr;
   pr.k = op.k;
@@ -1080,6 +1095,72 @@ int msc_solve(Plan& pl, const Options& op, hipStream_t st) {
   return 0;
 }
 
+// Block PCG for every node at once (the first sweep of a SOLVER_BLOCK perturbation solve): d_s
+// for all systems into sy.x from r = b.  Iteration 0 forms P = M R; every later iteration applies
+// C to the live nodes' blocks and updates them.
+int bcg_solve_all(Plan& pl, const Options& op, hipStream_t st) {
+  Inst& in = pl.in;
+  Sys& sy = pl.sy;
+  const LMP lmp = lmp_of(pl);
+  IE_CHECK(sy.bw && sy.bdone, INFOESRF_ERR_HIP, "internal: block solver buffers not allocated");
+  BcgState bs{};
+  bs.m = in.m;
+  bs.ld = sy.ldm;
+  bs.N = in.N;
+  bs.Q = op.bcg_Q;
+  bs.p = lmp.p;
+  bs.X = sy.x;
+  bs.R = sy.r;
+  bs.P = sy.p;
+  bs.W = sy.bw;
+  bs.Phi = lmp.Phi;
+  bs.SPhi = lmp.SPhi;
+  bs.ldphi = lmp.ld;
+  bs.G = lmp.G;
+  bs.theta = lmp.theta;
+  bs.dmin = lmp.dmin;
+  bs.sigma = sy.sigma;
+  bs.thresh = sy.thresh;
+  bs.bnorm = sy.bnorm;
+  bs.part = sy.bpart;
+  bs.nch = bcg_chunks(in.m);
+  bs.red = sy.bred;
+  bs.coef = sy.bcoef;
+  bs.bdone = sy.bdone;
+  bs.iters = sy.iters;
+  bs.relres = sy.rel_in;
+  bs.done = sy.done;
+  bs.flags = in.flags;
+  bs.max_iter = op.max_iter;
+  IE_HIP(launch_fill_i32(sy.bdone, 0, bs.Q, st));
+  IE_HIP(launch_bcg_iteration(bs, 0, 0, st));
+  LivePoll poll;
+  if (op.host_sync) IE_TRY(poll.init());
+  int64_t hint = sy.S;
+  const int check_every = 2;
+  for (int it = 1; it <= op.max_iter + 1; ++it) {
+    IE_HIP(launch_bcg_list(sy.bdone, bs.Q, in.N, sy.act, sy.nact, st));
+    const int64_t bp = round_up(hint, kSysTile);
+    IE_TRY(apply_S(pl, Prec::F64, sy.p, sy.ldm, sy.act, sy.nact, bp, sy.sigma, sy.bw, op.rows_per_wave, st));
+    IE_HIP(launch_bcg_iteration(bs, 1, it, st));
+    if (op.host_sync) {
+      int32_t seen = 0;
+      int got = poll.drain(&seen);
+      IE_TRY(got);
+      if (!got && (it % check_every) == 0) {
+        IE_HIP(launch_bcg_list(sy.bdone, bs.Q, in.N, sy.act2, sy.nact2, st));
+        got = poll.post(sy.nact2, st, &seen);
+        IE_TRY(got);
+      }
+      if (got) {
+        if (seen == 0) break;
+        hint = seen;
+      }
+    }
+  }
+  return 0;
+}
+
 // Iterative refinement around batched PCG.  Solves (1 + sigma_s) u_s + S u_s = b_s for all s.
 // Outer sweeps form the true residual r = b - C u in FP64; the inner PCG (apply precision
 // op.inner) solves C d = r to the per-system target and u += d.  One inner iteration is two
@@ -1118,6 +1199,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, sy.app_adj, (int64_t)0, (int64_t)1);
   IE_HIP(hipGetLastError());
   const bool msc = op.msc_q0 >= 0 && !warm;
+  const bool bcg = op.bcg_Q > 0 && !warm;
 
   // a fixed iteration count is one FP64 inner solve: the status pass after it finishes every system
   const int max_sweeps =
@@ -1155,8 +1237,9 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
     if (sweep == max_sweeps) break;
     // inner solve on C d = r from d = 0: the multi-shift process first when asked, else PCG
     IE_HIP(launch_fill_f64(sy.x, 0.0, flat, st));
-    if (msc && sweep == 0) {
-      IE_TRY(msc_solve(pl, op, st));
+    if ((msc || bcg) && sweep == 0) {
+      if (msc) IE_TRY(msc_solve(pl, op, st));
+      else IE_TRY(bcg_solve_all(pl, op, st));
       IE_HIP(launch_axpy(sy.u, sy.x, flat, st));
       continue;
     }
@@ -1381,6 +1464,7 @@ int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_
     op.p = 0;
     op.k = 0;
   }
+  if (op.solver == INFOESRF_SOLVER_BLOCK) op.bcg_Q = Q;
   IE_TRY(plan_for(pl, prob, op, S, N, ws, ws_bytes));
   IE_TRY(check_nnz(prob, op, st));
   IE_TRY(stage_setup(pl, op, st));

@@ -260,6 +260,41 @@ hipError_t launch_msc_step(const MscState& s, int mode, int obs_domain, const do
                            const int32_t* act, const int32_t* nact, int32_t* act_out, int32_t* nact_out, int64_t Bmax,
                            double* V, int64_t ldv, const int32_t* h_ptr, const int32_t* h_idx, const double* h_w,
                            const double* r_var, int64_t n_state, hipStream_t st);
+// Block PCG state: node q's block is the N system-major columns q N .. q N + N - 1 (ld).
+struct BcgState {
+  int64_t m, ld, N;
+  int Q, p;                      // nodes, Ritz pairs of the preconditioner
+  double *X, *R, *P, *W;         // iterate, residual, search block, W = C P
+  const double *Phi, *SPhi;      // m x p Ritz vectors (FP32-exact values), ld = ldphi
+  int64_t ldphi;
+  const double* G;               // the preconditioner's Gram blocks (3 p x p, row-major)
+  const double* theta;           // Ritz values of S
+  const double* dmin;            // min diag(S)
+  const double* sigma;           // per system node s_q
+  const double* thresh;          // per system absolute residual target
+  const double* bnorm;           // per system ||b||
+  double* part;                  // per node and 128-row chunk: partial products
+  int nch;                       // chunks
+  double* red;                   // per node: reduced products
+  double* coef;                  // per node: A, B, c1, gamma
+  int32_t* bdone;                // per node: 0 iterating, 1 converged, 2 capped
+  int32_t* iters;
+  double* relres;
+  int32_t* done;
+  int32_t* flags;
+  int max_iter;
+};
+// Sizes (doubles) of the block solver's buffers for m rows, N members, p Ritz pairs, Q nodes.
+int64_t bcg_partial_doubles(int64_t m, int64_t N, int p, int Q);
+int64_t bcg_reduced_doubles(int64_t N, int p, int Q);
+int64_t bcg_coef_doubles(int64_t N, int p, int Q);
+int bcg_chunks(int64_t m);
+// One block-PCG iteration for every live node (mode 0: the start, P = M R; mode 1: iteration
+// `it` after W = C P): partial products, their reduction, the per-node small solves and the
+// row-wise update.  N <= 64, p <= 20.
+hipError_t launch_bcg_iteration(const BcgState& s, int mode, int it, hipStream_t st);
+// act = systems of the live nodes (node-major), *nact their number.
+hipError_t launch_bcg_list(const int32_t* bdone, int Q, int64_t N, int32_t* act, int32_t* nact, hipStream_t st);
 hipError_t launch_pcg_fused(Prec prec, const PCGState& s, const LMP& lmp, int mode, int obs_domain, int plain,
                             const void* T, int64_t ldt, const int32_t* act, const int32_t* nact, int32_t* act_out,
                             int32_t* nact_out, int64_t Bmax, void* V, int64_t ldv, const int32_t* h_ptr,

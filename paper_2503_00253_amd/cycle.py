@@ -48,19 +48,27 @@ class CycleRunner:
         kw = {}
         if lattice and self.P.lattice() is not None:
             kw.update(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=self.P.lattice())
-        self.opts = opts if opts is not None else ie.default_opts(**kw)
         self.y = torch.empty(self.m, dtype=torch.float64, device=dev)
         self.noise_buf = torch.zeros(self.m, dtype=torch.float64, device=dev)
         self.noise = None if noise is None else torch.as_tensor(np.asarray(noise, dtype=np.float64)).to(dev)
         self.mean_a = torch.empty(self.n, dtype=torch.float64, device=dev)
         self.Xa = torch.empty((self.N, self.n), dtype=torch.float64, device=dev)
-        nbytes = max(ie.workspace_bytes(self.P, Q, self.opts), ie.workspace_bytes(self.P, 0, self.opts))
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.ws = None
+        self.set_opts(opts if opts is not None else ie.default_opts(**kw))
         self.sc_m, self.keep_m = ie._stats(1, dev)
         self.sc_p, self.keep_p = ie._stats(Q * self.N, dev)
         dp = C.POINTER(C.c_double)
         self._sp, self._pp = self.s.ctypes.data_as(dp), self.p.ctypes.data_as(dp)
         self.t = 0
+
+    def set_opts(self, opts):
+        """Options of the mean and perturbation updates; the workspace grows when they need more
+        (set options before capturing a cycle in a graph)."""
+        torch = ie._torch()
+        nbytes = max(ie.workspace_bytes(self.P, self.Q, opts), ie.workspace_bytes(self.P, 0, opts))
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.state.device)
+        self.opts = opts
 
     # --- the pieces of one cycle (each only enqueues library calls)
     def forecast(self):

@@ -20,7 +20,7 @@ OK, WARN_NOT_CONVERGED = 0, 1
 ERR_INVALID_ARG, ERR_NOT_SPD, ERR_NUMERIC, ERR_WORKSPACE, ERR_HIP = -1, -2, -3, -4, -5
 LOC_DENSE, LOC_STENCIL = 0, 1
 FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
-SOLVER_PLAIN, SOLVER_COMPACT, SOLVER_PERSISTENT, SOLVER_MULTISHIFT = 0, 1, 2, 3
+SOLVER_PLAIN, SOLVER_COMPACT, SOLVER_PERSISTENT, SOLVER_MULTISHIFT, SOLVER_BLOCK = 0, 1, 2, 3, 4
 DOMAIN_STATE, DOMAIN_OBS_LATTICE = 0, 1
 START_ZERO, START_LEARNED = 0, 1
 COV_AUTO, COV_OPERATOR, COV_BAND = 0, 1, 2

@@ -106,10 +106,17 @@ def test_option_and_node_validation():
                dict(cov_form=5), dict(cov_form=ie.COV_BAND, precision=ie.MIXED_BF16), dict(warm_start=1),
                dict(warm_start=3), dict(fixed_iters=-1), dict(fixed_iters=2, precision=ie.MIXED_FP32), dict(s_form=3),
                dict(s_form=ie.S_DENSE, precision=ie.MIXED_BF16), dict(solver=5),
-               dict(solver=ie.SOLVER_MULTISHIFT, precision=ie.MIXED_FP32)):
+               dict(solver=ie.SOLVER_MULTISHIFT, precision=ie.MIXED_FP32),
+               dict(solver=ie.SOLVER_BLOCK, precision=ie.MIXED_FP32)):
         o = ie.default_opts(**kw)
         assert lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(o)) == 0
     assert lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(ie.default_opts(fixed_iters=2))) > 0
+    # the block solver holds at most 64 members per block
+    wide = fake_problem(N=65)
+    assert lib.infoesrf_workspace_bytes(C.byref(wide), 4, C.byref(ie.default_opts(solver=ie.SOLVER_BLOCK))) == 0
+    assert "N <= 64" in lib.infoesrf_last_error().decode()
+    assert lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(ie.default_opts(solver=ie.SOLVER_BLOCK))) > \
+        lib.infoesrf_workspace_bytes(C.byref(p), 4, C.byref(ie.default_opts()))
     o = ie.default_opts()
     assert lib.infoesrf_perturbation_update(C.byref(p), 0, s.ctypes.data_as(dp), s.ctypes.data_as(dp), None,
                                             C.c_void_p(0x1000), C.byref(o), None, C.c_void_p(0x1000), 1 << 30,

@@ -124,14 +124,14 @@ def test_graph_captured_cycle_matches_eager():
     eager = CycleRunner(prob, Q=6, noise=noise)
     P = eager.P
     lat = P.lattice()
-    eager.opts = ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=lat, **kw)
+    eager.set_opts(ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=lat, **kw))
     for _ in range(3):
         eager.step()
     torch.cuda.synchronize()
     want = eager.state.clone()
 
     g_run = CycleRunner(prob, Q=6, noise=noise)
-    g_run.opts = ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=lat, **kw)
+    g_run.set_opts(ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=lat, **kw))
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     # one eager warm-up cycle on a copy of the state sets kernel attributes before capture
