@@ -50,6 +50,8 @@ def parse():
                     help="covariance form: explicit band of P, or the operator form sum_i z_i o L(z_i o v)")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip timing Sec. 3.2's two alternatives (block PCG, multi-shift CG) beside the line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-members", type=int, default=1)
     ap.add_argument("--workload", choices=["n4096", "batched64", "lorenz-cycle", "paper-sec5-cycle"],
@@ -190,6 +192,29 @@ def main():
            "iterations": {"total": int(st.iters.sum()), "max": int(st.iters.max()),
                           "fp64_sweeps": st.counter(ie.CNT_SWEEPS)},
            "roofline": roof}
+
+    if not a.no_compare and a.solver == "compact":
+        # Sec. 3.2's alternatives on the same workload and options, to the same true FP64 residual
+        comp = {}
+        for name in ("block", "multishift"):
+            okw = dict(kw, solver=SOLVERS[name])
+            if name == "multishift":
+                okw.pop("n_ritz", None)
+            arun = ie.PerturbationRunner(P, s, p, ie.default_opts(**okw))
+            arun.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                acode = arun.run()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ast = arun.stats(acode)
+            assert ast.counter(ie.CNT_NOT_CONVERGED) == 0, f"{name}: systems missed rtol"
+            diff = float((arun.result() - run.result()).norm() / run.result().norm())
+            comp[name] = {"value": round(systems * 3 / (t1 - t0), 2), "ms_per_step": round((t1 - t0) * 1e3 / 3, 4),
+                          "max_iterations": int(ast.iters.max()), "rel_diff_vs_line": diff}
+            log("alternative", name, comp[name])
+        out["solver_comparison"] = comp
 
     if not a.no_plain:
         # the plain baseline: FP64 operator-form applies in the state space, masked systems

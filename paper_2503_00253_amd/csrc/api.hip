@@ -649,7 +649,7 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
     pr.SPhi32 = ar.take<float>(sy.ldm * op.p);
     pr.theta = ar.take<double>(op.p);
     pr.G = ar.take<double>(3 * op.p * op.p);
-    pr.gscr = ar.take<double>(((in.m + 127) / 128) * op.k * op.k);
+    pr.gscr = ar.take<double>((int64_t)gram_chunks(in.m) * op.k * op.k);
     pr.sig = ar.take<double>(kl);
     pr.act = ar.take<int32_t>(kl);
     pr.nact = ar.take<int32_t>(1);

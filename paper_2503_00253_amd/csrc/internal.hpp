@@ -347,6 +347,7 @@ struct Strided {
 hipError_t launch_sketch(uint64_t seed, int64_t m, int k, double* out, int64_t ld, hipStream_t st);
 // Gram: G[a*k+b] = sum_r A(r, a) B(r, b), a,b < k (fixed order, deterministic)
 hipError_t launch_gram(Strided A, Strided B, int64_t m, int k, double* G, double* scratch, hipStream_t st);
+int gram_chunks(int64_t m);  // row chunks of launch_gram: scratch holds gram_chunks(m) * k * k doubles
 // One-workgroup small dense kernels.
 hipError_t launch_chol_inv(double* G, int k, int32_t* flags, hipStream_t st);   // G <- R^{-1} (upper), G = R^T R
 // out(r, j) = sum_a A(r, a) M[a*kout + j], out(r, j) at out[r*ors + j*ocs]

@@ -49,15 +49,31 @@ __global__ void k_sketch(uint64_t seed, int64_t m, int k, double* __restrict__ o
   out[j * ld + r] = g;
 }
 
-// partial Gram over a row chunk: scratch[chunk][a*k+b]
-__global__ void k_gram_partial(Strided A, Strided B, int64_t m, int k, int chunk_rows, double* __restrict__ scratch) {
-  const int64_t r0 = blockIdx.x * (int64_t)chunk_rows;
-  const int64_t r1 = min<int64_t>(m, r0 + chunk_rows);
+// partial Gram over a chunk of kGramChunk rows: scratch[chunk][a*k+b].  The chunk's rows of A and
+// B are staged in LDS first (unit-stride reads along each column), then each thread sums its
+// entries from LDS.
+constexpr int kGramChunk = 32;
+__global__ __launch_bounds__(256) void k_gram_partial(Strided A, Strided B, int64_t m, int k,
+                                                      double* __restrict__ scratch) {
+  __shared__ double sa[kMaxSketch][kGramChunk + 1];
+  __shared__ double sb[kMaxSketch][kGramChunk + 1];
+  const int64_t r0 = blockIdx.x * (int64_t)kGramChunk;
+  const int rows = (int)min<int64_t>(kGramChunk, m - r0);
+  for (int o = threadIdx.x; o < k * kGramChunk; o += blockDim.x) {
+    const int a = o / kGramChunk, r = o % kGramChunk;
+    const bool ok = r < rows;
+    sa[a][r] = ok ? A.ptr[(r0 + r) * A.rs + a * A.cs] : 0.0;
+    sb[a][r] = ok ? B.ptr[(r0 + r) * B.rs + a * B.cs] : 0.0;
+  }
+  __syncthreads();
   for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
     const int a = t / k, b = t % k;
-    double acc = 0.0;
-    for (int64_t r = r0; r < r1; ++r) acc += A.ptr[r * A.rs + a * A.cs] * B.ptr[r * B.rs + b * B.cs];
-    scratch[blockIdx.x * (int64_t)k * k + t] = acc;
+    double s0 = 0.0, s1 = 0.0;
+    for (int r = 0; r < kGramChunk; r += 2) {
+      s0 += sa[a][r] * sb[b][r];
+      s1 += sa[a][r + 1] * sb[b][r + 1];
+    }
+    scratch[blockIdx.x * (int64_t)k * k + t] = s0 + s1;
   }
 }
 
@@ -70,8 +86,10 @@ __global__ void k_gram_reduce(const double* __restrict__ scratch, int nchunks, i
 }
 
 // G (k x k, row-major, SPD) -> inverse of its upper Cholesky factor R (G = R^T R), in place.
+// One wavefront; the inverse's columns are built in LDS.
 __global__ void k_chol_inv(double* G, int k, int32_t* flags) {
   __shared__ double R[kMaxSketch * kMaxSketch];
+  __shared__ double X[kMaxSketch * kMaxSketch];
   __shared__ int bad;
   const int t = threadIdx.x;
   if (t == 0) bad = 0;
@@ -98,16 +116,17 @@ __global__ void k_chol_inv(double* G, int k, int32_t* flags) {
     }
     __syncthreads();
   }
-  // R is upper triangular in R[a*k+b], b >= a.  Invert by columns: Rinv[:, c] solves R x = e_c.
+  // R is upper triangular in R[a*k+b], b >= a.  Invert by columns: Rinv[:, c] solves R x = e_c
+  // (X[a*k + c] = x_a, written by the thread of column c only).
   for (int c = t; c < k; c += blockDim.x) {
-    double x[kMaxSketch];
     for (int a = k - 1; a >= 0; --a) {
       double s = (a == c) ? 1.0 : 0.0;
-      for (int b = a + 1; b < k; ++b) s -= R[a * k + b] * x[b];
-      x[a] = (a <= c) ? s / R[a * k + a] : 0.0;
+      for (int b = a + 1; b < k; ++b) s -= R[a * k + b] * X[b * k + c];
+      X[a * k + c] = (a <= c) ? s / R[a * k + a] : 0.0;
     }
-    for (int a = 0; a < k; ++a) G[a * k + c] = x[a];
   }
+  __syncthreads();
+  for (int e = t; e < k * k; e += blockDim.x) G[e] = X[e];
   if (t == 0 && bad) atomicOr(flags, kFlagNumeric);
 }
 
@@ -123,121 +142,151 @@ __global__ void k_right_mult(Strided A, int64_t m, int k, const double* __restri
   out[r * ors + j * ocs] = acc;
 }
 
-// Jacobi eigendecomposition of a small symmetric matrix on one workgroup with the
-// round-robin (tournament) ordering: each step rotates k/2 disjoint index pairs at
-// once, k-1 steps make a sweep in which every pair is visited once.
-// T (k x k row-major) is read; evec[a*k + j] = component a of eigenvector j.
-__global__ void k_sym_eig(double* T, int k, double* evec, double* evals) {
-  __shared__ double A[kMaxSketch * kMaxSketch];
+// Jacobi eigendecomposition of a small symmetric matrix on one workgroup with the round-robin
+// (tournament) ordering: each step rotates k/2 disjoint index pairs at once, k-1 steps make a
+// sweep in which every pair is visited once.  A step is two phases: the rotations of the pairs,
+// then, with A double-buffered, every thread's 2 x 2 blocks of the next A = J^T A J (one block
+// per pair of pairs) and its pair of eigenvector entries (V J, in place: each pair of entries
+// has one owner).  T (k x k row-major) is read;
+// evec[a*k + j] = component a of eigenvector j.
+__device__ inline void jacobi_player(int slot, int step, int ke, int k, int* p, int* q, int t) {
+  // players: slot 0 fixed, slots 1..ke-1 rotate by `step`; pair t holds slots t and ke-1-t
+  auto player = [&](int sl) { return sl == 0 ? 0 : 1 + (sl - 1 + step) % (ke - 1); };
+  int a = player(t), b = player(ke - 1 - t);
+  if (a > b) {
+    const int tmp = a;
+    a = b;
+    b = tmp;
+  }
+  *p = a;
+  *q = b;
+  (void)slot;
+  (void)k;
+}
+
+__device__ inline void jacobi_rot(const double* A, int k, int p, int q, double* c, double* sn) {
+  *c = 1.0;
+  *sn = 0.0;
+  if (q >= k) return;  // the dummy player of an odd k
+  const double apq = A[p * k + q];
+  if (apq == 0.0) return;
+  // the smaller root t of t^2 + 2 tau t - 1 = 0, tau = d / (2 a_pq), written as
+  // t = sign(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)): one square root and one division
+  const double d = A[q * k + q] - A[p * k + p];
+  const double a2 = 2.0 * apq;
+  const double tt = (d >= 0.0 ? a2 : -a2) / (fabs(d) + sqrt(d * d + a2 * a2));
+  *c = rsqrt(1.0 + tt * tt);
+  *sn = tt * *c;
+}
+
+__global__ __launch_bounds__(256) void k_sym_eig(double* T, int k, double* evec, double* evals) {
+  __shared__ double Ab[2][kMaxSketch * kMaxSketch];
   __shared__ double Vv[kMaxSketch * kMaxSketch];
   __shared__ double cs_c[kMaxSketch / 2], cs_s[kMaxSketch / 2];
   __shared__ int pp[kMaxSketch / 2], qq[kMaxSketch / 2];
-  __shared__ double red_off[256], red_dia[256];
+  __shared__ double red[2][4];
   const int t = threadIdx.x;
   const int ke = k + (k & 1);  // even number of players; index k (if odd) is a dummy
   const int half = ke / 2;
   for (int e = t; e < k * k; e += blockDim.x) {
-    A[e] = 0.5 * (T[e] + T[(e % k) * k + e / k]);
+    Ab[0][e] = 0.5 * (T[e] + T[(e % k) * k + e / k]);
     Vv[e] = (e / k == e % k) ? 1.0 : 0.0;
   }
   __syncthreads();
+  int cur = 0;
   for (int sweep = 0; sweep < 40; ++sweep) {
+    const double* A = Ab[cur];
     double off = 0.0, dia = 0.0;
     for (int e = t; e < k * k; e += blockDim.x) {
       const double v = A[e] * A[e];
       if (e / k == e % k) dia += v;
       else off += v;
     }
-    red_off[t] = off;
-    red_dia[t] = dia;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (t < w) {
-        red_off[t] += red_off[t + w];
-        red_dia[t] += red_dia[t + w];
-      }
-      __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      dia += __shfl_xor(dia, o, 64);
     }
-    const bool conv = red_off[0] <= 1e-30 * red_dia[0];
+    if ((t & 63) == 0) {
+      red[0][t >> 6] = off;
+      red[1][t >> 6] = dia;
+    }
     __syncthreads();
-    if (conv) break;
+    const double toff = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    const double tdia = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    __syncthreads();
+    // relative off-diagonal norm 1e-10: the Ritz vectors are rounded to FP32 afterwards
+    if (toff <= 1e-20 * tdia) break;
     for (int step = 0; step < ke - 1; ++step) {
+      const double* Ac = Ab[cur];
+      double* An = Ab[cur ^ 1];
       if (t < half) {
-        // players: slot 0 fixed, slots 1..ke-1 rotate by `step`
-        auto player = [&](int slot) { return slot == 0 ? 0 : 1 + (slot - 1 + step) % (ke - 1); };
-        int p = player(t), q = player(ke - 1 - t);
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        double c = 1.0, sn = 0.0;
-        if (q < k) {
-          const double apq = A[p * k + q];
-          if (apq != 0.0) {
-            const double tau = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
-            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            sn = tt * c;
-          }
-        }
+        int p, q;
+        jacobi_player(0, step, ke, k, &p, &q, t);
+        double c, sn;
+        jacobi_rot(Ac, k, p, q, &c, &sn);
         pp[t] = p;
-        qq[t] = (q < k) ? q : p;
+        qq[t] = q;
         cs_c[t] = c;
-        cs_s[t] = (q < k) ? sn : 0.0;
+        cs_s[t] = sn;
       }
       __syncthreads();
-      // rows p, q of every pair
-      for (int e = t; e < half * k; e += blockDim.x) {
-        const int i = e / k, j = e % k;
+      // 2 x 2 blocks of J^T A J: pairs (i1, i2), one block per thread
+      for (int w = t; w < half * half; w += blockDim.x) {
+        const int i1 = w / half, i2 = w % half;
+        const int p1 = pp[i1], q1 = qq[i1], p2 = pp[i2], q2 = qq[i2];
+        const double c1 = cs_c[i1], s1 = cs_s[i1], c2 = cs_c[i2], s2 = cs_s[i2];
+        const bool r1 = q1 < k, r2 = q2 < k;  // a dummy index has no row or column
+        const double app = Ac[p1 * k + p2];
+        const double apq = r2 ? Ac[p1 * k + q2] : 0.0;
+        const double aqp = r1 ? Ac[q1 * k + p2] : 0.0;
+        const double aqq = (r1 && r2) ? Ac[q1 * k + q2] : 0.0;
+        // rows: [p1; q1] <- [c1 -s1; s1 c1] [p1; q1], then columns likewise with (c2, s2)
+        const double xp = c1 * app - s1 * aqp, xq = s1 * app + c1 * aqp;  // column p2
+        const double yp = c1 * apq - s1 * aqq, yq = s1 * apq + c1 * aqq;  // column q2
+        An[p1 * k + p2] = c2 * xp - s2 * yp;
+        if (r2) An[p1 * k + q2] = s2 * xp + c2 * yp;
+        if (r1) An[q1 * k + p2] = c2 * xq - s2 * yq;
+        if (r1 && r2) An[q1 * k + q2] = s2 * xq + c2 * yq;
+      }
+      // eigenvector columns p, q of every pair: row j, pair i, one owner each
+      for (int w = t; w < half * k; w += blockDim.x) {
+        const int i = w / k, j = w % k;
         const double sn = cs_s[i];
         if (sn == 0.0) continue;
-        const int p = pp[i], q = qq[i];
+        const int pq = pp[i], q2 = qq[i];
         const double c = cs_c[i];
-        const double ap = A[p * k + j], aq = A[q * k + j];
-        A[p * k + j] = c * ap - sn * aq;
-        A[q * k + j] = sn * ap + c * aq;
+        const double vp = Vv[j * k + pq], vq = Vv[j * k + q2];
+        Vv[j * k + pq] = c * vp - sn * vq;
+        Vv[j * k + q2] = sn * vp + c * vq;
       }
       __syncthreads();
-      // columns p, q of every pair, and the eigenvector columns
-      for (int e = t; e < half * k; e += blockDim.x) {
-        const int i = e / k, j = e % k;
-        const double sn = cs_s[i];
-        if (sn == 0.0) continue;
-        const int p = pp[i], q = qq[i];
-        const double c = cs_c[i];
-        const double ap = A[j * k + p], aq = A[j * k + q];
-        A[j * k + p] = c * ap - sn * aq;
-        A[j * k + q] = sn * ap + c * aq;
-        const double vp = Vv[j * k + p], vq = Vv[j * k + q];
-        Vv[j * k + p] = c * vp - sn * vq;
-        Vv[j * k + q] = sn * vp + c * vq;
-      }
-      __syncthreads();
+      cur ^= 1;
     }
   }
+  const double* A = Ab[cur];
   for (int e = t; e < k * k; e += blockDim.x) evec[e] = Vv[e];
   for (int j = t; j < k; j += blockDim.x) evals[j] = A[j * k + j];
 }
 
 // Select the p largest eigenvalues: theta[j], and the selection/rotation matrix
-// sel (k x p, row-major) whose column j is the eigenvector of the j-th largest.
+// sel (k x p, row-major) whose column j is the eigenvector of the j-th largest.  Lane i finds
+// the rank of eigenvalue i (descending; ties by index, as a stable sort orders them).
 __global__ void k_lmp_finish(const double* evals, const double* evec, int k, int p, double* theta, double* sel) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int order[kMaxSketch];
-  for (int j = 0; j < k; ++j) order[j] = j;
-  for (int a = 1; a < k; ++a) {  // insertion sort, descending, stable
-    const int v = order[a];
-    int b = a - 1;
-    while (b >= 0 && evals[order[b]] < evals[v]) {
-      order[b + 1] = order[b];
-      --b;
-    }
-    order[b + 1] = v;
+  __shared__ int order[kMaxSketch];
+  __shared__ double ev[kMaxSketch];
+  const int t = threadIdx.x;
+  if (t < k) ev[t] = evals[t];
+  __syncthreads();
+  if (t < k) {
+    int rank = 0;
+    for (int i = 0; i < k; ++i) rank += (ev[i] > ev[t]) || (ev[i] == ev[t] && i < t);
+    order[rank] = t;
   }
-  for (int j = 0; j < p; ++j) {
-    theta[j] = evals[order[j]];
-    for (int a = 0; a < k; ++a) sel[a * p + j] = evec[a * k + order[j]];
+  __syncthreads();
+  if (t < p) theta[t] = ev[order[t]];
+  for (int e = t; e < k * p; e += blockDim.x) {
+    const int a = e / p, j = e % p;
+    sel[a * p + j] = evec[a * k + order[j]];
   }
 }
 
@@ -262,10 +311,12 @@ hipError_t launch_sketch(uint64_t seed, int64_t m, int k, double* out, int64_t l
   return hipGetLastError();
 }
 
+int gram_chunks(int64_t m) { return (int)((m + kGramChunk - 1) / kGramChunk); }
+
 hipError_t launch_gram(Strided A, Strided B, int64_t m, int k, double* G, double* scratch, hipStream_t st) {
-  const int chunk = 128;
-  const int nchunks = (int)((m + chunk - 1) / chunk);
-  hipLaunchKernelGGL(k_gram_partial, dim3(nchunks), dim3(256), 0, st, A, B, m, k, chunk, scratch);
+  if (k < 1 || k > kMaxSketch || m < 1) return hipErrorInvalidValue;
+  const int nchunks = gram_chunks(m);
+  hipLaunchKernelGGL(k_gram_partial, dim3(nchunks), dim3(256), 0, st, A, B, m, k, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_gram_reduce, dim3((k * k + 255) / 256), dim3(256), 0, st, scratch, nchunks, k, G);
@@ -273,6 +324,7 @@ hipError_t launch_gram(Strided A, Strided B, int64_t m, int k, double* G, double
 }
 
 hipError_t launch_chol_inv(double* G, int k, int32_t* flags, hipStream_t st) {
+  if (k < 1 || k > kMaxSketch) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), 0, st, G, k, flags);
   return hipGetLastError();
 }
@@ -286,12 +338,14 @@ hipError_t launch_right_mult(Strided A, int64_t m, int k, const double* M, int k
 }
 
 hipError_t launch_sym_eig(double* T, int k, double* evec, double* evals, hipStream_t st) {
+  if (k < 1 || k > kMaxSketch) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sym_eig, dim3(1), dim3(256), 0, st, T, k, evec, evals);
   return hipGetLastError();
 }
 
 hipError_t launch_lmp_finish(const double* evals, const double* evec, int k, int p, double* theta, double* sel,
                              hipStream_t st) {
+  if (k < 1 || k > kMaxSketch || p > k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_lmp_finish, dim3(1), dim3(64), 0, st, evals, evec, k, p, theta, sel);
   return hipGetLastError();
 }
