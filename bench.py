@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--graph", action="store_true", help="lorenz-cycle: replay a HIP graph of one cycle")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in block-shape rules")
     ap.add_argument("--n-ritz", type=int, default=10, help="Ritz pairs of the limited-memory preconditioner")
+    ap.add_argument("--tail", type=int, default=0,
+                    help="live systems at which one persistent launch finishes the PCG loop (0: the library's "
+                         "default, -1: never)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy before the timed region (scale for HBM counters)")
     return ap.parse_args()
@@ -110,7 +113,7 @@ def main():
     s, p = ie.quadrature_elliptic(prob.Q, prob.ell)
     kw = dict(precision=prec, solver=SOLVERS[a.solver],
               cov_form={"auto": ie.COV_AUTO, "operator": ie.COV_OPERATOR, "band": ie.COV_BAND}[a.form],
-              n_ritz=a.n_ritz)
+              n_ritz=a.n_ritz, tail_systems=a.tail)
     if a.domain == "lattice":
         kw.update(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=P.lattice())
     opts = ie.default_opts(**kw)
@@ -188,6 +191,7 @@ def main():
            "config": {"workload": prob.name, "n": prob.n, "N": prob.N, "m": prob.m, "Q": prob.Q,
                       "systems_per_step": systems, "rtol": 1e-8, "precision": a.precision,
                       "apply_domain": a.domain, "solver": a.solver, "cov_form": a.form, "n_ritz": a.n_ritz,
+                      "tail_systems": a.tail,
                       "autotuned": [list(t) for t in tuned]},
            "iterations": {"total": int(st.iters.sum()), "max": int(st.iters.max()),
                           "fp64_sweeps": st.counter(ie.CNT_SWEEPS)},
@@ -274,7 +278,8 @@ def bench_cycle(a, prec):
             raise SystemExit("paper-sec5-cycle runs its fixed iteration count in FP64 (--precision fp64)")
         prob = syn.experiment2_problem()
         noise = syn.experiment2_noise(cycles, prob.m)
-        kw = dict(precision=prec, cov_form=form, n_ritz=a.n_ritz, fixed_iters=10, solver=SOLVERS[a.solver])
+        kw = dict(precision=prec, cov_form=form, n_ritz=a.n_ritz, fixed_iters=10, solver=SOLVERS[a.solver],
+                  tail_systems=a.tail)
         run = CycleRunner(prob, noise=noise, opts=ie.default_opts(**kw), lattice=False)
         name = f"paper-sec5-lorenz96-32x40-N40-m40-Q{run.Q}-fixed10-cycle"
         metric = "shifted SPD solves/s at 10 fixed PCG iterations"
@@ -283,7 +288,7 @@ def bench_cycle(a, prec):
         noise = np.random.default_rng(4242).standard_normal((cycles, prob.m)) * np.sqrt(prob.r_var[0])
         run = CycleRunner(prob, noise=noise)
         kw = dict(precision=prec, apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=run.P.lattice(), cov_form=form,
-                  solver=SOLVERS[a.solver])
+                  solver=SOLVERS[a.solver], tail_systems=a.tail)
         run.set_opts(ie.default_opts(**kw))
         name = "lorenz96-8x480-N20-m1280-Q12-cycle"
         metric = "shifted SPD solves/s at rel-res 1e-8"
@@ -344,7 +349,8 @@ def bench_batched(a, prec):
     nodes = [ie.quadrature_elliptic(pr.Q, pr.ell) for pr in probs]
     systems = sum(pr.Q * pr.N for pr in probs)
     kw = dict(precision=prec, solver=SOLVERS[a.solver],
-              cov_form={"auto": ie.COV_AUTO, "operator": ie.COV_OPERATOR, "band": ie.COV_BAND}[a.form])
+              cov_form={"auto": ie.COV_AUTO, "operator": ie.COV_OPERATOR, "band": ie.COV_BAND}[a.form],
+              tail_systems=a.tail)
     lats = None
     if a.domain == "lattice":
         kw.update(apply_domain=ie.DOMAIN_OBS_LATTICE)

@@ -205,7 +205,12 @@ typedef struct infoesrf_opts {
                            an exactly zero residual; reaching the count is not a warning, and
                            stats->converged still reports relres <= rtol.  0: iterate to rtol. */
   int32_t s_form;       /* INFOESRF_S_AUTO | INFOESRF_S_OPERATOR | INFOESRF_S_DENSE */
-  int32_t reserved[4];
+  int32_t tail_systems; /* FP64 PCG on the observed lattice with the band form, or with the dense S,
+                           when that band or S takes at most 512 KiB: once at most this many systems
+                           are left, one persistent launch finishes them (each workgroup iterates a
+                           system to convergence, its direction in LDS, applying the band or S in
+                           place).  0 = 64, -1 = never. */
+  int32_t reserved[3];
 } infoesrf_opts;
 
 /* Per-system results (device arrays, each may be NULL).  Systems of the

@@ -289,6 +289,7 @@ struct Options {
   int sform;  // INFOESRF_S_*: requested form of S
   int msc_q0 = -1;  // multi-shift perturbation solve: the base node (-1: not used)
   int bcg_Q = 0;    // block perturbation solve: number of nodes (0: not used)
+  int tail = 64;    // live systems at which one persistent launch finishes the PCG loop (-1: never)
 };
 
 struct Inst {
@@ -337,6 +338,7 @@ struct Sys {
   double *zeta = nullptr, *zeta_prev = nullptr, *mrr = nullptr, *malpha = nullptr, *mbeta = nullptr;
   int32_t* mit = nullptr;
   int64_t* app_adj = nullptr;  // applies counter correction: member iterations replace system iterations
+  int32_t* qctr = nullptr;     // work-queue counter of the persistent finish
   // block PCG (SOLVER_BLOCK): W = C P, partial and reduced products, coefficients, node states
   double *bw = nullptr, *bpart = nullptr, *bred = nullptr, *bcoef = nullptr;
   int32_t* bdone = nullptr;
@@ -411,6 +413,7 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   IE_CHECK(o->rtol > 0.0 && o->rtol < 1.0, INFOESRF_ERR_INVALID_ARG, "rtol must be in (0, 1)");
   IE_CHECK(o->max_iter >= 1, INFOESRF_ERR_INVALID_ARG, "max_iter must be >= 1");
   IE_CHECK(o->fixed_iters >= 0, INFOESRF_ERR_INVALID_ARG, "fixed_iters must be >= 0");
+  IE_CHECK(o->tail_systems >= -1, INFOESRF_ERR_INVALID_ARG, "tail_systems must be >= -1");
   IE_CHECK(o->fixed_iters == 0 || o->precision == INFOESRF_FP64, INFOESRF_ERR_INVALID_ARG,
            "fixed_iters needs precision FP64 (a mixed solve counts inner and outer iterations)");
   IE_CHECK(o->n_ritz >= 0 && o->oversample >= 0, INFOESRF_ERR_INVALID_ARG, "n_ritz, oversample must be >= 0");
@@ -456,6 +459,7 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   }
   op.rtol = o->rtol;
   op.sform = o->s_form;
+  op.tail = o->tail_systems == 0 ? 64 : o->tail_systems;
   op.fixed = o->fixed_iters;
   op.max_iter = op.fixed > 0 ? op.fixed : o->max_iter;
   op.p = p;
@@ -620,6 +624,7 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
     sy.mit = ar.take<int32_t>(nm);
   }
   sy.app_adj = ar.take<int64_t>(1);
+  sy.qctr = ar.take<int32_t>(1);
   if (op.solver == INFOESRF_SOLVER_BLOCK && S > 1 && S % in.N == 0) {
     const int Qb = (int)(S / in.N);
     sy.bw = ar.take<double>(ms);
@@ -1208,6 +1213,23 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   const bool plain = (op.solver == INFOESRF_SOLVER_PLAIN);
   const bool od = in.odom();
   void* Vbuf = od ? pl.bf.V : nullptr;
+  // the persistent finish: FP64 inner PCG whose applies it can do in place
+  // (each workgroup reads the whole band or S once per iteration, so only small ones qualify:
+  // at most 512 KiB, which stays in the L2 of every XCD)
+  const double tail_bytes =
+      in.sd ? 8.0 * in.m * in.m : 8.0 * in.m * (2 * in.go.bz + 1) * (2 * in.go.bx + 1);
+  const bool tail_ok = op.tail > 0 && op.host_sync && fp64_inner && !plain && in.m <= 4096 &&
+                       ((in.obs && in.band && in.bandO) || (in.sd && in.Sd)) && tail_bytes <= 512.0 * 1024;
+  TailApply tap{};
+  if (tail_ok) {
+    tap.kind = in.sd ? 1 : 0;
+    tap.g = in.go;
+    tap.band = static_cast<const double*>(in.bandO);
+    tap.ldb = ld64(in.m);
+    tap.S = in.Sd;
+    tap.lds = in.lds;
+    tap.m = in.m;
+  }
   const int64_t ldr = ld64(od ? in.m : in.n);
   int32_t h_nact = (int32_t)S;
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
@@ -1276,6 +1298,12 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
         if (got) {
           if (seen == 0) break;
           if (!plain) hint = seen;  // compacted lists hold exactly the live systems
+          if (tail_ok && seen <= op.tail) {
+            // few systems left: one persistent launch iterates each of them to the end
+            IE_HIP(launch_fill_i32(sy.qctr, 0, 1, st));
+            IE_HIP(launch_pcg_tail(ps, lmp, tap, act_c, nact_c, sy.qctr, seen, st));
+            break;
+          }
         }
       }
     }

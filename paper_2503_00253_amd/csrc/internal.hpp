@@ -295,11 +295,27 @@ int bcg_chunks(int64_t m);
 hipError_t launch_bcg_iteration(const BcgState& s, int mode, int it, hipStream_t st);
 // act = systems of the live nodes (node-major), *nact their number.
 hipError_t launch_bcg_list(const int32_t* bdone, int Q, int64_t N, int32_t* act, int32_t* nact, hipStream_t st);
+// In-place apply of S for the persistent finish: kind 0 = explicit band of P on the observed
+// lattice g (rows = m), kind 1 = dense S (m x m, column-major, lds).
+struct TailApply {
+  int kind;
+  Grid g;
+  const double* band;
+  int64_t ldb;
+  const double* S;
+  int64_t lds;
+  int64_t m;
+};
+// Finish the listed systems (act, *nact) with one persistent launch of `grid` workgroups that take
+// systems from the queue counter qctr (zeroed beforehand) and iterate each to convergence, the
+// cap or a breakdown (FP64 PCG with the limited-memory preconditioner).  m <= 4096.
 hipError_t launch_pcg_fused(Prec prec, const PCGState& s, const LMP& lmp, int mode, int obs_domain, int plain,
                             const void* T, int64_t ldt, const int32_t* act, const int32_t* nact, int32_t* act_out,
                             int32_t* nact_out, int64_t Bmax, void* V, int64_t ldv, const int32_t* h_ptr,
                             const int32_t* h_idx, const double* h_w, const double* r_var, int64_t n_state,
                             hipStream_t st);
+hipError_t launch_pcg_tail(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
+                           const int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st);
 // The fused PCG step with the measurement hook (profile slot INFOESRF_PROF_PCG); arguments as
 // launch_pcg_fused.
 hipError_t pcg_fused_timed(Prec prec, const PCGState& s, const LMP& lmp, int mode, int obs_domain, int plain,

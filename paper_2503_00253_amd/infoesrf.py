@@ -57,7 +57,8 @@ class Opts(C.Structure):
                 ("host_sync", C.c_int32), ("apply_domain", C.c_int32), ("lattice", Lattice),
                 ("seed", C.c_uint64), ("sketch", C.c_void_p), ("net", C.c_void_p),
                 ("tile_rows", C.c_int32), ("cov_form", C.c_int32), ("fixed_iters", C.c_int32),
-                ("s_form", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("s_form", C.c_int32), ("tail_systems", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class StatsC(C.Structure):

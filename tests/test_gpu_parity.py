@@ -408,3 +408,26 @@ def test_autotune_records_choices_and_keeps_results():
     got, st = ie.perturbation_update(P, s, p, o)
     assert st.code == ie.OK and rel(got.cpu().numpy(), want) < 1e-6
     ie.autotune_reset()
+
+
+@pytest.mark.parametrize("form,domain", [("band", "lattice"), ("dense-s", "state"), ("dense-s", "lattice")])
+@pytest.mark.parametrize("case", ["gauss-n256-periodic", "2d-layers", "2d-periodic-z"])
+def test_persistent_finish_matches(case, form, domain):
+    """The persistent finish (one workgroup per remaining system, apply in place) against the
+    oracle and against the loop without it; tail_systems = S hands every system over at the first
+    poll, so the whole solve after four iterations runs in the persistent kernel."""
+    prob = CASES[case]()
+    say("persistent finish", case, form, domain)
+    dp = dense_of(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    P = ie.Problem.from_synthetic(prob)
+    S = prob.Q * prob.N
+    outs = {}
+    for tail in (-1, 0, S):
+        got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, form, tail_systems=tail))
+        assert st.code == ie.OK and np.all(st.relres <= 1e-8)
+        assert rel(got.cpu().numpy(), want) < 1e-6, tail
+        outs[tail] = (got.cpu().numpy(), st.iters.copy())
+    assert rel(outs[S][0], outs[-1][0]) < 1e-9
+    assert np.max(np.abs(outs[S][1] - outs[-1][1])) <= 2
