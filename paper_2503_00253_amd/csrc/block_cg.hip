@@ -4,7 +4,7 @@
 // spaces.  The node's limited-memory preconditioner (Appendix E) applies column by column.
 //
 // One iteration, for all live nodes at once, after the batched apply W = C_q P:
-//   partials:  per 128-row chunk, P^T W, P^T R, W^T R, W^T W (N x N) and Phi^T W, Phi^T R,
+//   partials:  per 64-row chunk, P^T W, P^T R, W^T R, W^T W (N x N) and Phi^T W, Phi^T R,
 //              (S Phi)^T W, (S Phi)^T R (p x N), diag R^T R;
 //   reduce:    chunk sums in a fixed order;
 //   small:     one workgroup per node: stop test on ||r_j||; G = P^T W = L L^T (Cholesky with
@@ -23,7 +23,7 @@ namespace infoesrf {
 
 namespace {
 
-constexpr int kBcgChunk = 128;  // rows per partial
+constexpr int kBcgChunk = 64;   // rows per partial
 constexpr int kBcgSub = 32;     // rows staged in LDS at a time
 constexpr int kBcgMaxN = 64;
 constexpr int kBcgMaxP = 20;
