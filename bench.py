@@ -221,8 +221,10 @@ def main():
         out["solver_comparison"] = comp
 
     if not a.no_plain:
-        # the plain baseline: FP64 operator-form applies in the state space, masked systems
-        popts = ie.default_opts(precision=ie.FP64, solver=ie.SOLVER_PLAIN, cov_form=ie.COV_OPERATOR)
+        # the plain baseline: FP64 operator-form applies of P in the state space every iteration
+        # (no band, no dense S), masked systems
+        popts = ie.default_opts(precision=ie.FP64, solver=ie.SOLVER_PLAIN, cov_form=ie.COV_OPERATOR,
+                                s_form=ie.S_OPERATOR)
         prun = ie.PerturbationRunner(P, s, p, popts)
         prun.run()
         torch.cuda.synchronize()
