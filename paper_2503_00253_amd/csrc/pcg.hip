@@ -176,9 +176,10 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
 
   // Next list: a system claims a slot (appended in any order) and writes its next apply input
   // there.  nact_out[0] counts the list; in the masked solver, where retired systems stay in the
-  // list, nact_out[1] counts the systems still iterating (the compacted list holds only those).
-  // A live system claims its slot as soon as it knows it continues, so the atomic's round trip
-  // overlaps the preconditioner arithmetic.
+  // list, nact_out[1] counts the systems still iterating.  In the masked solver a system claims
+  // its slot once it knows it continues (the atomic overlaps the preconditioner arithmetic); in
+  // the compacted one it claims at the start (see below).
+  int slot_reg = -1;  // thread 0: a slot claimed early whose number is consumed in write_v
   auto claim = [&](bool live) {
     if (tid == 0) {
       const int slot = atomicAdd(nact_out, 1);
@@ -187,7 +188,14 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       s_slot = slot;
     }
   };
+  auto claim_early = [&]() {
+    if (tid == 0) slot_reg = atomicAdd(nact_out, 1);
+  };
   auto write_v = [&](const double* pv) {
+    if (tid == 0 && slot_reg >= 0) {  // the early claim's result is needed only now
+      act_out[slot_reg] = s;
+      s_slot = slot_reg;
+    }
     __syncthreads();
     if (V) {
       TV* col = V + (int64_t)s_slot * ldv;
@@ -220,6 +228,13 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
     xv[j] = (ok && mode == 1) ? st.x[base + r] : 0.0;
     sv[j] = (ok && mode == 1 && obs_domain) ? (double)T[(int64_t)c * ldt + r] : 0.0;
   }
+  // The Ritz vectors are read in FP32 (the values the preconditioner's Gram matrices were formed
+  // from) for the dots of r and, when they fit in registers, kept for the preconditioned residual,
+  // so each system reads them once per iteration.  (They are not loaded with the system's data:
+  // that many loads in flight would stall the first round trip.)
+  constexpr bool kCache = (RPT * P <= 48);
+  constexpr int kC = (kCache && P > 0) ? RPT * P : 1;
+  float ph[kC], sph[kC];
   if (P > 0) {
     for (int o = tid; o < 3 * P * P; o += blockDim.x) sG[o] = lmp.G[o];
     if (tid < P) sG[3 * P * P + tid] = lmp.theta[tid];
@@ -230,6 +245,10 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
     if (plain) append(nullptr);
     return;
   }
+  // Compacted lists: a live system claims its next slot now, so the atomic's round trip overlaps
+  // the step.  A system that then converges or breaks down leaves a zero direction in the slot
+  // and drops out of the next step, where done != 0.
+  if (!plain) claim_early();
   if (mode == 1) {
     double qv[RPT];
     double pq = 0.0;
@@ -252,6 +271,7 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
         st.done[s] = 2;
       }
       if (plain) append(nullptr);
+      else write_v(nullptr);
       return;
     }
     const double alpha = rz_old / tot;
@@ -265,12 +285,7 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       }
     }
   }
-  // (3) dots of r: r^T r, Phi^T r, (S Phi)^T r.  The Ritz vectors are read in FP32 (the values
-  // the preconditioner's Gram matrices were formed from) and, when they fit, kept in registers
-  // for the preconditioned residual below, so each system reads them once per iteration.
-  constexpr bool kCache = (RPT * P <= 20);
-  constexpr int kC = (kCache && P > 0) ? RPT * P : 1;
-  float ph[kC], sph[kC];
+  // (3) dots of r: r^T r, Phi^T r, (S Phi)^T r.
   double acc[W];
   const double* d = sdot;
 #pragma unroll
@@ -304,19 +319,22 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       st.done[s] = 2;
     }
     if (plain) append(nullptr);
+    else write_v(nullptr);
     return;
   }
   if (rn <= thresh) {
     if (tid == 0) st.done[s] = 1;
     if (plain) append(nullptr);
+    else write_v(nullptr);
     return;
   }
   if (it >= st.max_iter) {
     if (tid == 0) st.done[s] = 2;
     if (plain) append(nullptr);
+    else write_v(nullptr);
     return;
   }
-  claim(true);
+  if (plain) claim(true);
   // limited-memory preconditioner coefficients (Appendix E), with Theta = diag(1 + sigma + theta_j):
   //   c1 = Theta^{-1} Phi^T r,  c2 = Theta^{-1} [(C Phi)^T r - (C Phi)^T (C Phi) c1],
   //   gamma = (1 + sigma - beta_L) c1 + c2,  z = r - S Phi c1 - Phi gamma,
