@@ -210,7 +210,9 @@ typedef struct infoesrf_opts {
                            are left, one persistent launch finishes them (each workgroup iterates a
                            system to convergence, its direction in LDS, applying the band or S in
                            place).  0 = 64, -1 = never. */
-  int32_t reserved[3];
+  int32_t warm_fp32;    /* learned start: 0 = BF16 inference on MFMA with FP32 accumulation
+                           (default), 1 = FP32 inference */
+  int32_t reserved[2];
 } infoesrf_opts;
 
 /* Per-system results (device arrays, each may be NULL).  Systems of the
@@ -356,6 +358,12 @@ int infoesrf_net_set_params(void* net, const float* host);        /* also resets
 size_t infoesrf_net_workspace_bytes(const void* net, int64_t B, int64_t m, int32_t training);
 int infoesrf_net_forward(const void* net, const float* X, int64_t B, int64_t m, float* Y, void* ws,
                          size_t ws_bytes, void* stream);
+/* The same network output with BF16 weights and activations on MFMA (v_mfma_f32_16x16x32_bf16) and
+ * FP32 accumulation, as the learned start runs it by default; needs H <= 64, H % 8 == 0.  Same
+ * workspace (training = 0).  The output differs from infoesrf_net_forward by the BF16 rounding of
+ * weights and activations (a relative error of order 1e-2). */
+int infoesrf_net_forward_bf16(const void* net, const float* X, int64_t B, int64_t m, float* Y, void* ws,
+                              size_t ws_bytes, void* stream);
 int infoesrf_net_gradients(const void* net, const float* X, const float* T, int64_t B, int64_t m,
                            float* grads, float* loss, void* ws, size_t ws_bytes, void* stream);
 int infoesrf_net_train_step(void* net, const float* X, const float* T, int64_t B, int64_t m, float lr,

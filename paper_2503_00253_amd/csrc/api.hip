@@ -290,6 +290,7 @@ struct Options {
   int msc_q0 = -1;  // multi-shift perturbation solve: the base node (-1: not used)
   int bcg_Q = 0;    // block perturbation solve: number of nodes (0: not used)
   int tail = 64;    // live systems at which one persistent launch finishes the PCG loop (-1: never)
+  int warm_fp32 = 0;  // learned start: FP32 inference instead of BF16 on MFMA
 };
 
 struct Inst {
@@ -320,6 +321,7 @@ struct Inst {
   // learned warm start: network buffers for a chunk of systems (features, outputs, the network's
   // own workspace)
   const Net* net = nullptr;
+  bool warm_fp32 = false;  // FP32 inference instead of BF16 on MFMA
   int64_t wchunk = 0;
   float *wX = nullptr, *wY = nullptr;
   void* wnet = nullptr;
@@ -460,6 +462,7 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   op.rtol = o->rtol;
   op.sform = o->s_form;
   op.tail = o->tail_systems == 0 ? 64 : o->tail_systems;
+  op.warm_fp32 = o->warm_fp32 != 0;
   op.fixed = o->fixed_iters;
   op.max_iter = op.fixed > 0 ? op.fixed : o->max_iter;
   op.p = p;
@@ -580,6 +583,7 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   in.counters = ar.take<int64_t>(INFOESRF_NUM_COUNTERS);
   if (op.warm == INFOESRF_START_LEARNED && S > 1) {
     in.net = static_cast<const Net*>(op.net);
+    in.warm_fp32 = op.warm_fp32;
     in.wchunk = std::min<int64_t>(S, 128);
     in.wX = ar.take<float>(in.wchunk * 3 * in.m);
     in.wY = ar.take<float>(in.wchunk * in.m);
@@ -1006,7 +1010,8 @@ int stage_warm(Plan& pl, hipStream_t st) {
     hipLaunchKernelGGL(k_net_features, dim3(nb(cnt * in.m)), dim3(256), 0, st, sy.b, sy.ldm, sy.bnorm, sy.sigma,
                        in.m, s0, cnt, in.wX);
     IE_HIP(hipGetLastError());
-    IE_TRY(net_forward(*in.net, in.wX, cnt, in.m, in.wY, in.wnet, in.wnet_bytes, st));
+    if (in.warm_fp32) IE_TRY(net_forward(*in.net, in.wX, cnt, in.m, in.wY, in.wnet, in.wnet_bytes, st));
+    else IE_TRY(net_forward_bf16(*in.net, in.wX, cnt, in.m, in.wY, in.wnet, in.wnet_bytes, st));
     hipLaunchKernelGGL(k_warm_init, dim3((unsigned)cnt), dim3(256), 0, st, in.wY, sy.bnorm, in.m, s0, sy.u, sy.ldm,
                        in.fallbacks);
     IE_HIP(hipGetLastError());

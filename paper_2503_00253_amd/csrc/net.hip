@@ -36,7 +36,9 @@ namespace {
 // two gradient buffers (B H m) and the flipped weights (H H K).  Inference: two (B H m) buffers.
 struct NetWs {
   float *z[3], *a[3], *y, *gy, *per, *loss, *g0, *g1, *wt;
-  float *p0, *p1;  // inference ping-pong
+  float *p0, *p1;                // inference ping-pong (FP32)
+  __hip_bfloat16 *q0, *q1;       // inference ping-pong (BF16, position-major)
+  __hip_bfloat16* wpk[4];        // packed BF16 weights of the four layers
 };
 
 int64_t al(int64_t n) { return (n + 63) / 64 * 64; }
@@ -66,6 +68,16 @@ NetWs carve(const Net& n, int64_t B, int64_t m, bool training, void* ws, size_t*
   } else {
     w.p0 = take(act);
     w.p1 = take(act);
+    const int64_t actb = B * (int64_t)bf16_cp(n.H) * m;  // BF16 elements
+    w.q0 = reinterpret_cast<__hip_bfloat16*>(take((actb + 1) / 2));
+    w.q1 = reinterpret_cast<__hip_bfloat16*>(take((actb + 1) / 2));
+    for (int l = 0; l < 4; ++l) {
+      int64_t wo, bo;
+      int ci, co;
+      net_layer(n, l, &wo, &bo, &ci, &co);
+      const int64_t cnt = (int64_t)bf16_opad(co) * bf16_kd(ci, n.K);
+      w.wpk[l] = reinterpret_cast<__hip_bfloat16*>(take((cnt + 1) / 2));
+    }
   }
   *bytes = (size_t)off * sizeof(float) + 256;
   return w;
@@ -91,6 +103,25 @@ int forward_layers(const Net& n, const float* X, int64_t B, int64_t m, const Net
     float* act = last ? Y : (training ? w.a[l] : (l % 2 == 0 ? w.p0 : w.p1));
     IE_HIP(launch_conv_fwd(in, ci, n.params + wo, n.params + bo, co, n.K, (int)m, B, pre, act, last ? 0 : 1, st));
     in = act;
+  }
+  return 0;
+}
+
+// BF16 inference: weights packed on every call (they may have been trained since), activations in
+// BF16 between layers, the last layer writes FP32
+int forward_layers_bf16(const Net& n, const float* X, int64_t B, int64_t m, const NetWs& w, float* Y,
+                        hipStream_t st) {
+  const void* in = X;
+  for (int l = 0; l < 4; ++l) {
+    int64_t wo, bo;
+    int ci, co;
+    net_layer(n, l, &wo, &bo, &ci, &co);
+    IE_HIP(launch_pack_weights_bf16(n.params + wo, co, ci, n.K, w.wpk[l], st));
+    const bool last = (l == 3);
+    void* out = last ? static_cast<void*>(Y) : static_cast<void*>(l % 2 == 0 ? w.q0 : w.q1);
+    IE_HIP(launch_conv_bf16(in, l == 0, ci, w.wpk[l], n.params + bo, co, n.K, (int)m, B, out, last, last ? 0 : 1,
+                            st));
+    in = out;
   }
   return 0;
 }
@@ -158,6 +189,15 @@ int net_forward(const Net& n, const float* X, int64_t B, int64_t m, float* Y, vo
   const NetWs w = carve(n, B, m, false, ws, &need);
   IE_CHECK(ws && ws_bytes >= need, INFOESRF_ERR_WORKSPACE, "network workspace too small");
   return forward_layers(n, X, B, m, w, false, Y, st);
+}
+
+int net_forward_bf16(const Net& n, const float* X, int64_t B, int64_t m, float* Y, void* ws, size_t ws_bytes,
+                     hipStream_t st) {
+  size_t need = 0;
+  const NetWs w = carve(n, B, m, false, ws, &need);
+  IE_CHECK(ws && ws_bytes >= need, INFOESRF_ERR_WORKSPACE, "network workspace too small");
+  IE_CHECK(n.H <= 64 && n.H % 8 == 0, INFOESRF_ERR_INVALID_ARG, "BF16 inference needs H <= 64, H % 8 == 0");
+  return forward_layers_bf16(n, X, B, m, w, Y, st);
 }
 
 }  // namespace infoesrf
@@ -296,6 +336,15 @@ extern "C" int infoesrf_net_forward(const void* net, const float* X, int64_t B, 
   IE_TRY(check_net_io(h, B, m));
   IE_CHECK(X && Y, INFOESRF_ERR_INVALID_ARG, "X and Y must be non-NULL");
   return net_forward(*h, X, B, m, Y, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int infoesrf_net_forward_bf16(const void* net, const float* X, int64_t B, int64_t m, float* Y, void* ws,
+                                         size_t ws_bytes, void* stream) {
+  clear_error();
+  const Net* h = static_cast<const Net*>(net);
+  IE_TRY(check_net_io(h, B, m));
+  IE_CHECK(X && Y, INFOESRF_ERR_INVALID_ARG, "X and Y must be non-NULL");
+  return net_forward_bf16(*h, X, B, m, Y, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 extern "C" int infoesrf_net_gradients(const void* net, const float* X, const float* T, int64_t B, int64_t m,

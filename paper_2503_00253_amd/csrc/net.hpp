@@ -1,5 +1,6 @@
 // Internal view of the warm-start network handle.
 #pragma once
+#include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -28,9 +29,22 @@ size_t net_ws_bytes(const Net& n, int64_t B, int64_t m, bool training);
 // Network output Y (B x m) of inputs X (B x 3 x m) in FP32; ws as sized by net_ws_bytes(.., false).
 int net_forward(const Net& n, const float* X, int64_t B, int64_t m, float* Y, void* ws, size_t ws_bytes,
                 hipStream_t st);
+// The same with BF16 weights and activations on MFMA, FP32 accumulation (H <= 64, H % 8 == 0);
+// the inference workspace covers both.
+int net_forward_bf16(const Net& n, const float* X, int64_t B, int64_t m, float* Y, void* ws, size_t ws_bytes,
+                     hipStream_t st);
 
 hipError_t launch_conv_fwd(const float* in, int Cin, const float* W, const float* bias, int Cout, int K, int m,
                            int64_t B, float* pre, float* act, int gelu, hipStream_t st);
+// BF16 inference: packed weights (round_up(Cout, 16) rows of bf16_kd(Cin, K) entries), and the
+// MFMA correlation (inputs (B, Cin, m) FP32 or (B, m, Cin) BF16 with Cin a multiple of 8; outputs
+// (B, m) FP32 when Cout = 1 or (B, m, Cout) BF16).  Cin, Cout <= 64.
+int bf16_cp(int Cin);
+int bf16_kd(int Cin, int K);
+int bf16_opad(int Cout);
+hipError_t launch_pack_weights_bf16(const float* W, int Cout, int Cin, int K, __hip_bfloat16* out, hipStream_t st);
+hipError_t launch_conv_bf16(const void* in, bool in_f32, int Cin, const __hip_bfloat16* Wp, const float* bias, int Cout,
+                            int K, int m, int64_t B, void* out, bool out_f32, int gelu, hipStream_t st);
 hipError_t launch_conv_wgrad(const float* a, int Cin, const float* g, int Cout, int K, int m, int64_t B, float* gW,
                              float* gb, hipStream_t st);
 hipError_t launch_flip_transpose(const float* W, int Cout, int Cin, int K, float* Wt, hipStream_t st);

@@ -77,6 +77,95 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ in, 
   }
 }
 
+// ---- BF16 inference on MFMA (FP32 accumulation) --------------------------------------------
+// The same correlation as an implicit GEMM: y[o, x] = bias[o] + sum_kd Wp[o, kd] A[kd, x] with
+// kd = k Cp + c (Cp = input channels rounded up to 8, so the 8 values a lane feeds to one MFMA
+// share k and are consecutive channels), A[kd, x] = a[c, x + k - K/2].  Weights are packed once
+// per call to BF16 rows of KD = round_up(K Cp, 32) entries (Cout rounded up to 16 rows, zeros in
+// the padding).  Activations between layers are BF16, position-major (b, x, c).
+typedef __bf16 nbf8 __attribute__((ext_vector_type(8)));
+typedef float nf4 __attribute__((ext_vector_type(4)));
+
+__global__ void k_pack_weights_bf16(const float* __restrict__ W, int Cout, int Cin, int K, int Cp, int KD, int Opad,
+                                    __hip_bfloat16* __restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)Opad * KD) return;
+  const int o = (int)(t / KD), kd = (int)(t % KD);
+  const int k = kd / Cp, c = kd % Cp;
+  const float v = (o < Cout && k < K && c < Cin) ? W[((int64_t)o * Cin + c) * K + k] : 0.f;
+  out[t] = __float2bfloat16(v);
+}
+
+// Block: 64 positions x 64 output channels (wavefront w: channels o0 + 16 w .. + 15, four
+// 16-position tiles).  The input window (64 + K - 1 positions x Cp channels) is staged in LDS as
+// BF16, rows padded by 8 channels (16 bytes) against bank conflicts.
+// IN_F32: input (B, Cin, m) FP32, else (B, m, Cp) BF16.  OUT_F32: output (B, m) FP32 (Cout = 1),
+// else (B, m, Cout) BF16.
+template <bool IN_F32, bool OUT_F32>
+__global__ __launch_bounds__(256) void k_conv_bf16(const void* __restrict__ in, int Cin, int Cp,
+                                                   const __hip_bfloat16* __restrict__ Wp, int KD,
+                                                   const float* __restrict__ bias, int Cout, int K, int m,
+                                                   void* __restrict__ out, int gelu) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char nsm[];
+  __hip_bfloat16* win = reinterpret_cast<__hip_bfloat16*>(nsm);
+  const int h = K / 2;
+  const int WX = 64 + K - 1;
+  const int Cs = Cp + 8;  // LDS row stride (channels)
+  const int x0 = blockIdx.x * 64;
+  const int o0 = blockIdx.y * 64;
+  const int64_t b = blockIdx.z;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lrow = lane & 15, lk = lane >> 4;
+  for (int t = tid; t < WX * Cp; t += 256) {
+    const int u = t / Cp, c = t % Cp;
+    const int x = x0 - h + u;
+    float v = 0.f;
+    if (x >= 0 && x < m && c < Cin) {
+      if (IN_F32) v = static_cast<const float*>(in)[(b * Cin + c) * (int64_t)m + x];
+      else v = __bfloat162float(static_cast<const __hip_bfloat16*>(in)[(b * m + x) * (int64_t)Cp + c]);
+    }
+    win[u * Cs + c] = __float2bfloat16(v);
+  }
+  __syncthreads();
+  const int ob = o0 + 16 * wave;
+  if (ob >= Cout) return;  // no channels for this wavefront (after the only barrier)
+  nf4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = nf4{0.f, 0.f, 0.f, 0.f};
+  const __hip_bfloat16* wrow = Wp + (int64_t)(ob + lrow) * KD + 8 * lk;
+  for (int kd0 = 0; kd0 < KD; kd0 += 32) {
+    const nbf8 a = *reinterpret_cast<const nbf8*>(wrow + kd0);
+    const int kd = kd0 + 8 * lk;
+    const int k = kd / Cp, c0 = kd % Cp;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      nbf8 bv;
+      if (k < K) {
+        bv = *reinterpret_cast<const nbf8*>(win + (16 * t + lrow + k) * Cs + c0);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bv[i] = (__bf16)0.f;
+      }
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[t], 0, 0, 0);
+    }
+  }
+  // D register v of lane l: channel ob + 4 (l / 16) + v, position x0 + 16 t + l % 16
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int x = x0 + 16 * t + lrow;
+    if (x >= m) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int o = ob + 4 * lk + v;
+      if (o >= Cout) continue;
+      const float z = acc[t][v] + (bias ? bias[o] : 0.f);
+      const float y = gelu ? gelu_f(z) : z;
+      if (OUT_F32) static_cast<float*>(out)[b * m + x] = y;
+      else static_cast<__hip_bfloat16*>(out)[(b * m + x) * (int64_t)Cout + o] = __float2bfloat16(y);
+    }
+  }
+}
+
 // Weight gradient of one layer: gW[o, c, k] = sum_{b, x} g[b, o, x] a[b, c, x + k - K/2] and
 // gb[o] = sum_{b, x} g[b, o, x].  Block (o, c-group of 8): threads stride over (b, x) and keep
 // 8 K partial sums; then a fixed-order reduction (wave shuffles, then the four waves).
@@ -228,6 +317,37 @@ hipError_t launch_conv_fwd(const float* in, int Cin, const float* W, const float
     hipLaunchKernelGGL((k_conv_fwd<CPW>), grid, dim3(256), net_conv_smem(K, CPW), st, in, Cin, W, bias, Cout, K, m,
                        pre, act, gelu);
   }
+  return hipGetLastError();
+}
+
+int bf16_cp(int Cin) { return (Cin + 7) / 8 * 8; }
+int bf16_kd(int Cin, int K) { return (K * bf16_cp(Cin) + 31) / 32 * 32; }
+int bf16_opad(int Cout) { return (Cout + 15) / 16 * 16; }
+
+hipError_t launch_pack_weights_bf16(const float* W, int Cout, int Cin, int K, __hip_bfloat16* out, hipStream_t st) {
+  const int Cp = bf16_cp(Cin), KD = bf16_kd(Cin, K), Op = bf16_opad(Cout);
+  const int64_t cnt = (int64_t)Op * KD;
+  hipLaunchKernelGGL(k_pack_weights_bf16, dim3(nb1(cnt)), dim3(256), 0, st, W, Cout, Cin, K, Cp, KD, Op, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_conv_bf16(const void* in, bool in_f32, int Cin, const __hip_bfloat16* Wp, const float* bias, int Cout,
+                            int K, int m, int64_t B, void* out, bool out_f32, int gelu, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  if (!in || !Wp || !out || K < 1 || K > 15 || (K % 2) == 0 || Cin > 64 || Cout > 64) return hipErrorInvalidValue;
+  if (out_f32 && Cout != 1) return hipErrorInvalidValue;
+  if (!in_f32 && bf16_cp(Cin) != Cin) return hipErrorInvalidValue;  // BF16 inputs carry Cp channels
+  const int Cp = bf16_cp(Cin), KD = bf16_kd(Cin, K);
+  const size_t smem = sizeof(__hip_bfloat16) * (size_t)(64 + K - 1) * (Cp + 8);
+  const dim3 grid((unsigned)((m + 63) / 64), (unsigned)((Cout + 63) / 64), (unsigned)B);
+#define IE_CB(I, O)                                                                                             \
+  hipLaunchKernelGGL((k_conv_bf16<I, O>), grid, dim3(256), smem, st, in, Cin, Cp, Wp, KD, bias, Cout, K, m, out, \
+                     gelu)
+  if (in_f32 && out_f32) IE_CB(true, true);
+  else if (in_f32) IE_CB(true, false);
+  else if (out_f32) IE_CB(false, true);
+  else IE_CB(false, false);
+#undef IE_CB
   return hipGetLastError();
 }
 

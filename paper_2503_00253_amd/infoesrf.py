@@ -58,7 +58,7 @@ class Opts(C.Structure):
                 ("seed", C.c_uint64), ("sketch", C.c_void_p), ("net", C.c_void_p),
                 ("tile_rows", C.c_int32), ("cov_form", C.c_int32), ("fixed_iters", C.c_int32),
                 ("s_form", C.c_int32), ("tail_systems", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("warm_fp32", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class StatsC(C.Structure):
@@ -123,6 +123,8 @@ def library():
     lib.infoesrf_net_workspace_bytes.restype = C.c_size_t
     lib.infoesrf_net_forward.argtypes = [VP, VP, C.c_int64, C.c_int64, VP, VP, C.c_size_t, VP]
     lib.infoesrf_net_forward.restype = C.c_int
+    lib.infoesrf_net_forward_bf16.argtypes = [VP, VP, C.c_int64, C.c_int64, VP, VP, C.c_size_t, VP]
+    lib.infoesrf_net_forward_bf16.restype = C.c_int
     lib.infoesrf_net_gradients.argtypes = [VP, VP, VP, C.c_int64, C.c_int64, VP, VP, VP, C.c_size_t, VP]
     lib.infoesrf_net_gradients.restype = C.c_int
     lib.infoesrf_net_train_step.argtypes = [VP, VP, VP, C.c_int64, C.c_int64, C.c_float, VP, VP, C.c_size_t, VP]
@@ -491,15 +493,15 @@ class Net:
             self._ws = {key: torch.empty(nbytes, dtype=torch.uint8, device="cuda")}
         return self._ws[key]
 
-    def forward(self, X):
-        """X: (B, 3, m) float32 CUDA tensor -> (B, m)."""
+    def forward(self, X, bf16=False):
+        """X: (B, 3, m) float32 CUDA tensor -> (B, m); bf16: BF16 weights and activations on MFMA."""
         torch = _torch()
         X = X.contiguous()
         B, _, m = X.shape
         Y = torch.empty((B, m), dtype=torch.float32, device=X.device)
         ws = self._workspace(B, m, False)
-        _check(library().infoesrf_net_forward(self.h, X.data_ptr(), B, m, Y.data_ptr(), ws.data_ptr(), ws.numel(),
-                                              _stream()), allow_warn=False)
+        fn = library().infoesrf_net_forward_bf16 if bf16 else library().infoesrf_net_forward
+        _check(fn(self.h, X.data_ptr(), B, m, Y.data_ptr(), ws.data_ptr(), ws.numel(), _stream()), allow_warn=False)
         return Y
 
     def gradients(self, X, T):

@@ -116,7 +116,9 @@ def main():
         P = ie.Problem.from_synthetic(prob)
         s, p = ie.quadrature_elliptic(prob.Q, prob.ell)
         res = {}
-        for name, kw in (("zero", {}), ("learned", dict(warm_start=ie.START_LEARNED, net=net))):
+        arms = (("zero", {}), ("learned", dict(warm_start=ie.START_LEARNED, net=net)),
+                ("learned_fp32_inference", dict(warm_start=ie.START_LEARNED, net=net, warm_fp32=1)))
+        for name, kw in arms:
             run = ie.PerturbationRunner(P, s, p, opts_for(ie, P, prec, **kw), y=prob.y)
             code = run.run()
             torch.cuda.synchronize()
@@ -131,8 +133,19 @@ def main():
                              ms_per_update=round(ms, 3), solves_per_s=round(prob.Q * prob.N / ms * 1e3, 1),
                              out=run.result().clone())
         diff = float((res["learned"]["out"] - res["zero"]["out"]).norm() / res["zero"]["out"].norm())
+        # the network's own cost per update: BF16 inference (the learned start's default) and FP32
+        Xq = torch.randn((P.c.N * prob.Q, 3, P.c.m), dtype=torch.float32, device="cuda")
+        for bf in (True, False):
+            net.forward(Xq[:128], bf16=bf)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for c0 in range(0, Xq.shape[0], 128):
+                net.forward(Xq[c0:c0 + 128], bf16=bf)
+            torch.cuda.synchronize()
+            res[f"inference_ms_{'bf16' if bf else 'fp32'}"] = round((time.perf_counter() - t1) * 1e3, 3)
         for r in res.values():
-            r.pop("out")
+            if isinstance(r, dict):
+                r.pop("out")
         rows.append(dict(problem=prob.name, systems=prob.Q * prob.N, rel_diff_learned_vs_zero=diff, **res))
         log(prob.name, json.dumps(rows[-1]))
     zero_it = float(np.mean([r["zero"]["iters_mean"] for r in rows]))

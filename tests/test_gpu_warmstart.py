@@ -1,6 +1,6 @@
 """Learned warm start on the GPU (through the C ABI) against the FP64 oracle.
 
-Tolerances: the network runs in FP32 with FP32 accumulation over at most
+Tolerances: the FP32 network runs with FP32 accumulation over at most
 3 x 9 + 2 x (H x 9) terms per output, so forward outputs agree with the FP64
 oracle to 1e-5 relative and gradients (a longer chain of FP32 sums over
 B x m positions) to 1e-4; one Adam step from a fresh state matches to 1e-6
@@ -67,6 +67,42 @@ def test_forward_matches_oracle(H, K, B, m):
     got = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
     want, _ = wr.forward(params, X.astype(np.float64))
     assert rel(got, want[:, 0, :]) < 1e-5
+
+
+def to_bf16(x):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16_emulated(params, X):
+    """The oracle's layers with BF16 weights, BF16 inputs and BF16 activations between layers
+    (the arithmetic itself in FP64): the precision the MFMA inference stores its operands in."""
+    a = to_bf16(X)
+    for li, (W, b) in enumerate(params):
+        z = wr.conv1d_same(a, to_bf16(W), b)
+        a = to_bf16(wr.gelu(z)) if li < len(params) - 1 else z
+    return a
+
+
+@pytest.mark.parametrize("H,K,B,m", [(8, 9, 3, 37), (64, 9, 2, 200), (16, 5, 5, 64), (8, 3, 1, 7), (64, 9, 3, 1024)])
+def test_forward_bf16_matches_oracle(H, K, B, m):
+    """BF16 inference on MFMA: against the oracle with the same BF16 roundings (operands and
+    activations) to 2e-3, the FP32 accumulation order and the few activations whose rounding
+    flips being the only differences; against the exact oracle within twice the oracle's own
+    change under those roundings."""
+    say("net forward bf16", H, K, B, m)
+    net, params = random_net(H, K, 11 + H + K)
+    X = np.random.default_rng(2).standard_normal((B, 3, m)).astype(np.float32)
+    got = net.forward(torch.from_numpy(X).cuda(), bf16=True).cpu().numpy()
+    want, _ = wr.forward(params, X.astype(np.float64))
+    emu = forward_bf16_emulated(params, X.astype(np.float64))
+    sens = rel(emu[:, 0, :], want[:, 0, :])
+    say("  bf16 sensitivity", sens, "gpu vs emulated", rel(got, emu[:, 0, :]))
+    assert rel(got, emu[:, 0, :]) < 2e-3
+    assert rel(got, want[:, 0, :]) < 2 * sens + 1e-3
 
 
 @pytest.mark.parametrize("H,K,B,m", [(8, 9, 3, 37), (32, 9, 4, 130)])
@@ -140,9 +176,11 @@ def test_learned_start_solve_meets_bound_and_fallback():
     dp = ref.DenseProblem.from_problem(prob)
     want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
     net, _ = random_net(16, 9, 21)
-    got, st = ie.perturbation_update(P, s, p, ie.default_opts(warm_start=ie.START_LEARNED, net=net), y=prob.y)
-    assert st.code == ie.OK and rel(got.cpu().numpy(), want) < 1e-6
-    assert np.all(st.relres <= 1e-8) and st.counter(ie.CNT_FALLBACKS) == 0
+    for fp32 in (0, 1):   # BF16 inference on MFMA (the default), FP32 inference
+        got, st = ie.perturbation_update(P, s, p, ie.default_opts(warm_start=ie.START_LEARNED, net=net,
+                                                                  warm_fp32=fp32), y=prob.y)
+        assert st.code == ie.OK and rel(got.cpu().numpy(), want) < 1e-6
+        assert np.all(st.relres <= 1e-8) and st.counter(ie.CNT_FALLBACKS) == 0
     # a network that predicts NaN: every system falls back to the zero start
     bad = ie.Net.create(16, 9, 3)
     v = bad.params()
