@@ -25,14 +25,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0}   # MI355X dense matrix peaks: FP64, FP32, BF16
+# FP64 vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
+PEAK_ALU_FP64 = 78.6
 PEAK_HBM_GBS = 8000.0                            # MI355X HBM3E
 DTYPE = {0: "f64", 1: "f32/f64", 2: "bf16/f64"}
 # profile slots of the covariance applies: (kernel, bound, MFMA peak key)
 SLOTS = {0: ("k_cov_stencil<fp64>", "mfma", 0), 1: ("k_cov_stencil<fp32>", "mfma", 1),
          2: ("k_cov_bf16", "mfma", 2), 3: ("k_band_apply<fp64>", "hbm", None),
-         4: ("k_band_apply<fp32>", "hbm", None), 5: ("k_pcg_fused", "hbm", None)}
+         4: ("k_band_apply<fp32>", "hbm", None), 5: ("k_pcg_fused", "hbm", None),
+         6: ("k_pcg_tail", "alu", None)}
 SOLVERS = {"plain": 0, "compact": 1, "multishift": 3, "block": 4}
-SRC = {0: "cov_apply.hip", 1: "cov_apply.hip", 2: "cov_apply.hip", 3: "band.hip", 4: "band.hip", 5: "pcg.hip"}
+SRC = {0: "cov_apply.hip", 1: "cov_apply.hip", 2: "cov_apply.hip", 3: "band.hip", 4: "band.hip", 5: "pcg.hip",
+       6: "pcg_tail.hip"}
 
 
 def parse():
@@ -169,6 +173,9 @@ def main():
     if bound == "mfma":
         achieved = flops[dom] / secs / 1e12 if secs > 0 else 0.0
         peak, unit = PEAK_TFLOPS[pk], "TFLOP/s"
+    elif bound == "alu":
+        achieved = flops[dom] / secs / 1e12 if secs > 0 else 0.0
+        peak, unit = PEAK_ALU_FP64, "TFLOP/s"
     else:
         achieved = nbytes[dom] / secs / 1e9 if secs > 0 else 0.0
         peak, unit = PEAK_HBM_GBS, "GB/s"

@@ -206,10 +206,14 @@ typedef struct infoesrf_opts {
                            stats->converged still reports relres <= rtol.  0: iterate to rtol. */
   int32_t s_form;       /* INFOESRF_S_AUTO | INFOESRF_S_OPERATOR | INFOESRF_S_DENSE */
   int32_t tail_systems; /* FP64 PCG on the observed lattice with the band form, or with the dense S,
-                           when that band or S takes at most 512 KiB: once at most this many systems
-                           are left, one persistent launch finishes them (each workgroup iterates a
-                           system to convergence, its direction in LDS, applying the band or S in
-                           place).  0 = 64, -1 = never. */
+                           when that band or S takes at most 1 MiB (m <= 4096): once at most this
+                           many systems are left, one persistent launch finishes them (each
+                           workgroup iterates a system to convergence, its direction in LDS,
+                           applying the band or S in place; the smallest shifts first).  A value
+                           of at least Q*N hands every system over after the first step (without
+                           host synchronization, the only hand-over point).  0 = every system
+                           from the first step (64 in infoesrf_update_batched, whose instances
+                           share the GPU), -1 = never. */
   int32_t warm_fp32;    /* learned start: 0 = BF16 inference on MFMA with FP32 accumulation
                            (default), 1 = FP32 inference */
   int32_t reserved[2];
@@ -452,12 +456,17 @@ int infoesrf_rtps_assemble(const double* Xf, int64_t ldf, const double* mean_a, 
 #define INFOESRF_PROF_BAND_FP64 3
 #define INFOESRF_PROF_BAND_FP32 4
 #define INFOESRF_PROF_PCG 5 /* the fused PCG step: vectors = live systems, bytes per system 6-8 m-vector passes */
-#define INFOESRF_PROF_SLOTS 6
+#define INFOESRF_PROF_TAIL 6 /* the persistent PCG kernel: vectors = system-iterations, FLOPs per
+                                system-iteration = the apply (2 nnz(L) on the observed lattice, or
+                                2 m^2 with the dense S) + the PCG step (12 + 8 p) m; bytes = one read
+                                and one write of x, r, p per system, plus the band (or S) and the
+                                FP32 Ritz bases once per launch */
+#define INFOESRF_PROF_SLOTS 7
 int infoesrf_profile_enable(int on);
 /* Restricts the hook to the slots whose bit (1 << slot) is set in mask (all slots after enabling);
  * launches of other slots then run without events.  Fewer event pairs perturb the timeline less. */
 int infoesrf_profile_select(uint32_t mask);
-int infoesrf_profile_read(double ms[6], int64_t launches[6], int64_t vectors[6], double flops[6], double bytes[6]);
+int infoesrf_profile_read(double ms[7], int64_t launches[7], int64_t vectors[7], double flops[7], double bytes[7]);
 
 #ifdef __cplusplus
 }

@@ -461,7 +461,7 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   }
   op.rtol = o->rtol;
   op.sform = o->s_form;
-  op.tail = o->tail_systems == 0 ? 64 : o->tail_systems;
+  op.tail = o->tail_systems == 0 ? INT32_MAX : o->tail_systems;
   op.warm_fp32 = o->warm_fp32 != 0;
   op.fixed = o->fixed_iters;
   op.max_iter = op.fixed > 0 ? op.fixed : o->max_iter;
@@ -1218,23 +1218,33 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   const bool plain = (op.solver == INFOESRF_SOLVER_PLAIN);
   const bool od = in.odom();
   void* Vbuf = od ? pl.bf.V : nullptr;
-  // the persistent finish: FP64 inner PCG whose applies it can do in place
-  // (each workgroup reads the whole band or S once per iteration, so only small ones qualify:
-  // at most 512 KiB, which stays in the L2 of every XCD)
+  // the persistent PCG: FP64 inner PCG whose applies it can do in place (each workgroup reads
+  // the whole band or S once per iteration, so only those that stay in the L2 of every XCD
+  // qualify: at most 1 MiB)
   const double tail_bytes =
       in.sd ? 8.0 * in.m * in.m : 8.0 * in.m * (2 * in.go.bz + 1) * (2 * in.go.bx + 1);
-  const bool tail_ok = op.tail > 0 && op.host_sync && fp64_inner && !plain && in.m <= 4096 &&
-                       ((in.obs && in.band && in.bandO) || (in.sd && in.Sd)) && tail_bytes <= 512.0 * 1024;
   TailApply tap{};
-  if (tail_ok) {
-    tap.kind = in.sd ? 1 : 0;
-    tap.g = in.go;
-    tap.band = static_cast<const double*>(in.bandO);
-    tap.ldb = ld64(in.m);
-    tap.S = in.Sd;
-    tap.lds = in.lds;
-    tap.m = in.m;
-  }
+  tap.kind = in.sd ? 1 : 0;
+  tap.g = in.go;
+  tap.band = static_cast<const double*>(in.bandO);
+  tap.ldb = ld64(in.m);
+  tap.S = in.Sd;
+  tap.lds = in.lds;
+  tap.m = in.m;
+  const bool tail_ok = op.tail > 0 && fp64_inner && !plain && in.m <= 4096 &&
+                       ((in.obs && in.band && in.bandO) || (in.sd && in.Sd)) && tail_bytes <= 1024.0 * 1024 &&
+                       tail_fits(tap);
+  // the queue hands out the smallest shifts (the longest solves) first
+  auto run_tail = [&](int32_t* list, const int32_t* count, int32_t* spare, int64_t bound) -> int {
+    const int32_t* q = list;
+    if (bound <= 4096) {
+      IE_HIP(launch_order_by_shift(list, count, sy.sigma, bound, spare, st));
+      q = spare;
+    }
+    IE_HIP(launch_fill_i32(sy.qctr, 0, 1, st));
+    IE_HIP(pcg_tail_timed(ps, lmp, tap, q, count, sy.qctr, bound, st));
+    return 0;
+  };
   const int64_t ldr = ld64(od ? in.m : in.n);
   int32_t h_nact = (int32_t)S;
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
@@ -1278,6 +1288,13 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
                             in.P->r_var, in.n, st));
     std::swap(act_c, act_n);
     std::swap(nact_c, nact_n);
+    if (tail_ok && hint <= op.tail) {
+      // few enough systems from the start (without host polling, hint is the system count): one
+      // persistent launch runs every iteration
+      IE_TRY(run_tail(act_c, nact_c, act_n, hint));
+      IE_HIP(launch_axpy(sy.u, sy.x, flat, st));
+      continue;
+    }
     LivePoll poll;
     if (op.host_sync) IE_TRY(poll.init());
     for (int it = 1; it <= op.max_iter; ++it) {
@@ -1305,8 +1322,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
           if (!plain) hint = seen;  // compacted lists hold exactly the live systems
           if (tail_ok && seen <= op.tail) {
             // few systems left: one persistent launch iterates each of them to the end
-            IE_HIP(launch_fill_i32(sy.qctr, 0, 1, st));
-            IE_HIP(launch_pcg_tail(ps, lmp, tap, act_c, nact_c, sy.qctr, seen, st));
+            IE_TRY(run_tail(act_c, nact_c, act_n, seen));
             break;
           }
         }
@@ -1886,6 +1902,9 @@ int infoesrf_update_batched(const infoesrf_problem* probs, int32_t count, const 
   else infoesrf_default_opts(&o);
   const bool per_lattice = o.apply_domain == INFOESRF_DOMAIN_OBS_LATTICE;
   IE_CHECK(!per_lattice || lattices, INFOESRF_ERR_INVALID_ARG, "the observed-lattice domain needs lattices[count]");
+  // concurrent instances share the GPU: the persistent kernel by default only finishes each
+  // instance's last 64 systems
+  if (o.tail_systems == 0) o.tail_systems = 64;
   std::vector<infoesrf_opts> oj(count, o);
   if (per_lattice)
     for (int j = 0; j < count; ++j) oj[j].lattice = lattices[j];

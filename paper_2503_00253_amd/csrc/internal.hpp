@@ -65,6 +65,29 @@ struct Grid {
 // Precision of a covariance apply.
 enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
 
+// ---------------------------------------------------------------- wavefront sums
+// A double moved across lanes by a DPP pattern (both 32-bit halves), lanes of rows outside
+// ROWMASK reading zero.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_f64(double x) {
+  const long long v = __builtin_bit_cast(long long, x);
+  const int lo = (int)(v & 0xffffffffll), hi = (int)(v >> 32);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)h2 << 32) | (unsigned)l2);
+}
+// Sum over the 64 lanes of a wavefront in a fixed order (pairs, quads, half rows, rows of 16,
+// then the four rows), held by lane 63: register-to-register moves instead of LDS shuffles.
+__device__ inline double wave_sum_dpp(double x) {
+  x += dpp_f64<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+  x += dpp_f64<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+  x += dpp_f64<0x141, 0xF>(x);  // row_half_mirror
+  x += dpp_f64<0x140, 0xF>(x);  // row_mirror
+  x += dpp_f64<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_f64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 // ---------------------------------------------------------------- kernels (launchers)
 // All launchers enqueue on `st` and return hipError_t of the launch.
 
@@ -316,6 +339,16 @@ hipError_t launch_pcg_fused(Prec prec, const PCGState& s, const LMP& lmp, int mo
                             hipStream_t st);
 hipError_t launch_pcg_tail(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
                            const int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st);
+// launch_pcg_tail with the measurement hook (profile slot INFOESRF_PROF_TAIL).
+hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
+                          const int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st);
+// Whether launch_pcg_tail takes this apply: m <= 4096, the padded lattice (or m values) within
+// its LDS budget, at most one wrapped copy per side along periodic axes.
+bool tail_fits(const TailApply& ap);
+// out = the list (act, *nact) ordered by increasing shift, ties by position; capacity (an upper
+// bound of *nact) <= 4096.
+hipError_t launch_order_by_shift(const int32_t* act, const int32_t* nact, const double* sigma, int64_t capacity,
+                                 int32_t* out, hipStream_t st);
 // The fused PCG step with the measurement hook (profile slot INFOESRF_PROF_PCG); arguments as
 // launch_pcg_fused.
 hipError_t pcg_fused_timed(Prec prec, const PCGState& s, const LMP& lmp, int mode, int obs_domain, int plain,

@@ -106,17 +106,15 @@ __global__ void k_apply_finish(int obs_domain, const double* __restrict__ P, int
 
 // --------------------------------------------------------------- fused PCG iteration
 
-// Sum over the workgroup (256 threads) of W values per thread; fixed tree (shuffles within a
+// Sum over the workgroup (256 threads) of W values per thread; fixed tree (DPP sums within a
 // wavefront, then the four wavefronts in order).  Result broadcast to every thread in out[].
 template <int W>
 __device__ inline void block_sum(const double* v, double (*sred)[4], double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int j = 0; j < W; ++j) {
-    double x = v[j];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    if (lane == 0) sred[j][wave] = x;
+    const double x = wave_sum_dpp(v[j]);
+    if (lane == 63) sred[j][wave] = x;
   }
   __syncthreads();
 #pragma unroll
@@ -130,10 +128,8 @@ __device__ inline void block_sum_lds(const double* v, double (*sred)[4], double*
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int j = 0; j < W; ++j) {
-    double x = v[j];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    if (lane == 0) sred[j][wave] = x;
+    const double x = wave_sum_dpp(v[j]);
+    if (lane == 63) sred[j][wave] = x;
   }
   __syncthreads();
   if ((int)threadIdx.x < W) {

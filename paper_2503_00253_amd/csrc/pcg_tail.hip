@@ -1,94 +1,195 @@
-// Persistent finish of the batched PCG: once few systems are left, one launch finishes them.
+// Persistent PCG: one launch iterates each listed system to the end.
 //
-// After most of the Q N systems have converged, the last ones (the smallest shifts) still need
-// tens of iterations, and every iteration costs two launches (the batched apply of S and the
-// fused PCG step) whose fixed latency no longer shrinks with the work.  Here each workgroup takes
-// a system from a work queue and iterates it to convergence on its own: its direction lives in
-// LDS, its iterate and residual in registers, and the apply of S is done in place, from the
-// explicit band of the localized covariance on the observed lattice or from the dense m x m S.
-// The PCG step and the limited-memory preconditioner (Appendix E) are the same arithmetic as the
-// fused step.  Every workgroup leaves when the queue is empty, and every system's loop ends at
-// convergence, breakdown or the iteration cap.
+// In the batched loop every PCG iteration costs two launches (the batched apply of S and the
+// fused PCG step) and a round trip of x, r and p through HBM, whatever the number of live
+// systems.  Here each workgroup takes a system from a work queue and iterates it to convergence
+// on its own: the iterate, residual and direction stay in registers, the direction also in LDS,
+// and the apply of S is done in place, from the explicit band of the localized covariance on the
+// observed lattice or from the dense m x m S.  Each workgroup streams the band (or S) once per
+// iteration from L2, so the apply trades L2 bandwidth for the launches and the HBM round trips;
+// it pays when that matrix is small enough to stay in every XCD's L2.  The PCG step and the
+// limited-memory preconditioner (Appendix E) are the same arithmetic as the fused step.  Every
+// workgroup leaves when the queue is empty, and every system's loop ends at convergence,
+// breakdown or the iteration cap.
+//
+// The band apply reads the direction from a padded copy of the observed lattice in LDS: bz rows
+// above and below and bx columns left and right of the nz x nx lattice, holding the wrapped
+// values along periodic axes (copied from the interior after each update) and zeros elsewhere, so the neighbour (z + li - bz, x + d - bx) of
+// lattice point (z, x) sits at (z + li) * Wp + x + d with no wrap or bounds test, and a thread
+// walks a stencil row through consecutive LDS words.  The band values are loaded a chunk at a
+// time ahead of their use, to keep many loads in flight per wavefront.
 #include "internal.hpp"
 
 namespace infoesrf {
 
 namespace {
 
-constexpr int kTailThreads = 256;
 constexpr int kTailMaxM = 4096;
+// dynamic LDS for the (padded) direction, in doubles
+constexpr int64_t kTailPadMax = 6144;
 
-__device__ inline int tail_wrap(int a, int n) {
-  a %= n;
-  return a < 0 ? a + n : a;
-}
-
-// Workgroup sums of W values per thread (shuffles in a wavefront, the four wavefronts in order),
-// written once to LDS.
-template <int W>
-__device__ inline void tail_sum(const double* v, double (*sred)[4], double* out) {
+// Workgroup sums of Wn values per thread: DPP sums in a wavefront, then the NT / 64 wavefront
+// partials in order (a fixed tree: bit-reproducible).  tail_sum1 returns its one sum to every
+// thread; tail_sums writes sum j to out_lds[j] (thread j) and returns after a second barrier.
+// sred must not be rewritten before every thread has passed a later barrier.
+template <int Wn, int NT>
+__device__ inline void tail_partials(const double* v, double (*sred)[NT / 64]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j < W; ++j) {
-    double x = v[j];
+  for (int j = 0; j < Wn; ++j) {
+    const double x = wave_sum_dpp(v[j]);
+    if (lane == 63) sred[j][wave] = x;
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ inline double tail_sum1(double v, double (*sred)[NT / 64]) {
+  tail_partials<1, NT>(&v, sred);
+  double t = sred[0][0];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    if (lane == 0) sred[j][wave] = x;
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < W) {
+  for (int w = 1; w < NT / 64; ++w) t += sred[0][w];
+  return t;
+}
+
+template <int Wn, int NT>
+__device__ inline void tail_sums(const double* v, double (*sred)[NT / 64], double* out_lds) {
+  tail_partials<Wn, NT>(v, sred);
+  if ((int)threadIdx.x < Wn) {
     const int j = threadIdx.x;
-    out[j] = ((sred[j][0] + sred[j][1]) + sred[j][2]) + sred[j][3];
+    double t = sred[j][0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) t += sred[j][w];
+    out_lds[j] = t;
   }
   __syncthreads();
 }
 
-// (S p)_r with p in LDS: banded product on the observed lattice, or row r of the dense S.
-__device__ inline double tail_apply_row(const TailApply& ap, const double* sp, int64_t r) {
-  double acc = 0.0;
-  if (ap.kind == 1) {
-    for (int64_t k = 0; k < ap.m; ++k) acc += ap.S[k * ap.lds + r] * sp[k];
-    return acc;
-  }
-  const Grid& g = ap.g;
-  const int z = (int)(r / g.nx), x = (int)(r % g.nx);
-  const int w = 2 * g.bx + 1;
-  for (int li = 0; li < 2 * g.bz + 1; ++li) {
-    int zz = z + li - g.bz;
-    if (g.pz) zz = tail_wrap(zz, g.nz);
-    else if (zz < 0 || zz >= g.nz) continue;
-    const double* brow = ap.band + (int64_t)(li * w) * ap.ldb + r;
-    const double* prow = sp + (int64_t)zz * g.nx;
-    for (int d = 0; d < w; ++d) {
-      int kx = x - g.bx + d;
-      if (g.px) kx = tail_wrap(kx, g.nx);
-      else if (kx < 0 || kx >= g.nx) continue;  // the band entry is 0 there
-      acc += brow[(int64_t)d * ap.ldb] * prow[kx];
-    }
-  }
-  return acc;
+// Raw buffer loads: a descriptor over the whole array (reads past its end return zero), a
+// per-lane byte offset in one vector register and a uniform byte offset in a scalar register, so
+// holding a load's address across iterations costs no more than its row's offset.
+__device__ inline __amdgpu_buffer_rsrc_t tail_rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline double tail_ld8(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+__device__ inline float tail_ld4(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
 }
 
-template <int P, int RPT>
-__global__ __launch_bounds__(kTailThreads) void k_pcg_tail(PCGState st, LMP lmp, TailApply ap,
-                                                           const int32_t* __restrict__ act,
-                                                           const int32_t* __restrict__ nact,
-                                                           int32_t* __restrict__ qctr) {
+// Whether the kernel keeps the thread's rows of the FP32 Ritz bases in registers.
+__host__ __device__ constexpr bool tail_caches_ritz(int P, int RPT, int NT) {
+  return P > 0 && RPT * P <= 24 && NT < 1024;
+}
+
+// Rows of a thread: pairs of adjacent rows, 2 (tid + NT jj) + b for jj < RPT / 2, b in {0, 1}, so
+// that one 16-byte load brings a band entry of both rows.
+template <int NT>
+__device__ inline int tail_row(int tid, int j) {
+  return 2 * (tid + NT * (j >> 1)) + (j & 1);
+}
+
+__device__ inline double2 tail_ld16(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+}
+
+// Halo cell t (of the nh cells that hold wrapped values) of the padded lattice: sets its position
+// and that of the interior cell it copies; false where the cell stays zero (a corner past an axis
+// that is not periodic).  Cells first along periodic z (2 bz rows of Wp), then along periodic x
+// (nz rows of 2 bx).  bz <= nz and bx <= nx along periodic axes (checked by the launcher).
+__device__ inline bool tail_halo(const Grid& g, int Wp, int t, int& dst, int& src) {
+  const int nzh = g.pz ? 2 * g.bz * Wp : 0;
+  int zz, xx;
+  if (t < nzh) {
+    const int row = t / Wp;
+    zz = row < g.bz ? row : row + g.nz;
+    xx = t % Wp;
+  } else {
+    const int t2 = t - nzh, c = t2 % (2 * g.bx);
+    zz = g.bz + t2 / (2 * g.bx);
+    xx = c < g.bx ? c : c + g.nx;
+  }
+  int z = zz - g.bz, x = xx - g.bx;
+  if (z < 0) z += g.nz;
+  else if (z >= g.nz) z -= g.nz;
+  if (x < 0 || x >= g.nx) {
+    if (!g.px) return false;
+    x = x < 0 ? x + g.nx : x - g.nx;
+  }
+  dst = zz * Wp + xx;
+  src = (z + g.bz) * Wp + x + g.bx;
+  return true;
+}
+
+template <int P, int RPT, int NT>
+__global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply ap,
+                                                 const int32_t* __restrict__ act, const int32_t* __restrict__ nact,
+                                                 int32_t* __restrict__ qctr, int phi_lds) {
   constexpr int W = 2 * P + 1;
-  __shared__ double sred[W][4];
+  constexpr int NW = NT / 64;
+  static_assert(RPT % 2 == 0, "rows come in pairs");
+  // band (or S) entries per chunk: RPT / 2 * CH 16-byte loads in flight per thread
+  constexpr int CH = RPT >= 4 ? 8 : 16;
+  // the Ritz vectors of the thread's rows stay in registers when they fit
+  constexpr bool kCache = tail_caches_ritz(P, RPT, NT);
+  constexpr int kC = kCache ? RPT * P : 1;
+  __shared__ double sred1[1][NW];
+  __shared__ double sredW[W][NW];
   __shared__ double sG[3 * P * P + P + 1];
   __shared__ double scoef[2 * P + 2];
   __shared__ double sdot[W];
-  __shared__ double sp[kTailMaxM];
   __shared__ int s_idx;
+  // padded direction (band) or direction (dense S); then, when phi_lds, the FP32 Ritz bases
+  extern __shared__ double sp[];
   const int tid = threadIdx.x;
   const int64_t m = st.m;
+  const bool band = ap.kind == 0;
+  const Grid g = ap.g;
+  const int w = 2 * g.bx + 1, h = 2 * g.bz + 1;
+  const int Wp = band ? g.nx + 2 * g.bx : 0;
+  const int npad = band ? (g.nz + 2 * g.bz) * Wp : (int)m;
+  // halo cells holding wrapped values
+  const int nh = band ? (g.pz ? 2 * g.bz * Wp : 0) + (g.px ? g.nz * 2 * g.bx : 0) : 0;
+  // stencil rows and entries per stencil row of the apply (the dense S: one row of m)
+  const int hh = band ? h : 1, ww = band ? w : (int)m;
   if (P > 0) {
-    for (int o = tid; o < 3 * P * P; o += kTailThreads) sG[o] = lmp.G[o];
+    for (int o = tid; o < 3 * P * P; o += NT) sG[o] = lmp.G[o];
     if (tid < P) sG[3 * P * P + tid] = lmp.theta[tid];
   }
+  // zeros in the halo along axes that are not periodic (never rewritten)
+  for (int o = tid; o < npad; o += NT) sp[o] = 0.0;
   const double dmin = (P > 0) ? *lmp.dmin : 0.0;
   const int na = *nact;
+  // descriptors of the band (or S) and the FP32 Ritz bases; byte strides of their columns
+  const __amdgpu_buffer_rsrc_t rsA =
+      band ? tail_rsrc(ap.band, (int64_t)h * w * ap.ldb * 8) : tail_rsrc(ap.S, m * ap.lds * 8);
+  const uint32_t colA = (uint32_t)((band ? ap.ldb : ap.lds) * 8);
+  const __amdgpu_buffer_rsrc_t rsF = tail_rsrc(lmp.Phi32, (int64_t)P * lmp.ld * 4);
+  const __amdgpu_buffer_rsrc_t rsG = tail_rsrc(lmp.SPhi32, (int64_t)P * lmp.ld * 4);
+  const uint32_t colF = (uint32_t)(lmp.ld * 4);
+  float* sF = reinterpret_cast<float*>(sp + npad);  // Phi32 (P x m), when phi_lds
+  float* sH = sF + (int64_t)P * m;                   // SPhi32 (P x m)
+  if (phi_lds) {
+    for (int o = tid; o < P * (int)m; o += NT) {
+      const int l = o / (int)m, r = o % (int)m;
+      sF[o] = tail_ld4(rsF, (uint32_t)r * 4, l * colF);
+      sH[o] = tail_ld4(rsG, (uint32_t)r * 4, l * colF);
+    }
+  }
+  // the corner of each row's stencil in the padded grid, and the row's byte offset in a column
+  int corner[RPT];
+  uint32_t roff[RPT / 2];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int r = tail_row<NT>(tid, j);
+    corner[j] = (band && r < m) ? (r / g.nx) * Wp + r % g.nx : 0;
+  }
+  // byte offset of each pair in a column (pairs past m read the last pair and are discarded;
+  // an odd m leaves its last pair one row into the column's padding, ld >= m + 1)
+#pragma unroll
+  for (int jj = 0; jj < RPT / 2; ++jj)
+    roff[jj] = (uint32_t)min<int64_t>(tail_row<NT>(tid, 2 * jj), (m - 1) & ~(int64_t)1) * (uint32_t)sizeof(double);
   __syncthreads();
   for (;;) {
     if (tid == 0) s_idx = atomicAdd(qctr, 1);
@@ -105,66 +206,132 @@ __global__ __launch_bounds__(kTailThreads) void k_pcg_tail(PCGState st, LMP lmp,
     double rz = st.rz[s];
     int it = st.iters[s];
     double rv[RPT], pv[RPT], xv[RPT];
+    float ph[kC], sph[kC];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-      const int64_t r = tid + kTailThreads * j;
+      const int64_t r = tail_row<NT>(tid, j);
       const bool ok = r < m;
       rv[j] = ok ? st.r[base + r] : 0.0;
       pv[j] = ok ? st.p[base + r] : 0.0;
       xv[j] = ok ? st.x[base + r] : 0.0;
+      if (kCache) {
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+          ph[(j * P + l) % kC] = ok ? tail_ld4(rsF, (uint32_t)r * 4, l * colF) : 0.f;
+          sph[(j * P + l) % kC] = ok ? tail_ld4(rsG, (uint32_t)r * 4, l * colF) : 0.f;
+        }
+      }
     }
     int state = 0;
     double relres = 0.0;
     for (;;) {
+      // the direction into LDS, then its wrapped copies
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
-        const int64_t r = tid + kTailThreads * j;
-        if (r < m) sp[r] = pv[j];
+        const int r = tail_row<NT>(tid, j);
+        if (r < m) sp[band ? corner[j] + g.bz * Wp + g.bx : r] = pv[j];
       }
       __syncthreads();
+      if (nh > 0) {
+        for (int t = tid; t < nh; t += NT) {
+          int dst, src;
+          if (tail_halo(g, Wp, t, dst, src)) sp[dst] = sp[src];
+        }
+        __syncthreads();
+      }
+      // q = (1 + sigma) p + S p
+      // A row of the band is h stencil rows of w consecutive entries, both in the band (columns
+      // of colA bytes) and in the padded direction; the dense S is one stencil row of m entries.
+      // Each stencil row goes in chunks of CH entries whose loads, for all the thread's row
+      // pairs, are issued ahead of their multiply-adds (16 bytes a lane: the entry for both rows
+      // of a pair; uniform column offsets in scalar registers, the pair a per-lane offset, the
+      // direction at immediate LDS offsets), then one chunk for the rest of the row, whose
+      // missing entries repeat the last one and are weighted by zero.
       double qv[RPT];
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) qv[j] = 0.0;
+      for (int li = 0; li < hh; ++li) {
+        uint32_t so = (uint32_t)(li * ww) * colA;
+        const int lrow = li * Wp;
+        int d0 = 0;
+        for (; d0 + CH <= ww; d0 += CH) {
+          double2 bv[RPT / 2][CH];
+#pragma unroll
+          for (int jj = 0; jj < RPT / 2; ++jj)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)k * colA);
+#pragma unroll
+          for (int jj = 0; jj < RPT / 2; ++jj) {
+            const double* p0 = sp + corner[2 * jj] + lrow + d0;
+            const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+              qv[2 * jj] += bv[jj][k].x * p0[k];
+              qv[2 * jj + 1] += bv[jj][k].y * p1[k];
+            }
+          }
+          so += (uint32_t)CH * colA;
+        }
+        if (d0 < ww) {
+          const int last = ww - d0 - 1;
+          double2 bv[RPT / 2][CH];
+#pragma unroll
+          for (int jj = 0; jj < RPT / 2; ++jj)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)min(k, last) * colA);
+#pragma unroll
+          for (int jj = 0; jj < RPT / 2; ++jj) {
+            const double* p0 = sp + corner[2 * jj] + lrow + d0;
+            const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+              const int kk = min(k, last);
+              qv[2 * jj] += (k <= last ? bv[jj][k].x : 0.0) * p0[kk];
+              qv[2 * jj + 1] += (k <= last ? bv[jj][k].y : 0.0) * p1[kk];
+            }
+          }
+        }
+      }
       double pq = 0.0;
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
-        const int64_t r = tid + kTailThreads * j;
-        qv[j] = 0.0;
-        if (r < m) {
-          qv[j] = sig1 * pv[j] + tail_apply_row(ap, sp, r);
-          pq += pv[j] * qv[j];
-        }
+        qv[j] += sig1 * pv[j];
+        pq += pv[j] * qv[j];
       }
-      double tot[1];
-      tail_sum<1>(&pq, sred, sdot);
-      tot[0] = sdot[0];
-      if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
-        if (tid == 0) atomicOr(st.flags, isfinite(tot[0]) ? kFlagNotSPD : kFlagNumeric);
+      const double tot = tail_sum1<NT>(pq, sred1);
+      if (!(tot > 0.0) || !isfinite(tot)) {
+        if (tid == 0) atomicOr(st.flags, isfinite(tot) ? kFlagNotSPD : kFlagNumeric);
         state = 2;
         break;
       }
-      const double alpha = rz / tot[0];
+      const double alpha = rz / tot;
       double acc[W];
 #pragma unroll
       for (int j = 0; j < W; ++j) acc[j] = 0.0;
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
-        const int64_t r = tid + kTailThreads * j;
+        const int64_t r = tail_row<NT>(tid, j);
         if (r < m) {
           xv[j] += alpha * pv[j];
           rv[j] -= alpha * qv[j];
           acc[0] += rv[j] * rv[j];
 #pragma unroll
           for (int l = 0; l < P; ++l) {
-            acc[1 + l] += (double)lmp.Phi32[l * lmp.ld + r] * rv[j];
-            acc[1 + P + l] += (double)lmp.SPhi32[l * lmp.ld + r] * rv[j];
+            const double a = kCache ? (double)ph[(j * P + l) % kC]
+                                    : (double)(phi_lds ? sF[l * m + r] : tail_ld4(rsF, (uint32_t)r * 4, l * colF));
+            const double b = kCache ? (double)sph[(j * P + l) % kC]
+                                    : (double)(phi_lds ? sH[l * m + r] : tail_ld4(rsG, (uint32_t)r * 4, l * colF));
+            acc[1 + l] += a * rv[j];
+            acc[1 + P + l] += b * rv[j];
           }
         }
       }
       ++it;
-      __syncthreads();  // sdot is rewritten below
-      tail_sum<W>(acc, sred, sdot);
-      const double rn = sqrt(sdot[0]);
+      tail_sums<W, NT>(acc, sredW, sdot);
+      const double* dt = sdot;
+      const double rn = sqrt(dt[0]);
       relres = bn > 0.0 ? rn / bn : 0.0;
-      if (!isfinite(sdot[0])) {
+      if (!isfinite(dt[0])) {
         if (tid == 0) atomicOr(st.flags, kFlagNumeric);
         state = 2;
         break;
@@ -180,10 +347,10 @@ __global__ __launch_bounds__(kTailThreads) void k_pcg_tail(PCGState st, LMP lmp,
       // limited-memory preconditioner coefficients, as in the fused step:
       //   c1 = Theta^{-1} Phi^T r,  c2 = Theta^{-1} [(C Phi)^T r - (C Phi)^T (C Phi) c1],
       //   gamma = (1 + sigma - beta_L) c1 + c2,  z = r - S Phi c1 - Phi gamma
-      double rzn = sdot[0];
+      double rzn = dt[0];
       if (P > 0) {
         const double* sth = sG + 3 * P * P;
-        if (tid < P) scoef[tid] = sdot[1 + tid] / (sig1 + sth[tid]);
+        if (tid < P) scoef[tid] = dt[1 + tid] / (sig1 + sth[tid]);
         __syncthreads();
         if (tid < P) {
           const double* Gpp = sG;
@@ -193,12 +360,12 @@ __global__ __launch_bounds__(kTailThreads) void k_pcg_tail(PCGState st, LMP lmp,
           for (int l = 0; l < P; ++l)
             mc += (Gss[tid * P + l] + sig1 * (Gps[tid * P + l] + Gps[l * P + tid]) + sig1 * sig1 * Gpp[tid * P + l]) *
                   scoef[l];
-          const double c2 = (sdot[1 + P + tid] + sig1 * sdot[1 + tid] - mc) / (sig1 + sth[tid]);
+          const double c2 = (dt[1 + P + tid] + sig1 * dt[1 + tid] - mc) / (sig1 + sth[tid]);
           const double beta_l = sig1 + dmin;
           scoef[P + tid] = (sig1 - beta_l) * scoef[tid] + c2;
         }
         __syncthreads();
-        for (int l = 0; l < P; ++l) rzn -= sdot[1 + P + l] * scoef[l] + sdot[1 + l] * scoef[P + l];
+        for (int l = 0; l < P; ++l) rzn -= dt[1 + P + l] * scoef[l] + dt[1 + l] * scoef[P + l];
       }
       if (!(rzn > 0.0) || !isfinite(rzn)) {
         if (tid == 0) atomicOr(st.flags, isfinite(rzn) ? kFlagNotSPD : kFlagNumeric);
@@ -209,20 +376,26 @@ __global__ __launch_bounds__(kTailThreads) void k_pcg_tail(PCGState st, LMP lmp,
       rz = rzn;
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
-        const int64_t r = tid + kTailThreads * j;
+        const int64_t r = tail_row<NT>(tid, j);
         if (r < m) {
           double z = rv[j];
 #pragma unroll
-          for (int l = 0; l < P; ++l)
-            z -= (double)lmp.SPhi32[l * lmp.ld + r] * scoef[l] + (double)lmp.Phi32[l * lmp.ld + r] * scoef[P + l];
+          for (int l = 0; l < P; ++l) {
+            const double a = kCache ? (double)ph[(j * P + l) % kC]
+                                    : (double)(phi_lds ? sF[l * m + r] : tail_ld4(rsF, (uint32_t)r * 4, l * colF));
+            const double b = kCache ? (double)sph[(j * P + l) % kC]
+                                    : (double)(phi_lds ? sH[l * m + r] : tail_ld4(rsG, (uint32_t)r * 4, l * colF));
+            z -= b * scoef[l] + a * scoef[P + l];
+          }
           pv[j] = z + beta * pv[j];
         }
       }
-      __syncthreads();  // the LDS direction and scoef are rewritten in the next iteration
+      // no barrier here: every thread read the LDS direction before the first reduction's
+      // barrier, and sred1, sredW, sdot and scoef are rewritten only after the next direction's
     }
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-      const int64_t r = tid + kTailThreads * j;
+      const int64_t r = tail_row<NT>(tid, j);
       if (r < m) {
         st.x[base + r] = xv[j];
         st.r[base + r] = rv[j];
@@ -230,6 +403,12 @@ __global__ __launch_bounds__(kTailThreads) void k_pcg_tail(PCGState st, LMP lmp,
       }
     }
     if (tid == 0) {
+      if (st.prof.vectors) {
+        const int done_its = it - st.iters[s];
+        atomicAdd(st.prof.vectors, (unsigned long long)done_its);
+        atomicAdd(st.prof.flops, (double)done_its * st.prof.flops_per_vector);
+        atomicAdd(st.prof.bytes, st.prof.bytes_per_vector);
+      }
       st.rz[s] = rz;
       st.iters[s] = it;
       st.relres[s] = relres;
@@ -239,32 +418,107 @@ __global__ __launch_bounds__(kTailThreads) void k_pcg_tail(PCGState st, LMP lmp,
   }
 }
 
+// The listed systems in order of increasing shift (the slowest first), ties by list position:
+// out[rank] = act[i].  One workgroup, keys in LDS; *nact <= kOrderMax (checked by the launcher
+// against the list's capacity).
+constexpr int kOrderMax = 4096;
+__global__ __launch_bounds__(1024) void k_order_by_shift(const int32_t* __restrict__ act,
+                                                         const int32_t* __restrict__ nact,
+                                                         const double* __restrict__ sigma,
+                                                         int32_t* __restrict__ out) {
+  __shared__ double key[kOrderMax];
+  const int n = min(*nact, kOrderMax);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) key[i] = sigma[act[i]];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double ki = key[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double kj = key[j];
+      rank += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+    }
+    out[rank] = act[i];
+  }
+}
+
+// two rows a thread (one pair) up to 1024 rows, on 128, 256 or 512 threads; four rows on 512 or
+// 1024 threads beyond
+int tail_threads(int64_t m) { return m > 2048 ? 1024 : (m > 512 ? 512 : (m > 256 ? 256 : 128)); }
+
+size_t tail_lds_bytes(const TailApply& ap) {
+  const int64_t npad = ap.kind == 0 ? (int64_t)(ap.g.nz + 2 * ap.g.bz) * (ap.g.nx + 2 * ap.g.bx) : ap.m;
+  return (size_t)npad * sizeof(double);
+}
+
+// LDS the launcher may give one workgroup (a 1024-thread workgroup occupies its CU alone)
+constexpr size_t kTailLdsBig = 150 * 1024;
+
+template <int P, int RPT, int NT>
+hipError_t tail_go(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act, const int32_t* nact,
+                   int32_t* qctr, int64_t grid, hipStream_t st) {
+  const void* fn = (const void*)k_pcg_tail<P, RPT, NT>;
+  size_t lds = tail_lds_bytes(ap);
+  // the Ritz bases in LDS when the kernel does not keep them in registers and there is room
+  const size_t phi = (size_t)8 * P * s.m;
+  const int phi_lds = (P > 0 && !tail_caches_ritz(P, RPT, NT) && lds + phi <= kTailLdsBig) ? 1 : 0;
+  if (phi_lds) lds += phi;
+  static bool big = false;  // the attribute is set once per instantiation
+  if (lds > 64 * 1024 && !big) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailLdsBig);
+    if (e != hipSuccess) return e;
+    big = true;
+  }
+  // no more workgroups than can be resident at once: the others would only find the queue empty
+  int dev = 0, per_cu = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds);
+  if (e != hipSuccess) return e;
+  const int64_t resident = std::max<int64_t>((int64_t)per_cu * cus, 1);
+  const dim3 gdim((unsigned)std::max<int64_t>(std::min(grid, resident), 1)), b(NT);
+  hipLaunchKernelGGL((k_pcg_tail<P, RPT, NT>), gdim, b, lds, st, s, lmp, ap, act, nact, qctr, phi_lds);
+  return hipGetLastError();
+}
+
 template <int P>
 hipError_t tail_rows(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act, const int32_t* nact,
                      int32_t* qctr, int64_t grid, hipStream_t st) {
-  const int64_t rpt = (s.m + kTailThreads - 1) / kTailThreads;
-  const dim3 g((unsigned)std::max<int64_t>(grid, 1)), b(kTailThreads);
-#define IE_T(R)                                                                            \
-  do {                                                                                      \
-    hipLaunchKernelGGL((k_pcg_tail<P, R>), g, b, 0, st, s, lmp, ap, act, nact, qctr);        \
-    return hipGetLastError();                                                               \
-  } while (0)
-  if (rpt <= 1) IE_T(1);
-  if (rpt <= 2) IE_T(2);
-  if (rpt <= 4) IE_T(4);
-  if (rpt <= 8) IE_T(8);
-  if (rpt <= 16) IE_T(16);
-#undef IE_T
+  const int nt = tail_threads(s.m);
+  const int64_t rpt = (s.m + nt - 1) / nt;
+  if (nt == 128) return tail_go<P, 2, 128>(s, lmp, ap, act, nact, qctr, grid, st);
+  if (nt == 256) return tail_go<P, 2, 256>(s, lmp, ap, act, nact, qctr, grid, st);
+  if (nt == 1024) return tail_go<P, 4, 1024>(s, lmp, ap, act, nact, qctr, grid, st);
+  if (rpt <= 2) return tail_go<P, 2, 512>(s, lmp, ap, act, nact, qctr, grid, st);
+  if (rpt <= 4) return tail_go<P, 4, 512>(s, lmp, ap, act, nact, qctr, grid, st);
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
+bool tail_fits(const TailApply& ap) {
+  if (ap.m < 1 || ap.m > kTailMaxM) return false;
+  if (ap.kind == 0) {
+    const Grid& g = ap.g;
+    if (g.nz < 1 || g.nx < 1 || (int64_t)g.nz * g.nx != ap.m || g.bz < 0 || g.bx < 0) return false;
+    // one wrapped copy per side along a periodic axis
+    if ((g.pz && g.bz > g.nz) || (g.px && g.bx > g.nx)) return false;
+  }
+  return (int64_t)(tail_lds_bytes(ap) / sizeof(double)) <= kTailPadMax;
+}
+
+hipError_t launch_order_by_shift(const int32_t* act, const int32_t* nact, const double* sigma, int64_t capacity,
+                                 int32_t* out, hipStream_t st) {
+  if (capacity > kOrderMax || !act || !nact || !sigma || !out) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_order_by_shift, dim3(1), dim3(1024), 0, st, act, nact, sigma, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_pcg_tail(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
                            const int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st) {
-  if (s.m < 1 || s.m > kTailMaxM || !act || !nact || !qctr) return hipErrorInvalidValue;
-  if (ap.kind == 0 && (!ap.band || (int64_t)ap.g.nz * ap.g.nx != s.m)) return hipErrorInvalidValue;
-  if (ap.kind == 1 && (!ap.S || ap.m != s.m)) return hipErrorInvalidValue;
+  if (s.m < 1 || s.m > kTailMaxM || s.m != ap.m || !act || !nact || !qctr || !tail_fits(ap))
+    return hipErrorInvalidValue;
+  if (ap.kind == 0 && !ap.band) return hipErrorInvalidValue;
+  if (ap.kind == 1 && !ap.S) return hipErrorInvalidValue;
   if (lmp.p > 0 && (!lmp.Phi32 || !lmp.SPhi32 || !lmp.G || !lmp.theta || !lmp.dmin)) return hipErrorInvalidValue;
   switch (lmp.p) {
     case 0: return tail_rows<0>(s, lmp, ap, act, nact, qctr, grid, st);

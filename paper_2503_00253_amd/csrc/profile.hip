@@ -138,6 +138,22 @@ hipError_t pcg_fused_timed(Prec prec, const PCGState& s, const LMP& lmp, int mod
   });
 }
 
+hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
+                          const int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st) {
+  if (!g_prof.on) return launch_pcg_tail(s, lmp, ap, act, nact, qctr, grid, st);
+  // per system-iteration: the apply and the PCG step; per system: x, r, p read and written once;
+  // per launch: the band (or S) and the FP32 Ritz bases
+  const double m = (double)s.m, P = (double)lmp.p;
+  const double apply = ap.kind == 1 ? 2.0 * m * m : 2.0 * grid_nnz(ap.g);
+  const double matrix = ap.kind == 1 ? 8.0 * m * m : 8.0 * m * (2 * ap.g.bz + 1) * (2 * ap.g.bx + 1);
+  return timed(INFOESRF_PROF_TAIL, apply + m * (12.0 + 8.0 * P), 6.0 * 8.0 * m, matrix + 2.0 * 4.0 * m * P, st,
+               [&](const ProfDev* pd) {
+                 PCGState sp = s;
+                 sp.prof = pd ? *pd : ProfDev{};
+                 return launch_pcg_tail(sp, lmp, ap, act, nact, qctr, grid, st);
+               });
+}
+
 hipError_t cov_band_timed(Prec prec, const Grid& g, const void* band, int64_t ldb, const void* V, int64_t ldv,
                           int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, hipStream_t st,
                           int32_t* zc) {
@@ -190,8 +206,8 @@ extern "C" int infoesrf_profile_select(uint32_t mask) {
   return INFOESRF_OK;
 }
 
-extern "C" int infoesrf_profile_read(double ms[6], int64_t launches[6], int64_t vectors[6], double flops[6],
-                                     double bytes[6]) {
+extern "C" int infoesrf_profile_read(double ms[7], int64_t launches[7], int64_t vectors[7], double flops[7],
+                                     double bytes[7]) {
   clear_error();
   IE_CHECK(ms && launches && vectors && flops && bytes, INFOESRF_ERR_INVALID_ARG, "outputs must be non-NULL");
   std::lock_guard<std::mutex> lock(g_prof_mu);

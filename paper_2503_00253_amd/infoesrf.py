@@ -25,8 +25,8 @@ DOMAIN_STATE, DOMAIN_OBS_LATTICE = 0, 1
 START_ZERO, START_LEARNED = 0, 1
 COV_AUTO, COV_OPERATOR, COV_BAND = 0, 1, 2
 S_AUTO, S_OPERATOR, S_DENSE = 0, 1, 2
-PROF_OP_FP64, PROF_OP_FP32, PROF_OP_BF16, PROF_BAND_FP64, PROF_BAND_FP32, PROF_PCG = 0, 1, 2, 3, 4, 5
-PROF_SLOTS = 6
+PROF_OP_FP64, PROF_OP_FP32, PROF_OP_BF16, PROF_BAND_FP64, PROF_BAND_FP32, PROF_PCG, PROF_TAIL = 0, 1, 2, 3, 4, 5, 6
+PROF_SLOTS = 7
 CNT_APPLIES, CNT_APPLIES_FP64, CNT_ITERATIONS, CNT_SWEEPS = 0, 1, 2, 3
 CNT_FALLBACKS, CNT_NOT_CONVERGED, CNT_MAX_ITERS, CNT_STATUS = 4, 5, 6, 7
 NUM_COUNTERS = 8
@@ -649,8 +649,8 @@ def profile_select(slots):
 
 
 def profile_read():
-    """Per slot (PROF_*: operator FP64/FP32/BF16, band FP64/FP32): kernel ms, launches, vectors,
-    algorithmic FLOPs and algorithmic bytes of the covariance applies."""
+    """Per slot (PROF_*: operator FP64/FP32/BF16, band FP64/FP32, the fused PCG step, the persistent
+    PCG kernel): kernel ms, launches, vectors, algorithmic FLOPs and algorithmic bytes."""
     lib = library()
     D, I = C.c_double * PROF_SLOTS, C.c_int64 * PROF_SLOTS
     lib.infoesrf_profile_read.argtypes = [D, I, I, D, D]

@@ -63,15 +63,19 @@ def make_opts(domain, precision, P=None, **kw):
     return ie.default_opts(precision=precision, **kw)
 
 
-@pytest.mark.parametrize("domain,precision", [("state", ie.FP64), ("lattice", ie.MIXED_BF16),
-                                              ("lattice", ie.MIXED_FP32)])
-def test_batched_equals_single_instances(domain, precision):
+@pytest.mark.parametrize("domain,precision,tail", [("state", ie.FP64, 0), ("lattice", ie.FP64, 100000),
+                                                   ("lattice", ie.MIXED_BF16, 0), ("lattice", ie.MIXED_FP32, 0)])
+def test_batched_equals_single_instances(domain, precision, tail):
+    """Every instance of the batched call equals the single-instance call bit for bit, with the
+    batched call's default hand-over to the persistent kernel (the last 64 systems) or with every
+    system handed over after the first step."""
     probs = batch()
     Ps = [ie.Problem.from_synthetic(pr) for pr in probs]
     nodes = [ie.quadrature_elliptic(pr.Q, pr.ell) for pr in probs]
     lats = [P.lattice() for P in Ps] if domain == "lattice" else None
-    say("batched", domain, precision, [pr.name for pr in probs])
-    runner = ie.BatchedRunner(Ps, nodes, make_opts(domain, precision), ys=[pr.y for pr in probs], lattices=lats)
+    say("batched", domain, precision, tail, [pr.name for pr in probs])
+    runner = ie.BatchedRunner(Ps, nodes, make_opts(domain, precision, tail_systems=tail), ys=[pr.y for pr in probs],
+                              lattices=lats)
     code = runner.run()
     torch.cuda.synchronize()
     assert code == ie.OK
@@ -81,7 +85,7 @@ def test_batched_equals_single_instances(domain, precision):
     totals = np.zeros(ie.NUM_COUNTERS, dtype=np.int64)
     for j, (pr, P, (s, p)) in enumerate(zip(probs, Ps, nodes)):
         say("single", j, pr.name)
-        Xa, mu, s1, sm = run_single(P, pr, s, p, make_opts(domain, precision, P))
+        Xa, mu, s1, sm = run_single(P, pr, s, p, make_opts(domain, precision, P, tail_systems=tail or 64))
         assert np.array_equal(Xs[j].cpu().numpy(), Xa), (j, pr.name)
         assert np.array_equal(mus[j].cpu().numpy(), mu), (j, pr.name)
         S = len(s) * pr.N

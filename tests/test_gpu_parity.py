@@ -411,7 +411,8 @@ def test_autotune_records_choices_and_keeps_results():
 
 
 @pytest.mark.parametrize("form,domain", [("band", "lattice"), ("dense-s", "state"), ("dense-s", "lattice")])
-@pytest.mark.parametrize("case", ["gauss-n256-periodic", "2d-layers", "2d-periodic-z"])
+@pytest.mark.parametrize("case", ["gauss-n256-periodic", "ragged-1d-nonperiodic", "small-nx-periodic", "2d-layers",
+                                  "2d-periodic-z"])
 def test_persistent_finish_matches(case, form, domain):
     """The persistent finish (one workgroup per remaining system, apply in place) against the
     oracle and against the loop without it; tail_systems = S hands every system over at the first
@@ -431,3 +432,30 @@ def test_persistent_finish_matches(case, form, domain):
         outs[tail] = (got.cpu().numpy(), st.iters.copy())
     assert rel(outs[S][0], outs[-1][0]) < 1e-9
     assert np.max(np.abs(outs[S][1] - outs[-1][1])) <= 2
+    # the default hands every system to the persistent kernel after the first step
+    assert rel(outs[0][0], outs[S][0]) < 1e-12
+
+
+@pytest.mark.parametrize("n_ritz", [0, 4])
+@pytest.mark.parametrize("fixed", [0, 5])
+def test_persistent_variants(n_ritz, fixed):
+    """The persistent kernel without the preconditioner (p = 0) and with a fixed iteration count,
+    on an odd number of observations (the last row pair reaches into the column padding)."""
+    prob = CASES["ragged-1d-nonperiodic"]()
+    dp = dense_of(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    P = ie.Problem.from_synthetic(prob)
+    say("persistent variants", n_ritz, fixed, "m", P.m)
+    outs = {}
+    for tail in (-1, 0):
+        o = opts_for(prob, P, "lattice", "band", tail_systems=tail, n_ritz=n_ritz, fixed_iters=fixed)
+        got, st = ie.perturbation_update(P, s, p, o)
+        assert st.code == ie.OK
+        outs[tail] = (got.cpu().numpy(), st.iters.copy())
+    if fixed:
+        assert np.array_equal(outs[0][1], outs[-1][1])
+        assert rel(outs[0][0], outs[-1][0]) < 1e-9
+    else:
+        want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+        assert rel(outs[0][0], want) < 1e-6
+        assert np.max(np.abs(outs[0][1] - outs[-1][1])) <= 2
