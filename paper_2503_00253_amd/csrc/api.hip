@@ -1234,15 +1234,13 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   const bool tail_ok = op.tail > 0 && fp64_inner && !plain && in.m <= 4096 &&
                        ((in.obs && in.band && in.bandO) || (in.sd && in.Sd)) && tail_bytes <= 1024.0 * 1024 &&
                        tail_fits(tap);
-  // the queue hands out the smallest shifts (the longest solves) first
-  auto run_tail = [&](int32_t* list, const int32_t* count, int32_t* spare, int64_t bound) -> int {
-    const int32_t* q = list;
-    if (bound <= 4096) {
-      IE_HIP(launch_order_by_shift(list, count, sy.sigma, bound, spare, st));
-      q = spare;
-    }
+  // the queue hands out the live systems node by node, smallest shift (the longest solves) first;
+  // the perturbation systems share a shift per group of N members, the mean solve is one system
+  const int64_t grp = (S % in.N == 0 && S / in.N <= 4096) ? in.N : S;
+  auto run_tail = [&](int32_t* list, int32_t* count, int64_t bound) -> int {
+    IE_HIP(launch_order_live(sy.done, sy.sigma, S, grp, list, count, st));
     IE_HIP(launch_fill_i32(sy.qctr, 0, 1, st));
-    IE_HIP(pcg_tail_timed(ps, lmp, tap, q, count, sy.qctr, bound, st));
+    IE_HIP(pcg_tail_timed(ps, lmp, tap, list, count, sy.qctr, bound, st));
     return 0;
   };
   const int64_t ldr = ld64(od ? in.m : in.n);
@@ -1291,7 +1289,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
     if (tail_ok && hint <= op.tail) {
       // few enough systems from the start (without host polling, hint is the system count): one
       // persistent launch runs every iteration
-      IE_TRY(run_tail(act_c, nact_c, act_n, hint));
+      IE_TRY(run_tail(act_c, nact_c, hint));
       IE_HIP(launch_axpy(sy.u, sy.x, flat, st));
       continue;
     }
@@ -1322,7 +1320,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
           if (!plain) hint = seen;  // compacted lists hold exactly the live systems
           if (tail_ok && seen <= op.tail) {
             // few systems left: one persistent launch iterates each of them to the end
-            IE_TRY(run_tail(act_c, nact_c, act_n, seen));
+            IE_TRY(run_tail(act_c, nact_c, seen));
             break;
           }
         }

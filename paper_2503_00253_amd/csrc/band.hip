@@ -53,6 +53,78 @@ __global__ __launch_bounds__(256) void k_band_build(Grid g, const double* __rest
   band[(int64_t)j * ldb + r] = (T)v;
 }
 
+// The same entries on MFMA.  For a tile of 16 consecutive lattice points (z, x0 .. x0 + 15) and
+// one stencil row li, the dot products of their member rows Z[r, :] with those of the 16 + 2bx
+// points (z + li - bz, x0 - bx ..) of the neighbour layer are a 16 x (16 + 2bx) block of Z Z^T
+// (contraction over the N members), formed 16 columns at a time by v_mfma_f64_16x16x4f64 (the
+// block's four wavefronts take every fourth column tile).  The products on the band,
+// d = c - r + bx in [0, 2bx], go to an LDS tile [d][row], written out plane by plane (16
+// consecutive rows, 128 bytes) times the table weight.  Neighbours off a non-periodic grid enter
+// as zero rows of Z, so their entries are 0.  N <= 64 (the A fragments stay in registers) and
+// 16 (2bx + 1) doubles of LDS.
+typedef double band_d4 __attribute__((ext_vector_type(4)));
+constexpr int kBuildMaxN = 64;
+constexpr int kBuildMaxW = 511;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_band_build_mfma(Grid g, const double* __restrict__ Z, int64_t ldz, int N,
+                                                         T* __restrict__ band, int64_t ldb, int tiles_per_layer) {
+  extern __shared__ double btile[];  // [w][16]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int w = 2 * g.bx + 1;
+  const int li = blockIdx.y;
+  const int z = blockIdx.x / tiles_per_layer;
+  const int x0 = (blockIdx.x % tiles_per_layer) * 16;
+  int zz = z + li - g.bz;
+  bool zok = true;
+  if (g.pz) zz = wrap_idx(zz, g.nz);
+  else zok = zz >= 0 && zz < g.nz;
+  // v_mfma_f64_16x16x4f64: A lane l -> (row l%16, k l/16); B lane l -> (k l/16, col l%16);
+  // D register v of lane l -> (row 4v + l/16, col l%16)
+  const int i = lane & 15, kq = lane >> 4;
+  const int KS = (N + 3) / 4;
+  const bool rok = x0 + i < g.nx;
+  const int64_t r = (int64_t)z * g.nx + x0 + i;
+  double a[kBuildMaxN / 4];
+#pragma unroll
+  for (int ks = 0; ks < kBuildMaxN / 4; ++ks) {
+    const int k = 4 * ks + kq;
+    a[ks] = (k < N && rok) ? Z[(int64_t)k * ldz + r] : 0.0;
+  }
+  const int nct = (16 + 2 * g.bx + 15) / 16;
+  for (int ct = wave; ct < nct; ct += 4) {
+    int xc = x0 - g.bx + 16 * ct + i;
+    bool cok = zok;
+    if (g.px) xc = wrap_idx(xc, g.nx);
+    else cok = cok && xc >= 0 && xc < g.nx;
+    const int64_t c = (int64_t)zz * g.nx + xc;
+    double b[kBuildMaxN / 4];
+#pragma unroll
+    for (int ks = 0; ks < kBuildMaxN / 4; ++ks) {
+      const int k = 4 * ks + kq;
+      b[ks] = (ks < KS && k < N && cok) ? Z[(int64_t)k * ldz + c] : 0.0;
+    }
+    band_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < kBuildMaxN / 4; ++ks)
+      if (ks < KS) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + kq;
+      const int d = 16 * ct + i - row;
+      if (d >= 0 && d < w) btile[d * 16 + row] = acc[v];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < w * 16; t += 256) {
+    const int d = t >> 4, row = t & 15;
+    if (x0 + row < g.nx) {
+      const double l = g.table[li * w + d];
+      band[(int64_t)(li * w + d) * ldb + (int64_t)z * g.nx + x0 + row] = (T)(l * btile[t]);
+    }
+  }
+}
+
 // T[:, b] = band * V[:, b] for the listed columns b < B (B from Bdev when given).
 // Block: TX = 64 consecutive x of one layer (one lane each) x NSB systems (the four waves take
 // systems w, w + 4, ...).  For each stencil layer the block stages the V window
@@ -190,6 +262,19 @@ hipError_t launch_band_build(Prec prec, const Grid& g, const double* Z, int64_t 
   const int rows = g.nz * g.nx;
   const int nb = (2 * g.bz + 1) * (2 * g.bx + 1);
   if (!band || !Z || !g.table) return hipErrorInvalidValue;
+  const int w = 2 * g.bx + 1;
+  if (N <= kBuildMaxN && w <= kBuildMaxW) {
+    const int tpl = (g.nx + 15) / 16;
+    const dim3 grid((unsigned)(g.nz * tpl), (unsigned)(2 * g.bz + 1));
+    const size_t lds = (size_t)w * 16 * sizeof(double);
+    if (prec == Prec::F64)
+      hipLaunchKernelGGL((k_band_build_mfma<double>), grid, dim3(256), lds, st, g, Z, ldz, (int)N, (double*)band,
+                         ldb, tpl);
+    else
+      hipLaunchKernelGGL((k_band_build_mfma<float>), grid, dim3(256), lds, st, g, Z, ldz, (int)N, (float*)band, ldb,
+                         tpl);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((rows + 255) / 256), (unsigned)nb);
   if (prec == Prec::F64)
     hipLaunchKernelGGL((k_band_build<double>), grid, dim3(256), 0, st, g, Z, ldz, (int)N, (double*)band, ldb);

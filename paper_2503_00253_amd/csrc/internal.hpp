@@ -345,10 +345,11 @@ hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap
 // Whether launch_pcg_tail takes this apply: m <= 4096, the padded lattice (or m values) within
 // its LDS budget, at most one wrapped copy per side along periodic axes.
 bool tail_fits(const TailApply& ap);
-// out = the list (act, *nact) ordered by increasing shift, ties by position; capacity (an upper
-// bound of *nact) <= 4096.
-hipError_t launch_order_by_shift(const int32_t* act, const int32_t* nact, const double* sigma, int64_t capacity,
-                                 int32_t* out, hipStream_t st);
+// (act, *nact) = the live systems (done == 0) of S = Q G systems s = q G + i that share one shift
+// per group of G, node by node in order of increasing shift (ties by node), members in order;
+// Q <= 4096.
+hipError_t launch_order_live(const int32_t* done, const double* sigma, int64_t S, int64_t G, int32_t* act,
+                             int32_t* nact, hipStream_t st);
 // The fused PCG step with the measurement hook (profile slot INFOESRF_PROF_PCG); arguments as
 // launch_pcg_fused.
 hipError_t pcg_fused_timed(Prec prec, const PCGState& s, const LMP& lmp, int mode, int obs_domain, int plain,

@@ -94,6 +94,14 @@ __device__ inline double2 tail_ld16(__amdgpu_buffer_rsrc_t rs, uint32_t voff, ui
   return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
 }
 
+// Lane l's value of a double, to every lane.
+__device__ inline double tail_readlane(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
 // Halo cell t (of the nh cells that hold wrapped values) of the padded lattice: sets its position
 // and that of the interior cell it copies; false where the cell stays zero (a corner past an axis
 // that is not periodic).  Cells first along periodic z (2 bz rows of Wp), then along periodic x
@@ -138,6 +146,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
   __shared__ double sredW[W][NW];
   __shared__ double sG[3 * P * P + P + 1];
   __shared__ double scoef[2 * P + 2];
+  __shared__ double sM[P * P + 1];
   __shared__ double sdot[W];
   __shared__ int s_idx;
   // padded direction (band) or direction (dense S); then, when phi_lds, the FP32 Ritz bases
@@ -220,6 +229,17 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
           ph[(j * P + l) % kC] = ok ? tail_ld4(rsF, (uint32_t)r * 4, l * colF) : 0.f;
           sph[(j * P + l) % kC] = ok ? tail_ld4(rsG, (uint32_t)r * 4, l * colF) : 0.f;
         }
+      }
+    }
+    // M(sigma) = (C Phi)^T (C Phi) = Gss + sigma (Gps + Gps^T) + sigma^2 Gpp for this system's shift
+    // (read after the first iteration's barriers)
+    if (P > 0) {
+      const double* Gpp = sG;
+      const double* Gps = sG + P * P;
+      const double* Gss = sG + 2 * P * P;
+      for (int o = tid; o < P * P; o += NT) {
+        const int a = o / P, l = o % P;
+        sM[o] = Gss[a * P + l] + sig1 * (Gps[a * P + l] + Gps[l * P + a]) + sig1 * sig1 * Gpp[a * P + l];
       }
     }
     int state = 0;
@@ -347,25 +367,34 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
       // limited-memory preconditioner coefficients, as in the fused step:
       //   c1 = Theta^{-1} Phi^T r,  c2 = Theta^{-1} [(C Phi)^T r - (C Phi)^T (C Phi) c1],
       //   gamma = (1 + sigma - beta_L) c1 + c2,  z = r - S Phi c1 - Phi gamma
+      // The first wavefront does it without a barrier: lane t < p holds c1_t, takes the others'
+      // by readlane for (C Phi)^T (C Phi) c1 = M(sigma) c1 (M precomputed per system), and the
+      // wavefront sums the p terms of r^T z's correction.
       double rzn = dt[0];
       if (P > 0) {
-        const double* sth = sG + 3 * P * P;
-        if (tid < P) scoef[tid] = dt[1 + tid] / (sig1 + sth[tid]);
-        __syncthreads();
-        if (tid < P) {
-          const double* Gpp = sG;
-          const double* Gps = sG + P * P;
-          const double* Gss = sG + 2 * P * P;
+        if (tid < 64) {
+          const double* sth = sG + 3 * P * P;
+          double c1 = 0.0, term = 0.0;
+          if (tid < P) c1 = dt[1 + tid] / (sig1 + sth[tid]);
           double mc = 0.0;
-          for (int l = 0; l < P; ++l)
-            mc += (Gss[tid * P + l] + sig1 * (Gps[tid * P + l] + Gps[l * P + tid]) + sig1 * sig1 * Gpp[tid * P + l]) *
-                  scoef[l];
-          const double c2 = (dt[1 + P + tid] + sig1 * dt[1 + tid] - mc) / (sig1 + sth[tid]);
-          const double beta_l = sig1 + dmin;
-          scoef[P + tid] = (sig1 - beta_l) * scoef[tid] + c2;
+#pragma unroll
+          for (int l = 0; l < P; ++l) {
+            const double c1l = tail_readlane(c1, l);
+            if (tid < P) mc += sM[tid * P + l] * c1l;
+          }
+          if (tid < P) {
+            const double c2 = (dt[1 + P + tid] + sig1 * dt[1 + tid] - mc) / (sig1 + sth[tid]);
+            const double beta_l = sig1 + dmin;
+            const double gam = (sig1 - beta_l) * c1 + c2;
+            scoef[tid] = c1;
+            scoef[P + tid] = gam;
+            term = dt[1 + P + tid] * c1 + dt[1 + tid] * gam;
+          }
+          const double tsum = wave_sum_dpp(term);
+          if (tid == 63) scoef[2 * P] = tsum;
         }
         __syncthreads();
-        for (int l = 0; l < P; ++l) rzn -= dt[1 + P + l] * scoef[l] + dt[1 + l] * scoef[P + l];
+        rzn -= scoef[2 * P];
       }
       if (!(rzn > 0.0) || !isfinite(rzn)) {
         if (tid == 0) atomicOr(st.flags, isfinite(rzn) ? kFlagNotSPD : kFlagNumeric);
@@ -418,26 +447,48 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
   }
 }
 
-// The listed systems in order of increasing shift (the slowest first), ties by list position:
-// out[rank] = act[i].  One workgroup, keys in LDS; *nact <= kOrderMax (checked by the launcher
-// against the list's capacity).
-constexpr int kOrderMax = 4096;
-__global__ __launch_bounds__(1024) void k_order_by_shift(const int32_t* __restrict__ act,
-                                                         const int32_t* __restrict__ nact,
-                                                         const double* __restrict__ sigma,
-                                                         int32_t* __restrict__ out) {
-  __shared__ double key[kOrderMax];
-  const int n = min(*nact, kOrderMax);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) key[i] = sigma[act[i]];
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double ki = key[i];
+// The live systems (done == 0) node by node in order of increasing shift (the slowest first),
+// members in order within a node: systems s = q G + i with one shift per group of G.  One
+// workgroup: the Q = S / G node shifts are ranked in LDS (ties by node index), then the systems
+// are compacted in that order (per-thread chunks, a serial scan of the 1024 chunk counts).
+constexpr int kOrderQ = 4096;
+__global__ __launch_bounds__(1024) void k_order_live(const int32_t* __restrict__ done,
+                                                     const double* __restrict__ sigma, int64_t S, int64_t G,
+                                                     int32_t* __restrict__ act, int32_t* __restrict__ nact) {
+  __shared__ int32_t perm[kOrderQ];
+  __shared__ int32_t cnt[1024];
+  const int t = threadIdx.x;
+  const int Q = (int)(S / G);
+  for (int q = t; q < Q; q += 1024) {
+    const double kq = sigma[(int64_t)q * G];
     int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double kj = key[j];
-      rank += (kj < ki || (kj == ki && j < i)) ? 1 : 0;
+    for (int j = 0; j < Q; ++j) {
+      const double kj = sigma[(int64_t)j * G];
+      rank += (kj < kq || (kj == kq && j < q)) ? 1 : 0;
     }
-    out[rank] = act[i];
+    perm[rank] = q;
+  }
+  __syncthreads();
+  const int64_t per = (S + 1023) / 1024;
+  const int64_t a = t * per, b = min<int64_t>(S, a + per);
+  int32_t c = 0;
+  for (int64_t u = a; u < b; ++u) c += (done[(int64_t)perm[u / G] * G + u % G] == 0);
+  cnt[t] = c;
+  __syncthreads();
+  if (t == 0) {
+    int32_t run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int32_t v = cnt[i];
+      cnt[i] = run;
+      run += v;
+    }
+    *nact = run;
+  }
+  __syncthreads();
+  int32_t pos = cnt[t];
+  for (int64_t u = a; u < b; ++u) {
+    const int64_t sys = (int64_t)perm[u / G] * G + u % G;
+    if (done[sys] == 0) act[pos++] = (int32_t)sys;
   }
 }
 
@@ -456,6 +507,7 @@ constexpr size_t kTailLdsBig = 150 * 1024;
 template <int P, int RPT, int NT>
 hipError_t tail_go(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act, const int32_t* nact,
                    int32_t* qctr, int64_t grid, hipStream_t st) {
+  if ((int64_t)RPT * NT < s.m) return hipErrorInvalidValue;  // every row has a thread
   const void* fn = (const void*)k_pcg_tail<P, RPT, NT>;
   size_t lds = tail_lds_bytes(ap);
   // the Ritz bases in LDS when the kernel does not keep them in registers and there is room
@@ -506,10 +558,11 @@ bool tail_fits(const TailApply& ap) {
   return (int64_t)(tail_lds_bytes(ap) / sizeof(double)) <= kTailPadMax;
 }
 
-hipError_t launch_order_by_shift(const int32_t* act, const int32_t* nact, const double* sigma, int64_t capacity,
-                                 int32_t* out, hipStream_t st) {
-  if (capacity > kOrderMax || !act || !nact || !sigma || !out) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_order_by_shift, dim3(1), dim3(1024), 0, st, act, nact, sigma, out);
+hipError_t launch_order_live(const int32_t* done, const double* sigma, int64_t S, int64_t G, int32_t* act,
+                             int32_t* nact, hipStream_t st) {
+  if (!done || !sigma || !act || !nact || G < 1 || S < 1 || S % G != 0 || S / G > kOrderQ)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_order_live, dim3(1), dim3(1024), 0, st, done, sigma, S, G, act, nact);
   return hipGetLastError();
 }
 
