@@ -458,9 +458,11 @@ int infoesrf_rtps_assemble(const double* Xf, int64_t ldf, const double* mean_a, 
 #define INFOESRF_PROF_PCG 5 /* the fused PCG step: vectors = live systems, bytes per system 6-8 m-vector passes */
 #define INFOESRF_PROF_TAIL 6 /* the persistent PCG kernel: vectors = system-iterations, FLOPs per
                                 system-iteration = the apply (2 nnz(L) on the observed lattice, or
-                                2 m^2 with the dense S) + the PCG step (12 + 8 p) m; bytes = one read
-                                and one write of x, r, p per system, plus the band (or S) and the
-                                FP32 Ritz bases once per launch */
+                                2 m^2 with the dense S) + the PCG step (12 + 8 p) m; bytes per
+                                system = a read of its residual and a read and write of its solution
+                                (a solve it starts) or a read and write of x, r, p (one it takes over
+                                from the batched loop), plus the band (or S) and the FP32 Ritz bases
+                                once per launch */
 #define INFOESRF_PROF_SLOTS 7
 int infoesrf_profile_enable(int on);
 /* Restricts the hook to the slots whose bit (1 << slot) is set in mask (all slots after enabling);

@@ -1237,32 +1237,41 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   // the queue hands out the live systems node by node, smallest shift (the longest solves) first;
   // the perturbation systems share a shift per group of N members, the mean solve is one system
   const int64_t grp = (S % in.N == 0 && S / in.N <= 4096) ? in.N : S;
-  auto run_tail = [&](int32_t* list, int32_t* count, int64_t bound) -> int {
+  // r0 != null: the kernel starts each solve from x = 0 with residual r0 and adds into u;
+  // otherwise it continues the batched loop's state
+  auto run_tail = [&](int32_t* list, int32_t* count, int64_t bound, const double* r0) -> int {
     IE_HIP(launch_order_live(sy.done, sy.sigma, S, grp, list, count, st));
     IE_HIP(launch_fill_i32(sy.qctr, 0, 1, st));
-    IE_HIP(pcg_tail_timed(ps, lmp, tap, list, count, sy.qctr, bound, st));
+    IE_HIP(pcg_tail_timed(ps, lmp, tap, list, count, sy.qctr, bound, r0, r0 ? sy.u : nullptr, st));
     return 0;
   };
+  // the persistent kernel takes every sweep's solve from its start (it needs neither x = 0 nor a
+  // copy of the first residual: with a zero start it reads b itself)
+  const bool persist = tail_ok && S <= op.tail && !msc && !bcg;
   const int64_t ldr = ld64(od ? in.m : in.n);
   int32_t h_nact = (int32_t)S;
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
     // outer residual r = b - C u (FP64).  Zero start: the first residual is b itself.
-    if (sweep == 0 && !warm) {
-      hipLaunchKernelGGL(k_copy_f64, dim3(nb(flat)), dim3(256), 0, st, sy.b, sy.r, flat);
-      IE_HIP(hipGetLastError());
+    const bool r_is_b = sweep == 0 && !warm;
+    if (r_is_b) {
+      if (!persist) {
+        hipLaunchKernelGGL(k_copy_f64, dim3(nb(flat)), dim3(256), 0, st, sy.b, sy.r, flat);
+        IE_HIP(hipGetLastError());
+      }
     } else {
       IE_HIP(launch_compact(sy.fdone, S, sy.act, sy.nact, st));
       IE_TRY(apply_S(pl, Prec::F64, sy.u, ldm, sy.act, sy.nact, S, sy.sigma, sy.q, op.rows_per_wave, st));
       IE_HIP(launch_sub(sy.b, sy.q, sy.r, flat, st));
     }
-    IE_HIP(launch_col_norms(sy.r, m, S, ldm, sy.rn, st));
+    const double* rcur = (r_is_b && persist) ? sy.b : sy.r;
+    IE_HIP(launch_col_norms(rcur, m, S, ldm, sy.rn, st));
     hipLaunchKernelGGL(k_sweep_status, dim3(nb(S)), dim3(256), 0, st, sy.rn, sy.bnorm, op.rtol, op.inner_rtol,
                        fp64_inner ? 1 : 0, sy.iters, op.max_iter, op.fixed > 0 ? 1 : 0, sy.relres, sy.fdone,
                        sy.done, sy.thresh,
                        sy.sweeps, (sweep > 0 || warm) ? 1 : 0, S, in.flags);
     IE_HIP(hipGetLastError());
     if (plain) IE_HIP(launch_iota(sy.act, sy.nact, S, st));
-    else IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
+    else if (!persist) IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
     if (op.host_sync) {
       IE_HIP(launch_compact(sy.done, S, sy.act2, sy.nact2, st));
       IE_HIP(hipMemcpyAsync(&h_nact, sy.nact2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1270,6 +1279,11 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
       if (h_nact == 0) break;
     }
     if (sweep == max_sweeps) break;
+    if (persist) {
+      // one persistent launch runs every iteration of every live system and adds into u
+      IE_TRY(run_tail(sy.act, sy.nact, plain ? S : (int64_t)h_nact, rcur));
+      continue;
+    }
     // inner solve on C d = r from d = 0: the multi-shift process first when asked, else PCG
     IE_HIP(launch_fill_f64(sy.x, 0.0, flat, st));
     if ((msc || bcg) && sweep == 0) {
@@ -1287,9 +1301,9 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
     std::swap(act_c, act_n);
     std::swap(nact_c, nact_n);
     if (tail_ok && hint <= op.tail) {
-      // few enough systems from the start (without host polling, hint is the system count): one
-      // persistent launch runs every iteration
-      IE_TRY(run_tail(act_c, nact_c, hint));
+      // few enough systems left after the first status: one persistent launch runs every
+      // iteration from the batched first step
+      IE_TRY(run_tail(act_c, nact_c, hint, nullptr));
       IE_HIP(launch_axpy(sy.u, sy.x, flat, st));
       continue;
     }
@@ -1320,7 +1334,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
           if (!plain) hint = seen;  // compacted lists hold exactly the live systems
           if (tail_ok && seen <= op.tail) {
             // few systems left: one persistent launch iterates each of them to the end
-            IE_TRY(run_tail(act_c, nact_c, seen));
+            IE_TRY(run_tail(act_c, nact_c, seen, nullptr));
             break;
           }
         }

@@ -337,11 +337,16 @@ hipError_t launch_pcg_fused(Prec prec, const PCGState& s, const LMP& lmp, int mo
                             int32_t* nact_out, int64_t Bmax, void* V, int64_t ldv, const int32_t* h_ptr,
                             const int32_t* h_idx, const double* h_w, const double* r_var, int64_t n_state,
                             hipStream_t st);
+// r0 and uacc (both given or both null): each system starts from x = 0 with residual r0 (the
+// kernel takes the first step itself) and adds its solution into uacc; otherwise it continues the
+// batched loop's x, r, p, r^T z and writes them back.
 hipError_t launch_pcg_tail(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
-                           const int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st);
+                           const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,
+                           hipStream_t st);
 // launch_pcg_tail with the measurement hook (profile slot INFOESRF_PROF_TAIL).
 hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
-                          const int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st);
+                          const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,
+                          hipStream_t st);
 // Whether launch_pcg_tail takes this apply: m <= 4096, the padded lattice (or m values) within
 // its LDS budget, at most one wrapped copy per side along periodic axes.
 bool tail_fits(const TailApply& ap);

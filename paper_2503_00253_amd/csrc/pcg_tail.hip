@@ -14,10 +14,11 @@
 //
 // The band apply reads the direction from a padded copy of the observed lattice in LDS: bz rows
 // above and below and bx columns left and right of the nz x nx lattice, holding the wrapped
-// values along periodic axes (copied from the interior after each update) and zeros elsewhere, so the neighbour (z + li - bz, x + d - bx) of
-// lattice point (z, x) sits at (z + li) * Wp + x + d with no wrap or bounds test, and a thread
-// walks a stencil row through consecutive LDS words.  The band values are loaded a chunk at a
-// time ahead of their use, to keep many loads in flight per wavefront.
+// values along periodic axes (copied from the interior after each update) and zeros elsewhere,
+// so the neighbour (z + li - bz, x + d - bx) of lattice point (z, x) sits at (z + li) Wp + x + d
+// with no wrap or bounds test, and a thread walks a stencil row through consecutive LDS words.
+// The band values are loaded a chunk at a time ahead of their use, to keep many loads in flight
+// per wavefront.
 #include "internal.hpp"
 
 namespace infoesrf {
@@ -133,7 +134,8 @@ __device__ inline bool tail_halo(const Grid& g, int Wp, int t, int& dst, int& sr
 template <int P, int RPT, int NT>
 __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply ap,
                                                  const int32_t* __restrict__ act, const int32_t* __restrict__ nact,
-                                                 int32_t* __restrict__ qctr, int phi_lds) {
+                                                 int32_t* __restrict__ qctr, int phi_lds,
+                                                 const double* __restrict__ r0, double* __restrict__ uacc) {
   constexpr int W = 2 * P + 1;
   constexpr int NW = NT / 64;
   static_assert(RPT % 2 == 0, "rows come in pairs");
@@ -212,7 +214,10 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
     const double sig1 = 1.0 + st.sigma[s];
     const double bn = st.bnorm[s];
     const double thresh = st.thresh[s];
-    double rz = st.rz[s];
+    // a start (r0 given) takes x = 0 and the residual r0 and begins with the first step's
+    // preconditioned residual; a continuation reads x, r, p and r^T z of the batched loop
+    const bool start = r0 != nullptr;
+    double rz = start ? 0.0 : st.rz[s];
     int it = st.iters[s];
     double rv[RPT], pv[RPT], xv[RPT];
     float ph[kC], sph[kC];
@@ -220,9 +225,9 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
     for (int j = 0; j < RPT; ++j) {
       const int64_t r = tail_row<NT>(tid, j);
       const bool ok = r < m;
-      rv[j] = ok ? st.r[base + r] : 0.0;
-      pv[j] = ok ? st.p[base + r] : 0.0;
-      xv[j] = ok ? st.x[base + r] : 0.0;
+      rv[j] = ok ? (start ? r0[base + r] : st.r[base + r]) : 0.0;
+      pv[j] = (ok && !start) ? st.p[base + r] : 0.0;
+      xv[j] = (ok && !start) ? st.x[base + r] : 0.0;
       if (kCache) {
 #pragma unroll
         for (int l = 0; l < P; ++l) {
@@ -244,87 +249,99 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
     }
     int state = 0;
     double relres = 0.0;
+    bool first = start;
     for (;;) {
-      // the direction into LDS, then its wrapped copies
+      if (!first) {  // the apply and the step (the first pass of a start only prepares p)
+        // the direction into LDS, then its wrapped copies
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        const int r = tail_row<NT>(tid, j);
-        if (r < m) sp[band ? corner[j] + g.bz * Wp + g.bx : r] = pv[j];
-      }
-      __syncthreads();
-      if (nh > 0) {
-        for (int t = tid; t < nh; t += NT) {
-          int dst, src;
-          if (tail_halo(g, Wp, t, dst, src)) sp[dst] = sp[src];
+        for (int j = 0; j < RPT; ++j) {
+          const int r = tail_row<NT>(tid, j);
+          if (r < m) sp[band ? corner[j] + g.bz * Wp + g.bx : r] = pv[j];
         }
         __syncthreads();
-      }
-      // q = (1 + sigma) p + S p
-      // A row of the band is h stencil rows of w consecutive entries, both in the band (columns
-      // of colA bytes) and in the padded direction; the dense S is one stencil row of m entries.
-      // Each stencil row goes in chunks of CH entries whose loads, for all the thread's row
-      // pairs, are issued ahead of their multiply-adds (16 bytes a lane: the entry for both rows
-      // of a pair; uniform column offsets in scalar registers, the pair a per-lane offset, the
-      // direction at immediate LDS offsets), then one chunk for the rest of the row, whose
-      // missing entries repeat the last one and are weighted by zero.
-      double qv[RPT];
+        if (nh > 0) {
+          for (int t = tid; t < nh; t += NT) {
+            int dst, src;
+            if (tail_halo(g, Wp, t, dst, src)) sp[dst] = sp[src];
+          }
+          __syncthreads();
+        }
+        // q = (1 + sigma) p + S p
+        // A row of the band is h stencil rows of w consecutive entries, both in the band (columns
+        // of colA bytes) and in the padded direction; the dense S is one stencil row of m entries.
+        // Each stencil row goes in chunks of CH entries whose loads, for all the thread's row
+        // pairs, are issued ahead of their multiply-adds (16 bytes a lane: the entry for both rows
+        // of a pair; uniform column offsets in scalar registers, the pair a per-lane offset, the
+        // direction at immediate LDS offsets), then one chunk for the rest of the row, whose
+        // missing entries repeat the last one and are weighted by zero.
+        double qv[RPT];
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) qv[j] = 0.0;
-      for (int li = 0; li < hh; ++li) {
-        uint32_t so = (uint32_t)(li * ww) * colA;
-        const int lrow = li * Wp;
-        int d0 = 0;
-        for (; d0 + CH <= ww; d0 += CH) {
-          double2 bv[RPT / 2][CH];
+        for (int j = 0; j < RPT; ++j) qv[j] = 0.0;
+        for (int li = 0; li < hh; ++li) {
+          uint32_t so = (uint32_t)(li * ww) * colA;
+          const int lrow = li * Wp;
+          int d0 = 0;
+          for (; d0 + CH <= ww; d0 += CH) {
+            double2 bv[RPT / 2][CH];
 #pragma unroll
-          for (int jj = 0; jj < RPT / 2; ++jj)
+            for (int jj = 0; jj < RPT / 2; ++jj)
 #pragma unroll
-            for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)k * colA);
+              for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)k * colA);
 #pragma unroll
-          for (int jj = 0; jj < RPT / 2; ++jj) {
-            const double* p0 = sp + corner[2 * jj] + lrow + d0;
-            const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
+            for (int jj = 0; jj < RPT / 2; ++jj) {
+              const double* p0 = sp + corner[2 * jj] + lrow + d0;
+              const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
 #pragma unroll
-            for (int k = 0; k < CH; ++k) {
-              qv[2 * jj] += bv[jj][k].x * p0[k];
-              qv[2 * jj + 1] += bv[jj][k].y * p1[k];
+              for (int k = 0; k < CH; ++k) {
+                qv[2 * jj] += bv[jj][k].x * p0[k];
+                qv[2 * jj + 1] += bv[jj][k].y * p1[k];
+              }
+            }
+            so += (uint32_t)CH * colA;
+          }
+          if (d0 < ww) {
+            const int last = ww - d0 - 1;
+            double2 bv[RPT / 2][CH];
+#pragma unroll
+            for (int jj = 0; jj < RPT / 2; ++jj)
+#pragma unroll
+              for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)min(k, last) * colA);
+#pragma unroll
+            for (int jj = 0; jj < RPT / 2; ++jj) {
+              const double* p0 = sp + corner[2 * jj] + lrow + d0;
+              const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
+#pragma unroll
+              for (int k = 0; k < CH; ++k) {
+                const int kk = min(k, last);
+                qv[2 * jj] += (k <= last ? bv[jj][k].x : 0.0) * p0[kk];
+                qv[2 * jj + 1] += (k <= last ? bv[jj][k].y : 0.0) * p1[kk];
+              }
             }
           }
-          so += (uint32_t)CH * colA;
         }
-        if (d0 < ww) {
-          const int last = ww - d0 - 1;
-          double2 bv[RPT / 2][CH];
+        double pq = 0.0;
 #pragma unroll
-          for (int jj = 0; jj < RPT / 2; ++jj)
+        for (int j = 0; j < RPT; ++j) {
+          qv[j] += sig1 * pv[j];
+          pq += pv[j] * qv[j];
+        }
+        const double tot = tail_sum1<NT>(pq, sred1);
+        if (!(tot > 0.0) || !isfinite(tot)) {
+          if (tid == 0) atomicOr(st.flags, isfinite(tot) ? kFlagNotSPD : kFlagNumeric);
+          state = 2;
+          break;
+        }
+        const double alpha = rz / tot;
 #pragma unroll
-            for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)min(k, last) * colA);
-#pragma unroll
-          for (int jj = 0; jj < RPT / 2; ++jj) {
-            const double* p0 = sp + corner[2 * jj] + lrow + d0;
-            const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
-#pragma unroll
-            for (int k = 0; k < CH; ++k) {
-              const int kk = min(k, last);
-              qv[2 * jj] += (k <= last ? bv[jj][k].x : 0.0) * p0[kk];
-              qv[2 * jj + 1] += (k <= last ? bv[jj][k].y : 0.0) * p1[kk];
-            }
+        for (int j = 0; j < RPT; ++j) {
+          if (tail_row<NT>(tid, j) < m) {
+            xv[j] += alpha * pv[j];
+            rv[j] -= alpha * qv[j];
           }
         }
-      }
-      double pq = 0.0;
-#pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        qv[j] += sig1 * pv[j];
-        pq += pv[j] * qv[j];
-      }
-      const double tot = tail_sum1<NT>(pq, sred1);
-      if (!(tot > 0.0) || !isfinite(tot)) {
-        if (tid == 0) atomicOr(st.flags, isfinite(tot) ? kFlagNotSPD : kFlagNumeric);
-        state = 2;
-        break;
-      }
-      const double alpha = rz / tot;
+        ++it;
+      }  // !first
+      // dots of r: r^T r, Phi^T r, (S Phi)^T r
       double acc[W];
 #pragma unroll
       for (int j = 0; j < W; ++j) acc[j] = 0.0;
@@ -332,8 +349,6 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
       for (int j = 0; j < RPT; ++j) {
         const int64_t r = tail_row<NT>(tid, j);
         if (r < m) {
-          xv[j] += alpha * pv[j];
-          rv[j] -= alpha * qv[j];
           acc[0] += rv[j] * rv[j];
 #pragma unroll
           for (int l = 0; l < P; ++l) {
@@ -346,7 +361,6 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
           }
         }
       }
-      ++it;
       tail_sums<W, NT>(acc, sredW, sdot);
       const double* dt = sdot;
       const double rn = sqrt(dt[0]);
@@ -401,8 +415,9 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
         state = 2;
         break;
       }
-      const double beta = rzn / rz;
+      const double beta = first ? 0.0 : rzn / rz;
       rz = rzn;
+      first = false;
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         const int64_t r = tail_row<NT>(tid, j);
@@ -422,13 +437,19 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
       // no barrier here: every thread read the LDS direction before the first reduction's
       // barrier, and sred1, sredW, sdot and scoef are rewritten only after the next direction's
     }
+    // a start adds its correction to the solution; a continuation hands x, r, p back to the
+    // batched loop, which adds x
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       const int64_t r = tail_row<NT>(tid, j);
       if (r < m) {
-        st.x[base + r] = xv[j];
-        st.r[base + r] = rv[j];
-        st.p[base + r] = pv[j];
+        if (start) {
+          uacc[base + r] += xv[j];
+        } else {
+          st.x[base + r] = xv[j];
+          st.r[base + r] = rv[j];
+          st.p[base + r] = pv[j];
+        }
       }
     }
     if (tid == 0) {
@@ -506,7 +527,7 @@ constexpr size_t kTailLdsBig = 150 * 1024;
 
 template <int P, int RPT, int NT>
 hipError_t tail_go(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act, const int32_t* nact,
-                   int32_t* qctr, int64_t grid, hipStream_t st) {
+                   int32_t* qctr, int64_t grid, const double* r0, double* uacc, hipStream_t st) {
   if ((int64_t)RPT * NT < s.m) return hipErrorInvalidValue;  // every row has a thread
   const void* fn = (const void*)k_pcg_tail<P, RPT, NT>;
   size_t lds = tail_lds_bytes(ap);
@@ -528,20 +549,20 @@ hipError_t tail_go(const PCGState& s, const LMP& lmp, const TailApply& ap, const
   if (e != hipSuccess) return e;
   const int64_t resident = std::max<int64_t>((int64_t)per_cu * cus, 1);
   const dim3 gdim((unsigned)std::max<int64_t>(std::min(grid, resident), 1)), b(NT);
-  hipLaunchKernelGGL((k_pcg_tail<P, RPT, NT>), gdim, b, lds, st, s, lmp, ap, act, nact, qctr, phi_lds);
+  hipLaunchKernelGGL((k_pcg_tail<P, RPT, NT>), gdim, b, lds, st, s, lmp, ap, act, nact, qctr, phi_lds, r0, uacc);
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t tail_rows(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act, const int32_t* nact,
-                     int32_t* qctr, int64_t grid, hipStream_t st) {
+                     int32_t* qctr, int64_t grid, const double* r0, double* uacc, hipStream_t st) {
   const int nt = tail_threads(s.m);
   const int64_t rpt = (s.m + nt - 1) / nt;
-  if (nt == 128) return tail_go<P, 2, 128>(s, lmp, ap, act, nact, qctr, grid, st);
-  if (nt == 256) return tail_go<P, 2, 256>(s, lmp, ap, act, nact, qctr, grid, st);
-  if (nt == 1024) return tail_go<P, 4, 1024>(s, lmp, ap, act, nact, qctr, grid, st);
-  if (rpt <= 2) return tail_go<P, 2, 512>(s, lmp, ap, act, nact, qctr, grid, st);
-  if (rpt <= 4) return tail_go<P, 4, 512>(s, lmp, ap, act, nact, qctr, grid, st);
+  if (nt == 128) return tail_go<P, 2, 128>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+  if (nt == 256) return tail_go<P, 2, 256>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+  if (nt == 1024) return tail_go<P, 4, 1024>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+  if (rpt <= 2) return tail_go<P, 2, 512>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+  if (rpt <= 4) return tail_go<P, 4, 512>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
   return hipErrorInvalidValue;
 }
 
@@ -567,20 +588,22 @@ hipError_t launch_order_live(const int32_t* done, const double* sigma, int64_t S
 }
 
 hipError_t launch_pcg_tail(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
-                           const int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st) {
-  if (s.m < 1 || s.m > kTailMaxM || s.m != ap.m || !act || !nact || !qctr || !tail_fits(ap))
+                           const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,
+                           hipStream_t st) {
+  if (s.m < 1 || s.m > kTailMaxM || s.m != ap.m || !act || !nact || !qctr || !tail_fits(ap) ||
+      ((r0 == nullptr) != (uacc == nullptr)))
     return hipErrorInvalidValue;
   if (ap.kind == 0 && !ap.band) return hipErrorInvalidValue;
   if (ap.kind == 1 && !ap.S) return hipErrorInvalidValue;
   if (lmp.p > 0 && (!lmp.Phi32 || !lmp.SPhi32 || !lmp.G || !lmp.theta || !lmp.dmin)) return hipErrorInvalidValue;
   switch (lmp.p) {
-    case 0: return tail_rows<0>(s, lmp, ap, act, nact, qctr, grid, st);
-    case 4: return tail_rows<4>(s, lmp, ap, act, nact, qctr, grid, st);
-    case 8: return tail_rows<8>(s, lmp, ap, act, nact, qctr, grid, st);
-    case 10: return tail_rows<10>(s, lmp, ap, act, nact, qctr, grid, st);
-    case 12: return tail_rows<12>(s, lmp, ap, act, nact, qctr, grid, st);
-    case 16: return tail_rows<16>(s, lmp, ap, act, nact, qctr, grid, st);
-    case 20: return tail_rows<20>(s, lmp, ap, act, nact, qctr, grid, st);
+    case 0: return tail_rows<0>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+    case 4: return tail_rows<4>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+    case 8: return tail_rows<8>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+    case 10: return tail_rows<10>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+    case 12: return tail_rows<12>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+    case 16: return tail_rows<16>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+    case 20: return tail_rows<20>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -139,18 +139,21 @@ hipError_t pcg_fused_timed(Prec prec, const PCGState& s, const LMP& lmp, int mod
 }
 
 hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
-                          const int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st) {
-  if (!g_prof.on) return launch_pcg_tail(s, lmp, ap, act, nact, qctr, grid, st);
-  // per system-iteration: the apply and the PCG step; per system: x, r, p read and written once;
-  // per launch: the band (or S) and the FP32 Ritz bases
+                          const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,
+                          hipStream_t st) {
+  if (!g_prof.on) return launch_pcg_tail(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+  // per system-iteration: the apply and the PCG step; per system: a start reads its residual and
+  // reads and writes its solution, a continuation reads and writes x, r, p; per launch: the band
+  // (or S) and the FP32 Ritz bases
   const double m = (double)s.m, P = (double)lmp.p;
   const double apply = ap.kind == 1 ? 2.0 * m * m : 2.0 * grid_nnz(ap.g);
   const double matrix = ap.kind == 1 ? 8.0 * m * m : 8.0 * m * (2 * ap.g.bz + 1) * (2 * ap.g.bx + 1);
-  return timed(INFOESRF_PROF_TAIL, apply + m * (12.0 + 8.0 * P), 6.0 * 8.0 * m, matrix + 2.0 * 4.0 * m * P, st,
+  return timed(INFOESRF_PROF_TAIL, apply + m * (12.0 + 8.0 * P), (r0 ? 3.0 : 6.0) * 8.0 * m,
+               matrix + 2.0 * 4.0 * m * P, st,
                [&](const ProfDev* pd) {
                  PCGState sp = s;
                  sp.prof = pd ? *pd : ProfDev{};
-                 return launch_pcg_tail(sp, lmp, ap, act, nact, qctr, grid, st);
+                 return launch_pcg_tail(sp, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
                });
 }
 
