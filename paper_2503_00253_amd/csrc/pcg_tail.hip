@@ -53,6 +53,33 @@ __device__ inline double tail_sum1(double v, double (*sred)[NT / 64]) {
   return t;
 }
 
+// The same sums through LDS when the workgroup's Wn x NT partials fit: every thread stores its
+// Wn values, then 16 threads per value add NT / 16 partials each (a fixed order) and a row of 16
+// lanes combines them by DPP.  Fewer cross-lane steps than Wn wavefront sums.
+__host__ __device__ constexpr bool tail_lds_sums(int Wn, int NT) { return Wn > 1 && Wn * NT * 8 <= 96 * 1024; }
+
+template <int Wn, int NT>
+__device__ inline void tail_sums_lds(const double* v, double* part, double* out_lds) {
+  constexpr int G = 16;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < Wn; ++j) part[j * NT + tid] = v[j];
+  __syncthreads();
+  for (int u = tid; u < Wn * G; u += NT) {  // whole rows of 16 lanes stay active together
+    const int j = u / G, c = u % G;
+    const double* pj = part + j * NT + c;
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / G; ++k) t += pj[G * k];
+    t += dpp_f64<0xB1, 0xF>(t);   // quad_perm [1,0,3,2]
+    t += dpp_f64<0x4E, 0xF>(t);   // quad_perm [2,3,0,1]
+    t += dpp_f64<0x141, 0xF>(t);  // row_half_mirror
+    t += dpp_f64<0x140, 0xF>(t);  // row_mirror
+    if (c == 0) out_lds[j] = t;
+  }
+  __syncthreads();
+}
+
 template <int Wn, int NT>
 __device__ inline void tail_sums(const double* v, double (*sred)[NT / 64], double* out_lds) {
   tail_partials<Wn, NT>(v, sred);
@@ -143,6 +170,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
   constexpr int CH = RPT >= 4 ? 8 : 16;
   // the Ritz vectors of the thread's rows stay in registers when they fit
   constexpr bool kCache = tail_caches_ritz(P, RPT, NT);
+  constexpr bool kLdsSums = tail_lds_sums(2 * P + 1, NT);
   constexpr int kC = kCache ? RPT * P : 1;
   __shared__ double sred1[1][NW];
   __shared__ double sredW[W][NW];
@@ -179,8 +207,9 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
   const __amdgpu_buffer_rsrc_t rsF = tail_rsrc(lmp.Phi32, (int64_t)P * lmp.ld * 4);
   const __amdgpu_buffer_rsrc_t rsG = tail_rsrc(lmp.SPhi32, (int64_t)P * lmp.ld * 4);
   const uint32_t colF = (uint32_t)(lmp.ld * 4);
-  float* sF = reinterpret_cast<float*>(sp + npad);  // Phi32 (P x m), when phi_lds
-  float* sH = sF + (int64_t)P * m;                   // SPhi32 (P x m)
+  double* part = sp + npad;                                         // W x NT partial sums
+  float* sF = reinterpret_cast<float*>(part + (kLdsSums ? W * NT : 0));  // Phi32 (P x m), when phi_lds
+  float* sH = sF + (int64_t)P * m;                                  // SPhi32 (P x m)
   if (phi_lds) {
     for (int o = tid; o < P * (int)m; o += NT) {
       const int l = o / (int)m, r = o % (int)m;
@@ -361,7 +390,8 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
           }
         }
       }
-      tail_sums<W, NT>(acc, sredW, sdot);
+      if (kLdsSums) tail_sums_lds<W, NT>(acc, part, sdot);
+      else tail_sums<W, NT>(acc, sredW, sdot);
       const double* dt = sdot;
       const double rn = sqrt(dt[0]);
       relres = bn > 0.0 ? rn / bn : 0.0;
@@ -531,6 +561,7 @@ hipError_t tail_go(const PCGState& s, const LMP& lmp, const TailApply& ap, const
   if ((int64_t)RPT * NT < s.m) return hipErrorInvalidValue;  // every row has a thread
   const void* fn = (const void*)k_pcg_tail<P, RPT, NT>;
   size_t lds = tail_lds_bytes(ap);
+  if (tail_lds_sums(2 * P + 1, NT)) lds += (size_t)(2 * P + 1) * NT * sizeof(double);
   // the Ritz bases in LDS when the kernel does not keep them in registers and there is room
   const size_t phi = (size_t)8 * P * s.m;
   const int phi_lds = (P > 0 && !tail_caches_ritz(P, RPT, NT) && lds + phi <= kTailLdsBig) ? 1 : 0;
