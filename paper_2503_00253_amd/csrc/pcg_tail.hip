@@ -552,7 +552,8 @@ size_t tail_lds_bytes(const TailApply& ap) {
   return (size_t)npad * sizeof(double);
 }
 
-// LDS the launcher may give one workgroup (a 1024-thread workgroup occupies its CU alone)
+// LDS (static and dynamic) the launcher lets one workgroup take: the kernel runs one workgroup
+// per CU at the sizes where it needs this much
 constexpr size_t kTailLdsBig = 150 * 1024;
 
 template <int P, int RPT, int NT>
@@ -560,17 +561,26 @@ hipError_t tail_go(const PCGState& s, const LMP& lmp, const TailApply& ap, const
                    int32_t* qctr, int64_t grid, const double* r0, double* uacc, hipStream_t st) {
   if ((int64_t)RPT * NT < s.m) return hipErrorInvalidValue;  // every row has a thread
   const void* fn = (const void*)k_pcg_tail<P, RPT, NT>;
+  // the kernel's static LDS (read once per instantiation): static + dynamic stays within the CU's
+  static size_t stat = ~(size_t)0;
+  if (stat == ~(size_t)0) {
+    hipFuncAttributes fa{};
+    const hipError_t e = hipFuncGetAttributes(&fa, fn);
+    if (e != hipSuccess) return e;
+    stat = fa.sharedSizeBytes;
+  }
   size_t lds = tail_lds_bytes(ap);
   if (tail_lds_sums(2 * P + 1, NT)) lds += (size_t)(2 * P + 1) * NT * sizeof(double);
+  if (stat + lds > kTailLdsBig) return hipErrorInvalidValue;
   // the Ritz bases in LDS when the kernel does not keep them in registers and there is room
   const size_t phi = (size_t)8 * P * s.m;
-  const int phi_lds = (P > 0 && !tail_caches_ritz(P, RPT, NT) && lds + phi <= kTailLdsBig) ? 1 : 0;
+  const int phi_lds = (P > 0 && !tail_caches_ritz(P, RPT, NT) && stat + lds + phi <= kTailLdsBig) ? 1 : 0;
   if (phi_lds) lds += phi;
-  static bool big = false;  // the attribute is set once per instantiation
-  if (lds > 64 * 1024 && !big) {
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTailLdsBig);
+  static size_t allowed = 64 * 1024;  // dynamic LDS this instantiation may take
+  if (lds > allowed) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    big = true;
+    allowed = lds;
   }
   // no more workgroups than can be resident at once: the others would only find the queue empty
   int dev = 0, per_cu = 0, cus = 0;

@@ -186,12 +186,19 @@ def test_solvers_agree_and_are_deterministic(solver):
     say("solver", solver)
     s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
     P = ie.Problem.from_synthetic(prob)
-    a, sa = ie.perturbation_update(P, s, p, ie.default_opts(solver=solver))
-    b, sb = ie.perturbation_update(P, s, p, ie.default_opts(solver=solver))
-    assert torch.equal(a, b)
-    assert np.array_equal(sa.iters, sb.iters)
-    c, _ = ie.perturbation_update(P, s, p, ie.default_opts(solver=ie.SOLVER_COMPACT))
+    # run to run bit-identical, with the persistent kernel (the compacted solver's default) and
+    # without it
+    for tail in (0, -1):
+        a, sa = ie.perturbation_update(P, s, p, ie.default_opts(solver=solver, tail_systems=tail))
+        b, sb = ie.perturbation_update(P, s, p, ie.default_opts(solver=solver, tail_systems=tail))
+        assert torch.equal(a, b)
+        assert np.array_equal(sa.iters, sb.iters)
+    # the batched compacted loop runs the same arithmetic as the masked one; the persistent kernel
+    # sums its applies and dots in another order
+    c, _ = ie.perturbation_update(P, s, p, ie.default_opts(solver=ie.SOLVER_COMPACT, tail_systems=-1))
     assert rel(a.cpu().numpy(), c.cpu().numpy()) < 1e-12
+    d, _ = ie.perturbation_update(P, s, p, ie.default_opts(solver=ie.SOLVER_COMPACT))
+    assert rel(a.cpu().numpy(), d.cpu().numpy()) < 1e-9
 
 
 @pytest.mark.parametrize("form", ["operator", "band", "dense-s"])
@@ -459,3 +466,24 @@ def test_persistent_variants(n_ritz, fixed):
         want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
         assert rel(outs[0][0], want) < 1e-6
         assert np.max(np.abs(outs[0][1] - outs[-1][1])) <= 2
+
+
+@pytest.mark.parametrize("n_ritz", [4, 16, 20])
+def test_persistent_kernel_variants_at_1024_observations(n_ritz):
+    """The persistent kernel at m = 1024 (the n = 4096 workload) with small and large Ritz bases,
+    which select different register and LDS layouts (the Ritz bases in registers or in LDS, the
+    dots summed through LDS or by wavefront sums): every system converges and the result agrees
+    with the batched loop."""
+    prob = syn.config2()
+    P = ie.Problem.from_synthetic(prob)
+    s, p = ie.quadrature_elliptic(prob.Q, prob.ell)
+    say("persistent m=1024", n_ritz)
+    outs = {}
+    for tail in (-1, 0):
+        o = ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=P.lattice(), n_ritz=n_ritz,
+                            tail_systems=tail)
+        got, st = ie.perturbation_update(P, s, p, o)
+        assert st.code == ie.OK and np.all(st.relres <= 1e-8)
+        outs[tail] = (got.cpu().numpy(), st.iters.copy())
+    assert rel(outs[0][0], outs[-1][0]) < 1e-8
+    assert np.max(np.abs(outs[0][1] - outs[-1][1])) <= 2
