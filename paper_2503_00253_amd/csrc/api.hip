@@ -1175,7 +1175,12 @@ int bcg_solve_all(Plan& pl, const Options& op, hipStream_t st) {
 // Outer sweeps form the true residual r = b - C u in FP64; the inner PCG (apply precision
 // op.inner) solves C d = r to the per-system target and u += d.  One inner iteration is two
 // launches: the covariance apply on the active columns, and the fused PCG kernel.
-int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
+// finalize (optional): enqueues the work that consumes u (the quadrature sum, the final update,
+// the statistics).  With host synchronization it is enqueued before each later sweep's status
+// is read, so the read overlaps it; *finalized tells whether the last enqueued copy saw the final
+// u (else the caller enqueues it once more).
+int stage_solve(Plan& pl, const Options& op, hipStream_t st, const std::function<int()>& finalize = {},
+                bool* finalized = nullptr) {
   Inst& in = pl.in;
   Sys& sy = pl.sy;
   const int64_t S = sy.S, ldm = sy.ldm, m = in.m;
@@ -1272,11 +1277,19 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
     IE_HIP(hipGetLastError());
     if (plain) IE_HIP(launch_iota(sy.act, sy.nact, S, st));
     else if (!persist) IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
-    if (op.host_sync) {
+    if (finalized) *finalized = false;
+    // the persistent kernel needs no live count before the first solve (an empty queue costs
+    // microseconds), so that status is not read on the host
+    if (op.host_sync && !(persist && sweep == 0)) {
       IE_HIP(launch_compact(sy.done, S, sy.act2, sy.nact2, st));
       IE_HIP(hipMemcpyAsync(&h_nact, sy.nact2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      const bool spec = finalize && sweep > 0;
+      if (spec) IE_TRY(finalize());
       IE_HIP(hipStreamSynchronize(st));
-      if (h_nact == 0) break;
+      if (h_nact == 0 || sweep == max_sweeps) {
+        if (finalized) *finalized = spec;
+        break;
+      }
     }
     if (sweep == max_sweeps) break;
     if (persist) {
@@ -1346,7 +1359,8 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st) {
   return 0;
 }
 
-int finish_status(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t extra_fp64, hipStream_t st) {
+// The device half of finish_status: counters and the caller's per-system statistics.
+int finish_enqueue(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t extra_fp64, hipStream_t st) {
   Sys& sy = pl.sy;
   hipLaunchKernelGGL(k_finish_counters, dim3(1), dim3(256), 0, st, sy.iters, sy.sweeps, sy.fdone, sy.S, extra_fp64,
                      sy.app_adj, op.inner == Prec::F64 ? 1 : 0, op.fixed > 0 ? 1 : 0, pl.in.flags, pl.in.fallbacks,
@@ -1360,6 +1374,11 @@ int finish_status(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t ex
       IE_HIP(hipMemcpyAsync(stats->counters, pl.in.counters, sizeof(int64_t) * INFOESRF_NUM_COUNTERS,
                             hipMemcpyDeviceToDevice, st));
   }
+  return 0;
+}
+
+// The host half: with host synchronization, the status code and its message.
+int finish_read(Plan& pl, const Options& op, hipStream_t st) {
   if (!op.host_sync) return 0;
   int64_t cnt[INFOESRF_NUM_COUNTERS];
   IE_HIP(hipMemcpyAsync(cnt, pl.in.counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
@@ -1373,6 +1392,11 @@ int finish_status(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t ex
     set_error(std::to_string(cnt[INFOESRF_CNT_NOT_CONVERGED]) + " system(s) did not reach rtol");
   }
   return code;
+}
+
+int finish_status(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t extra_fp64, hipStream_t st) {
+  IE_TRY(finish_enqueue(pl, op, stats, extra_fp64, st));
+  return finish_read(pl, op, st);
 }
 
 // nnz of H (device) sizes the CSC arrays: the reserved maximum is 64 entries per row on average;
@@ -1498,7 +1522,8 @@ size_t instance_ws_bytes(const infoesrf_problem* P, int32_t Q, bool mean, const 
 // validation, set-up, right-hand sides, nodes, preconditioner and the solves.
 int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_nodes, const double* p_weights,
                        const double* y, const infoesrf_opts* opts, Plan& pl, Options& op, void* ws,
-                       size_t ws_bytes, hipStream_t st) {
+                       size_t ws_bytes, hipStream_t st, const std::function<int()>& finalize = {},
+                       bool* finalized = nullptr) {
   IE_TRY(check_problem(prob));
   IE_TRY(resolve_options(prob, opts, op));
   IE_CHECK(Q >= 1 && Q <= kMaxQ, INFOESRF_ERR_INVALID_ARG, "Q must be in [1, 64]");
@@ -1538,7 +1563,7 @@ int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_
                      (int64_t)0, 0.0);
   IE_HIP(hipGetLastError());
   IE_TRY(stage_precond(pl, op, st));
-  IE_TRY(stage_solve(pl, op, st));
+  IE_TRY(stage_solve(pl, op, st, finalize, finalized));
   return 0;
 }
 
@@ -1730,16 +1755,22 @@ int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const 
   Plan pl;
   Options op;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  IE_TRY(perturbation_solve(prob, Q, s_nodes, p_weights, y, opts, pl, op, ws, ws_bytes, st));
-  Sys& sy = pl.sy;
   const int64_t N = prob->N;
-  // u_bar_i = sum_q p_q u_{q,i}; Xa_pert = sqrt(N-1) (Z - P H^T R^{-1/2} U_bar)
-  IE_HIP(launch_quad_combine(sy.u, sy.ldm, pl.in.m, N, Q, sy.pw, pl.fn.ubar, sy.ldm, 0, st));
-  IE_HIP(launch_iota(pl.fn.act, pl.fn.nact, N, st));
-  IE_TRY(apply_state(pl, pl.fn.ubar, sy.ldm, pl.fn.act, pl.fn.nact, N, op.rows_per_wave, st));
-  IE_HIP(launch_final_pert(pl.in.Z, (const double*)pl.bf.T, ld64(pl.in.n), pl.in.n, N, std::sqrt((double)(N - 1)),
-                           Xa_pert, st));
-  return finish_status(pl, op, stats, 2 * pl.pr.k + N, st);
+  // u_bar_i = sum_q p_q u_{q,i}; Xa_pert = sqrt(N-1) (Z - P H^T R^{-1/2} U_bar); idempotent, so
+  // the solve may enqueue it before its last status read and again if a later sweep changes u
+  auto finalize = [&]() -> int {
+    Sys& sy = pl.sy;
+    IE_HIP(launch_quad_combine(sy.u, sy.ldm, pl.in.m, N, Q, sy.pw, pl.fn.ubar, sy.ldm, 0, st));
+    IE_HIP(launch_iota(pl.fn.act, pl.fn.nact, N, st));
+    IE_TRY(apply_state(pl, pl.fn.ubar, sy.ldm, pl.fn.act, pl.fn.nact, N, op.rows_per_wave, st));
+    IE_HIP(launch_final_pert(pl.in.Z, (const double*)pl.bf.T, ld64(pl.in.n), pl.in.n, N,
+                             std::sqrt((double)(N - 1)), Xa_pert, st));
+    return finish_enqueue(pl, op, stats, 2 * pl.pr.k + N, st);
+  };
+  bool finalized = false;
+  IE_TRY(perturbation_solve(prob, Q, s_nodes, p_weights, y, opts, pl, op, ws, ws_bytes, st, finalize, &finalized));
+  if (!finalized) IE_TRY(finalize());
+  return finish_read(pl, op, st);
 }
 
 int infoesrf_autotune(const infoesrf_problem* prob, int32_t Q, const infoesrf_opts* opts, void* ws,
