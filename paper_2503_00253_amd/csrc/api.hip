@@ -1244,37 +1244,44 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const std::function
   const int64_t grp = (S % in.N == 0 && S / in.N <= 4096) ? in.N : S;
   // r0 != null: the kernel starts each solve from x = 0 with residual r0 and adds into u;
   // otherwise it continues the batched loop's state
+  // the persistent kernel takes every sweep's solve from its start (it needs neither x = 0 nor a
+  // copy of the first residual: with a zero start it reads b itself) and then the next sweep's
+  // residual and status
+  const bool persist = tail_ok && S <= op.tail && !msc && !bcg;
+  TailCheck chk{};
+  if (persist) chk = TailCheck{sy.b, sy.fdone, sy.sweeps, sy.relres, op.rtol, op.fixed > 0 ? 1 : 0};
   auto run_tail = [&](int32_t* list, int32_t* count, int64_t bound, const double* r0) -> int {
     IE_HIP(launch_order_live(sy.done, sy.sigma, S, grp, list, count, st));
     IE_HIP(launch_fill_i32(sy.qctr, 0, 1, st));
-    IE_HIP(pcg_tail_timed(ps, lmp, tap, list, count, sy.qctr, bound, r0, r0 ? sy.u : nullptr, st));
+    IE_HIP(pcg_tail_timed(ps, lmp, tap, list, count, sy.qctr, bound, r0, r0 ? sy.u : nullptr,
+                          r0 ? chk : TailCheck{}, st));
     return 0;
   };
-  // the persistent kernel takes every sweep's solve from its start (it needs neither x = 0 nor a
-  // copy of the first residual: with a zero start it reads b itself)
-  const bool persist = tail_ok && S <= op.tail && !msc && !bcg;
   const int64_t ldr = ld64(od ? in.m : in.n);
   int32_t h_nact = (int32_t)S;
   for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
-    // outer residual r = b - C u (FP64).  Zero start: the first residual is b itself.
+    // outer residual r = b - C u (FP64).  Zero start: the first residual is b itself.  After a
+    // persistent solve the kernel has already formed r and the status.
     const bool r_is_b = sweep == 0 && !warm;
+    const bool checked = persist && sweep > 0;
     if (r_is_b) {
       if (!persist) {
         hipLaunchKernelGGL(k_copy_f64, dim3(nb(flat)), dim3(256), 0, st, sy.b, sy.r, flat);
         IE_HIP(hipGetLastError());
       }
-    } else {
+    } else if (!checked) {
       IE_HIP(launch_compact(sy.fdone, S, sy.act, sy.nact, st));
       IE_TRY(apply_S(pl, Prec::F64, sy.u, ldm, sy.act, sy.nact, S, sy.sigma, sy.q, op.rows_per_wave, st));
       IE_HIP(launch_sub(sy.b, sy.q, sy.r, flat, st));
     }
     const double* rcur = (r_is_b && persist) ? sy.b : sy.r;
-    IE_HIP(launch_col_norms(rcur, m, S, ldm, sy.rn, st));
-    hipLaunchKernelGGL(k_sweep_status, dim3(nb(S)), dim3(256), 0, st, sy.rn, sy.bnorm, op.rtol, op.inner_rtol,
-                       fp64_inner ? 1 : 0, sy.iters, op.max_iter, op.fixed > 0 ? 1 : 0, sy.relres, sy.fdone,
-                       sy.done, sy.thresh,
-                       sy.sweeps, (sweep > 0 || warm) ? 1 : 0, S, in.flags);
-    IE_HIP(hipGetLastError());
+    if (!checked) {
+      IE_HIP(launch_col_norms(rcur, m, S, ldm, sy.rn, st));
+      hipLaunchKernelGGL(k_sweep_status, dim3(nb(S)), dim3(256), 0, st, sy.rn, sy.bnorm, op.rtol, op.inner_rtol,
+                         fp64_inner ? 1 : 0, sy.iters, op.max_iter, op.fixed > 0 ? 1 : 0, sy.relres, sy.fdone,
+                         sy.done, sy.thresh, sy.sweeps, (sweep > 0 || warm) ? 1 : 0, S, in.flags);
+      IE_HIP(hipGetLastError());
+    }
     if (plain) IE_HIP(launch_iota(sy.act, sy.nact, S, st));
     else if (!persist) IE_HIP(launch_compact(sy.done, S, sy.act, sy.nact, st));
     if (finalized) *finalized = false;

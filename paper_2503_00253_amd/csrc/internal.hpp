@@ -337,16 +337,29 @@ hipError_t launch_pcg_fused(Prec prec, const PCGState& s, const LMP& lmp, int mo
                             int32_t* nact_out, int64_t Bmax, void* V, int64_t ldv, const int32_t* h_ptr,
                             const int32_t* h_idx, const double* h_w, const double* r_var, int64_t n_state,
                             hipStream_t st);
+// The residual sweep's status, taken in the persistent kernel after a started solve: the true
+// residual r = b - (1 + sigma) u - S u of the new u (kept in the PCG state's r), its relative
+// norm, and the sweep's per-system status (converged to rtol / out of iterations / continue with
+// an inner threshold of rtol ||b|| / 2, 0 for a fixed count), as the status kernel sets it.
+struct TailCheck {
+  const double* b;   // right-hand sides (system-major, the state's ld); null: no check
+  int32_t* fdone;    // final status: 1 converged, 2 failed, 3 fixed count reached
+  int32_t* sweeps;   // sweeps per system (+1)
+  double* relres;    // true relative residual of the sweep (the PCG state's relres is the inner one)
+  double rtol;
+  int fixed;
+};
 // r0 and uacc (both given or both null): each system starts from x = 0 with residual r0 (the
-// kernel takes the first step itself) and adds its solution into uacc; otherwise it continues the
-// batched loop's x, r, p, r^T z and writes them back.
+// kernel takes the first step itself) and adds its solution into uacc, then, when chk->b is
+// given, takes the sweep's status; otherwise it continues the batched loop's x, r, p, r^T z and
+// writes them back.
 hipError_t launch_pcg_tail(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
                            const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,
-                           hipStream_t st);
+                           const TailCheck& chk, hipStream_t st);
 // launch_pcg_tail with the measurement hook (profile slot INFOESRF_PROF_TAIL).
 hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
                           const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,
-                          hipStream_t st);
+                          const TailCheck& chk, hipStream_t st);
 // Whether launch_pcg_tail takes this apply: m <= 4096, the padded lattice (or m values) within
 // its LDS budget, at most one wrapped copy per side along periodic axes.
 bool tail_fits(const TailApply& ap);

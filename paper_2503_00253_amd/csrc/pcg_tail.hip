@@ -162,7 +162,8 @@ template <int P, int RPT, int NT>
 __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply ap,
                                                  const int32_t* __restrict__ act, const int32_t* __restrict__ nact,
                                                  int32_t* __restrict__ qctr, int phi_lds,
-                                                 const double* __restrict__ r0, double* __restrict__ uacc) {
+                                                 const double* __restrict__ r0, double* __restrict__ uacc,
+                                                 TailCheck chk) {
   constexpr int W = 2 * P + 1;
   constexpr int NW = NT / 64;
   static_assert(RPT % 2 == 0, "rows come in pairs");
@@ -230,6 +231,78 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
 #pragma unroll
   for (int jj = 0; jj < RPT / 2; ++jj)
     roff[jj] = (uint32_t)min<int64_t>(tail_row<NT>(tid, 2 * jj), (m - 1) & ~(int64_t)1) * (uint32_t)sizeof(double);
+  // q = (1 + sigma) v + S v for the thread's rows: v to LDS (and its wrapped copies), then the
+  // band (or S) streamed from L2 against it
+  auto apply_C = [&](const double* v, double sig1, double* qv) {
+    // the direction into LDS, then its wrapped copies
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int r = tail_row<NT>(tid, j);
+      if (r < m) sp[band ? corner[j] + g.bz * Wp + g.bx : r] = v[j];
+    }
+    __syncthreads();
+    if (nh > 0) {
+      for (int t = tid; t < nh; t += NT) {
+        int dst, src;
+        if (tail_halo(g, Wp, t, dst, src)) sp[dst] = sp[src];
+      }
+      __syncthreads();
+    }
+    // q = (1 + sigma) v + S v
+    // A row of the band is h stencil rows of w consecutive entries, both in the band (columns
+    // of colA bytes) and in the padded direction; the dense S is one stencil row of m entries.
+    // Each stencil row goes in chunks of CH entries whose loads, for all the thread's row
+    // pairs, are issued ahead of their multiply-adds (16 bytes a lane: the entry for both rows
+    // of a pair; uniform column offsets in scalar registers, the pair a per-lane offset, the
+    // direction at immediate LDS offsets), then one chunk for the rest of the row, whose
+    // missing entries repeat the last one and are weighted by zero.
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) qv[j] = 0.0;
+    for (int li = 0; li < hh; ++li) {
+      uint32_t so = (uint32_t)(li * ww) * colA;
+      const int lrow = li * Wp;
+      int d0 = 0;
+      for (; d0 + CH <= ww; d0 += CH) {
+        double2 bv[RPT / 2][CH];
+#pragma unroll
+        for (int jj = 0; jj < RPT / 2; ++jj)
+#pragma unroll
+          for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)k * colA);
+#pragma unroll
+        for (int jj = 0; jj < RPT / 2; ++jj) {
+          const double* p0 = sp + corner[2 * jj] + lrow + d0;
+          const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
+#pragma unroll
+          for (int k = 0; k < CH; ++k) {
+            qv[2 * jj] += bv[jj][k].x * p0[k];
+            qv[2 * jj + 1] += bv[jj][k].y * p1[k];
+          }
+        }
+        so += (uint32_t)CH * colA;
+      }
+      if (d0 < ww) {
+        const int last = ww - d0 - 1;
+        double2 bv[RPT / 2][CH];
+#pragma unroll
+        for (int jj = 0; jj < RPT / 2; ++jj)
+#pragma unroll
+          for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)min(k, last) * colA);
+#pragma unroll
+        for (int jj = 0; jj < RPT / 2; ++jj) {
+          const double* p0 = sp + corner[2 * jj] + lrow + d0;
+          const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
+#pragma unroll
+          for (int k = 0; k < CH; ++k) {
+            const int kk = min(k, last);
+            qv[2 * jj] += (k <= last ? bv[jj][k].x : 0.0) * p0[kk];
+            qv[2 * jj + 1] += (k <= last ? bv[jj][k].y : 0.0) * p1[kk];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) qv[j] += sig1 * v[j];
+  };
   __syncthreads();
   for (;;) {
     if (tid == 0) s_idx = atomicAdd(qctr, 1);
@@ -281,79 +354,11 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
     bool first = start;
     for (;;) {
       if (!first) {  // the apply and the step (the first pass of a start only prepares p)
-        // the direction into LDS, then its wrapped copies
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          const int r = tail_row<NT>(tid, j);
-          if (r < m) sp[band ? corner[j] + g.bz * Wp + g.bx : r] = pv[j];
-        }
-        __syncthreads();
-        if (nh > 0) {
-          for (int t = tid; t < nh; t += NT) {
-            int dst, src;
-            if (tail_halo(g, Wp, t, dst, src)) sp[dst] = sp[src];
-          }
-          __syncthreads();
-        }
-        // q = (1 + sigma) p + S p
-        // A row of the band is h stencil rows of w consecutive entries, both in the band (columns
-        // of colA bytes) and in the padded direction; the dense S is one stencil row of m entries.
-        // Each stencil row goes in chunks of CH entries whose loads, for all the thread's row
-        // pairs, are issued ahead of their multiply-adds (16 bytes a lane: the entry for both rows
-        // of a pair; uniform column offsets in scalar registers, the pair a per-lane offset, the
-        // direction at immediate LDS offsets), then one chunk for the rest of the row, whose
-        // missing entries repeat the last one and are weighted by zero.
         double qv[RPT];
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) qv[j] = 0.0;
-        for (int li = 0; li < hh; ++li) {
-          uint32_t so = (uint32_t)(li * ww) * colA;
-          const int lrow = li * Wp;
-          int d0 = 0;
-          for (; d0 + CH <= ww; d0 += CH) {
-            double2 bv[RPT / 2][CH];
-#pragma unroll
-            for (int jj = 0; jj < RPT / 2; ++jj)
-#pragma unroll
-              for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)k * colA);
-#pragma unroll
-            for (int jj = 0; jj < RPT / 2; ++jj) {
-              const double* p0 = sp + corner[2 * jj] + lrow + d0;
-              const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
-#pragma unroll
-              for (int k = 0; k < CH; ++k) {
-                qv[2 * jj] += bv[jj][k].x * p0[k];
-                qv[2 * jj + 1] += bv[jj][k].y * p1[k];
-              }
-            }
-            so += (uint32_t)CH * colA;
-          }
-          if (d0 < ww) {
-            const int last = ww - d0 - 1;
-            double2 bv[RPT / 2][CH];
-#pragma unroll
-            for (int jj = 0; jj < RPT / 2; ++jj)
-#pragma unroll
-              for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)min(k, last) * colA);
-#pragma unroll
-            for (int jj = 0; jj < RPT / 2; ++jj) {
-              const double* p0 = sp + corner[2 * jj] + lrow + d0;
-              const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
-#pragma unroll
-              for (int k = 0; k < CH; ++k) {
-                const int kk = min(k, last);
-                qv[2 * jj] += (k <= last ? bv[jj][k].x : 0.0) * p0[kk];
-                qv[2 * jj + 1] += (k <= last ? bv[jj][k].y : 0.0) * p1[kk];
-              }
-            }
-          }
-        }
+        apply_C(pv, sig1, qv);
         double pq = 0.0;
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          qv[j] += sig1 * pv[j];
-          pq += pv[j] * qv[j];
-        }
+        for (int j = 0; j < RPT; ++j) pq += pv[j] * qv[j];
         const double tot = tail_sum1<NT>(pq, sred1);
         if (!(tot > 0.0) || !isfinite(tot)) {
           if (tid == 0) atomicOr(st.flags, isfinite(tot) ? kFlagNotSPD : kFlagNumeric);
@@ -469,12 +474,15 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
     }
     // a start adds its correction to the solution; a continuation hands x, r, p back to the
     // batched loop, which adds x
+    double un[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       const int64_t r = tail_row<NT>(tid, j);
+      un[j] = 0.0;
       if (r < m) {
         if (start) {
-          uacc[base + r] += xv[j];
+          un[j] = uacc[base + r] + xv[j];
+          uacc[base + r] = un[j];
         } else {
           st.x[base + r] = xv[j];
           st.r[base + r] = rv[j];
@@ -482,17 +490,58 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
         }
       }
     }
+    // the sweep's check of the new u: r = b - (1 + sigma) u - S u in FP64, kept for a further
+    // sweep, and the status from ||r|| / ||b|| (every thread has left the loop's last LDS reads
+    // behind the reductions' barriers)
+    const bool check = start && chk.b != nullptr;
+    double rr = 0.0;
+    if (check) {
+      double qv[RPT];
+      apply_C(un, sig1, qv);
+      double r2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int64_t r = tail_row<NT>(tid, j);
+        if (r < m) {
+          const double rt = chk.b[base + r] - qv[j];
+          st.r[base + r] = rt;
+          r2 += rt * rt;
+        }
+      }
+      const double rn = sqrt(tail_sum1<NT>(r2, sred1));
+      rr = bn > 0.0 ? rn / bn : 0.0;
+    }
     if (tid == 0) {
       if (st.prof.vectors) {
         const int done_its = it - st.iters[s];
         atomicAdd(st.prof.vectors, (unsigned long long)done_its);
-        atomicAdd(st.prof.flops, (double)done_its * st.prof.flops_per_vector);
+        atomicAdd(st.prof.flops, (double)(done_its + (check ? 1 : 0)) * st.prof.flops_per_vector);
         atomicAdd(st.prof.bytes, st.prof.bytes_per_vector);
       }
       st.rz[s] = rz;
       st.iters[s] = it;
-      st.relres[s] = relres;
-      st.done[s] = state;
+      if (!check) {
+        st.relres[s] = relres;
+        st.done[s] = state;
+      } else {
+        chk.sweeps[s] += 1;
+        st.relres[s] = relres;
+        chk.relres[s] = rr;
+        if (!isfinite(rr)) {
+          atomicOr(st.flags, kFlagNumeric);
+          chk.fdone[s] = 2;
+          st.done[s] = 1;
+        } else if (rr <= chk.rtol) {
+          chk.fdone[s] = 1;
+          st.done[s] = 1;
+        } else if (it >= st.max_iter) {
+          chk.fdone[s] = chk.fixed ? 3 : 2;
+          st.done[s] = 1;
+        } else {
+          st.done[s] = 0;
+          st.thresh[s] = chk.fixed ? 0.0 : 0.5 * chk.rtol * bn;
+        }
+      }
     }
     __syncthreads();
   }
@@ -558,7 +607,8 @@ constexpr size_t kTailLdsBig = 150 * 1024;
 
 template <int P, int RPT, int NT>
 hipError_t tail_go(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act, const int32_t* nact,
-                   int32_t* qctr, int64_t grid, const double* r0, double* uacc, hipStream_t st) {
+                   int32_t* qctr, int64_t grid, const double* r0, double* uacc, const TailCheck& chk,
+                   hipStream_t st) {
   if ((int64_t)RPT * NT < s.m) return hipErrorInvalidValue;  // every row has a thread
   const void* fn = (const void*)k_pcg_tail<P, RPT, NT>;
   // the kernel's static LDS (read once per instantiation): static + dynamic stays within the CU's
@@ -590,20 +640,22 @@ hipError_t tail_go(const PCGState& s, const LMP& lmp, const TailApply& ap, const
   if (e != hipSuccess) return e;
   const int64_t resident = std::max<int64_t>((int64_t)per_cu * cus, 1);
   const dim3 gdim((unsigned)std::max<int64_t>(std::min(grid, resident), 1)), b(NT);
-  hipLaunchKernelGGL((k_pcg_tail<P, RPT, NT>), gdim, b, lds, st, s, lmp, ap, act, nact, qctr, phi_lds, r0, uacc);
+  hipLaunchKernelGGL((k_pcg_tail<P, RPT, NT>), gdim, b, lds, st, s, lmp, ap, act, nact, qctr, phi_lds, r0, uacc,
+                     chk);
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t tail_rows(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act, const int32_t* nact,
-                     int32_t* qctr, int64_t grid, const double* r0, double* uacc, hipStream_t st) {
+                     int32_t* qctr, int64_t grid, const double* r0, double* uacc, const TailCheck& chk,
+                     hipStream_t st) {
   const int nt = tail_threads(s.m);
   const int64_t rpt = (s.m + nt - 1) / nt;
-  if (nt == 128) return tail_go<P, 2, 128>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
-  if (nt == 256) return tail_go<P, 2, 256>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
-  if (nt == 1024) return tail_go<P, 4, 1024>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
-  if (rpt <= 2) return tail_go<P, 2, 512>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
-  if (rpt <= 4) return tail_go<P, 4, 512>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+  if (nt == 128) return tail_go<P, 2, 128>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
+  if (nt == 256) return tail_go<P, 2, 256>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
+  if (nt == 1024) return tail_go<P, 4, 1024>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
+  if (rpt <= 2) return tail_go<P, 2, 512>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
+  if (rpt <= 4) return tail_go<P, 4, 512>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
   return hipErrorInvalidValue;
 }
 
@@ -630,21 +682,21 @@ hipError_t launch_order_live(const int32_t* done, const double* sigma, int64_t S
 
 hipError_t launch_pcg_tail(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
                            const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,
-                           hipStream_t st) {
+                           const TailCheck& chk, hipStream_t st) {
   if (s.m < 1 || s.m > kTailMaxM || s.m != ap.m || !act || !nact || !qctr || !tail_fits(ap) ||
-      ((r0 == nullptr) != (uacc == nullptr)))
+      ((r0 == nullptr) != (uacc == nullptr)) || (chk.b && (!r0 || !chk.fdone || !chk.sweeps || !chk.relres)))
     return hipErrorInvalidValue;
   if (ap.kind == 0 && !ap.band) return hipErrorInvalidValue;
   if (ap.kind == 1 && !ap.S) return hipErrorInvalidValue;
   if (lmp.p > 0 && (!lmp.Phi32 || !lmp.SPhi32 || !lmp.G || !lmp.theta || !lmp.dmin)) return hipErrorInvalidValue;
   switch (lmp.p) {
-    case 0: return tail_rows<0>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
-    case 4: return tail_rows<4>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
-    case 8: return tail_rows<8>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
-    case 10: return tail_rows<10>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
-    case 12: return tail_rows<12>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
-    case 16: return tail_rows<16>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
-    case 20: return tail_rows<20>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+    case 0: return tail_rows<0>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
+    case 4: return tail_rows<4>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
+    case 8: return tail_rows<8>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
+    case 10: return tail_rows<10>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
+    case 12: return tail_rows<12>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
+    case 16: return tail_rows<16>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
+    case 20: return tail_rows<20>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -140,8 +140,8 @@ hipError_t pcg_fused_timed(Prec prec, const PCGState& s, const LMP& lmp, int mod
 
 hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
                           const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,
-                          hipStream_t st) {
-  if (!g_prof.on) return launch_pcg_tail(s, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+                          const TailCheck& chk, hipStream_t st) {
+  if (!g_prof.on) return launch_pcg_tail(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
   // per system-iteration: the apply and the PCG step; per system: a start reads its residual and
   // reads and writes its solution, a continuation reads and writes x, r, p; per launch: the band
   // (or S) and the FP32 Ritz bases
@@ -153,7 +153,7 @@ hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap
                [&](const ProfDev* pd) {
                  PCGState sp = s;
                  sp.prof = pd ? *pd : ProfDev{};
-                 return launch_pcg_tail(sp, lmp, ap, act, nact, qctr, grid, r0, uacc, st);
+                 return launch_pcg_tail(sp, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
                });
 }
 
