@@ -227,7 +227,7 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
                                   int64_t extra_fp64_applies, const int64_t* adj, int inner_fp64, int fixed,
                                   const int32_t* flags,
                                   const int32_t* fallbacks, int64_t* out) {
-  __shared__ int64_t acc[4][256];
+  __shared__ int64_t acc[4][4];
   const int t = threadIdx.x;
   int64_t it = 0, sw = 0, nc = 0, mx = 0;
   for (int64_t s = t; s < S; s += 256) {
@@ -236,14 +236,24 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
     nc += (fdone[s] != 1);
     mx = max(mx, (int64_t)iters[s]);
   }
-  acc[0][t] = it;
-  acc[1][t] = sw;
-  acc[2][t] = nc;
-  acc[3][t] = mx;
+  // wavefront sums by shuffles, then the four wavefronts in order
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    it += __shfl_xor(it, o, 64);
+    sw += __shfl_xor(sw, o, 64);
+    nc += __shfl_xor(nc, o, 64);
+    mx = max(mx, __shfl_xor(mx, o, 64));
+  }
+  if ((t & 63) == 0) {
+    acc[0][t >> 6] = it;
+    acc[1][t >> 6] = sw;
+    acc[2][t >> 6] = nc;
+    acc[3][t >> 6] = mx;
+  }
   __syncthreads();
   if (t == 0) {
     int64_t a = 0, b = 0, c = 0, d = 0;
-    for (int j = 0; j < 256; ++j) {
+    for (int j = 0; j < 4; ++j) {
       a += acc[0][j];
       b += acc[1][j];
       c += acc[2][j];
@@ -1175,11 +1185,36 @@ int bcg_solve_all(Plan& pl, const Options& op, hipStream_t st) {
 // Outer sweeps form the true residual r = b - C u in FP64; the inner PCG (apply precision
 // op.inner) solves C d = r to the per-system target and u += d.  One inner iteration is two
 // launches: the covariance apply on the active columns, and the fused PCG kernel.
-// finalize (optional): enqueues the work that consumes u (the quadrature sum, the final update,
-// the statistics).  With host synchronization it is enqueued before each later sweep's status
-// is read, so the read overlaps it; *finalized tells whether the last enqueued copy saw the final
-// u (else the caller enqueues it once more).
-int stage_solve(Plan& pl, const Options& op, hipStream_t st, const std::function<int()>& finalize = {},
+// The sweep check's pinned landing place (live count, the call's counters) and its event, one per
+// host thread (calls on one thread are sequential), kept for the thread's lifetime.
+struct HostStage {
+  int32_t nact;
+  int32_t pad;
+  int64_t cnt[INFOESRF_NUM_COUNTERS];
+};
+HostStage* host_stage() {
+  static thread_local HostStage* h = nullptr;
+  if (!h && hipHostMalloc((void**)&h, sizeof(HostStage), hipHostMallocDefault) != hipSuccess) h = nullptr;
+  return h;
+}
+hipEvent_t host_event() {
+  static thread_local hipEvent_t e = nullptr;
+  if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+  return e;
+}
+
+// The work that consumes u: status (the call's counters and statistics) and output (the
+// quadrature sum and the final update).  Both are idempotent.
+struct Finalize {
+  std::function<int()> status, output;
+};
+
+// fin (optional): with host synchronization, each later sweep's check enqueues fin->status and
+// copies the counters with the live count, records an event, enqueues fin->output and waits
+// only for the event, so the output overlaps the wait and the call can return while it runs;
+// *finalized tells whether the last check did this with the final u (then host_stage() holds
+// the call's counters), else the caller runs both once more.
+int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin = nullptr,
                 bool* finalized = nullptr) {
   Inst& in = pl.in;
   Sys& sy = pl.sy;
@@ -1289,10 +1324,17 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const std::function
     // microseconds), so that status is not read on the host
     if (op.host_sync && !(persist && sweep == 0)) {
       IE_HIP(launch_compact(sy.done, S, sy.act2, sy.nact2, st));
-      IE_HIP(hipMemcpyAsync(&h_nact, sy.nact2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      const bool spec = finalize && sweep > 0;
-      if (spec) IE_TRY(finalize());
-      IE_HIP(hipStreamSynchronize(st));
+      HostStage* hs = host_stage();
+      hipEvent_t ev = host_event();
+      IE_CHECK(hs && ev, INFOESRF_ERR_HIP, "pinned host staging or event creation failed");
+      const bool spec = fin && sweep > 0;
+      if (spec) IE_TRY(fin->status());
+      IE_HIP(hipMemcpyAsync(&hs->nact, sy.nact2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      if (spec) IE_HIP(hipMemcpyAsync(hs->cnt, pl.in.counters, sizeof(hs->cnt), hipMemcpyDeviceToHost, st));
+      IE_HIP(hipEventRecord(ev, st));
+      if (spec) IE_TRY(fin->output());
+      IE_HIP(hipEventSynchronize(ev));
+      h_nact = hs->nact;
       if (h_nact == 0 || sweep == max_sweeps) {
         if (finalized) *finalized = spec;
         break;
@@ -1385,11 +1427,15 @@ int finish_enqueue(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t e
 }
 
 // The host half: with host synchronization, the status code and its message.
-int finish_read(Plan& pl, const Options& op, hipStream_t st) {
+int finish_read(Plan& pl, const Options& op, hipStream_t st, const int64_t* staged = nullptr) {
   if (!op.host_sync) return 0;
   int64_t cnt[INFOESRF_NUM_COUNTERS];
-  IE_HIP(hipMemcpyAsync(cnt, pl.in.counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
-  IE_HIP(hipStreamSynchronize(st));
+  if (staged) {
+    std::memcpy(cnt, staged, sizeof(cnt));
+  } else {
+    IE_HIP(hipMemcpyAsync(cnt, pl.in.counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
+    IE_HIP(hipStreamSynchronize(st));
+  }
   const int code = (int)cnt[INFOESRF_CNT_STATUS];
   if (code < 0) {
     if (code == INFOESRF_ERR_NOT_SPD) set_error("PCG curvature p^T C p <= 0: localized covariance not PSD");
@@ -1529,7 +1575,7 @@ size_t instance_ws_bytes(const infoesrf_problem* P, int32_t Q, bool mean, const 
 // validation, set-up, right-hand sides, nodes, preconditioner and the solves.
 int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_nodes, const double* p_weights,
                        const double* y, const infoesrf_opts* opts, Plan& pl, Options& op, void* ws,
-                       size_t ws_bytes, hipStream_t st, const std::function<int()>& finalize = {},
+                       size_t ws_bytes, hipStream_t st, const Finalize* fin = nullptr,
                        bool* finalized = nullptr) {
   IE_TRY(check_problem(prob));
   IE_TRY(resolve_options(prob, opts, op));
@@ -1570,7 +1616,7 @@ int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_
                      (int64_t)0, 0.0);
   IE_HIP(hipGetLastError());
   IE_TRY(stage_precond(pl, op, st));
-  IE_TRY(stage_solve(pl, op, st, finalize, finalized));
+  IE_TRY(stage_solve(pl, op, st, fin, finalized));
   return 0;
 }
 
@@ -1765,18 +1811,22 @@ int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const 
   const int64_t N = prob->N;
   // u_bar_i = sum_q p_q u_{q,i}; Xa_pert = sqrt(N-1) (Z - P H^T R^{-1/2} U_bar); idempotent, so
   // the solve may enqueue it before its last status read and again if a later sweep changes u
-  auto finalize = [&]() -> int {
+  Finalize fin;
+  fin.status = [&]() -> int { return finish_enqueue(pl, op, stats, 2 * pl.pr.k + N, st); };
+  fin.output = [&]() -> int {
     Sys& sy = pl.sy;
     IE_HIP(launch_quad_combine(sy.u, sy.ldm, pl.in.m, N, Q, sy.pw, pl.fn.ubar, sy.ldm, 0, st));
     IE_HIP(launch_iota(pl.fn.act, pl.fn.nact, N, st));
     IE_TRY(apply_state(pl, pl.fn.ubar, sy.ldm, pl.fn.act, pl.fn.nact, N, op.rows_per_wave, st));
     IE_HIP(launch_final_pert(pl.in.Z, (const double*)pl.bf.T, ld64(pl.in.n), pl.in.n, N,
                              std::sqrt((double)(N - 1)), Xa_pert, st));
-    return finish_enqueue(pl, op, stats, 2 * pl.pr.k + N, st);
+    return 0;
   };
   bool finalized = false;
-  IE_TRY(perturbation_solve(prob, Q, s_nodes, p_weights, y, opts, pl, op, ws, ws_bytes, st, finalize, &finalized));
-  if (!finalized) IE_TRY(finalize());
+  IE_TRY(perturbation_solve(prob, Q, s_nodes, p_weights, y, opts, pl, op, ws, ws_bytes, st, &fin, &finalized));
+  if (finalized) return finish_read(pl, op, st, host_stage()->cnt);  // counters came with the last check
+  IE_TRY(fin.status());
+  IE_TRY(fin.output());
   return finish_read(pl, op, st);
 }
 

@@ -88,6 +88,33 @@ __device__ inline double wave_sum_dpp(double x) {
   return x;
 }
 
+// Exclusive prefix sum of one int per thread over a workgroup of NT threads (wavefront scans by
+// shuffles, then the NT / 64 wavefront totals in order); *total (LDS) receives the sum.  swave
+// holds NT / 64 ints of LDS.
+template <int NT>
+__device__ inline int block_exclusive_scan(int v, int* swave, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) swave[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+      const int t = swave[w];
+      swave[w] = run;
+      run += t;
+    }
+    *total = run;
+  }
+  __syncthreads();
+  return swave[wave] + x - v;
+}
+
 // ---------------------------------------------------------------- kernels (launchers)
 // All launchers enqueue on `st` and return hipError_t of the launch.
 

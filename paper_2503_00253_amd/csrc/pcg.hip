@@ -398,27 +398,17 @@ __global__ void k_round_ritz(double* __restrict__ Phi, double* __restrict__ SPhi
 
 // --------------------------------------------------------------- list and vector kernels
 
-__global__ void k_compact(const int32_t* __restrict__ done, int64_t S, int32_t* __restrict__ act,
-                          int32_t* __restrict__ nact) {
-  __shared__ int32_t cnt[256];
+__global__ __launch_bounds__(256) void k_compact(const int32_t* __restrict__ done, int64_t S,
+                                                 int32_t* __restrict__ act, int32_t* __restrict__ nact) {
+  __shared__ int swave[4];
+  __shared__ int total;
   const int t = threadIdx.x;
   const int64_t per = (S + 255) / 256;
   const int64_t a = t * per, b = min<int64_t>(S, a + per);
   int32_t c = 0;
   for (int64_t s = a; s < b; ++s) c += (done[s] == 0);
-  cnt[t] = c;
-  __syncthreads();
-  if (t == 0) {
-    int32_t run = 0;
-    for (int i = 0; i < 256; ++i) {
-      const int32_t v = cnt[i];
-      cnt[i] = run;
-      run += v;
-    }
-    *nact = run;
-  }
-  __syncthreads();
-  int32_t pos = cnt[t];
+  int32_t pos = block_exclusive_scan<256>(c, swave, &total);
+  if (t == 0) *nact = total;
   for (int64_t s = a; s < b; ++s)
     if (done[s] == 0) act[pos++] = (int32_t)s;
 }

@@ -550,13 +550,14 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
 // The live systems (done == 0) node by node in order of increasing shift (the slowest first),
 // members in order within a node: systems s = q G + i with one shift per group of G.  One
 // workgroup: the Q = S / G node shifts are ranked in LDS (ties by node index), then the systems
-// are compacted in that order (per-thread chunks, a serial scan of the 1024 chunk counts).
+// are compacted in that order (per-thread chunks and a workgroup scan of their counts).
 constexpr int kOrderQ = 4096;
 __global__ __launch_bounds__(1024) void k_order_live(const int32_t* __restrict__ done,
                                                      const double* __restrict__ sigma, int64_t S, int64_t G,
                                                      int32_t* __restrict__ act, int32_t* __restrict__ nact) {
   __shared__ int32_t perm[kOrderQ];
-  __shared__ int32_t cnt[1024];
+  __shared__ int swave[16];
+  __shared__ int total;
   const int t = threadIdx.x;
   const int Q = (int)(S / G);
   for (int q = t; q < Q; q += 1024) {
@@ -573,19 +574,8 @@ __global__ __launch_bounds__(1024) void k_order_live(const int32_t* __restrict__
   const int64_t a = t * per, b = min<int64_t>(S, a + per);
   int32_t c = 0;
   for (int64_t u = a; u < b; ++u) c += (done[(int64_t)perm[u / G] * G + u % G] == 0);
-  cnt[t] = c;
-  __syncthreads();
-  if (t == 0) {
-    int32_t run = 0;
-    for (int i = 0; i < 1024; ++i) {
-      const int32_t v = cnt[i];
-      cnt[i] = run;
-      run += v;
-    }
-    *nact = run;
-  }
-  __syncthreads();
-  int32_t pos = cnt[t];
+  int32_t pos = block_exclusive_scan<1024>(c, swave, &total);
+  if (t == 0) *nact = total;
   for (int64_t u = a; u < b; ++u) {
     const int64_t sys = (int64_t)perm[u / G] * G + u % G;
     if (done[sys] == 0) act[pos++] = (int32_t)sys;

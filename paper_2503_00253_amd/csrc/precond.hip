@@ -77,6 +77,40 @@ __global__ __launch_bounds__(256) void k_gram_partial(Strided A, Strided B, int6
   }
 }
 
+// The whole Gram matrix in one workgroup when k <= K: each thread accumulates the K x K products
+// of its rows in registers, the wavefronts sum them by DPP and four partials per entry are added
+// in order.  One launch instead of partials + reduction for the small bases of the setup.
+template <int K>
+__global__ __launch_bounds__(256) void k_gram_small(Strided A, Strided B, int64_t m, int k, double* __restrict__ G) {
+  __shared__ double part[4][K * K];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double acc[K * K];
+#pragma unroll
+  for (int e = 0; e < K * K; ++e) acc[e] = 0.0;
+  for (int64_t r = tid; r < m; r += 256) {
+    double av[K], bv[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      av[a] = a < k ? A.ptr[r * A.rs + a * A.cs] : 0.0;
+      bv[a] = a < k ? B.ptr[r * B.rs + a * B.cs] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+#pragma unroll
+      for (int b = 0; b < K; ++b) acc[a * K + b] += av[a] * bv[b];
+  }
+#pragma unroll
+  for (int e = 0; e < K * K; ++e) {
+    const double x = wave_sum_dpp(acc[e]);
+    if (lane == 63) part[wave][e] = x;
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += 256) {
+    const int i = (e / k) * K + e % k;
+    G[e] = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
+  }
+}
+
 __global__ void k_gram_reduce(const double* __restrict__ scratch, int nchunks, int k, double* __restrict__ G) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= k * k) return;
@@ -315,6 +349,11 @@ int gram_chunks(int64_t m) { return (int)((m + kGramChunk - 1) / kGramChunk); }
 
 hipError_t launch_gram(Strided A, Strided B, int64_t m, int k, double* G, double* scratch, hipStream_t st) {
   if (k < 1 || k > kMaxSketch || m < 1) return hipErrorInvalidValue;
+  if (k <= 8 && m <= 8192) {
+    if (k <= 4) hipLaunchKernelGGL(k_gram_small<4>, dim3(1), dim3(256), 0, st, A, B, m, k, G);
+    else hipLaunchKernelGGL(k_gram_small<8>, dim3(1), dim3(256), 0, st, A, B, m, k, G);
+    return hipGetLastError();
+  }
   const int nchunks = gram_chunks(m);
   hipLaunchKernelGGL(k_gram_partial, dim3(nchunks), dim3(256), 0, st, A, B, m, k, scratch);
   hipError_t e = hipGetLastError();
