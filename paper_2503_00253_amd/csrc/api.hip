@@ -915,6 +915,13 @@ int stage_precond(Plan& pl, const Options& op, hipStream_t st) {
   IE_HIP(launch_iota(pr.act, pr.nact, k, st));
   IE_HIP(launch_fill_f64(pr.sig, -1.0, round_up(k, kSysTile), st));  // (1 + sigma) = 0: pure S
   IE_TRY(apply_S(pl, Prec::F64, pr.Om, ldm, pr.act, pr.nact, k, pr.sig, pr.Y, op.rows_per_wave, st));
+  if (small_basis_fits(k, pr.p, in.m)) {  // the small dense steps in two launches
+    IE_HIP(launch_cholqr2_small(pr.Y, in.m, k, ldm, pr.Qb, in.flags, st));
+    IE_TRY(apply_S(pl, Prec::F64, pr.Qb, ldm, pr.act, pr.nact, k, pr.sig, pr.SQ, op.rows_per_wave, st));
+    IE_HIP(launch_ritz_small(pr.Qb, pr.SQ, in.m, k, pr.p, ldm, pr.theta, pr.Phi, pr.SPhi, pr.Phi32, pr.SPhi32, pr.G,
+                             st));
+    return 0;
+  }
   // Cholesky-QR twice: Qb = Y R^{-1}
   const Strided Ys{pr.Y, 1, ldm}, Qs{pr.Qb, 1, ldm};
   IE_HIP(launch_gram(Ys, Ys, in.m, k, pr.Rinv, pr.gscr, st));

@@ -77,12 +77,12 @@ __global__ __launch_bounds__(256) void k_gram_partial(Strided A, Strided B, int6
   }
 }
 
-// The whole Gram matrix in one workgroup when k <= K: each thread accumulates the K x K products
-// of its rows in registers, the wavefronts sum them by DPP and four partials per entry are added
-// in order.  One launch instead of partials + reduction for the small bases of the setup.
+// The whole Gram matrix G = A^T B (row-major k x k) on one 256-thread workgroup when k <= K: each
+// thread accumulates the K x K products of its rows (tid + 256 i) in registers, the wavefronts
+// sum them by DPP and four partials per entry are added in order.  part holds 4 K^2 doubles of
+// LDS; G may be LDS or global memory and is complete when the call returns (a barrier ends it).
 template <int K>
-__global__ __launch_bounds__(256) void k_gram_small(Strided A, Strided B, int64_t m, int k, double* __restrict__ G) {
-  __shared__ double part[4][K * K];
+__device__ inline void gram_wg(Strided A, Strided B, int64_t m, int k, double* part, double* G) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double acc[K * K];
 #pragma unroll
@@ -102,13 +102,21 @@ __global__ __launch_bounds__(256) void k_gram_small(Strided A, Strided B, int64_
 #pragma unroll
   for (int e = 0; e < K * K; ++e) {
     const double x = wave_sum_dpp(acc[e]);
-    if (lane == 63) part[wave][e] = x;
+    if (lane == 63) part[wave * K * K + e] = x;
   }
   __syncthreads();
   for (int e = tid; e < k * k; e += 256) {
     const int i = (e / k) * K + e % k;
-    G[e] = ((part[0][i] + part[1][i]) + part[2][i]) + part[3][i];
+    G[e] = ((part[i] + part[K * K + i]) + part[2 * K * K + i]) + part[3 * K * K + i];
   }
+  __syncthreads();
+}
+
+// One launch instead of partials + reduction for the small bases of the setup.
+template <int K>
+__global__ __launch_bounds__(256) void k_gram_small(Strided A, Strided B, int64_t m, int k, double* __restrict__ G) {
+  __shared__ double part[4 * K * K];
+  gram_wg<K>(A, B, m, k, part, G);
 }
 
 __global__ void k_gram_reduce(const double* __restrict__ scratch, int nchunks, int k, double* __restrict__ G) {
@@ -198,19 +206,24 @@ __device__ inline void jacobi_player(int slot, int step, int ke, int k, int* p, 
   (void)k;
 }
 
+// The rotation (c, s) that zeroes a_pq of the 2 x 2 block [a_pp a_pq; a_pq a_qq]: the smaller
+// root t of t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp) / (2 a_pq), written as
+// t = sign(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)): one square root and one division.
+__device__ inline void jacobi_cs(double app, double aqq, double apq, double* c, double* sn) {
+  const double d = aqq - app;
+  const double a2 = 2.0 * apq;
+  const double tt = (d >= 0.0 ? a2 : -a2) / (fabs(d) + sqrt(d * d + a2 * a2));
+  *c = rsqrt(1.0 + tt * tt);
+  *sn = tt * *c;
+}
+
 __device__ inline void jacobi_rot(const double* A, int k, int p, int q, double* c, double* sn) {
   *c = 1.0;
   *sn = 0.0;
   if (q >= k) return;  // the dummy player of an odd k
   const double apq = A[p * k + q];
   if (apq == 0.0) return;
-  // the smaller root t of t^2 + 2 tau t - 1 = 0, tau = d / (2 a_pq), written as
-  // t = sign(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)): one square root and one division
-  const double d = A[q * k + q] - A[p * k + p];
-  const double a2 = 2.0 * apq;
-  const double tt = (d >= 0.0 ? a2 : -a2) / (fabs(d) + sqrt(d * d + a2 * a2));
-  *c = rsqrt(1.0 + tt * tt);
-  *sn = tt * *c;
+  jacobi_cs(A[p * k + p], A[q * k + q], apq, c, sn);
 }
 
 __global__ __launch_bounds__(256) void k_sym_eig(double* T, int k, double* evec, double* evals) {
@@ -324,6 +337,194 @@ __global__ void k_lmp_finish(const double* evals, const double* evec, int k, int
   }
 }
 
+// ----------------------------------------------------------- small bases on one workgroup
+// With at most 8 sketch columns (p + oversample) the setup's small dense steps run as two
+// launches: Cholesky-QR twice of Y = S Omega, then the Rayleigh quotient T = Qb^T (S Qb), its
+// eigendecomposition, the top-p selection, the FP32-rounded Ritz vectors Phi, S Phi and their
+// three Gram blocks; the same arithmetic as the step-per-launch chain.
+
+// Upper Cholesky factor of the SPD k x k matrix G (row-major) by one thread, in registers:
+// R[a*k+b] for b >= a.  A non-positive pivot is replaced by 1 and reported.
+template <int K>
+__device__ inline bool chol_upper_serial(const double* G, int k, double* R) {
+  double r[K][K];
+#pragma unroll
+  for (int a = 0; a < K; ++a)
+#pragma unroll
+    for (int b = 0; b < K; ++b) r[a][b] = (a < k && b < k && b >= a) ? G[a * k + b] : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    if (j < k) {
+      double d = r[j][j];
+      if (!(d > 0.0)) {
+        ok = false;
+        d = 1.0;
+      } else {
+        d = sqrt(d);
+      }
+      r[j][j] = d;
+#pragma unroll
+      for (int c = j + 1; c < K; ++c) r[j][c] /= d;
+#pragma unroll
+      for (int a = j + 1; a < K; ++a)
+#pragma unroll
+        for (int b = a; b < K; ++b) r[a][b] -= r[j][a] * r[j][b];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < K; ++a)
+#pragma unroll
+    for (int b = 0; b < K; ++b)
+      if (a < k && b < k) R[a * k + b] = r[a][b];
+  return ok;
+}
+
+// Q = orth(Y) by Cholesky-QR twice: G = X^T X, X <- X R^{-1} (each row q solves q R = x by
+// forward substitution), first with X = Y, then with X = Q.  Y and Q column-major, leading
+// dimension ld.  Every thread works on the same rows (tid + 256 i) in every pass.
+template <int K>
+__global__ __launch_bounds__(256) void k_cholqr2_small(const double* __restrict__ Y, int64_t m, int k, int64_t ld,
+                                                       double* __restrict__ Q, int32_t* flags) {
+  __shared__ double part[4 * K * K];
+  __shared__ double G[K * K], R[K * K];
+  for (int pass = 0; pass < 2; ++pass) {
+    const double* X = pass == 0 ? Y : Q;
+    gram_wg<K>(Strided{X, 1, ld}, Strided{X, 1, ld}, m, k, part, G);
+    if (threadIdx.x == 0 && !chol_upper_serial<K>(G, k, R)) atomicOr(flags, kFlagNumeric);
+    __syncthreads();
+    for (int64_t r = threadIdx.x; r < m; r += 256) {
+      double x[K], q[K];
+#pragma unroll
+      for (int a = 0; a < K; ++a) x[a] = a < k ? X[a * ld + r] : 0.0;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        q[j] = 0.0;
+        if (j < k) {
+          double t = x[j];
+#pragma unroll
+          for (int a = 0; a < j; ++a) t -= q[a] * R[a * k + j];
+          q[j] = t / R[j * k + j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (j < k) Q[j * ld + r] = q[j];
+    }
+    __syncthreads();  // R is rewritten by the next pass
+  }
+}
+
+// Lane src's value of a double, for each lane (ds_bpermute on both halves).
+__device__ inline double lane_shfl(double v, int src) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Partner of index i in step `step` of the round-robin ordering over ke (even) players: slot 0
+// holds player 0, slot t > 0 player 1 + (t - 1 + step) mod (ke - 1), and slots t and ke - 1 - t
+// are paired.  Indices >= ke partner themselves.
+__device__ inline int jacobi_partner(int i, int step, int ke) {
+  if (i >= ke) return i;
+  const int slot = i == 0 ? 0 : 1 + ((i - 1 - step) % (ke - 1) + (ke - 1)) % (ke - 1);
+  const int ps = ke - 1 - slot;
+  return ps == 0 ? 0 : 1 + (ps - 1 + step) % (ke - 1);
+}
+
+// T = Qb^T (S Qb), its Jacobi eigendecomposition on the first wavefront (lane i K + j holds A_ij
+// and V_ij; each step rotates the k/2 pairs of the round-robin ordering at once, exchanging
+// entries between lanes), the p largest eigenpairs (ties by index), Phi = Qb V_p and
+// S Phi = (S Qb) V_p rounded to FP32 (kept in FP32 and as the rounded FP64 values), theta, and
+// the Gram blocks Phi^T Phi, Phi^T S Phi, (S Phi)^T S Phi of the rounded vectors into G.
+template <int K, int PB>
+__global__ __launch_bounds__(256) void k_ritz_small(const double* __restrict__ Qb, const double* __restrict__ SQ,
+                                                    int64_t m, int k, int p, int64_t ld, double* __restrict__ theta,
+                                                    double* __restrict__ Phi, double* __restrict__ SPhi,
+                                                    float* __restrict__ Phi32, float* __restrict__ SPhi32,
+                                                    double* __restrict__ G) {
+  static_assert(K * K <= 64 && PB <= K, "one matrix entry a lane");
+  __shared__ double part[4 * K * K];
+  __shared__ double T[K * K], V[K * K], ev[K], sel[K * PB];
+  __shared__ int order[K];
+  const int tid = threadIdx.x;
+  gram_wg<K>(Strided{Qb, 1, ld}, Strided{SQ, 1, ld}, m, k, part, T);
+  if (tid < 64) {
+    const int i = tid / K, j = tid % K;
+    const bool in = tid < K * K && i < k && j < k;
+    double a = in ? 0.5 * (T[i * k + j] + T[j * k + i]) : 0.0;
+    double v = (in && i == j) ? 1.0 : 0.0;
+    const int ke = k + (k & 1);
+    for (int sweep = 0; sweep < 40; ++sweep) {
+      const double off = wave_sum_dpp(in && i != j ? a * a : 0.0);
+      const double dia = wave_sum_dpp(in && i == j ? a * a : 0.0);
+      // relative off-diagonal norm 1e-10: the Ritz vectors are rounded to FP32 afterwards
+      if (lane_shfl(off, 63) <= 1e-20 * lane_shfl(dia, 63)) break;
+      for (int step = 0; step < ke - 1; ++step) {
+        const int pi = jacobi_partner(i, step, ke), pj = jacobi_partner(j, step, ke);
+        const int p1 = min(i, pi), q1 = max(i, pi);
+        const double app = lane_shfl(a, p1 * K + p1), aqq = lane_shfl(a, q1 * K + q1);
+        const double apq = lane_shfl(a, p1 * K + q1);
+        double c1 = 1.0, s1 = 0.0;
+        if (q1 < k && q1 != p1 && apq != 0.0) jacobi_cs(app, aqq, apq, &c1, &s1);
+        // the column pair's rotation is the one row j's lanes found
+        const double c2 = lane_shfl(c1, j * K), s2 = lane_shfl(s1, j * K);
+        // rows [p; q] <- [c -s; s c] [p; q], then columns likewise; V <- V J
+        const double ar = lane_shfl(a, pi * K + j);
+        const double b = i <= pi ? c1 * a - s1 * ar : s1 * ar + c1 * a;
+        const double bc = lane_shfl(b, i * K + pj);
+        a = j <= pj ? c2 * b - s2 * bc : s2 * bc + c2 * b;
+        const double vc = lane_shfl(v, i * K + pj);
+        v = j <= pj ? c2 * v - s2 * vc : s2 * vc + c2 * v;
+      }
+    }
+    if (in) V[i * K + j] = v;
+    if (in && i == j) ev[i] = a;
+  }
+  __syncthreads();
+  if (tid < k) {
+    int rank = 0;
+    for (int i = 0; i < k; ++i) rank += (ev[i] > ev[tid]) || (ev[i] == ev[tid] && i < tid);
+    order[rank] = tid;
+  }
+  __syncthreads();
+  if (tid < p) theta[tid] = ev[order[tid]];
+  for (int e = tid; e < k * p; e += 256) sel[(e / p) * PB + e % p] = V[(e / p) * K + order[e % p]];
+  __syncthreads();
+  for (int64_t r = tid; r < m; r += 256) {
+    double q[K], sq[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      q[a] = a < k ? Qb[a * ld + r] : 0.0;
+      sq[a] = a < k ? SQ[a * ld + r] : 0.0;
+    }
+#pragma unroll
+    for (int jj = 0; jj < PB; ++jj) {
+      if (jj < p) {
+        double f = 0.0, g = 0.0;
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+          if (a < k) {
+            f += q[a] * sel[a * PB + jj];
+            g += sq[a] * sel[a * PB + jj];
+          }
+        }
+        const float f32 = (float)f, g32 = (float)g;
+        Phi32[jj * ld + r] = f32;
+        SPhi32[jj * ld + r] = g32;
+        Phi[jj * ld + r] = (double)f32;
+        SPhi[jj * ld + r] = (double)g32;
+      }
+    }
+  }
+  // the Gram blocks read back the rows this thread wrote
+  const Strided Ph{Phi, 1, ld}, SPh{SPhi, 1, ld};
+  gram_wg<PB>(Ph, Ph, m, p, part, G);
+  gram_wg<PB>(Ph, SPh, m, p, part, G + p * p);
+  gram_wg<PB>(SPh, SPh, m, p, part, G + 2 * p * p);
+}
+
 __global__ void k_min_reduce(const double* v, int64_t count, double* out) {
   __shared__ double red[256];
   double m = 1.0 / 0.0;
@@ -386,6 +587,32 @@ hipError_t launch_lmp_finish(const double* evals, const double* evec, int k, int
                              hipStream_t st) {
   if (k < 1 || k > kMaxSketch || p > k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_lmp_finish, dim3(1), dim3(64), 0, st, evals, evec, k, p, theta, sel);
+  return hipGetLastError();
+}
+
+bool small_basis_fits(int k, int p, int64_t m) { return k >= 1 && k <= 8 && p >= 1 && p <= k && m >= 1 && m <= 8192; }
+
+hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, double* Q, int32_t* flags,
+                                hipStream_t st) {
+  if (!Y || !Q || !flags || ld < m || !small_basis_fits(k, 1, m)) return hipErrorInvalidValue;
+  if (k <= 4) hipLaunchKernelGGL(k_cholqr2_small<4>, dim3(1), dim3(256), 0, st, Y, m, k, ld, Q, flags);
+  else hipLaunchKernelGGL(k_cholqr2_small<8>, dim3(1), dim3(256), 0, st, Y, m, k, ld, Q, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz_small(const double* Qb, const double* SQ, int64_t m, int k, int p, int64_t ld, double* theta,
+                             double* Phi, double* SPhi, float* Phi32, float* SPhi32, double* G, hipStream_t st) {
+  if (!Qb || !SQ || !theta || !Phi || !SPhi || !Phi32 || !SPhi32 || !G || ld < m || !small_basis_fits(k, p, m))
+    return hipErrorInvalidValue;
+  if (k <= 4)
+    hipLaunchKernelGGL((k_ritz_small<4, 4>), dim3(1), dim3(256), 0, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi, Phi32,
+                       SPhi32, G);
+  else if (p <= 4)
+    hipLaunchKernelGGL((k_ritz_small<8, 4>), dim3(1), dim3(256), 0, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi, Phi32,
+                       SPhi32, G);
+  else
+    hipLaunchKernelGGL((k_ritz_small<8, 8>), dim3(1), dim3(256), 0, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi, Phi32,
+                       SPhi32, G);
   return hipGetLastError();
 }
 
