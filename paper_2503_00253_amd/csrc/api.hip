@@ -114,9 +114,17 @@ __global__ void k_set_nodes(Nodes nd, int32_t Q, int64_t N, double* sigma, doubl
   if (t < extra) sigma[(int64_t)Q * N + t] = extra_sigma;
 }
 
-__global__ void k_fill_i64(int64_t* p, int64_t v, int64_t count) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < count) p[t] = v;
+// The per-system counters of a solve start at zero: iterations, sweeps, final status; and the
+// apply-count adjustment.
+__global__ void k_zero_counters(int32_t* __restrict__ iters, int32_t* __restrict__ sweeps,
+                                int32_t* __restrict__ fdone, int64_t count, int64_t* __restrict__ app_adj) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) {
+    iters[i] = 0;
+    sweeps[i] = 0;
+    fdone[i] = 0;
+  }
+  if (i == 0) *app_adj = 0;
 }
 
 // Sweep bookkeeping from true residual norms (iterative refinement).
@@ -906,14 +914,14 @@ int stage_precond(Plan& pl, const Options& op, hipStream_t st) {
   Inst& in = pl.in;
   const int k = pr.k;
   const int64_t ldm = pl.sy.ldm;
+  // the k sketch columns are applied as systems 0 .. k-1 with (1 + sigma) = 0: pure S
   if (op.sketch) {
     IE_HIP(launch_copy_cols(op.sketch, in.m, in.m, k, pr.Om, ldm, st));
+    IE_HIP(launch_iota(pr.act, pr.nact, k, st));
+    IE_HIP(launch_fill_f64(pr.sig, -1.0, round_up(k, kSysTile), st));
   } else {
-    IE_HIP(launch_fill_f64(pr.Om, 0.0, ldm * k, st));
-    IE_HIP(launch_sketch(op.seed, in.m, k, pr.Om, ldm, st));
+    IE_HIP(launch_sketch_setup(op.seed, in.m, k, pr.Om, ldm, pr.act, pr.nact, pr.sig, round_up(k, kSysTile), st));
   }
-  IE_HIP(launch_iota(pr.act, pr.nact, k, st));
-  IE_HIP(launch_fill_f64(pr.sig, -1.0, round_up(k, kSysTile), st));  // (1 + sigma) = 0: pure S
   IE_TRY(apply_S(pl, Prec::F64, pr.Om, ldm, pr.act, pr.nact, k, pr.sig, pr.Y, op.rows_per_wave, st));
   if (small_basis_fits(k, pr.p, in.m)) {  // the small dense steps in two launches
     IE_HIP(launch_cholqr2_small(pr.Y, in.m, k, ldm, pr.Qb, in.flags, st));
@@ -1250,10 +1258,8 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
   IE_HIP(launch_fill_f64(sy.u, 0.0, flat, st));
   const bool warm = in.net != nullptr;
   if (warm) IE_TRY(stage_warm(pl, st));
-  IE_HIP(launch_fill_i32(sy.iters, 0, sy.Spad, st));
-  IE_HIP(launch_fill_i32(sy.sweeps, 0, sy.Spad, st));
-  IE_HIP(launch_fill_i32(sy.fdone, 0, sy.Spad, st));
-  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, sy.app_adj, (int64_t)0, (int64_t)1);
+  hipLaunchKernelGGL(k_zero_counters, dim3(nb(sy.Spad)), dim3(256), 0, st, sy.iters, sy.sweeps, sy.fdone, sy.Spad,
+                     sy.app_adj);
   IE_HIP(hipGetLastError());
   const bool msc = op.msc_q0 >= 0 && !warm;
   const bool bcg = op.bcg_Q > 0 && !warm;
@@ -1293,8 +1299,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
   TailCheck chk{};
   if (persist) chk = TailCheck{sy.b, sy.fdone, sy.sweeps, sy.relres, op.rtol, op.fixed > 0 ? 1 : 0};
   auto run_tail = [&](int32_t* list, int32_t* count, int64_t bound, const double* r0) -> int {
-    IE_HIP(launch_order_live(sy.done, sy.sigma, S, grp, list, count, st));
-    IE_HIP(launch_fill_i32(sy.qctr, 0, 1, st));
+    IE_HIP(launch_order_live(sy.done, sy.sigma, S, grp, list, count, sy.qctr, st));
     IE_HIP(pcg_tail_timed(ps, lmp, tap, list, count, sy.qctr, bound, r0, r0 ? sy.u : nullptr,
                           r0 ? chk : TailCheck{}, st));
     return 0;
@@ -1318,8 +1323,10 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
     }
     const double* rcur = (r_is_b && persist) ? sy.b : sy.r;
     if (!checked) {
-      IE_HIP(launch_col_norms(rcur, m, S, ldm, sy.rn, st));
-      hipLaunchKernelGGL(k_sweep_status, dim3(nb(S)), dim3(256), 0, st, sy.rn, sy.bnorm, op.rtol, op.inner_rtol,
+      // the first residual of a zero start is b, whose norms are already there
+      const double* rn = r_is_b ? sy.bnorm : sy.rn;
+      if (!r_is_b) IE_HIP(launch_col_norms(rcur, m, S, ldm, sy.rn, st));
+      hipLaunchKernelGGL(k_sweep_status, dim3(nb(S)), dim3(256), 0, st, rn, sy.bnorm, op.rtol, op.inner_rtol,
                          fp64_inner ? 1 : 0, sy.iters, op.max_iter, op.fixed > 0 ? 1 : 0, sy.relres, sy.fdone,
                          sy.done, sy.thresh, sy.sweeps, (sweep > 0 || warm) ? 1 : 0, S, in.flags);
       IE_HIP(hipGetLastError());

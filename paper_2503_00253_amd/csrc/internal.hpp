@@ -392,9 +392,9 @@ hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap
 bool tail_fits(const TailApply& ap);
 // (act, *nact) = the live systems (done == 0) of S = Q G systems s = q G + i that share one shift
 // per group of G, node by node in order of increasing shift (ties by node), members in order;
-// Q <= 4096.
+// Q <= 4096.  A non-null qctr (the persistent kernel's queue counter) is set to zero.
 hipError_t launch_order_live(const int32_t* done, const double* sigma, int64_t S, int64_t G, int32_t* act,
-                             int32_t* nact, hipStream_t st);
+                             int32_t* nact, int32_t* qctr, hipStream_t st);
 // The fused PCG step with the measurement hook (profile slot INFOESRF_PROF_PCG); arguments as
 // launch_pcg_fused.
 hipError_t pcg_fused_timed(Prec prec, const PCGState& s, const LMP& lmp, int mode, int obs_domain, int plain,
@@ -440,6 +440,10 @@ struct Strided {
 };
 // Gaussian sketch by counter-based Philox4x32-10 + Box-Muller: out[j*ld + r] (system-major)
 hipError_t launch_sketch(uint64_t seed, int64_t m, int k, double* out, int64_t ld, hipStream_t st);
+// The same sketch over all ld rows (zeros past m), and the k columns as systems: act = 0 .. k-1,
+// *nact = k, sig[0 .. nsig) = -1 (nsig >= k).
+hipError_t launch_sketch_setup(uint64_t seed, int64_t m, int k, double* out, int64_t ld, int32_t* act, int32_t* nact,
+                               double* sig, int nsig, hipStream_t st);
 // Gram: G[a*k+b] = sum_r A(r, a) B(r, b), a,b < k (fixed order, deterministic)
 hipError_t launch_gram(Strided A, Strided B, int64_t m, int k, double* G, double* scratch, hipStream_t st);
 int gram_chunks(int64_t m);  // row chunks of launch_gram: scratch holds gram_chunks(m) * k * k doubles

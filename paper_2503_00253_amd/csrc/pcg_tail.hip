@@ -554,7 +554,8 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
 constexpr int kOrderQ = 4096;
 __global__ __launch_bounds__(1024) void k_order_live(const int32_t* __restrict__ done,
                                                      const double* __restrict__ sigma, int64_t S, int64_t G,
-                                                     int32_t* __restrict__ act, int32_t* __restrict__ nact) {
+                                                     int32_t* __restrict__ act, int32_t* __restrict__ nact,
+                                                     int32_t* __restrict__ qctr) {
   __shared__ int32_t perm[kOrderQ];
   __shared__ int swave[16];
   __shared__ int total;
@@ -575,7 +576,10 @@ __global__ __launch_bounds__(1024) void k_order_live(const int32_t* __restrict__
   int32_t c = 0;
   for (int64_t u = a; u < b; ++u) c += (done[(int64_t)perm[u / G] * G + u % G] == 0);
   int32_t pos = block_exclusive_scan<1024>(c, swave, &total);
-  if (t == 0) *nact = total;
+  if (t == 0) {
+    *nact = total;
+    if (qctr) *qctr = 0;
+  }
   for (int64_t u = a; u < b; ++u) {
     const int64_t sys = (int64_t)perm[u / G] * G + u % G;
     if (done[sys] == 0) act[pos++] = (int32_t)sys;
@@ -663,10 +667,10 @@ bool tail_fits(const TailApply& ap) {
 }
 
 hipError_t launch_order_live(const int32_t* done, const double* sigma, int64_t S, int64_t G, int32_t* act,
-                             int32_t* nact, hipStream_t st) {
+                             int32_t* nact, int32_t* qctr, hipStream_t st) {
   if (!done || !sigma || !act || !nact || G < 1 || S < 1 || S % G != 0 || S / G > kOrderQ)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_order_live, dim3(1), dim3(1024), 0, st, done, sigma, S, G, act, nact);
+  hipLaunchKernelGGL(k_order_live, dim3(1), dim3(1024), 0, st, done, sigma, S, G, act, nact, qctr);
   return hipGetLastError();
 }
 

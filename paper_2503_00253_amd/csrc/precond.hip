@@ -49,6 +49,29 @@ __global__ void k_sketch(uint64_t seed, int64_t m, int k, double* __restrict__ o
   out[j * ld + r] = g;
 }
 
+// The sketch of k_sketch over all ld rows of its k columns (rows past m zero), with the list of
+// the k columns as systems (act = 0 .. k-1, *nact = k) and their shifts (sig = -1: pure S).
+__global__ void k_sketch_setup(uint64_t seed, int64_t m, int k, double* __restrict__ out, int64_t ld,
+                               int32_t* __restrict__ act, int32_t* __restrict__ nact, double* __restrict__ sig,
+                               int nsig) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < nsig) sig[t] = -1.0;
+  if (t < k) act[t] = (int32_t)t;
+  if (t == 0) *nact = k;
+  if (t >= ld * k) return;
+  const int64_t j = t / ld, r = t % ld;
+  double g = 0.0;
+  if (r < m) {
+    const int64_t c = j * m + r;  // the counter of k_sketch's entry (r, j)
+    uint32_t ctr[4] = {(uint32_t)c, (uint32_t)(c >> 32), 0u, 0u};
+    philox4x32_10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u1 = ((double)((((uint64_t)ctr[0]) << 21) ^ (uint64_t)(ctr[1] >> 11)) + 1.0) * 0x1p-53;
+    const double u2 = ((double)((((uint64_t)ctr[2]) << 21) ^ (uint64_t)(ctr[3] >> 11)) + 0.5) * 0x1p-53;
+    g = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+  out[t] = g;
+}
+
 // partial Gram over a chunk of kGramChunk rows: scratch[chunk][a*k+b].  The chunk's rows of A and
 // B are staged in LDS first (unit-stride reads along each column), then each thread sums its
 // entries from LDS.
@@ -543,6 +566,15 @@ __global__ void k_min_reduce(const double* v, int64_t count, double* out) {
 hipError_t launch_sketch(uint64_t seed, int64_t m, int k, double* out, int64_t ld, hipStream_t st) {
   const int64_t cnt = m * k;
   hipLaunchKernelGGL(k_sketch, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, seed, m, k, out, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch_setup(uint64_t seed, int64_t m, int k, double* out, int64_t ld, int32_t* act, int32_t* nact,
+                               double* sig, int nsig, hipStream_t st) {
+  if (!out || !act || !nact || !sig || k < 1 || m < 1 || ld < m || nsig < k) return hipErrorInvalidValue;
+  const int64_t cnt = std::max<int64_t>(ld * k, nsig);
+  hipLaunchKernelGGL(k_sketch_setup, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, seed, m, k, out, ld, act,
+                     nact, sig, nsig);
   return hipGetLastError();
 }
 
