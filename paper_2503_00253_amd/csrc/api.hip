@@ -106,12 +106,14 @@ struct Nodes {
   double s[kMaxQ];
   double p[kMaxQ];
 };
+// Shifts past the Q N + extra systems, up to spad, are zero.
 __global__ void k_set_nodes(Nodes nd, int32_t Q, int64_t N, double* sigma, double* pw, int64_t extra,
-                            double extra_sigma) {
+                            double extra_sigma, int64_t spad) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t < (int64_t)Q * N) sigma[t] = nd.s[t / N];
   if (t < Q) pw[t] = nd.p[t];
   if (t < extra) sigma[(int64_t)Q * N + t] = extra_sigma;
+  if (t >= (int64_t)Q * N + extra && t < spad) sigma[t] = 0.0;
 }
 
 // The per-system counters of a solve start at zero: iterations, sweeps, final status; and the
@@ -1622,12 +1624,10 @@ int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_
   IE_TRY(check_nnz(prob, op, st));
   IE_TRY(stage_setup(pl, op, st));
   Sys& sy = pl.sy;
-  IE_HIP(launch_fill_f64(sy.b, 0.0, sy.ldm * sy.Spad, st));
-  IE_HIP(launch_obs_rhs(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, pl.in.Z, pl.in.n, N, pl.in.m, sy.b, sy.ldm,
-                        0, S, st));
-  IE_HIP(launch_fill_f64(sy.sigma, 0.0, sy.Spad, st));
-  hipLaunchKernelGGL(k_set_nodes, dim3(nb(std::max<int64_t>(S, kMaxQ))), dim3(256), 0, st, nd, Q, N, sy.sigma, sy.pw,
-                     (int64_t)0, 0.0);
+  IE_HIP(launch_obs_rhs_padded(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, pl.in.Z, pl.in.n, N, pl.in.m, sy.b,
+                               sy.ldm, S, sy.Spad, st));
+  hipLaunchKernelGGL(k_set_nodes, dim3(nb(std::max<int64_t>(sy.Spad, kMaxQ))), dim3(256), 0, st, nd, Q, N, sy.sigma,
+                     sy.pw, (int64_t)0, 0.0, sy.Spad);
   IE_HIP(hipGetLastError());
   IE_TRY(stage_precond(pl, op, st));
   IE_TRY(stage_solve(pl, op, st, fin, finalized));
@@ -1829,8 +1829,8 @@ int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const 
   fin.status = [&]() -> int { return finish_enqueue(pl, op, stats, 2 * pl.pr.k + N, st); };
   fin.output = [&]() -> int {
     Sys& sy = pl.sy;
-    IE_HIP(launch_quad_combine(sy.u, sy.ldm, pl.in.m, N, Q, sy.pw, pl.fn.ubar, sy.ldm, 0, st));
-    IE_HIP(launch_iota(pl.fn.act, pl.fn.nact, N, st));
+    IE_HIP(
+        launch_quad_combine(sy.u, sy.ldm, pl.in.m, N, Q, sy.pw, pl.fn.ubar, sy.ldm, 0, pl.fn.act, pl.fn.nact, st));
     IE_TRY(apply_state(pl, pl.fn.ubar, sy.ldm, pl.fn.act, pl.fn.nact, N, op.rows_per_wave, st));
     IE_HIP(launch_final_pert(pl.in.Z, (const double*)pl.bf.T, ld64(pl.in.n), pl.in.n, N,
                              std::sqrt((double)(N - 1)), Xa_pert, st));

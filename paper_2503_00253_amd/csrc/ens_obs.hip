@@ -115,6 +115,18 @@ __global__ void k_csc_sort(const int32_t* __restrict__ col_ptr, int64_t n, int32
   }
 }
 
+// dinv_r * sum_e w_e Z[idx_e, i]: observation r of member i
+__device__ inline double obs_rhs_entry(const int32_t* __restrict__ h_ptr, const int32_t* __restrict__ h_idx,
+                                       const double* __restrict__ h_w, const double* __restrict__ r_var,
+                                       const double* __restrict__ Z, int64_t n, int64_t r, int64_t i) {
+  double acc = 0.0;
+  for (int32_t e = h_ptr[r]; e < h_ptr[r + 1]; ++e) {
+    const int32_t j = h_idx[e];
+    if (j >= 0 && j < n) acc += h_w[e] * Z[j + i * n];  // invalid indices are flagged elsewhere
+  }
+  return acc / sqrt(r_var[r]);
+}
+
 // rhs[s * ld + r] = dinv_r * sum_e w_e Z[idx_e, i], i = (s - s0) % N
 __global__ void k_obs_rhs(const int32_t* __restrict__ h_ptr, const int32_t* __restrict__ h_idx,
                           const double* __restrict__ h_w, const double* __restrict__ r_var,
@@ -123,13 +135,19 @@ __global__ void k_obs_rhs(const int32_t* __restrict__ h_ptr, const int32_t* __re
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= m * cnt) return;
   const int64_t c = t / m, r = t % m;
-  const int64_t i = c % N;
-  double acc = 0.0;
-  for (int32_t e = h_ptr[r]; e < h_ptr[r + 1]; ++e) {
-    const int32_t j = h_idx[e];
-    if (j >= 0 && j < n) acc += h_w[e] * Z[j + i * n];  // invalid indices are flagged elsewhere
-  }
-  rhs[(s0 + c) * ld + r] = acc / sqrt(r_var[r]);
+  rhs[(s0 + c) * ld + r] = obs_rhs_entry(h_ptr, h_idx, h_w, r_var, Z, n, r, c % N);
+}
+
+// The same for systems 0 .. cnt-1 over the whole ld x spad block: zeros in the padding rows
+// (r >= m) and padding systems (s >= cnt).
+__global__ void k_obs_rhs_padded(const int32_t* __restrict__ h_ptr, const int32_t* __restrict__ h_idx,
+                                 const double* __restrict__ h_w, const double* __restrict__ r_var,
+                                 const double* __restrict__ Z, int64_t n, int64_t N, int64_t m,
+                                 double* __restrict__ rhs, int64_t ld, int64_t cnt, int64_t spad) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ld * spad) return;
+  const int64_t c = t / ld, r = t % ld;
+  rhs[t] = (c < cnt && r < m) ? obs_rhs_entry(h_ptr, h_idx, h_w, r_var, Z, n, r, c % N) : 0.0;
 }
 
 __global__ void k_innovation(const int32_t* __restrict__ h_ptr, const int32_t* __restrict__ h_idx,
@@ -280,6 +298,15 @@ hipError_t launch_csc_build(const int32_t* h_ptr, const int32_t* h_idx, const do
                      row_of, w_of, flags);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_csc_sort, dim3(blocks_for(n)), dim3(kBlock), 0, st, col_ptr, n, row_of, w_of, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_rhs_padded(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, const double* r_var,
+                                 const double* Z, int64_t n, int64_t N, int64_t m, double* rhs, int64_t ld,
+                                 int64_t cnt, int64_t spad, hipStream_t st) {
+  if (ld < m || spad < cnt || N < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_obs_rhs_padded, dim3(blocks_for(ld * spad)), dim3(kBlock), 0, st, h_ptr, h_idx, h_w, r_var, Z,
+                     n, N, m, rhs, ld, cnt, spad);
   return hipGetLastError();
 }
 

@@ -133,6 +133,11 @@ hipError_t launch_csc_build(const int32_t* h_ptr, const int32_t* h_idx, const do
 hipError_t launch_obs_rhs(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, const double* r_var,
                           const double* Z, int64_t n, int64_t N, int64_t m, double* rhs, int64_t ld, int64_t s0,
                           int64_t cnt, hipStream_t st);
+// The same for systems 0 .. cnt-1, writing the whole ld x spad block (zeros past m rows and past
+// cnt systems).
+hipError_t launch_obs_rhs_padded(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, const double* r_var,
+                                 const double* Z, int64_t n, int64_t N, int64_t m, double* rhs, int64_t ld,
+                                 int64_t cnt, int64_t spad, hipStream_t st);
 
 // innovation rhs: out[s * ld + r] = dinv[r] * (y[r] - sum_e h_w[e] mu[h_idx[e]])
 hipError_t launch_innovation(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, const double* r_var,
@@ -417,8 +422,9 @@ hipError_t launch_col_norms(const double* v, int64_t m, int64_t S, int64_t ld, d
 hipError_t launch_residual_status(const double* rn, const double* bn, double tol, double* relres, int32_t* done,
                                   int64_t S, int32_t* flags, hipStream_t st);
 // Quadrature combine: ubar[i * ldb + r] = sum_q p_q u[(s0 + q N + i) * ldu + r]
+// (with act and nact non-null it also lists the N combined columns: act = 0 .. N-1, *nact = N)
 hipError_t launch_quad_combine(const double* u, int64_t ldu, int64_t m, int64_t N, int32_t Q, const double* pw,
-                               double* ubar, int64_t ldb, int64_t s0, hipStream_t st);
+                               double* ubar, int64_t ldb, int64_t s0, int32_t* act, int32_t* nact, hipStream_t st);
 // Final state update: out[k + i*n] = scale * (Z[k + i*n] - T[i*ldt + k])  (column-major out)
 hipError_t launch_final_pert(const double* Z, const double* T, int64_t ldt, int64_t n, int64_t N, double scale,
                              double* out, hipStream_t st);

@@ -464,8 +464,11 @@ __global__ void k_residual_status(const double* rn, const double* bn, double tol
 }
 // ubar[i * ldb + r] = sum_q p_q u[(s0 + q N + i) * ldu + r]
 __global__ void k_quad_combine(const double* __restrict__ u, int64_t ldu, int64_t m, int64_t N, int32_t Q,
-                               const double* __restrict__ pw, double* __restrict__ ubar, int64_t ldb, int64_t s0) {
+                               const double* __restrict__ pw, double* __restrict__ ubar, int64_t ldb, int64_t s0,
+                               int32_t* __restrict__ act, int32_t* __restrict__ nact) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (act && t < N) act[t] = (int32_t)t;
+  if (act && t == 0) *nact = (int32_t)N;
   if (t >= m * N) return;
   const int64_t i = t / m, r = t % m;
   double acc = 0.0;
@@ -673,8 +676,10 @@ hipError_t launch_residual_status(const double* rn, const double* bn, double tol
   return hipGetLastError();
 }
 hipError_t launch_quad_combine(const double* u, int64_t ldu, int64_t m, int64_t N, int32_t Q, const double* pw,
-                               double* ubar, int64_t ldb, int64_t s0, hipStream_t st) {
-  hipLaunchKernelGGL(k_quad_combine, dim3(nb(m * N)), dim3(256), 0, st, u, ldu, m, N, Q, pw, ubar, ldb, s0);
+                               double* ubar, int64_t ldb, int64_t s0, int32_t* act, int32_t* nact, hipStream_t st) {
+  if ((act == nullptr) != (nact == nullptr) || m < 1 || N < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_quad_combine, dim3(nb(m * N)), dim3(256), 0, st, u, ldu, m, N, Q, pw, ubar, ldb, s0, act,
+                     nact);
   return hipGetLastError();
 }
 hipError_t launch_final_pert(const double* Z, const double* T, int64_t ldt, int64_t n, int64_t N, double scale,
