@@ -100,48 +100,6 @@ __global__ __launch_bounds__(256) void k_gram_partial(Strided A, Strided B, int6
   }
 }
 
-// The whole Gram matrix G = A^T B (row-major k x k) on one 256-thread workgroup when k <= K: each
-// thread accumulates the K x K products of its rows (tid + 256 i) in registers, the wavefronts
-// sum them by DPP and four partials per entry are added in order.  part holds 4 K^2 doubles of
-// LDS; G may be LDS or global memory and is complete when the call returns (a barrier ends it).
-template <int K>
-__device__ inline void gram_wg(Strided A, Strided B, int64_t m, int k, double* part, double* G) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double acc[K * K];
-#pragma unroll
-  for (int e = 0; e < K * K; ++e) acc[e] = 0.0;
-  for (int64_t r = tid; r < m; r += 256) {
-    double av[K], bv[K];
-#pragma unroll
-    for (int a = 0; a < K; ++a) {
-      av[a] = a < k ? A.ptr[r * A.rs + a * A.cs] : 0.0;
-      bv[a] = a < k ? B.ptr[r * B.rs + a * B.cs] : 0.0;
-    }
-#pragma unroll
-    for (int a = 0; a < K; ++a)
-#pragma unroll
-      for (int b = 0; b < K; ++b) acc[a * K + b] += av[a] * bv[b];
-  }
-#pragma unroll
-  for (int e = 0; e < K * K; ++e) {
-    const double x = wave_sum_dpp(acc[e]);
-    if (lane == 63) part[wave * K * K + e] = x;
-  }
-  __syncthreads();
-  for (int e = tid; e < k * k; e += 256) {
-    const int i = (e / k) * K + e % k;
-    G[e] = ((part[i] + part[K * K + i]) + part[2 * K * K + i]) + part[3 * K * K + i];
-  }
-  __syncthreads();
-}
-
-// One launch instead of partials + reduction for the small bases of the setup.
-template <int K>
-__global__ __launch_bounds__(256) void k_gram_small(Strided A, Strided B, int64_t m, int k, double* __restrict__ G) {
-  __shared__ double part[4 * K * K];
-  gram_wg<K>(A, B, m, k, part, G);
-}
-
 __global__ void k_gram_reduce(const double* __restrict__ scratch, int nchunks, int k, double* __restrict__ G) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= k * k) return;
@@ -360,6 +318,57 @@ __global__ void k_lmp_finish(const double* evals, const double* evec, int k, int
   }
 }
 
+// G = X^T Y (row-major k x k, k = k1 + k2 <= 16) over m rows on a 256-thread workgroup by FP64
+// MFMA, where X = [A1 A2] and Y = [B1 B2] are the column blocks of k1 and k2 columns: each
+// wavefront takes blocks of 4 rows (wave w: rows 4 w, 4 w + 16, ...) into one
+// v_mfma_f64_16x16x4f64 each (lane l brings column l % 16 of row 4 b + l / 16 of X and of Y: the
+// A operand (row l % 16, k l / 16) is X^T, the B operand (k l / 16, col l % 16) is Y), U blocks'
+// loads in flight before their products; then the four wavefront tiles are added in order.
+// part: 4 x 256 doubles of LDS; G complete on return.
+typedef double small_d4 __attribute__((ext_vector_type(4)));
+__device__ inline void gram_mfma2(Strided A1, Strided A2, Strided B1, Strided B2, int64_t m, int k1, int k2,
+                                  double* part, double* G) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = lane & 15, kk = lane >> 4;
+  const int k = k1 + k2;
+  const bool first = c < k1;
+  const Strided A = first ? A1 : A2, B = first ? B1 : B2;
+  const int cc = first ? c : c - k1;
+  small_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  constexpr int U = 16;
+  for (int64_t r0 = 4 * wave; r0 < m; r0 += 16 * U) {
+    double a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + 16 * u + kk;
+      const bool ok = c < k && r < m;
+      a[u] = ok ? A.ptr[r * A.rs + cc * A.cs] : 0.0;
+      b[u] = ok ? B.ptr[r * B.rs + cc * B.cs] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+  }
+  // D register v: (row 4 v + lane / 16, col lane % 16)
+#pragma unroll
+  for (int v = 0; v < 4; ++v) part[wave * 256 + (4 * v + kk) * 16 + c] = acc[v];
+  __syncthreads();
+  for (int e = tid; e < k * k; e += 256) {
+    const int i = (e / k) * 16 + e % k;
+    G[e] = ((part[i] + part[256 + i]) + part[512 + i]) + part[768 + i];
+  }
+  __syncthreads();
+}
+
+__device__ inline void gram_mfma(Strided A, Strided B, int64_t m, int k, double* part, double* G) {
+  gram_mfma2(A, A, B, B, m, k, 0, part, G);
+}
+
+// The whole Gram matrix in one launch for k <= 16 (instead of partials + reduction).
+__global__ __launch_bounds__(256) void k_gram_small(Strided A, Strided B, int64_t m, int k, double* __restrict__ G) {
+  __shared__ double part[4 * 256];
+  gram_mfma(A, B, m, k, part, G);
+}
+
 // ----------------------------------------------------------- small bases on one workgroup
 // With at most 8 sketch columns (p + oversample) the setup's small dense steps run as two
 // launches: Cholesky-QR twice of Y = S Omega, then the Rayleigh quotient T = Qb^T (S Qb), its
@@ -405,15 +414,16 @@ __device__ inline bool chol_upper_serial(const double* G, int k, double* R) {
 
 // Q = orth(Y) by Cholesky-QR twice: G = X^T X, X <- X R^{-1} (each row q solves q R = x by
 // forward substitution), first with X = Y, then with X = Q.  Y and Q column-major, leading
-// dimension ld.  Every thread works on the same rows (tid + 256 i) in every pass.
+// dimension ld.  A thread writes and later reads the same rows (tid + 256 i); the Gram passes
+// read every row, after the barrier that ends the previous pass.
 template <int K>
 __global__ __launch_bounds__(256) void k_cholqr2_small(const double* __restrict__ Y, int64_t m, int k, int64_t ld,
                                                        double* __restrict__ Q, int32_t* flags) {
-  __shared__ double part[4 * K * K];
+  __shared__ double part[4 * 256];
   __shared__ double G[K * K], R[K * K];
   for (int pass = 0; pass < 2; ++pass) {
     const double* X = pass == 0 ? Y : Q;
-    gram_wg<K>(Strided{X, 1, ld}, Strided{X, 1, ld}, m, k, part, G);
+    gram_mfma(Strided{X, 1, ld}, Strided{X, 1, ld}, m, k, part, G);
     if (threadIdx.x == 0 && !chol_upper_serial<K>(G, k, R)) atomicOr(flags, kFlagNumeric);
     __syncthreads();
     for (int64_t r = threadIdx.x; r < m; r += 256) {
@@ -468,11 +478,11 @@ __global__ __launch_bounds__(256) void k_ritz_small(const double* __restrict__ Q
                                                     float* __restrict__ Phi32, float* __restrict__ SPhi32,
                                                     double* __restrict__ G) {
   static_assert(K * K <= 64 && PB <= K, "one matrix entry a lane");
-  __shared__ double part[4 * K * K];
-  __shared__ double T[K * K], V[K * K], ev[K], sel[K * PB];
+  __shared__ double part[4 * 256];
+  __shared__ double T[K * K], V[K * K], ev[K], sel[K * PB], W[4 * PB * PB];
   __shared__ int order[K];
   const int tid = threadIdx.x;
-  gram_wg<K>(Strided{Qb, 1, ld}, Strided{SQ, 1, ld}, m, k, part, T);
+  gram_mfma(Strided{Qb, 1, ld}, Strided{SQ, 1, ld}, m, k, part, T);
   if (tid < 64) {
     const int i = tid / K, j = tid % K;
     const bool in = tid < K * K && i < k && j < k;
@@ -541,11 +551,17 @@ __global__ __launch_bounds__(256) void k_ritz_small(const double* __restrict__ Q
       }
     }
   }
-  // the Gram blocks read back the rows this thread wrote
+  __syncthreads();  // every row of Phi and S Phi is written
+  // the Gram of [Phi S Phi] (2p x 2p) in one pass; its blocks Phi^T Phi, Phi^T S Phi and
+  // (S Phi)^T S Phi go to G
   const Strided Ph{Phi, 1, ld}, SPh{SPhi, 1, ld};
-  gram_wg<PB>(Ph, Ph, m, p, part, G);
-  gram_wg<PB>(Ph, SPh, m, p, part, G + p * p);
-  gram_wg<PB>(SPh, SPh, m, p, part, G + 2 * p * p);
+  gram_mfma2(Ph, SPh, Ph, SPh, m, p, p, part, W);
+  const int p2 = 2 * p;
+  for (int e = tid; e < 3 * p * p; e += 256) {
+    const int blk = e / (p * p), a = (e % (p * p)) / p, b = e % p;
+    const int row = blk == 2 ? p + a : a, col = blk == 0 ? b : p + b;
+    G[e] = W[row * p2 + col];
+  }
 }
 
 __global__ void k_min_reduce(const double* v, int64_t count, double* out) {
@@ -582,9 +598,8 @@ int gram_chunks(int64_t m) { return (int)((m + kGramChunk - 1) / kGramChunk); }
 
 hipError_t launch_gram(Strided A, Strided B, int64_t m, int k, double* G, double* scratch, hipStream_t st) {
   if (k < 1 || k > kMaxSketch || m < 1) return hipErrorInvalidValue;
-  if (k <= 8 && m <= 8192) {
-    if (k <= 4) hipLaunchKernelGGL(k_gram_small<4>, dim3(1), dim3(256), 0, st, A, B, m, k, G);
-    else hipLaunchKernelGGL(k_gram_small<8>, dim3(1), dim3(256), 0, st, A, B, m, k, G);
+  if (k <= 16 && m <= 8192) {
+    hipLaunchKernelGGL(k_gram_small, dim3(1), dim3(256), 0, st, A, B, m, k, G);
     return hipGetLastError();
   }
   const int nchunks = gram_chunks(m);
