@@ -464,7 +464,7 @@ hipError_t launch_lmp_finish(const double* evals, const double* evec, int k, int
 hipError_t launch_min_reduce(const double* v, int64_t count, double* out, hipStream_t st);
 // The setup's small dense steps for k <= 8 sketch columns and m <= 8192 rows in two launches:
 // Q = orth(Y) by Cholesky-QR twice, then theta, Phi, S Phi (FP64 and FP32, rounded) and the
-// three Gram blocks from Qb and S Qb (all column-major with leading dimension ld).
+// three Gram blocks from Qb and S Qb (all column-major with leading dimension ld <= 2^26).
 bool small_basis_fits(int k, int p, int64_t m);
 hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, double* Q, int32_t* flags,
                                 hipStream_t st);

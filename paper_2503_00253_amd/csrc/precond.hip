@@ -318,55 +318,69 @@ __global__ void k_lmp_finish(const double* evals, const double* evec, int k, int
   }
 }
 
-// G = X^T Y (row-major k x k, k = k1 + k2 <= 16) over m rows on a 256-thread workgroup by FP64
+// G = X^T Y (row-major k x k, k = k1 + k2 <= 16) over m rows on an NT-thread workgroup by FP64
 // MFMA, where X = [A1 A2] and Y = [B1 B2] are the column blocks of k1 and k2 columns: each
-// wavefront takes blocks of 4 rows (wave w: rows 4 w, 4 w + 16, ...) into one
+// wavefront takes blocks of 4 rows (wave w of NW: rows 4 w, 4 w + 4 NW, ...) into one
 // v_mfma_f64_16x16x4f64 each (lane l brings column l % 16 of row 4 b + l / 16 of X and of Y: the
 // A operand (row l % 16, k l / 16) is X^T, the B operand (k l / 16, col l % 16) is Y), U blocks'
-// loads in flight before their products; then the four wavefront tiles are added in order.
-// part: 4 x 256 doubles of LDS; G complete on return.
+// loads in flight before their products; then the NW wavefront tiles are added in order.
+// part: NW x 256 doubles of LDS; G complete on return.
 typedef double small_d4 __attribute__((ext_vector_type(4)));
+template <int NT>
 __device__ inline void gram_mfma2(Strided A1, Strided A2, Strided B1, Strided B2, int64_t m, int k1, int k2,
                                   double* part, double* G) {
+  constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int c = lane & 15, kk = lane >> 4;
   const int k = k1 + k2;
   const bool first = c < k1;
   const Strided A = first ? A1 : A2, B = first ? B1 : B2;
   const int cc = first ? c : c - k1;
-  small_d4 acc = {0.0, 0.0, 0.0, 0.0};
-  constexpr int U = 16;
-  for (int64_t r0 = 4 * wave; r0 < m; r0 += 16 * U) {
+  // this lane's column of X and of Y (rows at stride rs; m, rs and the column offsets fit 32 bits)
+  const double* ac = A.ptr + (c < k ? cc * A.cs : 0);
+  const double* bc = B.ptr + (c < k ? cc * B.cs : 0);
+  const int ars = (int)A.rs, brs = (int)B.rs, mm = (int)m;
+  // four independent accumulation chains, added at the end
+  small_d4 acc[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) acc[h] = small_d4{0.0, 0.0, 0.0, 0.0};
+  constexpr int U = NT >= 1024 ? 8 : 16;  // within 128 registers on 1024 threads
+  for (int r0 = 4 * wave + kk; r0 - kk < mm; r0 += 4 * NW * U) {
     double a[U], b[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t r = r0 + 16 * u + kk;
-      const bool ok = c < k && r < m;
-      a[u] = ok ? A.ptr[r * A.rs + cc * A.cs] : 0.0;
-      b[u] = ok ? B.ptr[r * B.rs + cc * B.cs] : 0.0;
+      const int r = r0 + 4 * NW * u;
+      const bool ok = c < k && r < mm;
+      a[u] = ok ? ac[r * ars] : 0.0;
+      b[u] = ok ? bc[r * brs] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+    for (int u = 0; u < U; ++u) acc[u % 4] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc[u % 4], 0, 0, 0);
   }
   // D register v: (row 4 v + lane / 16, col lane % 16)
 #pragma unroll
-  for (int v = 0; v < 4; ++v) part[wave * 256 + (4 * v + kk) * 16 + c] = acc[v];
+  for (int v = 0; v < 4; ++v)
+    part[wave * 256 + (4 * v + kk) * 16 + c] = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
   __syncthreads();
-  for (int e = tid; e < k * k; e += 256) {
+  for (int e = tid; e < k * k; e += NT) {
     const int i = (e / k) * 16 + e % k;
-    G[e] = ((part[i] + part[256 + i]) + part[512 + i]) + part[768 + i];
+    double t = part[i];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) t += part[w * 256 + i];
+    G[e] = t;
   }
   __syncthreads();
 }
 
+template <int NT>
 __device__ inline void gram_mfma(Strided A, Strided B, int64_t m, int k, double* part, double* G) {
-  gram_mfma2(A, A, B, B, m, k, 0, part, G);
+  gram_mfma2<NT>(A, A, B, B, m, k, 0, part, G);
 }
 
 // The whole Gram matrix in one launch for k <= 16 (instead of partials + reduction).
 __global__ __launch_bounds__(256) void k_gram_small(Strided A, Strided B, int64_t m, int k, double* __restrict__ G) {
   __shared__ double part[4 * 256];
-  gram_mfma(A, B, m, k, part, G);
+  gram_mfma<256>(A, B, m, k, part, G);
 }
 
 // ----------------------------------------------------------- small bases on one workgroup
@@ -412,24 +426,68 @@ __device__ inline bool chol_upper_serial(const double* G, int k, double* R) {
   return ok;
 }
 
+// Columns [0, k) of the column-major m-row matrices A and B (leading dimension ld; B may be
+// null) into dA and dB, column-major with leading dimension m: 16 loads of each in flight per
+// thread ahead of their stores.
+template <int NT>
+__device__ inline void stage_cols(const double* __restrict__ A, const double* __restrict__ B, int64_t ld, int64_t m,
+                                  int k, double* dA, double* dB) {
+  constexpr int U = 16;
+  const int mm = (int)m, l = (int)ld;
+  for (int c = 0; c < k; ++c) {
+    const double* a = A + c * l;
+    const double* b = B ? B + c * l : nullptr;
+    for (int r0 = threadIdx.x; r0 < mm; r0 += NT * U) {
+      double va[U], vb[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = r0 + NT * u;
+        va[u] = r < mm ? a[r] : 0.0;
+        vb[u] = (b && r < mm) ? b[r] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = r0 + NT * u;
+        if (r < mm) {
+          dA[c * mm + r] = va[u];
+          if (b) dB[c * mm + r] = vb[u];
+        }
+      }
+    }
+  }
+}
+
 // Q = orth(Y) by Cholesky-QR twice: G = X^T X, X <- X R^{-1} (each row q solves q R = x by
 // forward substitution), first with X = Y, then with X = Q.  Y and Q column-major, leading
-// dimension ld.  A thread writes and later reads the same rows (tid + 256 i); the Gram passes
-// read every row, after the barrier that ends the previous pass.
+// dimension ld.  With stage set the working copy lives in dynamic LDS (m x k, leading
+// dimension m): one read of Y and one write of Q; otherwise Q itself is the working copy (a
+// thread writes and later reads the same rows, tid + 1024 i; the Gram passes read every row after
+// the barrier that ends the previous pass).
+constexpr int kSmallNT = 1024;
+
 template <int K>
-__global__ __launch_bounds__(256) void k_cholqr2_small(const double* __restrict__ Y, int64_t m, int k, int64_t ld,
-                                                       double* __restrict__ Q, int32_t* flags) {
-  __shared__ double part[4 * 256];
+__global__ __launch_bounds__(kSmallNT) void k_cholqr2_small(const double* __restrict__ Y, int64_t m, int k, int64_t ld,
+                                                       double* __restrict__ Q, int32_t* flags, int stage) {
+  extern __shared__ __attribute__((aligned(16))) double xs[];
+  __shared__ double part[kSmallNT / 64 * 256];
   __shared__ double G[K * K], R[K * K];
+  double* X = stage ? xs : Q;
+  const int64_t lx = stage ? m : ld;
+  if (stage) {
+    stage_cols<kSmallNT>(Y, nullptr, ld, m, k, xs, nullptr);
+    __syncthreads();
+  }
   for (int pass = 0; pass < 2; ++pass) {
-    const double* X = pass == 0 ? Y : Q;
-    gram_mfma(Strided{X, 1, ld}, Strided{X, 1, ld}, m, k, part, G);
+    const double* src = (pass == 0 && !stage) ? Y : X;
+    const int64_t ls = (pass == 0 && !stage) ? ld : lx;
+    gram_mfma<kSmallNT>(Strided{src, 1, ls}, Strided{src, 1, ls}, m, k, part, G);
     if (threadIdx.x == 0 && !chol_upper_serial<K>(G, k, R)) atomicOr(flags, kFlagNumeric);
     __syncthreads();
-    for (int64_t r = threadIdx.x; r < m; r += 256) {
+    const int ils = (int)ls, ilx = (int)lx;
+    for (int r = threadIdx.x; r < (int)m; r += kSmallNT) {
       double x[K], q[K];
 #pragma unroll
-      for (int a = 0; a < K; ++a) x[a] = a < k ? X[a * ld + r] : 0.0;
+      for (int a = 0; a < K; ++a) x[a] = a < k ? src[a * ils + r] : 0.0;
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         q[j] = 0.0;
@@ -442,9 +500,13 @@ __global__ __launch_bounds__(256) void k_cholqr2_small(const double* __restrict_
       }
 #pragma unroll
       for (int j = 0; j < K; ++j)
-        if (j < k) Q[j * ld + r] = q[j];
+        if (j < k) X[j * ilx + r] = q[j];
     }
     __syncthreads();  // R is rewritten by the next pass
+  }
+  if (stage) {
+    for (int c = 0; c < k; ++c)
+      for (int r = threadIdx.x; r < (int)m; r += kSmallNT) Q[c * (int)ld + r] = xs[c * (int)m + r];
   }
 }
 
@@ -467,48 +529,71 @@ __device__ inline int jacobi_partner(int i, int step, int ke) {
 }
 
 // T = Qb^T (S Qb), its Jacobi eigendecomposition on the first wavefront (lane i K + j holds A_ij
-// and V_ij; each step rotates the k/2 pairs of the round-robin ordering at once, exchanging
-// entries between lanes), the p largest eigenpairs (ties by index), Phi = Qb V_p and
+// and V_ij; each step rotates the k/2 pairs of the round-robin ordering at once, in one exchange
+// of entries between lanes: each lane forms the rotations of its row's and its column's pair),
+// the p largest eigenpairs (ties by index), Phi = Qb V_p and
 // S Phi = (S Qb) V_p rounded to FP32 (kept in FP32 and as the rounded FP64 values), theta, and
 // the Gram blocks Phi^T Phi, Phi^T S Phi, (S Phi)^T S Phi of the rounded vectors into G.
 template <int K, int PB>
-__global__ __launch_bounds__(256) void k_ritz_small(const double* __restrict__ Qb, const double* __restrict__ SQ,
+__global__ __launch_bounds__(kSmallNT) void k_ritz_small(const double* __restrict__ Qb, const double* __restrict__ SQ,
                                                     int64_t m, int k, int p, int64_t ld, double* __restrict__ theta,
                                                     double* __restrict__ Phi, double* __restrict__ SPhi,
                                                     float* __restrict__ Phi32, float* __restrict__ SPhi32,
-                                                    double* __restrict__ G) {
+                                                    double* __restrict__ G, int stage) {
   static_assert(K * K <= 64 && PB <= K, "one matrix entry a lane");
-  __shared__ double part[4 * 256];
+  // with stage set, Qb and S Qb are read once into dynamic LDS (m x k each, leading dimension m)
+  extern __shared__ __attribute__((aligned(16))) double xs[];
+  __shared__ double part[kSmallNT / 64 * 256];
   __shared__ double T[K * K], V[K * K], ev[K], sel[K * PB], W[4 * PB * PB];
   __shared__ int order[K];
   const int tid = threadIdx.x;
-  gram_mfma(Strided{Qb, 1, ld}, Strided{SQ, 1, ld}, m, k, part, T);
+  const double* Qs = stage ? xs : Qb;
+  const double* SQs = stage ? xs + m * k : SQ;
+  const int64_t lq = stage ? m : ld;
+  if (stage) {
+    stage_cols<kSmallNT>(Qb, SQ, ld, m, k, xs, xs + m * k);
+    __syncthreads();
+  }
+  gram_mfma<kSmallNT>(Strided{Qs, 1, lq}, Strided{SQs, 1, lq}, m, k, part, T);
   if (tid < 64) {
     const int i = tid / K, j = tid % K;
     const bool in = tid < K * K && i < k && j < k;
     double a = in ? 0.5 * (T[i * k + j] + T[j * k + i]) : 0.0;
     double v = (in && i == j) ? 1.0 : 0.0;
     const int ke = k + (k & 1);
+    // this lane's row and column partners at every step of a sweep (ke - 1 <= K - 1 steps)
+    int prow[K], pcol[K];
+#pragma unroll
+    for (int st = 0; st < K; ++st) {
+      prow[st] = st < ke - 1 ? jacobi_partner(i, st, ke) : i;
+      pcol[st] = st < ke - 1 ? jacobi_partner(j, st, ke) : j;
+    }
     for (int sweep = 0; sweep < 40; ++sweep) {
       const double off = wave_sum_dpp(in && i != j ? a * a : 0.0);
       const double dia = wave_sum_dpp(in && i == j ? a * a : 0.0);
       // relative off-diagonal norm 1e-10: the Ritz vectors are rounded to FP32 afterwards
       if (lane_shfl(off, 63) <= 1e-20 * lane_shfl(dia, 63)) break;
-      for (int step = 0; step < ke - 1; ++step) {
-        const int pi = jacobi_partner(i, step, ke), pj = jacobi_partner(j, step, ke);
-        const int p1 = min(i, pi), q1 = max(i, pi);
-        const double app = lane_shfl(a, p1 * K + p1), aqq = lane_shfl(a, q1 * K + q1);
-        const double apq = lane_shfl(a, p1 * K + q1);
-        double c1 = 1.0, s1 = 0.0;
-        if (q1 < k && q1 != p1 && apq != 0.0) jacobi_cs(app, aqq, apq, &c1, &s1);
-        // the column pair's rotation is the one row j's lanes found
-        const double c2 = lane_shfl(c1, j * K), s2 = lane_shfl(s1, j * K);
-        // rows [p; q] <- [c -s; s c] [p; q], then columns likewise; V <- V J
-        const double ar = lane_shfl(a, pi * K + j);
-        const double b = i <= pi ? c1 * a - s1 * ar : s1 * ar + c1 * a;
-        const double bc = lane_shfl(b, i * K + pj);
+#pragma unroll
+      for (int step = 0; step < K - 1; ++step) {
+        if (step >= ke - 1) break;
+        const int pi = prow[step], pj = pcol[step];
+        const int p1 = min(i, pi), q1 = max(i, pi), p2 = min(j, pj), q2 = max(j, pj);
+        // one exchange: the pivots of the row pair and of the column pair, the 2 x 2 block of A at
+        // rows {i, pi} and columns {j, pj}, and V's column partner
+        const double rpp = lane_shfl(a, p1 * K + p1), rqq = lane_shfl(a, q1 * K + q1);
+        const double rpq = lane_shfl(a, p1 * K + q1);
+        const double cpp = lane_shfl(a, p2 * K + p2), cqq = lane_shfl(a, q2 * K + q2);
+        const double cpq = lane_shfl(a, p2 * K + q2);
+        const double arj = lane_shfl(a, pi * K + j), aic = lane_shfl(a, i * K + pj);
+        const double arc = lane_shfl(a, pi * K + pj), vc = lane_shfl(v, i * K + pj);
+        double c1 = 1.0, s1 = 0.0, c2 = 1.0, s2 = 0.0;
+        if (q1 < k && q1 != p1 && rpq != 0.0) jacobi_cs(rpp, rqq, rpq, &c1, &s1);
+        if (q2 < k && q2 != p2 && cpq != 0.0) jacobi_cs(cpp, cqq, cpq, &c2, &s2);
+        // rows [p; q] <- [c -s; s c] [p; q] (entries j and pj of row i), then columns likewise;
+        // V <- V J
+        const double b = i <= pi ? c1 * a - s1 * arj : s1 * arj + c1 * a;
+        const double bc = i <= pi ? c1 * aic - s1 * arc : s1 * arc + c1 * aic;
         a = j <= pj ? c2 * b - s2 * bc : s2 * bc + c2 * b;
-        const double vc = lane_shfl(v, i * K + pj);
         v = j <= pj ? c2 * v - s2 * vc : s2 * vc + c2 * v;
       }
     }
@@ -523,14 +608,15 @@ __global__ __launch_bounds__(256) void k_ritz_small(const double* __restrict__ Q
   }
   __syncthreads();
   if (tid < p) theta[tid] = ev[order[tid]];
-  for (int e = tid; e < k * p; e += 256) sel[(e / p) * PB + e % p] = V[(e / p) * K + order[e % p]];
+  for (int e = tid; e < k * p; e += kSmallNT) sel[(e / p) * PB + e % p] = V[(e / p) * K + order[e % p]];
   __syncthreads();
-  for (int64_t r = tid; r < m; r += 256) {
+  const int ilq = (int)lq, ild = (int)ld;
+  for (int r = tid; r < (int)m; r += kSmallNT) {
     double q[K], sq[K];
 #pragma unroll
     for (int a = 0; a < K; ++a) {
-      q[a] = a < k ? Qb[a * ld + r] : 0.0;
-      sq[a] = a < k ? SQ[a * ld + r] : 0.0;
+      q[a] = a < k ? Qs[a * ilq + r] : 0.0;
+      sq[a] = a < k ? SQs[a * ilq + r] : 0.0;
     }
 #pragma unroll
     for (int jj = 0; jj < PB; ++jj) {
@@ -544,10 +630,10 @@ __global__ __launch_bounds__(256) void k_ritz_small(const double* __restrict__ Q
           }
         }
         const float f32 = (float)f, g32 = (float)g;
-        Phi32[jj * ld + r] = f32;
-        SPhi32[jj * ld + r] = g32;
-        Phi[jj * ld + r] = (double)f32;
-        SPhi[jj * ld + r] = (double)g32;
+        Phi32[jj * ild + r] = f32;
+        SPhi32[jj * ild + r] = g32;
+        Phi[jj * ild + r] = (double)f32;
+        SPhi[jj * ild + r] = (double)g32;
       }
     }
   }
@@ -555,9 +641,9 @@ __global__ __launch_bounds__(256) void k_ritz_small(const double* __restrict__ Q
   // the Gram of [Phi S Phi] (2p x 2p) in one pass; its blocks Phi^T Phi, Phi^T S Phi and
   // (S Phi)^T S Phi go to G
   const Strided Ph{Phi, 1, ld}, SPh{SPhi, 1, ld};
-  gram_mfma2(Ph, SPh, Ph, SPh, m, p, p, part, W);
+  gram_mfma2<kSmallNT>(Ph, SPh, Ph, SPh, m, p, p, part, W);
   const int p2 = 2 * p;
-  for (int e = tid; e < 3 * p * p; e += 256) {
+  for (int e = tid; e < 3 * p * p; e += kSmallNT) {
     const int blk = e / (p * p), a = (e % (p * p)) / p, b = e % p;
     const int row = blk == 2 ? p + a : a, col = blk == 0 ? b : p + b;
     G[e] = W[row * p2 + col];
@@ -638,28 +724,59 @@ hipError_t launch_lmp_finish(const double* evals, const double* evec, int k, int
 }
 
 bool small_basis_fits(int k, int p, int64_t m) { return k >= 1 && k <= 8 && p >= 1 && p <= k && m >= 1 && m <= 8192; }
+// the kernels index columns with 32-bit offsets
+constexpr int64_t kSmallMaxLd = int64_t(1) << 26;
+
+// dynamic LDS the small-basis kernels may take for a staged copy
+constexpr size_t kSmallStage = 96 * 1024;
+constexpr size_t kSmallStageRitz = 96 * 1024;
 
 hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, double* Q, int32_t* flags,
                                 hipStream_t st) {
-  if (!Y || !Q || !flags || ld < m || !small_basis_fits(k, 1, m)) return hipErrorInvalidValue;
-  if (k <= 4) hipLaunchKernelGGL(k_cholqr2_small<4>, dim3(1), dim3(256), 0, st, Y, m, k, ld, Q, flags);
-  else hipLaunchKernelGGL(k_cholqr2_small<8>, dim3(1), dim3(256), 0, st, Y, m, k, ld, Q, flags);
+  if (!Y || !Q || !flags || ld < m || ld > kSmallMaxLd || !small_basis_fits(k, 1, m)) return hipErrorInvalidValue;
+  const size_t bytes = (size_t)m * k * sizeof(double);
+  const int stage = bytes <= kSmallStage ? 1 : 0;
+  const size_t dyn = stage ? bytes : 0;
+  const void* fn = k <= 4 ? (const void*)k_cholqr2_small<4> : (const void*)k_cholqr2_small<8>;
+  static bool raised[2] = {false, false};
+  if (dyn > 64 * 1024 && !raised[k <= 4 ? 0 : 1]) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallStage);
+    if (e != hipSuccess) return e;
+    raised[k <= 4 ? 0 : 1] = true;
+  }
+  if (k <= 4)
+    hipLaunchKernelGGL(k_cholqr2_small<4>, dim3(1), dim3(kSmallNT), dyn, st, Y, m, k, ld, Q, flags, stage);
+  else
+    hipLaunchKernelGGL(k_cholqr2_small<8>, dim3(1), dim3(kSmallNT), dyn, st, Y, m, k, ld, Q, flags, stage);
   return hipGetLastError();
 }
 
 hipError_t launch_ritz_small(const double* Qb, const double* SQ, int64_t m, int k, int p, int64_t ld, double* theta,
                              double* Phi, double* SPhi, float* Phi32, float* SPhi32, double* G, hipStream_t st) {
-  if (!Qb || !SQ || !theta || !Phi || !SPhi || !Phi32 || !SPhi32 || !G || ld < m || !small_basis_fits(k, p, m))
+  if (!Qb || !SQ || !theta || !Phi || !SPhi || !Phi32 || !SPhi32 || !G || ld < m || ld > kSmallMaxLd ||
+      !small_basis_fits(k, p, m))
     return hipErrorInvalidValue;
-  if (k <= 4)
-    hipLaunchKernelGGL((k_ritz_small<4, 4>), dim3(1), dim3(256), 0, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi, Phi32,
-                       SPhi32, G);
-  else if (p <= 4)
-    hipLaunchKernelGGL((k_ritz_small<8, 4>), dim3(1), dim3(256), 0, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi, Phi32,
-                       SPhi32, G);
+  const size_t bytes = 2 * (size_t)m * k * sizeof(double);
+  const int stage = bytes <= kSmallStageRitz ? 1 : 0;
+  const size_t dyn = stage ? bytes : 0;
+  const int which = k <= 4 ? 0 : (p <= 4 ? 1 : 2);
+  const void* fn = which == 0 ? (const void*)k_ritz_small<4, 4>
+                              : (which == 1 ? (const void*)k_ritz_small<8, 4> : (const void*)k_ritz_small<8, 8>);
+  static bool raised[3] = {false, false, false};
+  if (dyn > 64 * 1024 && !raised[which]) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallStageRitz);
+    if (e != hipSuccess) return e;
+    raised[which] = true;
+  }
+  if (which == 0)
+    hipLaunchKernelGGL((k_ritz_small<4, 4>), dim3(1), dim3(kSmallNT), dyn, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi,
+                       Phi32, SPhi32, G, stage);
+  else if (which == 1)
+    hipLaunchKernelGGL((k_ritz_small<8, 4>), dim3(1), dim3(kSmallNT), dyn, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi,
+                       Phi32, SPhi32, G, stage);
   else
-    hipLaunchKernelGGL((k_ritz_small<8, 8>), dim3(1), dim3(256), 0, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi, Phi32,
-                       SPhi32, G);
+    hipLaunchKernelGGL((k_ritz_small<8, 8>), dim3(1), dim3(kSmallNT), dyn, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi,
+                       Phi32, SPhi32, G, stage);
   return hipGetLastError();
 }
 
