@@ -864,7 +864,9 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
     int32_t f = 0;
     IE_TRY(read_flags(pl, st, &f));
     if (f & kFlagBadInput) {
-      set_error("invalid observation operator (CSR out of range, unsorted, or not the stated lattice) or r_var <= 0");
+      set_error(
+          "invalid observation operator (CSR out of range, unsorted, more than max(64 m, 16 n) entries, or not the "
+          "stated lattice) or r_var <= 0");
       return INFOESRF_ERR_INVALID_ARG;
     }
     if (f & kFlagNumeric) {
@@ -1487,16 +1489,6 @@ int plan_for(Plan& pl, const infoesrf_problem* P, const Options& op, int64_t S, 
   return 0;
 }
 
-int check_nnz(const infoesrf_problem* P, const Options& op, hipStream_t st) {
-  if (!op.host_sync) return 0;
-  int32_t nnz = 0;
-  IE_HIP(hipMemcpyAsync(&nnz, P->h_ptr + P->m, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  IE_HIP(hipStreamSynchronize(st));
-  IE_CHECK(nnz >= 0 && nnz <= nnz_bound(P), INFOESRF_ERR_INVALID_ARG,
-           "H has more than max(64 m, 16 n) entries (h_ptr[m] too large)");
-  return 0;
-}
-
 // ------------------------------------------------------------------ batched instances
 // Sum of per-call counter blocks (k blocks of INFOESRF_NUM_COUNTERS); the status is the most
 // severe one: any error (the most negative), else the largest warning.
@@ -1621,7 +1613,6 @@ int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_
   }
   if (op.solver == INFOESRF_SOLVER_BLOCK) op.bcg_Q = Q;
   IE_TRY(plan_for(pl, prob, op, S, N, ws, ws_bytes));
-  IE_TRY(check_nnz(prob, op, st));
   IE_TRY(stage_setup(pl, op, st));
   Sys& sy = pl.sy;
   IE_HIP(launch_obs_rhs_padded(prob->h_ptr, prob->h_idx, prob->h_w, prob->r_var, pl.in.Z, pl.in.n, N, pl.in.m, sy.b,
@@ -1797,7 +1788,6 @@ int infoesrf_mean_update(const infoesrf_problem* prob, const double* y, double* 
   hipStream_t st = static_cast<hipStream_t>(stream);
   Plan pl;
   IE_TRY(plan_for(pl, prob, op, 1, 1, ws, ws_bytes));
-  IE_TRY(check_nnz(prob, op, st));
   IE_TRY(stage_setup(pl, op, st));
   Sys& sy = pl.sy;
   IE_HIP(launch_fill_f64(sy.b, 0.0, sy.ldm * sy.Spad, st));
@@ -1857,7 +1847,6 @@ int infoesrf_autotune(const infoesrf_problem* prob, int32_t Q, const infoesrf_op
   Plan pl;
   IE_TRY(plan_for(pl, prob, op, S, Q > 0 ? prob->N : 1, ws, ws_bytes));
   op.host_sync = 1;  // the tuner reads timings on the host
-  IE_TRY(check_nnz(prob, op, st));
   IE_TRY(stage_setup(pl, op, st));
   Inst& in = pl.in;
   IE_CHECK(!in.dense, INFOESRF_ERR_INVALID_ARG, "dense localization has nothing to tune");
