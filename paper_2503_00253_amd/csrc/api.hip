@@ -838,11 +838,24 @@ int apply_state(Plan& pl, const double* U, int64_t ld, const int32_t* act, const
 }
 
 // ------------------------------------------------------------------ stages
-int read_flags(Plan& pl, hipStream_t st, int32_t* out) {
-  IE_HIP(hipMemcpyAsync(out, pl.in.flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  IE_HIP(hipStreamSynchronize(st));
-  return 0;
+// Pinned words the host reads behind an event: the live count, the input-check flags, the
+// counters.
+struct HostStage {
+  int32_t nact;
+  int32_t flags;
+  int64_t cnt[INFOESRF_NUM_COUNTERS];
+};
+HostStage* host_stage() {
+  static thread_local HostStage* h = nullptr;
+  if (!h && hipHostMalloc((void**)&h, sizeof(HostStage), hipHostMallocDefault) != hipSuccess) h = nullptr;
+  return h;
 }
+hipEvent_t host_event() {
+  static thread_local hipEvent_t e = nullptr;
+  if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+  return e;
+}
+
 
 int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
   Inst& in = pl.in;
@@ -860,9 +873,24 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
                        P->loc.nx, in.flags);
     IE_HIP(hipGetLastError());
   }
+  // with host synchronization the input checks are read from pinned memory behind an event; the
+  // ensemble statistics (which read only X) are enqueued first, so the device works meanwhile
+  HostStage* hs = nullptr;
+  hipEvent_t ev = nullptr;
   if (op.host_sync) {
-    int32_t f = 0;
-    IE_TRY(read_flags(pl, st, &f));
+    hs = host_stage();
+    ev = host_event();
+    IE_CHECK(hs && ev, INFOESRF_ERR_HIP, "pinned host staging or event creation failed");
+    IE_HIP(hipMemcpyAsync(&hs->flags, in.flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    IE_HIP(hipEventRecord(ev, st));
+  }
+  // FP32 copies of Z and of the stencil exist only for the operator form in a low precision
+  // (plan_layout allocates them under the same condition)
+  const bool low = (op.inner != Prec::F64) && !in.band && !in.sd;
+  IE_HIP(launch_ens_stats(P->X, in.n, in.N, in.mu, in.Z, in.Z32, st));
+  if (op.host_sync) {
+    IE_HIP(hipEventSynchronize(ev));
+    const int32_t f = hs->flags;
     if (f & kFlagBadInput) {
       set_error(
           "invalid observation operator (CSR out of range, unsorted, more than max(64 m, 16 n) entries, or not the "
@@ -876,10 +904,6 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
   }
   // 2. ensemble and observation-space setup (indices are guarded against invalid values, which
   //    can only reach here when host_sync == 0; the flag then sets the call's status)
-  // FP32 copies of Z and of the stencil exist only for the operator form in a low precision
-  // (plan_layout allocates them under the same condition)
-  const bool low = (op.inner != Prec::F64) && !in.band && !in.sd;
-  IE_HIP(launch_ens_stats(P->X, in.n, in.N, in.mu, in.Z, in.Z32, st));
   IE_HIP(launch_diag_S(P->h_ptr, P->h_idx, P->h_w, P->r_var, in.Z, in.n, in.N, in.m, in.gs,
                        in.dense ? P->loc.dense : nullptr, in.diagS, st));
   IE_HIP(launch_min_reduce(in.diagS, in.m, in.dmin, st));
@@ -1206,22 +1230,6 @@ int bcg_solve_all(Plan& pl, const Options& op, hipStream_t st) {
 // launches: the covariance apply on the active columns, and the fused PCG kernel.
 // The sweep check's pinned landing place (live count, the call's counters) and its event, one per
 // host thread (calls on one thread are sequential), kept for the thread's lifetime.
-struct HostStage {
-  int32_t nact;
-  int32_t pad;
-  int64_t cnt[INFOESRF_NUM_COUNTERS];
-};
-HostStage* host_stage() {
-  static thread_local HostStage* h = nullptr;
-  if (!h && hipHostMalloc((void**)&h, sizeof(HostStage), hipHostMallocDefault) != hipSuccess) h = nullptr;
-  return h;
-}
-hipEvent_t host_event() {
-  static thread_local hipEvent_t e = nullptr;
-  if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
-  return e;
-}
-
 // The work that consumes u: status (the call's counters and statistics) and output (the
 // quadrature sum and the final update).  Both are idempotent.
 struct Finalize {
