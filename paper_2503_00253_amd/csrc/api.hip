@@ -51,14 +51,33 @@ struct Arena {
 constexpr int kChunk = 128;  // rows per reduction chunk
 
 // ------------------------------------------------------------------ kernels local to the runtime
-__global__ void k_lattice_check(const int32_t* h_ptr, const int32_t* h_idx, int64_t m, infoesrf_lattice lat,
-                                int32_t nx, int32_t* flags) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= m) return;
-  const int64_t a = k / lat.nxo, b = k % lat.nxo;
-  const int64_t want = (int64_t)(lat.z0 + a * lat.sz) * nx + (lat.x0 + b * lat.sx);
-  // h_idx[k] exists only when rows 0..k hold one entry each
-  if (h_ptr[k] != (int32_t)k || h_ptr[k + 1] != (int32_t)(k + 1) || h_idx[k] != want) atomicOr(flags, kFlagBadInput);
+// The call's flags and H's column counts start at zero.
+__global__ void k_input_zero(int32_t* flags, int32_t* fallbacks, int32_t* col_cnt, int64_t n) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) col_cnt[t] = 0;
+  if (t == 0) {
+    *flags = 0;
+    *fallbacks = 0;
+  }
+}
+
+// The element checks of the inputs in one pass: X finite (else the numeric flag); r_var positive
+// and finite, and, when declared, each observation one point of the stated lattice (else the
+// bad-input flag; h_idx[k] is read only when rows 0..k hold one entry each).
+__global__ void k_input_checks(const double* X, int64_t nN, const double* r_var, int64_t m, int lattice,
+                               const int32_t* h_ptr, const int32_t* h_idx, infoesrf_lattice lat, int32_t nx,
+                               int32_t* flags) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < nN && !isfinite(X[t])) atomicOr(flags, kFlagNumeric);
+  if (t < m) {
+    bool bad = !(r_var[t] > 0.0 && isfinite(r_var[t]));
+    if (lattice) {
+      const int64_t a = t / lat.nxo, b = t % lat.nxo;
+      const int64_t want = (int64_t)(lat.z0 + a * lat.sz) * nx + (lat.x0 + b * lat.sx);
+      bad = bad || h_ptr[t] != (int32_t)t || h_ptr[t + 1] != (int32_t)(t + 1) || h_idx[t] != want;
+    }
+    if (bad) atomicOr(flags, kFlagBadInput);
+  }
 }
 
 __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t count) {
@@ -94,11 +113,6 @@ __global__ void k_to_bf16_cols(const double* __restrict__ V, int64_t ldv, int64_
   if (t >= ldk * B) return;
   const int64_t k = t % ldk, b = t / ldk;
   out[t] = __float2bfloat16(k < n ? (float)V[k + b * ldv] : 0.f);
-}
-
-__global__ void k_positive_check(const double* v, int64_t count, int32_t* flags) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < count && !(v[t] > 0.0 && isfinite(v[t]))) atomicOr(flags, kFlagBadInput);
 }
 
 // Set per-system shifts: sigma[q*N + i] = s_q; the values arrive by kernel argument (capture safe).
@@ -860,21 +874,16 @@ hipEvent_t host_event() {
 int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
   Inst& in = pl.in;
   const infoesrf_problem* P = in.P;
-  // 1. validation kernels (they read H only within its own CSR bounds)
-  IE_HIP(launch_fill_i32(in.flags, 0, 1, st));
-  IE_HIP(launch_fill_i32(in.fallbacks, 0, 1, st));
-  IE_HIP(launch_nan_check(P->X, in.n * in.N, in.flags, st));
-  hipLaunchKernelGGL(k_positive_check, dim3(nb(in.m)), dim3(256), 0, st, P->r_var, in.m, in.flags);
+  // 1. input checks (they read H only within its own CSR bounds): the flags and column counts
+  //    zeroed, the element checks, the CSR check and count of H
+  hipLaunchKernelGGL(k_input_zero, dim3(nb(std::max<int64_t>(in.n, 1))), dim3(256), 0, st, in.flags, in.fallbacks,
+                     in.col_cnt, in.n);
   IE_HIP(hipGetLastError());
-  IE_HIP(launch_csc_build(P->h_ptr, P->h_idx, P->h_w, in.m, in.n, nnz_bound(P), in.col_cnt, in.col_ptr, in.row_of,
-                          in.w_of, in.flags, st));
-  if (in.obs) {
-    hipLaunchKernelGGL(k_lattice_check, dim3(nb(in.m)), dim3(256), 0, st, P->h_ptr, P->h_idx, in.m, op.lat,
-                       P->loc.nx, in.flags);
-    IE_HIP(hipGetLastError());
-  }
-  // with host synchronization the input checks are read from pinned memory behind an event; the
-  // ensemble statistics (which read only X) are enqueued first, so the device works meanwhile
+  hipLaunchKernelGGL(k_input_checks, dim3(nb(std::max<int64_t>(in.n * in.N, in.m))), dim3(256), 0, st, P->X,
+                     in.n * in.N, P->r_var, in.m, in.obs ? 1 : 0, P->h_ptr, P->h_idx, op.lat, P->loc.nx, in.flags);
+  IE_HIP(hipGetLastError());
+  IE_HIP(launch_csc_count(P->h_ptr, P->h_idx, in.m, in.n, nnz_bound(P), in.col_cnt, in.flags, st));
+  // with host synchronization the input checks are read from pinned memory behind an event
   HostStage* hs = nullptr;
   hipEvent_t ev = nullptr;
   if (op.host_sync) {
@@ -884,6 +893,10 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
     IE_HIP(hipMemcpyAsync(&hs->flags, in.flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     IE_HIP(hipEventRecord(ev, st));
   }
+  // the rest of H's transpose (it writes nothing when a check failed) and the ensemble statistics
+  // (which read only X) run meanwhile
+  IE_HIP(launch_csc_finish(P->h_ptr, P->h_idx, P->h_w, in.m, in.n, in.col_cnt, in.col_ptr, in.row_of, in.w_of,
+                           in.flags, st));
   // FP32 copies of Z and of the stencil exist only for the operator form in a low precision
   // (plan_layout allocates them under the same condition)
   const bool low = (op.inner != Prec::F64) && !in.band && !in.sd;

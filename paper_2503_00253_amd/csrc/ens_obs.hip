@@ -283,14 +283,17 @@ hipError_t launch_ens_stats(const double* X, int64_t n, int64_t N, double* mu, d
   return hipGetLastError();
 }
 
-hipError_t launch_csc_build(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, int64_t m, int64_t n,
-                            int64_t cap, int32_t* col_cnt, int32_t* col_ptr, int32_t* row_of, double* w_of,
-                            int32_t* flags, hipStream_t st) {
-  hipError_t e;
-  if ((e = launch_fill_i32(col_cnt, 0, n, st)) != hipSuccess) return e;
+hipError_t launch_csc_count(const int32_t* h_ptr, const int32_t* h_idx, int64_t m, int64_t n, int64_t cap,
+                            int32_t* col_cnt, int32_t* flags, hipStream_t st) {
   hipLaunchKernelGGL(k_csc_count, dim3(blocks_for(m)), dim3(kBlock), 0, st, h_ptr, h_idx, m, n, cap, col_cnt,
                      flags);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_csc_finish(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, int64_t m, int64_t n,
+                             int32_t* col_cnt, int32_t* col_ptr, int32_t* row_of, double* w_of, int32_t* flags,
+                             hipStream_t st) {
+  hipError_t e;
   hipLaunchKernelGGL(k_scan_one_block, dim3(1), dim3(kBlock), 0, st, col_cnt, n, col_ptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_fill_i32(col_cnt, 0, n, st)) != hipSuccess) return e;

@@ -122,11 +122,16 @@ __device__ inline int block_exclusive_scan(int v, int* swave, int* total) {
 hipError_t launch_ens_stats(const double* X, int64_t n, int64_t N, double* mu, double* Z, float* Z32,
                             hipStream_t st);
 
-// CSR -> CSC transpose of H (deterministic: entries of a column sorted by row).
-// cap: entries row_of / w_of can hold; h_ptr[m] > cap raises the bad-input flag and nothing is written.
-hipError_t launch_csc_build(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, int64_t m, int64_t n,
-                            int64_t cap, int32_t* col_cnt, int32_t* col_ptr, int32_t* row_of, double* w_of,
-                            int32_t* flags, hipStream_t st);
+// CSR -> CSC transpose of H (deterministic: entries of a column sorted by row) in two parts.
+// launch_csc_count checks the CSR (row bounds, sorted columns in range, h_ptr[m] <= cap, the
+// entries row_of / w_of can hold; else the bad-input flag) and counts each column's entries into
+// col_cnt, which must be zero; launch_csc_finish forms col_ptr and, unless a flag is set, the
+// sorted columns.
+hipError_t launch_csc_count(const int32_t* h_ptr, const int32_t* h_idx, int64_t m, int64_t n, int64_t cap,
+                            int32_t* col_cnt, int32_t* flags, hipStream_t st);
+hipError_t launch_csc_finish(const int32_t* h_ptr, const int32_t* h_idx, const double* h_w, int64_t m, int64_t n,
+                             int32_t* col_cnt, int32_t* col_ptr, int32_t* row_of, double* w_of, int32_t* flags,
+                             hipStream_t st);
 
 // rhs[s * ld + r] = dinv[r] * sum_e h_w[e] * Z[h_idx[e], member(s)] for systems s in [s0, s0+cnt),
 // member(s) = (s - s0) % N.
@@ -436,7 +441,6 @@ hipError_t launch_copy_cols(const double* src, int64_t lds, int64_t rows, int64_
 hipError_t launch_export_stats(const int32_t* iters, const double* relres, const int32_t* done, int64_t S,
                                int32_t* out_iters, double* out_relres, uint8_t* out_conv, double tol,
                                hipStream_t st);
-hipError_t launch_nan_check(const double* v, int64_t count, int32_t* flags, hipStream_t st);
 
 // ---------------------------------------------------------------- preconditioner setup (K8)
 // A strided m x k operand: element (r, a) at ptr[r * rs + a * cs].

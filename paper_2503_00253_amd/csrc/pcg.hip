@@ -503,11 +503,6 @@ __global__ void k_export_stats(const int32_t* iters, const double* relres, const
   if (orr) orr[s] = relres[s];
   if (oc) oc[s] = (done[s] == 1 && relres[s] <= tol) ? 1 : 0;
 }
-__global__ void k_nan_check(const double* v, int64_t count, int32_t* flags) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < count && !isfinite(v[t])) atomicOr(flags, kFlagNumeric);
-}
-
 template <int P, int RPT, typename TT, typename TV>
 hipError_t fused_typed(const PCGState& s, const LMP& lmp, int mode, int obs, int plain, const void* T, int64_t ldt,
                        const int32_t* act, const int32_t* nact, int32_t* act_out, int32_t* nact_out, int64_t Bmax,
@@ -703,10 +698,6 @@ hipError_t launch_export_stats(const int32_t* iters, const double* relres, const
                                hipStream_t st) {
   hipLaunchKernelGGL(k_export_stats, dim3(nb(S)), dim3(256), 0, st, iters, relres, done, S, out_iters, out_relres,
                      out_conv, tol);
-  return hipGetLastError();
-}
-hipError_t launch_nan_check(const double* v, int64_t count, int32_t* flags, hipStream_t st) {
-  hipLaunchKernelGGL(k_nan_check, dim3(nb(count)), dim3(256), 0, st, v, count, flags);
   return hipGetLastError();
 }
 
