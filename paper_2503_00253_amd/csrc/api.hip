@@ -80,6 +80,30 @@ __global__ void k_input_checks(const double* X, int64_t nN, const double* r_var,
   }
 }
 
+// Observation columns scattered to the state grid, R^{-1/2} weighted, when H is the declared
+// sub-lattice (row k = a nxo + b holds its one entry, index k, at state point
+// (z0 + a sz, x0 + b sx)): V[c][j] = w_k / sqrt(r_var_k) P[act_c][k] at the observed points, zero
+// elsewhere; the transposed-H scatter's sums, each of one term.
+__global__ void k_scatter_lattice(const double* __restrict__ P, int64_t ldp, const int32_t* __restrict__ act,
+                                  const int32_t* __restrict__ nact, infoesrf_lattice lat, int32_t nx,
+                                  const double* __restrict__ h_w, const double* __restrict__ r_var, int64_t n,
+                                  int64_t m, int64_t Bmax, double* __restrict__ V, int64_t ldv) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * Bmax) return;
+  const int64_t c = t / n, j = t % n;
+  const int32_t na = nact ? *nact : (int32_t)Bmax;
+  double acc = 0.0;
+  if (c < na) {
+    const int64_t dz = j / nx - lat.z0, dx = j % nx - lat.x0;
+    if (dz >= 0 && dx >= 0 && dz % lat.sz == 0 && dx % lat.sx == 0) {
+      const int64_t a = dz / lat.sz, b = dx / lat.sx;
+      const int64_t k = a * lat.nxo + b;
+      if (a < lat.nzo && b < lat.nxo && k < m) acc = h_w[k] / sqrt(r_var[k]) * P[(int64_t)act[c] * ldp + k];
+    }
+  }
+  V[c * ldv + j] = acc;
+}
+
 __global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t count) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t < count) b[t] = a[t];
@@ -331,6 +355,7 @@ struct Inst {
   const infoesrf_problem* P = nullptr;
   int64_t n = 0, N = 0, m = 0;
   bool dense = false, obs = false;
+  infoesrf_lattice lat{};  // the declared observation lattice (obs)
   // S assembled as a dense m x m matrix (column-major, ld = lds; FP32 copy for FP32 inner applies)
   bool sd = false;
   double* Sd = nullptr;
@@ -565,6 +590,7 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   in.m = P->m;
   in.dense = (P->loc.kind == INFOESRF_LOC_DENSE);
   in.obs = op.obs;
+  in.lat = op.lat;
   in.band = op.band;
   in.sd = use_dense_s(P, op, S);
   // the operator form in a low precision needs FP32 copies of Z and the stencil (with a dense S
@@ -836,8 +862,14 @@ int apply_state(Plan& pl, const double* U, int64_t ld, const int32_t* act, const
   Inst& in = pl.in;
   const int64_t Bpad = round_up(ncols, kSysTile);
   const int64_t ldr = ld64(in.n);
-  IE_HIP(launch_scatter_state(Prec::F64, U, ld, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n, in.m,
-                              Bpad, pl.bf.V, ldr, st));
+  if (in.obs) {  // the declared lattice: no transposed H
+    hipLaunchKernelGGL(k_scatter_lattice, dim3(nb(in.n * Bpad)), dim3(256), 0, st, U, ld, act, nact, in.lat,
+                       in.P->loc.nx, in.P->h_w, in.P->r_var, in.n, in.m, Bpad, (double*)pl.bf.V, ldr);
+    IE_HIP(hipGetLastError());
+  } else {
+    IE_HIP(launch_scatter_state(Prec::F64, U, ld, act, nact, in.col_ptr, in.row_of, in.w_of, in.P->r_var, in.n,
+                                in.m, Bpad, pl.bf.V, ldr, st));
+  }
   if (in.band) {
     IE_HIP(cov_band_timed(Prec::F64, in.gs, in.bandS, ldr, pl.bf.V, ldr, pl.bf.cols, ncols, nullptr, pl.bf.T, ldr,
                           st));
@@ -895,8 +927,10 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
   }
   // the rest of H's transpose (it writes nothing when a check failed) and the ensemble statistics
   // (which read only X) run meanwhile
-  IE_HIP(launch_csc_finish(P->h_ptr, P->h_idx, P->h_w, in.m, in.n, in.col_cnt, in.col_ptr, in.row_of, in.w_of,
-                           in.flags, st));
+  // (on the declared lattice the state scatter needs no transposed H)
+  if (!in.obs)
+    IE_HIP(launch_csc_finish(P->h_ptr, P->h_idx, P->h_w, in.m, in.n, in.col_cnt, in.col_ptr, in.row_of, in.w_of,
+                             in.flags, st));
   // FP32 copies of Z and of the stencil exist only for the operator form in a low precision
   // (plan_layout allocates them under the same condition)
   const bool low = (op.inner != Prec::F64) && !in.band && !in.sd;
