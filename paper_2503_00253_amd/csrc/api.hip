@@ -218,18 +218,16 @@ __global__ void k_net_targets(const double* __restrict__ u, int64_t ld, const do
 
 //   With a fixed iteration count, reaching it sets fdone = 3 (finished, not a failure) and the
 //   inner target is 0, so the inner PCG stops only at the count or on an exactly zero residual.
-__global__ void k_sweep_status(const double* rn, const double* bn, double rtol, double inner_rtol, int fp64_inner,
-                               const int32_t* iters, int max_iter, int fixed, double* relres, int32_t* fdone,
-                               int32_t* done, double* thresh, int32_t* sweeps, int count_sweep, int64_t S,
-                               int32_t* flags) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= S) return;
+// The sweep status of system s from its residual norm r and right-hand-side norm b.
+__device__ inline void sweep_status_one(int64_t s, double b, double r, double rtol, double inner_rtol, int fp64_inner,
+                                        const int32_t* iters, int max_iter, int fixed, double* relres,
+                                        int32_t* fdone, int32_t* done, double* thresh, int32_t* sweeps,
+                                        int count_sweep, int32_t* flags) {
   if (fdone[s] != 0) {
     done[s] = 1;
     return;
   }
   if (count_sweep) sweeps[s] += 1;
-  const double b = bn[s], r = rn[s];
   const double rr = b > 0.0 ? r / b : 0.0;
   relres[s] = rr;
   if (!isfinite(rr)) {
@@ -251,6 +249,54 @@ __global__ void k_sweep_status(const double* rn, const double* bn, double rtol, 
   done[s] = 0;
   const double target = 0.5 * rtol * b;
   thresh[s] = fixed ? 0.0 : (fp64_inner ? target : fmax(inner_rtol * r, target));
+}
+
+__global__ void k_sweep_status(const double* rn, const double* bn, double rtol, double inner_rtol, int fp64_inner,
+                               const int32_t* iters, int max_iter, int fixed, double* relres, int32_t* fdone,
+                               int32_t* done, double* thresh, int32_t* sweeps, int count_sweep, int64_t S,
+                               int32_t* flags) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  sweep_status_one(s, bn[s], rn[s], rtol, inner_rtol, fp64_inner, iters, max_iter, fixed, relres, fdone, done, thresh,
+                   sweeps, count_sweep, flags);
+}
+
+// The start of a zero-start solve, one 256-thread block per system slot s < spad: the counters
+// zeroed (and the apply-count correction); for s < S the norm of b, u = 0 and the first sweep's
+// status (its residual is b itself).
+__global__ __launch_bounds__(256) void k_solve_start(const double* __restrict__ b, int64_t m, int64_t ld, int64_t S,
+                                                     double* __restrict__ bnorm, double* __restrict__ u,
+                                                     int32_t* iters, int32_t* sweeps, int32_t* fdone,
+                                                     int64_t* app_adj, double rtol, double inner_rtol, int fp64_inner,
+                                                     int max_iter, int fixed, double* relres, int32_t* done,
+                                                     double* thresh, int32_t* flags) {
+  __shared__ double part[4];
+  const int64_t s = blockIdx.x;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    iters[s] = 0;
+    sweeps[s] = 0;
+    fdone[s] = 0;
+    if (s == 0) *app_adj = 0;
+  }
+  if (s >= S) return;
+  double acc = 0.0;
+  for (int64_t r = t; r < ld; r += 256) {
+    if (r < m) {
+      const double x = b[s * ld + r];
+      acc += x * x;
+    }
+    u[s * ld + r] = 0.0;
+  }
+  const double w = wave_sum_dpp(acc);
+  if ((t & 63) == 63) part[t >> 6] = w;
+  __syncthreads();
+  if (t == 0) {
+    const double bn = sqrt(((part[0] + part[1]) + part[2]) + part[3]);
+    bnorm[s] = bn;
+    sweep_status_one(s, bn, bn, rtol, inner_rtol, fp64_inner, iters, max_iter, fixed, relres, fdone, done, thresh,
+                     sweeps, 0, flags);
+  }
 }
 
 // Counters of the call (deterministic reduction over systems in one block).
@@ -1313,13 +1359,23 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
   ps.flags = in.flags;
   ps.max_iter = op.max_iter;
 
-  IE_HIP(launch_col_norms(sy.b, m, S, ldm, sy.bnorm, st));
-  IE_HIP(launch_fill_f64(sy.u, 0.0, flat, st));
   const bool warm = in.net != nullptr;
-  if (warm) IE_TRY(stage_warm(pl, st));
-  hipLaunchKernelGGL(k_zero_counters, dim3(nb(sy.Spad)), dim3(256), 0, st, sy.iters, sy.sweeps, sy.fdone, sy.Spad,
-                     sy.app_adj);
-  IE_HIP(hipGetLastError());
+  // a zero start forms the norms of b, u = 0, the counters and the first sweep's status in one
+  // launch; a learned start first needs the network's u
+  const bool fused_start = !warm;
+  if (fused_start) {
+    hipLaunchKernelGGL(k_solve_start, dim3((unsigned)sy.Spad), dim3(256), 0, st, sy.b, m, ldm, S, sy.bnorm, sy.u,
+                       sy.iters, sy.sweeps, sy.fdone, sy.app_adj, op.rtol, op.inner_rtol, fp64_inner ? 1 : 0,
+                       op.max_iter, op.fixed > 0 ? 1 : 0, sy.relres, sy.done, sy.thresh, in.flags);
+    IE_HIP(hipGetLastError());
+  } else {
+    IE_HIP(launch_col_norms(sy.b, m, S, ldm, sy.bnorm, st));
+    IE_HIP(launch_fill_f64(sy.u, 0.0, flat, st));
+    IE_TRY(stage_warm(pl, st));
+    hipLaunchKernelGGL(k_zero_counters, dim3(nb(sy.Spad)), dim3(256), 0, st, sy.iters, sy.sweeps, sy.fdone, sy.Spad,
+                       sy.app_adj);
+    IE_HIP(hipGetLastError());
+  }
   const bool msc = op.msc_q0 >= 0 && !warm;
   const bool bcg = op.bcg_Q > 0 && !warm;
 
@@ -1381,7 +1437,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
       IE_HIP(launch_sub(sy.b, sy.q, sy.r, flat, st));
     }
     const double* rcur = (r_is_b && persist) ? sy.b : sy.r;
-    if (!checked) {
+    if (!checked && !(sweep == 0 && fused_start)) {
       // the first residual of a zero start is b, whose norms are already there
       const double* rn = r_is_b ? sy.bnorm : sy.rn;
       if (!r_is_b) IE_HIP(launch_col_norms(rcur, m, S, ldm, sy.rn, st));
