@@ -1035,6 +1035,26 @@ int stage_precond(Plan& pl, const Options& op, hipStream_t st) {
   Inst& in = pl.in;
   const int k = pr.k;
   const int64_t ldm = pl.sy.ldm;
+  if (small_basis_fits(k, pr.p, in.m) && in.obs && in.band && !in.sd) {
+    // On the observed lattice the band apply reads its input block and writes its output block
+    // with the leading dimension of the systems: the sketch is written straight into the input
+    // block and Qb copied there by the Cholesky-QR kernel, and S Omega, S Qb are read from the
+    // output block in place (with (1 + sigma) = 0 the apply's finish would only copy them out).
+    double* V = static_cast<double*>(pl.bf.V);
+    const double* T = static_cast<const double*>(pl.bf.T);
+    const int64_t Bpad = round_up(k, kSysTile);
+    if (op.sketch) {
+      IE_HIP(launch_copy_cols(op.sketch, in.m, in.m, k, V, ldm, st));
+      IE_HIP(launch_iota(pr.act, pr.nact, k, st));
+    } else {
+      IE_HIP(launch_sketch_setup(op.seed, in.m, k, V, ldm, pr.act, pr.nact, pr.sig, Bpad, st));
+    }
+    IE_TRY(apply_raw(pl, Prec::F64, Bpad, pr.nact, op.rows_per_wave, st, nullptr));
+    IE_HIP(launch_cholqr2_small(T, in.m, k, ldm, pr.Qb, V, in.flags, st));
+    IE_TRY(apply_raw(pl, Prec::F64, Bpad, pr.nact, op.rows_per_wave, st, nullptr));
+    IE_HIP(launch_ritz_small(pr.Qb, T, in.m, k, pr.p, ldm, pr.theta, pr.Phi, pr.SPhi, pr.Phi32, pr.SPhi32, pr.G, st));
+    return 0;
+  }
   // the k sketch columns are applied as systems 0 .. k-1 with (1 + sigma) = 0: pure S
   if (op.sketch) {
     IE_HIP(launch_copy_cols(op.sketch, in.m, in.m, k, pr.Om, ldm, st));
@@ -1045,7 +1065,7 @@ int stage_precond(Plan& pl, const Options& op, hipStream_t st) {
   }
   IE_TRY(apply_S(pl, Prec::F64, pr.Om, ldm, pr.act, pr.nact, k, pr.sig, pr.Y, op.rows_per_wave, st));
   if (small_basis_fits(k, pr.p, in.m)) {  // the small dense steps in two launches
-    IE_HIP(launch_cholqr2_small(pr.Y, in.m, k, ldm, pr.Qb, in.flags, st));
+    IE_HIP(launch_cholqr2_small(pr.Y, in.m, k, ldm, pr.Qb, nullptr, in.flags, st));
     IE_TRY(apply_S(pl, Prec::F64, pr.Qb, ldm, pr.act, pr.nact, k, pr.sig, pr.SQ, op.rows_per_wave, st));
     IE_HIP(launch_ritz_small(pr.Qb, pr.SQ, in.m, k, pr.p, ldm, pr.theta, pr.Phi, pr.SPhi, pr.Phi32, pr.SPhi32, pr.G,
                              st));

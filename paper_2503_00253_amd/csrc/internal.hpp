@@ -470,7 +470,8 @@ hipError_t launch_min_reduce(const double* v, int64_t count, double* out, hipStr
 // Q = orth(Y) by Cholesky-QR twice, then theta, Phi, S Phi (FP64 and FP32, rounded) and the
 // three Gram blocks from Qb and S Qb (all column-major with leading dimension ld <= 2^26).
 bool small_basis_fits(int k, int p, int64_t m);
-hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, double* Q, int32_t* flags,
+// (Q2, if not null, receives a second copy of Q)
+hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, double* Q, double* Q2, int32_t* flags,
                                 hipStream_t st);
 hipError_t launch_ritz_small(const double* Qb, const double* SQ, int64_t m, int k, int p, int64_t ld, double* theta,
                              double* Phi, double* SPhi, float* Phi32, float* SPhi32, double* G, hipStream_t st);

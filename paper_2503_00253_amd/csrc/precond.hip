@@ -467,7 +467,8 @@ constexpr int kSmallNT = 1024;
 
 template <int K>
 __global__ __launch_bounds__(kSmallNT) void k_cholqr2_small(const double* __restrict__ Y, int64_t m, int k, int64_t ld,
-                                                       double* __restrict__ Q, int32_t* flags, int stage) {
+                                                       double* __restrict__ Q, double* __restrict__ Q2, int32_t* flags,
+                                                       int stage) {
   extern __shared__ __attribute__((aligned(16))) double xs[];
   __shared__ double part[kSmallNT / 64 * 256];
   __shared__ double G[K * K], R[K * K];
@@ -506,7 +507,13 @@ __global__ __launch_bounds__(kSmallNT) void k_cholqr2_small(const double* __rest
   }
   if (stage) {
     for (int c = 0; c < k; ++c)
-      for (int r = threadIdx.x; r < (int)m; r += kSmallNT) Q[c * (int)ld + r] = xs[c * (int)m + r];
+      for (int r = threadIdx.x; r < (int)m; r += kSmallNT) {
+        Q[c * (int)ld + r] = xs[c * (int)m + r];
+        if (Q2) Q2[c * (int)ld + r] = xs[c * (int)m + r];
+      }
+  } else if (Q2) {  // a thread copies the rows it wrote
+    for (int c = 0; c < k; ++c)
+      for (int r = threadIdx.x; r < (int)m; r += kSmallNT) Q2[c * (int)ld + r] = Q[c * (int)ld + r];
   }
 }
 
@@ -731,7 +738,7 @@ constexpr int64_t kSmallMaxLd = int64_t(1) << 26;
 constexpr size_t kSmallStage = 96 * 1024;
 constexpr size_t kSmallStageRitz = 96 * 1024;
 
-hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, double* Q, int32_t* flags,
+hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, double* Q, double* Q2, int32_t* flags,
                                 hipStream_t st) {
   if (!Y || !Q || !flags || ld < m || ld > kSmallMaxLd || !small_basis_fits(k, 1, m)) return hipErrorInvalidValue;
   const size_t bytes = (size_t)m * k * sizeof(double);
@@ -745,9 +752,9 @@ hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, d
     raised[k <= 4 ? 0 : 1] = true;
   }
   if (k <= 4)
-    hipLaunchKernelGGL(k_cholqr2_small<4>, dim3(1), dim3(kSmallNT), dyn, st, Y, m, k, ld, Q, flags, stage);
+    hipLaunchKernelGGL(k_cholqr2_small<4>, dim3(1), dim3(kSmallNT), dyn, st, Y, m, k, ld, Q, Q2, flags, stage);
   else
-    hipLaunchKernelGGL(k_cholqr2_small<8>, dim3(1), dim3(kSmallNT), dyn, st, Y, m, k, ld, Q, flags, stage);
+    hipLaunchKernelGGL(k_cholqr2_small<8>, dim3(1), dim3(kSmallNT), dyn, st, Y, m, k, ld, Q, Q2, flags, stage);
   return hipGetLastError();
 }
 

@@ -487,3 +487,37 @@ def test_persistent_kernel_variants_at_1024_observations(n_ritz):
         outs[tail] = (got.cpu().numpy(), st.iters.copy())
     assert rel(outs[0][0], outs[-1][0]) < 1e-8
     assert np.max(np.abs(outs[0][1] - outs[-1][1])) <= 2
+
+
+@pytest.mark.parametrize("oversample", [4, 3])
+def test_fixed_budget_small_sketch_on_the_lattice(oversample, monkeypatch):
+    """On the observed lattice with at most 8 sketch columns the preconditioner setup applies S
+    in place (the sketch written into the apply's input block, S Omega and S Qb read from its
+    output block) around the two one-workgroup kernels.  A 2-iteration budget depends on every
+    Ritz pair: the GPU agrees with the oracle fed FP32-rounded Ritz vectors to 1e-6, and with the
+    FP64 oracle to 1e-6 plus twice the oracle's own change under that rounding."""
+    prob = syn.config1()
+    say("small sketch on the lattice, oversample", oversample)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    Om = syn.sketch_matrix(prob.m, 4 + oversample, 41)
+    z64, it = ref.info_esrf_pcg(prob, s, p, rtol=0.0, n_ritz=4, Omega=Om, max_iter=2)
+    assert np.all(it == 2)
+    eig = ref.randomized_eig
+
+    def eig_fp32(apply_S, Omega, k):
+        Phi, SPhi, th = eig(apply_S, Omega, k)
+        return Phi.astype(np.float32).astype(np.float64), SPhi.astype(np.float32).astype(np.float64), th
+
+    monkeypatch.setattr(ref, "randomized_eig", eig_fp32)
+    z32, _ = ref.info_esrf_pcg(prob, s, p, rtol=0.0, n_ritz=4, Omega=Om, max_iter=2)
+    monkeypatch.setattr(ref, "randomized_eig", eig)
+    sens = rel(z32, z64)
+    P = ie.Problem.from_synthetic(prob)
+    Omt = torch.from_numpy(np.ascontiguousarray(Om.T)).cuda()
+    got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, "lattice", "band", n_ritz=4, oversample=oversample,
+                                                       sketch=Omt, fixed_iters=2))
+    assert np.all(st.iters == 2)
+    gz = got.cpu().numpy() / np.sqrt(prob.N - 1)
+    say("  sensitivity", sens, "gpu vs fp32-ritz oracle", rel(gz, z32))
+    assert rel(gz, z32) < 1e-6
+    assert rel(gz, z64) < 1e-6 + 2 * sens
