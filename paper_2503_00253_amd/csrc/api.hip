@@ -317,18 +317,25 @@ __global__ void k_msc_adjust(const int32_t* iters, int64_t S, const int32_t* mit
   }
 }
 
+// Also, when given: the live count (done == 0) into *nact_out, a copy of the counters into out2,
+// and the per-system statistics (iterations, relative residuals, converged at tol).
 __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, const int32_t* fdone, int64_t S,
                                   int64_t extra_fp64_applies, const int64_t* adj, int inner_fp64, int fixed,
-                                  const int32_t* flags,
-                                  const int32_t* fallbacks, int64_t* out) {
-  __shared__ int64_t acc[4][4];
+                                  const int32_t* flags, const int32_t* fallbacks, int64_t* out, const int32_t* done,
+                                  int32_t* nact_out, int64_t* out2, const double* relres, int32_t* oi, double* orr,
+                                  uint8_t* oc, double tol) {
+  __shared__ int64_t acc[5][4];
   const int t = threadIdx.x;
-  int64_t it = 0, sw = 0, nc = 0, mx = 0;
+  int64_t it = 0, sw = 0, nc = 0, mx = 0, lv = 0;
   for (int64_t s = t; s < S; s += 256) {
     it += iters[s];
     sw += sweeps[s];
     nc += (fdone[s] != 1);
     mx = max(mx, (int64_t)iters[s]);
+    if (done) lv += (done[s] == 0);
+    if (oi) oi[s] = iters[s];
+    if (orr) orr[s] = relres[s];
+    if (oc) oc[s] = (done[s] == 1 && relres[s] <= tol) ? 1 : 0;
   }
   // wavefront sums by shuffles, then the four wavefronts in order
 #pragma unroll
@@ -337,12 +344,14 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
     sw += __shfl_xor(sw, o, 64);
     nc += __shfl_xor(nc, o, 64);
     mx = max(mx, __shfl_xor(mx, o, 64));
+    lv += __shfl_xor(lv, o, 64);
   }
   if ((t & 63) == 0) {
     acc[0][t >> 6] = it;
     acc[1][t >> 6] = sw;
     acc[2][t >> 6] = nc;
     acc[3][t >> 6] = mx;
+    acc[4][t >> 6] = lv;
   }
   __syncthreads();
   if (t == 0) {
@@ -368,6 +377,9 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
     else if (f & kFlagNotSPD) status = INFOESRF_ERR_NOT_SPD;
     else if (c > 0 && !fixed) status = INFOESRF_WARN_NOT_CONVERGED;  // a fixed count is what was asked
     out[INFOESRF_CNT_STATUS] = status;
+    if (out2)
+      for (int j = 0; j < INFOESRF_NUM_COUNTERS; ++j) out2[j] = out[j];
+    if (nact_out) *nact_out = (int32_t)(((acc[4][0] + acc[4][1]) + acc[4][2]) + acc[4][3]);
   }
 }
 
@@ -1472,12 +1484,13 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
     // the persistent kernel needs no live count before the first solve (an empty queue costs
     // microseconds), so that status is not read on the host
     if (op.host_sync && !(persist && sweep == 0)) {
-      IE_HIP(launch_compact(sy.done, S, sy.act2, sy.nact2, st));
       HostStage* hs = host_stage();
       hipEvent_t ev = host_event();
       IE_CHECK(hs && ev, INFOESRF_ERR_HIP, "pinned host staging or event creation failed");
       const bool spec = fin && sweep > 0;
+      // the status kernel of the speculative finish counts the live systems itself
       if (spec) IE_TRY(fin->status());
+      else IE_HIP(launch_compact(sy.done, S, sy.act2, sy.nact2, st));
       IE_HIP(hipMemcpyAsync(&hs->nact, sy.nact2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       if (spec) IE_HIP(hipMemcpyAsync(hs->cnt, pl.in.counters, sizeof(hs->cnt), hipMemcpyDeviceToHost, st));
       IE_HIP(hipEventRecord(ev, st));
@@ -1560,18 +1573,15 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
 // The device half of finish_status: counters and the caller's per-system statistics.
 int finish_enqueue(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t extra_fp64, hipStream_t st) {
   Sys& sy = pl.sy;
+  // one block: the counters, the live count for the host check, and the caller's statistics
+  int32_t* oi = stats ? stats->iters : nullptr;
+  double* orr = stats ? stats->relres : nullptr;
+  uint8_t* oc = stats ? stats->converged : nullptr;
+  int64_t* out2 = stats ? stats->counters : nullptr;
   hipLaunchKernelGGL(k_finish_counters, dim3(1), dim3(256), 0, st, sy.iters, sy.sweeps, sy.fdone, sy.S, extra_fp64,
                      sy.app_adj, op.inner == Prec::F64 ? 1 : 0, op.fixed > 0 ? 1 : 0, pl.in.flags, pl.in.fallbacks,
-                     pl.in.counters);
+                     pl.in.counters, sy.done, sy.nact2, out2, sy.relres, oi, orr, oc, op.rtol);
   IE_HIP(hipGetLastError());
-  if (stats) {
-    if (stats->iters || stats->relres || stats->converged)
-      IE_HIP(launch_export_stats(sy.iters, sy.relres, sy.fdone, sy.S, stats->iters, stats->relres, stats->converged,
-                                 op.rtol, st));
-    if (stats->counters)
-      IE_HIP(hipMemcpyAsync(stats->counters, pl.in.counters, sizeof(int64_t) * INFOESRF_NUM_COUNTERS,
-                            hipMemcpyDeviceToDevice, st));
-  }
   return 0;
 }
 

@@ -438,9 +438,6 @@ hipError_t launch_final_mean(const double* mu, const double* T, int64_t ldt, int
 // dst[c*ldd + r] = src[c*lds + r] for r < rows, zero for rows <= r < ldd
 hipError_t launch_copy_cols(const double* src, int64_t lds, int64_t rows, int64_t cols, double* dst, int64_t ldd,
                             hipStream_t st);
-hipError_t launch_export_stats(const int32_t* iters, const double* relres, const int32_t* done, int64_t S,
-                               int32_t* out_iters, double* out_relres, uint8_t* out_conv, double tol,
-                               hipStream_t st);
 
 // ---------------------------------------------------------------- preconditioner setup (K8)
 // A strided m x k operand: element (r, a) at ptr[r * rs + a * cs].

@@ -495,14 +495,6 @@ __global__ void k_copy_cols(const double* __restrict__ src, int64_t lds, int64_t
   const int64_t c = t / ldd, r = t % ldd;
   dst[t] = (r < rows) ? src[c * lds + r] : 0.0;
 }
-__global__ void k_export_stats(const int32_t* iters, const double* relres, const int32_t* done, int64_t S,
-                               int32_t* oi, double* orr, uint8_t* oc, double tol) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  if (oi) oi[s] = iters[s];
-  if (orr) orr[s] = relres[s];
-  if (oc) oc[s] = (done[s] == 1 && relres[s] <= tol) ? 1 : 0;
-}
 template <int P, int RPT, typename TT, typename TV>
 hipError_t fused_typed(const PCGState& s, const LMP& lmp, int mode, int obs, int plain, const void* T, int64_t ldt,
                        const int32_t* act, const int32_t* nact, int32_t* act_out, int32_t* nact_out, int64_t Bmax,
@@ -691,13 +683,6 @@ hipError_t launch_copy_cols(const double* src, int64_t lds, int64_t rows, int64_
                             hipStream_t st) {
   if (cols <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_cols, dim3(nb(ldd * cols)), dim3(256), 0, st, src, lds, rows, cols, dst, ldd);
-  return hipGetLastError();
-}
-hipError_t launch_export_stats(const int32_t* iters, const double* relres, const int32_t* done, int64_t S,
-                               int32_t* out_iters, double* out_relres, uint8_t* out_conv, double tol,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_export_stats, dim3(nb(S)), dim3(256), 0, st, iters, relres, done, S, out_iters, out_relres,
-                     out_conv, tol);
   return hipGetLastError();
 }
 
