@@ -19,15 +19,33 @@ __global__ void k_ens_stats(const double* __restrict__ X, int64_t n, int64_t N, 
                             double* __restrict__ Z, float* __restrict__ Z32) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= n) return;
+  // the members eight at a time: their loads in flight together, the sum in member order
+  constexpr int U = 8;
   double s = 0.0;
-  for (int64_t i = 0; i < N; ++i) s += X[k + i * n];
+  int64_t i = 0;
+  for (; i + U <= N; i += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = X[k + (i + u) * n];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];
+  }
+  for (; i < N; ++i) s += X[k + i * n];
   const double m = s / (double)N;
   mu[k] = m;
   const double sc = 1.0 / sqrt((double)(N - 1));
-  for (int64_t i = 0; i < N; ++i) {
-    const double z = (X[k + i * n] - m) * sc;
-    Z[k + i * n] = z;
-    if (Z32) Z32[k + i * n] = (float)z;
+  for (i = 0; i < N; i += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = i + u < N ? X[k + (i + u) * n] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i + u < N) {
+        const double z = (v[u] - m) * sc;
+        Z[k + (i + u) * n] = z;
+        if (Z32) Z32[k + (i + u) * n] = (float)z;
+      }
+    }
   }
 }
 
@@ -244,16 +262,16 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_S(const int32_t* __restri
 __global__ void k_lattice_members(const int32_t* __restrict__ h_idx, const double* __restrict__ h_w,
                                   const double* __restrict__ r_var, const double* __restrict__ Z, int64_t n,
                                   int64_t N, int64_t m, double* __restrict__ Zt, float* __restrict__ Zt32) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= m) return;
+  // one thread per (observation k, member i)
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= m * N) return;
+  const int64_t k = t % m, i = t / m;
   const double sc = h_w[k] / sqrt(r_var[k]);
   int64_t j = h_idx[k];
   if (j < 0 || j >= n) j = 0;  // a wrong lattice claim is flagged by the lattice check
-  for (int64_t i = 0; i < N; ++i) {
-    const double v = sc * Z[j + i * n];
-    Zt[k + i * m] = v;
-    if (Zt32) Zt32[k + i * m] = (float)v;
-  }
+  const double v = sc * Z[j + i * n];
+  Zt[k + i * m] = v;
+  if (Zt32) Zt32[k + i * m] = (float)v;
 }
 
 __global__ void k_subsample_table(const double* __restrict__ table, int32_t bz, int32_t bx, int32_t sz, int32_t sx,
@@ -279,7 +297,8 @@ __global__ void k_convert_bf16(const double* __restrict__ in, __hip_bfloat16* __
 
 hipError_t launch_ens_stats(const double* X, int64_t n, int64_t N, double* mu, double* Z, float* Z32,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_ens_stats, dim3(blocks_for(n)), dim3(kBlock), 0, st, X, n, N, mu, Z, Z32);
+  // 64-thread blocks: a 4096-point grid spreads over 64 CUs
+  hipLaunchKernelGGL(k_ens_stats, dim3(blocks_for(n, 64)), dim3(64), 0, st, X, n, N, mu, Z, Z32);
   return hipGetLastError();
 }
 
@@ -340,8 +359,8 @@ hipError_t launch_diag_S(const int32_t* h_ptr, const int32_t* h_idx, const doubl
 
 hipError_t launch_lattice_members(const int32_t* h_idx, const double* h_w, const double* r_var, const double* Z,
                                   int64_t n, int64_t N, int64_t m, double* Zt, float* Zt32, hipStream_t st) {
-  hipLaunchKernelGGL(k_lattice_members, dim3(blocks_for(m)), dim3(kBlock), 0, st, h_idx, h_w, r_var, Z, n, N, m, Zt,
-                     Zt32);
+  hipLaunchKernelGGL(k_lattice_members, dim3(blocks_for(m * N)), dim3(kBlock), 0, st, h_idx, h_w, r_var, Z, n, N, m,
+                     Zt, Zt32);
   return hipGetLastError();
 }
 
