@@ -1018,9 +1018,17 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
     IE_HIP(launch_convert_f32(L.table, in.tab32, (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1), st));
   }
   if (in.obs) {
-    IE_HIP(launch_lattice_members(P->h_idx, P->h_w, P->r_var, in.Z, in.n, in.N, in.m, in.Zt, in.Zt32, st));
     const infoesrf_loc& L = P->loc;
-    IE_HIP(launch_subsample_table(L.table, L.bz, L.bx, op.lat.sz, op.lat.sx, in.go.bz, in.go.bx, in.subtab, st));
+    SubTable sub;
+    sub.table = L.table;
+    sub.bz = L.bz;
+    sub.bx = L.bx;
+    sub.sz = op.lat.sz;
+    sub.sx = op.lat.sx;
+    sub.bzs = in.go.bz;
+    sub.bxs = in.go.bx;
+    sub.out = in.subtab;
+    IE_HIP(launch_lattice_members(P->h_idx, P->h_w, P->r_var, in.Z, in.n, in.N, in.m, in.Zt, in.Zt32, st, sub));
     if (low) {
       IE_CHECK(in.subtab32 != nullptr, INFOESRF_ERR_HIP, "internal: FP32 lattice stencil not allocated");
       IE_HIP(launch_convert_f32(in.subtab, in.subtab32, (int64_t)(2 * in.go.bz + 1) * (2 * in.go.bx + 1), st));

@@ -261,9 +261,17 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_S(const int32_t* __restri
 
 __global__ void k_lattice_members(const int32_t* __restrict__ h_idx, const double* __restrict__ h_w,
                                   const double* __restrict__ r_var, const double* __restrict__ Z, int64_t n,
-                                  int64_t N, int64_t m, double* __restrict__ Zt, float* __restrict__ Zt32) {
-  // one thread per (observation k, member i)
+                                  int64_t N, int64_t m, double* __restrict__ Zt, float* __restrict__ Zt32,
+                                  SubTable sub) {
+  // one thread per (observation k, member i); the first threads also form the sub-sampled stencil
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (sub.out) {
+    const int w = 2 * sub.bxs + 1;
+    if (t < (2 * sub.bzs + 1) * w) {
+      const int dz = (int)(t / w) - sub.bzs, dx = (int)(t % w) - sub.bxs;
+      sub.out[t] = sub.table[(dz * sub.sz + sub.bz) * (2 * sub.bx + 1) + (dx * sub.sx + sub.bx)];
+    }
+  }
   if (t >= m * N) return;
   const int64_t k = t % m, i = t / m;
   const double sc = h_w[k] / sqrt(r_var[k]);
@@ -358,9 +366,11 @@ hipError_t launch_diag_S(const int32_t* h_ptr, const int32_t* h_idx, const doubl
 }
 
 hipError_t launch_lattice_members(const int32_t* h_idx, const double* h_w, const double* r_var, const double* Z,
-                                  int64_t n, int64_t N, int64_t m, double* Zt, float* Zt32, hipStream_t st) {
-  hipLaunchKernelGGL(k_lattice_members, dim3(blocks_for(m * N)), dim3(kBlock), 0, st, h_idx, h_w, r_var, Z, n, N, m,
-                     Zt, Zt32);
+                                  int64_t n, int64_t N, int64_t m, double* Zt, float* Zt32, hipStream_t st,
+                                  const SubTable& sub) {
+  const int64_t cnt = sub.out ? (int64_t)(2 * sub.bzs + 1) * (2 * sub.bxs + 1) : 0;
+  hipLaunchKernelGGL(k_lattice_members, dim3(blocks_for(std::max<int64_t>(m * N, cnt))), dim3(kBlock), 0, st, h_idx,
+                     h_w, r_var, Z, n, N, m, Zt, Zt32, sub);
   return hipGetLastError();
 }
 

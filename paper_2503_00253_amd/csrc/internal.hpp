@@ -155,8 +155,16 @@ hipError_t launch_diag_S(const int32_t* h_ptr, const int32_t* h_idx, const doubl
                          double* diagS, hipStream_t st);
 
 // Observed-lattice members: Zt[k, i] = dinv[k] * h_w[k] * Z[idx[k], i] (m x N col-major)
+// The sub-sampled stencil of the observed lattice: out[(dz + bzs) (2 bxs + 1) + dx + bxs] =
+// table[(dz sz + bz) (2 bx + 1) + dx sx + bx] (formed by launch_lattice_members when out is set).
+struct SubTable {
+  const double* table = nullptr;
+  int32_t bz = 0, bx = 0, sz = 1, sx = 1, bzs = 0, bxs = 0;
+  double* out = nullptr;
+};
 hipError_t launch_lattice_members(const int32_t* h_idx, const double* h_w, const double* r_var, const double* Z,
-                                  int64_t n, int64_t N, int64_t m, double* Zt, float* Zt32, hipStream_t st);
+                                  int64_t n, int64_t N, int64_t m, double* Zt, float* Zt32, hipStream_t st,
+                                  const SubTable& sub = SubTable{});
 // Sub-sampled stencil: sub[dz'][dx'] = table[dz' sz][dx' sx]
 hipError_t launch_subsample_table(const double* table, int32_t bz, int32_t bx, int32_t sz, int32_t sx, int32_t bzs,
                                   int32_t bxs, double* sub, hipStream_t st);
