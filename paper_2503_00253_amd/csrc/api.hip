@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstddef>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -323,7 +324,7 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
                                   int64_t extra_fp64_applies, const int64_t* adj, int inner_fp64, int fixed,
                                   const int32_t* flags, const int32_t* fallbacks, int64_t* out, const int32_t* done,
                                   int32_t* nact_out, int64_t* out2, const double* relres, int32_t* oi, double* orr,
-                                  uint8_t* oc, double tol) {
+                                  uint8_t* oc, double tol, int64_t* mirror) {
   __shared__ int64_t acc[5][4];
   const int t = threadIdx.x;
   int64_t it = 0, sw = 0, nc = 0, mx = 0, lv = 0;
@@ -379,7 +380,12 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
     out[INFOESRF_CNT_STATUS] = status;
     if (out2)
       for (int j = 0; j < INFOESRF_NUM_COUNTERS; ++j) out2[j] = out[j];
-    if (nact_out) *nact_out = (int32_t)(((acc[4][0] + acc[4][1]) + acc[4][2]) + acc[4][3]);
+    const int64_t live = ((acc[4][0] + acc[4][1]) + acc[4][2]) + acc[4][3];
+    if (nact_out) *nact_out = (int32_t)live;
+    if (mirror) {  // the live count in the low word of the first entry, then the counters
+      mirror[0] = (int64_t)(uint32_t)live;
+      for (int j = 0; j < INFOESRF_NUM_COUNTERS; ++j) mirror[1 + j] = out[j];
+    }
   }
 }
 
@@ -453,6 +459,8 @@ struct Sys {
          *thresh = nullptr, *pw = nullptr;
   int32_t *iters = nullptr, *sweeps = nullptr, *done = nullptr, *fdone = nullptr;
   int32_t *act = nullptr, *nact = nullptr, *act2 = nullptr, *nact2 = nullptr;
+  // the last host check's words in the pinned stage's layout: the live count, then the counters
+  int64_t* stage = nullptr;
   // multi-shift CG (SOLVER_MULTISHIFT): per-system zeta pair, per-member base scalars
   double *zeta = nullptr, *zeta_prev = nullptr, *mrr = nullptr, *malpha = nullptr, *mbeta = nullptr;
   int32_t* mit = nullptr;
@@ -736,6 +744,7 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   sy.nact = ar.take<int32_t>(2);  // list length, live count
   sy.act2 = ar.take<int32_t>(sy.Spad);
   sy.nact2 = ar.take<int32_t>(2);
+  sy.stage = ar.take<int64_t>(INFOESRF_NUM_COUNTERS + 1);
   if (op.solver == INFOESRF_SOLVER_MULTISHIFT) {
     const int64_t nm = round_up(std::max<int64_t>(in.N, 1), kSysTile);
     sy.zeta = ar.take<double>(sy.Spad);
@@ -949,6 +958,9 @@ struct HostStage {
   int32_t flags;
   int64_t cnt[INFOESRF_NUM_COUNTERS];
 };
+static_assert(offsetof(HostStage, cnt) == sizeof(int64_t) &&
+                  sizeof(HostStage) == sizeof(int64_t) * (INFOESRF_NUM_COUNTERS + 1),
+              "the device stage mirrors this layout");
 HostStage* host_stage() {
   static thread_local HostStage* h = nullptr;
   if (!h && hipHostMalloc((void**)&h, sizeof(HostStage), hipHostMallocDefault) != hipSuccess) h = nullptr;
@@ -1499,8 +1511,9 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
       // the status kernel of the speculative finish counts the live systems itself
       if (spec) IE_TRY(fin->status());
       else IE_HIP(launch_compact(sy.done, S, sy.act2, sy.nact2, st));
-      IE_HIP(hipMemcpyAsync(&hs->nact, sy.nact2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      if (spec) IE_HIP(hipMemcpyAsync(hs->cnt, pl.in.counters, sizeof(hs->cnt), hipMemcpyDeviceToHost, st));
+      // one copy of the live count and the counters (the status kernel laid them out as the stage)
+      if (spec) IE_HIP(hipMemcpyAsync(hs, sy.stage, sizeof(HostStage), hipMemcpyDeviceToHost, st));
+      else IE_HIP(hipMemcpyAsync(&hs->nact, sy.nact2, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       IE_HIP(hipEventRecord(ev, st));
       if (spec) IE_TRY(fin->output());
       IE_HIP(hipEventSynchronize(ev));
@@ -1588,7 +1601,7 @@ int finish_enqueue(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t e
   int64_t* out2 = stats ? stats->counters : nullptr;
   hipLaunchKernelGGL(k_finish_counters, dim3(1), dim3(256), 0, st, sy.iters, sy.sweeps, sy.fdone, sy.S, extra_fp64,
                      sy.app_adj, op.inner == Prec::F64 ? 1 : 0, op.fixed > 0 ? 1 : 0, pl.in.flags, pl.in.fallbacks,
-                     pl.in.counters, sy.done, sy.nact2, out2, sy.relres, oi, orr, oc, op.rtol);
+                     pl.in.counters, sy.done, sy.nact2, out2, sy.relres, oi, orr, oc, op.rtol, sy.stage);
   IE_HIP(hipGetLastError());
   return 0;
 }
