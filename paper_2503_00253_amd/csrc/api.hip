@@ -476,7 +476,6 @@ struct Pre {
   double *Om = nullptr, *Y = nullptr, *Qb = nullptr, *SQ = nullptr, *Tk = nullptr, *evec = nullptr,
          *evals = nullptr, *Rinv = nullptr, *sel = nullptr, *Phi = nullptr, *SPhi = nullptr, *theta = nullptr,
          *G = nullptr, *gscr = nullptr, *sig = nullptr;
-  float *Phi32 = nullptr, *SPhi32 = nullptr;
   int32_t *act = nullptr, *nact = nullptr;
 };
 
@@ -781,8 +780,6 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
     pr.sel = ar.take<double>(op.k * op.p);
     pr.Phi = ar.take<double>(sy.ldm * op.p);
     pr.SPhi = ar.take<double>(sy.ldm * op.p);
-    pr.Phi32 = ar.take<float>(sy.ldm * op.p);
-    pr.SPhi32 = ar.take<float>(sy.ldm * op.p);
     pr.theta = ar.take<double>(op.p);
     pr.G = ar.take<double>(3 * op.p * op.p);
     pr.gscr = ar.take<double>((int64_t)gram_chunks(in.m) * op.k * op.k);
@@ -1084,7 +1081,7 @@ int stage_precond(Plan& pl, const Options& op, hipStream_t st) {
     IE_TRY(apply_raw(pl, Prec::F64, Bpad, pr.nact, op.rows_per_wave, st, nullptr));
     IE_HIP(launch_cholqr2_small(T, in.m, k, ldm, pr.Qb, V, in.flags, st));
     IE_TRY(apply_raw(pl, Prec::F64, Bpad, pr.nact, op.rows_per_wave, st, nullptr));
-    IE_HIP(launch_ritz_small(pr.Qb, T, in.m, k, pr.p, ldm, pr.theta, pr.Phi, pr.SPhi, pr.Phi32, pr.SPhi32, pr.G, st));
+    IE_HIP(launch_ritz_small(pr.Qb, T, in.m, k, pr.p, ldm, pr.theta, pr.Phi, pr.SPhi, pr.G, st));
     return 0;
   }
   // the k sketch columns are applied as systems 0 .. k-1 with (1 + sigma) = 0: pure S
@@ -1099,8 +1096,7 @@ int stage_precond(Plan& pl, const Options& op, hipStream_t st) {
   if (small_basis_fits(k, pr.p, in.m)) {  // the small dense steps in two launches
     IE_HIP(launch_cholqr2_small(pr.Y, in.m, k, ldm, pr.Qb, nullptr, in.flags, st));
     IE_TRY(apply_S(pl, Prec::F64, pr.Qb, ldm, pr.act, pr.nact, k, pr.sig, pr.SQ, op.rows_per_wave, st));
-    IE_HIP(launch_ritz_small(pr.Qb, pr.SQ, in.m, k, pr.p, ldm, pr.theta, pr.Phi, pr.SPhi, pr.Phi32, pr.SPhi32, pr.G,
-                             st));
+    IE_HIP(launch_ritz_small(pr.Qb, pr.SQ, in.m, k, pr.p, ldm, pr.theta, pr.Phi, pr.SPhi, pr.G, st));
     return 0;
   }
   // Cholesky-QR twice: Qb = Y R^{-1}
@@ -1120,9 +1116,6 @@ int stage_precond(Plan& pl, const Options& op, hipStream_t st) {
   const int p = pr.p;
   IE_HIP(launch_right_mult(Qs, in.m, k, pr.sel, p, pr.Phi, 1, ldm, st));  // column-major m x p, ld = ldm
   IE_HIP(launch_right_mult(SQs, in.m, k, pr.sel, p, pr.SPhi, 1, ldm, st));
-  // the preconditioner works with FP32-rounded Ritz vectors; its Gram matrices come from the
-  // rounded values, so every part of it sees the same vectors
-  IE_HIP(launch_round_ritz(pr.Phi, pr.SPhi, in.m, p, ldm, pr.Phi32, pr.SPhi32, st));
   const Strided Ph{pr.Phi, 1, ldm}, SPh{pr.SPhi, 1, ldm};
   IE_HIP(launch_gram(Ph, Ph, in.m, p, pr.G, pr.gscr, st));
   IE_HIP(launch_gram(Ph, SPh, in.m, p, pr.G + p * p, pr.gscr, st));
@@ -1222,8 +1215,6 @@ LMP lmp_of(Plan& pl) {
   l.p = pl.pr.p;
   l.Phi = pl.pr.Phi;
   l.SPhi = pl.pr.SPhi;
-  l.Phi32 = pl.pr.Phi32;
-  l.SPhi32 = pl.pr.SPhi32;
   l.ld = pl.sy.ldm;
   l.theta = pl.pr.theta;
   l.G = pl.pr.G;

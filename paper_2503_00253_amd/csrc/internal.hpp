@@ -272,8 +272,6 @@ struct LMP {
   int p;               // number of Ritz pairs (0 = no preconditioner)
   const double* Phi;   // m x p column-major (Phi[j*ld + r]): a wavefront reads 64 consecutive rows
   const double* SPhi;  // m x p column-major, same ld
-  const float* Phi32;  // the same vectors in FP32 (Phi and SPhi hold these values exactly)
-  const float* SPhi32;
   int64_t ld;          // leading dimension of Phi and SPhi
   const double* theta; // p Ritz values of S
   const double* G;     // 3 p x p Gram matrices: Phi^T Phi, Phi^T S Phi, (S Phi)^T S Phi (row-major)
@@ -300,9 +298,6 @@ struct PCGState {
 // active are appended to act_out (*nact_out must be zero on entry) and their new p is written to
 // V (apply precision, observation domain; nullable).  plain != 0 keeps retired systems in the
 // list (masked solver).  m <= 4096.
-// Rounds Phi and SPhi (m x p, column-major, ld) to FP32 in place and writes the FP32 copies.
-hipError_t launch_round_ritz(double* Phi, double* SPhi, int64_t m, int p, int64_t ld, float* Phi32, float* SPhi32,
-                             hipStream_t st);
 // Multi-shift CG state (systems s = q N + i, system-major columns of ld; per-member scalars).
 struct MscState {
   int64_t m, ld, N;
@@ -333,7 +328,7 @@ struct BcgState {
   int64_t m, ld, N;
   int Q, p;                      // nodes, Ritz pairs of the preconditioner
   double *X, *R, *P, *W;         // iterate, residual, search block, W = C P
-  const double *Phi, *SPhi;      // m x p Ritz vectors (FP32-exact values), ld = ldphi
+  const double *Phi, *SPhi;      // m x p Ritz vectors, ld = ldphi
   int64_t ldphi;
   const double* G;               // the preconditioner's Gram blocks (3 p x p, row-major)
   const double* theta;           // Ritz values of S
@@ -472,13 +467,13 @@ hipError_t launch_lmp_finish(const double* evals, const double* evec, int k, int
                              hipStream_t st);                                  // top-p selection matrix
 hipError_t launch_min_reduce(const double* v, int64_t count, double* out, hipStream_t st);
 // The setup's small dense steps for k <= 8 sketch columns and m <= 8192 rows in two launches:
-// Q = orth(Y) by Cholesky-QR twice, then theta, Phi, S Phi (FP64 and FP32, rounded) and the
-// three Gram blocks from Qb and S Qb (all column-major with leading dimension ld <= 2^26).
+// Q = orth(Y) by Cholesky-QR twice, then theta, Phi, S Phi and the three Gram blocks from Qb and
+// S Qb (all column-major with leading dimension ld <= 2^26).
 bool small_basis_fits(int k, int p, int64_t m);
 // (Q2, if not null, receives a second copy of Q)
 hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, double* Q, double* Q2, int32_t* flags,
                                 hipStream_t st);
 hipError_t launch_ritz_small(const double* Qb, const double* SQ, int64_t m, int k, int p, int64_t ld, double* theta,
-                             double* Phi, double* SPhi, float* Phi32, float* SPhi32, double* G, hipStream_t st);
+                             double* Phi, double* SPhi, double* G, hipStream_t st);
 
 }  // namespace infoesrf

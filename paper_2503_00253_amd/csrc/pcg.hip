@@ -224,13 +224,12 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
     xv[j] = (ok && mode == 1) ? st.x[base + r] : 0.0;
     sv[j] = (ok && mode == 1 && obs_domain) ? (double)T[(int64_t)c * ldt + r] : 0.0;
   }
-  // The Ritz vectors are read in FP32 (the values the preconditioner's Gram matrices were formed
-  // from) for the dots of r and, when they fit in registers, kept for the preconditioned residual,
-  // so each system reads them once per iteration.  (They are not loaded with the system's data:
-  // that many loads in flight would stall the first round trip.)
-  constexpr bool kCache = (RPT * P <= 48);
+  // The Ritz vectors are read for the dots of r and, when they fit in registers, kept for the
+  // preconditioned residual, so each system reads them once per iteration.  (They are not loaded
+  // with the system's data: that many loads in flight would stall the first round trip.)
+  constexpr bool kCache = (RPT * P <= 24);
   constexpr int kC = (kCache && P > 0) ? RPT * P : 1;
-  float ph[kC], sph[kC];
+  double ph[kC], sph[kC];
   if (P > 0) {
     for (int o = tid; o < 3 * P * P; o += blockDim.x) sG[o] = lmp.G[o];
     if (tid < P) sG[3 * P * P + tid] = lmp.theta[tid];
@@ -293,13 +292,13 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       acc[0] += rv[j] * rv[j];
 #pragma unroll
       for (int l = 0; l < P; ++l) {
-        const float a = lmp.Phi32[l * lmp.ld + r], b = lmp.SPhi32[l * lmp.ld + r];
+        const double a = lmp.Phi[l * lmp.ld + r], b = lmp.SPhi[l * lmp.ld + r];
         if (kCache) {
           ph[j * P + l] = a;
           sph[j * P + l] = b;
         }
-        acc[1 + l] += (double)a * rv[j];
-        acc[1 + P + l] += (double)b * rv[j];
+        acc[1 + l] += a * rv[j];
+        acc[1 + P + l] += b * rv[j];
       }
     }
   }
@@ -373,8 +372,8 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
       double z = rv[j];
 #pragma unroll
       for (int l = 0; l < P; ++l) {
-        const double a = kCache ? (double)ph[j * P + l] : (double)lmp.Phi32[l * lmp.ld + r];
-        const double b = kCache ? (double)sph[j * P + l] : (double)lmp.SPhi32[l * lmp.ld + r];
+        const double a = kCache ? ph[j * P + l] : lmp.Phi[l * lmp.ld + r];
+        const double b = kCache ? sph[j * P + l] : lmp.SPhi[l * lmp.ld + r];
         z -= b * scoef[l] + a * scoef[P + l];
       }
       pv[j] = mode ? z + beta * pv[j] : z;
@@ -382,18 +381,6 @@ __global__ __launch_bounds__(256) void k_pcg_fused(PCGState st, LMP lmp, int mod
     }
   }
   write_v(pv);
-}
-
-__global__ void k_round_ritz(double* __restrict__ Phi, double* __restrict__ SPhi, int64_t m, int p, int64_t ld,
-                             float* __restrict__ Phi32, float* __restrict__ SPhi32) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= m * p) return;
-  const int64_t j = t / m, r = t % m, i = j * ld + r;
-  const float a = (float)Phi[i], b = (float)SPhi[i];
-  Phi32[i] = a;
-  SPhi32[i] = b;
-  Phi[i] = (double)a;
-  SPhi[i] = (double)b;
 }
 
 // --------------------------------------------------------------- list and vector kernels
@@ -546,15 +533,6 @@ hipError_t fused_rows(Prec prec, const PCGState& s, const LMP& lmp, int mode, in
 }
 
 }  // namespace
-
-hipError_t launch_round_ritz(double* Phi, double* SPhi, int64_t m, int p, int64_t ld, float* Phi32, float* SPhi32,
-                             hipStream_t st) {
-  const int64_t n = m * p;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_round_ritz, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Phi, SPhi, m, p, ld, Phi32,
-                     SPhi32);
-  return hipGetLastError();
-}
 
 hipError_t launch_gather_active(Prec prec, const double* P, int64_t ldp, const int32_t* act, const int32_t* nact,
                                 int64_t rows, int64_t Bmax, void* V, int64_t ldv, hipStream_t st) {

@@ -19,6 +19,8 @@
 // with no wrap or bounds test, and a thread walks a stencil row through consecutive LDS words.
 // The band values are loaded a chunk at a time ahead of their use, to keep many loads in flight
 // per wavefront.
+#include <atomic>
+
 #include "internal.hpp"
 
 namespace infoesrf {
@@ -102,13 +104,10 @@ __device__ inline __amdgpu_buffer_rsrc_t tail_rsrc(const void* p, int64_t bytes)
 __device__ inline double tail_ld8(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
 }
-__device__ inline float tail_ld4(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
-}
 
-// Whether the kernel keeps the thread's rows of the FP32 Ritz bases in registers.
+// Whether the kernel keeps the thread's rows of the Ritz bases in registers.
 __host__ __device__ constexpr bool tail_caches_ritz(int P, int RPT, int NT) {
-  return P > 0 && RPT * P <= 24 && NT < 1024;
+  return P > 0 && RPT * P <= 20 && NT < 1024;
 }
 
 // Rows of a thread: pairs of adjacent rows, 2 (tid + NT jj) + b for jj < RPT / 2, b in {0, 1}, so
@@ -180,7 +179,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
   __shared__ double sM[P * P + 1];
   __shared__ double sdot[W];
   __shared__ int s_idx;
-  // padded direction (band) or direction (dense S); then, when phi_lds, the FP32 Ritz bases
+  // padded direction (band) or direction (dense S); then, when phi_lds, the Ritz bases
   extern __shared__ double sp[];
   const int tid = threadIdx.x;
   const int64_t m = st.m;
@@ -201,21 +200,21 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
   for (int o = tid; o < npad; o += NT) sp[o] = 0.0;
   const double dmin = (P > 0) ? *lmp.dmin : 0.0;
   const int na = *nact;
-  // descriptors of the band (or S) and the FP32 Ritz bases; byte strides of their columns
+  // descriptors of the band (or S) and the Ritz bases; byte strides of their columns
   const __amdgpu_buffer_rsrc_t rsA =
       band ? tail_rsrc(ap.band, (int64_t)h * w * ap.ldb * 8) : tail_rsrc(ap.S, m * ap.lds * 8);
   const uint32_t colA = (uint32_t)((band ? ap.ldb : ap.lds) * 8);
-  const __amdgpu_buffer_rsrc_t rsF = tail_rsrc(lmp.Phi32, (int64_t)P * lmp.ld * 4);
-  const __amdgpu_buffer_rsrc_t rsG = tail_rsrc(lmp.SPhi32, (int64_t)P * lmp.ld * 4);
-  const uint32_t colF = (uint32_t)(lmp.ld * 4);
-  double* part = sp + npad;                                         // W x NT partial sums
-  float* sF = reinterpret_cast<float*>(part + (kLdsSums ? W * NT : 0));  // Phi32 (P x m), when phi_lds
-  float* sH = sF + (int64_t)P * m;                                  // SPhi32 (P x m)
+  const __amdgpu_buffer_rsrc_t rsF = tail_rsrc(lmp.Phi, (int64_t)P * lmp.ld * 8);
+  const __amdgpu_buffer_rsrc_t rsG = tail_rsrc(lmp.SPhi, (int64_t)P * lmp.ld * 8);
+  const uint32_t colF = (uint32_t)(lmp.ld * 8);
+  double* part = sp + npad;                           // W x NT partial sums
+  double* sF = part + (kLdsSums ? W * NT : 0);        // Phi (P x m), when phi_lds
+  double* sH = sF + (int64_t)P * m;                   // S Phi (P x m)
   if (phi_lds) {
     for (int o = tid; o < P * (int)m; o += NT) {
       const int l = o / (int)m, r = o % (int)m;
-      sF[o] = tail_ld4(rsF, (uint32_t)r * 4, l * colF);
-      sH[o] = tail_ld4(rsG, (uint32_t)r * 4, l * colF);
+      sF[o] = tail_ld8(rsF, (uint32_t)r * 8, l * colF);
+      sH[o] = tail_ld8(rsG, (uint32_t)r * 8, l * colF);
     }
   }
   // the corner of each row's stencil in the padded grid, and the row's byte offset in a column
@@ -322,7 +321,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
     double rz = start ? 0.0 : st.rz[s];
     int it = st.iters[s];
     double rv[RPT], pv[RPT], xv[RPT];
-    float ph[kC], sph[kC];
+    double ph[kC], sph[kC];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       const int64_t r = tail_row<NT>(tid, j);
@@ -333,8 +332,8 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
       if (kCache) {
 #pragma unroll
         for (int l = 0; l < P; ++l) {
-          ph[(j * P + l) % kC] = ok ? tail_ld4(rsF, (uint32_t)r * 4, l * colF) : 0.f;
-          sph[(j * P + l) % kC] = ok ? tail_ld4(rsG, (uint32_t)r * 4, l * colF) : 0.f;
+          ph[(j * P + l) % kC] = ok ? tail_ld8(rsF, (uint32_t)r * 8, l * colF) : 0.0;
+          sph[(j * P + l) % kC] = ok ? tail_ld8(rsG, (uint32_t)r * 8, l * colF) : 0.0;
         }
       }
     }
@@ -386,10 +385,10 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
           acc[0] += rv[j] * rv[j];
 #pragma unroll
           for (int l = 0; l < P; ++l) {
-            const double a = kCache ? (double)ph[(j * P + l) % kC]
-                                    : (double)(phi_lds ? sF[l * m + r] : tail_ld4(rsF, (uint32_t)r * 4, l * colF));
-            const double b = kCache ? (double)sph[(j * P + l) % kC]
-                                    : (double)(phi_lds ? sH[l * m + r] : tail_ld4(rsG, (uint32_t)r * 4, l * colF));
+            const double a = kCache ? ph[(j * P + l) % kC]
+                                    : (phi_lds ? sF[l * m + r] : tail_ld8(rsF, (uint32_t)r * 8, l * colF));
+            const double b = kCache ? sph[(j * P + l) % kC]
+                                    : (phi_lds ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
             acc[1 + l] += a * rv[j];
             acc[1 + P + l] += b * rv[j];
           }
@@ -460,10 +459,10 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
           double z = rv[j];
 #pragma unroll
           for (int l = 0; l < P; ++l) {
-            const double a = kCache ? (double)ph[(j * P + l) % kC]
-                                    : (double)(phi_lds ? sF[l * m + r] : tail_ld4(rsF, (uint32_t)r * 4, l * colF));
-            const double b = kCache ? (double)sph[(j * P + l) % kC]
-                                    : (double)(phi_lds ? sH[l * m + r] : tail_ld4(rsG, (uint32_t)r * 4, l * colF));
+            const double a = kCache ? ph[(j * P + l) % kC]
+                                    : (phi_lds ? sF[l * m + r] : tail_ld8(rsF, (uint32_t)r * 8, l * colF));
+            const double b = kCache ? sph[(j * P + l) % kC]
+                                    : (phi_lds ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
             z -= b * scoef[l] + a * scoef[P + l];
           }
           pv[j] = z + beta * pv[j];
@@ -606,25 +605,28 @@ hipError_t tail_go(const PCGState& s, const LMP& lmp, const TailApply& ap, const
   if ((int64_t)RPT * NT < s.m) return hipErrorInvalidValue;  // every row has a thread
   const void* fn = (const void*)k_pcg_tail<P, RPT, NT>;
   // the kernel's static LDS (read once per instantiation): static + dynamic stays within the CU's
-  static size_t stat = ~(size_t)0;
+  static std::atomic<size_t> stat_lds{~(size_t)0};
+  size_t stat = stat_lds.load();
   if (stat == ~(size_t)0) {
     hipFuncAttributes fa{};
     const hipError_t e = hipFuncGetAttributes(&fa, fn);
     if (e != hipSuccess) return e;
     stat = fa.sharedSizeBytes;
+    stat_lds.store(stat);
   }
   size_t lds = tail_lds_bytes(ap);
   if (tail_lds_sums(2 * P + 1, NT)) lds += (size_t)(2 * P + 1) * NT * sizeof(double);
   if (stat + lds > kTailLdsBig) return hipErrorInvalidValue;
   // the Ritz bases in LDS when the kernel does not keep them in registers and there is room
-  const size_t phi = (size_t)8 * P * s.m;
+  const size_t phi = (size_t)16 * P * s.m;
   const int phi_lds = (P > 0 && !tail_caches_ritz(P, RPT, NT) && stat + lds + phi <= kTailLdsBig) ? 1 : 0;
   if (phi_lds) lds += phi;
-  static size_t allowed = 64 * 1024;  // dynamic LDS this instantiation may take
-  if (lds > allowed) {
+  // dynamic LDS this instantiation may take (concurrent first calls raise it twice: harmless)
+  static std::atomic<size_t> allowed{64 * 1024};
+  if (lds > allowed.load()) {
     const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    allowed = lds;
+    allowed.store(lds);
   }
   // no more workgroups than can be resident at once: the others would only find the queue empty
   int dev = 0, per_cu = 0, cus = 0;
@@ -682,7 +684,7 @@ hipError_t launch_pcg_tail(const PCGState& s, const LMP& lmp, const TailApply& a
     return hipErrorInvalidValue;
   if (ap.kind == 0 && !ap.band) return hipErrorInvalidValue;
   if (ap.kind == 1 && !ap.S) return hipErrorInvalidValue;
-  if (lmp.p > 0 && (!lmp.Phi32 || !lmp.SPhi32 || !lmp.G || !lmp.theta || !lmp.dmin)) return hipErrorInvalidValue;
+  if (lmp.p > 0 && (!lmp.Phi || !lmp.SPhi || !lmp.G || !lmp.theta || !lmp.dmin)) return hipErrorInvalidValue;
   switch (lmp.p) {
     case 0: return tail_rows<0>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
     case 4: return tail_rows<4>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);

@@ -7,6 +7,8 @@
 //
 // All small dense steps run on one workgroup so the setup needs no host round
 // trip and can be captured in a HIP graph.
+#include <atomic>
+
 #include "internal.hpp"
 
 namespace infoesrf {
@@ -108,30 +110,40 @@ __global__ void k_gram_reduce(const double* __restrict__ scratch, int nchunks, i
   G[t] = acc;
 }
 
-// G (k x k, row-major, SPD) -> inverse of its upper Cholesky factor R (G = R^T R), in place.
-// One wavefront; the inverse's columns are built in LDS.
+// A Cholesky pivot at or below this fraction of the largest diagonal entry of the Gram matrix
+// marks a column that depends on the earlier ones (to rounding): Y = S Omega has rank at most
+// rank(S), which falls below the sketch width when, e.g., L = 1 and N - 1 < p + oversample.
+// Such a column gets a zero row in R and a zero column in Q; its Ritz value is then zero.
+constexpr double kCholDrop = 1e-12;
+
+// G (k x k, row-major, symmetric PSD) -> inverse of its upper Cholesky factor R (G = R^T R), in
+// place, with dependent columns (pivot <= kCholDrop max diag G) given zero rows in R and zero
+// columns in R^{-1}.  A non-finite pivot sets the numeric flag.  One wavefront; the inverse's
+// columns are built in LDS.
 __global__ void k_chol_inv(double* G, int k, int32_t* flags) {
   __shared__ double R[kMaxSketch * kMaxSketch];
   __shared__ double X[kMaxSketch * kMaxSketch];
   __shared__ int bad;
+  __shared__ double gmax;
   const int t = threadIdx.x;
-  if (t == 0) bad = 0;
+  if (t == 0) {
+    bad = 0;
+    double g = 0.0;
+    for (int j = 0; j < k; ++j) g = fmax(g, G[j * k + j]);
+    gmax = g;
+  }
   for (int e = t; e < k * k; e += blockDim.x) R[e] = G[e];
   __syncthreads();
   // right-looking Cholesky, column j
   for (int j = 0; j < k; ++j) {
     if (t == 0) {
       const double d = R[j * k + j];
-      if (!(d > 0.0)) {
-        bad = 1;
-        R[j * k + j] = 1.0;
-      } else {
-        R[j * k + j] = sqrt(d);
-      }
+      if (!isfinite(d)) bad = 1;
+      R[j * k + j] = (d > kCholDrop * gmax) ? sqrt(d) : 0.0;
     }
     __syncthreads();
     const double rjj = R[j * k + j];
-    for (int c = j + 1 + t; c < k; c += blockDim.x) R[j * k + c] /= rjj;
+    for (int c = j + 1 + t; c < k; c += blockDim.x) R[j * k + c] = rjj > 0.0 ? R[j * k + c] / rjj : 0.0;
     __syncthreads();
     for (int e = t; e < (k - j - 1) * (k - j - 1); e += blockDim.x) {
       const int a = j + 1 + e / (k - j - 1), b = j + 1 + e % (k - j - 1);
@@ -140,12 +152,12 @@ __global__ void k_chol_inv(double* G, int k, int32_t* flags) {
     __syncthreads();
   }
   // R is upper triangular in R[a*k+b], b >= a.  Invert by columns: Rinv[:, c] solves R x = e_c
-  // (X[a*k + c] = x_a, written by the thread of column c only).
+  // (X[a*k + c] = x_a, written by the thread of column c only); x_a = 0 on a dropped row.
   for (int c = t; c < k; c += blockDim.x) {
     for (int a = k - 1; a >= 0; --a) {
       double s = (a == c) ? 1.0 : 0.0;
       for (int b = a + 1; b < k; ++b) s -= R[a * k + b] * X[b * k + c];
-      X[a * k + c] = (a <= c) ? s / R[a * k + a] : 0.0;
+      X[a * k + c] = (a <= c && R[a * k + a] > 0.0) ? s / R[a * k + a] : 0.0;
     }
   }
   __syncthreads();
@@ -242,8 +254,8 @@ __global__ __launch_bounds__(256) void k_sym_eig(double* T, int k, double* evec,
     const double toff = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
     const double tdia = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
     __syncthreads();
-    // relative off-diagonal norm 1e-10: the Ritz vectors are rounded to FP32 afterwards
-    if (toff <= 1e-20 * tdia) break;
+    // relative off-diagonal norm 1e-14 (FP64 Ritz vectors)
+    if (toff <= 1e-28 * tdia) break;
     for (int step = 0; step < ke - 1; ++step) {
       const double* Ac = Ab[cur];
       double* An = Ab[cur ^ 1];
@@ -386,11 +398,12 @@ __global__ __launch_bounds__(256) void k_gram_small(Strided A, Strided B, int64_
 // ----------------------------------------------------------- small bases on one workgroup
 // With at most 8 sketch columns (p + oversample) the setup's small dense steps run as two
 // launches: Cholesky-QR twice of Y = S Omega, then the Rayleigh quotient T = Qb^T (S Qb), its
-// eigendecomposition, the top-p selection, the FP32-rounded Ritz vectors Phi, S Phi and their
-// three Gram blocks; the same arithmetic as the step-per-launch chain.
+// eigendecomposition, the top-p selection, the Ritz vectors Phi, S Phi and their three Gram
+// blocks; the same arithmetic as the step-per-launch chain.
 
-// Upper Cholesky factor of the SPD k x k matrix G (row-major) by one thread, in registers:
-// R[a*k+b] for b >= a.  A non-positive pivot is replaced by 1 and reported.
+// Upper Cholesky factor of the symmetric PSD k x k matrix G (row-major) by one thread, in
+// registers: R[a*k+b] for b >= a.  A dependent column (pivot <= kCholDrop max diag G) gets a zero
+// row; false when a pivot is not finite.
 template <int K>
 __device__ inline bool chol_upper_serial(const double* G, int k, double* R) {
   double r[K][K];
@@ -398,20 +411,19 @@ __device__ inline bool chol_upper_serial(const double* G, int k, double* R) {
   for (int a = 0; a < K; ++a)
 #pragma unroll
     for (int b = 0; b < K; ++b) r[a][b] = (a < k && b < k && b >= a) ? G[a * k + b] : 0.0;
+  double gmax = 0.0;
+#pragma unroll
+  for (int a = 0; a < K; ++a) gmax = fmax(gmax, r[a][a]);
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
     if (j < k) {
-      double d = r[j][j];
-      if (!(d > 0.0)) {
-        ok = false;
-        d = 1.0;
-      } else {
-        d = sqrt(d);
-      }
-      r[j][j] = d;
+      const double d = r[j][j];
+      if (!isfinite(d)) ok = false;
+      const double rjj = (d > kCholDrop * gmax) ? sqrt(d) : 0.0;
+      r[j][j] = rjj;
 #pragma unroll
-      for (int c = j + 1; c < K; ++c) r[j][c] /= d;
+      for (int c = j + 1; c < K; ++c) r[j][c] = rjj > 0.0 ? r[j][c] / rjj : 0.0;
 #pragma unroll
       for (int a = j + 1; a < K; ++a)
 #pragma unroll
@@ -496,7 +508,7 @@ __global__ __launch_bounds__(kSmallNT) void k_cholqr2_small(const double* __rest
           double t = x[j];
 #pragma unroll
           for (int a = 0; a < j; ++a) t -= q[a] * R[a * k + j];
-          q[j] = t / R[j * k + j];
+          q[j] = R[j * k + j] > 0.0 ? t / R[j * k + j] : 0.0;
         }
       }
 #pragma unroll
@@ -539,13 +551,12 @@ __device__ inline int jacobi_partner(int i, int step, int ke) {
 // and V_ij; each step rotates the k/2 pairs of the round-robin ordering at once, in one exchange
 // of entries between lanes: each lane forms the rotations of its row's and its column's pair),
 // the p largest eigenpairs (ties by index), Phi = Qb V_p and
-// S Phi = (S Qb) V_p rounded to FP32 (kept in FP32 and as the rounded FP64 values), theta, and
-// the Gram blocks Phi^T Phi, Phi^T S Phi, (S Phi)^T S Phi of the rounded vectors into G.
+// S Phi = (S Qb) V_p in FP64, theta, and the Gram blocks Phi^T Phi, Phi^T S Phi, (S Phi)^T S Phi
+// of those vectors into G.
 template <int K, int PB>
 __global__ __launch_bounds__(kSmallNT) void k_ritz_small(const double* __restrict__ Qb, const double* __restrict__ SQ,
                                                     int64_t m, int k, int p, int64_t ld, double* __restrict__ theta,
                                                     double* __restrict__ Phi, double* __restrict__ SPhi,
-                                                    float* __restrict__ Phi32, float* __restrict__ SPhi32,
                                                     double* __restrict__ G, int stage) {
   static_assert(K * K <= 64 && PB <= K, "one matrix entry a lane");
   // with stage set, Qb and S Qb are read once into dynamic LDS (m x k each, leading dimension m)
@@ -578,8 +589,8 @@ __global__ __launch_bounds__(kSmallNT) void k_ritz_small(const double* __restric
     for (int sweep = 0; sweep < 40; ++sweep) {
       const double off = wave_sum_dpp(in && i != j ? a * a : 0.0);
       const double dia = wave_sum_dpp(in && i == j ? a * a : 0.0);
-      // relative off-diagonal norm 1e-10: the Ritz vectors are rounded to FP32 afterwards
-      if (lane_shfl(off, 63) <= 1e-20 * lane_shfl(dia, 63)) break;
+      // relative off-diagonal norm 1e-14 (FP64 Ritz vectors)
+      if (lane_shfl(off, 63) <= 1e-28 * lane_shfl(dia, 63)) break;
 #pragma unroll
       for (int step = 0; step < K - 1; ++step) {
         if (step >= ke - 1) break;
@@ -636,11 +647,8 @@ __global__ __launch_bounds__(kSmallNT) void k_ritz_small(const double* __restric
             g += sq[a] * sel[a * PB + jj];
           }
         }
-        const float f32 = (float)f, g32 = (float)g;
-        Phi32[jj * ild + r] = f32;
-        SPhi32[jj * ild + r] = g32;
-        Phi[jj * ild + r] = (double)f32;
-        SPhi[jj * ild + r] = (double)g32;
+        Phi[jj * ild + r] = f;
+        SPhi[jj * ild + r] = g;
       }
     }
   }
@@ -745,11 +753,11 @@ hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, d
   const int stage = bytes <= kSmallStage ? 1 : 0;
   const size_t dyn = stage ? bytes : 0;
   const void* fn = k <= 4 ? (const void*)k_cholqr2_small<4> : (const void*)k_cholqr2_small<8>;
-  static bool raised[2] = {false, false};
-  if (dyn > 64 * 1024 && !raised[k <= 4 ? 0 : 1]) {
+  static std::atomic<bool> raised[2] = {false, false};
+  if (dyn > 64 * 1024 && !raised[k <= 4 ? 0 : 1].load()) {
     const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallStage);
     if (e != hipSuccess) return e;
-    raised[k <= 4 ? 0 : 1] = true;
+    raised[k <= 4 ? 0 : 1].store(true);
   }
   if (k <= 4)
     hipLaunchKernelGGL(k_cholqr2_small<4>, dim3(1), dim3(kSmallNT), dyn, st, Y, m, k, ld, Q, Q2, flags, stage);
@@ -759,8 +767,8 @@ hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, d
 }
 
 hipError_t launch_ritz_small(const double* Qb, const double* SQ, int64_t m, int k, int p, int64_t ld, double* theta,
-                             double* Phi, double* SPhi, float* Phi32, float* SPhi32, double* G, hipStream_t st) {
-  if (!Qb || !SQ || !theta || !Phi || !SPhi || !Phi32 || !SPhi32 || !G || ld < m || ld > kSmallMaxLd ||
+                             double* Phi, double* SPhi, double* G, hipStream_t st) {
+  if (!Qb || !SQ || !theta || !Phi || !SPhi || !G || ld < m || ld > kSmallMaxLd ||
       !small_basis_fits(k, p, m))
     return hipErrorInvalidValue;
   const size_t bytes = 2 * (size_t)m * k * sizeof(double);
@@ -769,21 +777,21 @@ hipError_t launch_ritz_small(const double* Qb, const double* SQ, int64_t m, int 
   const int which = k <= 4 ? 0 : (p <= 4 ? 1 : 2);
   const void* fn = which == 0 ? (const void*)k_ritz_small<4, 4>
                               : (which == 1 ? (const void*)k_ritz_small<8, 4> : (const void*)k_ritz_small<8, 8>);
-  static bool raised[3] = {false, false, false};
-  if (dyn > 64 * 1024 && !raised[which]) {
+  static std::atomic<bool> raised[3] = {false, false, false};
+  if (dyn > 64 * 1024 && !raised[which].load()) {
     const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallStageRitz);
     if (e != hipSuccess) return e;
-    raised[which] = true;
+    raised[which].store(true);
   }
   if (which == 0)
     hipLaunchKernelGGL((k_ritz_small<4, 4>), dim3(1), dim3(kSmallNT), dyn, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi,
-                       Phi32, SPhi32, G, stage);
+                       G, stage);
   else if (which == 1)
     hipLaunchKernelGGL((k_ritz_small<8, 4>), dim3(1), dim3(kSmallNT), dyn, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi,
-                       Phi32, SPhi32, G, stage);
+                       G, stage);
   else
     hipLaunchKernelGGL((k_ritz_small<8, 8>), dim3(1), dim3(kSmallNT), dyn, st, Qb, SQ, m, k, p, ld, theta, Phi, SPhi,
-                       Phi32, SPhi32, G, stage);
+                       G, stage);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import synthetic as syn
+from parity import upd  # noqa: E402
 from oracle import infoesrf_ref as ref
 
 pytestmark = pytest.mark.gpu
@@ -116,9 +117,9 @@ def test_batched_instance_matches_oracle():
         s0, p0, _ = ref.quadrature_elliptic(pr.Q, pr.ell)
         want = np.sqrt(pr.N - 1) * ref.perturbation_update_quadrature(dp, s0, p0)
         got = Xs[j].cpu().numpy()
-        assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-6, pr.name
+        assert upd(got, want) < 1e-6, pr.name
         mwant = ref.mean_update_cholesky(dp, pr.y)
-        assert np.linalg.norm(mus[j].cpu().numpy() - mwant) / np.linalg.norm(mwant) < 1e-6
+        assert upd(mus[j].cpu().numpy() - dp.mu, mwant - dp.mu) < 1e-6
 
 
 def test_batched_without_host_sync_matches():
@@ -159,3 +160,35 @@ def test_batched_reports_failing_instance():
     # the other instances are still solved
     Xa, _ = ie.perturbation_update(Ps[0], *nodes[0], ie.default_opts())
     assert np.array_equal(Xs[0].cpu().numpy(), Xa.cpu().numpy())
+
+
+def test_full_size_uneven_batch_matches_oracle():
+    """The 64-instance uneven batch (n = 4 U{128..2048}, N in {16, 32, 48, 64}, Q = U{8..24}) in
+    one batched call with the benchmark's options (FP64, observed lattice); three instances against
+    the dense oracle, each member to 1e-6: the largest n, the largest n among those with N = 64,
+    and the largest Q."""
+    probs = syn.config4_instances()
+    Ps = [ie.Problem.from_synthetic(pr) for pr in probs]
+    nodes = [ref.quadrature_elliptic(pr.Q, pr.ell)[:2] for pr in probs]
+    say("uneven batch of 64, full size")
+    runner = ie.BatchedRunner(Ps, nodes, ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE),
+                              ys=[pr.y for pr in probs], lattices=[P.lattice() for P in Ps])
+    code = runner.run()
+    torch.cuda.synchronize()
+    assert code == ie.OK
+    st = runner.stats(code)
+    assert st.converged.all() and np.all(st.relres <= 1e-8)
+    Xs, mus = runner.results()
+    largest_n = max(range(len(probs)), key=lambda j: probs[j].n)
+    largest_n64 = max((j for j in range(len(probs)) if probs[j].N == 64), key=lambda j: probs[j].n)
+    largest_q = max(range(len(probs)), key=lambda j: (probs[j].Q, probs[j].n))
+    for j in sorted({largest_n, largest_n64, largest_q}):
+        pr = probs[j]
+        say("  instance", j, "n", pr.n, "N", pr.N, "Q", pr.Q)
+        dp = ref.DenseProblem.from_problem(pr)
+        s0, p0 = nodes[j]
+        want = np.sqrt(pr.N - 1) * ref.perturbation_update_quadrature(dp, s0, p0)
+        err = upd(Xs[j].cpu().numpy(), want)
+        merr = upd(mus[j].cpu().numpy() - dp.mu, ref.mean_update_eig(dp, pr.y) - dp.mu)
+        say("    members", err, "mean", merr)
+        assert err < 1e-6 and merr < 1e-6

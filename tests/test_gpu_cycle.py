@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import synthetic as syn
+from parity import rel, upd  # noqa: E402
 from oracle import cycle_ref as cr
 from oracle import infoesrf_ref as ref
 
@@ -30,8 +31,6 @@ def say(*a):
     print("[case]", *a, file=sys.stderr, flush=True)
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 @pytest.mark.parametrize("nz,nx,k,steps,gamma", [(3, 20, 4, 7, 0.5), (8, 480, 21, 5, 0.1), (1, 40, 2, 20, 0.0)])
@@ -67,34 +66,42 @@ def test_observe_and_rtps_assemble():
     assert rel(out.cpu().numpy().T, want) < 1e-13
 
 
-def cycle_checks(prob, cycles, Q, tol=1e-6):
+def cycle_checks(prob, cycles, Q, tol=1e-6, opts=None, check_every=1):
+    """Runs `cycles` cycles on the GPU and checks the update of every `check_every`-th cycle
+    (the forecast ensemble and the observations the GPU itself produced) against the dense
+    oracle: each member's analysis perturbation and the analysis mean to `tol`."""
     rng = np.random.default_rng(123)
     noise = rng.standard_normal((cycles, prob.m)) * np.sqrt(prob.r_var[0])
     run = CycleRunner(prob, Q=Q, noise=noise)
+    if opts is not None:
+        run.set_opts(opts(run.P))
     s, p, _ = ref.quadrature_elliptic(Q, prob.ell)
     for t in range(cycles):
         run.load_noise(t)
         run.forecast()
         run.observe()
-        torch.cuda.synchronize()
-        Xf = run.state[:run.N].cpu().numpy().T.copy()
-        y = run.y.cpu().numpy().copy()
+        check = t % check_every == check_every - 1
+        if check:
+            torch.cuda.synchronize()
+            Xf = run.state[:run.N].cpu().numpy().T.copy()
+            y = run.y.cpu().numpy().copy()
         c1, c2 = run.update()
         torch.cuda.synchronize()
         assert c1 == ie.OK and c2 == ie.OK
-        fc = syn.Problem(n=prob.n, N=prob.N, m=prob.m, X=np.asfortranarray(Xf), h_ptr=prob.h_ptr,
-                         h_idx=prob.h_idx, h_w=prob.h_w, r_var=prob.r_var, y=y, nz=prob.nz, nx=prob.nx,
-                         periodic_z=prob.periodic_z, periodic_x=prob.periodic_x, bz=prob.bz, bx=prob.bx,
-                         table=prob.table, truth=prob.truth, Q=Q, ell=prob.ell, name="cycle")
-        dp = ref.DenseProblem.from_problem(fc)
-        want_pert = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
-        want_mean = ref.mean_update_eig(dp, y)
-        got_pert = run.Xa.cpu().numpy().T
-        got_mean = run.mean_a.cpu().numpy()
-        e1 = rel(got_pert, want_pert)
-        e2 = rel(got_mean - dp.mu, want_mean - dp.mu)
-        say("cycle", t, "pert", e1, "mean", e2)
-        assert e1 < tol and e2 < tol
+        if check:
+            fc = syn.Problem(n=prob.n, N=prob.N, m=prob.m, X=np.asfortranarray(Xf), h_ptr=prob.h_ptr,
+                             h_idx=prob.h_idx, h_w=prob.h_w, r_var=prob.r_var, y=y, nz=prob.nz, nx=prob.nx,
+                             periodic_z=prob.periodic_z, periodic_x=prob.periodic_x, bz=prob.bz, bx=prob.bx,
+                             table=prob.table, truth=prob.truth, Q=Q, ell=prob.ell, name="cycle")
+            dp = ref.DenseProblem.from_problem(fc)
+            want_pert = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+            want_mean = ref.mean_update_eig(dp, y)
+            got_pert = run.Xa.cpu().numpy().T
+            got_mean = run.mean_a.cpu().numpy()
+            e1 = upd(got_pert, want_pert)
+            e2 = upd(got_mean - dp.mu, want_mean - dp.mu)
+            say("cycle", t, "pert", e1, "mean", e2)
+            assert e1 < tol and e2 < tol
         run.assemble()
         run.t += 1
     return run
@@ -113,6 +120,21 @@ def test_cycle_full_size_matches_oracle():
     prob = syn.lorenz_problem()
     say("cycles 8x480")
     cycle_checks(prob, cycles=2, Q=12)
+
+
+def test_cycle_full_size_mixed_fp32_100_cycles():
+    """The 8 x 480 workload over 100 cycles with FP32 inner applies (FP64 vectors, scalars and
+    residual sweeps): every 10th cycle's update against the dense FP64 oracle to 1e-6."""
+    prob = syn.lorenz_problem()
+    say("cycles 8x480 mixed fp32, 100 cycles")
+
+    def mixed(P):
+        return ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=P.lattice(), precision=ie.MIXED_FP32)
+
+    run = cycle_checks(prob, cycles=100, Q=12, opts=mixed, check_every=10)
+    mse, var = run.diagnostics()
+    say("  after 100 cycles: forecast mse", mse, "variance", var)
+    assert np.isfinite(mse) and var > 0
 
 
 def test_graph_captured_cycle_matches_eager():

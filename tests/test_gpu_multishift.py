@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import synthetic as syn
+from parity import rel, upd  # noqa: E402
 from oracle import infoesrf_ref as ref
 
 pytestmark = pytest.mark.gpu
@@ -28,8 +29,6 @@ def say(*a):
     print("[case]", *a, file=sys.stderr, flush=True)
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 FORMS = {"operator": dict(cov_form=ie.COV_OPERATOR, s_form=ie.S_OPERATOR),
@@ -72,7 +71,7 @@ def test_multishift_update_matches_oracle(name, domain, form):
     got, st = ie.perturbation_update(P, s, p, opts(P, domain, form))
     assert st.code == ie.OK
     assert np.all(st.converged == 1) and np.all(st.relres <= 1e-8)
-    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert upd(got.cpu().numpy(), want) < 1e-6
     _, it_ref = ref.info_esrf_multishift(prob, s, p, rtol=0.5e-8)
     # a system whose true residual the FP64 check finds above rtol gets a few PCG iterations more
     got_it = st.iters.reshape(prob.Q, prob.N)
@@ -94,7 +93,7 @@ def test_multishift_gauss_legendre_nodes(Q):
     P = ie.Problem.from_synthetic(prob)
     got, st = ie.perturbation_update(P, s, p, opts(P, "state", "dense-s"))
     assert st.code == ie.OK and np.all(st.converged == 1)
-    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert upd(got.cpu().numpy(), want) < 1e-6
     it = st.iters.reshape(Q, prob.N).max(axis=1)
     assert it[np.argmax(s)] < it[np.argmin(s)]
 
@@ -112,7 +111,7 @@ def test_multishift_fixed_count_iterates(iters, form):
     assert st.code == ie.OK and np.all(st.iters == iters)
     inner = st.counter(ie.CNT_APPLIES) - st.counter(ie.CNT_SWEEPS)
     assert iters * prob.N <= inner <= iters * prob.N + 2 * prob.N  # plus the final state-space applies
-    assert rel(got.cpu().numpy(), np.sqrt(prob.N - 1) * want) < 1e-9
+    assert upd(got.cpu().numpy(), np.sqrt(prob.N - 1) * want) < 1e-9
 
 
 def test_multishift_rejects_mixed_precision():

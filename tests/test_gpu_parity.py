@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import synthetic as syn
+from parity import rel, upd  # noqa: E402
 from oracle import infoesrf_ref as ref
 
 pytestmark = pytest.mark.gpu
@@ -26,8 +27,6 @@ def say(*a):
     print("[case]", *a, file=sys.stderr, flush=True)
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 def stencil_problem(nz, nx, pz, px, ch, cv, N, stride, seed, r=0.3):
@@ -131,8 +130,8 @@ def test_mean_update_matches_oracle(case, domain, form):
     P = ie.Problem.from_synthetic(prob)
     got, st = ie.mean_update(P, prob.y, opts_for(prob, P, domain, form))
     assert st.code == ie.OK
-    assert rel(got.cpu().numpy(), want) < 1e-6
-    assert rel(got.cpu().numpy() - dp.mu, want - dp.mu) < 1e-6
+    assert upd(got.cpu().numpy(), want) < 1e-6
+    assert upd(got.cpu().numpy() - dp.mu, want - dp.mu) < 1e-6
     assert st.relres[0] <= 1e-8 and st.converged[0] == 1
 
 
@@ -148,7 +147,7 @@ def test_perturbation_update_matches_oracle(case, domain, form):
     P = ie.Problem.from_synthetic(prob)
     got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, form))
     assert st.code == ie.OK
-    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert upd(got.cpu().numpy(), want) < 1e-6
     assert np.all(st.relres <= 1e-8) and np.all(st.converged == 1)
     assert st.counter(ie.CNT_NOT_CONVERGED) == 0
     assert st.counter(ie.CNT_ITERATIONS) == int(st.iters.sum())
@@ -162,7 +161,7 @@ def test_perturbation_update_tight_tolerance():
     want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
     P = ie.Problem.from_synthetic(prob)
     got, st = ie.perturbation_update(P, s, p, ie.default_opts(rtol=1e-12))
-    assert rel(got.cpu().numpy(), want) < 1e-9
+    assert upd(got.cpu().numpy(), want) < 1e-9
     assert np.all(st.relres <= 1e-12)
 
 
@@ -212,7 +211,7 @@ def test_mixed_fp32_meets_fp64_bound(domain, form):
     P = ie.Problem.from_synthetic(prob)
     got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, form, precision=ie.MIXED_FP32))
     assert st.code == ie.OK
-    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert upd(got.cpu().numpy(), want) < 1e-6
     assert np.all(st.relres <= 1e-8)
     assert st.counter(ie.CNT_SWEEPS) >= prob.Q * prob.N  # every system had at least one FP64 check
 
@@ -294,11 +293,11 @@ def test_full_size_gaussian_n4096(domain, form):
     P = ie.Problem.from_synthetic(prob)
     got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, form))
     assert st.code == ie.OK
-    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert upd(got.cpu().numpy(), want) < 1e-6
     assert np.all(st.relres <= 1e-8)
     mean_want = ref.mean_update_eig(dp, prob.y)
     mean_got, sm = ie.mean_update(P, prob.y, opts_for(prob, P, domain, form))
-    assert rel(mean_got.cpu().numpy() - dp.mu, mean_want - dp.mu) < 1e-6
+    assert upd(mean_got.cpu().numpy() - dp.mu, mean_want - dp.mu) < 1e-6
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
@@ -327,7 +326,7 @@ def test_mixed_bf16_meets_fp64_bound(case, domain):
     P = ie.Problem.from_synthetic(prob)
     got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, precision=ie.MIXED_BF16))
     assert st.code == ie.OK
-    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert upd(got.cpu().numpy(), want) < 1e-6
     assert np.all(st.relres <= 1e-8)
     assert st.counter(ie.CNT_SWEEPS) >= prob.Q * prob.N
 
@@ -341,7 +340,7 @@ def test_mixed_bf16_full_size_lattice():
     P = ie.Problem.from_synthetic(prob)
     got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, "lattice", precision=ie.MIXED_BF16))
     assert st.code == ie.OK and np.all(st.relres <= 1e-8)
-    assert rel(got.cpu().numpy(), want) < 1e-6
+    assert upd(got.cpu().numpy(), want) < 1e-6
 
 
 def test_band_form_options():
@@ -413,7 +412,7 @@ def test_autotune_records_choices_and_keeps_results():
     dp = dense_of(prob)
     want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
     got, st = ie.perturbation_update(P, s, p, o)
-    assert st.code == ie.OK and rel(got.cpu().numpy(), want) < 1e-6
+    assert st.code == ie.OK and upd(got.cpu().numpy(), want) < 1e-6
     ie.autotune_reset()
 
 
@@ -435,12 +434,12 @@ def test_persistent_finish_matches(case, form, domain):
     for tail in (-1, 0, S):
         got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, form, tail_systems=tail))
         assert st.code == ie.OK and np.all(st.relres <= 1e-8)
-        assert rel(got.cpu().numpy(), want) < 1e-6, tail
+        assert upd(got.cpu().numpy(), want) < 1e-6, tail
         outs[tail] = (got.cpu().numpy(), st.iters.copy())
-    assert rel(outs[S][0], outs[-1][0]) < 1e-9
+    assert upd(outs[S][0], outs[-1][0]) < 1e-9
     assert np.max(np.abs(outs[S][1] - outs[-1][1])) <= 2
     # the default hands every system to the persistent kernel after the first step
-    assert rel(outs[0][0], outs[S][0]) < 1e-12
+    assert upd(outs[0][0], outs[S][0]) < 1e-12
 
 
 @pytest.mark.parametrize("n_ritz", [0, 4])
@@ -461,10 +460,10 @@ def test_persistent_variants(n_ritz, fixed):
         outs[tail] = (got.cpu().numpy(), st.iters.copy())
     if fixed:
         assert np.array_equal(outs[0][1], outs[-1][1])
-        assert rel(outs[0][0], outs[-1][0]) < 1e-9
+        assert upd(outs[0][0], outs[-1][0]) < 1e-9
     else:
         want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
-        assert rel(outs[0][0], want) < 1e-6
+        assert upd(outs[0][0], want) < 1e-6
         assert np.max(np.abs(outs[0][1] - outs[-1][1])) <= 2
 
 
@@ -485,39 +484,101 @@ def test_persistent_kernel_variants_at_1024_observations(n_ritz):
         got, st = ie.perturbation_update(P, s, p, o)
         assert st.code == ie.OK and np.all(st.relres <= 1e-8)
         outs[tail] = (got.cpu().numpy(), st.iters.copy())
+    # two solvers to the same residual, not the oracle: the whole update agrees to 1e-8
     assert rel(outs[0][0], outs[-1][0]) < 1e-8
     assert np.max(np.abs(outs[0][1] - outs[-1][1])) <= 2
 
 
 @pytest.mark.parametrize("oversample", [4, 3])
-def test_fixed_budget_small_sketch_on_the_lattice(oversample, monkeypatch):
+def test_fixed_budget_small_sketch_on_the_lattice(oversample):
     """On the observed lattice with at most 8 sketch columns the preconditioner setup applies S
     in place (the sketch written into the apply's input block, S Omega and S Qb read from its
     output block) around the two one-workgroup kernels.  A 2-iteration budget depends on every
-    Ritz pair: the GPU agrees with the oracle fed FP32-rounded Ritz vectors to 1e-6, and with the
-    FP64 oracle to 1e-6 plus twice the oracle's own change under that rounding."""
+    Ritz pair, so it checks the whole preconditioner: each member against the FP64 oracle's PCG
+    with the same sketch to 1e-6."""
     prob = syn.config1()
     say("small sketch on the lattice, oversample", oversample)
     s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
     Om = syn.sketch_matrix(prob.m, 4 + oversample, 41)
     z64, it = ref.info_esrf_pcg(prob, s, p, rtol=0.0, n_ritz=4, Omega=Om, max_iter=2)
     assert np.all(it == 2)
-    eig = ref.randomized_eig
-
-    def eig_fp32(apply_S, Omega, k):
-        Phi, SPhi, th = eig(apply_S, Omega, k)
-        return Phi.astype(np.float32).astype(np.float64), SPhi.astype(np.float32).astype(np.float64), th
-
-    monkeypatch.setattr(ref, "randomized_eig", eig_fp32)
-    z32, _ = ref.info_esrf_pcg(prob, s, p, rtol=0.0, n_ritz=4, Omega=Om, max_iter=2)
-    monkeypatch.setattr(ref, "randomized_eig", eig)
-    sens = rel(z32, z64)
     P = ie.Problem.from_synthetic(prob)
     Omt = torch.from_numpy(np.ascontiguousarray(Om.T)).cuda()
     got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, "lattice", "band", n_ritz=4, oversample=oversample,
                                                        sketch=Omt, fixed_iters=2))
     assert np.all(st.iters == 2)
     gz = got.cpu().numpy() / np.sqrt(prob.N - 1)
-    say("  sensitivity", sens, "gpu vs fp32-ritz oracle", rel(gz, z32))
-    assert rel(gz, z32) < 1e-6
-    assert rel(gz, z64) < 1e-6 + 2 * sens
+    say("  gpu vs fp64 oracle", upd(gz, z64))
+    assert upd(gz, z64) < 1e-6
+
+
+def test_headline_options_n4096():
+    """The n = 4096 workload with exactly the benchmark's options: observed lattice, automatic
+    covariance form (the band), 4 Ritz pairs from 4 + 4 sketch columns (the two-launch
+    preconditioner setup at m = 1024), every system to the persistent kernel (tail 0).  Each
+    member's analysis perturbation and the mean increment against the FP64 eigendecomposition
+    oracle to 1e-6, every system to a true FP64 relative residual of 1e-8."""
+    prob = syn.config2()
+    say("headline options n4096: lattice, band, n_ritz 4, oversample 4, tail 0")
+    dp = dense_of(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    P = ie.Problem.from_synthetic(prob)
+    o = ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=P.lattice(), cov_form=ie.COV_AUTO,
+                        n_ritz=4, oversample=4, tail_systems=0)
+    got, st = ie.perturbation_update(P, s, p, o)
+    assert st.code == ie.OK
+    assert np.all(st.relres <= 1e-8) and np.all(st.converged == 1)
+    err = upd(got.cpu().numpy(), want)
+    say("  members", err, "iterations max", int(st.iters.max()), "total", int(st.iters.sum()))
+    assert err < 1e-6
+    mean_want = ref.mean_update_eig(dp, prob.y)
+    mean_got, sm = ie.mean_update(P, prob.y, o)
+    assert sm.code == ie.OK and upd(mean_got.cpu().numpy() - dp.mu, mean_want - dp.mu) < 1e-6
+
+
+def ones_localization_problem(N=16, n=128, stride=4, seed=21):
+    """L = 1 everywhere, as a stencil on a non-periodic 1-D grid reaching every point: S has rank at
+    most N - 1, below the default sketch width of 20 columns."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, N)) + np.cos(np.arange(n) / 9.0)[:, None]
+    idx = np.arange(0, n, stride, dtype=np.int32)
+    m = idx.size
+    table = np.ones(2 * n - 1)
+    return syn.Problem(n=n, N=N, m=m, X=np.asfortranarray(X), h_ptr=np.arange(m + 1, dtype=np.int32), h_idx=idx,
+                       h_w=np.ones(m), r_var=0.5 * np.ones(m), y=rng.standard_normal(m), nz=1, nx=n,
+                       periodic_z=0, periodic_x=0, bz=0, bx=n - 1, table=table, truth=np.zeros(n), Q=8,
+                       ell=100.0, name="ones-localization")
+
+
+@pytest.mark.parametrize("form", ["band", "dense-L"])
+def test_rank_deficient_sketch(form):
+    """L = 1 and N = 16 with the default 10 Ritz pairs and 10 oversampling columns: the sketch
+    S Omega has rank at most 15 < 20, so Cholesky-QR meets dependent columns (zero columns of the
+    basis, zero Ritz values).  The update is still computed: to rtol against the dense oracle, and
+    at a 2-iteration budget against the oracle's PCG (Householder QR) with the same sketch, which
+    checks that the top 10 Ritz pairs are the same."""
+    prob = ones_localization_problem()
+    say("rank-deficient sketch", form, "N", prob.N, "k", 20)
+    dp = dense_of(prob)
+    assert np.allclose(dp.L, 1.0) and np.linalg.matrix_rank(dp.S) <= prob.N - 1
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    if form == "band":
+        P = ie.Problem.from_synthetic(prob)
+        kw = dict(cov_form=ie.COV_BAND)
+    else:
+        P = ie.Problem(prob.X, prob.h_ptr, prob.h_idx, prob.h_w, prob.r_var, dense=np.ones((prob.n, prob.n)))
+        kw = {}
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    got, st = ie.perturbation_update(P, s, p, ie.default_opts(**kw))
+    assert st.code == ie.OK and np.all(st.relres <= 1e-8)
+    assert upd(got.cpu().numpy(), want) < 1e-6
+    Om = syn.sketch_matrix(prob.m, 20, 5)
+    z64, it = ref.info_esrf_pcg(prob, s, p, rtol=0.0, n_ritz=10, Omega=Om, max_iter=2)
+    assert np.all(it == 2)
+    Omt = torch.from_numpy(np.ascontiguousarray(Om.T)).cuda()
+    got2, st2 = ie.perturbation_update(P, s, p, ie.default_opts(sketch=Omt, fixed_iters=2, **kw))
+    assert st2.code == ie.OK and np.all(st2.iters == 2)
+    e2 = upd(got2.cpu().numpy() / np.sqrt(prob.N - 1), z64)
+    say("  fixed budget vs oracle", e2)
+    assert e2 < 1e-6

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import synthetic as syn
+from parity import rel, upd  # noqa: E402
 from oracle import infoesrf_ref as ref
 from oracle import warmstart_ref as wr
 
@@ -27,8 +28,6 @@ def say(*a):
     print("[case]", *a, file=sys.stderr, flush=True)
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 def flat(params):
@@ -179,7 +178,7 @@ def test_learned_start_solve_meets_bound_and_fallback():
     for fp32 in (0, 1):   # BF16 inference on MFMA (the default), FP32 inference
         got, st = ie.perturbation_update(P, s, p, ie.default_opts(warm_start=ie.START_LEARNED, net=net,
                                                                   warm_fp32=fp32), y=prob.y)
-        assert st.code == ie.OK and rel(got.cpu().numpy(), want) < 1e-6
+        assert st.code == ie.OK and upd(got.cpu().numpy(), want) < 1e-6
         assert np.all(st.relres <= 1e-8) and st.counter(ie.CNT_FALLBACKS) == 0
     # a network that predicts NaN: every system falls back to the zero start
     bad = ie.Net.create(16, 9, 3)
@@ -187,7 +186,7 @@ def test_learned_start_solve_meets_bound_and_fallback():
     v[-1] = np.nan
     bad.set_params(v)
     got2, st2 = ie.perturbation_update(P, s, p, ie.default_opts(warm_start=ie.START_LEARNED, net=bad), y=prob.y)
-    assert st2.code == ie.OK and rel(got2.cpu().numpy(), want) < 1e-6
+    assert st2.code == ie.OK and upd(got2.cpu().numpy(), want) < 1e-6
     assert st2.counter(ie.CNT_FALLBACKS) == prob.Q * prob.N
     zero, stz = ie.perturbation_update(P, s, p, ie.default_opts())
     assert np.array_equal(st2.iters, stz.iters)   # the fallback is exactly the zero start
