@@ -251,6 +251,28 @@ int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ld
                        int64_t ldpv, const infoesrf_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * infoesrf_cov_apply for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and result, with no workspace argument.
+ * Its scratch is a fixed array of INFOESRF_NOALLOC_SCRATCH_BYTES (64 MiB) per
+ * device, part of the library's device code, held from the library's load
+ * until the process ends; the call allocates nothing (no hipMalloc/hipFree).
+ *   Limit: a call whose infoesrf_cov_apply_workspace_bytes(prob, B, opts)
+ *   exceeds INFOESRF_NOALLOC_SCRATCH_BYTES returns INFOESRF_ERR_WORKSPACE
+ *   (n = 4096, N = 40: up to 1667 columns per call with the band form,
+ *   1986 with the operator form; n = 256, N = 16: about 32000).
+ *   Sharing: every call on a device uses that device's array and leaves its
+ *   contents behind; nothing in it needs to start at zero.  Calls that
+ *   overlap on one device (other host threads, other streams) race: order
+ *   them on one stream or serialize them.  The device is the current one, on
+ *   which `stream` must live.
+ * Arguments, layouts, ownership and the other errors as infoesrf_cov_apply.
+ */
+#define INFOESRF_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int infoesrf_cov_apply_noalloc(const infoesrf_problem* prob, const double* V, int64_t ldv, int64_t B, double* PV,
+                               int64_t ldpv, const infoesrf_opts* opts, void* stream);
+
+/*
  * Mean update (Sec. 3.2, eq. 3.4): mean_a = mu + P H^T R^{-1/2} u0 where
  * (I + S) u0 = R^{-1/2} (y - H mu) is solved by PCG with the limited-memory
  * preconditioner.  y: m observations.  mean_a: n outputs.

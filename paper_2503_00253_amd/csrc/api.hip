@@ -1783,6 +1783,39 @@ int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_
 
 using namespace infoesrf;
 
+namespace infoesrf {
+
+int cov_apply_run(const infoesrf_problem* prob, const double* V, int64_t ldv, int64_t B, double* PV, int64_t ldpv,
+                  const Options& op, void* ws, hipStream_t st);
+
+// ------------------------------------------------------------------ no-allocation scratch
+// The workspace of infoesrf_cov_apply_noalloc: one array per device, held from the library's
+// load until the process ends.  In host code `scratch` names a host-side stand-in, never a device
+// address: kernels and copies get the address hipGetSymbolAddress returns for the current device,
+// looked up on the first call on that device and kept.  Calls that overlap on one device share
+// the array and race.
+static __device__ __align__(256) unsigned char scratch[INFOESRF_NOALLOC_SCRATCH_BYTES];
+constexpr int kNoAllocDevices = 64;
+std::atomic<void*> g_scratch_addr[kNoAllocDevices];
+
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  IE_HIP(hipGetDevice(&dev));
+  IE_CHECK(dev >= 0 && dev < kNoAllocDevices, INFOESRF_ERR_INVALID_ARG,
+           "infoesrf_cov_apply_noalloc: device index beyond " + std::to_string(kNoAllocDevices));
+  void* p = g_scratch_addr[dev].load();
+  if (!p) {
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    IE_CHECK(e == hipSuccess && p != nullptr, INFOESRF_ERR_HIP,
+             std::string("hipGetSymbolAddress of the no-allocation scratch failed: ") + hipGetErrorString(e));
+    g_scratch_addr[dev].store(p);  // the same address if two first calls race
+  }
+  *out = p;
+  return 0;
+}
+
+}  // namespace infoesrf
+
 extern "C" {
 
 void infoesrf_default_opts(infoesrf_opts* o) {
@@ -1863,7 +1896,38 @@ int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ld
   IE_CHECK(ws != nullptr, INFOESRF_ERR_WORKSPACE, "workspace is NULL");
   const size_t need = infoesrf_cov_apply_workspace_bytes(prob, B, opts);
   IE_CHECK(ws_bytes >= need, INFOESRF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
-  hipStream_t st = static_cast<hipStream_t>(stream);
+  return infoesrf::cov_apply_run(prob, V, ldv, B, PV, ldpv, op, ws, static_cast<hipStream_t>(stream));
+}
+
+int infoesrf_cov_apply_noalloc(const infoesrf_problem* prob, const double* V, int64_t ldv, int64_t B, double* PV,
+                               int64_t ldpv, const infoesrf_opts* opts, void* stream) {
+  clear_error();
+  IE_TRY(check_problem(prob));
+  Options op;
+  IE_TRY(resolve_options(prob, opts, op));
+  IE_CHECK(B >= 0, INFOESRF_ERR_INVALID_ARG, "B must be >= 0");
+  if (B == 0) return INFOESRF_OK;
+  IE_CHECK(V && PV, INFOESRF_ERR_INVALID_ARG, "V and PV must be non-NULL");
+  IE_CHECK(ldv >= prob->n && ldpv >= prob->n, INFOESRF_ERR_INVALID_ARG, "ldv and ldpv must be >= n");
+  const size_t need = infoesrf_cov_apply_workspace_bytes(prob, B, opts);
+  IE_CHECK(need > 0 && need <= INFOESRF_NOALLOC_SCRATCH_BYTES, INFOESRF_ERR_WORKSPACE,
+           "infoesrf_cov_apply_noalloc: this call needs " + std::to_string(need) +
+               " bytes of scratch, above its fixed " + std::to_string((size_t)INFOESRF_NOALLOC_SCRATCH_BYTES) +
+               " (use infoesrf_cov_apply with a caller workspace, or fewer columns per call)");
+  void* ws = nullptr;
+  IE_TRY(infoesrf::noalloc_scratch(&ws));
+  return infoesrf::cov_apply_run(prob, V, ldv, B, PV, ldpv, op, ws, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace infoesrf {
+
+// The body of infoesrf_cov_apply on a workspace of at least infoesrf_cov_apply_workspace_bytes:
+// every word of it that the call reads is written by the call first, so its contents on entry do
+// not matter.
+int cov_apply_run(const infoesrf_problem* prob, const double* V, int64_t ldv, int64_t B, double* PV, int64_t ldpv,
+                  const Options& op, void* ws, hipStream_t st) {
   const int64_t n = prob->n, N = prob->N;
   const int64_t ldr = ld64(n);
   Arena ar;
@@ -1929,6 +1993,10 @@ int infoesrf_cov_apply(const infoesrf_problem* prob, const double* V, int64_t ld
   if (op.host_sync) IE_HIP(hipStreamSynchronize(st));
   return INFOESRF_OK;
 }
+
+}  // namespace infoesrf
+
+extern "C" {
 
 int infoesrf_mean_update(const infoesrf_problem* prob, const double* y, double* mean_a, const infoesrf_opts* opts,
                          infoesrf_stats* stats, void* ws, size_t ws_bytes, void* stream) {

@@ -93,6 +93,8 @@ def library():
     lib.infoesrf_cov_apply.argtypes = [P(ProblemC), VP, C.c_int64, C.c_int64, VP, C.c_int64, P(Opts),
                                        VP, C.c_size_t, VP]
     lib.infoesrf_cov_apply.restype = C.c_int
+    lib.infoesrf_cov_apply_noalloc.argtypes = [P(ProblemC), VP, C.c_int64, C.c_int64, VP, C.c_int64, P(Opts), VP]
+    lib.infoesrf_cov_apply_noalloc.restype = C.c_int
     lib.infoesrf_mean_update.argtypes = [P(ProblemC), VP, VP, P(Opts), P(StatsC), VP, C.c_size_t, VP]
     lib.infoesrf_mean_update.restype = C.c_int
     lib.infoesrf_perturbation_update.argtypes = [P(ProblemC), C.c_int32, P(C.c_double), P(C.c_double), VP, VP,
@@ -330,6 +332,22 @@ def cov_apply(problem: Problem, V, opts: Opts | None = None):
     ws = _workspace(nbytes, Vt.device)
     _check(lib.infoesrf_cov_apply(C.byref(problem.c), Vt.data_ptr(), problem.n, B, out.data_ptr(), problem.n,
                                   C.byref(opts), ws.data_ptr(), ws.numel(), _stream()), allow_warn=False)
+    return out.t()
+
+
+def cov_apply_noalloc(problem: Problem, V, opts: Opts | None = None, out=None):
+    """P V through infoesrf_cov_apply_noalloc: no workspace (the library's fixed per-device
+    scratch); the caller passes V (n x B, as for cov_apply) and may pass the output buffer
+    (B x n contiguous, i.e. n x B column-major)."""
+    torch = _torch()
+    lib = library()
+    opts = opts or default_opts()
+    Vt = V.t().contiguous()
+    B = Vt.shape[0]
+    if out is None:
+        out = torch.empty_like(Vt)
+    _check(lib.infoesrf_cov_apply_noalloc(C.byref(problem.c), Vt.data_ptr(), problem.n, B, out.data_ptr(),
+                                          problem.n, C.byref(opts), _stream()), allow_warn=False)
     return out.t()
 
 
