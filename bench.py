@@ -28,6 +28,9 @@ PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0}   # MI355X dense matrix peaks: FP64
 # FP64 vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz
 PEAK_ALU_FP64 = 78.6
 PEAK_HBM_GBS = 8000.0                            # MI355X HBM3E
+# L2 -> CU reads: each CU's vector L1 fills at 64 B/clk from its XCD's L2 (16 channels x 128 B/clk
+# per XCD serve its 32 CUs): 256 CUs x 64 B x 2.4 GHz
+PEAK_L2_GBS = 256 * 64 * 2.4
 DTYPE = {0: "f64", 1: "f32/f64", 2: "bf16/f64"}
 # profile slots of the covariance applies: (kernel, bound, MFMA peak key)
 SLOTS = {0: ("k_cov_stencil<fp64>", "mfma", 0), 1: ("k_cov_stencil<fp32>", "mfma", 1),
@@ -99,6 +102,15 @@ def traffic_record(src_path, kernel):
         return None
     sha = hashlib.sha256(open(src_path, "rb").read()).hexdigest()
     return rec if rec.get("source_sha256") == sha else None
+
+
+def band_shape(prob, P, domain):
+    """(stencil planes, rows) of the band the persistent kernel applies: the sub-sampled stencil
+    on the observed lattice (rows = m), or the state grid's stencil (rows = n)."""
+    if domain == "lattice":
+        z0, sz, nzo, x0, sx, nxo = P.lattice()
+        return (2 * (prob.bz // sz) + 1) * (2 * (prob.bx // sx) + 1), nzo * nxo
+    return (2 * prob.bz + 1) * (2 * prob.bx + 1), prob.n
 
 
 def cpu_baseline(a):
@@ -280,18 +292,34 @@ def main():
     avg_ms = ms[dom] / max(launches[dom], 1)
     src = os.path.join(ROOT, "paper_2503_00253_amd", "csrc", SRC[dom])
     tr = traffic_record(src, kname)
+    extra = {}
     if bound == "mfma":
         achieved = flops[dom] / secs / 1e12 if secs > 0 else 0.0
         peak, unit = PEAK_TFLOPS[pk], "TFLOP/s"
     elif bound == "alu":
-        achieved = flops[dom] / secs / 1e12 if secs > 0 else 0.0
-        peak, unit = PEAK_ALU_FP64, "TFLOP/s"
+        # the persistent PCG kernel streams the band of S from L2 once per iteration: bound by the
+        # L2 -> CU path, with the FP64 ALU fraction beside it
+        # the kernel counts each system-iteration (vectors) and adds the flops of every apply,
+        # the residual checks' included, at 2 nnz(L) + m (12 + 8 p) each (periodic lattice: every
+        # stencil point of every row is a nonzero)
+        planes, m_rows = band_shape(prob, P, a.domain)
+        per_apply = 2.0 * planes * m_rows + m_rows * (12.0 + 8.0 * a.n_ritz)
+        checks = max(flops[dom] / per_apply - vectors[dom], 0.0)
+        it_bytes = planes * m_rows * (4.0 if a.precision == "fp32" else 8.0)
+        l2_bytes = vectors[dom] * it_bytes + checks * planes * m_rows * 8.0
+        alu = flops[dom] / secs / 1e12 if secs > 0 else 0.0
+        achieved = l2_bytes / secs / 1e9 if secs > 0 else 0.0
+        peak, unit, bound = PEAK_L2_GBS, "GB/s", "l2"
+        extra = {"alu_achieved_tflops": round(alu, 3), "alu_peak_tflops": PEAK_ALU_FP64,
+                 "alu_frac": round(alu / PEAK_ALU_FP64, 4),
+                 "l2_bytes_per_launch": l2_bytes / max(launches[dom], 1),
+                 "l2_bytes_per_iteration_apply": it_bytes, "band_planes": planes, "band_rows": m_rows}
     else:
         achieved = nbytes[dom] / secs / 1e9 if secs > 0 else 0.0
         peak, unit = PEAK_HBM_GBS, "GB/s"
     roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4),
-            "traffic": (tr or {}).get("bytes_per_launch"),
+            "traffic": (tr or {}).get("bytes_per_launch"), **extra,
             "kernel": kname, "launches": launches[dom], "avg_launch_ms": round(avg_ms, 4), "vectors": vectors[dom],
             "flops_per_launch": flops[dom] / max(launches[dom], 1),
             "flops_per_vector": flops[dom] / max(vectors[dom], 1),
@@ -343,7 +371,7 @@ def main():
         # the plain baseline: FP64 operator-form applies of P in the state space every iteration
         # (no band, no dense S), masked systems
         popts = ie.default_opts(precision=ie.FP64, solver=ie.SOLVER_PLAIN, cov_form=ie.COV_OPERATOR,
-                                s_form=ie.S_OPERATOR)
+                                s_form=ie.S_OPERATOR, n_ritz=a.n_ritz, oversample=a.oversample)
         prun = ie.PerturbationRunner(P, s, p, popts)
         prun.run()
         torch.cuda.synchronize()
@@ -355,8 +383,33 @@ def main():
         pv = systems * a.plain_steps / (t1 - t0)
         diff = float((run.result() - prun.result()).norm() / prun.result().norm())
         out["plain_gpu_pcg"] = {"value": round(pv, 2), "unit": "solves/s", "steps": a.plain_steps,
-                                "speedup": round(value / pv, 3), "rel_diff_vs_plain": diff}
+                                "speedup": round(value / pv, 3), "rel_diff_vs_plain": diff,
+                                "options": f"FP64, operator form sum_i z_i o L(z_i o v) in the state space, masked "
+                                           f"systems, one launch per iteration, zero start, {a.n_ritz} Ritz pairs "
+                                           f"+ {a.oversample} oversampling (the line's preconditioner)"}
         log("plain GPU PCG", pv, "speedup", value / pv, "diff", diff)
+        if a.domain == "lattice":
+            # the same solver and options in the state space (general H), beside the lattice line
+            skw = dict(kw)
+            skw.pop("apply_domain", None)
+            skw.pop("lattice", None)
+            srun = ie.PerturbationRunner(P, s, p, ie.default_opts(**skw))
+            srun.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.plain_steps):
+                scode = srun.run()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sst = srun.stats(scode)
+            assert sst.counter(ie.CNT_NOT_CONVERGED) == 0, "state-domain line: systems missed rtol"
+            sv = systems * a.plain_steps / (t1 - t0)
+            out["state_domain_line"] = {"value": round(sv, 2), "unit": "solves/s",
+                                        "ms_per_step": round((t1 - t0) * 1e3 / a.plain_steps, 4),
+                                        "max_iterations": int(sst.iters.max()),
+                                        "rel_diff_vs_line": float((srun.result() - run.result()).norm()
+                                                                  / run.result().norm())}
+            log("state-domain line", out["state_domain_line"])
 
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a)
@@ -458,6 +511,10 @@ def bench_batched(a, prec):
     kw = dict(precision=prec, solver=SOLVERS[a.solver],
               cov_form={"auto": ie.COV_AUTO, "operator": ie.COV_OPERATOR, "band": ie.COV_BAND}[a.form],
               tail_systems=a.tail)
+    if a.n_ritz is not None:
+        kw.update(n_ritz=a.n_ritz)
+    if a.oversample is not None:
+        kw.update(oversample=a.oversample)
     lats = None
     if a.domain == "lattice":
         kw.update(apply_domain=ie.DOMAIN_OBS_LATTICE)
@@ -486,7 +543,8 @@ def bench_batched(a, prec):
                       "n_range": [min(pr.n for pr in probs), max(pr.n for pr in probs)],
                       "N_range": [min(pr.N for pr in probs), max(pr.N for pr in probs)],
                       "Q_range": [min(pr.Q for pr in probs), max(pr.Q for pr in probs)], "rtol": 1e-8,
-                      "precision": a.precision, "apply_domain": a.domain, "solver": a.solver},
+                      "precision": a.precision, "apply_domain": a.domain, "solver": a.solver,
+                      "one_launch": run.one_launch()},
            "iterations": {"total": int(st.iters.sum()), "max": int(st.iters.max())}}
     log(f"{value:.1f} solves/s")
     print(json.dumps(out), flush=True)

@@ -313,16 +313,30 @@ int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const 
  *             the totals over all instances, the status the most severe one.
  *   ws        one workspace of infoesrf_batched_workspace_bytes() bytes,
  *             split into one slice per instance.
- * Instances run largest first on a pool of library-owned streams (default
- * priority) that fork from and join back into `stream`.  With host_sync 1 the
- * return code is the most severe instance code and the message names the
- * first failing instance; with host_sync 0 every launch is issued from the
- * calling thread and the status is left in stats->counters (this call is
- * not meant for HIP graph capture; the single-instance calls are).
- * Validation of every instance precedes any device work.
+ * One launch (infoesrf_batched_one_launch returns 1): when every instance's
+ * inner PCG can run in the persistent kernel (compacted solver, zero start,
+ * tail_systems >= 0, FP64 or MIXED_FP32, the band on the observed lattice or
+ * the dense S, m <= 4096, one n_ritz for all), each instance is set up in
+ * turn on `stream` (its mean system, at shift 0, joins its perturbation
+ * systems), then each sweep is one persistent launch over a queue of every
+ * instance's live systems (largest instance first, smallest shifts first
+ * within it), then each instance's quadrature sum and final update.  With
+ * host_sync 0 this issues kernels on `stream` only (capturable in a HIP
+ * graph, a fixed number of sweeps: 2 for FP64, 4 for MIXED_FP32).
+ * Otherwise instances run largest first on a pool of library-owned streams
+ * (default priority) that fork from and join back into `stream`, each as the
+ * single-instance calls.  With host_sync 1 the return code is the most severe
+ * instance code and the message names the first failing instance (an
+ * instance that fails does not stop the others); with host_sync 0 the status
+ * is left in stats->counters.  Validation of every instance precedes any
+ * device work.
  */
 size_t infoesrf_batched_workspace_bytes(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
                                         const infoesrf_opts* opts, const infoesrf_lattice* lattices);
+/* 1 when infoesrf_update_batched takes the one-launch path for these arguments, else 0 (also
+ * for invalid arguments).  Host only. */
+int infoesrf_batched_one_launch(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
+                                const infoesrf_opts* opts, const infoesrf_lattice* lattices);
 int infoesrf_update_batched(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
                             const double* const* s_nodes, const double* const* p_weights,
                             const double* const* y, double* const* mean_a, double* const* Xa_pert,
@@ -348,31 +362,33 @@ const char* infoesrf_last_error(void);
 /*
  * Learned warm start (an extension of the method; the paper starts every
  * system from zero).  A 1-D convolutional network over the m observation rows
- * (3 -> H -> H -> H -> 1 channels, odd kernel width K <= 15, "same" zero
- * padding, GELU after the first three layers, FP32 parameters) maps the
- * features of system (q, i), with bh = sqrt(m) b_i / ||b_i|| and
- * c = 1 / (1 + s_q),
- *     channel 0: bh c,  channel 1: bh c^2,  channel 2: c
- * (the first two are the leading terms of the Neumann series of C_q^{-1} b,
- * eq. E.1) to u0 = (||b_i|| / sqrt(m)) net(.), the initial guess of
- * C_q u = b_i.  A created network's output layer is zero (it predicts the
- * zero start until trained).  With
- * warm_start = INFOESRF_START_LEARNED and opts->net set, the perturbation
+ * runs once per member: the trunk (1 -> H -> H -> H -> D channels, D = 4, odd
+ * kernel width K <= 15, "same" zero padding, GELU after the first three
+ * layers, FP32 parameters) maps bh_i = sqrt(m) b_i / ||b_i|| to Y_i (D x m).
+ * The shift enters last: system (q, i), c_q = 1 / (1 + s_q), starts from
+ *     u0 = (||b_i|| / sqrt(m)) sum_d c_q^(d+1) Y_i[d]
+ * (the Neumann series of C_q^{-1} b = sum_d c^(d+1) (-S)^d b has this form,
+ * eq. E.1), so the convolutions cost N, not Q N, passes per update.  A created
+ * network's output layer is zero (it predicts the zero start until trained).
+ * With warm_start = INFOESRF_START_LEARNED and opts->net set, the perturbation
  * update starts every system from u0; a system whose u0 is not finite starts
  * from zero and counters[FALLBACKS] counts it.  The mean system always starts
  * from zero.
  *
  * Handles own device memory (parameters, Adam moments, a gradient buffer),
  * allocated by create/load and released by free; never on the update path.
- * File: little-endian "IENET001", 5 int32 (4, 3, H, K, 1), then the FP32
- * parameters W1 (H x 3 x K) b1 (H) W2 (H x H x K) b2 W3 b3 W4 (1 x H x K) b4 (1).
+ * File: little-endian "IENET002", 5 int32 (4, 1, H, K, D), then the FP32
+ * parameters W1 (H x 1 x K) b1 (H) W2 (H x H x K) b2 W3 b3 W4 (D x H x K) b4 (D).
  *
- * Batches: X is B x 3 x m, Y and targets T are B x m, FP32 row-contiguous
- * device arrays; workspaces from infoesrf_net_workspace_bytes (training != 0
- * keeps every activation for the backward pass).  The loss is the batch mean
- * of ||Y_b - T_b|| / ||T_b|| (T = sqrt(m) u* / ||b|| for exact solutions u*), written
- * to the device float *loss; gradients have the parameter layout; a training
- * step is one Adam update (beta1 0.9, beta2 0.999, eps 1e-8).
+ * Batches (FP32, row-contiguous device arrays): X is B x m (the members' bh),
+ * Y is B x D x m (the trunk output); training adds cq, the Q values
+ * c_q = 1 / (1 + s_q) shared by the batch, and targets T, B x Q x m
+ * (T[b, q] = sqrt(m) u*_{q,b} / ||b_b|| for exact solutions u*).  Workspaces
+ * from infoesrf_net_workspace_bytes (training != 0 keeps every activation for
+ * the backward pass; Q is read only then).  The loss is the mean over the B Q
+ * systems of ||y - T|| / ||T|| with y the head's output, written to the device
+ * float *loss; gradients have the parameter layout; a training step is one
+ * Adam update (beta1 0.9, beta2 0.999, eps 1e-8).
  */
 int infoesrf_net_create(int32_t hidden, int32_t kernel, uint64_t seed, void** net);
 int infoesrf_net_load(const char* path, void** net);
@@ -381,31 +397,31 @@ void infoesrf_net_free(void* net);
 int64_t infoesrf_net_param_count(const void* net);
 int infoesrf_net_get_params(const void* net, float* host);        /* host array of param_count */
 int infoesrf_net_set_params(void* net, const float* host);        /* also resets the Adam state */
-size_t infoesrf_net_workspace_bytes(const void* net, int64_t B, int64_t m, int32_t training);
+size_t infoesrf_net_workspace_bytes(const void* net, int64_t B, int64_t Q, int64_t m, int32_t training);
 int infoesrf_net_forward(const void* net, const float* X, int64_t B, int64_t m, float* Y, void* ws,
                          size_t ws_bytes, void* stream);
-/* The same network output with BF16 weights and activations on MFMA (v_mfma_f32_16x16x32_bf16) and
+/* The same trunk output with BF16 weights and activations on MFMA (v_mfma_f32_16x16x32_bf16) and
  * FP32 accumulation, as the learned start runs it by default; needs H <= 64, H % 8 == 0.  Same
  * workspace (training = 0).  The output differs from infoesrf_net_forward by the BF16 rounding of
  * weights and activations (a relative error of order 1e-2). */
 int infoesrf_net_forward_bf16(const void* net, const float* X, int64_t B, int64_t m, float* Y, void* ws,
                               size_t ws_bytes, void* stream);
-int infoesrf_net_gradients(const void* net, const float* X, const float* T, int64_t B, int64_t m,
-                           float* grads, float* loss, void* ws, size_t ws_bytes, void* stream);
-int infoesrf_net_train_step(void* net, const float* X, const float* T, int64_t B, int64_t m, float lr,
-                            float* loss, void* ws, size_t ws_bytes, void* stream);
+int infoesrf_net_gradients(const void* net, const float* X, const float* cq, const float* T, int64_t B, int64_t Q,
+                           int64_t m, float* grads, float* loss, void* ws, size_t ws_bytes, void* stream);
+int infoesrf_net_train_step(void* net, const float* X, const float* cq, const float* T, int64_t B, int64_t Q,
+                            int64_t m, float lr, float* loss, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Training pairs for the warm start: solves the Q N systems of the
  * perturbation update exactly as infoesrf_perturbation_update does (same
- * options; warm_start must be ZERO) and writes, for system s = q N + i,
- * X[s] (3 x m) the network features above and T[s] (m) = sqrt(m) u*_s / ||b_s||, the
- * converged solution scaled like the network output.  X: Q N x 3 x m FP32,
- * T: Q N x m FP32 (device).  y may be NULL (the systems do not depend on it).
- * Workspace: infoesrf_workspace_bytes(prob, Q, opts).
+ * options; warm_start must be ZERO) and writes the network's batch of the N
+ * members: X (N x m) their bh, cq (Q) the shift factors c_q = 1 / (1 + s_q),
+ * and T (N x Q x m) with T[i, q] = sqrt(m) u*_{q,i} / ||b_i||, the converged
+ * solutions scaled like the head's output (FP32, device).  y may be NULL (the
+ * systems do not depend on it).  Workspace: infoesrf_workspace_bytes(prob, Q, opts).
  */
 int infoesrf_warmstart_pairs(const infoesrf_problem* prob, int32_t Q, const double* s_nodes,
-                             const double* p_weights, const double* y, float* X, float* T,
+                             const double* p_weights, const double* y, float* X, float* cq, float* T,
                              const infoesrf_opts* opts, infoesrf_stats* stats, void* ws, size_t ws_bytes,
                              void* stream);
 

@@ -2,27 +2,30 @@
 
 The warm start extends the method (it is not in the paper): a small 1-D
 convolutional network predicts the initial guess of each shifted system
-C_q u = b_i (Appendix E, eq. E.1), C_q = (1 + s_q) I + S, from three input
-channels over the m observation rows, with bh = sqrt(m) b_i/||b_i|| (unit
-root-mean-square entries):
-    bh/(1+s_q), bh/(1+s_q)^2 and 1/(1+s_q),
-the first two being the leading terms of the Neumann series
-u = sum_k (-S)^k b / (1+s)^(k+1) (so a network that acts as a convolution
-like S reproduces its first-order truncation), and the prediction is
-u0 = (||b_i|| / sqrt(m)) net(.), so u0 scales with b_i.  Training targets are
-u* sqrt(m) / ||b_i||.
+C_q u = b_i (Appendix E, eq. E.1), C_q = (1 + s_q) I + S, over the m
+observation rows.  The shift enters only at the end, so the convolutions run
+once per member i, not once per system (q, i):
+  * trunk, per member: the input channel bh_i = sqrt(m) b_i / ||b_i|| (unit
+    root-mean-square entries) through 1 -> H -> H -> H -> D channels, GELU
+    after the first three layers, gives Y_i (D x m);
+  * head, per system: with c_q = 1 / (1 + s_q),
+        y_{q,i} = sum_d c_q^(d+1) Y_i[d],   u0_{q,i} = (||b_i|| / sqrt(m)) y_{q,i}.
+    The Neumann series u = sum_d c^(d+1) (-S)^d b (valid for c ||S|| < 1) has
+    this form with Y_i[d] = (-S)^d bh_i, so D channels can hold a truncation
+    of it, or any other shift profile the training data favour; u0 scales
+    with b_i.  Training targets are u* sqrt(m) / ||b_i||.
 
 Its arithmetic is standard and is written out here from the definitions:
   * cross-correlation with zero "same" padding:
         y[o, t] = bias[o] + sum_c sum_k W[o, c, k] x[c, t + k - K//2];
   * GELU(x) = x Phi(x), Phi the standard normal CDF (Hendrycks & Gimpel);
-  * relative L2 loss, mean over the batch of ||y_b - t_b|| / ||t_b||;
+  * relative L2 loss, mean over the systems of ||y - t|| / ||t||;
   * Adam (Kingma & Ba, Algorithm 1) with bias-corrected moments.
-Layers: 3 -> H -> H -> H -> 1 channels, kernel K, GELU after the first three.
 
 Parity: every function is pinned in tests/test_warmstart_pins.py (SciPy's
-correlate, the normal CDF, central finite differences, Adam's first step in
-closed form, the scaling of the prediction).
+correlate, the normal CDF, central finite differences through the trunk, the
+head and the loss, Adam's first step in closed form, the scaling of the
+prediction, the exact start at S = 0 and the truncated Neumann series).
 """
 from __future__ import annotations
 
@@ -73,7 +76,7 @@ def gelu_grad(x):
     return Phi + x * phi
 
 
-def init_params(channels=(3, 64, 64, 64, 1), K=9, seed=0):
+def init_params(channels=(1, 64, 64, 64, 4), K=9, seed=0):
     """He-style uniform weights, zero biases (for CPU experiments; the library has its own)."""
     rng = np.random.default_rng(seed)
     params = []
@@ -84,7 +87,7 @@ def init_params(channels=(3, 64, 64, 64, 1), K=9, seed=0):
 
 
 def forward(params, X):
-    """Network output (B, Cout_last, m) and the pre-activations needed by backward."""
+    """Trunk output (B, D, m) of member inputs X (B, 1, m) and the pre-activations backward needs."""
     cache = []
     a = X
     for li, (W, b) in enumerate(params):
@@ -95,7 +98,7 @@ def forward(params, X):
 
 
 def backward(params, cache, gout):
-    """Gradients (gW, gb) per layer of the loss whose gradient w.r.t. the output is gout."""
+    """Gradients (gW, gb) per layer of the loss whose gradient w.r.t. the trunk output is gout."""
     grads = [None] * len(params)
     g = gout
     for li in range(len(params) - 1, -1, -1):
@@ -109,44 +112,59 @@ def backward(params, cache, gout):
     return grads
 
 
-def features(b, s):
-    """Network input (B, 3, m) of systems with right-hand sides b (B, m) and shifts s (B,)."""
+def member_features(b):
+    """Trunk input (B, 1, m) of members with right-hand sides b (B, m): bh = sqrt(m) b / ||b||."""
     b = np.atleast_2d(np.asarray(b, dtype=np.float64))
-    B, m = b.shape
-    bh = np.sqrt(m) * b / np.linalg.norm(b, axis=1)[:, None]
+    m = b.shape[1]
+    return (np.sqrt(m) * b / np.linalg.norm(b, axis=1)[:, None])[:, None, :]
+
+
+def shift_basis(s, D):
+    """phi (Q, D): phi[q, d] = c_q^(d+1), c_q = 1 / (1 + s_q)."""
     c = 1.0 / (1.0 + np.asarray(s, dtype=np.float64))
-    X = np.empty((B, 3, m))
-    X[:, 0, :] = bh * c[:, None]
-    X[:, 1, :] = bh * (c * c)[:, None]
-    X[:, 2, :] = c[:, None]
-    return X
+    return np.stack([c ** (d + 1) for d in range(D)], axis=1)
+
+
+def head(Y, phi):
+    """Per-system outputs y (B, Q, m) = sum_d phi[q, d] Y[b, d] of trunk outputs Y (B, D, m)."""
+    return np.einsum("qd,bdt->bqt", phi, Y)
+
+
+def head_grad(gy, phi):
+    """Gradient w.r.t. the trunk output Y (B, D, m) given dL/dy = gy (B, Q, m)."""
+    return np.einsum("qd,bqt->bdt", phi, gy)
 
 
 def predict(params, b, s):
-    """Warm starts u0 = (||b|| / sqrt(m)) net(features) (B, m)."""
+    """Warm starts u0 (B, Q, m) of members with right-hand sides b (B, m) at the shifts s (Q,)."""
     b = np.atleast_2d(np.asarray(b, dtype=np.float64))
-    Y, _ = forward(params, features(b, s))
-    return (np.linalg.norm(b, axis=1) / np.sqrt(b.shape[1]))[:, None] * Y[:, 0, :]
+    Y, _ = forward(params, member_features(b))
+    y = head(Y, shift_basis(s, Y.shape[1]))
+    return (np.linalg.norm(b, axis=1) / np.sqrt(b.shape[1]))[:, None, None] * y
 
 
 def targets(u, b):
-    """Training targets u* sqrt(m) / ||b|| (B, m) of exact solutions u (B, m)."""
+    """Training targets u* sqrt(m) / ||b|| of exact solutions u (B, Q, m) for members b (B, m)."""
     b = np.atleast_2d(np.asarray(b, dtype=np.float64))
-    return np.sqrt(b.shape[1]) * np.atleast_2d(u) / np.linalg.norm(b, axis=1)[:, None]
+    return np.sqrt(b.shape[1]) * np.asarray(u) / np.linalg.norm(b, axis=1)[:, None, None]
 
 
 def loss_rel_l2(Y, T):
-    """mean_b ||Y_b - T_b|| / ||T_b|| over rows of (B, m) arrays, and its gradient w.r.t. Y."""
+    """mean over rows of ||Y_r - T_r|| / ||T_r|| for arrays (..., m) (every leading index a row),
+    and its gradient w.r.t. Y."""
     Y = np.asarray(Y, dtype=np.float64)
     T = np.asarray(T, dtype=np.float64)
-    B = Y.shape[0]
-    diff = Y - T
+    shape = Y.shape
+    Y2 = Y.reshape(-1, shape[-1])
+    T2 = T.reshape(-1, shape[-1])
+    B = Y2.shape[0]
+    diff = Y2 - T2
     dn = np.linalg.norm(diff, axis=1)
-    tn = np.linalg.norm(T, axis=1)
+    tn = np.linalg.norm(T2, axis=1)
     loss = float(np.mean(dn / tn))
     with np.errstate(invalid="ignore", divide="ignore"):
         g = np.where(dn[:, None] > 0, diff / (dn * tn)[:, None], 0.0) / B
-    return loss, g
+    return loss, g.reshape(shape)
 
 
 def adam_step(params, grads, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -171,48 +171,55 @@ __global__ void k_zero_counters(int32_t* __restrict__ iters, int32_t* __restrict
 // Sweep bookkeeping from true residual norms (iterative refinement).
 //   fdone: 1 converged (rn <= rtol bn), 2 failed (iteration cap or non-finite), 0 needs work.
 //   done (inner PCG status) = fdone ? 1 : 0; thresh = absolute inner target.
-// Network features of systems s0 .. s0 + cnt (see infoesrf.h): with bh = sqrt(m) b_s / ||b_s||
-// and c = 1 / (1 + sigma_s), X[(s - s0)] = (bh c, bh c^2, c), the first two being the leading
-// terms of the Neumann series of C_q^{-1} b.  b system-major (ld).
-__global__ void k_net_features(const double* __restrict__ b, int64_t ld, const double* __restrict__ bn,
-                               const double* __restrict__ sigma, int64_t m, int64_t s0, int64_t cnt,
-                               float* __restrict__ X) {
+// The trunk's inputs of the members (see infoesrf.h): X[i * m + r] = sqrt(m) b_i[r] / ||b_i||, with
+// member i's right-hand side in system i (node 0) of the system-major b (ld).
+__global__ void k_member_features(const double* __restrict__ b, int64_t ld, const double* __restrict__ bn, int64_t m,
+                                  int64_t N, float* __restrict__ X) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= cnt * m) return;
-  const int64_t j = t / m, r = t % m, s = s0 + j;
-  const double nb = bn[s];
-  const double c = 1.0 / (1.0 + sigma[s]);
-  const double bh = nb > 0.0 ? sqrt((double)m) * b[s * ld + r] / nb : 0.0;
-  float* x = X + j * 3 * m;
-  x[r] = (float)(bh * c);
-  x[m + r] = (float)(bh * c * c);
-  x[2 * m + r] = (float)c;
+  if (t >= N * m) return;
+  const int64_t i = t / m, r = t % m;
+  const double nb = bn[i];
+  X[t] = nb > 0.0 ? (float)(sqrt((double)m) * b[i * ld + r] / nb) : 0.f;
 }
 
-// u_s = (||b_s|| / sqrt(m)) Y_s for systems s0 .. s0 + cnt (one block each); a system whose
-// prediction is not finite starts from zero and is counted in *fallbacks.
-__global__ __launch_bounds__(256) void k_warm_init(const float* __restrict__ Y, const double* __restrict__ bn,
-                                                   int64_t m, int64_t s0, double* __restrict__ u, int64_t ld,
-                                                   int32_t* __restrict__ fallbacks) {
+// The shift head: system s = q N + i starts from u_s = (||b_s|| / sqrt(m)) sum_d c^(d+1) Y_i[d],
+// c = 1 / (1 + sigma_s), Y (N x D x m) the trunk's outputs; a system whose start is not finite
+// starts from zero and is counted in *fallbacks.  One block per system.
+__global__ __launch_bounds__(256) void k_head_init(const float* __restrict__ Y, int D, int64_t m, int64_t N,
+                                                   const double* __restrict__ sigma, const double* __restrict__ bn,
+                                                   double* __restrict__ u, int64_t ld, int32_t* __restrict__ fallbacks) {
   __shared__ int bad;
-  const int64_t s = s0 + blockIdx.x;
-  const float* y = Y + (int64_t)blockIdx.x * m;
+  const int64_t s = blockIdx.x, i = s % N;
+  const double c = 1.0 / (1.0 + sigma[s]);
+  const float* y = Y + i * D * m;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
-  for (int64_t r = threadIdx.x; r < m; r += 256)
-    if (!isfinite(y[r])) bad = 1;
-  __syncthreads();
   const double sc = bn[s] / sqrt((double)m);
-  for (int64_t r = threadIdx.x; r < m; r += 256) u[s * ld + r] = bad ? 0.0 : sc * (double)y[r];
-  if (bad && threadIdx.x == 0) atomicAdd(fallbacks, 1);
+  for (int64_t r = threadIdx.x; r < m; r += 256) {
+    double v = 0.0, p = c;
+    for (int d = 0; d < D; ++d) {
+      v += p * (double)y[d * m + r];
+      p *= c;
+    }
+    if (!isfinite(v)) bad = 1;
+    u[s * ld + r] = sc * v;
+  }
+  __syncthreads();
+  if (bad) {
+    for (int64_t r = threadIdx.x; r < m; r += 256) u[s * ld + r] = 0.0;
+    if (threadIdx.x == 0) atomicAdd(fallbacks, 1);
+  }
 }
 
-// Training targets T[s, r] = sqrt(m) u_s[r] / ||b_s|| (FP32).
-__global__ void k_net_targets(const double* __restrict__ u, int64_t ld, const double* __restrict__ bn, int64_t m,
-                              int64_t S, float* __restrict__ T) {
+// Training pairs of the Q N systems s = q N + i: cq[q] = 1 / (1 + sigma_{q N}) and
+// T[(i Q + q) m + r] = sqrt(m) u_s[r] / ||b_s|| (FP32).
+__global__ void k_net_targets(const double* __restrict__ u, int64_t ld, const double* __restrict__ bn,
+                              const double* __restrict__ sigma, int64_t m, int64_t N, int Q, float* __restrict__ cq,
+                              float* __restrict__ T) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= S * m) return;
-  const int64_t s = t / m, r = t % m;
+  if (t < Q) cq[t] = (float)(1.0 / (1.0 + sigma[t * N]));
+  if (t >= (int64_t)Q * N * m) return;
+  const int64_t r = t % m, iq = t / m, i = iq / Q, q = iq % Q, s = q * N + i;
   const double nb = bn[s];
   T[t] = nb > 0.0 ? (float)(sqrt((double)m) * u[s * ld + r] / nb) : 0.f;
 }
@@ -441,11 +448,11 @@ struct Inst {
   // for MIXED_FP32 inner applies in that domain, an FP32 copy
   bool band = false;
   void *bandS = nullptr, *bandS32 = nullptr, *bandO = nullptr, *bandO32 = nullptr;
-  // learned warm start: network buffers for a chunk of systems (features, outputs, the network's
+  // learned warm start: network buffers for the members (inputs, trunk outputs, the network's
   // own workspace)
   const Net* net = nullptr;
   bool warm_fp32 = false;  // FP32 inference instead of BF16 on MFMA
-  int64_t wchunk = 0;
+  int64_t wmem = 0;        // members the trunk runs on
   float *wX = nullptr, *wY = nullptr;
   void* wnet = nullptr;
   size_t wnet_bytes = 0;
@@ -709,10 +716,10 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
   if (op.warm == INFOESRF_START_LEARNED && S > 1) {
     in.net = static_cast<const Net*>(op.net);
     in.warm_fp32 = op.warm_fp32;
-    in.wchunk = std::min<int64_t>(S, 128);
-    in.wX = ar.take<float>(in.wchunk * 3 * in.m);
-    in.wY = ar.take<float>(in.wchunk * in.m);
-    in.wnet_bytes = net_ws_bytes(*in.net, in.wchunk, in.m, false);
+    in.wmem = std::min<int64_t>(S, in.N);
+    in.wX = ar.take<float>(in.wmem * in.m);
+    in.wY = ar.take<float>(in.wmem * in.net->D * in.m);
+    in.wnet_bytes = net_ws_bytes(*in.net, in.wmem, 1, in.m, false);
     in.wnet = ar.take<char>((int64_t)in.wnet_bytes);
   }
 
@@ -1191,22 +1198,19 @@ class LivePoll {
   int head_ = 0, pending_ = 0;
 };
 
-// Learned warm start: u = ||b|| net(features of b and sigma) for every system, in chunks of
-// in.wchunk systems (non-finite predictions fall back to zero).  Needs sy.bnorm.
+// Learned warm start: the trunk once per member, then the shift head for every system
+// (non-finite starts fall back to zero).  Needs sy.bnorm and sy.sigma.
 int stage_warm(Plan& pl, hipStream_t st) {
   Inst& in = pl.in;
   Sys& sy = pl.sy;
-  for (int64_t s0 = 0; s0 < sy.S; s0 += in.wchunk) {
-    const int64_t cnt = std::min<int64_t>(in.wchunk, sy.S - s0);
-    hipLaunchKernelGGL(k_net_features, dim3(nb(cnt * in.m)), dim3(256), 0, st, sy.b, sy.ldm, sy.bnorm, sy.sigma,
-                       in.m, s0, cnt, in.wX);
-    IE_HIP(hipGetLastError());
-    if (in.warm_fp32) IE_TRY(net_forward(*in.net, in.wX, cnt, in.m, in.wY, in.wnet, in.wnet_bytes, st));
-    else IE_TRY(net_forward_bf16(*in.net, in.wX, cnt, in.m, in.wY, in.wnet, in.wnet_bytes, st));
-    hipLaunchKernelGGL(k_warm_init, dim3((unsigned)cnt), dim3(256), 0, st, in.wY, sy.bnorm, in.m, s0, sy.u, sy.ldm,
-                       in.fallbacks);
-    IE_HIP(hipGetLastError());
-  }
+  hipLaunchKernelGGL(k_member_features, dim3(nb(in.wmem * in.m)), dim3(256), 0, st, sy.b, sy.ldm, sy.bnorm, in.m,
+                     in.wmem, in.wX);
+  IE_HIP(hipGetLastError());
+  if (in.warm_fp32) IE_TRY(net_forward(*in.net, in.wX, in.wmem, in.m, in.wY, in.wnet, in.wnet_bytes, st));
+  else IE_TRY(net_forward_bf16(*in.net, in.wX, in.wmem, in.m, in.wY, in.wnet, in.wnet_bytes, st));
+  hipLaunchKernelGGL(k_head_init, dim3((unsigned)sy.S), dim3(256), 0, st, in.wY, in.net->D, in.m, in.wmem, sy.sigma,
+                     sy.bnorm, sy.u, sy.ldm, in.fallbacks);
+  IE_HIP(hipGetLastError());
   return 0;
 }
 
@@ -1377,18 +1381,13 @@ struct Finalize {
 // only for the event, so the output overlaps the wait and the call can return while it runs;
 // *finalized tells whether the last check did this with the final u (then host_stage() holds
 // the call's counters), else the caller runs both once more.
-int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin = nullptr,
-                bool* finalized = nullptr) {
-  Inst& in = pl.in;
+// The PCG state of a plan's systems.
+PCGState pcg_state_of(Plan& pl, const Options& op) {
   Sys& sy = pl.sy;
-  const int64_t S = sy.S, ldm = sy.ldm, m = in.m;
-  const int64_t flat = S * ldm;
-  const LMP lmp = lmp_of(pl);
-  const bool fp64_inner = (op.inner == Prec::F64);
   PCGState ps{};
-  ps.m = m;
-  ps.S = S;
-  ps.ld = ldm;
+  ps.m = pl.in.m;
+  ps.S = sy.S;
+  ps.ld = sy.ldm;
   ps.x = sy.x;
   ps.r = sy.r;
   ps.p = sy.p;
@@ -1399,18 +1398,62 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
   ps.relres = sy.rel_in;
   ps.iters = sy.iters;
   ps.done = sy.done;
-  ps.flags = in.flags;
+  ps.flags = pl.in.flags;
   ps.max_iter = op.max_iter;
+  return ps;
+}
+
+// The persistent kernel's in-place apply of S for a plan: the explicit band on the observed
+// lattice or the dense S, in FP64 and, for FP32 inner applies, also in FP32 (false for other
+// inner precisions, other forms, or a lattice or LDS layout the kernel does not take).  Pointers
+// are those of the plan's workspace.
+bool tail_inplace(const Plan& pl, const Options& op, TailApply& tap) {
+  const Inst& in = pl.in;
+  if (op.inner != Prec::F64 && op.inner != Prec::F32) return false;
+  if (!in.sd && !(in.obs && in.band)) return false;
+  if (in.m > 4096) return false;
+  tap = TailApply{};
+  tap.kind = in.sd ? 1 : 0;
+  tap.g = in.go;
+  tap.band = static_cast<const double*>(in.bandO);
+  tap.ldb = ld64(in.m);
+  tap.S = in.Sd;
+  tap.lds = in.lds;
+  tap.m = in.m;
+  tap.low = op.inner == Prec::F32 ? 1 : 0;
+  tap.band32 = static_cast<const float*>(in.bandO32);
+  tap.S32 = in.Sd32;
+  return tail_fits(tap);
+}
+
+// The zero start of every system of a plan in one launch: the norms of b, u = 0, the per-system
+// counters and the first sweep's status (the residual is b itself).
+int solve_start(Plan& pl, const Options& op, hipStream_t st) {
+  Sys& sy = pl.sy;
+  hipLaunchKernelGGL(k_solve_start, dim3((unsigned)sy.Spad), dim3(256), 0, st, sy.b, pl.in.m, sy.ldm, sy.S, sy.bnorm,
+                     sy.u, sy.iters, sy.sweeps, sy.fdone, sy.app_adj, op.rtol, op.inner_rtol,
+                     op.inner == Prec::F64 ? 1 : 0, op.max_iter, op.fixed > 0 ? 1 : 0, sy.relres, sy.done,
+                     sy.thresh, pl.in.flags);
+  IE_HIP(hipGetLastError());
+  return 0;
+}
+
+int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin = nullptr,
+                bool* finalized = nullptr) {
+  Inst& in = pl.in;
+  Sys& sy = pl.sy;
+  const int64_t S = sy.S, ldm = sy.ldm, m = in.m;
+  const int64_t flat = S * ldm;
+  const LMP lmp = lmp_of(pl);
+  const bool fp64_inner = (op.inner == Prec::F64);
+  const PCGState ps = pcg_state_of(pl, op);
 
   const bool warm = in.net != nullptr;
   // a zero start forms the norms of b, u = 0, the counters and the first sweep's status in one
   // launch; a learned start first needs the network's u
   const bool fused_start = !warm;
   if (fused_start) {
-    hipLaunchKernelGGL(k_solve_start, dim3((unsigned)sy.Spad), dim3(256), 0, st, sy.b, m, ldm, S, sy.bnorm, sy.u,
-                       sy.iters, sy.sweeps, sy.fdone, sy.app_adj, op.rtol, op.inner_rtol, fp64_inner ? 1 : 0,
-                       op.max_iter, op.fixed > 0 ? 1 : 0, sy.relres, sy.done, sy.thresh, in.flags);
-    IE_HIP(hipGetLastError());
+    IE_TRY(solve_start(pl, op, st));
   } else {
     IE_HIP(launch_col_norms(sy.b, m, S, ldm, sy.bnorm, st));
     IE_HIP(launch_fill_f64(sy.u, 0.0, flat, st));
@@ -1429,22 +1472,14 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
   const bool plain = (op.solver == INFOESRF_SOLVER_PLAIN);
   const bool od = in.odom();
   void* Vbuf = od ? pl.bf.V : nullptr;
-  // the persistent PCG: FP64 inner PCG whose applies it can do in place (each workgroup reads
-  // the whole band or S once per iteration, so only those that stay in the L2 of every XCD
-  // qualify: at most 1 MiB)
+  // the persistent PCG: FP64 or FP32 inner PCG whose applies it can do in place (each workgroup
+  // reads the whole band or S once per iteration, so only those that stay in the L2 of every XCD
+  // qualify: at most 1 MiB in the iterations' precision)
+  const double elem = op.inner == Prec::F32 ? 4.0 : 8.0;
   const double tail_bytes =
-      in.sd ? 8.0 * in.m * in.m : 8.0 * in.m * (2 * in.go.bz + 1) * (2 * in.go.bx + 1);
+      in.sd ? elem * in.m * in.m : elem * in.m * (2 * in.go.bz + 1) * (2 * in.go.bx + 1);
   TailApply tap{};
-  tap.kind = in.sd ? 1 : 0;
-  tap.g = in.go;
-  tap.band = static_cast<const double*>(in.bandO);
-  tap.ldb = ld64(in.m);
-  tap.S = in.Sd;
-  tap.lds = in.lds;
-  tap.m = in.m;
-  const bool tail_ok = op.tail > 0 && fp64_inner && !plain && in.m <= 4096 &&
-                       ((in.obs && in.band && in.bandO) || (in.sd && in.Sd)) && tail_bytes <= 1024.0 * 1024 &&
-                       tail_fits(tap);
+  const bool tail_ok = op.tail > 0 && !plain && tail_inplace(pl, op, tap) && tail_bytes <= 1024.0 * 1024;
   // the queue hands out the live systems node by node, smallest shift (the longest solves) first;
   // the perturbation systems share a shift per group of N members, the mean solve is one system
   const int64_t grp = (S % in.N == 0 && S / in.N <= 4096) ? in.N : S;
@@ -1455,7 +1490,7 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
   // residual and status
   const bool persist = tail_ok && S <= op.tail && !msc && !bcg;
   TailCheck chk{};
-  if (persist) chk = TailCheck{sy.b, sy.fdone, sy.sweeps, sy.relres, op.rtol, op.fixed > 0 ? 1 : 0};
+  if (persist) chk = TailCheck{sy.b, sy.fdone, sy.sweeps, sy.relres, op.rtol, op.fixed > 0 ? 1 : 0, op.inner_rtol};
   auto run_tail = [&](int32_t* list, int32_t* count, int64_t bound, const double* r0) -> int {
     IE_HIP(launch_order_live(sy.done, sy.sigma, S, grp, list, count, sy.qctr, st));
     IE_HIP(pcg_tail_timed(ps, lmp, tap, list, count, sy.qctr, bound, r0, r0 ? sy.u : nullptr,
@@ -1776,6 +1811,265 @@ int perturbation_solve(const infoesrf_problem* prob, int32_t Q, const double* s_
   IE_TRY(stage_precond(pl, op, st));
   IE_TRY(stage_solve(pl, op, st, fin, finalized));
   return 0;
+}
+
+// ------------------------------------------------------------------ batched instances, one launch
+// Every instance's systems (Q N perturbation systems and, when its mean is wanted, the mean system
+// at shift 0, all in one plan) in one persistent launch per sweep (Sec. 3.2: the (q, i) systems are
+// independent).  Set-up per instance on the caller's stream, then per sweep the queue over every
+// instance's live systems and the launch, then per instance the quadrature sum, the final update
+// and the counters.  Taken when every instance's inner solve can run in the persistent kernel.
+
+// Workspace of one instance on this path (its mean system included).
+size_t combined_ws_bytes(const infoesrf_problem* P, int32_t Q, const infoesrf_opts* o) {
+  Options op;
+  if (check_problem(P) < 0 || resolve_options(P, o, op) < 0) return 0;
+  if (Q < 1 || Q > kMaxQ) return 0;
+  Plan pl;
+  if (plan_for(pl, P, op, (int64_t)Q * P->N + 1, P->N + 1, nullptr, 0) < 0) return 0;
+  return pl.bytes;
+}
+
+// Whether every instance qualifies: the compacted PCG solver from a zero start, the persistent
+// kernel allowed (tail_systems >= 0), FP64 or FP32 inner applies done in place, m <= 4096, and one
+// preconditioner size for all.
+bool batch_one_launch(const infoesrf_problem* probs, int count, const int32_t* Q,
+                      const std::vector<infoesrf_opts>& oj) {
+  int p = -1;
+  for (int j = 0; j < count; ++j) {
+    const infoesrf_opts& o = oj[j];
+    if (o.solver != INFOESRF_SOLVER_COMPACT || o.warm_start != INFOESRF_START_ZERO || o.tail_systems < 0)
+      return false;
+    Options op;
+    if (check_problem(&probs[j]) < 0 || resolve_options(&probs[j], &o, op) < 0) return false;
+    if (Q[j] < 1 || Q[j] > kMaxQ || (int64_t)Q[j] * probs[j].N + 1 >= (int64_t(1) << kTailSysBits)) return false;
+    Plan pl;
+    if (plan_for(pl, &probs[j], op, (int64_t)Q[j] * probs[j].N + 1, probs[j].N + 1, nullptr, 0) < 0) return false;
+    TailApply tap;
+    if (!tail_inplace(pl, op, tap)) return false;
+    if (p >= 0 && op.p != p) return false;
+    p = op.p;
+  }
+  clear_error();
+  return true;
+}
+
+// Batch-level arrays after the instances' slices: descriptors, queue scratch and the summed
+// counters.
+struct BatchArea {
+  TailInst* table;
+  int32_t *seg, *list, *cnt, *words;  // words: live count, queue counter, live total
+  int64_t* total;                     // summed counters
+  size_t bytes;
+};
+BatchArea batch_area(char* base, int count, int64_t systems) {
+  Arena ar;
+  ar.base = base;
+  BatchArea b{};
+  b.table = ar.take<TailInst>(count);
+  b.seg = ar.take<int32_t>(systems);
+  b.list = ar.take<int32_t>(systems);
+  b.cnt = ar.take<int32_t>(count);
+  b.words = ar.take<int32_t>(8);
+  b.total = ar.take<int64_t>(INFOESRF_NUM_COUNTERS);
+  b.bytes = ar.off + 256;
+  return b;
+}
+
+// The message of a status code from the device counters.
+std::string status_message(int code, int64_t not_converged) {
+  if (code == INFOESRF_ERR_NOT_SPD) return "PCG curvature p^T C p <= 0: localized covariance not PSD";
+  if (code == INFOESRF_ERR_NUMERIC) return "non-finite value met during the solve";
+  if (code < 0) return "invalid input detected on the device (observation operator, r_var or X)";
+  if (code == INFOESRF_WARN_NOT_CONVERGED) return std::to_string(not_converged) + " system(s) did not reach rtol";
+  return "";
+}
+
+int batched_one_launch(const infoesrf_problem* probs, int count, const int32_t* Q, const double* const* s_nodes,
+                       const double* const* p_weights, const double* const* y, double* const* mean_a,
+                       double* const* Xa_pert, std::vector<infoesrf_opts>& oj, infoesrf_stats* stats, char* base,
+                       const std::vector<size_t>& off, const std::vector<int64_t>& sys_off, int64_t* cnt,
+                       const BatchArea& ba, const std::vector<int>& order, bool host_sync, hipStream_t st) {
+  std::vector<Plan> pl(count);
+  std::vector<Options> op(count);
+  std::vector<TailInst> desc(count);
+  std::vector<char> mean(count, 0);
+  std::vector<int> codes(count, 0);
+  std::vector<std::string> msgs(count);
+  int64_t seg = 0;
+  // one instance's set-up on stream ss, without host reads (inputs that fail the device's checks
+  // set its flags, reported through its counters); an instance that fails on the host is left
+  // out of the launches and reported
+  auto setup = [&](int j, hipStream_t ss) -> int {
+    const infoesrf_problem* P = &probs[j];
+    const int64_t N = P->N, QN = (int64_t)Q[j] * N;
+    mean[j] = (mean_a && mean_a[j]) ? 1 : 0;
+    const int64_t S = QN + mean[j];
+    IE_TRY(resolve_options(P, &oj[j], op[j]));
+    op[j].host_sync = 0;
+    IE_TRY(plan_for(pl[j], P, op[j], S, N + mean[j], base + off[j], off[j + 1] - off[j]));
+    Nodes nd{};
+    for (int q = 0; q < Q[j]; ++q) {
+      IE_CHECK(std::isfinite(s_nodes[j][q]) && s_nodes[j][q] >= 0.0 && std::isfinite(p_weights[j][q]) &&
+                   p_weights[j][q] >= 0.0,
+               INFOESRF_ERR_INVALID_ARG, "quadrature nodes and weights must be >= 0");
+      nd.s[q] = s_nodes[j][q];
+      nd.p[q] = p_weights[j][q];
+    }
+    Plan& p = pl[j];
+    Sys& sy = p.sy;
+    IE_TRY(stage_setup(p, op[j], ss));
+    IE_HIP(launch_obs_rhs_padded(P->h_ptr, P->h_idx, P->h_w, P->r_var, p.in.Z, p.in.n, N, p.in.m, sy.b, sy.ldm, QN,
+                                 sy.Spad, ss));
+    if (mean[j])
+      IE_HIP(launch_innovation(P->h_ptr, P->h_idx, P->h_w, P->r_var, y[j], p.in.mu, p.in.m, p.in.n, sy.b, sy.ldm, QN,
+                               ss));
+    hipLaunchKernelGGL(k_set_nodes, dim3(nb(std::max<int64_t>(sy.Spad, kMaxQ))), dim3(256), 0, ss, nd, Q[j], N,
+                       sy.sigma, sy.pw, (int64_t)mean[j], 0.0, sy.Spad);
+    IE_HIP(hipGetLastError());
+    IE_TRY(stage_precond(p, op[j], ss));
+    IE_TRY(solve_start(p, op[j], ss));
+    TailInst& d = desc[j];
+    d.st = pcg_state_of(p, op[j]);
+    d.lmp = lmp_of(p);
+    IE_CHECK(tail_inplace(p, op[j], d.ap), INFOESRF_ERR_INVALID_ARG, "no in-place apply for the persistent kernel");
+    d.chk = TailCheck{sy.b, sy.fdone, sy.sweeps, sy.relres, op[j].rtol, op[j].fixed > 0 ? 1 : 0, op[j].inner_rtol};
+    d.r0 = sy.b;  // the first sweep's residual (zero start)
+    d.uacc = sy.u;
+    d.grp = (int32_t)N;
+    return 0;
+  };
+  // the set-ups fork from `st` over the worker streams and join back (capture safe)
+  int dev = 0;
+  IE_HIP(hipGetDevice(&dev));
+  struct Events {
+    std::vector<hipEvent_t> e;
+    ~Events() {
+      for (auto x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  const int nw = std::min<int>(WorkerPool::kWorkers, count);
+  ev.e.assign(1 + nw, nullptr);
+  for (auto& x : ev.e) IE_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+  IE_HIP(hipEventRecord(ev.e[0], st));
+  std::vector<hipStream_t> ws(nw);
+  for (int w = 0; w < nw; ++w) {
+    IE_HIP(WorkerPool::worker_stream(dev, w, &ws[w]));
+    IE_HIP(hipStreamWaitEvent(ws[w], ev.e[0], 0));
+  }
+  std::vector<int> live;  // instances in the launches, largest first
+  for (int k = 0; k < count; ++k) {
+    const int j = order[k];
+    codes[j] = setup(j, ws[k % nw]);
+    if (codes[j] < 0) msgs[j] = g_last_error;
+    else live.push_back(j);
+  }
+  for (int w = 0; w < nw; ++w) {
+    IE_HIP(hipEventRecord(ev.e[1 + w], ws[w]));
+    IE_HIP(hipStreamWaitEvent(st, ev.e[1 + w], 0));
+  }
+  // one launch per shape of the kernel (rows a thread, from m): the larger instances first, each
+  // class with its slice of the table, the queue's scratch and its counters
+  std::vector<int> big, small;
+  for (int j : live) (probs[j].m > 1024 ? big : small).push_back(j);
+  std::vector<std::vector<int>> classes;
+  if (!big.empty()) classes.push_back(big);
+  if (!small.empty()) classes.push_back(small);
+  const int nl = (int)live.size();
+  // the sweeps: each launch iterates every live system to its inner target, adds the correction
+  // into u and checks the true FP64 residual; a later sweep restarts from that residual
+  if (nl > 0) {
+    const Options& o0 = op[live[0]];
+    const int max_sweeps = o0.fixed > 0 ? 1 : (host_sync ? 40 : (o0.inner == Prec::F64 ? 2 : 4));
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+      int t0 = 0;
+      int64_t s0 = 0;
+      for (size_t c = 0; c < classes.size(); ++c) {
+        const std::vector<int>& cl = classes[c];
+        std::vector<TailInst> ordered(cl.size());
+        int64_t segc = 0;
+        for (size_t k = 0; k < cl.size(); ++k) {
+          ordered[k] = desc[cl[k]];
+          ordered[k].seg = segc;
+          segc += ordered[k].st.S;
+          if (sweep > 0) ordered[k].r0 = pl[cl[k]].sy.r;
+        }
+        // the launch writes the table, builds the queue (live systems instance by instance,
+        // largest first) and iterates
+        IE_HIP(launch_pcg_tail_multi(ordered.data(), (int)cl.size(), ba.table + t0, ba.seg + s0, ba.cnt + t0,
+                                     ba.list + s0, ba.words + 2 * c, ba.words + 2 * c + 1, segc, st));
+        t0 += (int)cl.size();
+        s0 += segc;
+      }
+      if (host_sync && sweep + 1 < max_sweeps) {
+        HostStage* hs = host_stage();
+        hipEvent_t he = host_event();
+        IE_CHECK(hs && he, INFOESRF_ERR_HIP, "pinned host staging or event creation failed");
+        IE_HIP(launch_batch_live_total(ba.table, nl, ba.words + 4, st));
+        IE_HIP(hipMemcpyAsync(&hs->nact, ba.words + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        IE_HIP(hipEventRecord(he, st));
+        IE_HIP(hipEventSynchronize(he));
+        if (hs->nact == 0) break;
+      }
+    }
+  }
+  // per instance: u_bar_i = sum_q p_q u_{q,i} (and the mean's u as column N), the final updates
+  // and the counters
+  for (int k = 0; k < nl; ++k) {
+    const int j = live[k];
+    Plan& p = pl[j];
+    Sys& sy = p.sy;
+    const int64_t N = probs[j].N, QN = (int64_t)Q[j] * N;
+    IE_HIP(launch_quad_combine(sy.u, sy.ldm, p.in.m, N, Q[j], sy.pw, p.fn.ubar, sy.ldm, 0, p.fn.act, p.fn.nact, st));
+    if (mean[j]) {
+      IE_HIP(launch_copy_cols(sy.u + QN * sy.ldm, sy.ldm, p.in.m, 1, p.fn.ubar + N * sy.ldm, sy.ldm, st));
+      IE_HIP(launch_iota(p.fn.act, p.fn.nact, N + 1, st));
+    }
+    IE_TRY(apply_state(p, p.fn.ubar, sy.ldm, p.fn.act, p.fn.nact, N + mean[j], op[j].rows_per_wave, st));
+    IE_HIP(launch_final_pert(p.in.Z, (const double*)p.bf.T, ld64(p.in.n), p.in.n, N, std::sqrt((double)(N - 1)),
+                             Xa_pert[j], st));
+    if (mean[j]) IE_HIP(launch_final_mean(p.in.mu, (const double*)p.bf.T, ld64(p.in.n), p.in.n, N, mean_a[j], st));
+    infoesrf_stats sj{};
+    if (stats) {
+      sj.iters = stats->iters ? stats->iters + sys_off[j] : nullptr;
+      sj.relres = stats->relres ? stats->relres + sys_off[j] : nullptr;
+      sj.converged = stats->converged ? stats->converged + sys_off[j] : nullptr;
+    }
+    sj.counters = cnt + (int64_t)(2 * j) * INFOESRF_NUM_COUNTERS;
+    IE_TRY(finish_enqueue(p, op[j], &sj, 2 * p.pr.k + N + mean[j], st));
+  }
+  hipLaunchKernelGGL(k_sum_counters, dim3(1), dim3(64), 0, st, cnt, 2 * count, ba.total);
+  IE_HIP(hipGetLastError());
+  if (stats && stats->counters)
+    IE_HIP(hipMemcpyAsync(stats->counters, ba.total, sizeof(int64_t) * INFOESRF_NUM_COUNTERS,
+                          hipMemcpyDeviceToDevice, st));
+  if (!host_sync) {
+    for (int j = 0; j < count; ++j)
+      if (codes[j] < 0) {
+        set_error("instance " + std::to_string(j) + ": " + msgs[j]);
+        return codes[j];
+      }
+    return 0;
+  }
+  // the instances' own counters name the first that failed on the device
+  std::vector<int64_t> blocks((size_t)2 * count * INFOESRF_NUM_COUNTERS);
+  int64_t tot[INFOESRF_NUM_COUNTERS];
+  IE_HIP(hipMemcpyAsync(blocks.data(), cnt, sizeof(int64_t) * blocks.size(), hipMemcpyDeviceToHost, st));
+  IE_HIP(hipMemcpyAsync(tot, ba.total, sizeof(tot), hipMemcpyDeviceToHost, st));
+  IE_HIP(hipStreamSynchronize(st));
+  for (int j = 0; j < count; ++j) {
+    const int64_t* bj = blocks.data() + (size_t)2 * j * INFOESRF_NUM_COUNTERS;
+    const int cj = codes[j] < 0 ? codes[j] : (int)bj[INFOESRF_CNT_STATUS];
+    if (cj < 0) {
+      set_error("instance " + std::to_string(j) + ": " +
+                (codes[j] < 0 ? msgs[j] : status_message(cj, bj[INFOESRF_CNT_NOT_CONVERGED])));
+      return cj;
+    }
+  }
+  const int code = (int)tot[INFOESRF_CNT_STATUS];
+  if (code != 0) set_error(status_message(code, tot[INFOESRF_CNT_NOT_CONVERGED]));
+  return code;
 }
 
 }  // namespace
@@ -2162,11 +2456,11 @@ int infoesrf_autotune(const infoesrf_problem* prob, int32_t Q, const infoesrf_op
 void infoesrf_autotune_reset(void) { tune_reset(); }
 
 int infoesrf_warmstart_pairs(const infoesrf_problem* prob, int32_t Q, const double* s_nodes,
-                             const double* p_weights, const double* y, float* X, float* T,
+                             const double* p_weights, const double* y, float* X, float* cq, float* T,
                              const infoesrf_opts* opts, infoesrf_stats* stats, void* ws, size_t ws_bytes,
                              void* stream) {
   clear_error();
-  IE_CHECK(X && T, INFOESRF_ERR_INVALID_ARG, "X and T must be non-NULL");
+  IE_CHECK(X && cq && T, INFOESRF_ERR_INVALID_ARG, "X, cq and T must be non-NULL");
   IE_CHECK(!opts || opts->warm_start == INFOESRF_START_ZERO, INFOESRF_ERR_INVALID_ARG,
            "training pairs are solved from the zero start");
   Plan pl;
@@ -2175,12 +2469,27 @@ int infoesrf_warmstart_pairs(const infoesrf_problem* prob, int32_t Q, const doub
   IE_TRY(perturbation_solve(prob, Q, s_nodes, p_weights, y, opts, pl, op, ws, ws_bytes, st));
   Inst& in = pl.in;
   Sys& sy = pl.sy;
-  hipLaunchKernelGGL(k_net_features, dim3(nb(sy.S * in.m)), dim3(256), 0, st, sy.b, sy.ldm, sy.bnorm, sy.sigma,
-                     in.m, (int64_t)0, sy.S, X);
+  hipLaunchKernelGGL(k_member_features, dim3(nb(in.N * in.m)), dim3(256), 0, st, sy.b, sy.ldm, sy.bnorm, in.m, in.N,
+                     X);
   IE_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_net_targets, dim3(nb(sy.S * in.m)), dim3(256), 0, st, sy.u, sy.ldm, sy.bnorm, in.m, sy.S, T);
+  hipLaunchKernelGGL(k_net_targets, dim3(nb(std::max<int64_t>(sy.S * in.m, Q))), dim3(256), 0, st, sy.u, sy.ldm,
+                     sy.bnorm, sy.sigma, in.m, in.N, Q, cq, T);
   IE_HIP(hipGetLastError());
   return finish_status(pl, op, stats, 2 * pl.pr.k, st);
+}
+
+int infoesrf_batched_one_launch(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
+                                const infoesrf_opts* opts, const infoesrf_lattice* lattices) {
+  clear_error();
+  if (!probs || !Q || count < 1) return 0;
+  infoesrf_opts o;
+  if (opts) o = *opts;
+  else infoesrf_default_opts(&o);
+  if (o.apply_domain == INFOESRF_DOMAIN_OBS_LATTICE && !lattices) return 0;
+  std::vector<infoesrf_opts> oj(count, o);
+  if (o.apply_domain == INFOESRF_DOMAIN_OBS_LATTICE)
+    for (int j = 0; j < count; ++j) oj[j].lattice = lattices[j];
+  return batch_one_launch(probs, count, Q, oj) ? 1 : 0;
 }
 
 size_t infoesrf_batched_workspace_bytes(const infoesrf_problem* probs, int32_t count, const int32_t* Q,
@@ -2197,18 +2506,24 @@ size_t infoesrf_batched_workspace_bytes(const infoesrf_problem* probs, int32_t c
     set_error("the observed-lattice domain needs lattices[count]");
     return 0;
   }
+  std::vector<infoesrf_opts> oj(count, o);
+  if (o.apply_domain == INFOESRF_DOMAIN_OBS_LATTICE)
+    for (int j = 0; j < count; ++j) oj[j].lattice = lattices[j];
+  const bool one = batch_one_launch(probs, count, Q, oj);
   size_t total = 0;
+  int64_t systems = 0;
   for (int j = 0; j < count; ++j) {
-    if (o.apply_domain == INFOESRF_DOMAIN_OBS_LATTICE) o.lattice = lattices[j];
-    const size_t b = instance_ws_bytes(&probs[j], Q[j], true, &o);
+    const size_t b = one ? combined_ws_bytes(&probs[j], Q[j], &oj[j]) : instance_ws_bytes(&probs[j], Q[j], true, &oj[j]);
     if (b == 0) {
       set_error("instance " + std::to_string(j) + ": " + g_last_error);
       return 0;
     }
     total += (b + 255) / 256 * 256;
+    systems += (int64_t)Q[j] * probs[j].N + 1;
   }
-  // two counter blocks per instance (perturbation and mean calls)
+  // two counter blocks per instance (perturbation and mean), and for one launch the batch arrays
   total += (size_t)2 * count * INFOESRF_NUM_COUNTERS * sizeof(int64_t) + 256;
+  if (one) total += batch_area(nullptr, count, systems).bytes;
   return total;
 }
 
@@ -2226,22 +2541,28 @@ int infoesrf_update_batched(const infoesrf_problem* probs, int32_t count, const 
   else infoesrf_default_opts(&o);
   const bool per_lattice = o.apply_domain == INFOESRF_DOMAIN_OBS_LATTICE;
   IE_CHECK(!per_lattice || lattices, INFOESRF_ERR_INVALID_ARG, "the observed-lattice domain needs lattices[count]");
-  // concurrent instances share the GPU: the persistent kernel by default only finishes each
-  // instance's last 64 systems
-  if (o.tail_systems == 0) o.tail_systems = 64;
   std::vector<infoesrf_opts> oj(count, o);
   if (per_lattice)
     for (int j = 0; j < count; ++j) oj[j].lattice = lattices[j];
-  // per-instance workspace slices and system offsets (validates every instance first)
-  std::vector<size_t> off(count + 1, 0);
-  std::vector<int64_t> sys_off(count + 1, 0);
+  // every instance's systems in one persistent launch per sweep when each can run there;
+  // otherwise a call per instance over a pool of streams, where the persistent kernel by default
+  // only finishes each instance's last 64 systems (concurrent instances share the GPU)
   for (int j = 0; j < count; ++j) {
     const bool want_mean = mean_a && mean_a[j];
     IE_CHECK(!want_mean || (y && y[j]), INFOESRF_ERR_INVALID_ARG,
              "instance " + std::to_string(j) + ": the mean update needs y");
     IE_CHECK(Xa_pert[j] && s_nodes[j] && p_weights[j], INFOESRF_ERR_INVALID_ARG,
              "instance " + std::to_string(j) + ": s_nodes, p_weights and Xa_pert must be non-NULL");
-    const size_t b = instance_ws_bytes(&probs[j], Q[j], want_mean, &oj[j]);
+  }
+  const bool one = batch_one_launch(probs, count, Q, oj);
+  if (!one && o.tail_systems == 0)
+    for (int j = 0; j < count; ++j) oj[j].tail_systems = 64;
+  // per-instance workspace slices and system offsets (validates every instance first)
+  std::vector<size_t> off(count + 1, 0);
+  std::vector<int64_t> sys_off(count + 1, 0);
+  for (int j = 0; j < count; ++j) {
+    const bool want_mean = mean_a && mean_a[j];
+    const size_t b = one ? combined_ws_bytes(&probs[j], Q[j], &oj[j]) : instance_ws_bytes(&probs[j], Q[j], want_mean, &oj[j]);
     if (b == 0) {
       set_error("instance " + std::to_string(j) + ": " + g_last_error);
       return INFOESRF_ERR_INVALID_ARG;
@@ -2250,7 +2571,8 @@ int infoesrf_update_batched(const infoesrf_problem* probs, int32_t count, const 
     sys_off[j + 1] = sys_off[j] + (int64_t)Q[j] * probs[j].N + 1;
   }
   const size_t cnt_bytes = (size_t)2 * count * INFOESRF_NUM_COUNTERS * sizeof(int64_t);
-  const size_t need = off[count] + cnt_bytes + 256;
+  const size_t area = one ? batch_area(nullptr, count, sys_off[count]).bytes : 0;
+  const size_t need = off[count] + cnt_bytes + area + 256;
   IE_CHECK(ws_bytes >= need, INFOESRF_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
   char* base = static_cast<char*>(ws);
   int64_t* cnt = reinterpret_cast<int64_t*>(base + off[count]);
@@ -2268,6 +2590,11 @@ int infoesrf_update_batched(const infoesrf_problem* probs, int32_t count, const 
     return (double)Q[j] * P.N * (double)P.m * P.N * (2.0 * P.loc.bx + 1) * (2.0 * P.loc.bz + 1);
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  if (one) {
+    const BatchArea ba = batch_area(base + off[count] + cnt_bytes, count, sys_off[count]);
+    return batched_one_launch(probs, count, Q, s_nodes, p_weights, y, mean_a, Xa_pert, oj, stats, base, off, sys_off,
+                              cnt, ba, order, o.host_sync != 0, st);
+  }
 
   hipEvent_t fork = nullptr;
   IE_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));

@@ -360,6 +360,8 @@ hipError_t launch_bcg_iteration(const BcgState& s, int mode, int it, hipStream_t
 hipError_t launch_bcg_list(const int32_t* bdone, int Q, int64_t N, int32_t* act, int32_t* nact, hipStream_t st);
 // In-place apply of S for the persistent finish: kind 0 = explicit band of P on the observed
 // lattice g (rows = m), kind 1 = dense S (m x m, column-major, lds).
+// low != 0: the PCG iterations apply FP32 copies (band32 or S32, same layout and leading
+// dimension), widened to FP64 as they are read; the residual check applies the FP64 band or S.
 struct TailApply {
   int kind;
   Grid g;
@@ -368,6 +370,9 @@ struct TailApply {
   const double* S;
   int64_t lds;
   int64_t m;
+  int low;
+  const float* band32;
+  const float* S32;
 };
 // Finish the listed systems (act, *nact) with one persistent launch of `grid` workgroups that take
 // systems from the queue counter qctr (zeroed beforehand) and iterate each to convergence, the
@@ -388,6 +393,7 @@ struct TailCheck {
   double* relres;    // true relative residual of the sweep (the PCG state's relres is the inner one)
   double rtol;
   int fixed;
+  double inner_rtol; // FP32 inner applies: the next sweep's inner target relative to the residual
 };
 // r0 and uacc (both given or both null): each system starts from x = 0 with residual r0 (the
 // kernel takes the first step itself) and adds its solution into uacc, then, when chk->b is
@@ -396,6 +402,32 @@ struct TailCheck {
 hipError_t launch_pcg_tail(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
                            const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,
                            const TailCheck& chk, hipStream_t st);
+// One instance of a persistent launch: its PCG state, preconditioner, in-place apply and sweep
+// check, where its solves start (r0) and add their solutions (uacc), the group size of its
+// shifts (systems q grp .. q grp + grp - 1 share one; systems past the last whole group have
+// their own and are taken first) and its segment in the queue builder's scratch.
+struct TailInst {
+  PCGState st;
+  LMP lmp;
+  TailApply ap;
+  TailCheck chk;
+  const double* r0;
+  double* uacc;
+  int64_t seg;
+  int32_t grp;
+  int32_t phi_lds;  // set by the launcher: the Ritz bases staged in LDS
+};
+// A queue entry of a launch over many instances: (instance << kTailSysBits) | system.
+constexpr int kTailSysBits = 20;
+// One persistent launch for the live systems of every instance of descs (host copies, count of
+// them): writes the descriptors into `table` (device, count entries), orders each instance's live
+// systems into its segment of `seg` (sum of the instances' S entries) with its count in cnt
+// (count entries), packs them into `list` (same size as seg) with the total in *nact, and runs
+// them.  All instances share the Ritz-basis count and the iterations' precision; m <= 4096.
+hipError_t launch_pcg_tail_multi(TailInst* descs, int count, TailInst* table, int32_t* seg, int32_t* cnt,
+                                 int32_t* list, int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st);
+// *total = the live systems (done == 0) of the count instances of the device table.
+hipError_t launch_batch_live_total(const TailInst* table, int count, int32_t* total, hipStream_t st);
 // launch_pcg_tail with the measurement hook (profile slot INFOESRF_PROF_TAIL).
 hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
                           const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,

@@ -1,10 +1,10 @@
 // Warm-start network handle: creation, file I/O, inference and training steps.
 //
 // File format (little endian):
-//   8 bytes  magic "IENET001"
-//   5 int32  layers (4), input channels (3), hidden channels H, kernel width K, output channels (1)
-//   float32  parameters in order W1 (H x 3 x K), b1 (H), W2 (H x H x K), b2 (H),
-//            W3 (H x H x K), b3 (H), W4 (1 x H x K), b4 (1)
+//   8 bytes  magic "IENET002"
+//   5 int32  layers (4), input channels (1), hidden channels H, kernel width K, output channels D
+//   float32  parameters in order W1 (H x 1 x K), b1 (H), W2 (H x H x K), b2 (H),
+//            W3 (H x H x K), b3 (H), W4 (D x H x K), b4 (D)
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -15,13 +15,13 @@
 
 namespace infoesrf {
 
-int64_t net_param_count(int H, int K) {
-  return (int64_t)H * 3 * K + H + 2 * ((int64_t)H * H * K + H) + (int64_t)H * K + 1;
+int64_t net_param_count(int H, int K, int D) {
+  return (int64_t)H * 1 * K + H + 2 * ((int64_t)H * H * K + H) + (int64_t)D * H * K + D;
 }
 
 void net_layer(const Net& n, int l, int64_t* w_off, int64_t* b_off, int* cin, int* cout) {
-  const int ci[4] = {3, n.H, n.H, n.H};
-  const int co[4] = {n.H, n.H, n.H, 1};
+  const int ci[4] = {1, n.H, n.H, n.H};
+  const int co[4] = {n.H, n.H, n.H, n.D};
   int64_t off = 0;
   for (int j = 0; j < l; ++j) off += (int64_t)co[j] * ci[j] * n.K + co[j];
   *w_off = off;
@@ -32,10 +32,11 @@ void net_layer(const Net& n, int l, int64_t* w_off, int64_t* b_off, int* cin, in
 
 namespace {
 
-// Training workspace (floats): z1 a1 z2 a2 z3 a3 (B H m each), y gy (B m), per (B), loss (1),
-// two gradient buffers (B H m) and the flipped weights (H H K).  Inference: two (B H m) buffers.
+// Training workspace (floats): z1 a1 z2 a2 z3 a3 (B H m each), the trunk output y and its gradient
+// gy (B D m), per-system errors and gradient factors (B Q each), loss (1), two gradient buffers
+// (B H m) and the flipped weights (H H K).  Inference: two (B H m) buffers.
 struct NetWs {
-  float *z[3], *a[3], *y, *gy, *per, *loss, *g0, *g1, *wt;
+  float *z[3], *a[3], *y, *gy, *per, *scale, *loss, *g0, *g1, *wt;
   float *p0, *p1;                // inference ping-pong (FP32)
   __hip_bfloat16 *q0, *q1;       // inference ping-pong (BF16, position-major)
   __hip_bfloat16* wpk[4];        // packed BF16 weights of the four layers
@@ -43,7 +44,7 @@ struct NetWs {
 
 int64_t al(int64_t n) { return (n + 63) / 64 * 64; }
 
-NetWs carve(const Net& n, int64_t B, int64_t m, bool training, void* ws, size_t* bytes) {
+NetWs carve(const Net& n, int64_t B, int64_t Q, int64_t m, bool training, void* ws, size_t* bytes) {
   NetWs w{};
   float* base = static_cast<float*>(ws);
   int64_t off = 0;
@@ -58,9 +59,10 @@ NetWs carve(const Net& n, int64_t B, int64_t m, bool training, void* ws, size_t*
       w.z[l] = take(act);
       w.a[l] = take(act);
     }
-    w.y = take(B * m);
-    w.gy = take(B * m);
-    w.per = take(B);
+    w.y = take(B * n.D * m);
+    w.gy = take(B * n.D * m);
+    w.per = take(B * Q);
+    w.scale = take(B * Q);
     w.loss = take(1);
     w.g0 = take(act);
     w.g1 = take(act);
@@ -87,6 +89,11 @@ int check_net_io(const Net* n, int64_t B, int64_t m) {
   IE_CHECK(n && n->params, INFOESRF_ERR_INVALID_ARG, "network handle is NULL");
   IE_CHECK(B >= 1 && B <= 65535, INFOESRF_ERR_INVALID_ARG, "batch B must be in [1, 65535]");
   IE_CHECK(m >= 1 && m <= (1 << 24), INFOESRF_ERR_INVALID_ARG, "length m out of range");
+  return 0;
+}
+
+int check_shifts(int64_t B, int64_t Q) {
+  IE_CHECK(Q >= 1 && Q <= 64 && B * Q <= (int64_t)1 << 31, INFOESRF_ERR_INVALID_ARG, "shifts Q must be in [1, 64]");
   return 0;
 }
 
@@ -126,11 +133,13 @@ int forward_layers_bf16(const Net& n, const float* X, int64_t B, int64_t m, cons
   return 0;
 }
 
-// gradients of the mean relative L2 loss into n.grads (and the loss into *loss_dev)
-int gradients(const Net& n, const float* X, const float* T, int64_t B, int64_t m, const NetWs& w, float* grads,
-              float* loss_dev, hipStream_t st) {
+// gradients of the mean relative L2 loss of the B x Q systems (shift factors cq) into grads (and
+// the loss into *loss_dev): the trunk forward, the head's loss and gradient, the trunk backward
+int gradients(const Net& n, const float* X, const float* cq, const float* T, int64_t B, int64_t Q, int64_t m,
+              const NetWs& w, float* grads, float* loss_dev, hipStream_t st) {
   IE_TRY(forward_layers(n, X, B, m, w, true, w.y, st));
-  IE_HIP(launch_rel_l2(w.y, T, (int)m, B, w.gy, w.per, loss_dev ? loss_dev : w.loss, st));
+  IE_HIP(launch_head_loss_grad(w.y, n.D, cq, (int)Q, T, (int)m, B, w.per, w.scale, loss_dev ? loss_dev : w.loss,
+                               w.gy, st));
   const float* g = w.gy;  // gradient w.r.t. layer l's output
   for (int l = 3; l >= 0; --l) {
     int64_t wo, bo;
@@ -177,16 +186,16 @@ void free_state(Net* h) {
 
 }  // namespace
 
-size_t net_ws_bytes(const Net& n, int64_t B, int64_t m, bool training) {
+size_t net_ws_bytes(const Net& n, int64_t B, int64_t Q, int64_t m, bool training) {
   size_t b = 0;
-  (void)carve(n, B, m, training, nullptr, &b);
+  (void)carve(n, B, Q, m, training, nullptr, &b);
   return b;
 }
 
 int net_forward(const Net& n, const float* X, int64_t B, int64_t m, float* Y, void* ws, size_t ws_bytes,
                 hipStream_t st) {
   size_t need = 0;
-  const NetWs w = carve(n, B, m, false, ws, &need);
+  const NetWs w = carve(n, B, 1, m, false, ws, &need);
   IE_CHECK(ws && ws_bytes >= need, INFOESRF_ERR_WORKSPACE, "network workspace too small");
   return forward_layers(n, X, B, m, w, false, Y, st);
 }
@@ -194,7 +203,7 @@ int net_forward(const Net& n, const float* X, int64_t B, int64_t m, float* Y, vo
 int net_forward_bf16(const Net& n, const float* X, int64_t B, int64_t m, float* Y, void* ws, size_t ws_bytes,
                      hipStream_t st) {
   size_t need = 0;
-  const NetWs w = carve(n, B, m, false, ws, &need);
+  const NetWs w = carve(n, B, 1, m, false, ws, &need);
   IE_CHECK(ws && ws_bytes >= need, INFOESRF_ERR_WORKSPACE, "network workspace too small");
   IE_CHECK(n.H <= 64 && n.H % 8 == 0, INFOESRF_ERR_INVALID_ARG, "BF16 inference needs H <= 64, H % 8 == 0");
   return forward_layers_bf16(n, X, B, m, w, Y, st);
@@ -214,7 +223,8 @@ extern "C" int infoesrf_net_create(int32_t hidden, int32_t kernel, uint64_t seed
   Net* h = new Net();
   h->H = hidden;
   h->K = kernel;
-  h->count = net_param_count(hidden, kernel);
+  h->D = kNetD;
+  h->count = net_param_count(hidden, kernel, h->D);
   std::vector<float> host((size_t)h->count, 0.f);
   // uniform(-a, a) weights with a = sqrt(6 / (Cin K)), zero biases; the output layer starts at
   // zero, so an untrained network predicts the zero start
@@ -248,16 +258,16 @@ extern "C" int infoesrf_net_load(const char* path, void** net) {
   IE_CHECK(f != nullptr, INFOESRF_ERR_INVALID_ARG, std::string("cannot open ") + path);
   char magic[8];
   int32_t hdr[5];
-  const bool ok_hdr = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "IENET001", 8) == 0 &&
+  const bool ok_hdr = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "IENET002", 8) == 0 &&
                       std::fread(hdr, sizeof(int32_t), 5, f) == 5;
-  if (!ok_hdr || hdr[0] != 4 || hdr[1] != 3 || hdr[4] != 1 || hdr[2] < 1 || hdr[2] > 256 || hdr[3] < 1 ||
-      hdr[3] > 15 || (hdr[3] % 2) == 0) {
+  if (!ok_hdr || hdr[0] != 4 || hdr[1] != 1 || hdr[4] < 1 || hdr[4] > 16 || hdr[2] < 1 || hdr[2] > 256 ||
+      hdr[3] < 1 || hdr[3] > 15 || (hdr[3] % 2) == 0) {
     std::fclose(f);
     set_error("not a warm-start network file (bad magic or header)");
     return INFOESRF_ERR_INVALID_ARG;
   }
-  const int H = hdr[2], K = hdr[3];
-  const int64_t cnt = net_param_count(H, K);
+  const int H = hdr[2], K = hdr[3], D = hdr[4];
+  const int64_t cnt = net_param_count(H, K, D);
   std::vector<float> host((size_t)cnt);
   const size_t got = std::fread(host.data(), sizeof(float), (size_t)cnt, f);
   std::fclose(f);
@@ -265,6 +275,7 @@ extern "C" int infoesrf_net_load(const char* path, void** net) {
   Net* h = new Net();
   h->H = H;
   h->K = K;
+  h->D = D;
   h->count = cnt;
   if (alloc_state(h) < 0 ||
       hipMemcpy(h->params, host.data(), sizeof(float) * cnt, hipMemcpyHostToDevice) != hipSuccess) {
@@ -285,8 +296,8 @@ extern "C" int infoesrf_net_save(const void* net, const char* path) {
   IE_HIP(hipMemcpy(host.data(), h->params, sizeof(float) * h->count, hipMemcpyDeviceToHost));
   FILE* f = std::fopen(path, "wb");
   IE_CHECK(f != nullptr, INFOESRF_ERR_INVALID_ARG, std::string("cannot write ") + path);
-  const int32_t hdr[5] = {4, 3, h->H, h->K, 1};
-  bool ok = std::fwrite("IENET001", 1, 8, f) == 8 && std::fwrite(hdr, sizeof(int32_t), 5, f) == 5 &&
+  const int32_t hdr[5] = {4, 1, h->H, h->K, h->D};
+  bool ok = std::fwrite("IENET002", 1, 8, f) == 8 && std::fwrite(hdr, sizeof(int32_t), 5, f) == 5 &&
             std::fwrite(host.data(), sizeof(float), host.size(), f) == host.size();
   ok = (std::fclose(f) == 0) && ok;
   IE_CHECK(ok, INFOESRF_ERR_INVALID_ARG, std::string("write failed: ") + path);
@@ -323,10 +334,11 @@ extern "C" int infoesrf_net_set_params(void* net, const float* host) {
   return INFOESRF_OK;
 }
 
-extern "C" size_t infoesrf_net_workspace_bytes(const void* net, int64_t B, int64_t m, int32_t training) {
+extern "C" size_t infoesrf_net_workspace_bytes(const void* net, int64_t B, int64_t Q, int64_t m, int32_t training) {
   clear_error();
   if (check_net_io(static_cast<const Net*>(net), B, m) < 0) return 0;
-  return net_ws_bytes(*static_cast<const Net*>(net), B, m, training != 0);
+  if (training && check_shifts(B, Q) < 0) return 0;
+  return net_ws_bytes(*static_cast<const Net*>(net), B, training ? Q : 1, m, training != 0);
 }
 
 extern "C" int infoesrf_net_forward(const void* net, const float* X, int64_t B, int64_t m, float* Y, void* ws,
@@ -347,30 +359,34 @@ extern "C" int infoesrf_net_forward_bf16(const void* net, const float* X, int64_
   return net_forward_bf16(*h, X, B, m, Y, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
-extern "C" int infoesrf_net_gradients(const void* net, const float* X, const float* T, int64_t B, int64_t m,
-                                      float* grads, float* loss, void* ws, size_t ws_bytes, void* stream) {
+extern "C" int infoesrf_net_gradients(const void* net, const float* X, const float* cq, const float* T, int64_t B,
+                                      int64_t Q, int64_t m, float* grads, float* loss, void* ws, size_t ws_bytes,
+                                      void* stream) {
   clear_error();
   const Net* h = static_cast<const Net*>(net);
   IE_TRY(check_net_io(h, B, m));
-  IE_CHECK(X && T && grads, INFOESRF_ERR_INVALID_ARG, "X, T and grads must be non-NULL");
+  IE_TRY(check_shifts(B, Q));
+  IE_CHECK(X && cq && T && grads, INFOESRF_ERR_INVALID_ARG, "X, cq, T and grads must be non-NULL");
   size_t need = 0;
-  const NetWs w = carve(*h, B, m, true, ws, &need);
+  const NetWs w = carve(*h, B, Q, m, true, ws, &need);
   IE_CHECK(ws && ws_bytes >= need, INFOESRF_ERR_WORKSPACE, "network workspace too small");
-  return gradients(*h, X, T, B, m, w, grads, loss, static_cast<hipStream_t>(stream));
+  return gradients(*h, X, cq, T, B, Q, m, w, grads, loss, static_cast<hipStream_t>(stream));
 }
 
-extern "C" int infoesrf_net_train_step(void* net, const float* X, const float* T, int64_t B, int64_t m, float lr,
-                                       float* loss, void* ws, size_t ws_bytes, void* stream) {
+extern "C" int infoesrf_net_train_step(void* net, const float* X, const float* cq, const float* T, int64_t B,
+                                       int64_t Q, int64_t m, float lr, float* loss, void* ws, size_t ws_bytes,
+                                       void* stream) {
   clear_error();
   Net* h = static_cast<Net*>(net);
   IE_TRY(check_net_io(h, B, m));
-  IE_CHECK(X && T, INFOESRF_ERR_INVALID_ARG, "X and T must be non-NULL");
+  IE_TRY(check_shifts(B, Q));
+  IE_CHECK(X && cq && T, INFOESRF_ERR_INVALID_ARG, "X, cq and T must be non-NULL");
   IE_CHECK(lr > 0.f && std::isfinite(lr), INFOESRF_ERR_INVALID_ARG, "learning rate must be positive");
   size_t need = 0;
-  const NetWs w = carve(*h, B, m, true, ws, &need);
+  const NetWs w = carve(*h, B, Q, m, true, ws, &need);
   IE_CHECK(ws && ws_bytes >= need, INFOESRF_ERR_WORKSPACE, "network workspace too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  IE_TRY(gradients(*h, X, T, B, m, w, h->grads, loss, st));
+  IE_TRY(gradients(*h, X, cq, T, B, Q, m, w, h->grads, loss, st));
   h->step += 1;
   IE_HIP(launch_adam(h->params, h->grads, h->adam_m, h->adam_v, h->count, lr, h->step, st));
   return INFOESRF_OK;

@@ -99,8 +99,8 @@ __global__ void k_pack_weights_bf16(const float* __restrict__ W, int Cout, int C
 // Block: 64 positions x 64 output channels (wavefront w: channels o0 + 16 w .. + 15, four
 // 16-position tiles).  The input window (64 + K - 1 positions x Cp channels) is staged in LDS as
 // BF16, rows padded by 8 channels (16 bytes) against bank conflicts.
-// IN_F32: input (B, Cin, m) FP32, else (B, m, Cp) BF16.  OUT_F32: output (B, m) FP32 (Cout = 1),
-// else (B, m, Cout) BF16.
+// IN_F32: input (B, Cin, m) FP32, else (B, m, Cp) BF16.  OUT_F32: output (B, Cout, m) FP32, else
+// (B, m, Cout) BF16.
 template <bool IN_F32, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_conv_bf16(const void* __restrict__ in, int Cin, int Cp,
                                                    const __hip_bfloat16* __restrict__ Wp, int KD,
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_conv_bf16(const void* __restrict__ in, 
       if (o >= Cout) continue;
       const float z = acc[t][v] + (bias ? bias[o] : 0.f);
       const float y = gelu ? gelu_f(z) : z;
-      if (OUT_F32) static_cast<float*>(out)[b * m + x] = y;
+      if (OUT_F32) static_cast<float*>(out)[(b * Cout + o) * (int64_t)m + x] = y;
       else static_cast<__hip_bfloat16*>(out)[(b * m + x) * (int64_t)Cout + o] = __float2bfloat16(y);
     }
   }
@@ -238,35 +238,6 @@ __global__ void k_gelu_bwd(float* __restrict__ g, const float* __restrict__ z, i
   if (t < n) g[t] *= gelu_grad_f(z[t]);
 }
 
-// Relative L2 loss per sample: per[b] = ||y_b - t_b|| / ||t_b||, and the gradient
-// gy_b = (y_b - t_b) / (||y_b - t_b|| ||t_b|| B).  One block per sample.
-__global__ __launch_bounds__(256) void k_rel_l2(const float* __restrict__ y, const float* __restrict__ t, int m,
-                                                int64_t B, float* __restrict__ gy, float* __restrict__ per) {
-  __shared__ float sd[4], st[4];
-  const int64_t b = blockIdx.x;
-  float dd = 0.f, tt = 0.f;
-  for (int x = threadIdx.x; x < m; x += 256) {
-    const float d = y[b * m + x] - t[b * m + x];
-    dd = fmaf(d, d, dd);
-    tt = fmaf(t[b * m + x], t[b * m + x], tt);
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    dd += __shfl_xor(dd, off, 64);
-    tt += __shfl_xor(tt, off, 64);
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    sd[wave] = dd;
-    st[wave] = tt;
-  }
-  __syncthreads();
-  const float dn = sqrtf(((sd[0] + sd[1]) + sd[2]) + sd[3]);
-  const float tn = sqrtf(((st[0] + st[1]) + st[2]) + st[3]);
-  const float scale = (dn > 0.f && tn > 0.f) ? 1.0f / (dn * tn * (float)B) : 0.f;
-  for (int x = threadIdx.x; x < m; x += 256) gy[b * m + x] = (y[b * m + x] - t[b * m + x]) * scale;
-  if (threadIdx.x == 0) per[b] = tn > 0.f ? dn / tn : 0.f;
-}
-
 // mean of B values in one block (fixed order)
 __global__ void k_mean(const float* __restrict__ v, int64_t B, float* __restrict__ out) {
   __shared__ float s[256];
@@ -293,6 +264,73 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   mo[t] = m1;
   ve[t] = v1;
   p[t] -= lr * (m1 * c1) / (sqrtf(v1 * c2) + eps);
+}
+
+// The shift head (per system (b, q) of a batch of B members x Q shifts, c_q = 1 / (1 + s_q)):
+// y_{b,q} = sum_d c_q^(d+1) Y[b, d] over the trunk output Y (B, D, m).
+__device__ inline float head_value(const float* __restrict__ Y, int64_t b, int D, int m, int x, float c) {
+  float y = 0.f, p = c;
+  for (int d = 0; d < D; ++d) {
+    y = fmaf(p, Y[(b * D + d) * (int64_t)m + x], y);
+    p *= c;
+  }
+  return y;
+}
+
+// Relative L2 loss of each system against its target T (B, Q, m): per[b Q + q] = ||y - t|| / ||t||
+// and scale[b Q + q] = 1 / (||y - t|| ||t|| B Q), the factor of its gradient.  One block per system.
+__global__ __launch_bounds__(256) void k_head_rel_l2(const float* __restrict__ Y, int D, const float* __restrict__ cq,
+                                                     int Q, const float* __restrict__ T, int m, int64_t B,
+                                                     float* __restrict__ per, float* __restrict__ scale) {
+  __shared__ float sd[4], st[4];
+  const int64_t sys = blockIdx.x, b = sys / Q;
+  const float c = cq[sys % Q];
+  float dd = 0.f, tt = 0.f;
+  for (int x = threadIdx.x; x < m; x += 256) {
+    const float tv = T[sys * m + x];
+    const float d = head_value(Y, b, D, m, x, c) - tv;
+    dd = fmaf(d, d, dd);
+    tt = fmaf(tv, tv, tt);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    dd += __shfl_xor(dd, off, 64);
+    tt += __shfl_xor(tt, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sd[wave] = dd;
+    st[wave] = tt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float dn = sqrtf(((sd[0] + sd[1]) + sd[2]) + sd[3]);
+    const float tn = sqrtf(((st[0] + st[1]) + st[2]) + st[3]);
+    scale[sys] = (dn > 0.f && tn > 0.f) ? 1.0f / (dn * tn * (float)(B * Q)) : 0.f;
+    per[sys] = tn > 0.f ? dn / tn : 0.f;
+  }
+}
+
+// Gradient of the mean loss w.r.t. the trunk output: gY[b, d, x] = sum_q c_q^(d+1) scale_{b,q}
+// (y_{b,q}[x] - T_{b,q}[x]).  One thread per (b, x).
+__global__ void k_head_grad(const float* __restrict__ Y, int D, const float* __restrict__ cq, int Q,
+                            const float* __restrict__ T, const float* __restrict__ scale, int m, int64_t B,
+                            float* __restrict__ gY) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= B * m) return;
+  const int64_t b = t / m;
+  const int x = (int)(t % m);
+  float g[16];
+  for (int d = 0; d < D; ++d) g[d] = 0.f;
+  for (int q = 0; q < Q; ++q) {
+    const float c = cq[q];
+    const float r = scale[b * Q + q] * (head_value(Y, b, D, m, x, c) - T[(b * Q + q) * (int64_t)m + x]);
+    float p = c;
+    for (int d = 0; d < D; ++d) {
+      g[d] = fmaf(p, r, g[d]);
+      p *= c;
+    }
+  }
+  for (int d = 0; d < D; ++d) gY[(b * D + d) * (int64_t)m + x] = g[d];
 }
 
 }  // namespace
@@ -335,7 +373,7 @@ hipError_t launch_conv_bf16(const void* in, bool in_f32, int Cin, const __hip_bf
                             int K, int m, int64_t B, void* out, bool out_f32, int gelu, hipStream_t st) {
   if (B <= 0) return hipSuccess;
   if (!in || !Wp || !out || K < 1 || K > 15 || (K % 2) == 0 || Cin > 64 || Cout > 64) return hipErrorInvalidValue;
-  if (out_f32 && Cout != 1) return hipErrorInvalidValue;
+
   if (!in_f32 && bf16_cp(Cin) != Cin) return hipErrorInvalidValue;  // BF16 inputs carry Cp channels
   const int Cp = bf16_cp(Cin), KD = bf16_kd(Cin, K);
   const size_t smem = sizeof(__hip_bfloat16) * (size_t)(64 + K - 1) * (Cp + 8);
@@ -370,12 +408,15 @@ hipError_t launch_gelu_bwd(float* g, const float* z, int64_t n, hipStream_t st) 
   return hipGetLastError();
 }
 
-hipError_t launch_rel_l2(const float* y, const float* t, int m, int64_t B, float* gy, float* per, float* mean,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_rel_l2, dim3((unsigned)B), dim3(256), 0, st, y, t, m, B, gy, per);
+hipError_t launch_head_loss_grad(const float* Y, int D, const float* cq, int Q, const float* T, int m, int64_t B,
+                                 float* per, float* scale, float* mean, float* gY, hipStream_t st) {
+  if (D < 1 || D > 16 || Q < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_head_rel_l2, dim3((unsigned)(B * Q)), dim3(256), 0, st, Y, D, cq, Q, T, m, B, per, scale);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, per, B, mean);
+  hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, st, per, B * Q, mean);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_head_grad, dim3(nb1(B * m)), dim3(256), 0, st, Y, D, cq, Q, T, scale, m, B, gY);
   return hipGetLastError();
 }
 

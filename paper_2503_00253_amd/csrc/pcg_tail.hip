@@ -105,9 +105,10 @@ __device__ inline double tail_ld8(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
 }
 
-// Whether the kernel keeps the thread's rows of the Ritz bases in registers.
+// Whether the kernel keeps the thread's rows of the Ritz bases in registers (2 RPT P doubles):
+// with two rows a thread up to 10 pairs; four rows a thread need their registers for the apply.
 __host__ __device__ constexpr bool tail_caches_ritz(int P, int RPT, int NT) {
-  return P > 0 && RPT * P <= 20 && NT < 1024;
+  return P > 0 && RPT * P <= (RPT > 2 ? 8 : 20) && NT < 1024;
 }
 
 // Rows of a thread: pairs of adjacent rows, 2 (tid + NT jj) + b for jj < RPT / 2, b in {0, 1}, so
@@ -119,6 +120,89 @@ __device__ inline int tail_row(int tid, int j) {
 
 __device__ inline double2 tail_ld16(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+}
+
+// One band (or S) entry of a row pair, widened to FP64: 16 bytes of an FP64 band, 8 of an FP32 one.
+template <typename BT>
+__device__ inline double2 tail_ld_pair(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(BT) == 8) {
+    return tail_ld16(rs, voff, soff);
+  } else {
+    const float2 f = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+    return double2{(double)f.x, (double)f.y};
+  }
+}
+
+// S v for the thread's rows, v being in LDS (the padded lattice, or the whole vector for the
+// dense S): a row of the band is hh stencil rows of ww consecutive entries, both in the band
+// (columns of colA bytes) and in the padded direction; the dense S is one stencil row of m
+// entries.  Each stencil row goes in chunks of CH entries whose loads, for all the thread's row
+// pairs, are issued ahead of their multiply-adds (one load brings the entry of both rows of a
+// pair; uniform column offsets in scalar registers, the pair a per-lane offset), then one chunk
+// for the rest of the row, whose missing entries repeat the last one and are weighted by zero.
+// Entries of an FP32 band are widened and the sums kept in FP64.
+
+template <typename BT, int RPT, int NT, int CH>
+__device__ inline void tail_apply_rows(__amdgpu_buffer_rsrc_t rsA, uint32_t colA, const uint32_t* roff,
+                                       const int* corner, const double* sp, int hh, int ww, int Wp, int64_t m,
+                                       double* qv) {
+  // with two row pairs a thread, pairs whose whole wavefront lies past m are skipped (a uniform
+  // branch; with one pair every wavefront has rows)
+  bool live[RPT / 2];
+#pragma unroll
+  for (int jj = 0; jj < RPT / 2; ++jj)
+    live[jj] = RPT <= 2 || 2 * ((int64_t)(threadIdx.x & ~63) + (int64_t)NT * jj) < m;
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) qv[j] = 0.0;
+  for (int li = 0; li < hh; ++li) {
+    uint32_t so = (uint32_t)(li * ww) * colA;
+    const int lrow = li * Wp;
+    int d0 = 0;
+    for (; d0 + CH <= ww; d0 += CH) {
+      double2 bv[RPT / 2][CH];
+#pragma unroll
+      for (int jj = 0; jj < RPT / 2; ++jj)
+        if (live[jj]) {
+#pragma unroll
+          for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld_pair<BT>(rsA, roff[jj], so + (uint32_t)k * colA);
+        }
+#pragma unroll
+      for (int jj = 0; jj < RPT / 2; ++jj) {
+        if (!live[jj]) continue;
+        const double* p0 = sp + corner[2 * jj] + lrow + d0;
+        const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          qv[2 * jj] += bv[jj][k].x * p0[k];
+          qv[2 * jj + 1] += bv[jj][k].y * p1[k];
+        }
+      }
+      so += (uint32_t)CH * colA;
+    }
+    if (d0 < ww) {
+      const int last = ww - d0 - 1;
+      double2 bv[RPT / 2][CH];
+#pragma unroll
+      for (int jj = 0; jj < RPT / 2; ++jj)
+        if (live[jj]) {
+#pragma unroll
+          for (int k = 0; k < CH; ++k)
+            bv[jj][k] = tail_ld_pair<BT>(rsA, roff[jj], so + (uint32_t)min(k, last) * colA);
+        }
+#pragma unroll
+      for (int jj = 0; jj < RPT / 2; ++jj) {
+        if (!live[jj]) continue;
+        const double* p0 = sp + corner[2 * jj] + lrow + d0;
+        const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int kk = min(k, last);
+          qv[2 * jj] += (k <= last ? bv[jj][k].x : 0.0) * p0[kk];
+          qv[2 * jj + 1] += (k <= last ? bv[jj][k].y : 0.0) * p1[kk];
+        }
+      }
+    }
+  }
 }
 
 // Lane l's value of a double, to every lane.
@@ -157,21 +241,25 @@ __device__ inline bool tail_halo(const Grid& g, int Wp, int t, int& dst, int& sr
   return true;
 }
 
-template <int P, int RPT, int NT>
-__global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply ap,
+// BT: element type of the band (or S) in the PCG iterations (double, or float for FP32 inner
+// applies); the sweep's residual check always applies the FP64 band (or S).  MULTI: the queue
+// holds (instance << kTailSysBits) | system entries over the descriptors in `table` (one launch
+// for many instances); otherwise systems of the one instance `one`.
+template <int P, int RPT, int NT, typename BT, bool MULTI>
+__global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* __restrict__ table,
                                                  const int32_t* __restrict__ act, const int32_t* __restrict__ nact,
-                                                 int32_t* __restrict__ qctr, int phi_lds,
-                                                 const double* __restrict__ r0, double* __restrict__ uacc,
-                                                 TailCheck chk) {
+                                                 int32_t* __restrict__ qctr) {
   constexpr int W = 2 * P + 1;
   constexpr int NW = NT / 64;
   static_assert(RPT % 2 == 0, "rows come in pairs");
-  // band (or S) entries per chunk: RPT / 2 * CH 16-byte loads in flight per thread
-  constexpr int CH = RPT >= 4 ? 8 : 16;
+  // band (or S) entries per chunk: RPT / 2 * CH loads in flight per thread (fewer where the
+  // per-instance values of a launch over many instances take registers)
+  constexpr int CH = RPT >= 4 ? (MULTI ? 4 : 8) : 16;
   // the Ritz vectors of the thread's rows stay in registers when they fit
   constexpr bool kCache = tail_caches_ritz(P, RPT, NT);
   constexpr bool kLdsSums = tail_lds_sums(2 * P + 1, NT);
   constexpr int kC = kCache ? RPT * P : 1;
+  constexpr bool kLow = sizeof(BT) == 4;
   __shared__ double sred1[1][NW];
   __shared__ double sredW[W][NW];
   __shared__ double sG[3 * P * P + P + 1];
@@ -179,161 +267,147 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
   __shared__ double sM[P * P + 1];
   __shared__ double sdot[W];
   __shared__ int s_idx;
-  // padded direction (band) or direction (dense S); then, when phi_lds, the Ritz bases
+  // padded direction (band) or direction (dense S); then the partial sums and, when phi_lds, the
+  // Ritz bases
   extern __shared__ double sp[];
   const int tid = threadIdx.x;
-  const int64_t m = st.m;
-  const bool band = ap.kind == 0;
-  const Grid g = ap.g;
-  const int w = 2 * g.bx + 1, h = 2 * g.bz + 1;
-  const int Wp = band ? g.nx + 2 * g.bx : 0;
-  const int npad = band ? (g.nz + 2 * g.bz) * Wp : (int)m;
-  // halo cells holding wrapped values
-  const int nh = band ? (g.pz ? 2 * g.bz * Wp : 0) + (g.px ? g.nz * 2 * g.bx : 0) : 0;
-  // stencil rows and entries per stencil row of the apply (the dense S: one row of m)
-  const int hh = band ? h : 1, ww = band ? w : (int)m;
-  if (P > 0) {
-    for (int o = tid; o < 3 * P * P; o += NT) sG[o] = lmp.G[o];
-    if (tid < P) sG[3 * P * P + tid] = lmp.theta[tid];
-  }
-  // zeros in the halo along axes that are not periodic (never rewritten)
-  for (int o = tid; o < npad; o += NT) sp[o] = 0.0;
-  const double dmin = (P > 0) ? *lmp.dmin : 0.0;
   const int na = *nact;
-  // descriptors of the band (or S) and the Ritz bases; byte strides of their columns
-  const __amdgpu_buffer_rsrc_t rsA =
-      band ? tail_rsrc(ap.band, (int64_t)h * w * ap.ldb * 8) : tail_rsrc(ap.S, m * ap.lds * 8);
-  const uint32_t colA = (uint32_t)((band ? ap.ldb : ap.lds) * 8);
-  const __amdgpu_buffer_rsrc_t rsF = tail_rsrc(lmp.Phi, (int64_t)P * lmp.ld * 8);
-  const __amdgpu_buffer_rsrc_t rsG = tail_rsrc(lmp.SPhi, (int64_t)P * lmp.ld * 8);
-  const uint32_t colF = (uint32_t)(lmp.ld * 8);
-  double* part = sp + npad;                           // W x NT partial sums
-  double* sF = part + (kLdsSums ? W * NT : 0);        // Phi (P x m), when phi_lds
-  double* sH = sF + (int64_t)P * m;                   // S Phi (P x m)
-  if (phi_lds) {
-    for (int o = tid; o < P * (int)m; o += NT) {
-      const int l = o / (int)m, r = o % (int)m;
-      sF[o] = tail_ld8(rsF, (uint32_t)r * 8, l * colF);
-      sH[o] = tail_ld8(rsG, (uint32_t)r * 8, l * colF);
-    }
-  }
-  // the corner of each row's stencil in the padded grid, and the row's byte offset in a column
+
+  // The instance's values the loop uses, set when the queue reaches a system of another instance
+  // (a single-instance launch sets them once).
+  int cur = -1;
+  int64_t m = 0;
+  bool band = true;
+  Grid g{};
+  int Wp = 0, npad = 0, nh = 0, hh = 1, ww = 1, phi_lds = 0;
+  double dmin = 0.0;
+  __amdgpu_buffer_rsrc_t rsA = tail_rsrc(nullptr, 0), rsI = rsA, rsF = rsA, rsG = rsA;
+  uint32_t colA = 0, colI = 0, colF = 0;
+  double *part = sp, *sF = sp, *sH = sp;
+  // the corner of each row's stencil in the padded grid, and the byte offsets of each row pair in
+  // a column of the FP64 band and of the iterations' band (pairs past m read the last pair and
+  // are discarded; an odd m leaves its last pair one row into the column's padding, ld >= m + 1)
   int corner[RPT];
-  uint32_t roff[RPT / 2];
+  uint32_t roff[RPT / 2], roffI[RPT / 2];
+
+  // the instance's layout, its preconditioner's small matrices, the zero halo of the padded
+  // direction along axes that are not periodic (never rewritten), and its Ritz bases in LDS (the
+  // previous system's last LDS reads are behind the loop's closing barrier)
+  auto load_instance = [&](const TailInst& d) {
+      const PCGState& st = d.st;
+      const TailApply& ap = d.ap;
+      const LMP& lmp = d.lmp;
+      m = st.m;
+      band = ap.kind == 0;
+      g = ap.g;
+      const int w = 2 * g.bx + 1, h = 2 * g.bz + 1;
+      Wp = band ? g.nx + 2 * g.bx : 0;
+      npad = band ? (g.nz + 2 * g.bz) * Wp : (int)m;
+      nh = band ? (g.pz ? 2 * g.bz * Wp : 0) + (g.px ? g.nz * 2 * g.bx : 0) : 0;
+      hh = band ? h : 1;
+      ww = band ? w : (int)m;
+      phi_lds = d.phi_lds;
+      if (P > 0) {
+        for (int o = tid; o < 3 * P * P; o += NT) sG[o] = lmp.G[o];
+        if (tid < P) sG[3 * P * P + tid] = lmp.theta[tid];
+      }
+      for (int o = tid; o < npad; o += NT) sp[o] = 0.0;
+      dmin = (P > 0) ? *lmp.dmin : 0.0;
+      rsA = band ? tail_rsrc(ap.band, (int64_t)h * w * ap.ldb * 8) : tail_rsrc(ap.S, m * ap.lds * 8);
+      colA = (uint32_t)((band ? ap.ldb : ap.lds) * 8);
+      rsI = !kLow ? rsA
+                  : (band ? tail_rsrc(ap.band32, (int64_t)h * w * ap.ldb * 4) : tail_rsrc(ap.S32, m * ap.lds * 4));
+      colI = kLow ? colA / 2 : colA;
+      rsF = tail_rsrc(lmp.Phi, (int64_t)P * lmp.ld * 8);
+      rsG = tail_rsrc(lmp.SPhi, (int64_t)P * lmp.ld * 8);
+      colF = (uint32_t)(lmp.ld * 8);
+      part = sp + npad;                     // W x NT partial sums
+      sF = part + (kLdsSums ? W * NT : 0);  // Phi (P x m), when phi_lds
+      sH = sF + (int64_t)P * m;             // S Phi (P x m)
+      if (phi_lds) {
+        for (int o = tid; o < P * (int)m; o += NT) {
+          const int l = o / (int)m, r = o % (int)m;
+          sF[o] = tail_ld8(rsF, (uint32_t)r * 8, l * colF);
+          sH[o] = tail_ld8(rsG, (uint32_t)r * 8, l * colF);
+        }
+      }
 #pragma unroll
-  for (int j = 0; j < RPT; ++j) {
-    const int r = tail_row<NT>(tid, j);
-    corner[j] = (band && r < m) ? (r / g.nx) * Wp + r % g.nx : 0;
-  }
-  // byte offset of each pair in a column (pairs past m read the last pair and are discarded;
-  // an odd m leaves its last pair one row into the column's padding, ld >= m + 1)
+      for (int jj = 0; jj < RPT; ++jj) {
+        const int r = tail_row<NT>(tid, jj);
+        corner[jj] = (band && r < m) ? (r / g.nx) * Wp + r % g.nx : 0;
+      }
 #pragma unroll
-  for (int jj = 0; jj < RPT / 2; ++jj)
-    roff[jj] = (uint32_t)min<int64_t>(tail_row<NT>(tid, 2 * jj), (m - 1) & ~(int64_t)1) * (uint32_t)sizeof(double);
-  // q = (1 + sigma) v + S v for the thread's rows: v to LDS (and its wrapped copies), then the
-  // band (or S) streamed from L2 against it
-  auto apply_C = [&](const double* v, double sig1, double* qv) {
-    // the direction into LDS, then its wrapped copies
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      const int r = tail_row<NT>(tid, j);
-      if (r < m) sp[band ? corner[j] + g.bz * Wp + g.bx : r] = v[j];
-    }
-    __syncthreads();
-    if (nh > 0) {
-      for (int t = tid; t < nh; t += NT) {
-        int dst, src;
-        if (tail_halo(g, Wp, t, dst, src)) sp[dst] = sp[src];
+      for (int jj = 0; jj < RPT / 2; ++jj) {
+        const uint32_t row = (uint32_t)min<int64_t>(tail_row<NT>(tid, 2 * jj), (m - 1) & ~(int64_t)1);
+        roff[jj] = row * (uint32_t)sizeof(double);
+        roffI[jj] = row * (uint32_t)sizeof(BT);
       }
       __syncthreads();
-    }
-    // q = (1 + sigma) v + S v
-    // A row of the band is h stencil rows of w consecutive entries, both in the band (columns
-    // of colA bytes) and in the padded direction; the dense S is one stencil row of m entries.
-    // Each stencil row goes in chunks of CH entries whose loads, for all the thread's row
-    // pairs, are issued ahead of their multiply-adds (16 bytes a lane: the entry for both rows
-    // of a pair; uniform column offsets in scalar registers, the pair a per-lane offset, the
-    // direction at immediate LDS offsets), then one chunk for the rest of the row, whose
-    // missing entries repeat the last one and are weighted by zero.
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) qv[j] = 0.0;
-    for (int li = 0; li < hh; ++li) {
-      uint32_t so = (uint32_t)(li * ww) * colA;
-      const int lrow = li * Wp;
-      int d0 = 0;
-      for (; d0 + CH <= ww; d0 += CH) {
-        double2 bv[RPT / 2][CH];
-#pragma unroll
-        for (int jj = 0; jj < RPT / 2; ++jj)
-#pragma unroll
-          for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)k * colA);
-#pragma unroll
-        for (int jj = 0; jj < RPT / 2; ++jj) {
-          const double* p0 = sp + corner[2 * jj] + lrow + d0;
-          const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
-#pragma unroll
-          for (int k = 0; k < CH; ++k) {
-            qv[2 * jj] += bv[jj][k].x * p0[k];
-            qv[2 * jj + 1] += bv[jj][k].y * p1[k];
-          }
-        }
-        so += (uint32_t)CH * colA;
-      }
-      if (d0 < ww) {
-        const int last = ww - d0 - 1;
-        double2 bv[RPT / 2][CH];
-#pragma unroll
-        for (int jj = 0; jj < RPT / 2; ++jj)
-#pragma unroll
-          for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)min(k, last) * colA);
-#pragma unroll
-        for (int jj = 0; jj < RPT / 2; ++jj) {
-          const double* p0 = sp + corner[2 * jj] + lrow + d0;
-          const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
-#pragma unroll
-          for (int k = 0; k < CH; ++k) {
-            const int kk = min(k, last);
-            qv[2 * jj] += (k <= last ? bv[jj][k].x : 0.0) * p0[kk];
-            qv[2 * jj + 1] += (k <= last ? bv[jj][k].y : 0.0) * p1[kk];
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) qv[j] += sig1 * v[j];
   };
-  __syncthreads();
+  if (!MULTI) load_instance(one);
+
   for (;;) {
     if (tid == 0) s_idx = atomicAdd(qctr, 1);
     __syncthreads();
     const int idx = s_idx;
     __syncthreads();  // every thread has read s_idx before it is written again
     if (idx >= na) break;
-    const int32_t s = act[idx];
+    const int32_t e = act[idx];
+    const int j = MULTI ? (int)(e >> kTailSysBits) : 0;
+    const int32_t s = MULTI ? (e & ((1 << kTailSysBits) - 1)) : e;
+    const TailInst& d = MULTI ? table[j] : one;
+    const PCGState& st = d.st;
     if (st.done[s] != 0) continue;
+    if (MULTI && j != cur) {
+      cur = j;
+      load_instance(d);
+    }
+    // q = (1 + sigma) v + S v for the thread's rows: v to LDS (and its wrapped copies), then the
+    // band (or S) streamed from L2 against it: the iterations' band, or the FP64 one (fp64)
+    auto apply_C = [&](const double* v, double sig1, double* qv, bool fp64) {
+#pragma unroll
+      for (int jj = 0; jj < RPT; ++jj) {
+        const int r = tail_row<NT>(tid, jj);
+        if (r < m) sp[band ? corner[jj] + g.bz * Wp + g.bx : r] = v[jj];
+      }
+      __syncthreads();
+      if (nh > 0) {
+        for (int t = tid; t < nh; t += NT) {
+          int dst, src;
+          if (tail_halo(g, Wp, t, dst, src)) sp[dst] = sp[src];
+        }
+        __syncthreads();
+      }
+      if (!kLow || fp64) tail_apply_rows<double, RPT, NT, CH>(rsA, colA, roff, corner, sp, hh, ww, Wp, m, qv);
+      else tail_apply_rows<BT, RPT, NT, CH>(rsI, colI, roffI, corner, sp, hh, ww, Wp, m, qv);
+#pragma unroll
+      for (int jj = 0; jj < RPT; ++jj) qv[jj] += sig1 * v[jj];
+    };
     const int64_t base = (int64_t)s * st.ld;
     const double sig1 = 1.0 + st.sigma[s];
     const double bn = st.bnorm[s];
     const double thresh = st.thresh[s];
     // a start (r0 given) takes x = 0 and the residual r0 and begins with the first step's
     // preconditioned residual; a continuation reads x, r, p and r^T z of the batched loop
+    const double* r0 = d.r0;
+    double* uacc = d.uacc;
     const bool start = r0 != nullptr;
     double rz = start ? 0.0 : st.rz[s];
     int it = st.iters[s];
     double rv[RPT], pv[RPT], xv[RPT];
     double ph[kC], sph[kC];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      const int64_t r = tail_row<NT>(tid, j);
+    for (int jj = 0; jj < RPT; ++jj) {
+      const int64_t r = tail_row<NT>(tid, jj);
       const bool ok = r < m;
-      rv[j] = ok ? (start ? r0[base + r] : st.r[base + r]) : 0.0;
-      pv[j] = (ok && !start) ? st.p[base + r] : 0.0;
-      xv[j] = (ok && !start) ? st.x[base + r] : 0.0;
+      rv[jj] = ok ? (start ? r0[base + r] : st.r[base + r]) : 0.0;
+      pv[jj] = (ok && !start) ? st.p[base + r] : 0.0;
+      xv[jj] = (ok && !start) ? st.x[base + r] : 0.0;
       if (kCache) {
 #pragma unroll
         for (int l = 0; l < P; ++l) {
-          ph[(j * P + l) % kC] = ok ? tail_ld8(rsF, (uint32_t)r * 8, l * colF) : 0.0;
-          sph[(j * P + l) % kC] = ok ? tail_ld8(rsG, (uint32_t)r * 8, l * colF) : 0.0;
+          ph[(jj * P + l) % kC] = ok ? tail_ld8(rsF, (uint32_t)r * 8, l * colF) : 0.0;
+          sph[(jj * P + l) % kC] = ok ? tail_ld8(rsG, (uint32_t)r * 8, l * colF) : 0.0;
         }
       }
     }
@@ -354,10 +428,10 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
     for (;;) {
       if (!first) {  // the apply and the step (the first pass of a start only prepares p)
         double qv[RPT];
-        apply_C(pv, sig1, qv);
+        apply_C(pv, sig1, qv, false);
         double pq = 0.0;
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) pq += pv[j] * qv[j];
+        for (int jj = 0; jj < RPT; ++jj) pq += pv[jj] * qv[jj];
         const double tot = tail_sum1<NT>(pq, sred1);
         if (!(tot > 0.0) || !isfinite(tot)) {
           if (tid == 0) atomicOr(st.flags, isfinite(tot) ? kFlagNotSPD : kFlagNumeric);
@@ -366,10 +440,10 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
         }
         const double alpha = rz / tot;
 #pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          if (tail_row<NT>(tid, j) < m) {
-            xv[j] += alpha * pv[j];
-            rv[j] -= alpha * qv[j];
+        for (int jj = 0; jj < RPT; ++jj) {
+          if (tail_row<NT>(tid, jj) < m) {
+            xv[jj] += alpha * pv[jj];
+            rv[jj] -= alpha * qv[jj];
           }
         }
         ++it;
@@ -377,20 +451,20 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
       // dots of r: r^T r, Phi^T r, (S Phi)^T r
       double acc[W];
 #pragma unroll
-      for (int j = 0; j < W; ++j) acc[j] = 0.0;
+      for (int jj = 0; jj < W; ++jj) acc[jj] = 0.0;
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        const int64_t r = tail_row<NT>(tid, j);
+      for (int jj = 0; jj < RPT; ++jj) {
+        const int64_t r = tail_row<NT>(tid, jj);
         if (r < m) {
-          acc[0] += rv[j] * rv[j];
+          acc[0] += rv[jj] * rv[jj];
 #pragma unroll
           for (int l = 0; l < P; ++l) {
-            const double a = kCache ? ph[(j * P + l) % kC]
+            const double a = kCache ? ph[(jj * P + l) % kC]
                                     : (phi_lds ? sF[l * m + r] : tail_ld8(rsF, (uint32_t)r * 8, l * colF));
-            const double b = kCache ? sph[(j * P + l) % kC]
+            const double b = kCache ? sph[(jj * P + l) % kC]
                                     : (phi_lds ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
-            acc[1 + l] += a * rv[j];
-            acc[1 + P + l] += b * rv[j];
+            acc[1 + l] += a * rv[jj];
+            acc[1 + P + l] += b * rv[jj];
           }
         }
       }
@@ -453,19 +527,19 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
       rz = rzn;
       first = false;
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        const int64_t r = tail_row<NT>(tid, j);
+      for (int jj = 0; jj < RPT; ++jj) {
+        const int64_t r = tail_row<NT>(tid, jj);
         if (r < m) {
-          double z = rv[j];
+          double z = rv[jj];
 #pragma unroll
           for (int l = 0; l < P; ++l) {
-            const double a = kCache ? ph[(j * P + l) % kC]
+            const double a = kCache ? ph[(jj * P + l) % kC]
                                     : (phi_lds ? sF[l * m + r] : tail_ld8(rsF, (uint32_t)r * 8, l * colF));
-            const double b = kCache ? sph[(j * P + l) % kC]
+            const double b = kCache ? sph[(jj * P + l) % kC]
                                     : (phi_lds ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
             z -= b * scoef[l] + a * scoef[P + l];
           }
-          pv[j] = z + beta * pv[j];
+          pv[jj] = z + beta * pv[jj];
         }
       }
       // no barrier here: every thread read the LDS direction before the first reduction's
@@ -475,34 +549,35 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
     // batched loop, which adds x
     double un[RPT];
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      const int64_t r = tail_row<NT>(tid, j);
-      un[j] = 0.0;
+    for (int jj = 0; jj < RPT; ++jj) {
+      const int64_t r = tail_row<NT>(tid, jj);
+      un[jj] = 0.0;
       if (r < m) {
         if (start) {
-          un[j] = uacc[base + r] + xv[j];
-          uacc[base + r] = un[j];
+          un[jj] = uacc[base + r] + xv[jj];
+          uacc[base + r] = un[jj];
         } else {
-          st.x[base + r] = xv[j];
-          st.r[base + r] = rv[j];
-          st.p[base + r] = pv[j];
+          st.x[base + r] = xv[jj];
+          st.r[base + r] = rv[jj];
+          st.p[base + r] = pv[jj];
         }
       }
     }
     // the sweep's check of the new u: r = b - (1 + sigma) u - S u in FP64, kept for a further
     // sweep, and the status from ||r|| / ||b|| (every thread has left the loop's last LDS reads
     // behind the reductions' barriers)
+    const TailCheck& chk = d.chk;
     const bool check = start && chk.b != nullptr;
     double rr = 0.0;
     if (check) {
       double qv[RPT];
-      apply_C(un, sig1, qv);
+      apply_C(un, sig1, qv, true);
       double r2 = 0.0;
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        const int64_t r = tail_row<NT>(tid, j);
+      for (int jj = 0; jj < RPT; ++jj) {
+        const int64_t r = tail_row<NT>(tid, jj);
         if (r < m) {
-          const double rt = chk.b[base + r] - qv[j];
+          const double rt = chk.b[base + r] - qv[jj];
           st.r[base + r] = rt;
           r2 += rt * rt;
         }
@@ -538,7 +613,10 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(PCGState st, LMP lmp, TailApply
           st.done[s] = 1;
         } else {
           st.done[s] = 0;
-          st.thresh[s] = chk.fixed ? 0.0 : 0.5 * chk.rtol * bn;
+          // the next sweep's inner target, as the status kernel sets it: rtol ||b|| / 2 for FP64
+          // inner applies, else inner_rtol times the true residual (not below that)
+          const double target = 0.5 * chk.rtol * bn;
+          st.thresh[s] = chk.fixed ? 0.0 : (kLow ? fmax(chk.inner_rtol * rr * bn, target) : target);
         }
       }
     }
@@ -585,10 +663,101 @@ __global__ __launch_bounds__(1024) void k_order_live(const int32_t* __restrict__
   }
 }
 
+// The queue of a launch over many instances, in two kernels.  k_batch_live: one workgroup per
+// instance j orders its live systems (done == 0) as k_order_live does, its systems past the last
+// whole group of grp (systems with their own shift, such as the mean update's) first, into its
+// segment of `seg` (from table[j].seg) and their number into cnt[j].  k_batch_pack: one
+// workgroup packs the segments, instance by instance, into `list` as (j << kTailSysBits) | s,
+// with the total in *nact and the queue counter reset.
+__global__ __launch_bounds__(1024) void k_batch_live(const TailInst* __restrict__ table, int32_t* __restrict__ seg,
+                                                     int32_t* __restrict__ cnt) {
+  __shared__ int32_t perm[kOrderQ];
+  __shared__ int swave[16];
+  __shared__ int total;
+  const int j = blockIdx.x, t = threadIdx.x;
+  const TailInst& d = table[j];
+  const int32_t* done = d.st.done;
+  const double* sigma = d.st.sigma;
+  const int64_t S = d.st.S, G = d.grp;
+  const int64_t Sg = S / G * G;    // systems in whole groups
+  const int Q = (int)(Sg / G);
+  const int64_t extra = S - Sg;    // they go first
+  for (int q = t; q < Q; q += 1024) {
+    const double kq = sigma[(int64_t)q * G];
+    int rank = 0;
+    for (int i = 0; i < Q; ++i) {
+      const double ki = sigma[(int64_t)i * G];
+      rank += (ki < kq || (ki == kq && i < q)) ? 1 : 0;
+    }
+    perm[rank] = q;
+  }
+  __syncthreads();
+  // position u < extra: system Sg + u; else node perm[(u - extra) / G], member (u - extra) % G
+  auto sys_at = [&](int64_t u) -> int64_t {
+    return u < extra ? Sg + u : (int64_t)perm[(u - extra) / G] * G + (u - extra) % G;
+  };
+  const int64_t per = (S + 1023) / 1024;
+  const int64_t a = t * per, b = min<int64_t>(S, a + per);
+  int32_t c = 0;
+  for (int64_t u = a; u < b; ++u) c += (done[sys_at(u)] == 0);
+  int32_t pos = block_exclusive_scan<1024>(c, swave, &total);
+  if (t == 0) cnt[j] = total;
+  int32_t* out = seg + d.seg;
+  for (int64_t u = a; u < b; ++u) {
+    const int64_t sys = sys_at(u);
+    if (done[sys] == 0) out[pos++] = (int32_t)sys;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_batch_pack(const TailInst* __restrict__ table, int count,
+                                                     const int32_t* __restrict__ seg, const int32_t* __restrict__ cnt,
+                                                     int32_t* __restrict__ list, int32_t* __restrict__ nact,
+                                                     int32_t* __restrict__ qctr) {
+  __shared__ int swave[16];
+  __shared__ int total;
+  __shared__ int32_t start;
+  const int t = threadIdx.x;
+  if (t == 0) start = 0;
+  __syncthreads();
+  for (int j0 = 0; j0 < count; j0 += 1024) {
+    const int j = j0 + t;
+    const int32_t c = j < count ? cnt[j] : 0;
+    const int32_t pos = start + block_exclusive_scan<1024>(c, swave, &total);
+    __syncthreads();
+    if (t == 0) start += total;
+    if (j < count) {
+      const int32_t* src = seg + table[j].seg;
+      const int32_t tag = j << kTailSysBits;
+      for (int32_t i = 0; i < c; ++i) list[pos + i] = tag | src[i];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    *nact = start;
+    *qctr = 0;
+  }
+}
+
+// The number of live systems (done == 0) over every instance of the table, into *total.  One
+// workgroup (a fixed summation order).
+__global__ __launch_bounds__(1024) void k_batch_live_total(const TailInst* __restrict__ table, int count,
+                                                           int32_t* __restrict__ total) {
+  __shared__ int swave[16];
+  __shared__ int sum;
+  int32_t c = 0;
+  for (int j = 0; j < count; ++j) {
+    const int32_t* done = table[j].st.done;
+    for (int64_t s = threadIdx.x; s < table[j].st.S; s += 1024) c += done[s] == 0;
+  }
+  block_exclusive_scan<1024>(c, swave, &sum);
+  if (threadIdx.x == 0) *total = sum;
+}
+
 // two rows a thread (one pair) up to 1024 rows, on 128, 256 or 512 threads; four rows on 512 or
 // 1024 threads beyond
 int tail_threads(int64_t m) { return m > 2048 ? 1024 : (m > 512 ? 512 : (m > 256 ? 256 : 128)); }
 
+// the padded direction
 size_t tail_lds_bytes(const TailApply& ap) {
   const int64_t npad = ap.kind == 0 ? (int64_t)(ap.g.nz + 2 * ap.g.bz) * (ap.g.nx + 2 * ap.g.bx) : ap.m;
   return (size_t)npad * sizeof(double);
@@ -598,61 +767,149 @@ size_t tail_lds_bytes(const TailApply& ap) {
 // per CU at the sizes where it needs this much
 constexpr size_t kTailLdsBig = 150 * 1024;
 
-template <int P, int RPT, int NT>
-hipError_t tail_go(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act, const int32_t* nact,
-                   int32_t* qctr, int64_t grid, const double* r0, double* uacc, const TailCheck& chk,
-                   hipStream_t st) {
-  if ((int64_t)RPT * NT < s.m) return hipErrorInvalidValue;  // every row has a thread
-  const void* fn = (const void*)k_pcg_tail<P, RPT, NT>;
-  // the kernel's static LDS (read once per instantiation): static + dynamic stays within the CU's
-  static std::atomic<size_t> stat_lds{~(size_t)0};
-  size_t stat = stat_lds.load();
+// The static LDS of an instantiation (read once).
+hipError_t tail_static_lds(const void* fn, std::atomic<size_t>& cache, size_t* out) {
+  size_t stat = cache.load();
   if (stat == ~(size_t)0) {
     hipFuncAttributes fa{};
     const hipError_t e = hipFuncGetAttributes(&fa, fn);
     if (e != hipSuccess) return e;
     stat = fa.sharedSizeBytes;
-    stat_lds.store(stat);
+    cache.store(stat);
   }
-  size_t lds = tail_lds_bytes(ap);
+  *out = stat;
+  return hipSuccess;
+}
+
+// Dynamic LDS of one instance: the padded direction, the partial sums of the dots and, when the
+// kernel does not keep the Ritz bases in registers and there is room, the bases (sets phi_lds).
+// 0 when the instance does not fit.
+template <int P, int RPT, int NT>
+size_t tail_inst_lds(TailInst& d, size_t stat) {
+  size_t lds = tail_lds_bytes(d.ap);
   if (tail_lds_sums(2 * P + 1, NT)) lds += (size_t)(2 * P + 1) * NT * sizeof(double);
-  if (stat + lds > kTailLdsBig) return hipErrorInvalidValue;
-  // the Ritz bases in LDS when the kernel does not keep them in registers and there is room
-  const size_t phi = (size_t)16 * P * s.m;
-  const int phi_lds = (P > 0 && !tail_caches_ritz(P, RPT, NT) && stat + lds + phi <= kTailLdsBig) ? 1 : 0;
-  if (phi_lds) lds += phi;
+  if (stat + lds > kTailLdsBig) return 0;
+  const size_t phi = (size_t)16 * P * d.st.m;
+  d.phi_lds = (P > 0 && !tail_caches_ritz(P, RPT, NT) && stat + lds + phi <= kTailLdsBig) ? 1 : 0;
+  if (d.phi_lds) lds += phi;
+  return lds;
+}
+
+// Writes descriptors into the device table (kernel arguments carry them: capture safe).
+constexpr int kPutPer = 6;
+struct PutBatch {
+  TailInst d[kPutPer];
+};
+__global__ void k_put_insts(PutBatch b, int cnt, TailInst* __restrict__ dst) {
+  const int i = threadIdx.x;
+  if (i < cnt) dst[i] = b.d[i];
+}
+
+// queue(): enqueues whatever builds the queue (after the table is written)
+template <int P, int RPT, int NT, typename BT, bool MULTI, typename QF>
+hipError_t tail_go(TailInst* descs, int count, TailInst* table, const int32_t* act, const int32_t* nact,
+                   int32_t* qctr, int64_t grid, hipStream_t st, QF& queue) {
+  const void* fn = (const void*)k_pcg_tail<P, RPT, NT, BT, MULTI>;
+  static std::atomic<size_t> stat_cache{~(size_t)0};
+  size_t stat = 0;
+  hipError_t e = tail_static_lds(fn, stat_cache, &stat);
+  if (e != hipSuccess) return e;
+  size_t lds = 0;
+  for (int j = 0; j < count; ++j) {
+    if ((int64_t)RPT * NT < descs[j].st.m) return hipErrorInvalidValue;  // every row has a thread
+    const size_t b = tail_inst_lds<P, RPT, NT>(descs[j], stat);
+    if (b == 0) return hipErrorInvalidValue;
+    lds = std::max(lds, b);
+  }
   // dynamic LDS this instantiation may take (concurrent first calls raise it twice: harmless)
   static std::atomic<size_t> allowed{64 * 1024};
   if (lds > allowed.load()) {
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     allowed.store(lds);
   }
+  if (MULTI) {
+    for (int j0 = 0; j0 < count; j0 += kPutPer) {
+      PutBatch b{};
+      const int cnt = std::min(kPutPer, count - j0);
+      for (int i = 0; i < cnt; ++i) b.d[i] = descs[j0 + i];
+      hipLaunchKernelGGL(k_put_insts, dim3(1), dim3(64), 0, st, b, cnt, table + j0);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  if ((e = queue()) != hipSuccess) return e;
   // no more workgroups than can be resident at once: the others would only find the queue empty
   int dev = 0, per_cu = 0, cus = 0;
-  hipError_t e = hipGetDevice(&dev);
+  e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, lds);
   if (e != hipSuccess) return e;
   const int64_t resident = std::max<int64_t>((int64_t)per_cu * cus, 1);
   const dim3 gdim((unsigned)std::max<int64_t>(std::min(grid, resident), 1)), b(NT);
-  hipLaunchKernelGGL((k_pcg_tail<P, RPT, NT>), gdim, b, lds, st, s, lmp, ap, act, nact, qctr, phi_lds, r0, uacc,
-                     chk);
+  hipLaunchKernelGGL((k_pcg_tail<P, RPT, NT, BT, MULTI>), gdim, b, lds, st, descs[0], MULTI ? table : nullptr, act,
+                     nact, qctr);
   return hipGetLastError();
 }
 
-template <int P>
-hipError_t tail_rows(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act, const int32_t* nact,
-                     int32_t* qctr, int64_t grid, const double* r0, double* uacc, const TailCheck& chk,
-                     hipStream_t st) {
-  const int nt = tail_threads(s.m);
-  const int64_t rpt = (s.m + nt - 1) / nt;
-  if (nt == 128) return tail_go<P, 2, 128>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
-  if (nt == 256) return tail_go<P, 2, 256>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
-  if (nt == 1024) return tail_go<P, 4, 1024>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
-  if (rpt <= 2) return tail_go<P, 2, 512>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
-  if (rpt <= 4) return tail_go<P, 4, 512>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
+template <int P, typename BT, typename QF>
+hipError_t tail_rows(TailInst* descs, int count, TailInst* table, const int32_t* act, const int32_t* nact,
+                     int32_t* qctr, int64_t grid, hipStream_t st, QF& queue) {
+  int64_t m = 0;
+  for (int j = 0; j < count; ++j) m = std::max<int64_t>(m, descs[j].st.m);
+  if (table) {  // many instances: one shape for all, from the largest m
+    if (m <= 1024) return tail_go<P, 2, 512, BT, true>(descs, count, table, act, nact, qctr, grid, st, queue);
+    if (m <= 2048) return tail_go<P, 4, 512, BT, true>(descs, count, table, act, nact, qctr, grid, st, queue);
+    return tail_go<P, 4, 1024, BT, true>(descs, count, table, act, nact, qctr, grid, st, queue);
+  }
+  const int nt = tail_threads(m);
+  const int64_t rpt = (m + nt - 1) / nt;
+  if (nt == 128) return tail_go<P, 2, 128, BT, false>(descs, 1, nullptr, act, nact, qctr, grid, st, queue);
+  if (nt == 256) return tail_go<P, 2, 256, BT, false>(descs, 1, nullptr, act, nact, qctr, grid, st, queue);
+  if (nt == 1024) return tail_go<P, 4, 1024, BT, false>(descs, 1, nullptr, act, nact, qctr, grid, st, queue);
+  if (rpt <= 2) return tail_go<P, 2, 512, BT, false>(descs, 1, nullptr, act, nact, qctr, grid, st, queue);
+  if (rpt <= 4) return tail_go<P, 4, 512, BT, false>(descs, 1, nullptr, act, nact, qctr, grid, st, queue);
   return hipErrorInvalidValue;
+}
+
+template <int P, typename QF>
+hipError_t tail_prec(TailInst* descs, int count, TailInst* table, const int32_t* act, const int32_t* nact,
+                     int32_t* qctr, int64_t grid, hipStream_t st, QF& queue) {
+  if (descs[0].ap.low) return tail_rows<P, float>(descs, count, table, act, nact, qctr, grid, st, queue);
+  return tail_rows<P, double>(descs, count, table, act, nact, qctr, grid, st, queue);
+}
+
+// Checks one instance's descriptor.
+bool tail_inst_ok(const TailInst& d) {
+  const PCGState& s = d.st;
+  const TailApply& ap = d.ap;
+  const LMP& lmp = d.lmp;
+  const TailCheck& chk = d.chk;
+  if (s.m < 1 || s.m > kTailMaxM || s.m != ap.m || !tail_fits(ap) || ((d.r0 == nullptr) != (d.uacc == nullptr)) ||
+      (chk.b && (!d.r0 || !chk.fdone || !chk.sweeps || !chk.relres)))
+    return false;
+  if (ap.kind == 0 && (!ap.band || (ap.low && !ap.band32))) return false;
+  if (ap.kind == 1 && (!ap.S || (ap.low && !ap.S32))) return false;
+  if (lmp.p > 0 && (!lmp.Phi || !lmp.SPhi || !lmp.G || !lmp.theta || !lmp.dmin)) return false;
+  return true;
+}
+
+template <typename QF>
+hipError_t tail_dispatch(TailInst* descs, int count, TailInst* table, const int32_t* act, const int32_t* nact,
+                         int32_t* qctr, int64_t grid, hipStream_t st, QF&& queue) {
+  if (count < 1 || !act || !nact || !qctr || (count > 1 && !table)) return hipErrorInvalidValue;
+  for (int j = 0; j < count; ++j)
+    if (!tail_inst_ok(descs[j]) || descs[j].lmp.p != descs[0].lmp.p || descs[j].ap.low != descs[0].ap.low)
+      return hipErrorInvalidValue;
+  switch (descs[0].lmp.p) {
+    case 0: return tail_prec<0>(descs, count, table, act, nact, qctr, grid, st, queue);
+    case 4: return tail_prec<4>(descs, count, table, act, nact, qctr, grid, st, queue);
+    case 8: return tail_prec<8>(descs, count, table, act, nact, qctr, grid, st, queue);
+    case 10: return tail_prec<10>(descs, count, table, act, nact, qctr, grid, st, queue);
+    case 12: return tail_prec<12>(descs, count, table, act, nact, qctr, grid, st, queue);
+    case 16: return tail_prec<16>(descs, count, table, act, nact, qctr, grid, st, queue);
+    case 20: return tail_prec<20>(descs, count, table, act, nact, qctr, grid, st, queue);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -679,22 +936,38 @@ hipError_t launch_order_live(const int32_t* done, const double* sigma, int64_t S
 hipError_t launch_pcg_tail(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
                            const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,
                            const TailCheck& chk, hipStream_t st) {
-  if (s.m < 1 || s.m > kTailMaxM || s.m != ap.m || !act || !nact || !qctr || !tail_fits(ap) ||
-      ((r0 == nullptr) != (uacc == nullptr)) || (chk.b && (!r0 || !chk.fdone || !chk.sweeps || !chk.relres)))
+  TailInst d{};
+  d.st = s;
+  d.lmp = lmp;
+  d.ap = ap;
+  d.chk = chk;
+  d.r0 = r0;
+  d.uacc = uacc;
+  return tail_dispatch(&d, 1, nullptr, act, nact, qctr, grid, st, []() { return hipSuccess; });
+}
+
+hipError_t launch_batch_live_total(const TailInst* table, int count, int32_t* total, hipStream_t st) {
+  if (!table || !total || count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_batch_live_total, dim3(1), dim3(1024), 0, st, table, count, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_tail_multi(TailInst* descs, int count, TailInst* table, int32_t* seg, int32_t* cnt,
+                                 int32_t* list, int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st) {
+  if (count < 1 || count > (1 << (31 - kTailSysBits)) || !table || !seg || !cnt || !list || !nact || !qctr)
     return hipErrorInvalidValue;
-  if (ap.kind == 0 && !ap.band) return hipErrorInvalidValue;
-  if (ap.kind == 1 && !ap.S) return hipErrorInvalidValue;
-  if (lmp.p > 0 && (!lmp.Phi || !lmp.SPhi || !lmp.G || !lmp.theta || !lmp.dmin)) return hipErrorInvalidValue;
-  switch (lmp.p) {
-    case 0: return tail_rows<0>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
-    case 4: return tail_rows<4>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
-    case 8: return tail_rows<8>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
-    case 10: return tail_rows<10>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
-    case 12: return tail_rows<12>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
-    case 16: return tail_rows<16>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
-    case 20: return tail_rows<20>(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
-    default: return hipErrorInvalidValue;
+  for (int j = 0; j < count; ++j) {
+    const TailInst& d = descs[j];
+    if (d.st.S < 1 || d.st.S >= (int64_t(1) << kTailSysBits) || d.grp < 1 || d.st.S / d.grp > kOrderQ || d.seg < 0)
+      return hipErrorInvalidValue;
   }
+  return tail_dispatch(descs, count, table, list, nact, qctr, grid, st, [&]() -> hipError_t {
+    hipLaunchKernelGGL(k_batch_live, dim3((unsigned)count), dim3(1024), 0, st, table, seg, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_pack, dim3(1), dim3(1024), 0, st, table, count, seg, cnt, list, nact, qctr);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace infoesrf

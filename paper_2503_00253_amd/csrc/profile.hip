@@ -144,13 +144,15 @@ hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap
   if (!g_prof.on) return launch_pcg_tail(s, lmp, ap, act, nact, qctr, grid, r0, uacc, chk, st);
   // per system-iteration: the apply and the PCG step; per system: a start reads its residual and
   // reads and writes its solution, a continuation reads and writes x, r, p, and the residual check
-  // reads b and writes the true residual; per launch: the band (or S) and the FP32 Ritz bases
+  // reads b and writes the true residual; per launch from HBM: the band (or S) in the iterations'
+  // precision and in FP64 for the check (one array when both are FP64), and the Ritz bases
   const double m = (double)s.m, P = (double)lmp.p;
   const double apply = ap.kind == 1 ? 2.0 * m * m : 2.0 * grid_nnz(ap.g);
-  const double matrix = ap.kind == 1 ? 8.0 * m * m : 8.0 * m * (2 * ap.g.bz + 1) * (2 * ap.g.bx + 1);
+  const double entries = ap.kind == 1 ? m * m : m * (2 * ap.g.bz + 1) * (2 * ap.g.bx + 1);
+  const double matrix = entries * (ap.low ? 8.0 + 4.0 : 8.0);
   const double per_system = ((r0 ? 3.0 : 6.0) + (chk.b ? 2.0 : 0.0)) * 8.0 * m;
   return timed(INFOESRF_PROF_TAIL, apply + m * (12.0 + 8.0 * P), per_system,
-               matrix + 2.0 * 4.0 * m * P, st,
+               matrix + 2.0 * 8.0 * m * P, st,
                [&](const ProfDev* pd) {
                  PCGState sp = s;
                  sp.prof = pd ? *pd : ProfDev{};

@@ -106,6 +106,8 @@ def library():
     lib.infoesrf_update_batched.argtypes = [P(ProblemC), C.c_int32, P(C.c_int32), P(PD), P(PD), P(VP), P(VP),
                                             P(VP), P(Opts), P(Lattice), P(StatsC), VP, C.c_size_t, VP]
     lib.infoesrf_update_batched.restype = C.c_int
+    lib.infoesrf_batched_one_launch.argtypes = [P(ProblemC), C.c_int32, P(C.c_int32), P(Opts), P(Lattice)]
+    lib.infoesrf_batched_one_launch.restype = C.c_int
     FP = P(C.c_float)
     lib.infoesrf_net_create.argtypes = [C.c_int32, C.c_int32, C.c_uint64, P(VP)]
     lib.infoesrf_net_create.restype = C.c_int
@@ -121,17 +123,19 @@ def library():
     lib.infoesrf_net_get_params.restype = C.c_int
     lib.infoesrf_net_set_params.argtypes = [VP, FP]
     lib.infoesrf_net_set_params.restype = C.c_int
-    lib.infoesrf_net_workspace_bytes.argtypes = [VP, C.c_int64, C.c_int64, C.c_int32]
+    lib.infoesrf_net_workspace_bytes.argtypes = [VP, C.c_int64, C.c_int64, C.c_int64, C.c_int32]
     lib.infoesrf_net_workspace_bytes.restype = C.c_size_t
     lib.infoesrf_net_forward.argtypes = [VP, VP, C.c_int64, C.c_int64, VP, VP, C.c_size_t, VP]
     lib.infoesrf_net_forward.restype = C.c_int
     lib.infoesrf_net_forward_bf16.argtypes = [VP, VP, C.c_int64, C.c_int64, VP, VP, C.c_size_t, VP]
     lib.infoesrf_net_forward_bf16.restype = C.c_int
-    lib.infoesrf_net_gradients.argtypes = [VP, VP, VP, C.c_int64, C.c_int64, VP, VP, VP, C.c_size_t, VP]
+    lib.infoesrf_net_gradients.argtypes = [VP, VP, VP, VP, C.c_int64, C.c_int64, C.c_int64, VP, VP, VP, C.c_size_t,
+                                           VP]
     lib.infoesrf_net_gradients.restype = C.c_int
-    lib.infoesrf_net_train_step.argtypes = [VP, VP, VP, C.c_int64, C.c_int64, C.c_float, VP, VP, C.c_size_t, VP]
+    lib.infoesrf_net_train_step.argtypes = [VP, VP, VP, VP, C.c_int64, C.c_int64, C.c_int64, C.c_float, VP, VP,
+                                            C.c_size_t, VP]
     lib.infoesrf_net_train_step.restype = C.c_int
-    lib.infoesrf_warmstart_pairs.argtypes = [P(ProblemC), C.c_int32, P(C.c_double), P(C.c_double), VP, VP, VP,
+    lib.infoesrf_warmstart_pairs.argtypes = [P(ProblemC), C.c_int32, P(C.c_double), P(C.c_double), VP, VP, VP, VP,
                                              P(Opts), P(StatsC), VP, C.c_size_t, VP]
     lib.infoesrf_warmstart_pairs.restype = C.c_int
     lib.infoesrf_l96_forecast.argtypes = [VP, C.c_int64, C.c_int64, C.c_int32, C.c_int32, VP, C.c_double,
@@ -402,6 +406,16 @@ def batched_workspace_bytes(problems, Qs, opts: Opts, lattices=None) -> int:
     return int(b)
 
 
+def batched_one_launch(problems, Qs, opts: Opts, lattices=None) -> bool:
+    """Whether infoesrf_update_batched runs these instances in one persistent launch per sweep."""
+    arr = (ProblemC * len(problems))(*[pb.c for pb in problems])
+    qa = (C.c_int32 * len(Qs))(*Qs)
+    lat = None
+    if lattices is not None:
+        lat = lattices if isinstance(lattices, C.Array) else (Lattice * len(lattices))(*[Lattice(*t) for t in lattices])
+    return bool(library().infoesrf_batched_one_launch(arr, len(problems), qa, C.byref(opts), lat))
+
+
 class BatchedRunner:
     """Many independent instances in one infoesrf_update_batched call (buffers preallocated).
 
@@ -444,6 +458,10 @@ class BatchedRunner:
         return _check(self.lib.infoesrf_update_batched(
             self._probs, len(self.problems), self._qa, self._sp, self._pp, self._yp, self._mp, self._xp,
             C.byref(self.opts), self._lat, C.byref(self.sc), self.ws.data_ptr(), self.ws.numel(), _stream()))
+
+    def one_launch(self):
+        return bool(self.lib.infoesrf_batched_one_launch(self._probs, len(self.problems), self._qa,
+                                                         C.byref(self.opts), self._lat))
 
     def results(self):
         """(list of n_j x N_j analysis deviations, list of analysis means or None)."""
@@ -501,54 +519,76 @@ class Net:
         assert v.size == self.param_count
         _check(library().infoesrf_net_set_params(self.h, v.ctypes.data_as(C.POINTER(C.c_float))), allow_warn=False)
 
-    def _workspace(self, B, m, training):
+    D = 4  # trunk output channels (terms of the shift head)
+
+    def _workspace(self, B, Q, m, training):
         torch = _torch()
-        key = (B, m, bool(training))
+        key = (B, Q if training else 1, m, bool(training))
         if key not in self._ws:
-            nbytes = library().infoesrf_net_workspace_bytes(self.h, B, m, 1 if training else 0)
+            nbytes = library().infoesrf_net_workspace_bytes(self.h, B, Q, m, 1 if training else 0)
             if nbytes == 0:
                 raise InfoEsrfError(ERR_INVALID_ARG, library().infoesrf_last_error().decode())
-            self._ws = {key: torch.empty(nbytes, dtype=torch.uint8, device="cuda")}
+            self._ws = {key: torch.empty(nbytes, dtype=torch.float32, device="cuda")}
         return self._ws[key]
 
     def forward(self, X, bf16=False):
-        """X: (B, 3, m) float32 CUDA tensor -> (B, m); bf16: BF16 weights and activations on MFMA."""
+        """Trunk: X (B, m) float32 CUDA tensor of the members' bh -> Y (B, D, m); bf16: BF16 weights
+        and activations on MFMA."""
         torch = _torch()
         X = X.contiguous()
-        B, _, m = X.shape
-        Y = torch.empty((B, m), dtype=torch.float32, device=X.device)
-        ws = self._workspace(B, m, False)
+        B, m = X.shape
+        Y = torch.empty((B, self.D, m), dtype=torch.float32, device=X.device)
+        ws = self._workspace(B, 1, m, False)
         fn = library().infoesrf_net_forward_bf16 if bf16 else library().infoesrf_net_forward
-        _check(fn(self.h, X.data_ptr(), B, m, Y.data_ptr(), ws.data_ptr(), ws.numel(), _stream()), allow_warn=False)
+        _check(fn(self.h, X.data_ptr(), B, m, Y.data_ptr(), ws.data_ptr(), ws.numel() * 4, _stream()),
+               allow_warn=False)
         return Y
 
-    def gradients(self, X, T):
-        """(gradient in the parameter layout, loss) of the mean relative L2 loss."""
+    @staticmethod
+    def head(Y, cq):
+        """The shift head: y (B, Q, m) = sum_d c_q^(d+1) Y[b, d] for cq (Q,) (torch, on Y's device)."""
+        D = Y.shape[1]
+        phi = torch_stack_pow(cq, D)
+        return _torch().einsum("qd,bdt->bqt", phi, Y)
+
+    def gradients(self, X, cq, T):
+        """(gradient in the parameter layout, loss) of the mean relative L2 loss of the B x Q
+        systems: X (B, m), cq (Q,), T (B, Q, m)."""
         torch = _torch()
-        X, T = X.contiguous(), T.contiguous()
-        B, _, m = X.shape
+        X, cq, T = X.contiguous(), cq.contiguous(), T.contiguous()
+        B, m = X.shape
+        Q = cq.shape[0]
         g = torch.empty(self.param_count, dtype=torch.float32, device=X.device)
         loss = torch.empty(1, dtype=torch.float32, device=X.device)
-        ws = self._workspace(B, m, True)
-        _check(library().infoesrf_net_gradients(self.h, X.data_ptr(), T.data_ptr(), B, m, g.data_ptr(),
-                                                loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream()),
-               allow_warn=False)
+        ws = self._workspace(B, Q, m, True)
+        _check(library().infoesrf_net_gradients(self.h, X.data_ptr(), cq.data_ptr(), T.data_ptr(), B, Q, m,
+                                                g.data_ptr(), loss.data_ptr(), ws.data_ptr(), ws.numel() * 4,
+                                                _stream()), allow_warn=False)
         return g, loss
 
-    def train_step(self, X, T, lr):
-        """One Adam step; returns the batch loss before the step (device tensor)."""
+    def train_step(self, X, cq, T, lr):
+        """One Adam step on a batch X (B, m), cq (Q,), T (B, Q, m); returns the batch loss before the
+        step (device tensor)."""
         torch = _torch()
-        B, _, m = X.shape
+        B, m = X.shape
+        Q = cq.shape[0]
         loss = torch.empty(1, dtype=torch.float32, device=X.device)
-        ws = self._workspace(B, m, True)
-        _check(library().infoesrf_net_train_step(self.h, X.data_ptr(), T.data_ptr(), B, m, float(lr),
-                                                 loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream()),
-               allow_warn=False)
+        ws = self._workspace(B, Q, m, True)
+        _check(library().infoesrf_net_train_step(self.h, X.data_ptr(), cq.data_ptr(), T.data_ptr(), B, Q, m,
+                                                 float(lr), loss.data_ptr(), ws.data_ptr(), ws.numel() * 4,
+                                                 _stream()), allow_warn=False)
         return loss
 
 
+def torch_stack_pow(cq, D):
+    """(Q, D) powers c_q^(d+1)."""
+    torch = _torch()
+    return torch.stack([cq ** (d + 1) for d in range(D)], dim=1)
+
+
 def warmstart_pairs(problem: Problem, s_nodes, p_weights, y=None, opts: Opts | None = None):
-    """Training pairs (X (QN, 3, m), T (QN, m), Stats) of the perturbation update's systems."""
+    """Training batch of the perturbation update's systems: X (N, m) the members' bh, cq (Q,) the
+    shift factors, T (N, Q, m) the scaled solutions, and the solve's Stats."""
     torch = _torch()
     lib = library()
     opts = opts or default_opts()
@@ -557,8 +597,9 @@ def warmstart_pairs(problem: Problem, s_nodes, p_weights, y=None, opts: Opts | N
     p_weights = np.ascontiguousarray(p_weights, dtype=np.float64)
     Q = len(s_nodes)
     S = Q * problem.N
-    X = torch.empty((S, 3, problem.m), dtype=torch.float32, device=dev)
-    T = torch.empty((S, problem.m), dtype=torch.float32, device=dev)
+    X = torch.empty((problem.N, problem.m), dtype=torch.float32, device=dev)
+    cq = torch.empty(Q, dtype=torch.float32, device=dev)
+    T = torch.empty((problem.N, Q, problem.m), dtype=torch.float32, device=dev)
     yp = 0
     if y is not None:
         yt = torch.as_tensor(np.asarray(y, dtype=np.float64)).to(dev)
@@ -568,10 +609,10 @@ def warmstart_pairs(problem: Problem, s_nodes, p_weights, y=None, opts: Opts | N
     dp = C.POINTER(C.c_double)
     code = _check(lib.infoesrf_warmstart_pairs(C.byref(problem.c), Q, s_nodes.ctypes.data_as(dp),
                                                p_weights.ctypes.data_as(dp), C.c_void_p(yp), X.data_ptr(),
-                                               T.data_ptr(), C.byref(opts), C.byref(sc), ws.data_ptr(), ws.numel(),
-                                               _stream()))
+                                               cq.data_ptr(), T.data_ptr(), C.byref(opts), C.byref(sc),
+                                               ws.data_ptr(), ws.numel(), _stream()))
     torch.cuda.synchronize()
-    return X, T, Stats(code, *(t.cpu().numpy() for t in keep))
+    return X, cq, T, Stats(code, *(t.cpu().numpy() for t in keep))
 
 
 def l96_forecast(X, nz, nx, forcing, gamma, dt, steps):

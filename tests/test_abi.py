@@ -219,12 +219,17 @@ def test_net_argument_validation(tmp_path):
     assert lib.infoesrf_net_create(64, 8, 1, C.byref(h)) == ie.ERR_INVALID_ARG
     assert lib.infoesrf_net_create(64, 17, 1, C.byref(h)) == ie.ERR_INVALID_ARG
     assert lib.infoesrf_net_param_count(None) == 0
-    assert lib.infoesrf_net_workspace_bytes(None, 4, 100, 0) == 0
+    assert lib.infoesrf_net_workspace_bytes(None, 4, 8, 100, 0) == 0
     bad = tmp_path / "bad.ienet"
     bad.write_bytes(b"NOTANET!" + b"\0" * 40)
     assert lib.infoesrf_net_load(str(bad).encode(), C.byref(h)) == ie.ERR_INVALID_ARG
     assert "not a warm-start network" in lib.infoesrf_last_error().decode()
     assert lib.infoesrf_net_load(str(tmp_path / "missing").encode(), C.byref(h)) == ie.ERR_INVALID_ARG
+    # the first version's files (3 input channels, one output) are not this network
+    old = tmp_path / "v1.ienet"
+    import struct
+    old.write_bytes(b"IENET001" + struct.pack("<5i", 4, 3, 8, 9, 1) + b"\0" * 64)
+    assert lib.infoesrf_net_load(str(old).encode(), C.byref(h)) == ie.ERR_INVALID_ARG
     # the learned start needs a network
     p = fake_problem()
     o = ie.default_opts(warm_start=ie.START_LEARNED)

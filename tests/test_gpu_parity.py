@@ -582,3 +582,47 @@ def test_rank_deficient_sketch(form):
     e2 = upd(got2.cpu().numpy() / np.sqrt(prob.N - 1), z64)
     say("  fixed budget vs oracle", e2)
     assert e2 < 1e-6
+
+
+def test_headline_options_mixed_fp32_n4096():
+    """The benchmark's options with FP32 inner applies: the persistent kernel iterates on the FP32
+    band (FP64 vectors, scalars and accumulation) and checks each sweep's true residual with the
+    FP64 band; every system to 1e-8, each member against the FP64 oracle to 1e-6."""
+    prob = syn.config2()
+    say("headline options n4096, mixed fp32")
+    dp = dense_of(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    P = ie.Problem.from_synthetic(prob)
+    o = ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=P.lattice(), precision=ie.MIXED_FP32,
+                        n_ritz=4, oversample=4, tail_systems=0)
+    got, st = ie.perturbation_update(P, s, p, o)
+    assert st.code == ie.OK
+    assert np.all(st.relres <= 1e-8) and np.all(st.converged == 1)
+    assert st.counter(ie.CNT_SWEEPS) >= prob.Q * prob.N
+    err = upd(got.cpu().numpy(), want)
+    say("  members", err, "iterations max", int(st.iters.max()), "total", int(st.iters.sum()),
+        "sweeps", st.counter(ie.CNT_SWEEPS))
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("form,domain", [("band", "lattice"), ("dense-s", "state")])
+@pytest.mark.parametrize("case", ["gauss-n256-periodic", "2d-periodic-z", "ragged-1d-nonperiodic"])
+def test_persistent_mixed_fp32(case, form, domain):
+    """FP32 inner applies in the persistent kernel (every solve from its start, and the batched
+    loop handing its state over), against the oracle and the batched loop."""
+    prob = CASES[case]()
+    say("persistent mixed fp32", case, form, domain)
+    dp = dense_of(prob)
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    P = ie.Problem.from_synthetic(prob)
+    S = prob.Q * prob.N
+    outs = {}
+    for tail in (-1, 0, S):
+        got, st = ie.perturbation_update(P, s, p, opts_for(prob, P, domain, form, tail_systems=tail,
+                                                         precision=ie.MIXED_FP32))
+        assert st.code == ie.OK and np.all(st.relres <= 1e-8)
+        assert upd(got.cpu().numpy(), want) < 1e-6, tail
+        outs[tail] = got.cpu().numpy()
+    assert rel(outs[0], outs[-1]) < 1e-8

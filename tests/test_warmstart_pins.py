@@ -38,21 +38,24 @@ def test_gelu_definition_and_derivative():
     assert np.allclose(wr.gelu_grad(x), fd, rtol=1e-8, atol=1e-9)
 
 
-def _loss(params, X, T):
+def _loss(params, X, phi, T):
     Y, _ = wr.forward(params, X)
-    return wr.loss_rel_l2(Y[:, 0, :], T)[0]
+    return wr.loss_rel_l2(wr.head(Y, phi), T)[0]
 
 
 def test_gradients_match_finite_differences():
+    """Trunk, shift head and loss together: every parameter's gradient against central
+    differences of the loss."""
     rng = np.random.default_rng(2)
-    params = wr.init_params(channels=(3, 4, 4, 4, 1), K=9, seed=3)
+    params = wr.init_params(channels=(1, 4, 4, 4, 3), K=9, seed=3)
     params = [(W, 0.1 * rng.standard_normal(b.shape)) for W, b in params]
-    B, m = 3, 13
-    X = rng.standard_normal((B, 3, m))
-    T = rng.standard_normal((B, m))
+    B, m, Q = 3, 13, 4
+    X = rng.standard_normal((B, 1, m))
+    phi = wr.shift_basis(np.array([0.02, 0.3, 2.0, 15.0]), 3)
+    T = rng.standard_normal((B, Q, m))
     Y, cache = wr.forward(params, X)
-    _, gY = wr.loss_rel_l2(Y[:, 0, :], T)
-    grads = wr.backward(params, cache, gY[:, None, :])
+    _, gy = wr.loss_rel_l2(wr.head(Y, phi), T)
+    grads = wr.backward(params, cache, wr.head_grad(gy, phi))
     h = 1e-6
     worst = 0.0
     for li, (W, b) in enumerate(params):
@@ -62,14 +65,32 @@ def test_gradients_match_finite_differences():
             for k in idx:
                 old = flat[k]
                 flat[k] = old + h
-                lp = _loss(params, X, T)
+                lp = _loss(params, X, phi, T)
                 flat[k] = old - h
-                lm = _loss(params, X, T)
+                lm = _loss(params, X, phi, T)
                 flat[k] = old
                 fd = (lp - lm) / (2 * h)
                 an = grads[li][j].reshape(-1)[k]
                 worst = max(worst, abs(fd - an) / max(1e-6, abs(fd) + abs(an)))
     assert worst < 1e-6, worst
+
+
+def test_head_gradient_matches_finite_differences():
+    """The head's gradient w.r.t. the trunk output, entry by entry."""
+    rng = np.random.default_rng(12)
+    B, D, Q, m = 2, 3, 5, 7
+    Y = rng.standard_normal((B, D, m))
+    phi = wr.shift_basis(rng.uniform(0.0, 20.0, Q), D)
+    T = rng.standard_normal((B, Q, m))
+    _, gy = wr.loss_rel_l2(wr.head(Y, phi), T)
+    gY = wr.head_grad(gy, phi)
+    h = 1e-6
+    for idx in np.ndindex(Y.shape):
+        Yp, Ym = Y.copy(), Y.copy()
+        Yp[idx] += h
+        Ym[idx] -= h
+        fd = (wr.loss_rel_l2(wr.head(Yp, phi), T)[0] - wr.loss_rel_l2(wr.head(Ym, phi), T)[0]) / (2 * h)
+        assert abs(fd - gY[idx]) <= 1e-7 * max(1.0, abs(fd)), idx
 
 
 def test_adam_first_step_closed_form():
@@ -85,25 +106,58 @@ def test_adam_first_step_closed_form():
 
 def test_prediction_scales_with_rhs():
     rng = np.random.default_rng(5)
-    params = wr.init_params(channels=(3, 8, 8, 8, 1), K=9, seed=6)
+    params = wr.init_params(channels=(1, 8, 8, 8, 4), K=9, seed=6)
     b = rng.standard_normal((4, 30))
     s = np.array([0.0, 1.5, 10.0, 100.0])
     u1 = wr.predict(params, b, s)
     u2 = wr.predict(params, 7.5 * b, s)
+    assert u1.shape == (4, 4, 30)
     assert np.allclose(u2, 7.5 * u1, rtol=1e-13, atol=0)
 
 
-def test_neumann_features_solve_the_unlocalized_limit():
-    """With S = 0 the first feature times ||b|| is the exact solution b / (1 + s)."""
+def test_shift_head_solves_the_unlocalized_limit():
+    """With S = 0, C_q = (1 + s_q) I: a trunk whose first channel is its input and whose other
+    channels are zero predicts the exact solution b / (1 + s_q) at every shift (the basis starts
+    at c, not 1)."""
     rng = np.random.default_rng(8)
     b = rng.standard_normal((3, 20))
-    s = np.array([0.5, 3.0, 40.0])
-    X = wr.features(b, s)
-    scale = (np.linalg.norm(b, axis=1) / np.sqrt(b.shape[1]))[:, None]
-    assert np.allclose(scale * X[:, 0, :], b / (1 + s)[:, None], rtol=1e-14)
-    assert np.allclose(X[:, 1, :] * (1 + s)[:, None], X[:, 0, :], rtol=1e-14)
-    # the exact solution's target is the first feature when S = 0
-    assert np.allclose(wr.targets(b / (1 + s)[:, None], b), X[:, 0, :], rtol=1e-14)
+    s = np.array([0.5, 3.0, 40.0, 0.0])
+    X = wr.member_features(b)
+    Y = np.zeros((3, 4, 20))
+    Y[:, 0, :] = X[:, 0, :]
+    y = wr.head(Y, wr.shift_basis(s, 4))
+    scale = (np.linalg.norm(b, axis=1) / np.sqrt(b.shape[1]))[:, None, None]
+    exact = b[:, None, :] / (1 + s)[None, :, None]
+    assert np.allclose(scale * y, exact, rtol=1e-14, atol=0)
+    assert np.allclose(wr.targets(exact, b), y, rtol=1e-14)
+
+
+def test_shift_head_is_the_truncated_neumann_series():
+    """With Y[d] = (-S)^d bh the head is sum_{d<D} c^(d+1) (-S)^d b, the Neumann series of
+    ((1 + s) I + S)^{-1} b truncated after D terms: its error against a dense solve falls like
+    (c ||S||)^D for a small S (each added channel divides it by about c ||S||)."""
+    rng = np.random.default_rng(9)
+    m = 12
+    A = rng.standard_normal((m, m))
+    S = 0.05 * (A @ A.T) / m
+    b = rng.standard_normal(m)
+    s = np.array([0.0, 0.7])
+    bh = wr.member_features(b[None, :])[0, 0]
+    scale = np.linalg.norm(b) / np.sqrt(m)
+    errs = []
+    for D in (1, 2, 3, 4):
+        Y = np.zeros((1, D, m))
+        v = bh.copy()
+        for d in range(D):
+            Y[0, d] = v
+            v = -S @ v
+        u = scale * wr.head(Y, wr.shift_basis(s, D))[0]
+        exact = np.stack([np.linalg.solve((1 + sq) * np.eye(m) + S, b) for sq in s])
+        errs.append(np.linalg.norm(u - exact) / np.linalg.norm(exact))
+    rho = np.linalg.norm(S, 2)
+    for e0, e1 in zip(errs, errs[1:]):
+        assert e1 < 1.1 * rho * e0
+    assert errs[-1] < 2 * rho ** 4
 
 
 def test_loss_zero_at_target():
