@@ -448,6 +448,9 @@ struct Inst {
   // for MIXED_FP32 inner applies in that domain, an FP32 copy
   bool band = false;
   void *bandS = nullptr, *bandS32 = nullptr, *bandO = nullptr, *bandO32 = nullptr;
+  // FP32 copies of the observed-lattice band and of the dense S in the persistent kernel's packed
+  // layout (four stencil entries of a row in 16 bytes), for FP32 inner applies
+  float *bandQ32 = nullptr, *SdQ32 = nullptr;
   // learned warm start: network buffers for the members (inputs, trunk outputs, the network's
   // own workspace)
   const Net* net = nullptr;
@@ -699,12 +702,16 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
       const int64_t po = (int64_t)(2 * in.go.bz + 1) * (2 * in.go.bx + 1) * ld64(in.m);
       in.bandO = ar.take<double>(po);
       in.bandO32 = (f32 && !in.sd) ? ar.take<float>(po) : nullptr;
+      in.bandQ32 = (f32 && !in.sd)
+                       ? ar.take<float>((int64_t)(2 * in.go.bz + 1) * ((2 * in.go.bx + 1 + 3) / 4) * ld64(in.m) * 4)
+                       : nullptr;
     }
   }
   if (in.sd) {
     in.lds = ld64(in.m);
     in.Sd = ar.take<double>(in.lds * in.m);
     in.Sd32 = (op.inner == Prec::F32) ? ar.take<float>(in.lds * in.m) : nullptr;
+    in.SdQ32 = (op.inner == Prec::F32) ? ar.take<float>((in.m + 3) / 4 * in.lds * 4) : nullptr;
   }
   in.col_cnt = ar.take<int32_t>(in.n);
   in.col_ptr = ar.take<int32_t>(in.n + 1);
@@ -892,6 +899,7 @@ int build_dense_s(Plan& pl, const Options& op, hipStream_t st) {
                                 P->h_w, P->r_var, in.n, in.m, j0, bc, in.Sd, in.lds, st));
   }
   IE_HIP(launch_symmetrize(in.Sd, in.m, in.lds, in.Sd32, st));
+  if (in.SdQ32) IE_HIP(launch_pack_quads(in.Sd, 1, in.m, in.lds, in.m, in.SdQ32, st));
   return 0;
 }
 
@@ -1057,6 +1065,9 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
     if (in.obs) {
       IE_HIP(launch_band_build(Prec::F64, in.go, in.Zt, in.m, in.N, in.bandO, ld64(in.m), st));
       if (in.bandO32) IE_HIP(launch_band_build(Prec::F32, in.go, in.Zt, in.m, in.N, in.bandO32, ld64(in.m), st));
+      if (in.bandQ32)
+        IE_HIP(launch_pack_quads(static_cast<const double*>(in.bandO), 2 * in.go.bz + 1, 2 * in.go.bx + 1, ld64(in.m),
+                                 in.m, in.bandQ32, st));
     }
   }
   // 4. dense S (m applies of P)
@@ -1421,8 +1432,8 @@ bool tail_inplace(const Plan& pl, const Options& op, TailApply& tap) {
   tap.lds = in.lds;
   tap.m = in.m;
   tap.low = op.inner == Prec::F32 ? 1 : 0;
-  tap.band32 = static_cast<const float*>(in.bandO32);
-  tap.S32 = in.Sd32;
+  tap.band32 = in.bandQ32;
+  tap.S32 = in.SdQ32;
   return tail_fits(tap);
 }
 
@@ -1490,7 +1501,8 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
   // residual and status
   const bool persist = tail_ok && S <= op.tail && !msc && !bcg;
   TailCheck chk{};
-  if (persist) chk = TailCheck{sy.b, sy.fdone, sy.sweeps, sy.relres, op.rtol, op.fixed > 0 ? 1 : 0, op.inner_rtol};
+  if (persist)
+    chk = TailCheck{sy.b, sy.fdone, sy.sweeps, sy.relres, op.rtol, op.fixed > 0 ? 1 : 0, op.inner_rtol, max_sweeps};
   auto run_tail = [&](int32_t* list, int32_t* count, int64_t bound, const double* r0) -> int {
     IE_HIP(launch_order_live(sy.done, sy.sigma, S, grp, list, count, sy.qctr, st));
     IE_HIP(pcg_tail_timed(ps, lmp, tap, list, count, sy.qctr, bound, r0, r0 ? sy.u : nullptr,
@@ -1933,7 +1945,9 @@ int batched_one_launch(const infoesrf_problem* probs, int count, const int32_t* 
     d.st = pcg_state_of(p, op[j]);
     d.lmp = lmp_of(p);
     IE_CHECK(tail_inplace(p, op[j], d.ap), INFOESRF_ERR_INVALID_ARG, "no in-place apply for the persistent kernel");
-    d.chk = TailCheck{sy.b, sy.fdone, sy.sweeps, sy.relres, op[j].rtol, op[j].fixed > 0 ? 1 : 0, op[j].inner_rtol};
+    const int budget = op[j].fixed > 0 ? 1 : (host_sync ? 40 : (op[j].inner == Prec::F64 ? 2 : 4));
+    d.chk = TailCheck{sy.b, sy.fdone, sy.sweeps, sy.relres, op[j].rtol, op[j].fixed > 0 ? 1 : 0,
+                      op[j].inner_rtol, budget};
     d.r0 = sy.b;  // the first sweep's residual (zero start)
     d.uacc = sy.u;
     d.grp = (int32_t)N;

@@ -244,6 +244,11 @@ hipError_t launch_gather_s_cols(int obs_domain, const double* T, int64_t ldt, co
                                 const int32_t* h_idx, const double* h_w, const double* r_var, int64_t n, int64_t m,
                                 int64_t j0, int64_t bc, double* S, int64_t lds, hipStream_t st);
 hipError_t launch_symmetrize(double* S, int64_t m, int64_t lds, float* S32, hipStream_t st);
+// FP32 copy of hh stencil rows of ww columns (column-major, ld, m rows) in the persistent kernel's
+// packed layout: entry k of row r of stencil row li at float ((li ww4 / 4 + k / 4) ld + r) 4 +
+// k % 4, ww4 = ww rounded up to 4, zeros past ww and at rows >= m.  dst holds hh ww4 ld floats.
+hipError_t launch_pack_quads(const double* src, int64_t hh, int64_t ww, int64_t ld, int64_t m, float* dst,
+                             hipStream_t st);
 hipError_t launch_dense_s_apply(Prec prec, const void* S, int64_t lds, int64_t m, const void* V, int64_t ldv,
                                 const int32_t* nact, int64_t Bmax, void* T, int64_t ldt, int32_t* zero_counter,
                                 hipStream_t st);
@@ -360,8 +365,9 @@ hipError_t launch_bcg_iteration(const BcgState& s, int mode, int it, hipStream_t
 hipError_t launch_bcg_list(const int32_t* bdone, int Q, int64_t N, int32_t* act, int32_t* nact, hipStream_t st);
 // In-place apply of S for the persistent finish: kind 0 = explicit band of P on the observed
 // lattice g (rows = m), kind 1 = dense S (m x m, column-major, lds).
-// low != 0: the PCG iterations apply FP32 copies (band32 or S32, same layout and leading
-// dimension), widened to FP64 as they are read; the residual check applies the FP64 band or S.
+// low != 0: the PCG iterations apply FP32 copies (band32 or S32, packed by launch_pack_quads with
+// the same leading dimension), widened to FP64 as they are read; the residual check applies the
+// FP64 band or S.
 struct TailApply {
   int kind;
   Grid g;
@@ -394,6 +400,8 @@ struct TailCheck {
   double rtol;
   int fixed;
   double inner_rtol; // FP32 inner applies: the next sweep's inner target relative to the residual
+  int max_sweeps;    // sweeps a system may take in all; > 0: the kernel runs them back to back,
+                     // 0: one sweep a launch (the host decides on the next)
 };
 // r0 and uacc (both given or both null): each system starts from x = 0 with residual r0 (the
 // kernel takes the first step itself) and adds its solution into uacc, then, when chk->b is

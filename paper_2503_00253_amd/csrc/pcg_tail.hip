@@ -20,6 +20,7 @@
 // The band values are loaded a chunk at a time ahead of their use, to keep many loads in flight
 // per wavefront.
 #include <atomic>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -30,6 +31,9 @@ namespace {
 constexpr int kTailMaxM = 4096;
 // dynamic LDS for the (padded) direction, in doubles
 constexpr int64_t kTailPadMax = 6144;
+// zeroed doubles after the padded direction: the packed FP32 band reads up to 3 entries past a
+// stencil row's end
+constexpr int kTailSlack = 4;
 
 // Workgroup sums of Wn values per thread: DPP sums in a wavefront, then the NT / 64 wavefront
 // partials in order (a fixed tree: bit-reproducible).  tail_sum1 returns its one sum to every
@@ -112,7 +116,7 @@ __host__ __device__ constexpr bool tail_caches_ritz(int P, int RPT, int NT) {
 }
 
 // Rows of a thread: pairs of adjacent rows, 2 (tid + NT jj) + b for jj < RPT / 2, b in {0, 1}, so
-// that one 16-byte load brings a band entry of both rows.
+// that one 16-byte load brings an entry of the FP64 band for both rows.
 template <int NT>
 __device__ inline int tail_row(int tid, int j) {
   return 2 * (tid + NT * (j >> 1)) + (j & 1);
@@ -122,15 +126,8 @@ __device__ inline double2 tail_ld16(__amdgpu_buffer_rsrc_t rs, uint32_t voff, ui
   return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
 }
 
-// One band (or S) entry of a row pair, widened to FP64: 16 bytes of an FP64 band, 8 of an FP32 one.
-template <typename BT>
-__device__ inline double2 tail_ld_pair(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
-  if constexpr (sizeof(BT) == 8) {
-    return tail_ld16(rs, voff, soff);
-  } else {
-    const float2 f = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
-    return double2{(double)f.x, (double)f.y};
-  }
+__device__ inline float4 tail_ld16f(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
 }
 
 // S v for the thread's rows, v being in LDS (the padded lattice, or the whole vector for the
@@ -140,9 +137,11 @@ __device__ inline double2 tail_ld_pair(__amdgpu_buffer_rsrc_t rs, uint32_t voff,
 // pairs, are issued ahead of their multiply-adds (one load brings the entry of both rows of a
 // pair; uniform column offsets in scalar registers, the pair a per-lane offset), then one chunk
 // for the rest of the row, whose missing entries repeat the last one and are weighted by zero.
-// Entries of an FP32 band are widened and the sums kept in FP64.
+// ADJ: the second row of every pair starts its stencil one entry after the first (a lattice of
+// even width), so both rows read one window of the direction and the compiler loads each LDS word
+// once for the two.
 
-template <typename BT, int RPT, int NT, int CH>
+template <int RPT, int NT, int CH, bool ADJ>
 __device__ inline void tail_apply_rows(__amdgpu_buffer_rsrc_t rsA, uint32_t colA, const uint32_t* roff,
                                        const int* corner, const double* sp, int hh, int ww, int Wp, int64_t m,
                                        double* qv) {
@@ -164,13 +163,13 @@ __device__ inline void tail_apply_rows(__amdgpu_buffer_rsrc_t rsA, uint32_t colA
       for (int jj = 0; jj < RPT / 2; ++jj)
         if (live[jj]) {
 #pragma unroll
-          for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld_pair<BT>(rsA, roff[jj], so + (uint32_t)k * colA);
+          for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)k * colA);
         }
 #pragma unroll
       for (int jj = 0; jj < RPT / 2; ++jj) {
         if (!live[jj]) continue;
         const double* p0 = sp + corner[2 * jj] + lrow + d0;
-        const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
+        const double* p1 = ADJ ? p0 + 1 : sp + corner[2 * jj + 1] + lrow + d0;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
           qv[2 * jj] += bv[jj][k].x * p0[k];
@@ -186,19 +185,95 @@ __device__ inline void tail_apply_rows(__amdgpu_buffer_rsrc_t rsA, uint32_t colA
       for (int jj = 0; jj < RPT / 2; ++jj)
         if (live[jj]) {
 #pragma unroll
-          for (int k = 0; k < CH; ++k)
-            bv[jj][k] = tail_ld_pair<BT>(rsA, roff[jj], so + (uint32_t)min(k, last) * colA);
+          for (int k = 0; k < CH; ++k) bv[jj][k] = tail_ld16(rsA, roff[jj], so + (uint32_t)min(k, last) * colA);
         }
 #pragma unroll
       for (int jj = 0; jj < RPT / 2; ++jj) {
         if (!live[jj]) continue;
         const double* p0 = sp + corner[2 * jj] + lrow + d0;
-        const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
+        const double* p1 = ADJ ? p0 + 1 : sp + corner[2 * jj + 1] + lrow + d0;
 #pragma unroll
         for (int k = 0; k < CH; ++k) {
           const int kk = min(k, last);
           qv[2 * jj] += (k <= last ? bv[jj][k].x : 0.0) * p0[kk];
           qv[2 * jj + 1] += (k <= last ? bv[jj][k].y : 0.0) * p1[kk];
+        }
+      }
+    }
+  }
+}
+
+// The same with the FP32 band (or S) in its packed layout: four consecutive stencil entries of a
+// row in 16 bytes, entry k of row r of stencil row li at float ((li ww4 / 4 + k / 4) ld + r) 4 +
+// k % 4 (ww4: ww rounded up to 4, zeros past ww).  A load brings four entries of one row, so a
+// row's stencil row takes ww4 / 4 loads: half the loads of the FP64 pairs, and the load unit
+// takes about as long for a 16-byte load as for the 8 bytes of an FP32 pair (colQ: bytes of one
+// column of quads; rowq: a row's byte offset in it).  The direction past a stencil row's last
+// entry holds finite values (the next lattice row, or the zeroed slack after the padded lattice),
+// which the zero weights cancel.  CH entries a chunk (a multiple of 4); the sums are in FP64.
+template <int RPT, int NT, int CH, bool ADJ>
+__device__ inline void tail_apply_rows_q(__amdgpu_buffer_rsrc_t rsQ, uint32_t colQ, const uint32_t* rowq,
+                                         const int* corner, const double* sp, int hh, int ww4, int Wp, int64_t m,
+                                         double* qv) {
+  static_assert(CH % 4 == 0, "whole quads");
+  constexpr int CQ = CH / 4;
+  bool live[RPT / 2];
+#pragma unroll
+  for (int jj = 0; jj < RPT / 2; ++jj)
+    live[jj] = RPT <= 2 || 2 * ((int64_t)(threadIdx.x & ~63) + (int64_t)NT * jj) < m;
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) qv[j] = 0.0;
+  for (int li = 0; li < hh; ++li) {
+    uint32_t so = (uint32_t)(li * (ww4 / 4)) * colQ;
+    const int lrow = li * Wp;
+    int d0 = 0;
+    for (; d0 + CH <= ww4; d0 += CH) {
+      float4 bv[RPT][CQ];
+#pragma unroll
+      for (int j = 0; j < RPT; ++j)
+        if (live[j / 2]) {
+#pragma unroll
+          for (int q = 0; q < CQ; ++q) bv[j][q] = tail_ld16f(rsQ, rowq[j], so + (uint32_t)q * colQ);
+        }
+      // every load of the chunk goes out before the first is used (widening each one as it lands
+      // lets the compiler reuse its registers and wait for every load in turn)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        if (!live[j / 2]) continue;
+        const double* pj = (ADJ && (j & 1)) ? sp + corner[j - 1] + lrow + d0 + 1 : sp + corner[j] + lrow + d0;
+#pragma unroll
+        for (int q = 0; q < CQ; ++q) {
+          qv[j] += (double)bv[j][q].x * pj[4 * q];
+          qv[j] += (double)bv[j][q].y * pj[4 * q + 1];
+          qv[j] += (double)bv[j][q].z * pj[4 * q + 2];
+          qv[j] += (double)bv[j][q].w * pj[4 * q + 3];
+        }
+      }
+      so += (uint32_t)CQ * colQ;
+    }
+    if (d0 < ww4) {
+      // the rest in whole quads: missing quads repeat the last one and are weighted by zero
+      const int lastq = (ww4 - d0) / 4 - 1;
+      float4 bv[RPT][CQ];
+#pragma unroll
+      for (int j = 0; j < RPT; ++j)
+        if (live[j / 2]) {
+#pragma unroll
+          for (int q = 0; q < CQ; ++q)
+            bv[j][q] = tail_ld16f(rsQ, rowq[j], so + (uint32_t)min(q, lastq) * colQ);
+        }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        if (!live[j / 2]) continue;
+        const double* pj = (ADJ && (j & 1)) ? sp + corner[j - 1] + lrow + d0 + 1 : sp + corner[j] + lrow + d0;
+#pragma unroll
+        for (int q = 0; q < CQ; ++q) {
+          const int qq = 4 * min(q, lastq);
+          const double t = (double)bv[j][q].x * pj[qq] + (double)bv[j][q].y * pj[qq + 1] +
+                           (double)bv[j][q].z * pj[qq + 2] + (double)bv[j][q].w * pj[qq + 3];
+          qv[j] += q <= lastq ? t : 0.0;
         }
       }
     }
@@ -252,9 +327,11 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
   constexpr int W = 2 * P + 1;
   constexpr int NW = NT / 64;
   static_assert(RPT % 2 == 0, "rows come in pairs");
-  // band (or S) entries per chunk: RPT / 2 * CH loads in flight per thread (fewer where the
-  // per-instance values of a launch over many instances take registers)
+  // band (or S) entries per chunk: RPT / 2 * CH loads of FP64 pairs in flight per thread (fewer
+  // where the per-instance values of a launch over many instances take registers); the packed
+  // FP32 band takes RPT * CHQ / 4 loads of as many bytes
   constexpr int CH = RPT >= 4 ? (MULTI ? 4 : 8) : 16;
+  constexpr int CHQ = RPT >= 4 ? (MULTI ? 8 : 16) : 32;
   // the Ritz vectors of the thread's rows stay in registers when they fit
   constexpr bool kCache = tail_caches_ritz(P, RPT, NT);
   constexpr bool kLdsSums = tail_lds_sums(2 * P + 1, NT);
@@ -280,15 +357,17 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
   bool band = true;
   Grid g{};
   int Wp = 0, npad = 0, nh = 0, hh = 1, ww = 1, phi_lds = 0;
+  bool adj = false;  // every row pair's stencils are one entry apart
   double dmin = 0.0;
   __amdgpu_buffer_rsrc_t rsA = tail_rsrc(nullptr, 0), rsI = rsA, rsF = rsA, rsG = rsA;
   uint32_t colA = 0, colI = 0, colF = 0;
   double *part = sp, *sF = sp, *sH = sp;
   // the corner of each row's stencil in the padded grid, and the byte offsets of each row pair in
-  // a column of the FP64 band and of the iterations' band (pairs past m read the last pair and
-  // are discarded; an odd m leaves its last pair one row into the column's padding, ld >= m + 1)
+  // a column of the FP64 band (pairs past m read the last pair and are discarded; an odd m leaves
+  // its last pair one row into the column's padding, ld >= m + 1) and of each row in a column of
+  // quads of the packed FP32 band (rows past m read row m - 1)
   int corner[RPT];
-  uint32_t roff[RPT / 2], roffI[RPT / 2];
+  uint32_t roff[RPT / 2], roffI[RPT];
 
   // the instance's layout, its preconditioner's small matrices, the zero halo of the padded
   // direction along axes that are not periodic (never rewritten), and its Ritz bases in LDS (the
@@ -306,22 +385,25 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
       nh = band ? (g.pz ? 2 * g.bz * Wp : 0) + (g.px ? g.nz * 2 * g.bx : 0) : 0;
       hh = band ? h : 1;
       ww = band ? w : (int)m;
+      adj = band && g.nx % 2 == 0;
       phi_lds = d.phi_lds;
       if (P > 0) {
         for (int o = tid; o < 3 * P * P; o += NT) sG[o] = lmp.G[o];
         if (tid < P) sG[3 * P * P + tid] = lmp.theta[tid];
       }
-      for (int o = tid; o < npad; o += NT) sp[o] = 0.0;
+      for (int o = tid; o < npad + kTailSlack; o += NT) sp[o] = 0.0;
       dmin = (P > 0) ? *lmp.dmin : 0.0;
       rsA = band ? tail_rsrc(ap.band, (int64_t)h * w * ap.ldb * 8) : tail_rsrc(ap.S, m * ap.lds * 8);
       colA = (uint32_t)((band ? ap.ldb : ap.lds) * 8);
+      // the packed FP32 band (or S): (ww rounded up to 4) / 4 columns of 16-byte quads a stencil row
       rsI = !kLow ? rsA
-                  : (band ? tail_rsrc(ap.band32, (int64_t)h * w * ap.ldb * 4) : tail_rsrc(ap.S32, m * ap.lds * 4));
-      colI = kLow ? colA / 2 : colA;
+                  : (band ? tail_rsrc(ap.band32, (int64_t)h * ((w + 3) / 4) * ap.ldb * 16)
+                          : tail_rsrc(ap.S32, (m + 3) / 4 * ap.lds * 16));
+      colI = kLow ? colA * 2 : colA;
       rsF = tail_rsrc(lmp.Phi, (int64_t)P * lmp.ld * 8);
       rsG = tail_rsrc(lmp.SPhi, (int64_t)P * lmp.ld * 8);
       colF = (uint32_t)(lmp.ld * 8);
-      part = sp + npad;                     // W x NT partial sums
+      part = sp + npad + kTailSlack;        // W x NT partial sums
       sF = part + (kLdsSums ? W * NT : 0);  // Phi (P x m), when phi_lds
       sH = sF + (int64_t)P * m;             // S Phi (P x m)
       if (phi_lds) {
@@ -335,29 +417,45 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
       for (int jj = 0; jj < RPT; ++jj) {
         const int r = tail_row<NT>(tid, jj);
         corner[jj] = (band && r < m) ? (r / g.nx) * Wp + r % g.nx : 0;
+        roffI[jj] = (uint32_t)min<int64_t>(r, m - 1) * 16u;
       }
 #pragma unroll
       for (int jj = 0; jj < RPT / 2; ++jj) {
         const uint32_t row = (uint32_t)min<int64_t>(tail_row<NT>(tid, 2 * jj), (m - 1) & ~(int64_t)1);
         roff[jj] = row * (uint32_t)sizeof(double);
-        roffI[jj] = row * (uint32_t)sizeof(BT);
       }
       __syncthreads();
   };
   if (!MULTI) load_instance(one);
 
+  // A system whose sweep's check leaves it above rtol is taken again at once, before the next
+  // queue entry (its entry, iteration count, sweep count and inner target; the same in all threads)
+  int32_t rs_e = -1;
+  int rs_it = 0, rs_nsw = 0;
+  double rs_thresh = 0.0;
   for (;;) {
-    if (tid == 0) s_idx = atomicAdd(qctr, 1);
-    __syncthreads();
-    const int idx = s_idx;
-    __syncthreads();  // every thread has read s_idx before it is written again
-    if (idx >= na) break;
-    const int32_t e = act[idx];
+    const bool resumed = rs_e >= 0;
+    int32_t e = rs_e;
+    rs_e = -1;
+    if (!resumed) {
+      if (tid == 0) s_idx = atomicAdd(qctr, 1);
+      __syncthreads();
+      const int idx = s_idx;
+      __syncthreads();  // every thread has read s_idx before it is written again
+      if (idx >= na) break;
+      e = act[idx];
+    }
     const int j = MULTI ? (int)(e >> kTailSysBits) : 0;
     const int32_t s = MULTI ? (e & ((1 << kTailSysBits) - 1)) : e;
     const TailInst& d = MULTI ? table[j] : one;
     const PCGState& st = d.st;
-    if (st.done[s] != 0) continue;
+    const TailCheck& chk = d.chk;
+    const bool check = d.r0 != nullptr && chk.b != nullptr;
+    if (!resumed) {
+      if (st.done[s] != 0) continue;
+      // a system whose sweep budget is spent stays live for the host to finish
+      if (check && chk.max_sweeps > 0 && chk.sweeps[s] >= chk.max_sweeps) continue;
+    }
     if (MULTI && j != cur) {
       cur = j;
       load_instance(d);
@@ -378,22 +476,30 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
         }
         __syncthreads();
       }
-      if (!kLow || fp64) tail_apply_rows<double, RPT, NT, CH>(rsA, colA, roff, corner, sp, hh, ww, Wp, m, qv);
-      else tail_apply_rows<BT, RPT, NT, CH>(rsI, colI, roffI, corner, sp, hh, ww, Wp, m, qv);
+      if (!kLow || fp64) {
+        if (adj) tail_apply_rows<RPT, NT, CH, true>(rsA, colA, roff, corner, sp, hh, ww, Wp, m, qv);
+        else tail_apply_rows<RPT, NT, CH, false>(rsA, colA, roff, corner, sp, hh, ww, Wp, m, qv);
+      } else {
+        const int ww4 = (ww + 3) & ~3;
+        if (adj) tail_apply_rows_q<RPT, NT, CHQ, true>(rsI, colI, roffI, corner, sp, hh, ww4, Wp, m, qv);
+        else tail_apply_rows_q<RPT, NT, CHQ, false>(rsI, colI, roffI, corner, sp, hh, ww4, Wp, m, qv);
+      }
 #pragma unroll
       for (int jj = 0; jj < RPT; ++jj) qv[jj] += sig1 * v[jj];
     };
     const int64_t base = (int64_t)s * st.ld;
     const double sig1 = 1.0 + st.sigma[s];
     const double bn = st.bnorm[s];
-    const double thresh = st.thresh[s];
+    const double thresh = resumed ? rs_thresh : st.thresh[s];
     // a start (r0 given) takes x = 0 and the residual r0 and begins with the first step's
     // preconditioned residual; a continuation reads x, r, p and r^T z of the batched loop
-    const double* r0 = d.r0;
+    // (a resumed sweep starts from the true residual its check left in st.r)
+    const double* r0 = resumed ? st.r : d.r0;
     double* uacc = d.uacc;
-    const bool start = r0 != nullptr;
+    const bool start = d.r0 != nullptr;
     double rz = start ? 0.0 : st.rz[s];
-    int it = st.iters[s];
+    const int it0 = resumed ? rs_it : st.iters[s];
+    int it = it0;
     double rv[RPT], pv[RPT], xv[RPT];
     double ph[kC], sph[kC];
 #pragma unroll
@@ -566,8 +672,6 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
     // the sweep's check of the new u: r = b - (1 + sigma) u - S u in FP64, kept for a further
     // sweep, and the status from ||r|| / ||b|| (every thread has left the loop's last LDS reads
     // behind the reductions' barriers)
-    const TailCheck& chk = d.chk;
-    const bool check = start && chk.b != nullptr;
     double rr = 0.0;
     if (check) {
       double qv[RPT];
@@ -585,9 +689,14 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
       const double rn = sqrt(tail_sum1<NT>(r2, sred1));
       rr = bn > 0.0 ? rn / bn : 0.0;
     }
+    const int nsw = check ? (resumed ? rs_nsw : chk.sweeps[s]) + 1 : 0;
+    // the next sweep runs here only after a converged inner solve (breakdowns and the iteration
+    // cap go to the status below)
+    const bool again = check && state == 1 && isfinite(rr) && !(rr <= chk.rtol) && it < st.max_iter && !chk.fixed &&
+                       chk.max_sweeps > 0 && nsw < chk.max_sweeps;
     if (tid == 0) {
       if (st.prof.vectors) {
-        const int done_its = it - st.iters[s];
+        const int done_its = it - it0;
         atomicAdd(st.prof.vectors, (unsigned long long)done_its);
         atomicAdd(st.prof.flops, (double)(done_its + (check ? 1 : 0)) * st.prof.flops_per_vector);
         atomicAdd(st.prof.bytes, st.prof.bytes_per_vector);
@@ -598,7 +707,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
         st.relres[s] = relres;
         st.done[s] = state;
       } else {
-        chk.sweeps[s] += 1;
+        chk.sweeps[s] = nsw;
         st.relres[s] = relres;
         chk.relres[s] = rr;
         if (!isfinite(rr)) {
@@ -619,6 +728,13 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
           st.thresh[s] = chk.fixed ? 0.0 : (kLow ? fmax(chk.inner_rtol * rr * bn, target) : target);
         }
       }
+    }
+    if (again) {
+      rs_e = e;
+      rs_it = it;
+      rs_nsw = nsw;
+      const double target = 0.5 * chk.rtol * bn;
+      rs_thresh = kLow ? fmax(chk.inner_rtol * rr * bn, target) : target;
     }
     __syncthreads();
   }
@@ -760,7 +876,7 @@ int tail_threads(int64_t m) { return m > 2048 ? 1024 : (m > 512 ? 512 : (m > 256
 // the padded direction
 size_t tail_lds_bytes(const TailApply& ap) {
   const int64_t npad = ap.kind == 0 ? (int64_t)(ap.g.nz + 2 * ap.g.bz) * (ap.g.nx + 2 * ap.g.bx) : ap.m;
-  return (size_t)npad * sizeof(double);
+  return (size_t)(npad + kTailSlack) * sizeof(double);
 }
 
 // LDS (static and dynamic) the launcher lets one workgroup take: the kernel runs one workgroup
@@ -923,6 +1039,37 @@ bool tail_fits(const TailApply& ap) {
     if ((g.pz && g.bz > g.nz) || (g.px && g.bx > g.nx)) return false;
   }
   return (int64_t)(tail_lds_bytes(ap) / sizeof(double)) <= kTailPadMax;
+}
+
+namespace {
+
+// One thread per (column of quads, row): four entries rounded to FP32 and stored as one 16-byte
+// word.
+__global__ void k_pack_quads(const double* __restrict__ src, int64_t hh, int64_t ww, int64_t ld, int64_t m,
+                             float4* __restrict__ dst) {
+  const int64_t wq = (ww + 3) / 4;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= hh * wq * ld) return;
+  const int64_t r = i % ld, c = i / ld;
+  const int64_t li = c / wq, k0 = (c % wq) * 4;
+  float v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t k = k0 + e;
+    v[e] = (k < ww && r < m) ? (float)src[(li * ww + k) * ld + r] : 0.0f;
+  }
+  dst[i] = float4{v[0], v[1], v[2], v[3]};
+}
+
+}  // namespace
+
+hipError_t launch_pack_quads(const double* src, int64_t hh, int64_t ww, int64_t ld, int64_t m, float* dst,
+                             hipStream_t st) {
+  if (!src || !dst || hh < 1 || ww < 1 || ld < m || m < 1) return hipErrorInvalidValue;
+  const int64_t n = hh * ((ww + 3) / 4) * ld;
+  hipLaunchKernelGGL(k_pack_quads, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, hh, ww, ld, m,
+                     reinterpret_cast<float4*>(dst));
+  return hipGetLastError();
 }
 
 hipError_t launch_order_live(const int32_t* done, const double* sigma, int64_t S, int64_t G, int32_t* act,
