@@ -64,6 +64,16 @@ __device__ inline double tail_sum1(double v, double (*sred)[NT / 64]) {
 // lanes combines them by DPP.  Fewer cross-lane steps than Wn wavefront sums.
 __host__ __device__ constexpr bool tail_lds_sums(int Wn, int NT) { return Wn > 1 && Wn * NT * 8 <= 96 * 1024; }
 
+// One reduction an iteration (up to 4 Ritz pairs, where its 4p + 4 sums fit in LDS): the sums of
+// the new direction's apply q (p^T q, q^T q, r^T q, Phi^T q, (S Phi)^T q) and of the current
+// residual (r^T r, Phi^T r, (S Phi)^T r) in one pass; the next residual's dots follow from them
+// and the step length.  Otherwise p^T q and the residual's dots are two reductions.
+__host__ __device__ constexpr bool tail_merged(int P, int NT) { return P <= 4 && tail_lds_sums(4 * P + 4, NT); }
+// Doubles a thread writes for the LDS sums (0: the sums go through wavefront partials).
+__host__ __device__ constexpr int tail_sum_words(int P, int NT) {
+  return tail_merged(P, NT) ? 4 * P + 4 : (tail_lds_sums(2 * P + 1, NT) ? 2 * P + 1 : 0);
+}
+
 template <int Wn, int NT>
 __device__ inline void tail_sums_lds(const double* v, double* part, double* out_lds) {
   constexpr int G = 16;
@@ -74,9 +84,16 @@ __device__ inline void tail_sums_lds(const double* v, double* part, double* out_
   for (int u = tid; u < Wn * G; u += NT) {  // whole rows of 16 lanes stay active together
     const int j = u / G, c = u % G;
     const double* pj = part + j * NT + c;
-    double t = 0.0;
+    // four independent chains (a fixed order), then their sum
+    constexpr int KC = NT / G >= 8 ? 4 : 1;
+    double tc[KC];
 #pragma unroll
-    for (int k = 0; k < NT / G; ++k) t += pj[G * k];
+    for (int i = 0; i < KC; ++i) tc[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / G; ++k) tc[k % KC] += pj[G * k];
+    double t = tc[0];
+#pragma unroll
+    for (int i = 1; i < KC; ++i) t += tc[i];
     t += dpp_f64<0xB1, 0xF>(t);   // quad_perm [1,0,3,2]
     t += dpp_f64<0x4E, 0xF>(t);   // quad_perm [2,3,0,1]
     t += dpp_f64<0x141, 0xF>(t);  // row_half_mirror
@@ -335,6 +352,8 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
   // the Ritz vectors of the thread's rows stay in registers when they fit
   constexpr bool kCache = tail_caches_ritz(P, RPT, NT);
   constexpr bool kLdsSums = tail_lds_sums(2 * P + 1, NT);
+  constexpr bool kMerged = tail_merged(P, NT);
+  constexpr int WM = 4 * P + 4;
   constexpr int kC = kCache ? RPT * P : 1;
   constexpr bool kLow = sizeof(BT) == 4;
   __shared__ double sred1[1][NW];
@@ -342,7 +361,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
   __shared__ double sG[3 * P * P + P + 1];
   __shared__ double scoef[2 * P + 2];
   __shared__ double sM[P * P + 1];
-  __shared__ double sdot[W];
+  __shared__ double sdot[kMerged ? WM : W];
   __shared__ int s_idx;
   // padded direction (band) or direction (dense S); then the partial sums and, when phi_lds, the
   // Ritz bases
@@ -358,6 +377,9 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
   Grid g{};
   int Wp = 0, npad = 0, nh = 0, hh = 1, ww = 1, phi_lds = 0;
   bool adj = false;  // every row pair's stencils are one entry apart
+  // the wrapped copies of a row's direction entry are written with it (no halo pass) where each
+  // periodic axis is at least twice its stencil reach: then an entry has at most 3 copies
+  bool hdirect = false;
   double dmin = 0.0;
   __amdgpu_buffer_rsrc_t rsA = tail_rsrc(nullptr, 0), rsI = rsA, rsF = rsA, rsG = rsA;
   uint32_t colA = 0, colI = 0, colF = 0;
@@ -367,6 +389,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
   // its last pair one row into the column's padding, ld >= m + 1) and of each row in a column of
   // quads of the packed FP32 band (rows past m read row m - 1)
   int corner[RPT];
+  int hcode[RPT];  // a row's wrapped copies: bit 0 along z, bit 1 its sign (-nz); bits 2, 3 along x
   uint32_t roff[RPT / 2], roffI[RPT];
 
   // the instance's layout, its preconditioner's small matrices, the zero halo of the padded
@@ -386,6 +409,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
       hh = band ? h : 1;
       ww = band ? w : (int)m;
       adj = band && g.nx % 2 == 0;
+      hdirect = band && nh > 0 && (!g.px || g.nx >= 2 * g.bx) && (!g.pz || g.nz >= 2 * g.bz);
       phi_lds = d.phi_lds;
       if (P > 0) {
         for (int o = tid; o < 3 * P * P; o += NT) sG[o] = lmp.G[o];
@@ -404,7 +428,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
       rsG = tail_rsrc(lmp.SPhi, (int64_t)P * lmp.ld * 8);
       colF = (uint32_t)(lmp.ld * 8);
       part = sp + npad + kTailSlack;        // W x NT partial sums
-      sF = part + (kLdsSums ? W * NT : 0);  // Phi (P x m), when phi_lds
+      sF = part + tail_sum_words(P, NT) * NT;  // Phi (P x m), when phi_lds
       sH = sF + (int64_t)P * m;             // S Phi (P x m)
       if (phi_lds) {
         for (int o = tid; o < P * (int)m; o += NT) {
@@ -417,6 +441,16 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
       for (int jj = 0; jj < RPT; ++jj) {
         const int r = tail_row<NT>(tid, jj);
         corner[jj] = (band && r < m) ? (r / g.nx) * Wp + r % g.nx : 0;
+        // the row's wrapped copies: at z + nz or z - nz along a periodic z within bz of an end,
+        // at x + nx or x - nx likewise along x, and both together (every copy but the interior one)
+        hcode[jj] = 0;
+        if (hdirect && r < m) {
+          const int z = r / g.nx, x = r % g.nx;
+          if (g.pz && z < g.bz) hcode[jj] |= 1;
+          else if (g.pz && z >= g.nz - g.bz) hcode[jj] |= 3;
+          if (g.px && x < g.bx) hcode[jj] |= 4;
+          else if (g.px && x >= g.nx - g.bx) hcode[jj] |= 12;
+        }
         roffI[jj] = (uint32_t)min<int64_t>(r, m - 1) * 16u;
       }
 #pragma unroll
@@ -466,10 +500,20 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
 #pragma unroll
       for (int jj = 0; jj < RPT; ++jj) {
         const int r = tail_row<NT>(tid, jj);
-        if (r < m) sp[band ? corner[jj] + g.bz * Wp + g.bx : r] = v[jj];
+        if (r < m) {
+          const int at = band ? corner[jj] + g.bz * Wp + g.bx : r;
+          sp[at] = v[jj];
+          const int hc = hcode[jj];
+          if (hc != 0) {
+            const int dz = (hc & 2) ? -g.nz * Wp : g.nz * Wp, dx = (hc & 8) ? -g.nx : g.nx;
+            if (hc & 1) sp[at + dz] = v[jj];
+            if (hc & 4) sp[at + dx] = v[jj];
+            if ((hc & 5) == 5) sp[at + dz + dx] = v[jj];
+          }
+        }
       }
       __syncthreads();
-      if (nh > 0) {
+      if (nh > 0 && !hdirect) {
         for (int t = tid; t < nh; t += NT) {
           int dst, src;
           if (tail_halo(g, Wp, t, dst, src)) sp[dst] = sp[src];
@@ -531,6 +575,134 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
     int state = 0;
     double relres = 0.0;
     bool first = start;
+    if constexpr (kMerged) {
+    // 1 / (1 + sigma + theta_l) for this system
+    double rth[P > 0 ? P : 1];
+#pragma unroll
+    for (int l = 0; l < P; ++l) rth[l] = 1.0 / (sig1 + sG[3 * P * P + l]);
+    for (;;) {
+      // the apply (the first pass of a start only prepares p: q = 0), then one reduction
+      double qv[RPT];
+      if (!first) apply_C(pv, sig1, qv, false);
+      else {
+#pragma unroll
+        for (int jj = 0; jj < RPT; ++jj) qv[jj] = 0.0;
+      }
+      // sums: 0 p^T q, 1 q^T q, 2 r^T q, 3 r^T r, then Phi^T q, (S Phi)^T q, Phi^T r, (S Phi)^T r
+      double acc[WM];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) acc[i] = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < RPT; ++jj) {
+        const int64_t r = tail_row<NT>(tid, jj);
+        if (r < m) {
+          const double rj = rv[jj], qj = qv[jj];
+          acc[0] += pv[jj] * qj;
+          acc[1] += qj * qj;
+          acc[2] += rj * qj;
+          acc[3] += rj * rj;
+#pragma unroll
+          for (int l = 0; l < P; ++l) {
+            const double a = kCache ? ph[(jj * P + l) % kC]
+                                    : (phi_lds ? sF[l * m + r] : tail_ld8(rsF, (uint32_t)r * 8, l * colF));
+            const double b = kCache ? sph[(jj * P + l) % kC]
+                                    : (phi_lds ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
+            acc[4 + l] += a * qj;
+            acc[4 + P + l] += b * qj;
+            acc[4 + 2 * P + l] += a * rj;
+            acc[4 + 3 * P + l] += b * rj;
+          }
+        }
+      }
+      tail_sums_lds<WM, NT>(acc, part, sdot);
+      const double* dt = sdot;
+      // the step: r <- r - alpha q, and the new residual's dots from the old ones
+      //   r'^T r' = r^T r - alpha (2 r^T q - alpha q^T q),  Phi^T r' = Phi^T r - alpha Phi^T q, ...
+      double alpha = 0.0;
+      if (!first) {
+        const double tot = dt[0];
+        if (!(tot > 0.0) || !isfinite(tot)) {
+          if (tid == 0) atomicOr(st.flags, isfinite(tot) ? kFlagNotSPD : kFlagNumeric);
+          state = 2;
+          break;
+        }
+        alpha = rz / tot;
+#pragma unroll
+        for (int jj = 0; jj < RPT; ++jj) {
+          if (tail_row<NT>(tid, jj) < m) {
+            xv[jj] += alpha * pv[jj];
+            rv[jj] -= alpha * qv[jj];
+          }
+        }
+        ++it;
+      }
+      const double rr = fmax(dt[3] - alpha * (2.0 * dt[2] - alpha * dt[1]), 0.0);
+      const double rn = sqrt(rr);
+      relres = bn > 0.0 ? rn / bn : 0.0;
+      if (!isfinite(rr)) {
+        if (tid == 0) atomicOr(st.flags, kFlagNumeric);
+        state = 2;
+        break;
+      }
+      if (rn <= thresh) {
+        state = 1;
+        break;
+      }
+      if (it >= st.max_iter) {
+        state = 2;
+        break;
+      }
+      // the preconditioner's coefficients (as in the fused step), in every thread:
+      //   c1 = Theta^{-1} Phi^T r,  c2 = Theta^{-1} [(C Phi)^T r - M(sigma) c1],
+      //   gamma = (1 + sigma - beta_L) c1 + c2,  z = r - S Phi c1 - Phi gamma
+      double c1[P > 0 ? P : 1], gm[P > 0 ? P : 1];
+      double rzn = rr;
+      if (P > 0) {
+        const double beta_l = sig1 + dmin;
+#pragma unroll
+        for (int l = 0; l < P; ++l) c1[l] = (dt[4 + 2 * P + l] - alpha * dt[4 + l]) * rth[l];
+        double tsum = 0.0;
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+          double mc = 0.0;
+#pragma unroll
+          for (int j2 = 0; j2 < P; ++j2) mc += sM[l * P + j2] * c1[j2];
+          const double phr = dt[4 + 2 * P + l] - alpha * dt[4 + l];
+          const double sphr = dt[4 + 3 * P + l] - alpha * dt[4 + P + l];
+          const double c2 = (sphr + sig1 * phr - mc) * rth[l];
+          gm[l] = (sig1 - beta_l) * c1[l] + c2;
+          tsum += sphr * c1[l] + phr * gm[l];
+        }
+        rzn -= tsum;
+      }
+      if (!(rzn > 0.0) || !isfinite(rzn)) {
+        if (tid == 0) atomicOr(st.flags, isfinite(rzn) ? kFlagNotSPD : kFlagNumeric);
+        state = 2;
+        break;
+      }
+      const double beta = first ? 0.0 : rzn / rz;
+      rz = rzn;
+      first = false;
+#pragma unroll
+      for (int jj = 0; jj < RPT; ++jj) {
+        const int64_t r = tail_row<NT>(tid, jj);
+        if (r < m) {
+          double z = rv[jj];
+#pragma unroll
+          for (int l = 0; l < P; ++l) {
+            const double a = kCache ? ph[(jj * P + l) % kC]
+                                    : (phi_lds ? sF[l * m + r] : tail_ld8(rsF, (uint32_t)r * 8, l * colF));
+            const double b = kCache ? sph[(jj * P + l) % kC]
+                                    : (phi_lds ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
+            z -= b * c1[l] + a * gm[l];
+          }
+          pv[jj] = z + beta * pv[jj];
+        }
+      }
+      // no barrier here: every thread has read the LDS direction and sdot before the next
+      // direction's barrier, and part and sdot are rewritten only after it
+    }
+    } else {
     for (;;) {
       if (!first) {  // the apply and the step (the first pass of a start only prepares p)
         double qv[RPT];
@@ -651,6 +823,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
       // no barrier here: every thread read the LDS direction before the first reduction's
       // barrier, and sred1, sredW, sdot and scoef are rewritten only after the next direction's
     }
+    }  // kMerged
     // a start adds its correction to the solution; a continuation hands x, r, p back to the
     // batched loop, which adds x
     double un[RPT];
@@ -903,7 +1076,7 @@ hipError_t tail_static_lds(const void* fn, std::atomic<size_t>& cache, size_t* o
 template <int P, int RPT, int NT>
 size_t tail_inst_lds(TailInst& d, size_t stat) {
   size_t lds = tail_lds_bytes(d.ap);
-  if (tail_lds_sums(2 * P + 1, NT)) lds += (size_t)(2 * P + 1) * NT * sizeof(double);
+  lds += (size_t)tail_sum_words(P, NT) * NT * sizeof(double);
   if (stat + lds > kTailLdsBig) return 0;
   const size_t phi = (size_t)16 * P * d.st.m;
   d.phi_lds = (P > 0 && !tail_caches_ritz(P, RPT, NT) && stat + lds + phi <= kTailLdsBig) ? 1 : 0;
