@@ -47,7 +47,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default=None,
+                    help="inner applies: fp64, or fp32/bf16 with FP64 residual sweeps (default: fp32 for the "
+                         "n4096 and batched64 workloads, fp64 for the cycles)")
     ap.add_argument("--domain", choices=["state", "lattice"], default="lattice")
     ap.add_argument("--solver", choices=["plain", "compact", "multishift", "block"], default="compact",
                     help="compact: batched PCG with the limited-memory preconditioner (default); plain: the "
@@ -68,6 +70,13 @@ def parse():
                          "paper-sec5-cycle: the cycled experiment of Sec. 5 (32 x 40 atmosphere, 40 "
                          "members, 40 vertical channels, 10 fixed PCG iterations, p = 10)")
     ap.add_argument("--graph", action="store_true", help="lorenz-cycle: replay a HIP graph of one cycle")
+    ap.add_argument("--eager", action="store_true",
+                    help="n4096: time host-synchronized calls instead of replays of a captured update")
+    ap.add_argument("--no-fp64-line", action="store_true", help="n4096: skip the FP64 line beside a mixed one")
+    ap.add_argument("--no-learned", action="store_true", help="n4096: skip the learned+mixed line")
+    ap.add_argument("--learn-updates", type=int, default=24,
+                    help="n4096 learned line: n = 4096 updates (other seeds) whose 640 systems each train the net")
+    ap.add_argument("--learn-steps", type=int, default=1500, help="n4096 learned line: Adam steps of 8 members")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in block-shape rules")
     ap.add_argument("--n-ritz", type=int, default=None,
                     help="Ritz pairs of the limited-memory preconditioner (default: 4 for the n = 4096 workload, "
@@ -222,6 +231,8 @@ def main():
     import synthetic as syn
     from paper_2503_00253_amd import infoesrf as ie
 
+    if a.precision is None:
+        a.precision = "fp32" if a.workload in ("n4096", "batched64") else "fp64"
     prec = {"fp64": ie.FP64, "fp32": ie.MIXED_FP32, "bf16": ie.MIXED_BF16}[a.precision]
     if a.workload == "batched64":
         return bench_batched(a, prec)
@@ -343,11 +354,58 @@ def main():
                           "fp64_sweeps": st.counter(ie.CNT_SWEEPS)},
            "roofline": roof}
 
+    if not a.eager:
+        # the same update captured once without host synchronization and replayed: the setup's
+        # launches cost no host time.  The roofline above comes from the eager steps (the graph
+        # holds the same kernels with the same arguments); every replay must reproduce the eager
+        # result, and the device statistics after the replays must show every system converged.
+        gvalue, gms, gres, gst = time_replays(ie, torch, P, s, p, kw, a.steps, systems)
+        gdiff = float((gres - run.result()).norm() / run.result().norm())
+        assert gdiff <= 1e-12, f"graph replay differs from the eager update: {gdiff}"
+        out["eager"] = {"value": out["value"], "ms_per_step": out["ms_per_step"]}
+        out["value"] = round(gvalue, 2)
+        out["ms_per_step"] = round(gms, 4)
+        out["config"]["graph"] = True
+        out["roofline"]["time_share"] = round(roof["avg_launch_ms"] / gms, 4)
+        value = gvalue
+        log(f"graph replay: {gvalue:.1f} solves/s, {gms:.3f} ms/step, rel diff vs eager {gdiff:.2e}")
+    else:
+        out["config"]["graph"] = False
+
+    if prec != ie.FP64 and not a.no_fp64_line:
+        # the same options with FP64 inner applies: the mixed line's error against it, per member
+        fkw = dict(kw, precision=ie.FP64)
+        if a.eager:
+            frun = ie.PerturbationRunner(P, s, p, ie.default_opts(**fkw))
+            frun.run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(a.steps):
+                fcode = frun.run()
+            torch.cuda.synchronize()
+            fms = (time.perf_counter() - t0) * 1e3 / a.steps
+            fst, fres = frun.stats(fcode), frun.result()
+            fvalue = systems * 1e3 / fms
+        else:
+            fvalue, fms, fres, fst = time_replays(ie, torch, P, s, p, fkw, a.steps, systems)
+        assert fst.counter(ie.CNT_NOT_CONVERGED) == 0, "FP64 line: systems missed rtol"
+        col = ((run.result() - fres).norm(dim=0) / fres.norm(dim=0)).max()
+        out["fp64_line"] = {"value": round(fvalue, 2), "unit": "solves/s", "ms_per_step": round(fms, 4),
+                            "max_iterations": int(fst.iters.max()),
+                            "mixed_vs_fp64_rel_err": float((run.result() - fres).norm() / fres.norm()),
+                            "mixed_vs_fp64_max_member_rel_err": float(col),
+                            "mixed_speedup": round(value / fvalue, 3)}
+        log("FP64 line", out["fp64_line"])
+
+    if not a.no_learned:
+        out["learned_mixed"] = learned_line(a, ie, torch, syn, P, s, p, kw, run, st, systems)
+        log("learned line", out["learned_mixed"])
+
     if not a.no_compare and a.solver == "compact":
         # Sec. 3.2's alternatives on the same workload and options, to the same true FP64 residual
         comp = {}
         for name in ("block", "multishift"):
-            okw = dict(kw, solver=SOLVERS[name])
+            okw = dict(kw, solver=SOLVERS[name], precision=ie.FP64)   # both run FP64 inner solves
             if name == "multishift":
                 okw.pop("n_ritz", None)
                 okw.pop("oversample", None)
@@ -382,6 +440,8 @@ def main():
         t1 = time.perf_counter()
         pv = systems * a.plain_steps / (t1 - t0)
         diff = float((run.result() - prun.result()).norm() / prun.result().norm())
+        if "learned_mixed" in out:
+            out["learned_mixed"]["speedup_vs_plain"] = round(out["learned_mixed"]["value"] / pv, 3)
         out["plain_gpu_pcg"] = {"value": round(pv, 2), "unit": "solves/s", "steps": a.plain_steps,
                                 "speedup": round(value / pv, 3), "rel_diff_vs_plain": diff,
                                 "options": f"FP64, operator form sum_i z_i o L(z_i o v) in the state space, masked "
@@ -415,6 +475,89 @@ def main():
         out["cpu_baseline"] = cpu_baseline(a)
         log("cpu baseline", out["cpu_baseline"])
     print(json.dumps(out), flush=True)
+
+
+def time_replays(ie, torch, P, s, p, kw, steps, systems):
+    """One update with these options captured without host synchronization, replayed twice, then
+    timed over `steps` replays: (solves/s, ms per update, result, device statistics)."""
+    grun = ie.PerturbationRunner(P, s, p, ie.default_opts(host_sync=0, **kw))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        grun.run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        grun.run()
+    torch.cuda.synchronize()
+    for _ in range(2):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gst = grun.stats(0)
+    assert gst.counter(ie.CNT_NOT_CONVERGED) == 0, "graph replay: systems missed rtol"
+    ms = (t1 - t0) * 1e3 / steps
+    return systems * 1e3 / ms, ms, grun.result().clone(), gst
+
+
+def learned_line(a, ie, torch, syn, P, s, p, kw, run, st, systems):
+    """The learned start on the line's options: a network trained here, on the GPU by the
+    library's kernels, on the systems of other n = 4096 updates (seeds 1..k), then the update run
+    from its start (host-synchronized, eager) against the zero start timed the same way."""
+    import numpy as np
+
+    t0 = time.perf_counter()
+    Xs, Ts, cq = [], [], None
+    for seed in range(1, 1 + a.learn_updates):
+        pr = syn.config2(seed)
+        Pj = ie.Problem.from_synthetic(pr)
+        okw = dict(kw)
+        if "lattice" in okw:
+            okw["lattice"] = Pj.lattice()
+        X, cq, T, wst = ie.warmstart_pairs(Pj, s, p, None, ie.default_opts(**okw))
+        assert wst.code == ie.OK
+        Xs.append(X)
+        Ts.append(T)
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    gen_s = time.perf_counter() - t0
+    net = ie.Net.create(64, 9, 2503)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    t0 = time.perf_counter()
+    for step in range(a.learn_steps):
+        idx = torch.randint(0, X.shape[0], (8,), generator=g).cuda()
+        lr = 2e-3 * (0.1 + 0.9 * 0.5 * (1 + np.cos(np.pi * step / a.learn_steps)))
+        net.train_step(X[idx].contiguous(), cq, T[idx].contiguous(), lr)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    def eager(opts):
+        r = ie.PerturbationRunner(P, s, p, opts)
+        r.run()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(a.steps):
+            code = r.run()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / a.steps
+        rst = r.stats(code)
+        assert rst.counter(ie.CNT_NOT_CONVERGED) == 0, "learned line: systems missed rtol"
+        return systems * 1e3 / ms, ms, rst, r.result()
+
+    lv, lms, lst, lres = eager(ie.default_opts(warm_start=ie.START_LEARNED, net=net, **kw))
+    zv, zms, zst, _ = eager(ie.default_opts(**kw))
+    return {"value": round(lv, 2), "unit": "solves/s", "ms_per_step": round(lms, 4),
+            "zero_start_value": round(zv, 2), "zero_start_ms_per_step": round(zms, 4),
+            "mean_iterations": {"zero": round(float(zst.iters.mean()), 3), "learned": round(float(lst.iters.mean()), 3)},
+            "max_iterations": {"zero": int(zst.iters.max()), "learned": int(lst.iters.max())},
+            "rel_diff_vs_line": float((lres - run.result()).norm() / run.result().norm()),
+            "train": {"pairs": int(T.shape[0] * T.shape[1]), "updates": a.learn_updates, "steps": a.learn_steps,
+                      "pair_seconds": round(gen_s, 2), "train_seconds": round(train_s, 2)},
+            "timing": "both host-synchronized calls (no graph), same options as the line"}
 
 
 def bench_cycle(a, prec):

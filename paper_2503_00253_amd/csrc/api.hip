@@ -1563,9 +1563,11 @@ int stage_solve(Plan& pl, const Options& op, hipStream_t st, const Finalize* fin
     }
     if (sweep == max_sweeps) break;
     if (persist) {
-      // one persistent launch runs every iteration of every live system and adds into u
+      // one persistent launch runs every iteration of every live system and adds into u, its
+      // sweeps included (the kernel restarts a system from its true residual while that is above
+      // rtol and the budget allows); a further launch would skip every system it left
       IE_TRY(run_tail(sy.act, sy.nact, plain ? S : (int64_t)h_nact, rcur));
-      continue;
+      break;
     }
     // inner solve on C d = r from d = 0: the multi-shift process first when asked, else PCG
     IE_HIP(launch_fill_f64(sy.x, 0.0, flat, st));
@@ -1870,7 +1872,7 @@ bool batch_one_launch(const infoesrf_problem* probs, int count, const int32_t* Q
 // counters.
 struct BatchArea {
   TailInst* table;
-  int32_t *seg, *list, *cnt, *words;  // words: live count, queue counter, live total
+  int32_t *seg, *list, *cnt, *words;  // words: live count and queue counter of each class
   int64_t* total;                     // summed counters
   size_t bytes;
 };
@@ -1882,7 +1884,7 @@ BatchArea batch_area(char* base, int count, int64_t systems) {
   b.seg = ar.take<int32_t>(systems);
   b.list = ar.take<int32_t>(systems);
   b.cnt = ar.take<int32_t>(count);
-  b.words = ar.take<int32_t>(8);
+  b.words = ar.take<int32_t>(4);
   b.total = ar.take<int64_t>(INFOESRF_NUM_COUNTERS);
   b.bytes = ar.off + 256;
   return b;
@@ -1991,41 +1993,28 @@ int batched_one_launch(const infoesrf_problem* probs, int count, const int32_t* 
   if (!big.empty()) classes.push_back(big);
   if (!small.empty()) classes.push_back(small);
   const int nl = (int)live.size();
-  // the sweeps: each launch iterates every live system to its inner target, adds the correction
-  // into u and checks the true FP64 residual; a later sweep restarts from that residual
+  // one launch per class runs every sweep: each workgroup iterates a system to its inner target,
+  // adds the correction into u, checks the true FP64 residual and, while that is above rtol and
+  // the instance's sweep budget allows, restarts from it at once.  A system that spends its
+  // budget stays live and is reported not converged; a further launch would skip it.
   if (nl > 0) {
-    const Options& o0 = op[live[0]];
-    const int max_sweeps = o0.fixed > 0 ? 1 : (host_sync ? 40 : (o0.inner == Prec::F64 ? 2 : 4));
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-      int t0 = 0;
-      int64_t s0 = 0;
-      for (size_t c = 0; c < classes.size(); ++c) {
-        const std::vector<int>& cl = classes[c];
-        std::vector<TailInst> ordered(cl.size());
-        int64_t segc = 0;
-        for (size_t k = 0; k < cl.size(); ++k) {
-          ordered[k] = desc[cl[k]];
-          ordered[k].seg = segc;
-          segc += ordered[k].st.S;
-          if (sweep > 0) ordered[k].r0 = pl[cl[k]].sy.r;
-        }
-        // the launch writes the table, builds the queue (live systems instance by instance,
-        // largest first) and iterates
-        IE_HIP(launch_pcg_tail_multi(ordered.data(), (int)cl.size(), ba.table + t0, ba.seg + s0, ba.cnt + t0,
-                                     ba.list + s0, ba.words + 2 * c, ba.words + 2 * c + 1, segc, st));
-        t0 += (int)cl.size();
-        s0 += segc;
+    int t0 = 0;
+    int64_t s0 = 0;
+    for (size_t c = 0; c < classes.size(); ++c) {
+      const std::vector<int>& cl = classes[c];
+      std::vector<TailInst> ordered(cl.size());
+      int64_t segc = 0;
+      for (size_t k = 0; k < cl.size(); ++k) {
+        ordered[k] = desc[cl[k]];
+        ordered[k].seg = segc;
+        segc += ordered[k].st.S;
       }
-      if (host_sync && sweep + 1 < max_sweeps) {
-        HostStage* hs = host_stage();
-        hipEvent_t he = host_event();
-        IE_CHECK(hs && he, INFOESRF_ERR_HIP, "pinned host staging or event creation failed");
-        IE_HIP(launch_batch_live_total(ba.table, nl, ba.words + 4, st));
-        IE_HIP(hipMemcpyAsync(&hs->nact, ba.words + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        IE_HIP(hipEventRecord(he, st));
-        IE_HIP(hipEventSynchronize(he));
-        if (hs->nact == 0) break;
-      }
+      // the launch writes the table, builds the queue (live systems instance by instance,
+      // largest first) and iterates
+      IE_HIP(launch_pcg_tail_multi(ordered.data(), (int)cl.size(), ba.table + t0, ba.seg + s0, ba.cnt + t0,
+                                   ba.list + s0, ba.words + 2 * c, ba.words + 2 * c + 1, segc, st));
+      t0 += (int)cl.size();
+      s0 += segc;
     }
   }
   // per instance: u_bar_i = sum_q p_q u_{q,i} (and the mean's u as column N), the final updates

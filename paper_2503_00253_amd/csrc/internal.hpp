@@ -434,8 +434,6 @@ constexpr int kTailSysBits = 20;
 // them.  All instances share the Ritz-basis count and the iterations' precision; m <= 4096.
 hipError_t launch_pcg_tail_multi(TailInst* descs, int count, TailInst* table, int32_t* seg, int32_t* cnt,
                                  int32_t* list, int32_t* nact, int32_t* qctr, int64_t grid, hipStream_t st);
-// *total = the live systems (done == 0) of the count instances of the device table.
-hipError_t launch_batch_live_total(const TailInst* table, int count, int32_t* total, hipStream_t st);
 // launch_pcg_tail with the measurement hook (profile slot INFOESRF_PROF_TAIL).
 hipError_t pcg_tail_timed(const PCGState& s, const LMP& lmp, const TailApply& ap, const int32_t* act,
                           const int32_t* nact, int32_t* qctr, int64_t grid, const double* r0, double* uacc,

@@ -1027,21 +1027,6 @@ __global__ __launch_bounds__(1024) void k_batch_pack(const TailInst* __restrict_
   }
 }
 
-// The number of live systems (done == 0) over every instance of the table, into *total.  One
-// workgroup (a fixed summation order).
-__global__ __launch_bounds__(1024) void k_batch_live_total(const TailInst* __restrict__ table, int count,
-                                                           int32_t* __restrict__ total) {
-  __shared__ int swave[16];
-  __shared__ int sum;
-  int32_t c = 0;
-  for (int j = 0; j < count; ++j) {
-    const int32_t* done = table[j].st.done;
-    for (int64_t s = threadIdx.x; s < table[j].st.S; s += 1024) c += done[s] == 0;
-  }
-  block_exclusive_scan<1024>(c, swave, &sum);
-  if (threadIdx.x == 0) *total = sum;
-}
-
 // two rows a thread (one pair) up to 1024 rows, on 128, 256 or 512 threads; four rows on 512 or
 // 1024 threads beyond
 int tail_threads(int64_t m) { return m > 2048 ? 1024 : (m > 512 ? 512 : (m > 256 ? 256 : 128)); }
@@ -1264,12 +1249,6 @@ hipError_t launch_pcg_tail(const PCGState& s, const LMP& lmp, const TailApply& a
   d.r0 = r0;
   d.uacc = uacc;
   return tail_dispatch(&d, 1, nullptr, act, nact, qctr, grid, st, []() { return hipSuccess; });
-}
-
-hipError_t launch_batch_live_total(const TailInst* table, int count, int32_t* total, hipStream_t st) {
-  if (!table || !total || count < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_batch_live_total, dim3(1), dim3(1024), 0, st, table, count, total);
-  return hipGetLastError();
 }
 
 hipError_t launch_pcg_tail_multi(TailInst* descs, int count, TailInst* table, int32_t* seg, int32_t* cnt,

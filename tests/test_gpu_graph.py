@@ -62,3 +62,43 @@ def test_graph_replays_match_eager(precision, domain):
     ref_opts = ie.default_opts(**{k: v for k, v in kw.items() if k != "host_sync"})
     want, _ = ie.perturbation_update(P, s, p, ref_opts)
     assert torch.equal(want, eager)
+
+
+@pytest.mark.parametrize("precision", [ie.FP64, ie.MIXED_FP32])
+def test_graph_replays_persistent_headline(precision):
+    """The n = 4096 update with the bench's options (observed-lattice band, every system in
+    the persistent kernel from its zero start, p = 4 + 4): one persistent launch per update
+    runs every sweep, so the captured graph holds no host-decided launch count; each replay
+    must equal the eager result bit for bit and the host-synchronized call too."""
+    prob = syn.config2()
+    P = ie.Problem.from_synthetic(prob)
+    s, p = ie.quadrature_elliptic(prob.Q, prob.ell)
+    kw = dict(precision=precision, apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=P.lattice(), n_ritz=4,
+              oversample=4, tail_systems=0)
+    say("graph headline", precision)
+    run = ie.PerturbationRunner(P, s, p, ie.default_opts(host_sync=0, **kw))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        assert run.run() == ie.OK
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    eager = run.result().clone()
+    st = run.stats()
+    assert st.counter(ie.CNT_STATUS) == 0 and st.counter(ie.CNT_NOT_CONVERGED) == 0
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run.run()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        run.out.fill_(float("nan"))
+        run.keep[3].zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        say("replay", rep)
+        assert torch.equal(run.result(), eager), rep
+        st = run.stats()
+        assert st.counter(ie.CNT_STATUS) == 0 and st.counter(ie.CNT_NOT_CONVERGED) == 0
+    want, _ = ie.perturbation_update(P, s, p, ie.default_opts(**kw))
+    assert torch.equal(want, eager)
