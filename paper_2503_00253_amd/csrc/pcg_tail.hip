@@ -344,11 +344,12 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
   constexpr int W = 2 * P + 1;
   constexpr int NW = NT / 64;
   static_assert(RPT % 2 == 0, "rows come in pairs");
-  // band (or S) entries per chunk: RPT / 2 * CH loads of FP64 pairs in flight per thread (fewer
-  // where the per-instance values of a launch over many instances take registers); the packed
-  // FP32 band takes RPT * CHQ / 4 loads of as many bytes
-  constexpr int CH = RPT >= 4 ? (MULTI ? 4 : 8) : 16;
-  constexpr int CHQ = RPT >= 4 ? (MULTI ? 8 : 16) : 32;
+  // band (or S) entries per chunk: RPT / 2 * CH loads of FP64 pairs per thread, RPT * CHQ / 4
+  // loads of the packed FP32 band.  Short chunks measured fastest at the n = 4096 lattice (the
+  // FP64 kernel 0.56 ms per launch with 8 entries against 0.67 ms with 16; FP32 0.45 ms with 8
+  // against 0.57 ms with 32)
+  constexpr int CH = RPT >= 4 ? 4 : 8;
+  constexpr int CHQ = 8;
   // the Ritz vectors of the thread's rows stay in registers when they fit
   constexpr bool kCache = tail_caches_ritz(P, RPT, NT);
   constexpr bool kLdsSums = tail_lds_sums(2 * P + 1, NT);
