@@ -985,7 +985,21 @@ hipEvent_t host_event() {
 }
 
 
-int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
+bool tail_inplace(const Plan& pl, const Options& op, TailApply& tap);
+
+// Whether a solve with these options hands every system to the persistent kernel from its first
+// sweep (the conditions stage_solve tests): then the batched loop's FP32 band is never applied.
+bool persistent_only(const Plan& pl, const Options& op) {
+  const Inst& in = pl.in;
+  TailApply tap{};
+  if (op.tail != INT32_MAX || op.solver != INFOESRF_SOLVER_COMPACT || !tail_inplace(pl, op, tap)) return false;
+  const double elem = op.inner == Prec::F32 ? 4.0 : 8.0;
+  const double bytes = in.sd ? elem * in.m * in.m : elem * in.m * (2 * in.go.bz + 1) * (2 * in.go.bx + 1);
+  return bytes <= 1024.0 * 1024;
+}
+
+// solve: the plan serves solves (the autotuner's plan times every apply, so it builds every band)
+int stage_setup(Plan& pl, const Options& op, hipStream_t st, bool solve = true) {
   Inst& in = pl.in;
   const infoesrf_problem* P = in.P;
   // 1. input checks (they read H only within its own CSR bounds): the flags and column counts
@@ -1064,7 +1078,8 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st) {
     if (in.bandS32) IE_HIP(launch_band_build(Prec::F32, in.gs, in.Z, in.n, in.N, in.bandS32, ld64(in.n), st));
     if (in.obs) {
       IE_HIP(launch_band_build(Prec::F64, in.go, in.Zt, in.m, in.N, in.bandO, ld64(in.m), st));
-      if (in.bandO32) IE_HIP(launch_band_build(Prec::F32, in.go, in.Zt, in.m, in.N, in.bandO32, ld64(in.m), st));
+      if (in.bandO32 && !(solve && persistent_only(pl, op)))
+        IE_HIP(launch_band_build(Prec::F32, in.go, in.Zt, in.m, in.N, in.bandO32, ld64(in.m), st));
       if (in.bandQ32)
         IE_HIP(launch_pack_quads(static_cast<const double*>(in.bandO), 2 * in.go.bz + 1, 2 * in.go.bx + 1, ld64(in.m),
                                  in.m, in.bandQ32, st));
@@ -2365,7 +2380,7 @@ int infoesrf_autotune(const infoesrf_problem* prob, int32_t Q, const infoesrf_op
   Plan pl;
   IE_TRY(plan_for(pl, prob, op, S, Q > 0 ? prob->N : 1, ws, ws_bytes));
   op.host_sync = 1;  // the tuner reads timings on the host
-  IE_TRY(stage_setup(pl, op, st));
+  IE_TRY(stage_setup(pl, op, st, /*solve=*/false));
   Inst& in = pl.in;
   IE_CHECK(!in.dense, INFOESRF_ERR_INVALID_ARG, "dense localization has nothing to tune");
   const Grid& g = in.obs ? in.go : in.gs;

@@ -335,8 +335,9 @@ __global__ void k_lmp_finish(const double* evals, const double* evec, int k, int
 // wavefront takes blocks of 4 rows (wave w of NW: rows 4 w, 4 w + 4 NW, ...) into one
 // v_mfma_f64_16x16x4f64 each (lane l brings column l % 16 of row 4 b + l / 16 of X and of Y: the
 // A operand (row l % 16, k l / 16) is X^T, the B operand (k l / 16, col l % 16) is Y), U blocks'
-// loads in flight before their products; then the NW wavefront tiles are added in order.
-// part: NW x 256 doubles of LDS; G complete on return.
+// loads in flight before their products; then the NW wavefront tiles are added in a fixed order
+// (wave w + NW / 2's into wave w's, then the NW / 2 sums in order).
+// part: NW / 2 x 256 doubles of LDS; G complete on return.
 typedef double small_d4 __attribute__((ext_vector_type(4)));
 template <int NT>
 __device__ inline void gram_mfma2(Strided A1, Strided A2, Strided B1, Strided B2, int64_t m, int k1, int k2,
@@ -370,15 +371,29 @@ __device__ inline void gram_mfma2(Strided A1, Strided A2, Strided B1, Strided B2
     for (int u = 0; u < U; ++u) acc[u % 4] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc[u % 4], 0, 0, 0);
   }
   // D register v: (row 4 v + lane / 16, col lane % 16)
+  static_assert(NW >= 2 && NW % 2 == 0, "tiles added in pairs");
+  constexpr int NH = NW / 2;
+  double tv[4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
-    part[wave * 256 + (4 * v + kk) * 16 + c] = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
+  for (int v = 0; v < 4; ++v) tv[v] = (acc[0][v] + acc[1][v]) + (acc[2][v] + acc[3][v]);
+  if (wave >= NH) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[(wave - NH) * 256 + (4 * v + kk) * 16 + c] = tv[v];
+  }
+  __syncthreads();
+  if (wave < NH) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double* pp = part + wave * 256 + (4 * v + kk) * 16 + c;
+      *pp = tv[v] + *pp;
+    }
+  }
   __syncthreads();
   for (int e = tid; e < k * k; e += NT) {
     const int i = (e / k) * 16 + e % k;
     double t = part[i];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) t += part[w * 256 + i];
+    for (int w = 1; w < NH; ++w) t += part[w * 256 + i];
     G[e] = t;
   }
   __syncthreads();
@@ -391,7 +406,7 @@ __device__ inline void gram_mfma(Strided A, Strided B, int64_t m, int k, double*
 
 // The whole Gram matrix in one launch for k <= 16 (instead of partials + reduction).
 __global__ __launch_bounds__(256) void k_gram_small(Strided A, Strided B, int64_t m, int k, double* __restrict__ G) {
-  __shared__ double part[4 * 256];
+  __shared__ double part[2 * 256];
   gram_mfma<256>(A, B, m, k, part, G);
 }
 
@@ -401,69 +416,78 @@ __global__ __launch_bounds__(256) void k_gram_small(Strided A, Strided B, int64_
 // eigendecomposition, the top-p selection, the Ritz vectors Phi, S Phi and their three Gram
 // blocks; the same arithmetic as the step-per-launch chain.
 
-// Upper Cholesky factor of the symmetric PSD k x k matrix G (row-major) by one thread, in
-// registers: R[a*k+b] for b >= a.  A dependent column (pivot <= kCholDrop max diag G) gets a zero
-// row; false when a pivot is not finite.
+// Lane l's value of a double, to every lane (l uniform).
+__device__ inline double small_readlane(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Lane src's value of a double, for each lane (ds_bpermute on both halves).
+__device__ inline double lane_shfl(double v, int src) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Upper Cholesky factor of the symmetric PSD k x k matrix G (row-major) on the first wavefront,
+// lane i K + j holding entry (i, j): R[a*k+b] for b >= a (zero below) and 1 / R[a*k+a] in rinv[a]
+// (zero for a dependent column).  A dependent column (pivot <= kCholDrop max diag G) gets a zero
+// row; false when a pivot is not finite (the same in every lane).  Step c: the pivot by readlane,
+// row c scaled, then the trailing block updated with row c's entries by two lane exchanges.
 template <int K>
-__device__ inline bool chol_upper_serial(const double* G, int k, double* R) {
-  double r[K][K];
-#pragma unroll
-  for (int a = 0; a < K; ++a)
-#pragma unroll
-    for (int b = 0; b < K; ++b) r[a][b] = (a < k && b < k && b >= a) ? G[a * k + b] : 0.0;
+__device__ inline bool chol_upper_wave(const double* G, int k, double* R, double* rinv) {
+  static_assert(K * K <= 64, "one entry a lane");
+  const int lane = threadIdx.x & 63, i = lane / K, j = lane % K;
+  const bool in = lane < K * K && i < k && j < k;
+  double a = in ? G[i * k + j] : 0.0;
   double gmax = 0.0;
 #pragma unroll
-  for (int a = 0; a < K; ++a) gmax = fmax(gmax, r[a][a]);
+  for (int d = 0; d < K; ++d)
+    if (d < k) gmax = fmax(gmax, small_readlane(a, d * K + d));
   bool ok = true;
 #pragma unroll
-  for (int j = 0; j < K; ++j) {
-    if (j < k) {
-      const double d = r[j][j];
+  for (int c = 0; c < K; ++c) {
+    if (c < k) {
+      const double d = small_readlane(a, c * K + c);
       if (!isfinite(d)) ok = false;
-      const double rjj = (d > kCholDrop * gmax) ? sqrt(d) : 0.0;
-      r[j][j] = rjj;
-#pragma unroll
-      for (int c = j + 1; c < K; ++c) r[j][c] = rjj > 0.0 ? r[j][c] / rjj : 0.0;
-#pragma unroll
-      for (int a = j + 1; a < K; ++a)
-#pragma unroll
-        for (int b = a; b < K; ++b) r[a][b] -= r[j][a] * r[j][b];
+      const double rcc = (d > kCholDrop * gmax) ? sqrt(d) : 0.0;
+      const double inv = rcc > 0.0 ? 1.0 / rcc : 0.0;
+      if (i == c) a = j == c ? rcc : (j > c ? a * inv : a);
+      const double rci = lane_shfl(a, c * K + i), rcj = lane_shfl(a, c * K + j);
+      if (in && i > c && j >= i) a -= rci * rcj;
+      if (lane == 0) rinv[c] = inv;
     }
   }
-#pragma unroll
-  for (int a = 0; a < K; ++a)
-#pragma unroll
-    for (int b = 0; b < K; ++b)
-      if (a < k && b < k) R[a * k + b] = r[a][b];
+  if (in) R[i * k + j] = j >= i ? a : 0.0;
   return ok;
 }
 
+// Leading dimension of a staged m-row block in LDS: m rounded up to 32 plus 4 doubles, so that the
+// 16 columns x 4 rows a wavefront reads for an FP64 MFMA fall in distinct banks.
+__host__ __device__ constexpr int small_lp(int64_t m) { return (int)(((m + 31) / 32) * 32 + 4); }
+
 // Columns [0, k) of the column-major m-row matrices A and B (leading dimension ld; B may be
-// null) into dA and dB, column-major with leading dimension m: 16 loads of each in flight per
-// thread ahead of their stores.
-template <int NT>
+// null) into dA and dB (leading dimension lp): a thread loads every column of its rows at once
+// (2 K loads in flight) and stores them.
+template <int NT, int K>
 __device__ inline void stage_cols(const double* __restrict__ A, const double* __restrict__ B, int64_t ld, int64_t m,
-                                  int k, double* dA, double* dB) {
-  constexpr int U = 16;
+                                  int k, double* dA, double* dB, int lp) {
   const int mm = (int)m, l = (int)ld;
-  for (int c = 0; c < k; ++c) {
-    const double* a = A + c * l;
-    const double* b = B ? B + c * l : nullptr;
-    for (int r0 = threadIdx.x; r0 < mm; r0 += NT * U) {
-      double va[U], vb[U];
+  for (int r = threadIdx.x; r < mm; r += NT) {
+    double va[K], vb[K];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int r = r0 + NT * u;
-        va[u] = r < mm ? a[r] : 0.0;
-        vb[u] = (b && r < mm) ? b[r] : 0.0;
-      }
+    for (int c = 0; c < K; ++c) {
+      va[c] = c < k ? A[c * l + r] : 0.0;
+      vb[c] = (B && c < k) ? B[c * l + r] : 0.0;
+    }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int r = r0 + NT * u;
-        if (r < mm) {
-          dA[c * mm + r] = va[u];
-          if (b) dB[c * mm + r] = vb[u];
-        }
+    for (int c = 0; c < K; ++c) {
+      if (c < k) {
+        dA[c * lp + r] = va[c];
+        if (B) dB[c * lp + r] = vb[c];
       }
     }
   }
@@ -482,19 +506,23 @@ __global__ __launch_bounds__(kSmallNT) void k_cholqr2_small(const double* __rest
                                                        double* __restrict__ Q, double* __restrict__ Q2, int32_t* flags,
                                                        int stage) {
   extern __shared__ __attribute__((aligned(16))) double xs[];
-  __shared__ double part[kSmallNT / 64 * 256];
-  __shared__ double G[K * K], R[K * K];
+  __shared__ double part[kSmallNT / 128 * 256];
+  __shared__ double G[K * K], R[K * K], Rinv[K];
+  const int lp = small_lp(m);
   double* X = stage ? xs : Q;
-  const int64_t lx = stage ? m : ld;
+  const int64_t lx = stage ? lp : ld;
   if (stage) {
-    stage_cols<kSmallNT>(Y, nullptr, ld, m, k, xs, nullptr);
+    stage_cols<kSmallNT, K>(Y, nullptr, ld, m, k, xs, nullptr, lp);
     __syncthreads();
   }
   for (int pass = 0; pass < 2; ++pass) {
     const double* src = (pass == 0 && !stage) ? Y : X;
     const int64_t ls = (pass == 0 && !stage) ? ld : lx;
     gram_mfma<kSmallNT>(Strided{src, 1, ls}, Strided{src, 1, ls}, m, k, part, G);
-    if (threadIdx.x == 0 && !chol_upper_serial<K>(G, k, R)) atomicOr(flags, kFlagNumeric);
+    if (threadIdx.x < 64) {
+      const bool ok = chol_upper_wave<K>(G, k, R, Rinv);
+      if (threadIdx.x == 0 && !ok) atomicOr(flags, kFlagNumeric);
+    }
     __syncthreads();
     const int ils = (int)ls, ilx = (int)lx;
     for (int r = threadIdx.x; r < (int)m; r += kSmallNT) {
@@ -508,7 +536,7 @@ __global__ __launch_bounds__(kSmallNT) void k_cholqr2_small(const double* __rest
           double t = x[j];
 #pragma unroll
           for (int a = 0; a < j; ++a) t -= q[a] * R[a * k + j];
-          q[j] = R[j * k + j] > 0.0 ? t / R[j * k + j] : 0.0;
+          q[j] = t * Rinv[j];
         }
       }
 #pragma unroll
@@ -518,23 +546,22 @@ __global__ __launch_bounds__(kSmallNT) void k_cholqr2_small(const double* __rest
     __syncthreads();  // R is rewritten by the next pass
   }
   if (stage) {
-    for (int c = 0; c < k; ++c)
-      for (int r = threadIdx.x; r < (int)m; r += kSmallNT) {
-        Q[c * (int)ld + r] = xs[c * (int)m + r];
-        if (Q2) Q2[c * (int)ld + r] = xs[c * (int)m + r];
+    for (int r = threadIdx.x; r < (int)m; r += kSmallNT) {
+      double v[K];
+#pragma unroll
+      for (int c = 0; c < K; ++c) v[c] = c < k ? xs[c * lp + r] : 0.0;
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        if (c < k) {
+          Q[c * (int)ld + r] = v[c];
+          if (Q2) Q2[c * (int)ld + r] = v[c];
+        }
       }
+    }
   } else if (Q2) {  // a thread copies the rows it wrote
     for (int c = 0; c < k; ++c)
       for (int r = threadIdx.x; r < (int)m; r += kSmallNT) Q2[c * (int)ld + r] = Q[c * (int)ld + r];
   }
-}
-
-// Lane src's value of a double, for each lane (ds_bpermute on both halves).
-__device__ inline double lane_shfl(double v, int src) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
-  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
 // Partner of index i in step `step` of the round-robin ordering over ke (even) players: slot 0
@@ -559,17 +586,19 @@ __global__ __launch_bounds__(kSmallNT) void k_ritz_small(const double* __restric
                                                     double* __restrict__ Phi, double* __restrict__ SPhi,
                                                     double* __restrict__ G, int stage) {
   static_assert(K * K <= 64 && PB <= K, "one matrix entry a lane");
-  // with stage set, Qb and S Qb are read once into dynamic LDS (m x k each, leading dimension m)
+  // with stage set, Qb and S Qb are read once into dynamic LDS (m x k each, leading dimension
+  // small_lp(m)); Phi and S Phi then replace their first p columns there for the last Gram pass
   extern __shared__ __attribute__((aligned(16))) double xs[];
-  __shared__ double part[kSmallNT / 64 * 256];
+  __shared__ double part[kSmallNT / 128 * 256];
   __shared__ double T[K * K], V[K * K], ev[K], sel[K * PB], W[4 * PB * PB];
   __shared__ int order[K];
   const int tid = threadIdx.x;
+  const int lp = small_lp(m);
   const double* Qs = stage ? xs : Qb;
-  const double* SQs = stage ? xs + m * k : SQ;
-  const int64_t lq = stage ? m : ld;
+  const double* SQs = stage ? xs + (int64_t)lp * k : SQ;
+  const int64_t lq = stage ? lp : ld;
   if (stage) {
-    stage_cols<kSmallNT>(Qb, SQ, ld, m, k, xs, xs + m * k);
+    stage_cols<kSmallNT, K>(Qb, SQ, ld, m, k, xs, xs + (int64_t)lp * k, lp);
     __syncthreads();
   }
   gram_mfma<kSmallNT>(Strided{Qs, 1, lq}, Strided{SQs, 1, lq}, m, k, part, T);
@@ -649,13 +678,18 @@ __global__ __launch_bounds__(kSmallNT) void k_ritz_small(const double* __restric
         }
         Phi[jj * ild + r] = f;
         SPhi[jj * ild + r] = g;
+        if (stage) {  // this thread read its rows of Qb and S Qb above
+          xs[jj * ilq + r] = f;
+          xs[(int64_t)lp * k + jj * ilq + r] = g;
+        }
       }
     }
   }
   __syncthreads();  // every row of Phi and S Phi is written
   // the Gram of [Phi S Phi] (2p x 2p) in one pass; its blocks Phi^T Phi, Phi^T S Phi and
   // (S Phi)^T S Phi go to G
-  const Strided Ph{Phi, 1, ld}, SPh{SPhi, 1, ld};
+  const Strided Ph = stage ? Strided{xs, 1, lq} : Strided{Phi, 1, ld};
+  const Strided SPh = stage ? Strided{xs + (int64_t)lp * k, 1, lq} : Strided{SPhi, 1, ld};
   gram_mfma2<kSmallNT>(Ph, SPh, Ph, SPh, m, p, p, part, W);
   const int p2 = 2 * p;
   for (int e = tid; e < 3 * p * p; e += kSmallNT) {
@@ -744,12 +778,12 @@ constexpr int64_t kSmallMaxLd = int64_t(1) << 26;
 
 // dynamic LDS the small-basis kernels may take for a staged copy
 constexpr size_t kSmallStage = 96 * 1024;
-constexpr size_t kSmallStageRitz = 96 * 1024;
+constexpr size_t kSmallStageRitz = 136 * 1024;
 
 hipError_t launch_cholqr2_small(const double* Y, int64_t m, int k, int64_t ld, double* Q, double* Q2, int32_t* flags,
                                 hipStream_t st) {
   if (!Y || !Q || !flags || ld < m || ld > kSmallMaxLd || !small_basis_fits(k, 1, m)) return hipErrorInvalidValue;
-  const size_t bytes = (size_t)m * k * sizeof(double);
+  const size_t bytes = (size_t)small_lp(m) * k * sizeof(double);
   const int stage = bytes <= kSmallStage ? 1 : 0;
   const size_t dyn = stage ? bytes : 0;
   const void* fn = k <= 4 ? (const void*)k_cholqr2_small<4> : (const void*)k_cholqr2_small<8>;
@@ -771,7 +805,7 @@ hipError_t launch_ritz_small(const double* Qb, const double* SQ, int64_t m, int 
   if (!Qb || !SQ || !theta || !Phi || !SPhi || !G || ld < m || ld > kSmallMaxLd ||
       !small_basis_fits(k, p, m))
     return hipErrorInvalidValue;
-  const size_t bytes = 2 * (size_t)m * k * sizeof(double);
+  const size_t bytes = 2 * (size_t)small_lp(m) * k * sizeof(double);
   const int stage = bytes <= kSmallStageRitz ? 1 : 0;
   const size_t dyn = stage ? bytes : 0;
   const int which = k <= 4 ? 0 : (p <= 4 ? 1 : 2);
