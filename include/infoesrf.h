@@ -205,15 +205,15 @@ typedef struct infoesrf_opts {
                            an exactly zero residual; reaching the count is not a warning, and
                            stats->converged still reports relres <= rtol.  0: iterate to rtol. */
   int32_t s_form;       /* INFOESRF_S_AUTO | INFOESRF_S_OPERATOR | INFOESRF_S_DENSE */
-  int32_t tail_systems; /* FP64 PCG on the observed lattice with the band form, or with the dense S,
-                           when that band or S takes at most 1 MiB (m <= 4096): once at most this
-                           many systems are left, one persistent launch finishes them (each
-                           workgroup iterates a system to convergence, its direction in LDS,
-                           applying the band or S in place; the smallest shifts first).  A value
-                           of at least Q*N hands every system over after the first step (without
-                           host synchronization, the only hand-over point).  0 = every system
-                           from the first step (64 in infoesrf_update_batched, whose instances
-                           share the GPU), -1 = never. */
+  int32_t tail_systems; /* FP64 or MIXED_FP32 PCG on the observed lattice with the band form, or
+                           with the dense S, when that band or S takes at most 1 MiB in the
+                           iterations' precision (m <= 4096): once at most this many systems are
+                           left, one persistent launch finishes them (each workgroup iterates a
+                           system to convergence, its direction in LDS, applying the band or S in
+                           place, the smallest shifts first; from a zero start it also takes the
+                           first step and every FP64 residual sweep).  0 = every system from its
+                           zero start in one launch (the default; 64 in infoesrf_update_batched
+                           when it does not take its one-launch path), -1 = never. */
   int32_t warm_fp32;    /* learned start: 0 = BF16 inference on MFMA with FP32 accumulation
                            (default), 1 = FP32 inference */
   int32_t reserved[2];
@@ -316,13 +316,18 @@ int infoesrf_perturbation_update(const infoesrf_problem* prob, int32_t Q, const 
  * One launch (infoesrf_batched_one_launch returns 1): when every instance's
  * inner PCG can run in the persistent kernel (compacted solver, zero start,
  * tail_systems >= 0, FP64 or MIXED_FP32, the band on the observed lattice or
- * the dense S, m <= 4096, one n_ritz for all), each instance is set up in
- * turn on `stream` (its mean system, at shift 0, joins its perturbation
- * systems), then each sweep is one persistent launch over a queue of every
- * instance's live systems (largest instance first, smallest shifts first
- * within it), then each instance's quadrature sum and final update.  With
- * host_sync 0 this issues kernels on `stream` only (capturable in a HIP
- * graph, a fixed number of sweeps: 2 for FP64, 4 for MIXED_FP32).
+ * the dense S, m <= 4096, one n_ritz for all), the instances' set-ups are
+ * forked onto library-owned streams (default priority) that wait on and join
+ * back into `stream` through events (its mean system, at shift 0, joins an
+ * instance's perturbation systems); then one persistent launch per kernel
+ * shape (instances with m <= 1024, and larger ones) runs every sweep of every
+ * instance's systems from a queue (largest instance first, smallest shifts
+ * first within it): a workgroup restarts a system from its true FP64 residual
+ * while that is above rtol, up to the sweep budget (2 for FP64 and 4 for
+ * MIXED_FP32 inner applies with host_sync 0, 40 with host_sync 1); then each
+ * instance's quadrature sum and final update.  The call makes no host read
+ * before the final status when host_sync is 1 and none at all when it is 0
+ * (capturable in a HIP graph).
  * Otherwise instances run largest first on a pool of library-owned streams
  * (default priority) that fork from and join back into `stream`, each as the
  * single-instance calls.  With host_sync 1 the return code is the most severe
