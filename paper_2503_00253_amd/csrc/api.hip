@@ -451,6 +451,11 @@ struct Inst {
   // FP32 copies of the observed-lattice band and of the dense S in the persistent kernel's packed
   // layout (four stencil entries of a row in 16 bytes), for FP32 inner applies
   float *bandQ32 = nullptr, *SdQ32 = nullptr;
+  // on a declared lattice with the band form: the final apply's rectangular band (state points x
+  // the lattice points of their window) in place of the state grid's band
+  bool rect = false;
+  RectGeom rg{};
+  double* rectS = nullptr;
   // learned warm start: network buffers for the members (inputs, trunk outputs, the network's
   // own workspace)
   const Net* net = nullptr;
@@ -696,7 +701,12 @@ void plan_layout(Plan& pl, Arena& ar, const infoesrf_problem* P, const Options& 
     const infoesrf_loc& L = P->loc;
     const bool f32 = op.inner == Prec::F32;
     const int64_t ps = (int64_t)(2 * L.bz + 1) * (2 * L.bx + 1) * ld64(in.n);
-    in.bandS = ar.take<double>(ps);
+    in.rect = in.obs && !in.dense && rect_fits(in.gs, op.lat, in.N);
+    if (in.rect) {
+      in.rg = rect_geom(in.gs, op.lat);
+      in.rectS = ar.take<double>((int64_t)in.rg.wz * in.rg.wx * ld64(in.n));
+    }
+    in.bandS = in.rect ? nullptr : ar.take<double>(ps);
     in.bandS32 = (f32 && !in.obs && !in.sd) ? ar.take<float>(ps) : nullptr;
     if (in.obs) {
       const int64_t po = (int64_t)(2 * in.go.bz + 1) * (2 * in.go.bx + 1) * ld64(in.m);
@@ -941,6 +951,10 @@ int apply_state(Plan& pl, const double* U, int64_t ld, const int32_t* act, const
   Inst& in = pl.in;
   const int64_t Bpad = round_up(ncols, kSysTile);
   const int64_t ldr = ld64(in.n);
+  if (in.rect) {  // the declared lattice with the band form: the rectangular band on the lattice columns
+    IE_HIP(launch_rect_apply(in.rg, in.rectS, ldr, U, ld, act, nact, ncols, static_cast<double*>(pl.bf.T), ldr, st));
+    return 0;
+  }
   if (in.obs) {  // the declared lattice: no transposed H
     hipLaunchKernelGGL(k_scatter_lattice, dim3(nb(in.n * Bpad)), dim3(256), 0, st, U, ld, act, nact, in.lat,
                        in.P->loc.nx, in.P->h_w, in.P->r_var, in.n, in.m, Bpad, (double*)pl.bf.V, ldr);
@@ -1074,7 +1088,8 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st, bool solve = true) 
   }
   // 3. explicit bands of P (band form): one pass over the members each
   if (in.band) {
-    IE_HIP(launch_band_build(Prec::F64, in.gs, in.Z, in.n, in.N, in.bandS, ld64(in.n), st));
+    if (in.rect) IE_HIP(launch_rect_build(in.rg, in.Z, in.n, in.Zt, in.m, in.N, in.rectS, ld64(in.n), st));
+    else IE_HIP(launch_band_build(Prec::F64, in.gs, in.Z, in.n, in.N, in.bandS, ld64(in.n), st));
     if (in.bandS32) IE_HIP(launch_band_build(Prec::F32, in.gs, in.Z, in.n, in.N, in.bandS32, ld64(in.n), st));
     if (in.obs) {
       IE_HIP(launch_band_build(Prec::F64, in.go, in.Zt, in.m, in.N, in.bandO, ld64(in.m), st));
@@ -1925,7 +1940,6 @@ int batched_one_launch(const infoesrf_problem* probs, int count, const int32_t* 
   std::vector<char> mean(count, 0);
   std::vector<int> codes(count, 0);
   std::vector<std::string> msgs(count);
-  int64_t seg = 0;
   // one instance's set-up on stream ss, without host reads (inputs that fail the device's checks
   // set its flags, reported through its counters); an instance that fails on the host is left
   // out of the launches and reported

@@ -314,4 +314,243 @@ hipError_t launch_band_apply(Prec prec, const Grid& g, const void* band, int64_t
   return hipErrorInvalidValue;  // the band form has FP64 and FP32 entries only
 }
 
+// ---------------------------------------------------------------- rectangular state x lattice band
+namespace {
+
+constexpr int kRectTX = 64;  // state points of one grid row a block takes
+
+__host__ __device__ inline int rect_floor_div(int p, int q) { return p >= 0 ? p / q : -((-p + q - 1) / q); }
+__host__ __device__ inline int rect_ceil_div(int p, int q) { return -rect_floor_div(-p, q); }
+__device__ inline int rect_wrap(int a, int n) {
+  a %= n;
+  return a < 0 ? a + n : a;
+}
+// Lattice columns a block's window spans: those of its first point's window up to its last
+// point's (at most (TX - 1) / sx + 1 more than one point's wx).
+__host__ __device__ inline int rect_window_cols(const RectGeom& g) { return (kRectTX - 1) / g.sx + 1 + g.wx; }
+
+// The block's tile and window: grid row z, first column x0, nxt points; the window's first
+// lattice row a0 and column b0 and its nb columns.
+struct RectTile {
+  int z, x0, nxt, a0, b0, nb;
+};
+__device__ inline RectTile rect_tile(const RectGeom& g, int tiles_per_row) {
+  RectTile t;
+  t.z = blockIdx.x / tiles_per_row;
+  t.x0 = (blockIdx.x % tiles_per_row) * kRectTX;
+  t.nxt = min(kRectTX, g.nx - t.x0);
+  t.a0 = rect_ceil_div(t.z - g.bz - g.z0, g.sz);
+  t.b0 = rect_ceil_div(t.x0 - g.bx - g.x0, g.sx);
+  t.nb = rect_ceil_div(t.x0 + t.nxt - 1 - g.bx - g.x0, g.sx) + g.wx - t.b0;
+  return t;
+}
+// Row-major lattice index of window point (ia, ib), or -1 past a lattice end that is not periodic.
+__device__ inline int rect_window_point(const RectGeom& g, const RectTile& t, int ia, int ib) {
+  int a = t.a0 + ia, b = t.b0 + ib;
+  if (g.pz) a = rect_wrap(a, g.nzo);
+  else if (a < 0 || a >= g.nzo) return -1;
+  if (g.px) b = rect_wrap(b, g.nxo);
+  else if (b < 0 || b >= g.nxo) return -1;
+  return a * g.nxo + b;
+}
+
+// One block per (tile, chunk of kRectEB entries): Z of its points and the lattice members of its
+// window staged in LDS, then R[e ldr + j] = L(dz, dx) sum_i Z[j, i] Zt[k, i] for the chunk's
+// entries e = ia wx + ib of every point j (zero where the lattice point lies outside the point's
+// window or past a lattice end); four independent chains over the members.
+constexpr int kRectEB = 16;
+__global__ __launch_bounds__(256) void k_rect_build(RectGeom g, const double* __restrict__ Z, int64_t ldz,
+                                                     const double* __restrict__ Zt, int64_t ldzt, int N,
+                                                     double* __restrict__ R, int64_t ldr, int tiles_per_row) {
+  extern __shared__ __attribute__((aligned(16))) double sm[];
+  const RectTile t = rect_tile(g, tiles_per_row);
+  const int tid = threadIdx.x;
+  const int nw = g.wz * t.nb;
+  double* Zs = sm;                   // N x kRectTX
+  double* Ws = sm + N * kRectTX;     // N x nw
+  const int64_t row0 = (int64_t)t.z * g.nx + t.x0;
+  // a point (or window point) a thread and its members in batches of 8 loads ahead of their
+  // stores (a store right after each load would wait for every load in turn)
+  constexpr int LB = 8;
+  for (int xx = tid; xx < kRectTX * 4; xx += 256) {
+    const int p = xx & (kRectTX - 1), i0 = xx / kRectTX;
+    if (p >= t.nxt) continue;
+    for (int ib = i0; ib < N; ib += 4 * LB) {
+      double v[LB];
+#pragma unroll
+      for (int h = 0; h < LB; ++h) v[h] = ib + 4 * h < N ? Z[(ib + 4 * h) * ldz + row0 + p] : 0.0;
+#pragma unroll
+      for (int h = 0; h < LB; ++h)
+        if (ib + 4 * h < N) Zs[(ib + 4 * h) * kRectTX + p] = v[h];
+    }
+  }
+  for (int v = tid; v < nw; v += 256) {
+    const int k = rect_window_point(g, t, v / t.nb, v % t.nb);
+    for (int ib = 0; ib < N; ib += LB) {
+      double w[LB];
+#pragma unroll
+      for (int h = 0; h < LB; ++h) w[h] = (k >= 0 && ib + h < N) ? Zt[(ib + h) * ldzt + k] : 0.0;
+#pragma unroll
+      for (int h = 0; h < LB; ++h)
+        if (ib + h < N) Ws[(ib + h) * nw + v] = w[h];
+    }
+  }
+  __syncthreads();
+  const int W = g.wz * g.wx, wt = 2 * g.bx + 1;
+  const int e0 = blockIdx.y * kRectEB, e1 = min(W, e0 + kRectEB);
+  for (int u = tid; u < (e1 - e0) * kRectTX; u += 256) {
+    const int e = e0 + u / kRectTX, xx = u % kRectTX;  // consecutive threads take consecutive points
+    if (xx >= t.nxt) continue;
+    const int x = t.x0 + xx, ia = e / g.wx, ib = e % g.wx;
+    const int blo = rect_ceil_div(x - g.bx - g.x0, g.sx);
+    const int dz = g.z0 + g.sz * (t.a0 + ia) - t.z, dx = g.x0 + g.sx * (blo + ib) - x;
+    double val = 0.0;
+    if (dz <= g.bz && dx <= g.bx) {
+      const int v = ia * t.nb + (blo - t.b0) + ib;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      int i = 0;
+      for (; i + 4 <= N; i += 4) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) acc[h] += Zs[(i + h) * kRectTX + xx] * Ws[(i + h) * nw + v];
+      }
+      for (; i < N; ++i) acc[0] += Zs[i * kRectTX + xx] * Ws[i * nw + v];
+      val = g.table[(dz + g.bz) * wt + dx + g.bx] * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+    }
+    R[(int64_t)e * ldr + row0 + xx] = val;
+  }
+}
+
+// One block per (tile, group of 4 CPT columns): the window's entries of those listed columns of U
+// staged in LDS, then wavefront w takes the tile's 64 points for columns w, w + 4, ... of the
+// group; the band entries go in batches of 8 loads ahead of their use.
+template <int CPT>
+__global__ __launch_bounds__(256) void k_rect_apply(RectGeom g, const double* __restrict__ R, int64_t ldr,
+                                                     const double* __restrict__ U, int64_t ldu,
+                                                     const int32_t* __restrict__ act, const int32_t* __restrict__ nact,
+                                                     int ncols, double* __restrict__ T, int64_t ldt,
+                                                     int tiles_per_row) {
+  extern __shared__ __attribute__((aligned(16))) double sm[];
+  const RectTile t = rect_tile(g, tiles_per_row);
+  const int tid = threadIdx.x;
+  const int nw = g.wz * t.nb;
+  const int na = nact ? min(*nact, ncols) : ncols;
+  const int cb = blockIdx.y * 4 * CPT;  // the group's first column
+  const int nc = min(4 * CPT, na - cb);
+  if (nc <= 0) return;
+  for (int v = tid; v < nw; v += 256) {
+    const int k = rect_window_point(g, t, v / t.nb, v % t.nb);
+    double w[4 * CPT];
+#pragma unroll
+    for (int c = 0; c < 4 * CPT; ++c) w[c] = (k >= 0 && c < nc) ? U[(int64_t)act[cb + c] * ldu + k] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4 * CPT; ++c)
+      if (c < nc) sm[c * nw + v] = w[c];
+  }
+  __syncthreads();
+  const int xx = tid & 63, grp = tid >> 6;
+  if (xx >= t.nxt) return;
+  const int x = t.x0 + xx;
+  const int64_t j = (int64_t)t.z * g.nx + x;
+  const int boff = rect_ceil_div(x - g.bx - g.x0, g.sx) - t.b0;
+  double acc[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) acc[q] = 0.0;
+  constexpr int EB = 8;
+  for (int ia = 0; ia < g.wz; ++ia) {
+    const double* rrow = R + (int64_t)(ia * g.wx) * ldr + j;  // zero outside the point's window
+    const double* srow = sm + ia * t.nb + boff;
+    int ib = 0;
+    for (; ib + EB <= g.wx; ib += EB) {
+      double r[EB];
+#pragma unroll
+      for (int u = 0; u < EB; ++u) r[u] = rrow[(int64_t)(ib + u) * ldr];
+#pragma unroll
+      for (int u = 0; u < EB; ++u)
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          const int c = grp + 4 * q;
+          if (c < nc) acc[q] += r[u] * srow[c * nw + ib + u];
+        }
+    }
+    for (; ib < g.wx; ++ib) {
+      const double r = rrow[(int64_t)ib * ldr];
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int c = grp + 4 * q;
+        if (c < nc) acc[q] += r * srow[c * nw + ib];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int c = grp + 4 * q;
+    if (c < nc) T[(int64_t)(cb + c) * ldt + j] = acc[q];
+  }
+}
+
+size_t rect_build_lds(const RectGeom& g, int64_t N) {
+  return sizeof(double) * (size_t)N * (kRectTX + (size_t)g.wz * rect_window_cols(g));
+}
+constexpr int kRectCPT = 2;  // columns a thread accumulates in the apply (8 a block)
+size_t rect_apply_lds(const RectGeom& g, int64_t ncols) {
+  return sizeof(double) * (size_t)std::min<int64_t>(ncols, 4 * kRectCPT) * g.wz * rect_window_cols(g);
+}
+
+}  // namespace
+
+bool rect_fits(const Grid& gs, const infoesrf_lattice& lat, int64_t N) {
+  if (lat.sz < 1 || lat.sx < 1 || lat.nzo < 1 || lat.nxo < 1) return false;
+  if (gs.pz && (int64_t)lat.nzo * lat.sz != gs.nz) return false;
+  if (gs.px && (int64_t)lat.nxo * lat.sx != gs.nx) return false;
+  const RectGeom g = rect_geom(gs, lat);
+  // the final apply takes N + 1 columns at most (members and the mean)
+  return rect_build_lds(g, N) <= 64 * 1024 && rect_apply_lds(g, N + 1) <= 64 * 1024;
+}
+
+RectGeom rect_geom(const Grid& gs, const infoesrf_lattice& lat) {
+  RectGeom g{};
+  g.nz = gs.nz;
+  g.nx = gs.nx;
+  g.pz = gs.pz;
+  g.px = gs.px;
+  g.bz = gs.bz;
+  g.bx = gs.bx;
+  g.z0 = lat.z0;
+  g.sz = lat.sz;
+  g.nzo = lat.nzo;
+  g.x0 = lat.x0;
+  g.sx = lat.sx;
+  g.nxo = lat.nxo;
+  g.wz = 2 * gs.bz / lat.sz + 1;
+  g.wx = 2 * gs.bx / lat.sx + 1;
+  g.table = gs.table;
+  return g;
+}
+
+hipError_t launch_rect_build(const RectGeom& g, const double* Z, int64_t ldz, const double* Zt, int64_t ldzt,
+                             int64_t N, double* R, int64_t ldr, hipStream_t st) {
+  const int64_t n = (int64_t)g.nz * g.nx;
+  const size_t lds = rect_build_lds(g, N);
+  if (!Z || !Zt || !R || !g.table || ldr < n || N < 1 || lds > 64 * 1024) return hipErrorInvalidValue;
+  const int tpr = (g.nx + kRectTX - 1) / kRectTX;
+  const int chunks = (g.wz * g.wx + kRectEB - 1) / kRectEB;
+  hipLaunchKernelGGL(k_rect_build, dim3((unsigned)(tpr * g.nz), (unsigned)chunks), dim3(256), lds, st, g, Z, ldz, Zt,
+                     ldzt, (int)N, R, ldr, tpr);
+  return hipGetLastError();
+}
+
+hipError_t launch_rect_apply(const RectGeom& g, const double* R, int64_t ldr, const double* U, int64_t ldu,
+                             const int32_t* act, const int32_t* nact, int64_t ncols, double* T, int64_t ldt,
+                             hipStream_t st) {
+  if (ncols <= 0) return hipSuccess;
+  const int64_t n = (int64_t)g.nz * g.nx;
+  const size_t lds = rect_apply_lds(g, ncols);
+  if (!R || !U || !act || !T || ldt < n || lds > 64 * 1024) return hipErrorInvalidValue;
+  const int tpr = (g.nx + kRectTX - 1) / kRectTX;
+  const int groups = (int)((ncols + 4 * kRectCPT - 1) / (4 * kRectCPT));
+  hipLaunchKernelGGL((k_rect_apply<kRectCPT>), dim3((unsigned)(tpr * g.nz), (unsigned)groups), dim3(256), lds, st, g, R,
+                     ldr, U, ldu, act, nact, (int)ncols, T, ldt, tpr);
+  return hipGetLastError();
+}
+
 }  // namespace infoesrf

@@ -227,6 +227,32 @@ hipError_t launch_band_build(Prec prec, const Grid& g, const double* Z, int64_t 
 hipError_t launch_band_apply(Prec prec, const Grid& g, const void* band, int64_t ldb, const void* V, int64_t ldv,
                              int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, hipStream_t st,
                              const ProfDev* prof = nullptr, int32_t* zero_counter = nullptr);
+
+// The final state-space apply on a declared observed lattice: P Ht R^{-1/2} u for point
+// observations on the lattice needs, for each state point, only the lattice points inside its
+// localization window, so the product is kept as a rectangular band of n rows x wz wx entries
+// (entry (ia, ib) of state point (z, x): lattice point (ceil((z - bz - z0) / sz) + ia,
+// ceil((x - bx - x0) / sx) + ib), wrapped along an axis the lattice tiles periodically, weight 0
+// when outside the window or the lattice): R = L o (Z Zt^T) restricted to those entries, Zt the
+// weighted lattice members R^{-1/2} H Z.  wz = 2 bz / sz + 1, wx = 2 bx / sx + 1.
+struct RectGeom {
+  int32_t nz, nx, pz, px, bz, bx;    // state grid, periodic flags, stencil half-extents
+  int32_t z0, sz, nzo, x0, sx, nxo;  // the observed lattice
+  int32_t wz, wx;                    // lattice points a window spans along z and x
+  const double* table;               // (2 bz + 1) x (2 bx + 1) localization stencil, row-major
+};
+// Whether the rectangular form applies: along a periodic state axis the lattice must tile it, and
+// the build's and the apply's LDS tiles (N members, N + 1 columns) fit in 64 KiB.
+bool rect_fits(const Grid& gs, const infoesrf_lattice& lat, int64_t N);
+RectGeom rect_geom(const Grid& gs, const infoesrf_lattice& lat);
+// R (ldr rows, wz wx columns of entries) from Z (n x N, ldz) and Zt (m x N, ldzt).
+hipError_t launch_rect_build(const RectGeom& g, const double* Z, int64_t ldz, const double* Zt, int64_t ldzt,
+                             int64_t N, double* R, int64_t ldr, hipStream_t st);
+// T[:, c] = R applied to column act[c] of U (m rows, ldu), for c < *nact (<= ncols); the n x ncols
+// result column-major with leading dimension ldt.
+hipError_t launch_rect_apply(const RectGeom& g, const double* R, int64_t ldr, const double* U, int64_t ldu,
+                             const int32_t* act, const int32_t* nact, int64_t ncols, double* T, int64_t ldt,
+                             hipStream_t st);
 hipError_t cov_band_timed(Prec prec, const Grid& g, const void* band, int64_t ldb, const void* V, int64_t ldv,
                           int64_t vcols, int64_t B, const int32_t* Bdev, void* T, int64_t ldt, hipStream_t st,
                           int32_t* zero_counter = nullptr);
