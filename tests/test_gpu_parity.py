@@ -55,6 +55,10 @@ CASES = {
     "small-nx-periodic": lambda: stencil_problem(1, 40, 0, 1, 3.0, 1.0, 5, 2, 12),
     "2d-layers": lambda: stencil_problem(4, 50, 0, 1, 3.0, 1.0, 6, 2, 13),
     "2d-periodic-z": lambda: stencil_problem(6, 37, 1, 1, 2.5, 1.0, 5, 1, 14),
+    # every point observed, 40 members: a block's lattice window (3 rows of 64 + 11 columns) with
+    # the members of its 64 state points needs 92 KiB of LDS, past the 64 KiB the rectangular
+    # state x lattice band allows, so the final state-space apply takes the state band instead
+    "2d-full-obs-40": lambda: stencil_problem(4, 50, 0, 1, 3.0, 1.0, 40, 1, 15),
 }
 
 
@@ -151,6 +155,25 @@ def test_perturbation_update_matches_oracle(case, domain, form):
     assert np.all(st.relres <= 1e-8) and np.all(st.converged == 1)
     assert st.counter(ie.CNT_NOT_CONVERGED) == 0
     assert st.counter(ie.CNT_ITERATIONS) == int(st.iters.sum())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed-fp32"])
+def test_lattice_update_past_the_rectangular_band(precision):
+    prob = CASES["2d-full-obs-40"]()
+    say("mean + perturbation update, lattice, state-band final apply", precision)
+    dp = dense_of(prob)
+    P = ie.Problem.from_synthetic(prob)
+    kw = dict(precision=ie.MIXED_FP32) if precision == "mixed-fp32" else {}
+    o = opts_for(prob, P, "lattice", "band", **kw)
+    got, st = ie.mean_update(P, prob.y, o)
+    assert st.code == ie.OK
+    assert upd(got.cpu().numpy(), ref.mean_update_eig(dp, prob.y)) < 1e-6
+    s, p, _ = ref.quadrature_elliptic(prob.Q, prob.ell)
+    want = np.sqrt(prob.N - 1) * ref.perturbation_update_quadrature(dp, s, p)
+    got, st = ie.perturbation_update(P, s, p, o)
+    assert st.code == ie.OK
+    assert upd(got.cpu().numpy(), want) < 1e-6
+    assert np.all(st.relres <= 1e-8) and np.all(st.converged == 1)
 
 
 def test_perturbation_update_tight_tolerance():
