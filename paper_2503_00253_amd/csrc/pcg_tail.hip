@@ -59,10 +59,17 @@ __device__ inline double tail_sum1(double v, double (*sred)[NT / 64]) {
   return t;
 }
 
-// The same sums through LDS when the workgroup's Wn x NT partials fit: every thread stores its
+// Doubles between the partials of consecutive sums: NT and 16 more, so that the four 16-lane
+// groups of a wavefront that add the partials of four sums read distinct LDS banks in each half
+// wavefront (NT doubles apart they would all read the same banks).
+__host__ __device__ constexpr int tail_part_stride(int NT) { return NT + 16; }
+
+// The same sums through LDS when the workgroup's Wn rows of NT partials fit: every thread stores its
 // Wn values, then 16 threads per value add NT / 16 partials each (a fixed order) and a row of 16
 // lanes combines them by DPP.  Fewer cross-lane steps than Wn wavefront sums.
-__host__ __device__ constexpr bool tail_lds_sums(int Wn, int NT) { return Wn > 1 && Wn * NT * 8 <= 96 * 1024; }
+__host__ __device__ constexpr bool tail_lds_sums(int Wn, int NT) {
+  return Wn > 1 && Wn * tail_part_stride(NT) * 8 <= 96 * 1024;
+}
 
 // One reduction an iteration (up to 4 Ritz pairs, where its 4p + 4 sums fit in LDS): the sums of
 // the new direction's apply q (p^T q, q^T q, r^T q, Phi^T q, (S Phi)^T q) and of the current
@@ -79,11 +86,11 @@ __device__ inline void tail_sums_lds(const double* v, double* part, double* out_
   constexpr int G = 16;
   const int tid = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < Wn; ++j) part[j * NT + tid] = v[j];
+  for (int j = 0; j < Wn; ++j) part[j * tail_part_stride(NT) + tid] = v[j];
   __syncthreads();
   for (int u = tid; u < Wn * G; u += NT) {  // whole rows of 16 lanes stay active together
     const int j = u / G, c = u % G;
-    const double* pj = part + j * NT + c;
+    const double* pj = part + j * tail_part_stride(NT) + c;
     // four independent chains (a fixed order), then their sum
     constexpr int KC = NT / G >= 8 ? 4 : 1;
     double tc[KC];
@@ -186,11 +193,28 @@ __device__ inline void tail_apply_rows(__amdgpu_buffer_rsrc_t rsA, uint32_t colA
       for (int jj = 0; jj < RPT / 2; ++jj) {
         if (!live[jj]) continue;
         const double* p0 = sp + corner[2 * jj] + lrow + d0;
-        const double* p1 = ADJ ? p0 + 1 : sp + corner[2 * jj + 1] + lrow + d0;
+        if constexpr (ADJ) {
+          // the pair's shared window (CH + 1 entries from an even index) in 16-byte LDS reads
+          double w[CH + 1];
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
-          qv[2 * jj] += bv[jj][k].x * p0[k];
-          qv[2 * jj + 1] += bv[jj][k].y * p1[k];
+          for (int i = 0; i < CH / 2; ++i) {
+            const double2 t2 = reinterpret_cast<const double2*>(p0)[i];
+            w[2 * i] = t2.x;
+            w[2 * i + 1] = t2.y;
+          }
+          w[CH] = p0[CH];
+#pragma unroll
+          for (int k = 0; k < CH; ++k) {
+            qv[2 * jj] += bv[jj][k].x * w[k];
+            qv[2 * jj + 1] += bv[jj][k].y * w[k + 1];
+          }
+        } else {
+          const double* p1 = sp + corner[2 * jj + 1] + lrow + d0;
+#pragma unroll
+          for (int k = 0; k < CH; ++k) {
+            qv[2 * jj] += bv[jj][k].x * p0[k];
+            qv[2 * jj + 1] += bv[jj][k].y * p1[k];
+          }
         }
       }
       so += (uint32_t)CH * colA;
@@ -255,16 +279,44 @@ __device__ inline void tail_apply_rows_q(__amdgpu_buffer_rsrc_t rsQ, uint32_t co
       // every load of the chunk goes out before the first is used (widening each one as it lands
       // lets the compiler reuse its registers and wait for every load in turn)
       __builtin_amdgcn_sched_barrier(0);
+      if constexpr (ADJ) {
+        // the pair's shared window (CH + 1 entries from an even index) in 16-byte LDS reads
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        if (!live[j / 2]) continue;
-        const double* pj = (ADJ && (j & 1)) ? sp + corner[j - 1] + lrow + d0 + 1 : sp + corner[j] + lrow + d0;
+        for (int jj = 0; jj < RPT / 2; ++jj) {
+          if (!live[jj]) continue;
+          const double* pw = sp + corner[2 * jj] + lrow + d0;
+          double w[CH + 1];
 #pragma unroll
-        for (int q = 0; q < CQ; ++q) {
-          qv[j] += (double)bv[j][q].x * pj[4 * q];
-          qv[j] += (double)bv[j][q].y * pj[4 * q + 1];
-          qv[j] += (double)bv[j][q].z * pj[4 * q + 2];
-          qv[j] += (double)bv[j][q].w * pj[4 * q + 3];
+          for (int i = 0; i < CH / 2; ++i) {
+            const double2 t2 = reinterpret_cast<const double2*>(pw)[i];
+            w[2 * i] = t2.x;
+            w[2 * i + 1] = t2.y;
+          }
+          w[CH] = pw[CH];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int j = 2 * jj + h;
+#pragma unroll
+            for (int q = 0; q < CQ; ++q) {
+              qv[j] += (double)bv[j][q].x * w[4 * q + h];
+              qv[j] += (double)bv[j][q].y * w[4 * q + h + 1];
+              qv[j] += (double)bv[j][q].z * w[4 * q + h + 2];
+              qv[j] += (double)bv[j][q].w * w[4 * q + h + 3];
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          if (!live[j / 2]) continue;
+          const double* pj = sp + corner[j] + lrow + d0;
+#pragma unroll
+          for (int q = 0; q < CQ; ++q) {
+            qv[j] += (double)bv[j][q].x * pj[4 * q];
+            qv[j] += (double)bv[j][q].y * pj[4 * q + 1];
+            qv[j] += (double)bv[j][q].z * pj[4 * q + 2];
+            qv[j] += (double)bv[j][q].w * pj[4 * q + 3];
+          }
         }
       }
       so += (uint32_t)CQ * colQ;
@@ -366,7 +418,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
   __shared__ int s_idx;
   // padded direction (band) or direction (dense S); then the partial sums and, when phi_lds, the
   // Ritz bases
-  extern __shared__ double sp[];
+  extern __shared__ __attribute__((aligned(16))) double sp[];
   const int tid = threadIdx.x;
   const int na = *nact;
 
@@ -428,8 +480,8 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
       rsF = tail_rsrc(lmp.Phi, (int64_t)P * lmp.ld * 8);
       rsG = tail_rsrc(lmp.SPhi, (int64_t)P * lmp.ld * 8);
       colF = (uint32_t)(lmp.ld * 8);
-      part = sp + npad + kTailSlack;        // W x NT partial sums
-      sF = part + tail_sum_words(P, NT) * NT;  // Phi (P x m), when phi_lds
+      part = sp + npad + kTailSlack;        // rows of NT partial sums (tail_part_stride apart)
+      sF = part + tail_sum_words(P, NT) * tail_part_stride(NT);  // Phi (P x m), when phi_lds
       sH = sF + (int64_t)P * m;             // S Phi (P x m)
       if (phi_lds) {
         for (int o = tid; o < P * (int)m; o += NT) {
@@ -1062,7 +1114,7 @@ hipError_t tail_static_lds(const void* fn, std::atomic<size_t>& cache, size_t* o
 template <int P, int RPT, int NT>
 size_t tail_inst_lds(TailInst& d, size_t stat) {
   size_t lds = tail_lds_bytes(d.ap);
-  lds += (size_t)tail_sum_words(P, NT) * NT * sizeof(double);
+  lds += (size_t)tail_sum_words(P, NT) * tail_part_stride(NT) * sizeof(double);
   if (stat + lds > kTailLdsBig) return 0;
   const size_t phi = (size_t)16 * P * d.st.m;
   d.phi_lds = (P > 0 && !tail_caches_ritz(P, RPT, NT) && stat + lds + phi <= kTailLdsBig) ? 1 : 0;
