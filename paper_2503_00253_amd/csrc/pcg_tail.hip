@@ -631,6 +631,10 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
     if constexpr (kMerged) {
     // 1 / (1 + sigma + theta_l) for this system
     double rth[P > 0 ? P : 1];
+    // the squared residual norm against the squared target (no square root an iteration); the
+    // relative residual is formed once the loop ends
+    const double thresh2 = thresh * thresh;
+    double rr_last = -1.0;
 #pragma unroll
     for (int l = 0; l < P; ++l) rth[l] = 1.0 / (sig1 + sG[3 * P * P + l]);
     for (;;) {
@@ -690,14 +694,13 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
         ++it;
       }
       const double rr = fmax(dt[3] - alpha * (2.0 * dt[2] - alpha * dt[1]), 0.0);
-      const double rn = sqrt(rr);
-      relres = bn > 0.0 ? rn / bn : 0.0;
+      rr_last = rr;
       if (!isfinite(rr)) {
         if (tid == 0) atomicOr(st.flags, kFlagNumeric);
         state = 2;
         break;
       }
-      if (rn <= thresh) {
+      if (rr <= thresh2) {
         state = 1;
         break;
       }
@@ -755,6 +758,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
       // no barrier here: every thread has read the LDS direction and sdot before the next
       // direction's barrier, and part and sdot are rewritten only after it
     }
+    if (rr_last >= 0.0 || !isfinite(rr_last)) relres = bn > 0.0 ? sqrt(rr_last) / bn : 0.0;
     } else {
     for (;;) {
       if (!first) {  // the apply and the step (the first pass of a start only prepares p)
