@@ -1017,14 +1017,17 @@ int stage_setup(Plan& pl, const Options& op, hipStream_t st, bool solve = true) 
   Inst& in = pl.in;
   const infoesrf_problem* P = in.P;
   // 1. input checks (they read H only within its own CSR bounds): the flags and column counts
-  //    zeroed, the element checks, the CSR check and count of H
-  hipLaunchKernelGGL(k_input_zero, dim3(nb(std::max<int64_t>(in.n, 1))), dim3(256), 0, st, in.flags, in.fallbacks,
-                     in.col_cnt, in.n);
+  //    zeroed, the element checks, the CSR check and count of H.  On a declared lattice the
+  //    element checks require every row of H to be its one lattice point (a CSR of m entries,
+  //    in range: the lattice lies in the grid), and nothing uses H's transpose: no count.
+  const int64_t ncnt = in.obs ? 0 : in.n;
+  hipLaunchKernelGGL(k_input_zero, dim3(nb(std::max<int64_t>(ncnt, 1))), dim3(256), 0, st, in.flags, in.fallbacks,
+                     in.col_cnt, ncnt);
   IE_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_input_checks, dim3(nb(std::max<int64_t>(in.n * in.N, in.m))), dim3(256), 0, st, P->X,
                      in.n * in.N, P->r_var, in.m, in.obs ? 1 : 0, P->h_ptr, P->h_idx, op.lat, P->loc.nx, in.flags);
   IE_HIP(hipGetLastError());
-  IE_HIP(launch_csc_count(P->h_ptr, P->h_idx, in.m, in.n, nnz_bound(P), in.col_cnt, in.flags, st));
+  if (!in.obs) IE_HIP(launch_csc_count(P->h_ptr, P->h_idx, in.m, in.n, nnz_bound(P), in.col_cnt, in.flags, st));
   // with host synchronization the input checks are read from pinned memory behind an event
   HostStage* hs = nullptr;
   hipEvent_t ev = nullptr;

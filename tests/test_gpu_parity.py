@@ -286,6 +286,12 @@ def test_bad_observation_operator_is_an_error():
         ie.perturbation_update(P, s, p, ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE,
                                                         lattice=(0, 1, 1, 1, 4, 64)))
     assert e.value.code == ie.ERR_INVALID_ARG
+    say("out-of-range index under a true lattice claim")
+    P = ie.Problem(prob.X, prob.h_ptr, idx, prob.h_w, prob.r_var, nx=prob.nx, bx=prob.bx, table=prob.table)
+    lat = ie.Problem.from_synthetic(prob).lattice()
+    with pytest.raises(ie.InfoEsrfError) as e:
+        ie.perturbation_update(P, s, p, ie.default_opts(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=lat))
+    assert e.value.code == ie.ERR_INVALID_ARG
 
 
 def test_indefinite_localization_is_not_spd():
