@@ -400,8 +400,11 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
   // loads of the packed FP32 band.  Short chunks measured fastest at the n = 4096 lattice (the
   // FP64 kernel 0.56 ms per launch with 8 entries against 0.67 ms with 16; FP32 0.45 ms with 8
   // against 0.57 ms with 32)
-  constexpr int CH = RPT >= 4 ? 4 : 8;
-  constexpr int CHQ = 8;
+  // With four rows a thread, 2 FP64 entries (4 entries of the packed FP32 band) a chunk still keep
+  // four 16-byte loads in flight per thread, and the registers they save keep the kernel that serves
+  // many instances from spilling.
+  constexpr int CH = RPT >= 4 ? 2 : 8;
+  constexpr int CHQ = RPT >= 4 ? 4 : 8;
   // the Ritz vectors of the thread's rows stay in registers when they fit
   constexpr bool kCache = tail_caches_ritz(P, RPT, NT);
   constexpr bool kLdsSums = tail_lds_sums(2 * P + 1, NT);
