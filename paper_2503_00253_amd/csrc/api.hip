@@ -332,10 +332,20 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
                                   const int32_t* flags, const int32_t* fallbacks, int64_t* out, const int32_t* done,
                                   int32_t* nact_out, int64_t* out2, const double* relres, int32_t* oi, double* orr,
                                   uint8_t* oc, double tol, int64_t* mirror) {
-  __shared__ int64_t acc[5][4];
+  // 1024 threads: up to 1024 systems in one pass of loads
+  constexpr int NT = 1024, NW = NT / 64;
+  __shared__ int64_t acc[5][NW];
   const int t = threadIdx.x;
+  // the single words thread 0 reports, loaded before the per-system pass (not after it)
+  int32_t f = 0, fb = 0;
+  int64_t ad = 0;
+  if (t == 0) {
+    f = *flags;
+    fb = fallbacks ? *fallbacks : 0;
+    ad = adj ? *adj : 0;
+  }
   int64_t it = 0, sw = 0, nc = 0, mx = 0, lv = 0;
-  for (int64_t s = t; s < S; s += 256) {
+  for (int64_t s = t; s < S; s += NT) {
     it += iters[s];
     sw += sweeps[s];
     nc += (fdone[s] != 1);
@@ -345,7 +355,7 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
     if (orr) orr[s] = relres[s];
     if (oc) oc[s] = (done[s] == 1 && relres[s] <= tol) ? 1 : 0;
   }
-  // wavefront sums by shuffles, then the four wavefronts in order
+  // wavefront sums by shuffles, then the wavefronts in order
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     it += __shfl_xor(it, o, 64);
@@ -363,8 +373,9 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
   }
   __syncthreads();
   if (t == 0) {
-    int64_t a = 0, b = 0, c = 0, d = 0;
-    for (int j = 0; j < 4; ++j) {
+    int64_t a = 0, b = 0, c = 0, d = 0, live = 0;
+    for (int j = 0; j < NW; ++j) {
+      live += acc[4][j];
       a += acc[0][j];
       b += acc[1][j];
       c += acc[2][j];
@@ -374,11 +385,10 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
     out[INFOESRF_CNT_SWEEPS] = b;
     out[INFOESRF_CNT_NOT_CONVERGED] = c;
     out[INFOESRF_CNT_MAX_ITERS] = d;
-    const int64_t ai = a + (adj ? *adj : 0);  // inner applies
+    const int64_t ai = a + ad;  // inner applies
     out[INFOESRF_CNT_APPLIES] = ai + b + extra_fp64_applies;
     out[INFOESRF_CNT_APPLIES_FP64] = (inner_fp64 ? ai : 0) + b + extra_fp64_applies;
-    out[INFOESRF_CNT_FALLBACKS] = fallbacks ? *fallbacks : 0;
-    const int32_t f = *flags;
+    out[INFOESRF_CNT_FALLBACKS] = fb;
     int64_t status = INFOESRF_OK;
     if (f & kFlagBadInput) status = INFOESRF_ERR_INVALID_ARG;
     else if (f & kFlagNumeric) status = INFOESRF_ERR_NUMERIC;
@@ -387,7 +397,6 @@ __global__ void k_finish_counters(const int32_t* iters, const int32_t* sweeps, c
     out[INFOESRF_CNT_STATUS] = status;
     if (out2)
       for (int j = 0; j < INFOESRF_NUM_COUNTERS; ++j) out2[j] = out[j];
-    const int64_t live = ((acc[4][0] + acc[4][1]) + acc[4][2]) + acc[4][3];
     if (nact_out) *nact_out = (int32_t)live;
     if (mirror) {  // the live count in the low word of the first entry, then the counters
       mirror[0] = (int64_t)(uint32_t)live;
@@ -1672,7 +1681,7 @@ int finish_enqueue(Plan& pl, const Options& op, infoesrf_stats* stats, int64_t e
   double* orr = stats ? stats->relres : nullptr;
   uint8_t* oc = stats ? stats->converged : nullptr;
   int64_t* out2 = stats ? stats->counters : nullptr;
-  hipLaunchKernelGGL(k_finish_counters, dim3(1), dim3(256), 0, st, sy.iters, sy.sweeps, sy.fdone, sy.S, extra_fp64,
+  hipLaunchKernelGGL(k_finish_counters, dim3(1), dim3(1024), 0, st, sy.iters, sy.sweeps, sy.fdone, sy.S, extra_fp64,
                      sy.app_adj, op.inner == Prec::F64 ? 1 : 0, op.fixed > 0 ? 1 : 0, pl.in.flags, pl.in.fallbacks,
                      pl.in.counters, sy.done, sy.nact2, out2, sy.relres, oi, orr, oc, op.rtol, sy.stage);
   IE_HIP(hipGetLastError());

@@ -458,8 +458,17 @@ __global__ void k_quad_combine(const double* __restrict__ u, int64_t ldu, int64_
   if (act && t == 0) *nact = (int32_t)N;
   if (t >= m * N) return;
   const int64_t i = t / m, r = t % m;
+  // eight loads in flight, then the terms in order of q
+  constexpr int U = 8;
   double acc = 0.0;
-  for (int32_t q = 0; q < Q; ++q) acc += pw[q] * u[(s0 + (int64_t)q * N + i) * ldu + r];
+  for (int32_t q0 = 0; q0 < Q; q0 += U) {
+    double v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) v[k] = q0 + k < Q ? u[(s0 + (int64_t)(q0 + k) * N + i) * ldu + r] : 0.0;
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (q0 + k < Q) acc += pw[q0 + k] * v[k];
+  }
   ubar[i * ldb + r] = acc;
 }
 __global__ void k_final_pert(const double* __restrict__ Z, const double* __restrict__ T, int64_t ldt, int64_t n,
