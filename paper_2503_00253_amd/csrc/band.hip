@@ -247,7 +247,10 @@ hipError_t band_apply_typed(const Grid& g, const T* band, int64_t ldb, const T* 
 
 static int band_systems_per_block(const Grid& g, size_t elem, int64_t B) {
   // a measured choice for this grid and batch size (infoesrf_autotune), if it fits in LDS
-  const int t = tuned_choice(TuneKey{0, elem == 8 ? 0 : 1, g.nz, g.nx, g.bz, g.bx, 0}, B);
+  // (halved while half of it still holds the batch: wider blocks would only add zero columns, and
+  // a bucket's choice is measured at a larger batch than its smallest)
+  int t = tuned_choice(TuneKey{0, elem == 8 ? 0 : 1, g.nz, g.nx, g.bz, g.bx, 0}, B);
+  while (t > 8 && t / 2 >= B) t /= 2;
   if ((t == 8 || t == 16 || t == 32 || t == 64) && (size_t)t * (64 + 2 * g.bx) * elem <= 150 * 1024) return t;
   // else the widest system block whose V window stays within 48 KiB of LDS (four blocks per CU),
   // and no wider than the batch needs
