@@ -78,6 +78,9 @@ def parse():
                     help="n4096 learned line: n = 4096 updates (other seeds) whose 640 systems each train the net")
     ap.add_argument("--learn-steps", type=int, default=1500, help="n4096 learned line: Adam steps of 8 members")
     ap.add_argument("--no-autotune", action="store_true", help="use the built-in block-shape rules")
+    ap.add_argument("--inner-rtol", type=float, default=None,
+                    help="mixed precision: the first sweep's inner target relative to the residual "
+                         "(default: the library's)")
     ap.add_argument("--n-ritz", type=int, default=None,
                     help="Ritz pairs of the limited-memory preconditioner (default: 4 for the n = 4096 workload, "
                          "the library's 10 for the cycles and the batch)")
@@ -251,6 +254,8 @@ def main():
     kw = dict(precision=prec, solver=SOLVERS[a.solver],
               cov_form={"auto": ie.COV_AUTO, "operator": ie.COV_OPERATOR, "band": ie.COV_BAND}[a.form],
               n_ritz=a.n_ritz, oversample=a.oversample, tail_systems=a.tail)
+    if a.inner_rtol is not None:
+        kw.update(inner_rtol=a.inner_rtol)
     if a.domain == "lattice":
         kw.update(apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=P.lattice())
     opts = ie.default_opts(**kw)
@@ -594,6 +599,8 @@ def bench_cycle(a, prec):
         kw = dict(precision=prec, apply_domain=ie.DOMAIN_OBS_LATTICE, lattice=run.P.lattice(), cov_form=form,
                   solver=SOLVERS[a.solver], tail_systems=a.tail, n_ritz=4 if a.n_ritz is None else a.n_ritz,
                   oversample=4 if a.oversample is None else a.oversample)
+        if a.inner_rtol is not None:
+            kw.update(inner_rtol=a.inner_rtol)
         run.set_opts(ie.default_opts(**kw))
         name = "lorenz96-8x480-N20-m1280-Q12-cycle"
         metric = "shifted SPD solves/s at rel-res 1e-8"
@@ -663,6 +670,8 @@ def bench_batched(a, prec):
     if a.oversample is None:
         a.oversample = 4
     kw.update(n_ritz=a.n_ritz, oversample=a.oversample)
+    if a.inner_rtol is not None:
+        kw.update(inner_rtol=a.inner_rtol)
     lats = None
     if a.domain == "lattice":
         kw.update(apply_domain=ie.DOMAIN_OBS_LATTICE)

@@ -183,7 +183,7 @@ typedef struct infoesrf_lattice {
 
 typedef struct infoesrf_opts {
   double rtol;          /* target of the true FP64 relative residual ||b - C u|| / ||b|| per system (default 1e-8) */
-  double inner_rtol;    /* mixed precision: inner PCG tolerance (0 = 1e-2 for BF16, 1e-5 for FP32) */
+  double inner_rtol;    /* mixed precision: inner PCG tolerance (0 = 1e-2 for BF16, 1e-7 for FP32) */
   int32_t max_iter;     /* cap on PCG iterations per system (inner iterations summed in mixed mode) */
   int32_t n_ritz;       /* p: Ritz pairs in the limited-memory preconditioner (Appendix E), one of
                            0 (none), 4, 8, 10, 12, 16, 20; n_ritz + oversample <= min(48, m) */

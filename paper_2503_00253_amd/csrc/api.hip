@@ -616,7 +616,11 @@ int resolve_options(const infoesrf_problem* P, const infoesrf_opts* o, Options& 
   op.p = p;
   op.k = p > 0 ? p + o->oversample : 0;
   op.inner = (o->precision == INFOESRF_FP64) ? Prec::F64 : (o->precision == INFOESRF_MIXED_FP32 ? Prec::F32 : Prec::BF16);
-  op.inner_rtol = o->inner_rtol > 0.0 ? o->inner_rtol : (op.inner == Prec::F32 ? 1e-5 : 1e-2);
+  // FP32 inner applies: a first sweep taken to 1e-7 of the residual lets many systems pass the
+  // FP64 check at once and shortens the longest solves (n = 4096 lattice: 18015 -> 17729
+  // iterations, 79 -> 78 at most, 1280 -> 1163 sweeps); looser targets restart more, and
+  // tighter ones iterate on a recursive residual the FP32 apply no longer tracks
+  op.inner_rtol = o->inner_rtol > 0.0 ? o->inner_rtol : (op.inner == Prec::F32 ? 1e-7 : 1e-2);
   op.solver = o->solver;
   op.host_sync = o->host_sync;
   op.rows_per_wave = o->tile_rows;  // 0: chosen per launch from the batch size

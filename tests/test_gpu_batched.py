@@ -89,6 +89,11 @@ def test_batched_equals_single_instances(domain, precision, tail):
     st = runner.stats(code)
     off = 0
     totals = np.zeros(ie.NUM_COUNTERS, dtype=np.int64)
+    # per-system iterations of the two schedules (one persistent launch against the batched loop
+    # handing over at 64 live systems): with FP32 inner applies the first sweep runs to 1e-7 of the
+    # residual, near the FP32 apply's rounding level, so where each schedule's recursive residual
+    # crosses it moves by a few iterations
+    it_tol = 4 if precision == ie.MIXED_FP32 else 2
     for j, (pr, P, (s, p)) in enumerate(zip(probs, Ps, nodes)):
         say("single", j, pr.name)
         Xa, mu, s1, sm = run_single(P, pr, s, p, make_opts(domain, precision, P, tail_systems=tail or 64))
@@ -96,8 +101,8 @@ def test_batched_equals_single_instances(domain, precision, tail):
         if one:
             assert upd(Xs[j].cpu().numpy(), Xa) < 1e-7, (j, pr.name)
             assert upd(mus[j].cpu().numpy(), mu) < 1e-7
-            assert np.max(np.abs(st.iters[off:off + S] - s1.iters)) <= 2
-            assert abs(int(st.iters[off + S]) - int(sm.iters[0])) <= 2
+            assert np.max(np.abs(st.iters[off:off + S] - s1.iters)) <= it_tol
+            assert abs(int(st.iters[off + S]) - int(sm.iters[0])) <= it_tol
         else:
             assert np.array_equal(Xs[j].cpu().numpy(), Xa), (j, pr.name)
             assert np.array_equal(mus[j].cpu().numpy(), mu), (j, pr.name)
