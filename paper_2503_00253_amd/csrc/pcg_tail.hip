@@ -63,41 +63,56 @@ __device__ inline double tail_sum1(double v, double (*sred)[NT / 64]) {
 // groups of a wavefront that add the partials of four sums read distinct LDS banks in each half
 // wavefront (NT doubles apart they would all read the same banks).
 __host__ __device__ constexpr int tail_part_stride(int NT) { return NT + 16; }
+// Partials a sum keeps: one a thread, or with four rows a thread on 512 threads one per pair of
+// lanes (added by one lane exchange first), which halves the area and leaves room in LDS for the
+// Ritz bases that such a thread cannot keep in registers.
+__host__ __device__ constexpr int tail_part_rows(int NT, int RPT) { return RPT >= 4 && NT <= 512 ? NT / 2 : NT; }
 
 // The same sums through LDS when the workgroup's Wn rows of NT partials fit: every thread stores its
 // Wn values, then 16 threads per value add NT / 16 partials each (a fixed order) and a row of 16
 // lanes combines them by DPP.  Fewer cross-lane steps than Wn wavefront sums.
-__host__ __device__ constexpr bool tail_lds_sums(int Wn, int NT) {
-  return Wn > 1 && Wn * tail_part_stride(NT) * 8 <= 96 * 1024;
+__host__ __device__ constexpr bool tail_lds_sums(int Wn, int NT, int RPT) {
+  return Wn > 1 && Wn * tail_part_stride(tail_part_rows(NT, RPT)) * 8 <= 96 * 1024;
 }
 
 // One reduction an iteration (up to 4 Ritz pairs, where its 4p + 4 sums fit in LDS): the sums of
 // the new direction's apply q (p^T q, q^T q, r^T q, Phi^T q, (S Phi)^T q) and of the current
 // residual (r^T r, Phi^T r, (S Phi)^T r) in one pass; the next residual's dots follow from them
 // and the step length.  Otherwise p^T q and the residual's dots are two reductions.
-__host__ __device__ constexpr bool tail_merged(int P, int NT) { return P <= 4 && tail_lds_sums(4 * P + 4, NT); }
+__host__ __device__ constexpr bool tail_merged(int P, int NT, int RPT) {
+  return P <= 4 && tail_lds_sums(4 * P + 4, NT, RPT);
+}
 // Doubles a thread writes for the LDS sums (0: the sums go through wavefront partials).
-__host__ __device__ constexpr int tail_sum_words(int P, int NT) {
-  return tail_merged(P, NT) ? 4 * P + 4 : (tail_lds_sums(2 * P + 1, NT) ? 2 * P + 1 : 0);
+__host__ __device__ constexpr int tail_sum_words(int P, int NT, int RPT) {
+  return tail_merged(P, NT, RPT) ? 4 * P + 4 : (tail_lds_sums(2 * P + 1, NT, RPT) ? 2 * P + 1 : 0);
 }
 
-template <int Wn, int NT>
+template <int Wn, int NT, int RPT>
 __device__ inline void tail_sums_lds(const double* v, double* part, double* out_lds) {
   constexpr int G = 16;
+  constexpr int ROWS = tail_part_rows(NT, RPT), ST = tail_part_stride(ROWS);
   const int tid = threadIdx.x;
+  if constexpr (ROWS == NT) {
 #pragma unroll
-  for (int j = 0; j < Wn; ++j) part[j * tail_part_stride(NT) + tid] = v[j];
+    for (int j = 0; j < Wn; ++j) part[j * ST + tid] = v[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < Wn; ++j) {
+      const double x = v[j] + dpp_f64<0xB1, 0xF>(v[j]);  // quad_perm [1,0,3,2]: this lane and its pair
+      if ((tid & 1) == 0) part[j * ST + (tid >> 1)] = x;
+    }
+  }
   __syncthreads();
   for (int u = tid; u < Wn * G; u += NT) {  // whole rows of 16 lanes stay active together
     const int j = u / G, c = u % G;
-    const double* pj = part + j * tail_part_stride(NT) + c;
+    const double* pj = part + j * ST + c;
     // four independent chains (a fixed order), then their sum
-    constexpr int KC = NT / G >= 8 ? 4 : 1;
+    constexpr int KC = ROWS / G >= 8 ? 4 : 1;
     double tc[KC];
 #pragma unroll
     for (int i = 0; i < KC; ++i) tc[i] = 0.0;
 #pragma unroll
-    for (int k = 0; k < NT / G; ++k) tc[k % KC] += pj[G * k];
+    for (int k = 0; k < ROWS / G; ++k) tc[k % KC] += pj[G * k];
     double t = tc[0];
 #pragma unroll
     for (int i = 1; i < KC; ++i) t += tc[i];
@@ -407,8 +422,8 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
   constexpr int CHQ = RPT >= 4 ? 4 : 8;
   // the Ritz vectors of the thread's rows stay in registers when they fit
   constexpr bool kCache = tail_caches_ritz(P, RPT, NT);
-  constexpr bool kLdsSums = tail_lds_sums(2 * P + 1, NT);
-  constexpr bool kMerged = tail_merged(P, NT);
+  constexpr bool kLdsSums = tail_lds_sums(2 * P + 1, NT, RPT);
+  constexpr bool kMerged = tail_merged(P, NT, RPT);
   constexpr int WM = 4 * P + 4;
   constexpr int kC = kCache ? RPT * P : 1;
   constexpr bool kLow = sizeof(BT) == 4;
@@ -483,8 +498,9 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
       rsF = tail_rsrc(lmp.Phi, (int64_t)P * lmp.ld * 8);
       rsG = tail_rsrc(lmp.SPhi, (int64_t)P * lmp.ld * 8);
       colF = (uint32_t)(lmp.ld * 8);
-      part = sp + npad + kTailSlack;        // rows of NT partial sums (tail_part_stride apart)
-      sF = part + tail_sum_words(P, NT) * tail_part_stride(NT);  // Phi (P x m), when phi_lds
+      // rows of partial sums (tail_part_stride apart), then Phi (P x m), when phi_lds
+      part = sp + npad + kTailSlack;
+      sF = part + tail_sum_words(P, NT, RPT) * tail_part_stride(tail_part_rows(NT, RPT));
       sH = sF + (int64_t)P * m;             // S Phi (P x m)
       if (phi_lds) {
         for (int o = tid; o < P * (int)m; o += NT) {
@@ -674,7 +690,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
           }
         }
       }
-      tail_sums_lds<WM, NT>(acc, part, sdot);
+      tail_sums_lds<WM, NT, RPT>(acc, part, sdot);
       const double* dt = sdot;
       // the step: r <- r - alpha q, and the new residual's dots from the old ones
       //   r'^T r' = r^T r - alpha (2 r^T q - alpha q^T q),  Phi^T r' = Phi^T r - alpha Phi^T q, ...
@@ -806,7 +822,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
           }
         }
       }
-      if (kLdsSums) tail_sums_lds<W, NT>(acc, part, sdot);
+      if (kLdsSums) tail_sums_lds<W, NT, RPT>(acc, part, sdot);
       else tail_sums<W, NT>(acc, sredW, sdot);
       const double* dt = sdot;
       const double rn = sqrt(dt[0]);
@@ -1121,7 +1137,7 @@ hipError_t tail_static_lds(const void* fn, std::atomic<size_t>& cache, size_t* o
 template <int P, int RPT, int NT>
 size_t tail_inst_lds(TailInst& d, size_t stat) {
   size_t lds = tail_lds_bytes(d.ap);
-  lds += (size_t)tail_sum_words(P, NT) * tail_part_stride(NT) * sizeof(double);
+  lds += (size_t)tail_sum_words(P, NT, RPT) * tail_part_stride(tail_part_rows(NT, RPT)) * sizeof(double);
   if (stat + lds > kTailLdsBig) return 0;
   const size_t phi = (size_t)16 * P * d.st.m;
   d.phi_lds = (P > 0 && !tail_caches_ritz(P, RPT, NT) && stat + lds + phi <= kTailLdsBig) ? 1 : 0;
