@@ -449,7 +449,7 @@ struct TailInst {
   double* uacc;
   int64_t seg;
   int32_t grp;
-  int32_t phi_lds;  // set by the launcher: the Ritz bases staged in LDS
+  int32_t phi_lds;  // set by the launcher: Ritz bases staged in LDS (2 both, 1 Phi only, 0 none)
 };
 // A queue entry of a launch over many instances: (instance << kTailSysBits) | system.
 constexpr int kTailSysBits = 20;

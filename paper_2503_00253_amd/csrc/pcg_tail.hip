@@ -502,11 +502,11 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
       part = sp + npad + kTailSlack;
       sF = part + tail_sum_words(P, NT, RPT) * tail_part_stride(tail_part_rows(NT, RPT));
       sH = sF + (int64_t)P * m;             // S Phi (P x m)
-      if (phi_lds) {
+      if (phi_lds) {  // 1: Phi only, 2: Phi and S Phi
         for (int o = tid; o < P * (int)m; o += NT) {
           const int l = o / (int)m, r = o % (int)m;
           sF[o] = tail_ld8(rsF, (uint32_t)r * 8, l * colF);
-          sH[o] = tail_ld8(rsG, (uint32_t)r * 8, l * colF);
+          if (phi_lds == 2) sH[o] = tail_ld8(rsG, (uint32_t)r * 8, l * colF);
         }
       }
 #pragma unroll
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
             const double a = kCache ? ph[(jj * P + l) % kC]
                                     : (phi_lds ? sF[l * m + r] : tail_ld8(rsF, (uint32_t)r * 8, l * colF));
             const double b = kCache ? sph[(jj * P + l) % kC]
-                                    : (phi_lds ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
+                                    : (phi_lds == 2 ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
             acc[4 + l] += a * qj;
             acc[4 + P + l] += b * qj;
             acc[4 + 2 * P + l] += a * rj;
@@ -768,7 +768,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
             const double a = kCache ? ph[(jj * P + l) % kC]
                                     : (phi_lds ? sF[l * m + r] : tail_ld8(rsF, (uint32_t)r * 8, l * colF));
             const double b = kCache ? sph[(jj * P + l) % kC]
-                                    : (phi_lds ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
+                                    : (phi_lds == 2 ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
             z -= b * c1[l] + a * gm[l];
           }
           pv[jj] = z + beta * pv[jj];
@@ -816,7 +816,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
             const double a = kCache ? ph[(jj * P + l) % kC]
                                     : (phi_lds ? sF[l * m + r] : tail_ld8(rsF, (uint32_t)r * 8, l * colF));
             const double b = kCache ? sph[(jj * P + l) % kC]
-                                    : (phi_lds ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
+                                    : (phi_lds == 2 ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
             acc[1 + l] += a * rv[jj];
             acc[1 + P + l] += b * rv[jj];
           }
@@ -890,7 +890,7 @@ __global__ __launch_bounds__(NT) void k_pcg_tail(TailInst one, const TailInst* _
             const double a = kCache ? ph[(jj * P + l) % kC]
                                     : (phi_lds ? sF[l * m + r] : tail_ld8(rsF, (uint32_t)r * 8, l * colF));
             const double b = kCache ? sph[(jj * P + l) % kC]
-                                    : (phi_lds ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
+                                    : (phi_lds == 2 ? sH[l * m + r] : tail_ld8(rsG, (uint32_t)r * 8, l * colF));
             z -= b * scoef[l] + a * scoef[P + l];
           }
           pv[jj] = z + beta * pv[jj];
@@ -1132,16 +1132,20 @@ hipError_t tail_static_lds(const void* fn, std::atomic<size_t>& cache, size_t* o
 }
 
 // Dynamic LDS of one instance: the padded direction, the partial sums of the dots and, when the
-// kernel does not keep the Ritz bases in registers and there is room, the bases (sets phi_lds).
-// 0 when the instance does not fit.
+// kernel does not keep the Ritz bases in registers, as much of them as there is room for (sets
+// phi_lds: 2 both, 1 Phi only, S Phi then read from L2).  0 when the instance does not fit.
 template <int P, int RPT, int NT>
 size_t tail_inst_lds(TailInst& d, size_t stat) {
   size_t lds = tail_lds_bytes(d.ap);
   lds += (size_t)tail_sum_words(P, NT, RPT) * tail_part_stride(tail_part_rows(NT, RPT)) * sizeof(double);
   if (stat + lds > kTailLdsBig) return 0;
-  const size_t phi = (size_t)16 * P * d.st.m;
-  d.phi_lds = (P > 0 && !tail_caches_ritz(P, RPT, NT) && stat + lds + phi <= kTailLdsBig) ? 1 : 0;
-  if (d.phi_lds) lds += phi;
+  const size_t one = (size_t)8 * P * d.st.m;  // one basis, FP64
+  d.phi_lds = 0;
+  if (P > 0 && !tail_caches_ritz(P, RPT, NT)) {
+    if (stat + lds + 2 * one <= kTailLdsBig) d.phi_lds = 2;
+    else if (stat + lds + one <= kTailLdsBig) d.phi_lds = 1;
+  }
+  lds += (size_t)d.phi_lds * one;
   return lds;
 }
 
