@@ -1930,7 +1930,7 @@ BatchArea batch_area(char* base, int count, int64_t systems) {
   b.seg = ar.take<int32_t>(systems);
   b.list = ar.take<int32_t>(systems);
   b.cnt = ar.take<int32_t>(count);
-  b.words = ar.take<int32_t>(4);
+  b.words = ar.take<int32_t>(6);  // three classes
   b.total = ar.take<int64_t>(INFOESRF_NUM_COUNTERS);
   b.bytes = ar.off + 256;
   return b;
@@ -2030,13 +2030,15 @@ int batched_one_launch(const infoesrf_problem* probs, int count, const int32_t* 
     IE_HIP(hipEventRecord(ev.e[1 + w], ws[w]));
     IE_HIP(hipStreamWaitEvent(st, ev.e[1 + w], 0));
   }
-  // one launch per shape of the kernel (rows a thread, from m): the larger instances first, each
-  // class with its slice of the table, the queue's scratch and its counters
-  std::vector<int> big, small;
-  for (int j : live) (probs[j].m > 1024 ? big : small).push_back(j);
+  // one launch per shape of the kernel (rows a thread and workgroup size, from m): the larger
+  // instances first, each class with its slice of the table, the queue's scratch and its counters
+  // (m <= 512 on 256-thread workgroups, several a CU, rather than leaving most of a 1024-row
+  // workgroup idle)
+  std::vector<int> big, mid, small;
+  for (int j : live) (probs[j].m > 1024 ? big : (probs[j].m > 512 ? mid : small)).push_back(j);
   std::vector<std::vector<int>> classes;
-  if (!big.empty()) classes.push_back(big);
-  if (!small.empty()) classes.push_back(small);
+  for (const auto* cl : {&big, &mid, &small})
+    if (!cl->empty()) classes.push_back(*cl);
   const int nl = (int)live.size();
   // one launch per class runs every sweep: each workgroup iterates a system to its inner target,
   // adds the correction into u, checks the true FP64 residual and, while that is above rtol and

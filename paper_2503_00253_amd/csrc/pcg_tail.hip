@@ -1211,6 +1211,7 @@ hipError_t tail_rows(TailInst* descs, int count, TailInst* table, const int32_t*
   int64_t m = 0;
   for (int j = 0; j < count; ++j) m = std::max<int64_t>(m, descs[j].st.m);
   if (table) {  // many instances: one shape for all, from the largest m
+    if (m <= 512) return tail_go<P, 2, 256, BT, true>(descs, count, table, act, nact, qctr, grid, st, queue);
     if (m <= 1024) return tail_go<P, 2, 512, BT, true>(descs, count, table, act, nact, qctr, grid, st, queue);
     if (m <= 2048) return tail_go<P, 4, 512, BT, true>(descs, count, table, act, nact, qctr, grid, st, queue);
     return tail_go<P, 4, 1024, BT, true>(descs, count, table, act, nact, qctr, grid, st, queue);
